@@ -1,0 +1,314 @@
+"""ctypes wrapper of the FP64 CPU oracle (oracle/liborc.so).
+
+TEST INFRASTRUCTURE ONLY: imported by tests/, by the smoke check and by the
+CPU-baseline leg of bench.py.  The product library never uses it.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liborc.so")
+_lib = None
+
+
+class OrcCfg(C.Structure):
+    _fields_ = [
+        ("a", C.c_double), ("b", C.c_double), ("L", C.c_double),
+        ("nr", C.c_int), ("nz", C.c_int),
+        ("V_inner", C.c_double), ("V_outer", C.c_double), ("V_end", C.c_double),
+        ("end_mode", C.c_int),
+        ("B0", C.c_double), ("mirror_k", C.c_double),
+        ("p_mbar", C.c_double), ("T_gas_K", C.c_double), ("M_gas_amu", C.c_double),
+        ("sigma_el", C.c_double), ("iz_I_eV", C.c_double), ("lotz_a", C.c_double),
+        ("lotz_q", C.c_double), ("opal_Ebar_eV", C.c_double), ("okh_xi", C.c_double),
+        ("E_cap_eV", C.c_double),
+        ("n_init", C.c_int64), ("r_lo", C.c_double), ("r_hi", C.c_double),
+        ("z_lo", C.c_double), ("z_hi", C.c_double), ("T_init_eV", C.c_double),
+        ("weight", C.c_double), ("load_mode", C.c_int),
+        ("seed", C.c_uint64), ("dt", C.c_double),
+        ("fx_shift", C.c_int), ("diag_interval", C.c_int), ("collisions", C.c_int),
+    ]
+
+
+class OrcDerived(C.Structure):
+    _fields_ = [(n, C.c_double) for n in (
+        "dr", "dz", "inv_dr", "inv_dz", "h", "n_n", "v_cap", "sig_iz_max", "nu_prime",
+        "P_null", "nsig_el", "lotz_aq", "half_me_over_e", "two_e_over_me", "mass_ratio2",
+        "two_S", "inv_two_S", "bscale")]
+
+
+class OrcDiag(C.Structure):
+    _fields_ = [
+        ("step", C.c_int64), ("n_live", C.c_int64),
+        ("n_elastic", C.c_int64), ("n_ioniz", C.c_int64), ("n_null_cand", C.c_int64),
+        ("n_cap_overflow", C.c_int64),
+        ("n_absorbed", C.c_int64 * 4), ("absorbed_W", C.c_int64 * 4),
+        ("total_Q", C.c_int64), ("n_samples", C.c_int64),
+        ("I_wall", C.c_double * 4), ("peak_density", C.c_double),
+        ("peak_I_outer", C.c_double), ("peak_I_inner", C.c_double),
+    ]
+
+
+_D = C.POINTER(C.c_double)
+_I64 = C.POINTER(C.c_int64)
+_U64 = C.POINTER(C.c_uint64)
+_U32 = C.POINTER(C.c_uint32)
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            from . import build as _b
+            _b.build()
+        L = C.CDLL(_LIB_PATH)
+        L.orc_philox4x32_10.argtypes = [_U32, _U32, _U32]
+        L.orc_u52.argtypes = [C.c_uint32, C.c_uint32]
+        L.orc_u52.restype = C.c_double
+        L.orc_derive.argtypes = [C.POINTER(OrcCfg), C.POINTER(OrcDerived)]
+        L.orc_auto_shift.argtypes = [C.c_double]
+        L.orc_auto_shift.restype = C.c_int
+        L.orc_okh_cos.argtypes = [C.c_double, C.c_double]
+        L.orc_okh_cos.restype = C.c_double
+        L.orc_opal_split.argtypes = [C.c_double, C.c_double, C.c_double]
+        L.orc_opal_split.restype = C.c_double
+        L.orc_scatter.argtypes = [C.c_double] * 5 + [_D]
+        L.orc_sigma_iz.argtypes = [C.POINTER(OrcCfg), C.c_double]
+        L.orc_sigma_iz.restype = C.c_double
+        L.orc_bfield.argtypes = [C.POINTER(OrcCfg), _D, _D]
+        L.orc_vacuum.argtypes = [C.POINTER(OrcCfg), _D]
+        L.orc_solve.argtypes = [C.POINTER(OrcCfg), _D, _D]
+        L.orc_poisson_charge.argtypes = [C.POINTER(OrcCfg), _I64, _D]
+        L.orc_efield.argtypes = [C.POINTER(OrcCfg), _D, _D, _D]
+        L.orc_node_volume.argtypes = [C.POINTER(OrcCfg), _D]
+        L.orc_deposit_one.argtypes = [C.POINTER(OrcCfg), C.c_double, C.c_double, C.c_double, _I64]
+        L.orc_create.argtypes = [C.POINTER(OrcCfg), C.c_int64]
+        L.orc_create.restype = C.c_void_p
+        L.orc_destroy.argtypes = [C.c_void_p]
+        L.orc_load.argtypes = [C.c_void_p]
+        L.orc_set_particles.argtypes = [C.c_void_p, C.c_int64] + [_D] * 6 + [_U64]
+        L.orc_get_particles.argtypes = [C.c_void_p, C.c_int64] + [_D] * 6 + [_U64]
+        L.orc_get_particles.restype = C.c_int64
+        L.orc_set_fields.argtypes = [C.c_void_p, _D, _D, _D, _D, C.c_int]
+        L.orc_get_fields.argtypes = [C.c_void_p, _D, _D, _D, _D]
+        L.orc_set_step.argtypes = [C.c_void_p, C.c_int64]
+        L.orc_step.argtypes = [C.c_void_p, C.c_int]
+        L.orc_get_charge.argtypes = [C.c_void_p, _I64]
+        L.orc_get_phi.argtypes = [C.c_void_p, _D]
+        L.orc_get_diag.argtypes = [C.c_void_p, C.POINTER(OrcDiag)]
+        L.orc_get_time_avg_density.argtypes = [C.c_void_p, _D]
+        L.orc_num_threads.restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _dp(a):
+    return a.ctypes.data_as(_D)
+
+
+def make_cfg(d, fx_shift=None):
+    c = OrcCfg()
+    for name, _ in OrcCfg._fields_:
+        if name in d:
+            setattr(c, name, d[name])
+    if fx_shift is not None:
+        c.fx_shift = int(fx_shift)
+    elif c.fx_shift == 0:
+        c.fx_shift = auto_shift(d["weight"])
+    return c
+
+
+# ---- unit functions -------------------------------------------------------
+
+def philox(ctr, key):
+    ctr = (C.c_uint32 * 4)(*[int(x) & 0xFFFFFFFF for x in ctr])
+    key = (C.c_uint32 * 2)(*[int(x) & 0xFFFFFFFF for x in key])
+    out = (C.c_uint32 * 4)()
+    lib().orc_philox4x32_10(ctr, key, out)
+    return list(out)
+
+
+def u52(hi, lo):
+    return lib().orc_u52(hi, lo)
+
+
+def derive(d, fx_shift=None):
+    c = make_cfg(d, fx_shift)
+    out = OrcDerived()
+    lib().orc_derive(C.byref(c), C.byref(out))
+    return {n: getattr(out, n) for n, _ in OrcDerived._fields_}
+
+
+def auto_shift(w_max):
+    return lib().orc_auto_shift(float(w_max))
+
+
+def okh_cos(xi, u):
+    return lib().orc_okh_cos(xi, u)
+
+
+def opal_split(Ebar, E_av, u):
+    return lib().orc_opal_split(Ebar, E_av, u)
+
+
+def scatter(u, cosx, phi):
+    out = (C.c_double * 3)()
+    lib().orc_scatter(float(u[0]), float(u[1]), float(u[2]), float(cosx), float(phi), out)
+    return np.array(list(out))
+
+
+def sigma_iz(d, E):
+    c = make_cfg(d)
+    return lib().orc_sigma_iz(C.byref(c), float(E))
+
+
+def _nodes(d):
+    return (d["nr"] + 1) * (d["nz"] + 1)
+
+
+def _shape(d):
+    return (d["nr"] + 1, d["nz"] + 1)
+
+
+def bfield(d):
+    c = make_cfg(d)
+    Br = np.zeros(_nodes(d)); Bz = np.zeros(_nodes(d))
+    lib().orc_bfield(C.byref(c), _dp(Br), _dp(Bz))
+    return Br.reshape(_shape(d)), Bz.reshape(_shape(d))
+
+
+def vacuum(d):
+    c = make_cfg(d)
+    phi = np.zeros(_nodes(d))
+    lib().orc_vacuum(C.byref(c), _dp(phi))
+    return phi.reshape(_shape(d))
+
+
+def solve(d, rhs):
+    c = make_cfg(d)
+    rhs = np.ascontiguousarray(rhs, dtype=np.float64).reshape(-1)
+    phi = np.zeros(_nodes(d))
+    lib().orc_solve(C.byref(c), _dp(rhs), _dp(phi))
+    return phi.reshape(_shape(d))
+
+
+def poisson_charge(d, Q, fx_shift=None):
+    c = make_cfg(d, fx_shift)
+    Q = np.ascontiguousarray(Q, dtype=np.int64).reshape(-1)
+    phi = np.zeros(_nodes(d))
+    lib().orc_poisson_charge(C.byref(c), Q.ctypes.data_as(_I64), _dp(phi))
+    return phi.reshape(_shape(d))
+
+
+def efield(d, phi):
+    c = make_cfg(d)
+    phi = np.ascontiguousarray(phi, dtype=np.float64).reshape(-1)
+    Er = np.zeros(_nodes(d)); Ez = np.zeros(_nodes(d))
+    lib().orc_efield(C.byref(c), _dp(phi), _dp(Er), _dp(Ez))
+    return Er.reshape(_shape(d)), Ez.reshape(_shape(d))
+
+
+def node_volume(d):
+    c = make_cfg(d)
+    V = np.zeros(_nodes(d))
+    lib().orc_node_volume(C.byref(c), _dp(V))
+    return V.reshape(_shape(d))
+
+
+def deposit_one(d, r, z, w, fx_shift=None):
+    c = make_cfg(d, fx_shift)
+    Q = np.zeros(_nodes(d), dtype=np.int64)
+    lib().orc_deposit_one(C.byref(c), float(r), float(z), float(w), Q.ctypes.data_as(_I64))
+    return Q.reshape(_shape(d))
+
+
+def num_threads():
+    return lib().orc_num_threads()
+
+
+# ---- simulation object ----------------------------------------------------
+
+class Sim:
+    """One oracle instance.  Mirrors the product library's calls."""
+
+    def __init__(self, d, fx_shift=None, capacity=0):
+        self.d = dict(d)
+        self.cfg = make_cfg(d, fx_shift)
+        self.S = self.cfg.fx_shift
+        self.nodes = _nodes(d)
+        self.shape = _shape(d)
+        self.h = lib().orc_create(C.byref(self.cfg), int(capacity or d.get("n_init", 1024)))
+
+    def close(self):
+        if self.h:
+            lib().orc_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def load(self):
+        lib().orc_load(self.h)
+
+    def set_particles(self, st):
+        n = len(st["r"])
+        arrs = [np.ascontiguousarray(st[k], dtype=np.float64) for k in ("r", "z", "vr", "vt", "vz", "w")]
+        key = np.ascontiguousarray(st["key"], dtype=np.uint64)
+        lib().orc_set_particles(self.h, n, *[_dp(a) for a in arrs], key.ctypes.data_as(_U64))
+
+    def get_particles(self):
+        n = self.diag()["n_live"]
+        arrs = [np.zeros(n) for _ in range(6)]
+        key = np.zeros(n, dtype=np.uint64)
+        lib().orc_get_particles(self.h, n, *[_dp(a) for a in arrs], key.ctypes.data_as(_U64))
+        return dict(zip(("r", "z", "vr", "vt", "vz", "w"), arrs), key=key)
+
+    def set_fields(self, Er=None, Ez=None, Br=None, Bz=None, frozen=1):
+        def p(a):
+            if a is None:
+                return None
+            a = np.ascontiguousarray(a, dtype=np.float64).reshape(-1)
+            self._keep.append(a)
+            return _dp(a)
+        self._keep = []
+        lib().orc_set_fields(self.h, p(Er), p(Ez), p(Br), p(Bz), int(frozen))
+
+    def get_fields(self):
+        a = [np.zeros(self.nodes) for _ in range(4)]
+        lib().orc_get_fields(self.h, *[_dp(x) for x in a])
+        return {k: v.reshape(self.shape) for k, v in zip(("Er", "Ez", "Br", "Bz"), a)}
+
+    def set_step(self, step):
+        lib().orc_set_step(self.h, int(step))
+
+    def step(self, n=1):
+        lib().orc_step(self.h, int(n))
+
+    def charge(self):
+        Q = np.zeros(self.nodes, dtype=np.int64)
+        lib().orc_get_charge(self.h, Q.ctypes.data_as(_I64))
+        return Q.reshape(self.shape)
+
+    def phi(self):
+        p = np.zeros(self.nodes)
+        lib().orc_get_phi(self.h, _dp(p))
+        return p.reshape(self.shape)
+
+    def diag(self):
+        dg = OrcDiag()
+        lib().orc_get_diag(self.h, C.byref(dg))
+        out = {}
+        for name, _ in OrcDiag._fields_:
+            v = getattr(dg, name)
+            out[name] = list(v) if hasattr(v, "__len__") else v
+        return out
+
+    def time_avg_density(self):
+        n = np.zeros(self.nodes)
+        lib().orc_get_time_avg_density(self.h, _dp(n))
+        return n.reshape(self.shape)

@@ -1,0 +1,28 @@
+"""Build the FP64 CPU oracle (test infrastructure) into oracle/liborc.so.
+
+The oracle is plain C compiled by gcc with floating-point contraction off, so
+every multiply and add rounds on its own, as written.
+"""
+import os
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SOURCES = ["orc_core.c", "orc_field.c", "orc_sim.c"]
+LIB = os.path.join(HERE, "liborc.so")
+
+
+def build(verbose=False):
+    cmd = ["gcc", "-std=c11", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
+           "-fPIC", "-shared", "-D_GNU_SOURCE", "-Wall", "-Wno-unknown-pragmas",
+           "-o", LIB + ".tmp"] + [os.path.join(HERE, s) for s in SOURCES] + ["-lm"]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(LIB + ".tmp", LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    build(verbose=True)
+    sys.exit(0)

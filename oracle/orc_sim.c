@@ -1,0 +1,498 @@
+/*
+ * orc_sim.c -- oracle: the particle loop (load, gather, Boris push with the
+ * cylindrical remap, absorption, null-collision MCC, deposit) and the step
+ * sequence with its diagnostics.  TEST INFRASTRUCTURE ONLY (see oracle.h).
+ *
+ * Step n (the paper leaves the ordering to a later publication; this is the
+ * standard explicit PIC-MCC cycle):
+ *   1. every live particle: gather E^n,B at x^n, Boris v^{n-1/2} -> v^{n+1/2},
+ *      move to x^{n+1} in the local Cartesian frame and rotate back to (r,z),
+ *      remove it if it reached an electrode or an end;
+ *   2. null-collision test for every survivor, elastic or ionising event;
+ *   3. deposit survivors and newly created electrons at x^{n+1};
+ *   4. field solve for E^{n+1} (unless the field is frozen);
+ *   5. every D steps: density and current samples.
+ */
+#include "oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORC_E 1.602176634e-19
+
+struct orc_sim {
+    orc_cfg c;
+    orc_derived d;
+    int64_t n, cap;
+    double *r, *z, *vr, *vt, *vz, *w;
+    uint64_t* key;
+    int nodes;
+    int64_t* Q;
+    double *phi_vac, *phi, *Er, *Ez, *Br, *Bz, *V, *avg_acc;
+    int frozen;
+    int64_t step;
+    orc_diag dg;
+    int64_t absorbed_W_last[4];
+};
+
+int orc_num_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+static void sim_reserve(orc_sim* s, int64_t need) {
+    if (need <= s->cap) return;
+    int64_t cap = s->cap > 0 ? s->cap : 1024;
+    while (cap < need) cap *= 2;
+    s->r = (double*)realloc(s->r, sizeof(double) * cap);
+    s->z = (double*)realloc(s->z, sizeof(double) * cap);
+    s->vr = (double*)realloc(s->vr, sizeof(double) * cap);
+    s->vt = (double*)realloc(s->vt, sizeof(double) * cap);
+    s->vz = (double*)realloc(s->vz, sizeof(double) * cap);
+    s->w = (double*)realloc(s->w, sizeof(double) * cap);
+    s->key = (uint64_t*)realloc(s->key, sizeof(uint64_t) * cap);
+    s->cap = cap;
+}
+
+/* ---- shape function (bilinear, order-1 spline) ---- */
+typedef struct { int i, j; double w00, w10, w01, w11; } orc_shape;
+
+static inline orc_shape shape_at(const orc_cfg* c, const orc_derived* d, double r, double z) {
+    orc_shape sh;
+    double s = (r - c->a) * d->inv_dr;
+    int i = (int)floor(s);
+    if (i < 0) i = 0;
+    if (i > c->nr - 1) i = c->nr - 1;
+    double fr = s - (double)i;
+    double t = z * d->inv_dz;
+    int j = (int)floor(t);
+    if (j < 0) j = 0;
+    if (j > c->nz - 1) j = c->nz - 1;
+    double fz = t - (double)j;
+    sh.i = i; sh.j = j;
+    sh.w00 = (1.0 - fr) * (1.0 - fz);
+    sh.w10 = fr * (1.0 - fz);
+    sh.w01 = (1.0 - fr) * fz;
+    sh.w11 = fr * fz;
+    return sh;
+}
+
+static inline double gather(const orc_shape* sh, const double* F, int W) {
+    size_t n00 = (size_t)sh->i * W + sh->j;
+    size_t n10 = n00 + W, n01 = n00 + 1, n11 = n00 + W + 1;
+    return ((sh->w00 * F[n00] + sh->w10 * F[n10]) + sh->w01 * F[n01]) + sh->w11 * F[n11];
+}
+
+/* Fixed-point deposit of one particle: the four node charges round
+ * W * (node weight) to the nearest integer, and the last node takes the
+ * remainder so the particle's charge is conserved exactly. */
+static inline void deposit_shape(const orc_shape* sh, int64_t Wq, int64_t* Q, int W) {
+    double Wd = (double)Wq;
+    int64_t q00 = (int64_t)rint(Wd * sh->w00);
+    int64_t q10 = (int64_t)rint(Wd * sh->w10);
+    int64_t q01 = (int64_t)rint(Wd * sh->w01);
+    int64_t q11 = Wq - q00 - q10 - q01;
+    size_t n00 = (size_t)sh->i * W + sh->j;
+    Q[n00] += q00;
+    Q[n00 + W] += q10;
+    Q[n00 + 1] += q01;
+    Q[n00 + W + 1] += q11;
+}
+
+void orc_deposit_one(const orc_cfg* c, double r, double z, double w, int64_t* Q) {
+    orc_derived d;
+    orc_derive(c, &d);
+    orc_shape sh = shape_at(c, &d, r, z);
+    deposit_shape(&sh, (int64_t)rint(w * d.two_S), Q, c->nz + 1);
+}
+
+/* ---- push: Boris in the local (r,theta,z) frame, then the remap ---- */
+/* returns -1 if the particle survives, else the wall index 0..3 */
+static inline int push_one(const orc_sim* s, int64_t p, double* rr, double* zz,
+                           double* vrr, double* vtt, double* vzz) {
+    const orc_cfg* c = &s->c;
+    const orc_derived* d = &s->d;
+    const int W = c->nz + 1;
+    double r = rr[p], z = zz[p], vr = vrr[p], vt = vtt[p], vz = vzz[p];
+    orc_shape sh = shape_at(c, d, r, z);
+    double Er = gather(&sh, s->Er, W), Ez = gather(&sh, s->Ez, W);
+    double Br = gather(&sh, s->Br, W), Bz = gather(&sh, s->Bz, W);
+    const double h = d->h;
+    /* half electric kick */
+    double hEr = h * Er, hEz = h * Ez;
+    double mr = vr + hEr, mt = vt, mz = vz + hEz;
+    /* magnetic rotation: t = h B, s = 2 t / (1 + t.t) */
+    double tr = h * Br, tz = h * Bz;
+    double tt = tr * tr + tz * tz;
+    double f = 2.0 / (1.0 + tt);
+    double sr = f * tr, sz = f * tz;
+    double pr = mr + mt * tz;              /* v' = v- + v- x t */
+    double pt = mt + (mz * tr - mr * tz);
+    double pz = mz - mt * tr;
+    double qr = mr + pt * sz;              /* v+ = v- + v' x s */
+    double qt = mt + (pz * sr - pr * sz);
+    double qz = mz - pt * sr;
+    /* second half electric kick */
+    vr = qr + hEr; vt = qt; vz = qz + hEz;
+    /* move in the Cartesian frame whose x axis is the particle's radius */
+    double x = r + vr * c->dt;
+    double y = vt * c->dt;
+    double zn = z + vz * c->dt;
+    double rn = sqrt(x * x + y * y);
+    int wall = -1;
+    if (rn <= c->a) wall = 0;
+    else if (rn >= c->b) wall = 1;
+    else if (zn <= 0.0) wall = 2;
+    else if (zn >= c->L) wall = 3;
+    if (wall >= 0) return wall;
+    /* rotate the velocity into the new (r,theta) frame */
+    double cs = x / rn, sn = y / rn;
+    double vrn = cs * vr + sn * vt;
+    double vtn = cs * vt - sn * vr;
+    rr[p] = rn; zz[p] = zn; vrr[p] = vrn; vtt[p] = vtn; vzz[p] = vz;
+    return -1;
+}
+
+/* ---- MCC ---- */
+typedef struct { double r, z, vr, vt, vz, w; uint64_t key; } orc_part;
+
+static inline void philox_blk(const orc_sim* s, uint64_t key, uint32_t step, uint32_t blk, uint32_t o[4]) {
+    uint32_t ctr[4] = {(uint32_t)key, (uint32_t)(key >> 32), step, blk};
+    uint32_t k[2] = {(uint32_t)s->c.seed, (uint32_t)(s->c.seed >> 32)};
+    orc_philox4x32_10(ctr, k, o);
+}
+
+/* event: 0 none, 1 elastic, 2 ionisation (child filled), 3 candidate rejected */
+static inline int mcc_one(const orc_sim* s, int64_t p, orc_part* child) {
+    const orc_cfg* c = &s->c;
+    const orc_derived* d = &s->d;
+    uint32_t step = (uint32_t)s->step;
+    uint32_t b0[4];
+    philox_blk(s, s->key[p], step, 0u, b0);
+    double u_null = orc_u52(b0[0], b0[1]);
+    if (!(u_null < d->P_null)) return 0;
+    double u_proc = orc_u52(b0[2], b0[3]);
+    double vr = s->vr[p], vt = s->vt[p], vz = s->vz[p];
+    double v2 = (vr * vr + vt * vt) + vz * vz;
+    double v = sqrt(v2);
+    double E = v2 * d->half_me_over_e;
+    double nu_el = d->nsig_el * v;
+    double sig_iz = 0.0;
+    if (E > c->iz_I_eV) sig_iz = (d->lotz_aq * log(E / c->iz_I_eV)) / (E * c->iz_I_eV);
+    double nu_iz = (d->n_n * sig_iz) * v;
+    double R = u_proc * d->nu_prime;
+    int ev;
+    if (R < nu_el) ev = 1;
+    else if (R < nu_el + nu_iz) ev = 2;
+    else return 3;
+    double ur = vr / v, ut = vt / v, uz = vz / v;
+    uint32_t b1[4];
+    philox_blk(s, s->key[p], step, 1u, b1);
+    double cos1 = orc_okh_cos(c->okh_xi, orc_u52(b1[0], b1[1]));
+    double phi1 = (2.0 * M_PI) * orc_u52(b1[2], b1[3]);
+    double dir[3];
+    if (ev == 1) {
+        double En = E * (1.0 - d->mass_ratio2 * (1.0 - cos1));
+        double vn = sqrt(En * d->two_e_over_me);
+        orc_scatter(ur, ut, uz, cos1, phi1, dir);
+        s->vr[p] = vn * dir[0]; s->vt[p] = vn * dir[1]; s->vz[p] = vn * dir[2];
+        return 1;
+    }
+    uint32_t b2[4], b3[4];
+    philox_blk(s, s->key[p], step, 2u, b2);
+    philox_blk(s, s->key[p], step, 3u, b3);
+    double E_av = E - c->iz_I_eV;
+    double E_s = orc_opal_split(c->opal_Ebar_eV, E_av, orc_u52(b2[0], b2[1]));
+    double E_p = E_av - E_s;
+    double cos2 = orc_okh_cos(c->okh_xi, orc_u52(b2[2], b2[3]));
+    double phi2 = (2.0 * M_PI) * orc_u52(b3[0], b3[1]);
+    double vp = sqrt(E_p * d->two_e_over_me);
+    double vs = sqrt(E_s * d->two_e_over_me);
+    orc_scatter(ur, ut, uz, cos1, phi1, dir);
+    s->vr[p] = vp * dir[0]; s->vt[p] = vp * dir[1]; s->vz[p] = vp * dir[2];
+    orc_scatter(ur, ut, uz, cos2, phi2, dir);
+    child->r = s->r[p]; child->z = s->z[p];
+    child->vr = vs * dir[0]; child->vt = vs * dir[1]; child->vz = vs * dir[2];
+    child->w = s->w[p];
+    child->key = ((((uint64_t)b3[2]) << 32) | (uint64_t)b3[3]) | (1ull << 63);
+    return 2;
+}
+
+/* ---- deposit of all particles into s->Q (per-thread grids, exact sums) ---- */
+static void deposit_all(orc_sim* s) {
+    const int W = s->c.nz + 1;
+    const int N = s->nodes;
+    memset(s->Q, 0, sizeof(int64_t) * N);
+#pragma omp parallel
+    {
+        int64_t* loc = (int64_t*)calloc(N, sizeof(int64_t));
+#pragma omp for schedule(static)
+        for (int64_t p = 0; p < s->n; ++p) {
+            orc_shape sh = shape_at(&s->c, &s->d, s->r[p], s->z[p]);
+            deposit_shape(&sh, (int64_t)rint(s->w[p] * s->d.two_S), loc, W);
+        }
+#pragma omp critical
+        for (int k = 0; k < N; ++k) s->Q[k] += loc[k];
+        free(loc);
+    }
+}
+
+static void solve_fields(orc_sim* s) {
+    if (s->frozen) return;
+    orc_poisson_charge(&s->c, s->Q, s->phi);
+    for (int k = 0; k < s->nodes; ++k) s->phi[k] += s->phi_vac[k];
+    orc_efield(&s->c, s->phi, s->Er, s->Ez);
+}
+
+/* ---- public sim API ---- */
+orc_sim* orc_create(const orc_cfg* c, int64_t capacity) {
+    orc_sim* s = (orc_sim*)calloc(1, sizeof(orc_sim));
+    s->c = *c;
+    if (s->c.diag_interval <= 0) s->c.diag_interval = 1;
+    orc_derive(&s->c, &s->d);
+    s->nodes = (c->nr + 1) * (c->nz + 1);
+    sim_reserve(s, capacity > 0 ? capacity : 1024);
+    s->Q = (int64_t*)calloc(s->nodes, sizeof(int64_t));
+    s->phi_vac = (double*)calloc(s->nodes, sizeof(double));
+    s->phi = (double*)calloc(s->nodes, sizeof(double));
+    s->Er = (double*)calloc(s->nodes, sizeof(double));
+    s->Ez = (double*)calloc(s->nodes, sizeof(double));
+    s->Br = (double*)calloc(s->nodes, sizeof(double));
+    s->Bz = (double*)calloc(s->nodes, sizeof(double));
+    s->V = (double*)calloc(s->nodes, sizeof(double));
+    s->avg_acc = (double*)calloc(s->nodes, sizeof(double));
+    orc_bfield(&s->c, s->Br, s->Bz);
+    orc_vacuum(&s->c, s->phi_vac);
+    memcpy(s->phi, s->phi_vac, sizeof(double) * s->nodes);
+    orc_efield(&s->c, s->phi, s->Er, s->Ez);
+    orc_node_volume(&s->c, s->V);
+    return s;
+}
+
+void orc_destroy(orc_sim* s) {
+    if (!s) return;
+    free(s->r); free(s->z); free(s->vr); free(s->vt); free(s->vz); free(s->w); free(s->key);
+    free(s->Q); free(s->phi_vac); free(s->phi); free(s->Er); free(s->Ez);
+    free(s->Br); free(s->Bz); free(s->V); free(s->avg_acc);
+    free(s);
+}
+
+/*
+ * Initial load (Sec. III.A: homogeneous Maxwellian cloud; Sec. II.A seed
+ * source: uniform in space, Maxwellian in velocity).  Particle p draws from
+ * Philox counter {p, 0xFFFFFFFF, block}; positions uniform in volume
+ * (load_mode 0) or in r (load_mode 1); velocity components by Box-Muller.
+ */
+int orc_load(orc_sim* s) {
+    const orc_cfg* c = &s->c;
+    int64_t n = c->n_init;
+    sim_reserve(s, n);
+    double sv = sqrt((c->T_init_eV * ORC_E) / 9.1093837015e-31);
+#pragma omp parallel for schedule(static)
+    for (int64_t p = 0; p < n; ++p) {
+        uint32_t b0[4], b1[4], b2[4];
+        philox_blk(s, (uint64_t)p, 0xFFFFFFFFu, 0u, b0);
+        philox_blk(s, (uint64_t)p, 0xFFFFFFFFu, 1u, b1);
+        philox_blk(s, (uint64_t)p, 0xFFFFFFFFu, 2u, b2);
+        double ur = orc_u52(b0[0], b0[1]), uz = orc_u52(b0[2], b0[3]);
+        double r;
+        if (c->load_mode == 1) r = c->r_lo + ur * (c->r_hi - c->r_lo);
+        else r = sqrt(c->r_lo * c->r_lo + ur * (c->r_hi * c->r_hi - c->r_lo * c->r_lo));
+        double z = c->z_lo + uz * (c->z_hi - c->z_lo);
+        double u1 = orc_u52(b1[0], b1[1]), u2 = orc_u52(b1[2], b1[3]);
+        double u3 = orc_u52(b2[0], b2[1]), u4 = orc_u52(b2[2], b2[3]);
+        double m1 = sqrt(-2.0 * log(u1)), m3 = sqrt(-2.0 * log(u3));
+        s->r[p] = r; s->z[p] = z;
+        s->vr[p] = sv * (m1 * cos((2.0 * M_PI) * u2));
+        s->vt[p] = sv * (m1 * sin((2.0 * M_PI) * u2));
+        s->vz[p] = sv * (m3 * cos((2.0 * M_PI) * u4));
+        s->w[p] = c->weight;
+        s->key[p] = (uint64_t)p;
+    }
+    s->n = n;
+    deposit_all(s);
+    solve_fields(s);
+    return 0;
+}
+
+int orc_set_particles(orc_sim* s, int64_t n, const double* r, const double* z,
+                      const double* vr, const double* vt, const double* vz,
+                      const double* w, const uint64_t* key) {
+    sim_reserve(s, n);
+    memcpy(s->r, r, sizeof(double) * n);
+    memcpy(s->z, z, sizeof(double) * n);
+    memcpy(s->vr, vr, sizeof(double) * n);
+    memcpy(s->vt, vt, sizeof(double) * n);
+    memcpy(s->vz, vz, sizeof(double) * n);
+    memcpy(s->w, w, sizeof(double) * n);
+    memcpy(s->key, key, sizeof(uint64_t) * n);
+    s->n = n;
+    deposit_all(s);
+    solve_fields(s);
+    return 0;
+}
+
+int64_t orc_get_particles(const orc_sim* s, int64_t cap, double* r, double* z,
+                          double* vr, double* vt, double* vz, double* w, uint64_t* key) {
+    int64_t n = s->n < cap ? s->n : cap;
+    memcpy(r, s->r, sizeof(double) * n);
+    memcpy(z, s->z, sizeof(double) * n);
+    memcpy(vr, s->vr, sizeof(double) * n);
+    memcpy(vt, s->vt, sizeof(double) * n);
+    memcpy(vz, s->vz, sizeof(double) * n);
+    memcpy(w, s->w, sizeof(double) * n);
+    memcpy(key, s->key, sizeof(uint64_t) * n);
+    return s->n;
+}
+
+void orc_set_fields(orc_sim* s, const double* Er, const double* Ez,
+                    const double* Br, const double* Bz, int frozen) {
+    size_t b = sizeof(double) * s->nodes;
+    if (Er) memcpy(s->Er, Er, b);
+    if (Ez) memcpy(s->Ez, Ez, b);
+    if (Br) memcpy(s->Br, Br, b);
+    if (Bz) memcpy(s->Bz, Bz, b);
+    s->frozen = frozen;
+}
+
+void orc_get_fields(const orc_sim* s, double* Er, double* Ez, double* Br, double* Bz) {
+    size_t b = sizeof(double) * s->nodes;
+    if (Er) memcpy(Er, s->Er, b);
+    if (Ez) memcpy(Ez, s->Ez, b);
+    if (Br) memcpy(Br, s->Br, b);
+    if (Bz) memcpy(Bz, s->Bz, b);
+}
+
+void orc_set_step(orc_sim* s, int64_t step) { s->step = step; }
+
+static void sample_diag(orc_sim* s) {
+    const int D = s->c.diag_interval;
+    double peak = 0.0;
+    for (int k = 0; k < s->nodes; ++k) {
+        double dens = ((double)s->Q[k] * s->d.inv_two_S) / s->V[k];
+        if (dens > peak) peak = dens;
+        s->avg_acc[k] += (double)s->Q[k];
+    }
+    if (peak > s->dg.peak_density) s->dg.peak_density = peak;
+    s->dg.n_samples += 1;
+    double span = (double)D * s->c.dt;
+    for (int wl = 0; wl < 4; ++wl) {
+        int64_t dW = s->dg.absorbed_W[wl] - s->absorbed_W_last[wl];
+        s->dg.I_wall[wl] = (((double)dW * ORC_E) * s->d.inv_two_S) / span;
+        s->absorbed_W_last[wl] = s->dg.absorbed_W[wl];
+    }
+    if (s->dg.I_wall[1] > s->dg.peak_I_outer) s->dg.peak_I_outer = s->dg.I_wall[1];
+    if (s->dg.I_wall[0] > s->dg.peak_I_inner) s->dg.peak_I_inner = s->dg.I_wall[0];
+}
+
+int orc_step(orc_sim* s, int n_steps) {
+    const double vcap2 = s->d.v_cap * s->d.v_cap;
+    for (int it = 0; it < n_steps; ++it) {
+        const int64_t n = s->n;
+        int* wall = (int*)malloc(sizeof(int) * (n > 0 ? n : 1));
+        /* 1. push and absorb */
+#pragma omp parallel for schedule(static)
+        for (int64_t p = 0; p < n; ++p) wall[p] = push_one(s, p, s->r, s->z, s->vr, s->vt, s->vz);
+        int64_t m = 0;
+        for (int64_t p = 0; p < n; ++p) {
+            if (wall[p] >= 0) {
+                s->dg.n_absorbed[wall[p]] += 1;
+                s->dg.absorbed_W[wall[p]] += (int64_t)rint(s->w[p] * s->d.two_S);
+                continue;
+            }
+            s->r[m] = s->r[p]; s->z[m] = s->z[p]; s->vr[m] = s->vr[p];
+            s->vt[m] = s->vt[p]; s->vz[m] = s->vz[p]; s->w[m] = s->w[p]; s->key[m] = s->key[p];
+            ++m;
+        }
+        s->n = m;
+        free(wall);
+        /* 2. MCC on the survivors */
+        int64_t cap_over = 0;
+        for (int64_t p = 0; p < m; ++p) {
+            double v2 = (s->vr[p] * s->vr[p] + s->vt[p] * s->vt[p]) + s->vz[p] * s->vz[p];
+            if (v2 > vcap2) ++cap_over;
+        }
+        s->dg.n_cap_overflow += cap_over;
+        if (s->c.collisions) {
+            int nt = orc_num_threads();
+            orc_part** kids = (orc_part**)calloc(nt, sizeof(orc_part*));
+            int64_t* nk = (int64_t*)calloc(nt, sizeof(int64_t));
+            int64_t* ck = (int64_t*)calloc(nt, sizeof(int64_t));
+            int64_t n_el = 0, n_iz = 0, n_cand = 0;
+#pragma omp parallel reduction(+ : n_el, n_iz, n_cand)
+            {
+#ifdef _OPENMP
+                int t = omp_get_thread_num();
+#else
+                int t = 0;
+#endif
+#pragma omp for schedule(static)
+                for (int64_t p = 0; p < m; ++p) {
+                    orc_part ch;
+                    int ev = mcc_one(s, p, &ch);
+                    if (ev != 0) ++n_cand;
+                    if (ev == 1) ++n_el;
+                    if (ev == 2) {
+                        ++n_iz;
+                        if (nk[t] == ck[t]) {
+                            ck[t] = ck[t] ? 2 * ck[t] : 64;
+                            kids[t] = (orc_part*)realloc(kids[t], sizeof(orc_part) * ck[t]);
+                        }
+                        kids[t][nk[t]++] = ch;
+                    }
+                }
+            }
+            s->dg.n_elastic += n_el;
+            s->dg.n_ioniz += n_iz;
+            s->dg.n_null_cand += n_cand;
+            int64_t tot = 0;
+            for (int t = 0; t < nt; ++t) tot += nk[t];
+            sim_reserve(s, m + tot);
+            int64_t q = m;
+            for (int t = 0; t < nt; ++t) {
+                for (int64_t k = 0; k < nk[t]; ++k, ++q) {
+                    s->r[q] = kids[t][k].r; s->z[q] = kids[t][k].z;
+                    s->vr[q] = kids[t][k].vr; s->vt[q] = kids[t][k].vt; s->vz[q] = kids[t][k].vz;
+                    s->w[q] = kids[t][k].w; s->key[q] = kids[t][k].key;
+                }
+                free(kids[t]);
+            }
+            s->n = q;
+            free(kids); free(nk); free(ck);
+        }
+        /* 3. deposit, 4. field */
+        deposit_all(s);
+        solve_fields(s);
+        /* 5. diagnostics */
+        s->step += 1;
+        s->dg.step = s->step;
+        if (s->step % s->c.diag_interval == 0) sample_diag(s);
+    }
+    return 0;
+}
+
+void orc_get_charge(const orc_sim* s, int64_t* Q) { memcpy(Q, s->Q, sizeof(int64_t) * s->nodes); }
+void orc_get_phi(const orc_sim* s, double* phi) { memcpy(phi, s->phi, sizeof(double) * s->nodes); }
+
+void orc_get_diag(const orc_sim* s, orc_diag* d) {
+    *d = s->dg;
+    d->step = s->step;
+    d->n_live = s->n;
+    int64_t tq = 0;
+    for (int k = 0; k < s->nodes; ++k) tq += s->Q[k];
+    d->total_Q = tq;
+}
+
+void orc_get_time_avg_density(const orc_sim* s, double* n_avg) {
+    for (int k = 0; k < s->nodes; ++k) {
+        if (s->dg.n_samples == 0) { n_avg[k] = 0.0; continue; }
+        n_avg[k] = ((s->avg_acc[k] * s->d.inv_two_S) / (double)s->dg.n_samples) / s->V[k];
+    }
+}

@@ -1,0 +1,546 @@
+"""Pins of the FP64 CPU oracle against closed forms, invariants, brute force
+and the paper's printed time scales (no GPU).
+
+Each test names the part of the oracle it pins and the fact it checks; a
+dropped term, a flipped sign or a transposed index in the oracle fails at
+least one of them.
+"""
+import cmath
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+from scipy import stats
+
+import oracle
+import pic_inputs as pi
+
+E = 1.602176634e-19
+ME = 9.1093837015e-31
+EPS0 = 8.8541878128e-12
+KB = 1.380649e-23
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def quiet(**over):
+    """Small trap with collisions off, for single-particle orbit tests."""
+    c = pi.coax64(collisions=0, p_mbar=1e-12, **over)
+    return c
+
+
+def one_particle(c, r, z, vr, vt, vz, key=7):
+    return dict(r=np.array([r]), z=np.array([z]), vr=np.array([vr]), vt=np.array([vt]),
+                vz=np.array([vz]), w=np.array([c["weight"]]), key=np.array([key], dtype=np.uint64))
+
+
+def frozen_sim(c, fields, state):
+    s = oracle.Sim(c)
+    s.set_fields(**fields, frozen=1)
+    s.set_particles(state)
+    return s
+
+
+# --------------------------------------------------------------------------
+# Philox and uniforms (statistical pins only: no published answer vectors are
+# available here, so the generator's constants are pinned by behaviour).
+# --------------------------------------------------------------------------
+
+def test_philox_uniform_and_bit_balance():
+    n = 1 << 14
+    words = np.array([oracle.philox([i, 0, 5, 0], [123, 456]) for i in range(n)], dtype=np.uint64)
+    # every output bit is set half of the time
+    bits = np.stack([(words >> np.uint64(b)) & np.uint64(1) for b in range(32)], axis=-1)
+    frac = bits.mean(axis=0)
+    assert np.all(np.abs(frac - 0.5) < 5.0 * 0.5 / math.sqrt(n))
+    # u52 of (w0,w1) is uniform on (0,1)
+    u = np.array([oracle.u52(int(a), int(b)) for a, b in words[:, :2]])
+    assert stats.kstest(u, "uniform").pvalue > 1e-4
+    assert u.min() > 0.0 and u.max() < 1.0
+
+
+def test_philox_avalanche_and_key_dependence():
+    rng = np.random.default_rng(1)
+    flips = []
+    for _ in range(300):
+        ctr = [int(x) for x in rng.integers(0, 2**32, 4)]
+        key = [int(x) for x in rng.integers(0, 2**32, 2)]
+        base = oracle.philox(ctr, key)
+        bit = int(rng.integers(0, 128))
+        c2 = list(ctr)
+        c2[bit // 32] ^= 1 << (bit % 32)
+        o2 = oracle.philox(c2, key)
+        flips.append(sum(bin(a ^ b).count("1") for a, b in zip(base, o2)))
+        k2 = list(key)
+        k2[0] ^= 1
+        assert oracle.philox(ctr, k2) != base
+    # a 10-round bijective mixer flips about half of the 128 output bits
+    assert abs(np.mean(flips) - 64.0) < 2.0
+
+
+def test_u52_open_interval_and_monotone():
+    assert oracle.u52(0, 0) == 0.5 * 2.0**-52
+    assert oracle.u52(0xFFFFFFFF, 0xFFFFFFFF) == 1.0 - 0.5 * 2.0**-52
+    assert oracle.u52(0, 1 << 12) > oracle.u52(0, 0)
+
+
+# --------------------------------------------------------------------------
+# Derived constants
+# --------------------------------------------------------------------------
+
+def test_derived_constants_closed_forms():
+    c = pi.coax64()
+    d = oracle.derive(c)
+    assert d["n_n"] == pytest.approx(100.0 * 1e-6 / (KB * 300.0), rel=1e-14)
+    assert d["n_n"] == pytest.approx(2.414e16, rel=1e-3)
+    nu = d["n_n"] * (c["sigma_el"] + d["sig_iz_max"]) * d["v_cap"]
+    assert d["P_null"] == pytest.approx(1.0 - math.exp(-nu * c["dt"]), rel=1e-9)
+    assert 0.5 * ME * d["v_cap"] ** 2 / E == pytest.approx(c["E_cap_eV"], rel=1e-14)
+    # the Lotz maximum in closed form equals the numerical maximum
+    Es = np.linspace(c["iz_I_eV"] * 1.01, 400.0, 200001)
+    sig = np.array([oracle.sigma_iz(c, x) for x in Es[::50]])
+    assert d["sig_iz_max"] == pytest.approx(sig.max(), rel=1e-5)
+    assert oracle.sigma_iz(c, c["iz_I_eV"]) == 0.0
+    assert oracle.sigma_iz(c, 0.5 * c["iz_I_eV"]) == 0.0
+
+
+def test_fixed_point_shift_rule():
+    for w in (1.0, 312.5, 1250.0, 1e5, 3.3e7):
+        S = oracle.auto_shift(w)
+        assert w * 2.0**S <= 2.0**31 < w * 2.0 ** (S + 1)
+
+
+# --------------------------------------------------------------------------
+# Push: Boris rotation, remap, leapfrog positions (closed forms)
+# --------------------------------------------------------------------------
+
+def gyration_closed_form(r0, v0r, v0t, B, dt, n):
+    """Boris in a uniform Bz rotates v by alpha = 2 atan(Omega dt / 2) per
+    step (counter-clockwise for an electron in +Bz); positions follow
+    x^n = x^0 + dt V sum_{m=1..n} e^{i m alpha}."""
+    Om = E * B / ME
+    alpha = 2.0 * math.atan(0.5 * Om * dt)
+    V = complex(v0r, v0t)
+    q = cmath.exp(1j * alpha)
+    xs, vs = [], []
+    for k in range(1, n + 1):
+        x = r0 + dt * V * q * (1 - q**k) / (1 - q)
+        xs.append(x)
+        vs.append(V * q**k * cmath.exp(-1j * cmath.phase(x)))
+    return np.array(xs), np.array(vs), alpha
+
+
+def test_gyration_matches_closed_form():
+    c = quiet()
+    B = 0.28
+    st = one_particle(c, 5e-3, 30e-3, 4e5, -7e5, 0.0)
+    s = frozen_sim(c, pi.uniform_fields(c, Bz=B), st)
+    n = 1500
+    rs, vrs, vts = [], [], []
+    for _ in range(n):
+        s.step(1)
+        p = s.get_particles()
+        rs.append(p["r"][0]); vrs.append(p["vr"][0]); vts.append(p["vt"][0])
+    xs, vs, alpha = gyration_closed_form(5e-3, 4e5, -7e5, B, c["dt"], n)
+    np.testing.assert_allclose(rs, np.abs(xs), rtol=1e-12, atol=0)
+    np.testing.assert_allclose(vrs, vs.real, rtol=0, atol=1e-10 * abs(complex(4e5, -7e5)))
+    np.testing.assert_allclose(vts, vs.imag, rtol=0, atol=1e-10 * abs(complex(4e5, -7e5)))
+    assert alpha == pytest.approx(2 * math.atan(0.5 * E * B / ME * c["dt"]), rel=1e-15)
+
+
+def test_speed_conserved_under_pure_B():
+    c = quiet(mirror_k=0.3)
+    st = pi.cloud_state(c, 200, seed=4)
+    st["vz"] *= 0.0  # stay well inside in z
+    Br, Bz = oracle.bfield(c)
+    s = frozen_sim(c, dict(Er=np.zeros_like(Br), Ez=np.zeros_like(Br), Br=Br, Bz=Bz), st)
+    v0 = np.sqrt(st["vr"] ** 2 + st["vt"] ** 2 + st["vz"] ** 2)
+    s.step(3000)
+    p = s.get_particles()
+    order = np.argsort(p["key"])
+    v1 = np.sqrt(p["vr"] ** 2 + p["vt"] ** 2 + p["vz"] ** 2)[order]
+    alive = p["key"][order].astype(np.int64)
+    assert len(alive) > 150
+    np.testing.assert_allclose(v1, v0[alive], rtol=1e-12)
+
+
+def test_free_streaming_straight_line_and_angular_momentum():
+    c = quiet()
+    r0, z0, vr, vt, vz = 4e-3, 25e-3, -3e5, 8e5, 2e5
+    s = frozen_sim(c, pi.uniform_fields(c), one_particle(c, r0, z0, vr, vt, vz))
+    dt = c["dt"]
+    for n in range(1, 2001):
+        s.step(1)
+        if n % 250 == 0:
+            p = s.get_particles()
+            r_exact = math.hypot(r0 + vr * n * dt, vt * n * dt)
+            assert p["r"][0] == pytest.approx(r_exact, rel=1e-12)
+            assert p["z"][0] == pytest.approx(z0 + vz * n * dt, rel=1e-12)
+            assert p["r"][0] * p["vt"][0] == pytest.approx(r0 * vt, rel=1e-12)
+            assert math.hypot(p["vr"][0], p["vt"][0]) == pytest.approx(math.hypot(vr, vt), rel=1e-13)
+
+
+def test_exb_rigid_rotor_orbit():
+    """Circular orbit in uniform E_r, Bz: the slow root of
+    m w^2 r0 = e (E_r + w r0 Bz) (electron, q = -e); its azimuthal speed
+    approaches the E x B drift u_theta = -E_r / Bz (Sec. IV.A, eq. for u_theta)."""
+    c = quiet()
+    B, Er, r0 = 0.28, -2.0e5, 5e-3
+    disc = (E * r0 * B) ** 2 + 4.0 * ME * r0 * E * Er
+    w = (E * r0 * B - math.sqrt(disc)) / (2.0 * ME * r0)
+    vt0 = w * r0
+    vE, Om = -Er / B, E * B / ME
+    assert vt0 == pytest.approx(vE, rel=2.0 * vE / (Om * r0))
+    s = frozen_sim(c, pi.uniform_fields(c, Er=Er, Bz=B), one_particle(c, r0, 30e-3, 0.0, vt0, 0.0))
+    rs, vts = [], []
+    for _ in range(2000):
+        s.step(1)
+        p = s.get_particles()
+        rs.append(p["r"][0]); vts.append(p["vt"][0])
+    assert np.max(np.abs(np.array(rs) - r0)) / r0 < 1e-3
+    assert np.mean(vts) == pytest.approx(vt0, rel=1e-3)
+
+
+def test_cyclotron_period_vs_paper_and_limit():
+    gold = json.load(open(os.path.join(GOLD, "paper_timescales.json")))
+    B = gold["tau_ce_B_T"]
+    for dt, rel in ((1e-12, 3e-4), (1e-14, 1e-7)):
+        alpha = 2.0 * math.atan(0.5 * E * B / ME * dt)
+        T = 2.0 * math.pi / alpha * dt
+        assert T == pytest.approx(2.0 * math.pi * ME / (E * B), rel=rel)
+    # the oracle's orbit rotates by alpha per step: measure it over one period
+    c = quiet()
+    s = frozen_sim(c, pi.uniform_fields(c, Bz=B), one_particle(c, 5e-3, 30e-3, 3e5, 0.0, 0.0))
+    xs, vs, alpha = gyration_closed_form(5e-3, 3e5, 0.0, B, c["dt"], 1)
+    T_orbit = 2.0 * math.pi / alpha * c["dt"]
+    f = gold["tolerance_factor"]
+    assert gold["tau_ce_s"] / f < T_orbit < gold["tau_ce_s"] * f
+    # plasma period at the quoted density
+    wp = math.sqrt(gold["tau_pe_density_m3"] * E * E / (EPS0 * ME))
+    assert gold["tau_pe_s"] / f < 2 * math.pi / wp < gold["tau_pe_s"] * f
+
+
+def test_gather_reproduces_bilinear_fields():
+    """With B = 0 and v = 0 one step gives v_r = 2 h E_r(x) exactly (no
+    rotation since y = 0), so the gathered field is observable; bilinear
+    weights reproduce fields of the form alpha + beta r + gamma z + delta r z."""
+    c = quiet()
+    d = oracle.derive(c)
+    nr, nz = c["nr"], c["nz"]
+    r = c["a"] + d["dr"] * np.arange(nr + 1)[:, None]
+    z = d["dz"] * np.arange(nz + 1)[None, :]
+    Er = 3e5 + 2e7 * r - 5e6 * z + 4e9 * r * z
+    Ez = -1e5 + 7e6 * z + 1e7 * r
+    f = dict(Er=Er, Ez=Ez, Br=np.zeros_like(Er), Bz=np.zeros_like(Er))
+    st = pi.particle_state(c, 400, seed=11, v_scale=0.0)
+    s = frozen_sim(c, f, st)
+    s.step(1)
+    p = s.get_particles()
+    k = p["key"].astype(np.int64)
+    r0, z0 = st["r"][k], st["z"][k]
+    np.testing.assert_allclose(p["vr"] / (2 * d["h"]), 3e5 + 2e7 * r0 - 5e6 * z0 + 4e9 * r0 * z0,
+                               rtol=1e-11, atol=1e-9 * 3e5)
+    np.testing.assert_allclose(p["vz"] / (2 * d["h"]), -1e5 + 7e6 * z0 + 1e7 * r0,
+                               rtol=1e-11, atol=1e-9 * 1e5)
+
+
+# --------------------------------------------------------------------------
+# Deposit (brute force with hat functions, exact charge)
+# --------------------------------------------------------------------------
+
+def test_deposit_brute_force_hat_functions():
+    c = pi.coax64(nr=8, nz=12)
+    d = oracle.derive(c)
+    S = oracle.auto_shift(c["weight"])
+    W = round(c["weight"] * 2.0**S)
+    rn = c["a"] + d["dr"] * np.arange(c["nr"] + 1)
+    zn = d["dz"] * np.arange(c["nz"] + 1)
+    rng = np.random.default_rng(5)
+    for _ in range(200):
+        r = rng.uniform(c["a"], c["b"])
+        z = rng.uniform(0, c["L"])
+        Q = oracle.deposit_one(c, r, z, c["weight"], fx_shift=S)
+        hat_r = np.maximum(0.0, 1.0 - np.abs(r - rn) / d["dr"])
+        hat_z = np.maximum(0.0, 1.0 - np.abs(z - zn) / d["dz"])
+        N = np.outer(hat_r, hat_z)
+        assert Q.sum() == W
+        assert np.max(np.abs(Q - W * N)) <= 3.0  # rounding, plus the exact-sum remainder
+        assert np.count_nonzero(Q) <= 4
+        # first moments of the hat-function projection are preserved
+        assert abs((Q.sum(axis=1) * rn).sum() - W * r) <= 4 * d["dr"]
+        assert abs((Q.sum(axis=0) * zn).sum() - W * z) <= 4 * d["dz"]
+
+
+# --------------------------------------------------------------------------
+# Field solve (closed forms, convergence, symmetry)
+# --------------------------------------------------------------------------
+
+def coax_exact(c, r):
+    return c["V_inner"] + (c["V_outer"] - c["V_inner"]) * np.log(r / c["a"]) / math.log(c["b"] / c["a"])
+
+
+def test_vacuum_coax_second_order():
+    """With end_mode 0 and V_end = 0 the electrode data are the coaxial
+    profile V ln(r/a)/ln(b/a) everywhere; the discrete solution and the nodal
+    E converge to it at second order (E is pre-asymptotic on coarse meshes
+    because ln r curves strongly near r = a)."""
+    errs, eerrs = [], []
+    for nr in (32, 64, 128, 256):
+        c = pi.coax64(nr=nr, nz=16, V_end=0.0)
+        phi = oracle.vacuum(c)
+        d = oracle.derive(c)
+        r = c["a"] + d["dr"] * np.arange(nr + 1)
+        exact = coax_exact(c, r)[:, None]
+        errs.append(np.max(np.abs(phi - exact)) / abs(c["V_inner"]))
+        Er, Ez = oracle.efield(c, phi)
+        Er_exact = -(c["V_outer"] - c["V_inner"]) / (r * math.log(c["b"] / c["a"]))
+        eerrs.append(np.max(np.abs(Er - Er_exact[:, None])) / np.max(np.abs(Er_exact)))
+    assert errs[-1] < 2e-5
+    orders = [math.log2(errs[i] / errs[i + 1]) for i in range(3)]
+    assert min(orders) > 1.95, (errs, orders)
+    eorders = [math.log2(eerrs[i] / eerrs[i + 1]) for i in range(3)]
+    assert eorders[0] < eorders[1] < eorders[2] and eorders[2] > 1.85, (eerrs, eorders)
+
+
+def test_uniform_charge_column_closed_form():
+    """Uniform electron density n0 filling a < r < b with phi = 0 on the
+    electrodes: far from the ends phi = (e n0 / 4 eps0) r^2 + C1 ln r + C2."""
+    n0 = 1e15
+    errs = []
+    for nr in (16, 32, 64):
+        c = pi.coax64(nr=nr, nz=4 * nr)
+        S = 10
+        V = oracle.node_volume(c)
+        Q = np.rint(n0 * V * 2.0**S).astype(np.int64)
+        phi = oracle.poisson_charge(c, Q, fx_shift=S)
+        d = oracle.derive(c)
+        r = c["a"] + d["dr"] * np.arange(nr + 1)
+        k = E * n0 / (4 * EPS0)
+        a, b = c["a"], c["b"]
+        C1 = -k * (b * b - a * a) / math.log(b / a)
+        C2 = -k * a * a - C1 * math.log(a)
+        exact = k * r * r + C1 * np.log(r) + C2
+        mid = phi[:, c["nz"] // 2]
+        errs.append(np.max(np.abs(mid - exact)) / np.max(np.abs(exact)))
+    assert errs[-1] < 1e-3
+    orders = [math.log2(errs[i] / errs[i + 1]) for i in range(len(errs) - 1)]
+    assert min(orders) > 1.7, (errs, orders)
+
+
+def test_poisson_green_reciprocity():
+    c = pi.coax64(nr=12, nz=20)
+    rng = np.random.default_rng(2)
+    for _ in range(6):
+        p = (int(rng.integers(1, 12)), int(rng.integers(1, 20)))
+        q = (int(rng.integers(1, 12)), int(rng.integers(1, 20)))
+        rp = np.zeros((13, 21)); rp[p] = 1.0
+        rq = np.zeros((13, 21)); rq[q] = 1.0
+        gp, gq = oracle.solve(c, rp), oracle.solve(c, rq)
+        assert gp[q] == pytest.approx(gq[p], rel=1e-12)
+        assert gp[p] > 0 and gq[q] > 0  # the operator is positive definite
+
+
+def test_node_volume_uniform_density():
+    """A quasi-uniform volume load (midpoint rule in r^2 and z) deposits
+    n0 V_i at every node, so the sampled density equals n0."""
+    c = pi.coax64(nr=16, nz=32, collisions=0)
+    K, M = 400, 320
+    a, b, L = c["a"], c["b"], c["L"]
+    r = np.sqrt(a * a + (np.arange(K) + 0.5) / K * (b * b - a * a))
+    z = (np.arange(M) + 0.5) / M * L
+    R, Z = np.meshgrid(r, z, indexing="ij")
+    n = R.size
+    n0 = 1e15
+    w = n0 * math.pi * (b * b - a * a) * L / n
+    c["weight"] = w
+    st = dict(r=R.ravel(), z=Z.ravel(), vr=np.zeros(n), vt=np.zeros(n), vz=np.zeros(n),
+              w=np.full(n, w), key=np.arange(n, dtype=np.uint64))
+    s = oracle.Sim(c)
+    s.set_particles(st)
+    V = oracle.node_volume(c)
+    dens = s.charge() * 2.0**-s.S / V
+    assert np.allclose(dens[1:-1, 1:-1], n0, rtol=2e-3)
+    assert np.allclose(dens, n0, rtol=3e-2)  # boundary rows: midpoint-rule error only
+    assert V.sum() == pytest.approx(math.pi * (b * b - a * a) * L, rel=1e-12)
+
+
+# --------------------------------------------------------------------------
+# Collision sampling
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("xi", [0.0, 0.5, 0.9, -0.3])
+def test_okhrimovskyy_cdf(xi):
+    u = (np.arange(4000) + 0.5) / 4000
+    rng = np.random.default_rng(3)
+    u = rng.uniform(size=20000)
+    mu = np.array([oracle.okh_cos(xi, x) for x in u])
+    assert mu.min() >= -1.0 and mu.max() <= 1.0
+    if xi == 0.0:
+        cdf = lambda m: (m + 1.0) / 2.0
+    else:
+        cdf = lambda m: (1 - xi * xi) / (2 * xi) * (1.0 / (1.0 - xi * m) - 1.0 / (1.0 + xi))
+    assert stats.kstest(mu, cdf).pvalue > 1e-4
+
+
+def test_opal_cdf():
+    Ebar, E_av = 10.0, 200.0
+    rng = np.random.default_rng(4)
+    Es = np.array([oracle.opal_split(Ebar, E_av, x) for x in rng.uniform(size=20000)])
+    assert Es.min() >= 0.0 and Es.max() <= E_av / 2.0 * (1 + 1e-15)
+    cdf = lambda e: np.arctan(e / Ebar) / math.atan(E_av / (2 * Ebar))
+    assert stats.kstest(Es, cdf).pvalue > 1e-4
+
+
+def test_scatter_geometry():
+    rng = np.random.default_rng(6)
+    for _ in range(500):
+        u = rng.normal(size=3)
+        u /= np.linalg.norm(u)
+        if rng.uniform() < 0.2:
+            u = np.array([0.05, 0.02, math.copysign(1.0, rng.normal())])
+            u /= np.linalg.norm(u)
+        cx = rng.uniform(-1, 1)
+        ph = rng.uniform(0, 2 * math.pi)
+        o = oracle.scatter(u, cx, ph)
+        assert np.linalg.norm(o) == pytest.approx(1.0, abs=1e-15)
+        assert float(o @ u) == pytest.approx(cx, abs=1e-14)
+    # azimuth uniform: the mean over phi is cos(chi) u
+    u = np.array([0.6, 0.0, 0.8])
+    outs = np.array([oracle.scatter(u, 0.3, ph) for ph in np.linspace(0, 2 * math.pi, 4000, endpoint=False)])
+    np.testing.assert_allclose(outs.mean(axis=0), 0.3 * u, atol=1e-12)
+
+
+def rate_cfg(p_mbar):
+    return pi.coax64(p_mbar=p_mbar, lotz_a=0.0, M_gas_amu=1e12, E_cap_eV=10.0,
+                     collisions=1, diag_interval=1)
+
+
+def test_null_collision_rate_constant_sigma():
+    """Monoenergetic particles, constant sigma, no fields: candidate and real
+    event counts are binomial with p = P_null and p = P_null v0 / v_cap, and the
+    real rate approaches n sigma v0 dt."""
+    c = rate_cfg(10.0)
+    d = oracle.derive(c)
+    n, K = 20000, 100
+    v0 = 1.0e6
+    rng = np.random.default_rng(8)
+    u = rng.normal(size=(3, n))
+    u /= np.linalg.norm(u, axis=0)
+    st = dict(r=np.full(n, 5e-3), z=np.full(n, 30e-3), vr=v0 * u[0], vt=v0 * u[1], vz=v0 * u[2],
+              w=np.full(n, c["weight"]), key=np.arange(n, dtype=np.uint64))
+    s = frozen_sim(c, pi.uniform_fields(c), st)
+    s.step(K)
+    dg = s.diag()
+    trials = n * K
+    p_cand = d["P_null"]
+    assert abs(dg["n_null_cand"] - trials * p_cand) < 5 * math.sqrt(trials * p_cand * (1 - p_cand))
+    p_el = d["P_null"] * v0 / d["v_cap"]
+    assert abs(dg["n_elastic"] - trials * p_el) < 5 * math.sqrt(trials * p_el * (1 - p_el))
+    nu_dt = d["n_n"] * c["sigma_el"] * v0 * c["dt"]
+    assert dg["n_elastic"] / trials == pytest.approx(nu_dt, rel=d["nu_prime"] * c["dt"] + 5 / math.sqrt(trials * p_el))
+    assert dg["n_ioniz"] == 0
+
+
+def _step_pair(c, st):
+    """Same particles stepped with and without collisions."""
+    f = pi.uniform_fields(c)
+    a = frozen_sim(dict(c, collisions=0), f, st)
+    b = frozen_sim(c, f, st)
+    a.step(1)
+    b.step(1)
+    return a.get_particles(), b.get_particles(), b.diag()
+
+
+def test_elastic_energy_loss_matches_angle():
+    c = pi.coax64(p_mbar=300.0, lotz_a=0.0, M_gas_amu=4.0, E_cap_eV=2000.0)
+    d = oracle.derive(c)
+    st = pi.cloud_state(c, 4000, seed=9)
+    pre, post, dg = _step_pair(c, st)
+    assert dg["n_elastic"] > 50
+    i0 = np.argsort(pre["key"]); i1 = np.argsort(post["key"])
+    v0 = np.stack([pre[k][i0] for k in ("vr", "vt", "vz")])
+    v1 = np.stack([post[k][i1] for k in ("vr", "vt", "vz")])
+    s0, s1 = np.linalg.norm(v0, axis=0), np.linalg.norm(v1, axis=0)
+    hit = np.abs(s1 / s0 - 1.0) > 1e-13
+    assert hit.sum() == dg["n_elastic"]
+    cosx = (v0 * v1).sum(axis=0)[hit] / (s0[hit] * s1[hit])
+    np.testing.assert_allclose((s1[hit] / s0[hit]) ** 2, 1.0 - d["mass_ratio2"] * (1.0 - cosx), rtol=1e-12)
+
+
+def test_ionisation_energy_balance_and_child():
+    c = pi.coax64(p_mbar=300.0, sigma_el=0.0, lotz_a=4.5e-16, E_cap_eV=2000.0)
+    st = pi.cloud_state(c, 4000, seed=10)
+    pre, post, dg = _step_pair(c, st)
+    assert dg["n_ioniz"] > 50 and dg["n_elastic"] == 0
+    kids = post["key"] >= np.uint64(1 << 63)
+    assert kids.sum() == dg["n_ioniz"]
+    assert len(post["key"]) == len(pre["key"]) + dg["n_ioniz"]
+    pre_by_pos = {(r, z): i for i, (r, z) in enumerate(zip(pre["r"], pre["z"]))}
+    post_by_key = {int(k): i for i, k in enumerate(post["key"])}
+    half_m_e = 0.5 * ME / E
+    for j in np.nonzero(kids)[0]:
+        i = pre_by_pos[(post["r"][j], post["z"][j])]
+        par = post_by_key[int(pre["key"][i])]
+        E0 = half_m_e * (pre["vr"][i] ** 2 + pre["vt"][i] ** 2 + pre["vz"][i] ** 2)
+        Ep = half_m_e * (post["vr"][par] ** 2 + post["vt"][par] ** 2 + post["vz"][par] ** 2)
+        Es = half_m_e * (post["vr"][j] ** 2 + post["vt"][j] ** 2 + post["vz"][j] ** 2)
+        assert E0 > c["iz_I_eV"]
+        assert Ep + Es == pytest.approx(E0 - c["iz_I_eV"], rel=1e-12, abs=1e-12)
+        assert Es <= 0.5 * (E0 - c["iz_I_eV"]) * (1 + 1e-12)
+        assert post["w"][j] == pre["w"][i]
+
+
+# --------------------------------------------------------------------------
+# Load and whole-run invariants
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_initial_load_distribution(mode):
+    c = pi.coax64(n_init=40000, load_mode=mode, T_init_eV=2.0)
+    s = oracle.Sim(c)
+    s.load()
+    p = s.get_particles()
+    assert np.array_equal(np.sort(p["key"]), np.arange(40000, dtype=np.uint64))
+    u = (p["z"] - c["z_lo"]) / (c["z_hi"] - c["z_lo"])
+    assert stats.kstest(u, "uniform").pvalue > 1e-4
+    if mode == 1:
+        ur = (p["r"] - c["r_lo"]) / (c["r_hi"] - c["r_lo"])
+    else:
+        ur = (p["r"] ** 2 - c["r_lo"] ** 2) / (c["r_hi"] ** 2 - c["r_lo"] ** 2)
+    assert stats.kstest(ur, "uniform").pvalue > 1e-4
+    sv = math.sqrt(c["T_init_eV"] * E / ME)
+    for k in ("vr", "vt", "vz"):
+        assert stats.kstest(p[k] / sv, "norm").pvalue > 1e-4
+
+
+def test_charge_bookkeeping_with_collisions():
+    c = pi.coax64hot(n_init=20000)
+    s = oracle.Sim(c)
+    s.load()
+    W = round(c["weight"] * 2.0**s.S)
+    q0 = s.diag()["total_Q"]
+    assert q0 == 20000 * W
+    s.step(200)
+    dg = s.diag()
+    p = s.get_particles()
+    assert dg["n_ioniz"] > 0 and dg["n_elastic"] > 0
+    assert dg["total_Q"] == len(p["r"]) * W == s.charge().sum()
+    assert dg["n_live"] + sum(dg["n_absorbed"]) == 20000 + dg["n_ioniz"]
+    assert dg["total_Q"] + sum(dg["absorbed_W"]) == q0 + dg["n_ioniz"] * W
+    assert np.all((p["r"] > c["a"]) & (p["r"] < c["b"]) & (p["z"] > 0) & (p["z"] < c["L"]))
+
+
+def test_absorbing_walls_and_current():
+    """Particles launched straight at the outer electrode are all absorbed
+    there and the windowed current equals their charge over the window."""
+    c = pi.coax64(collisions=0, diag_interval=50)
+    n = 500
+    st = dict(r=np.full(n, 9.9e-3), z=np.linspace(10e-3, 50e-3, n), vr=np.full(n, 2e6),
+              vt=np.zeros(n), vz=np.zeros(n), w=np.full(n, c["weight"]), key=np.arange(n, dtype=np.uint64))
+    s = frozen_sim(c, pi.uniform_fields(c), st)
+    s.step(50)
+    dg = s.diag()
+    assert dg["n_absorbed"] == [0, n, 0, 0] and dg["n_live"] == 0
+    assert dg["I_wall"][1] == pytest.approx(n * c["weight"] * E / (50 * c["dt"]), rel=1e-12)
+    assert dg["peak_I_outer"] == dg["I_wall"][1]
