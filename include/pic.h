@@ -1,0 +1,257 @@
+/*
+ * pic.h -- C ABI of the MI355X (gfx950) particle loop of an axisymmetric
+ * 2D3V (r,z) particle-in-cell code with Monte-Carlo electron-neutral
+ * collisions (Le Bars et al., arXiv 2206.14662, Sec. II.A "Numerical model"
+ * and Sec. II.B "Geometry and numerical parameters").
+ *
+ * The problem the calls describe (Sec. II.A-B): electrons between two coaxial
+ * electrodes with an applied bias, an external (possibly non-uniform) axial
+ * magnetic field, perfectly absorbing walls, a uniform constant neutral gas
+ * given by its pressure and temperature, elastic and ionising collisions
+ * given by their cross sections; ions are not followed.  One step advances
+ * every instance by dt: gather + Boris push + cylindrical remap + absorb,
+ * null-collision MCC (elastic, ionisation with a new electron), charge
+ * deposit, FP64 Poisson solve.
+ *
+ * Conventions
+ *   - Units are SI unless a name says otherwise (_eV, _mbar, _amu).
+ *   - Node arrays are r-major: node (i,j), i in [0,nr], j in [0,nz], sits at
+ *     index i*(nz+1)+j; r_i = a + i (b-a)/nr, z_j = j L/nz.
+ *   - Every call returns a pic_status; nothing throws or aborts across the
+ *     ABI.  pic_last_error() gives a message for the last failing call.
+ *   - Host buffers passed in are owned by the caller and only read or
+ *     written during the call.  Device memory is owned by the context and
+ *     released by pic_destroy(); it comes from the caller's allocator when
+ *     one is given in pic_run_cfg, else from hipMalloc.
+ *   - pic_step() is asynchronous on the context's stream.  Device-side error
+ *     flags (spawn overflow, fixed-point overflow) are sticky and reported by
+ *     the next call that synchronises (pic_diag, pic_get_*, pic_sync).
+ *   - One context must not be used from two host threads at once.
+ */
+#ifndef PIC_H
+#define PIC_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pic_ctx pic_ctx;
+
+typedef enum {
+    PIC_OK = 0,
+    PIC_EINVAL = -1,     /* bad argument or configuration                        */
+    PIC_ENOMEM = -2,     /* device or host allocation failed                     */
+    PIC_EDEVICE = -3,    /* HIP runtime error (message in pic_last_error)        */
+    PIC_ECAPACITY = -4,  /* particle storage full: new electrons were dropped    */
+    PIC_EOVERFLOW = -5,  /* a weight does not fit the fixed-point charge scale   */
+    PIC_ESTATE = -6      /* call not valid in the current state                  */
+} pic_status;
+
+typedef enum {
+    PIC_MODE_FP64_PLAIN = 0,   /* FP64 particles, one kernel per stage, no sort  */
+    PIC_MODE_FP32_BATCHED = 1  /* FP32 particles, tile-sorted, fused, persistent */
+} pic_mode;
+
+/* Device memory provider.  alloc returns a device pointer of at least
+ * `bytes` bytes (256-byte aligned) or NULL; free releases it. */
+typedef struct {
+    void* (*alloc)(size_t bytes, void* user);
+    void (*free)(void* ptr, void* user);
+    void* user;
+} pic_allocator;
+
+/* One simulation instance (one coaxial trap). */
+typedef struct {
+    double a, b, L;            /* inner radius, outer radius, length (m); 0<a<b  */
+    int nr, nz;                /* cells in r and z; nz a power of two >= 4       */
+    double V_inner, V_outer;   /* electrode potentials at r=a, r=b (V)           */
+    double V_end;              /* end electrodes at z=0,L (V), see end_mode      */
+    int end_mode;              /* 0: phi_end(r) = phi_coax(r) + V_end; 1: V_end  */
+    double B0, mirror_k;       /* Bz = B0 (1 + k zeta^2), zeta = (z-L/2)/(L/2),
+                                  Br = -(r/2) dBz/dz                             */
+    double p_mbar, T_gas_K;    /* neutral pressure and temperature: n = p/(kT)   */
+    double M_gas_amu;          /* neutral mass (elastic recoil loss)             */
+    double sigma_el;           /* elastic momentum-transfer cross section (m^2)  */
+    double iz_I_eV;            /* ionisation threshold = binding energy (eV)     */
+    double lotz_a, lotz_q;     /* Lotz sigma_iz = a q ln(E/I)/(E I), a [m^2 eV^2] */
+    double opal_Ebar_eV;       /* Opal energy-split parameter (eV)               */
+    double okh_xi;             /* Okhrimovskyy DCS parameter in [0,1), 0 isotropic */
+    double E_cap_eV;           /* energy bound of the null-collision frequency   */
+    long long n_init;          /* initial macro-electrons                        */
+    double r_lo, r_hi, z_lo, z_hi; /* initial load box (m)                       */
+    double T_init_eV;          /* Maxwellian temperature of the load (eV)        */
+    double weight;             /* electrons per macro-electron                   */
+    int load_mode;             /* 0: uniform in volume, 1: uniform in r          */
+    unsigned long long seed;   /* Philox key of the instance                     */
+    double dt;                 /* time step (s)                                  */
+    int fx_shift;              /* S of the 2^S fixed-point charge; 0 = automatic */
+    int diag_interval;         /* D: steps between density/current samples      */
+    int collisions;            /* 0 switches the MCC stage off                   */
+} pic_instance_cfg;
+
+typedef struct {
+    int mode;                  /* pic_mode                                       */
+    int n_instances;           /* >= 1; PIC_MODE_FP64_PLAIN loops over them      */
+    int tile_r, tile_z;        /* sort tile in cells (FP32 form); 0 = default    */
+    int halo;                  /* LDS deposit-window halo in cells; 0 = default  */
+    int sort_interval;         /* steps between tile sorts; 0 = default          */
+    int chunk;                 /* max particles per work item; 0 = default       */
+    int use_graph;             /* 1: replay the step as a captured HIP graph     */
+    int device;                /* HIP device ordinal                             */
+    void* stream;              /* hipStream_t to run on; NULL = a library stream */
+    pic_allocator alloc;       /* alloc == NULL: hipMalloc/hipFree               */
+    double capacity_factor;    /* particle slots = factor * n_init; 0 = 2.0      */
+    long long capacity_min;    /* lower bound on slots per instance; 0 = 4096    */
+} pic_run_cfg;
+
+/* Per-instance diagnostics (Sec. III.A: peak density and boundary currents). */
+typedef struct {
+    long long step;            /* steps taken                                    */
+    long long n_live;          /* live macro-electrons                           */
+    long long n_elastic, n_ioniz;   /* real collision events so far              */
+    long long n_null_cand;     /* null-collision candidates (u < P_null)         */
+    long long n_cap_overflow;  /* particle-steps with |v| > v_cap                */
+    long long n_spawn_dropped; /* new electrons lost to a full buffer (must be 0) */
+    long long n_absorbed[4];   /* absorbed macro-electrons: inner, outer, left, right */
+    long long absorbed_W[4];   /* absorbed charge per wall, units 2^-S electrons */
+    long long total_Q;         /* sum of the deposited grid, units 2^-S electrons */
+    long long n_samples;       /* density samples in the time average            */
+    int S;                     /* fixed-point shift                              */
+    double total_charge_C;     /* -e 2^-S total_Q                                */
+    double I_wall[4];          /* last-window electron current into each wall (A) */
+    double peak_density;       /* time max of the spatial max density (m^-3)    */
+    double peak_time_avg_density; /* spatial max of the time-averaged density    */
+    double peak_I_outer, peak_I_inner; /* max over windows of I_wall[1], I_wall[0] */
+} pic_diag_t;
+
+/* Host-derived constants of an instance (FP64); see pic_derive. */
+typedef struct {
+    double dr, dz, inv_dr, inv_dz;
+    double h;                  /* (q/m) dt / 2 with q = -e                       */
+    double n_n;                /* neutral density 100 p_mbar / (k_B T) (m^-3)    */
+    double v_cap, sig_iz_max, nu_prime, P_null;
+    double nsig_el, lotz_aq, half_me_over_e, two_e_over_me, mass_ratio2;
+    double two_S, inv_two_S;
+    double bscale;             /* Q -> FEM load / eps0: -e 2^-S / (2 pi eps0)    */
+} pic_derived_t;
+
+/*
+ * pic_init -- create a context: validate every instance, derive constants,
+ * allocate device storage, build the static B and the vacuum potential
+ * (discrete Laplace solution with the electrode data), load n_init
+ * Maxwellian electrons per instance from the instance's Philox stream
+ * (Sec. III.A initial homogeneous Maxwellian cloud), deposit them and solve
+ * for the first field.  run->n_instances entries of inst are read.
+ * Errors: PIC_EINVAL (bad configuration; nz must be a power of two),
+ * PIC_ENOMEM, PIC_EDEVICE, PIC_EOVERFLOW (weight too large for S).  On
+ * error *out is NULL and nothing is leaked.
+ */
+pic_status pic_init(const pic_run_cfg* run, const pic_instance_cfg* inst, pic_ctx** out);
+
+/*
+ * pic_step -- advance every instance by n_steps steps (Sec. II.A particle
+ * loop: Boris push, absorbing walls, Monte-Carlo collisions, deposit,
+ * Poisson).  Asynchronous on the context's stream.  Errors: PIC_EINVAL
+ * (n_steps < 0), PIC_EDEVICE, PIC_ECAPACITY (reported when a capacity check
+ * between sort intervals finds dropped electrons).
+ */
+pic_status pic_step(pic_ctx* ctx, int n_steps);
+
+/*
+ * pic_diag -- synchronise and copy instance `inst`'s diagnostics to *out.
+ * density and time_avg_density are optional host arrays of (nr+1)(nz+1)
+ * doubles receiving the current density Q 2^-S / V_i and the time average
+ * over the samples taken every diag_interval steps, where V_i is the FEM
+ * node volume (integral of the hat function over 2 pi r dr dz).
+ */
+pic_status pic_diag(pic_ctx* ctx, int inst, pic_diag_t* out, double* density,
+                    double* time_avg_density);
+
+/* pic_destroy -- release all device memory, streams and graphs of ctx. */
+pic_status pic_destroy(pic_ctx* ctx);
+
+/* pic_last_error -- message of the last failing call on ctx (or of the last
+ * failing pic_init when ctx is NULL); valid until the next call. */
+const char* pic_last_error(const pic_ctx* ctx);
+
+/* pic_sync -- wait for the context's stream and report sticky device errors. */
+pic_status pic_sync(pic_ctx* ctx);
+
+/*
+ * pic_get_particles -- copy instance `inst`'s live particles to host FP64
+ * arrays of `cap` entries (storage order, FP32 values widened), set *n to
+ * the live count.  Keys identify particles across steps: loaded electrons
+ * have keys 0..n_init-1, electrons created by ionisation have the top bit
+ * set.  If cap < *n only cap entries are written and PIC_EINVAL is returned.
+ */
+pic_status pic_get_particles(pic_ctx* ctx, int inst, double* r, double* z, double* vr,
+                             double* vt, double* vz, double* w, unsigned long long* key,
+                             long long cap, long long* n);
+
+/*
+ * pic_set_particles -- replace instance `inst`'s particles with n host FP64
+ * particles (velocities are v^{n-1/2}), redeposit and, unless the field is
+ * frozen, solve for the field.  Every particle must lie in a<r<b, 0<z<L.
+ * Errors: PIC_EINVAL, PIC_ECAPACITY (n above the slots), PIC_EOVERFLOW.
+ */
+pic_status pic_set_particles(pic_ctx* ctx, int inst, long long n, const double* r,
+                             const double* z, const double* vr, const double* vt,
+                             const double* vz, const double* w,
+                             const unsigned long long* key);
+
+/*
+ * pic_set_fields -- overwrite instance `inst`'s nodal fields with host FP64
+ * node arrays (NULL leaves a component unchanged).  frozen = 1 keeps E fixed
+ * (the Poisson stage is skipped; charge is still deposited), frozen = 0
+ * returns to the self-consistent field at the next solve.
+ */
+pic_status pic_set_fields(pic_ctx* ctx, int inst, const double* Er, const double* Ez,
+                          const double* Br, const double* Bz, int frozen);
+
+/* pic_get_fields -- copy the nodal fields the next push will gather (FP64
+ * node arrays; NULL skips a component). */
+pic_status pic_get_fields(pic_ctx* ctx, int inst, double* Er, double* Ez, double* Br,
+                          double* Bz);
+
+/* pic_get_charge -- copy the last deposited fixed-point grid (units 2^-S
+ * electrons, FEM-weighted node charge) of instance `inst`. */
+pic_status pic_get_charge(pic_ctx* ctx, int inst, long long* Q);
+
+/* pic_get_phi -- copy the last solved potential (V) of instance `inst`. */
+pic_status pic_get_phi(pic_ctx* ctx, int inst, double* phi);
+
+/* pic_set_step -- set the step counter that keys the Philox streams
+ * (checkpoint/resume: a resumed run draws the same numbers). */
+pic_status pic_set_step(pic_ctx* ctx, long long step);
+
+/*
+ * pic_derive -- host-only: the FP64 constants one instance derives (mesh
+ * spacings, (q/m)dt/2, neutral density, null-collision bound and P_null,
+ * fixed-point scale).  S is the fixed-point shift; S = 0 picks it
+ * automatically (pic_auto_shift).  Needs no GPU.
+ */
+pic_status pic_derive(const pic_instance_cfg* inst, int S, pic_derived_t* out);
+
+/* pic_auto_shift -- host-only: largest S with w_max 2^S <= 2^31. */
+int pic_auto_shift(double w_max);
+
+/*
+ * pic_timing -- event timing of the dominant particle kernel.  enable = 1
+ * records HIP events around every particle-kernel launch on the context's
+ * stream in later pic_step calls (steps then run as plain launches, not a
+ * graph); the call resets the accumulators.  With enable = 0 it returns the
+ * number of timed launches and their summed duration (ms) since the last
+ * reset, synchronising first.
+ */
+pic_status pic_timing(pic_ctx* ctx, int enable, long long* launches, double* total_ms);
+
+/* pic_tuning -- the tile shape, halo, sort interval and chunk in use. */
+pic_status pic_tuning(pic_ctx* ctx, int* tile_r, int* tile_z, int* halo, int* sort_interval,
+                      int* chunk);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,980 @@
+// api.hip -- host side of the C ABI declared in include/pic.h: validation,
+// derived constants, device storage, the vacuum potential, the step
+// sequence of both forms, checkpoint hooks and diagnostics.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "pic_internal.h"
+#include "fp32.h"
+
+using namespace pic;
+
+struct Inst {
+    pic_instance_cfg c;
+    pic_derived_t d;
+    DevInst I;
+    int S = 0;
+    long long cap = 0;
+    long long nodes = 0;
+    bool frozen = false;
+    P64 p64[2];
+    int cur = 0;
+    long long* Q = nullptr;
+    double *rhs = nullptr, *phi = nullptr, *phi_vac = nullptr, *phiB = nullptr;
+    double *Er = nullptr, *Ez = nullptr, *Br = nullptr, *Bz = nullptr, *V = nullptr;
+    double *avg_acc = nullptr, *th_cp = nullptr, *th_im = nullptr, *th_lo = nullptr;
+    float4* EB = nullptr;
+    long long* cnt = nullptr;
+    std::vector<double> V_host;
+};
+
+struct pic_ctx {
+    pic_run_cfg run;
+    int mode = 0;
+    std::vector<Inst> in;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    std::string err;
+    std::vector<void*> allocs;
+    DevInst* dI = nullptr;
+    FieldDev* dF = nullptr;
+    FieldDev* dFvac = nullptr;
+    double* dbscale = nullptr;
+    long long* dcnt = nullptr;
+    long long* dtmp = nullptr;
+    double2* tw = nullptr;
+    int tw_n = 0;
+    int max_nr = 0, max_nz = 0;
+    long long max_nodes = 0;
+    long long host_step = 0;
+    bool timing = false;
+    std::vector<hipEvent_t> ev;      // pairs (start, stop)
+    size_t ev_used = 0;
+    long long timed_launches = 0;
+    double timed_ms = 0.0;
+    F32State* f32 = nullptr;
+};
+
+static std::string g_init_error;
+
+// ---------------------------------------------------------------------------
+// helpers
+// ---------------------------------------------------------------------------
+
+#define CK(call)                                                                     \
+    do {                                                                             \
+        hipError_t e_ = (call);                                                      \
+        if (e_ != hipSuccess) return fail(ctx, PIC_EDEVICE, std::string(#call) + ": " + \
+                                          hipGetErrorString(e_));                    \
+    } while (0)
+
+static pic_status fail(pic_ctx* ctx, pic_status st, const std::string& msg) {
+    if (ctx) ctx->err = msg;
+    else g_init_error = msg;
+    return st;
+}
+
+void* pic_dev_alloc(pic_ctx* ctx, size_t bytes) {
+    if (bytes == 0) bytes = 256;
+    void* p = nullptr;
+    if (ctx->run.alloc.alloc) {
+        p = ctx->run.alloc.alloc(bytes, ctx->run.alloc.user);
+    } else {
+        if (hipMalloc(&p, bytes) != hipSuccess) p = nullptr;
+    }
+    if (p) ctx->allocs.push_back(p);
+    return p;
+}
+
+void pic_dev_free(pic_ctx* ctx, void* p) {
+    if (!p) return;
+    auto it = std::find(ctx->allocs.begin(), ctx->allocs.end(), p);
+    if (it != ctx->allocs.end()) ctx->allocs.erase(it);
+    if (ctx->run.alloc.alloc) {
+        if (ctx->run.alloc.free) ctx->run.alloc.free(p, ctx->run.alloc.user);
+    } else {
+        (void)hipFree(p);
+    }
+}
+
+hipStream_t pic_stream(pic_ctx* ctx) { return ctx->stream; }
+
+template <class T>
+static T* dalloc(pic_ctx* ctx, long long count) {
+    return (T*)pic_dev_alloc(ctx, sizeof(T) * (size_t)(count > 0 ? count : 1));
+}
+
+// ---------------------------------------------------------------------------
+// host-only: derived constants (same expressions and order as documented for
+// the FP64 form; evaluated once per instance)
+// ---------------------------------------------------------------------------
+
+extern "C" int pic_auto_shift(double w_max) {
+    int S = 0;
+    while (ldexp(w_max, S + 1) <= 2147483648.0) ++S;
+    while (ldexp(w_max, S) > 2147483648.0) --S;
+    return S;
+}
+
+extern "C" pic_status pic_derive(const pic_instance_cfg* c, int S, pic_derived_t* d) {
+    if (!c || !d) return PIC_EINVAL;
+    if (S == 0) S = c->fx_shift != 0 ? c->fx_shift : pic_auto_shift(c->weight);
+    d->dr = (c->b - c->a) / (double)c->nr;
+    d->dz = c->L / (double)c->nz;
+    d->inv_dr = 1.0 / d->dr;
+    d->inv_dz = 1.0 / d->dz;
+    double qm = -kE / kMe;
+    d->h = (0.5 * qm) * c->dt;
+    d->n_n = (100.0 * c->p_mbar) / (kKb * c->T_gas_K);
+    d->v_cap = sqrt(((2.0 * c->E_cap_eV) * kE) / kMe);
+    d->sig_iz_max = (c->lotz_a * c->lotz_q) / ((exp(1.0) * c->iz_I_eV) * c->iz_I_eV);
+    d->nu_prime = (d->n_n * (c->sigma_el + d->sig_iz_max)) * d->v_cap;
+    d->P_null = -expm1(-(d->nu_prime * c->dt));
+    d->nsig_el = d->n_n * c->sigma_el;
+    d->lotz_aq = c->lotz_a * c->lotz_q;
+    d->half_me_over_e = (0.5 * kMe) / kE;
+    d->two_e_over_me = (2.0 * kE) / kMe;
+    d->mass_ratio2 = (2.0 * kMe) / (c->M_gas_amu * kAmu);
+    d->two_S = ldexp(1.0, S);
+    d->inv_two_S = ldexp(1.0, -S);
+    d->bscale = ((-kE) * d->inv_two_S) / ((2.0 * kPi) * kEps0);
+    return PIC_OK;
+}
+
+// Integer form of the null test: u52(x) < P  <=>  (x >> 12) < k.
+static unsigned long long null_threshold(double P) {
+    if (!(P > 0.0)) return 0ull;
+    double lim = 4503599627370496.0;  // 2^52
+    double x = P * lim;
+    unsigned long long k = x >= lim ? (1ull << 52) : (unsigned long long)x;
+    while (k > 0 && (((double)(k - 1) + 0.5) * 0x1p-52) >= P) --k;
+    while (k < (1ull << 52) && (((double)k + 0.5) * 0x1p-52) < P) ++k;
+    return k;
+}
+
+static bool is_pow2(int x) { return x > 0 && (x & (x - 1)) == 0; }
+
+static std::string validate(const pic_instance_cfg& c) {
+    if (!(c.a > 0.0 && c.b > c.a && c.L > 0.0)) return "need 0 < a < b and L > 0";
+    if (c.nr < 4 || c.nr > 16384) return "nr must be in [4, 16384]";
+    if (!is_pow2(c.nz) || c.nz < 4 || c.nz > 4096) return "nz must be a power of two in [4, 4096]";
+    if (!(c.dt > 0.0)) return "dt must be > 0";
+    if (!(c.T_gas_K > 0.0) || !(c.p_mbar >= 0.0)) return "need T_gas_K > 0 and p_mbar >= 0";
+    if (!(c.M_gas_amu > 0.0)) return "M_gas_amu must be > 0";
+    if (!(c.sigma_el >= 0.0) || !(c.lotz_a >= 0.0) || !(c.lotz_q >= 0.0)) return "cross sections must be >= 0";
+    if (!(c.iz_I_eV > 0.0) || !(c.opal_Ebar_eV > 0.0)) return "iz_I_eV and opal_Ebar_eV must be > 0";
+    if (!(c.okh_xi > -1.0 && c.okh_xi < 1.0)) return "okh_xi must be in (-1, 1)";
+    if (!(c.E_cap_eV > 0.0)) return "E_cap_eV must be > 0";
+    if (c.n_init < 0) return "n_init must be >= 0";
+    if (c.n_init > 0) {
+        if (!(c.r_lo >= c.a && c.r_hi <= c.b && c.r_lo < c.r_hi)) return "load box must satisfy a <= r_lo < r_hi <= b";
+        if (!(c.z_lo >= 0.0 && c.z_hi <= c.L && c.z_lo < c.z_hi)) return "load box must satisfy 0 <= z_lo < z_hi <= L";
+        if (!(c.T_init_eV >= 0.0) || !(c.weight > 0.0)) return "need T_init_eV >= 0 and weight > 0";
+    }
+    if (c.load_mode != 0 && c.load_mode != 1) return "load_mode must be 0 or 1";
+    if (c.end_mode != 0 && c.end_mode != 1) return "end_mode must be 0 or 1";
+    if (c.diag_interval < 0) return "diag_interval must be >= 0";
+    return "";
+}
+
+// ---------------------------------------------------------------------------
+// host-side static arrays of an instance
+// ---------------------------------------------------------------------------
+
+static double r_at(const pic_instance_cfg& c, double dr, double i) { return c.a + i * dr; }
+
+static void host_bfield(const pic_instance_cfg& c, std::vector<double>& Br, std::vector<double>& Bz) {
+    const int W = c.nz + 1;
+    const double dr = (c.b - c.a) / (double)c.nr, dz = c.L / (double)c.nz;
+    const double halfL = 0.5 * c.L;
+    Br.assign((size_t)(c.nr + 1) * W, 0.0);
+    Bz.assign((size_t)(c.nr + 1) * W, 0.0);
+    for (int i = 0; i <= c.nr; ++i) {
+        double r = r_at(c, dr, (double)i);
+        for (int j = 0; j <= c.nz; ++j) {
+            double z = (double)j * dz;
+            double zeta = (z - halfL) / halfL;
+            size_t n = (size_t)i * W + j;
+            Bz[n] = c.B0 * (1.0 + c.mirror_k * (zeta * zeta));
+            Br[n] = -(r * ((c.B0 * c.mirror_k) * zeta)) / halfL;
+        }
+    }
+}
+
+// 1D assembled FEM entries between node i and i+di (r with weight r, z plain).
+static double kr(const pic_instance_cfg& c, double dr, int i, int di) {
+    double rm = r_at(c, dr, i - 0.5), rp = r_at(c, dr, i + 0.5);
+    if (di == 0) return (i > 0 ? rm / dr : 0.0) + (i < c.nr ? rp / dr : 0.0);
+    return di < 0 ? -rm / dr : -rp / dr;
+}
+static double mr(const pic_instance_cfg& c, double dr, int i, int di) {
+    double rm = r_at(c, dr, i - 1), r0 = r_at(c, dr, i), rp = r_at(c, dr, i + 1);
+    if (di == 0)
+        return (i > 0 ? dr * (rm + 3.0 * r0) / 12.0 : 0.0) + (i < c.nr ? dr * (3.0 * r0 + rp) / 12.0 : 0.0);
+    return di < 0 ? dr * (rm + r0) / 12.0 : dr * (r0 + rp) / 12.0;
+}
+static double kz(double dz, int dj) { return dj == 0 ? 2.0 / dz : -1.0 / dz; }
+static double mz(double dz, int dj) { return dj == 0 ? 4.0 * dz / 6.0 : dz / 6.0; }
+
+static double edge_value(const pic_instance_cfg& c, double dr, int i) {
+    if (i == 0) return c.V_inner;
+    if (i == c.nr) return c.V_outer;
+    if (c.end_mode == 1) return c.V_end;
+    double r = r_at(c, dr, (double)i);
+    return c.V_inner + (c.V_outer - c.V_inner) * (log(r / c.a) / log(c.b / c.a)) + c.V_end;
+}
+
+static void host_vacuum_rhs(const pic_instance_cfg& c, std::vector<double>& phiB, std::vector<double>& rhs) {
+    const int nr = c.nr, nz = c.nz, W = nz + 1;
+    const double dr = (c.b - c.a) / (double)nr, dz = c.L / (double)nz;
+    phiB.assign((size_t)(nr + 1) * W, 0.0);
+    rhs.assign((size_t)(nr + 1) * W, 0.0);
+    auto edge = [&](int i, int j) { return i == 0 || i == nr || j == 0 || j == nz; };
+    for (int i = 0; i <= nr; ++i)
+        for (int j = 0; j <= nz; ++j)
+            if (edge(i, j)) phiB[(size_t)i * W + j] = edge_value(c, dr, i);
+    for (int i = 1; i < nr; ++i)
+        for (int j = 1; j < nz; ++j) {
+            double s = 0.0;
+            for (int di = -1; di <= 1; ++di)
+                for (int dj = -1; dj <= 1; ++dj) {
+                    if (!edge(i + di, j + dj)) continue;
+                    double A = kr(c, dr, i, di) * mz(dz, dj) + mr(c, dr, i, di) * kz(dz, dj);
+                    s -= A * phiB[(size_t)(i + di) * W + (j + dj)];
+                }
+            rhs[(size_t)i * W + j] = s;
+        }
+}
+
+static void host_thomas(const pic_instance_cfg& c, std::vector<double>& cp, std::vector<double>& im,
+                        std::vector<double>& lo) {
+    const int nr = c.nr, nz = c.nz, W = nz + 1;
+    const double dr = (c.b - c.a) / (double)nr, dz = c.L / (double)nz;
+    size_t N = (size_t)(nr + 1) * W;
+    cp.assign(N, 0.0); im.assign(N, 0.0); lo.assign(N, 0.0);
+    for (int k = 1; k < nz; ++k) {
+        double ck = cos(kPi * (double)k / (double)nz);
+        double mu = (dz / 3.0) * (2.0 + ck), lam = (2.0 / dz) * (1.0 - ck);
+        double cprev = 0.0;
+        for (int i = 1; i < nr; ++i) {
+            double dg = mu * kr(c, dr, i, 0) + lam * mr(c, dr, i, 0);
+            double up = mu * kr(c, dr, i, +1) + lam * mr(c, dr, i, +1);
+            double lw = i > 1 ? mu * kr(c, dr, i, -1) + lam * mr(c, dr, i, -1) : 0.0;
+            double m = dg - lw * cprev;
+            size_t n = (size_t)i * W + k;
+            lo[n] = lw;
+            im[n] = 1.0 / m;
+            cp[n] = up / m;
+            cprev = cp[n];
+        }
+    }
+}
+
+static void host_volume(const pic_instance_cfg& c, std::vector<double>& V) {
+    const int nr = c.nr, nz = c.nz, W = nz + 1;
+    const double dr = (c.b - c.a) / (double)nr, dz = c.L / (double)nz;
+    V.assign((size_t)(nr + 1) * W, 0.0);
+    for (int i = 0; i <= nr; ++i) {
+        double lr = i == 0 ? dr * (c.a / 2.0 + dr / 6.0)
+                  : (i == nr ? dr * (c.b / 2.0 - dr / 6.0) : r_at(c, dr, (double)i) * dr);
+        for (int j = 0; j <= nz; ++j) {
+            double lz = (j == 0 || j == nz) ? dz / 2.0 : dz;
+            V[(size_t)i * W + j] = 2.0 * kPi * lr * lz;
+        }
+    }
+}
+
+static void fill_devinst(Inst& in) {
+    const pic_instance_cfg& c = in.c;
+    const pic_derived_t& d = in.d;
+    DevInst& I = in.I;
+    memset(&I, 0, sizeof(I));
+    I.a = c.a; I.b = c.b; I.L = c.L; I.dr = d.dr; I.dz = d.dz; I.inv_dr = d.inv_dr; I.inv_dz = d.inv_dz;
+    I.nr = c.nr; I.nz = c.nz; I.W = c.nz + 1; I.nodes = (c.nr + 1) * (c.nz + 1);
+    I.h = d.h; I.dt = c.dt;
+    I.P_null = d.P_null; I.nu_prime = d.nu_prime; I.nsig_el = d.nsig_el; I.n_n = d.n_n;
+    I.lotz_aq = d.lotz_aq; I.iz_I = c.iz_I_eV; I.opal_Ebar = c.opal_Ebar_eV; I.okh_xi = c.okh_xi;
+    I.half_me_over_e = d.half_me_over_e; I.two_e_over_me = d.two_e_over_me;
+    I.mass_ratio2 = d.mass_ratio2; I.v_cap2 = d.v_cap * d.v_cap;
+    I.null_k = null_threshold(d.P_null);
+    I.seed_lo = (unsigned int)c.seed; I.seed_hi = (unsigned int)(c.seed >> 32);
+    I.collisions = c.collisions;
+    I.frozen = in.frozen ? 1 : 0;
+    I.two_S = d.two_S; I.inv_two_S = d.inv_two_S;
+    I.p_cap = in.cap;
+    I.a_f = (float)c.a; I.b_f = (float)c.b; I.L_f = (float)c.L;
+    I.inv_dr_f = (float)d.inv_dr; I.inv_dz_f = (float)d.inv_dz; I.h_f = (float)d.h; I.dt_f = (float)c.dt;
+    I.nu_prime_f = (float)d.nu_prime; I.nsig_el_f = (float)d.nsig_el; I.n_n_f = (float)d.n_n;
+    I.lotz_aq_f = (float)d.lotz_aq; I.iz_I_f = (float)c.iz_I_eV; I.opal_Ebar_f = (float)c.opal_Ebar_eV;
+    I.okh_xi_f = (float)c.okh_xi; I.half_me_over_e_f = (float)d.half_me_over_e;
+    I.two_e_over_me_f = (float)d.two_e_over_me; I.mass_ratio2_f = (float)d.mass_ratio2;
+    I.v_cap2_f = (float)(d.v_cap * d.v_cap);
+    I.diag_D = c.diag_interval > 0 ? c.diag_interval : 1;
+}
+
+static pic_status upload_tables(pic_ctx* ctx) {
+    std::vector<DevInst> I;
+    std::vector<FieldDev> F, Fv;
+    std::vector<double> bs;
+    for (auto& in : ctx->in) {
+        in.I.frozen = in.frozen ? 1 : 0;
+        I.push_back(in.I);
+        FieldDev f;
+        memset(&f, 0, sizeof(f));
+        f.Q = in.Q; f.rhs = in.rhs; f.phi = in.phi; f.phi_vac = in.phi_vac;
+        f.th_cp = in.th_cp; f.th_im = in.th_im; f.th_lo = in.th_lo;
+        f.Er = in.Er; f.Ez = in.Ez; f.Br = in.Br; f.Bz = in.Bz; f.EB = in.EB;
+        f.V = in.V; f.avg_acc = in.avg_acc;
+        F.push_back(f);
+        FieldDev v = f;  // vacuum solve: boundary data in, phi_vac out
+        v.phi_vac = in.phiB;
+        v.phi = in.phi_vac;
+        Fv.push_back(v);
+        bs.push_back(in.d.bscale);
+    }
+    hipStream_t s = ctx->stream;
+    CK(hipMemcpyAsync(ctx->dI, I.data(), sizeof(DevInst) * I.size(), hipMemcpyHostToDevice, s));
+    CK(hipMemcpyAsync(ctx->dF, F.data(), sizeof(FieldDev) * F.size(), hipMemcpyHostToDevice, s));
+    CK(hipMemcpyAsync(ctx->dFvac, Fv.data(), sizeof(FieldDev) * Fv.size(), hipMemcpyHostToDevice, s));
+    CK(hipMemcpyAsync(ctx->dbscale, bs.data(), sizeof(double) * bs.size(), hipMemcpyHostToDevice, s));
+    CK(hipStreamSynchronize(s));
+    return PIC_OK;
+}
+
+// Field of every non-frozen instance from its current Q.
+pic_status pic_solve_all(pic_ctx* ctx) {
+    int n = (int)ctx->in.size();
+    hipStream_t s = ctx->stream;
+    CK(launch_solve_tab(ctx->dI, ctx->dF, 0, n, ctx->max_nr, ctx->max_nz, ctx->tw, ctx->tw_n, 0,
+                        ctx->dbscale, s));
+    CK(launch_efield_tab(ctx->dI, ctx->dF, 0, n, ctx->max_nodes, s));
+    return PIC_OK;
+}
+
+pic_status pic_sample_all(pic_ctx* ctx) {
+    CK(launch_sample_tab(ctx->dI, ctx->dF, 0, (int)ctx->in.size(), ctx->dcnt, ctx->stream));
+    return PIC_OK;
+}
+
+pic_status pic_commit_all(pic_ctx* ctx) {
+    CK(launch_commit(ctx->dI, ctx->dcnt, (int)ctx->in.size(), ctx->stream));
+    return PIC_OK;
+}
+
+// Accessors used by the FP32 form (fp32.hip).
+int pic_n_inst(pic_ctx* ctx) { return (int)ctx->in.size(); }
+DevInst& pic_inst_dev(pic_ctx* ctx, int k) { return ctx->in[k].I; }
+const pic_instance_cfg& pic_inst_cfg(pic_ctx* ctx, int k) { return ctx->in[k].c; }
+long long* pic_counters(pic_ctx* ctx) { return ctx->dcnt; }
+long long* pic_inst_Q(pic_ctx* ctx, int k) { return ctx->in[k].Q; }
+float4* pic_inst_EB(pic_ctx* ctx, int k) { return ctx->in[k].EB; }
+DevInst* pic_dev_table(pic_ctx* ctx) { return ctx->dI; }
+const pic_run_cfg& pic_run(pic_ctx* ctx) { return ctx->run; }
+void pic_set_error(pic_ctx* ctx, const std::string& m) { ctx->err = m; }
+bool pic_timing_on(pic_ctx* ctx) { return ctx->timing; }
+
+// Record a timed launch: returns the start event to record before the launch
+// and stores the stop event in *stop.
+hipEvent_t pic_timing_begin(pic_ctx* ctx, hipEvent_t* stop) {
+    if (ctx->ev_used + 2 > ctx->ev.size()) {
+        for (int k = 0; k < 64; ++k) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) return nullptr;
+            ctx->ev.push_back(e);
+        }
+    }
+    hipEvent_t a = ctx->ev[ctx->ev_used], b = ctx->ev[ctx->ev_used + 1];
+    ctx->ev_used += 2;
+    *stop = b;
+    return a;
+}
+
+static pic_status timing_collect(pic_ctx* ctx) {
+    if (ctx->ev_used == 0) return PIC_OK;
+    CK(hipStreamSynchronize(ctx->stream));
+    for (size_t k = 0; k + 1 < ctx->ev_used; k += 2) {
+        float ms = 0.f;
+        CK(hipEventElapsedTime(&ms, ctx->ev[k], ctx->ev[k + 1]));
+        ctx->timed_ms += ms;
+        ctx->timed_launches += 1;
+    }
+    ctx->ev_used = 0;
+    return PIC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// init / destroy
+// ---------------------------------------------------------------------------
+
+static pic_status init_instance_storage(pic_ctx* ctx, Inst& in) {
+    const long long N = in.nodes;
+    in.Q = dalloc<long long>(ctx, N);
+    in.rhs = dalloc<double>(ctx, N);
+    in.phi = dalloc<double>(ctx, N);
+    in.phi_vac = dalloc<double>(ctx, N);
+    in.phiB = dalloc<double>(ctx, N);
+    in.Br = dalloc<double>(ctx, N);
+    in.Bz = dalloc<double>(ctx, N);
+    in.V = dalloc<double>(ctx, N);
+    in.avg_acc = dalloc<double>(ctx, N);
+    in.th_cp = dalloc<double>(ctx, N);
+    in.th_im = dalloc<double>(ctx, N);
+    in.th_lo = dalloc<double>(ctx, N);
+    if (!in.Q || !in.rhs || !in.phi || !in.phi_vac || !in.phiB || !in.Br || !in.Bz || !in.V ||
+        !in.avg_acc || !in.th_cp || !in.th_im || !in.th_lo)
+        return fail(ctx, PIC_ENOMEM, "device allocation of node arrays failed");
+    if (ctx->mode == PIC_MODE_FP64_PLAIN) {
+        in.Er = dalloc<double>(ctx, N);
+        in.Ez = dalloc<double>(ctx, N);
+        if (!in.Er || !in.Ez) return fail(ctx, PIC_ENOMEM, "device allocation of E failed");
+        for (int b = 0; b < 2; ++b) {
+            P64& p = in.p64[b];
+            p.r = dalloc<double>(ctx, in.cap);
+            p.z = dalloc<double>(ctx, in.cap);
+            p.vr = dalloc<double>(ctx, in.cap);
+            p.vt = dalloc<double>(ctx, in.cap);
+            p.vz = dalloc<double>(ctx, in.cap);
+            p.w = dalloc<double>(ctx, in.cap);
+            p.key = dalloc<unsigned long long>(ctx, in.cap);
+            if (!p.r || !p.z || !p.vr || !p.vt || !p.vz || !p.w || !p.key)
+                return fail(ctx, PIC_ENOMEM, "device allocation of FP64 particles failed");
+        }
+    } else {
+        in.EB = dalloc<float4>(ctx, N);
+        if (!in.EB) return fail(ctx, PIC_ENOMEM, "device allocation of EB failed");
+    }
+    hipStream_t s = ctx->stream;
+    std::vector<double> a, b, cc;
+    host_bfield(in.c, a, b);
+    CK(hipMemcpyAsync(in.Br, a.data(), sizeof(double) * N, hipMemcpyHostToDevice, s));
+    CK(hipMemcpyAsync(in.Bz, b.data(), sizeof(double) * N, hipMemcpyHostToDevice, s));
+    CK(hipStreamSynchronize(s));
+    host_volume(in.c, in.V_host);
+    CK(hipMemcpyAsync(in.V, in.V_host.data(), sizeof(double) * N, hipMemcpyHostToDevice, s));
+    host_thomas(in.c, a, b, cc);
+    CK(hipMemcpyAsync(in.th_cp, a.data(), sizeof(double) * N, hipMemcpyHostToDevice, s));
+    CK(hipMemcpyAsync(in.th_im, b.data(), sizeof(double) * N, hipMemcpyHostToDevice, s));
+    CK(hipMemcpyAsync(in.th_lo, cc.data(), sizeof(double) * N, hipMemcpyHostToDevice, s));
+    CK(hipStreamSynchronize(s));
+    host_vacuum_rhs(in.c, a, b);
+    CK(hipMemcpyAsync(in.phiB, a.data(), sizeof(double) * N, hipMemcpyHostToDevice, s));
+    CK(hipMemcpyAsync(in.rhs, b.data(), sizeof(double) * N, hipMemcpyHostToDevice, s));
+    CK(hipMemsetAsync(in.avg_acc, 0, sizeof(double) * N, s));
+    CK(hipMemsetAsync(in.Q, 0, sizeof(long long) * N, s));
+    CK(hipStreamSynchronize(s));
+    return PIC_OK;
+}
+
+static void destroy_ctx(pic_ctx* ctx) {
+    if (!ctx) return;
+    if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+    if (ctx->f32) f32_destroy(ctx);
+    for (auto e : ctx->ev) (void)hipEventDestroy(e);
+    std::vector<void*> all = ctx->allocs;
+    for (void* p : all) pic_dev_free(ctx, p);
+    if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
+    delete ctx;
+}
+
+void pic_set_f32(pic_ctx* ctx, F32State* s) { ctx->f32 = s; }
+F32State* pic_get_f32(pic_ctx* ctx) { return ctx->f32; }
+
+static pic_status deposit_and_solve(pic_ctx* ctx, int k_only);
+
+extern "C" pic_status pic_init(const pic_run_cfg* run, const pic_instance_cfg* inst, pic_ctx** out) {
+    g_init_error.clear();
+    if (!out) return fail(nullptr, PIC_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!run || !inst) return fail(nullptr, PIC_EINVAL, "run or inst is NULL");
+    if (run->n_instances < 1 || run->n_instances > 4096) return fail(nullptr, PIC_EINVAL, "n_instances must be in [1, 4096]");
+    if (run->mode != PIC_MODE_FP64_PLAIN && run->mode != PIC_MODE_FP32_BATCHED)
+        return fail(nullptr, PIC_EINVAL, "unknown mode");
+    if (run->capacity_factor < 0.0 || (run->capacity_factor > 0.0 && run->capacity_factor < 1.0))
+        return fail(nullptr, PIC_EINVAL, "capacity_factor must be 0 or >= 1");
+    for (int k = 0; k < run->n_instances; ++k) {
+        std::string m = validate(inst[k]);
+        if (!m.empty()) return fail(nullptr, PIC_EINVAL, "instance " + std::to_string(k) + ": " + m);
+    }
+    pic_ctx* ctx = new pic_ctx();
+    ctx->run = *run;
+    ctx->mode = run->mode;
+    hipError_t e = hipSetDevice(run->device);
+    if (e != hipSuccess) {
+        std::string m = std::string("hipSetDevice: ") + hipGetErrorString(e);
+        delete ctx;
+        return fail(nullptr, PIC_EDEVICE, m);
+    }
+    if (run->stream) {
+        ctx->stream = (hipStream_t)run->stream;
+    } else {
+        if (hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking) != hipSuccess) {
+            delete ctx;
+            return fail(nullptr, PIC_EDEVICE, "hipStreamCreate failed");
+        }
+        ctx->own_stream = true;
+    }
+    double cf = run->capacity_factor > 0.0 ? run->capacity_factor : 2.0;
+    long long cmin = run->capacity_min > 0 ? run->capacity_min : 4096;
+    ctx->in.resize(run->n_instances);
+    pic_status st = PIC_OK;
+    for (int k = 0; k < run->n_instances && st == PIC_OK; ++k) {
+        Inst& in = ctx->in[k];
+        in.c = inst[k];
+        if (in.c.diag_interval <= 0) in.c.diag_interval = 1;
+        in.S = in.c.fx_shift != 0 ? in.c.fx_shift : pic_auto_shift(in.c.n_init > 0 ? in.c.weight : 1.0);
+        in.c.fx_shift = in.S;
+        pic_derive(&in.c, in.S, &in.d);
+        if (in.c.n_init > 0 && ldexp(in.c.weight, in.S) > 2147483648.0)
+            st = fail(ctx, PIC_EOVERFLOW, "weight * 2^S exceeds 2^31");
+        in.cap = std::max<long long>(cmin, (long long)ceil(cf * (double)in.c.n_init));
+        in.nodes = (long long)(in.c.nr + 1) * (in.c.nz + 1);
+        fill_devinst(in);
+        ctx->max_nr = std::max(ctx->max_nr, in.c.nr);
+        ctx->max_nz = std::max(ctx->max_nz, in.c.nz);
+        ctx->max_nodes = std::max(ctx->max_nodes, in.nodes);
+    }
+    int n = run->n_instances;
+    if (st == PIC_OK) {
+        ctx->dI = dalloc<DevInst>(ctx, n);
+        ctx->dF = dalloc<FieldDev>(ctx, n);
+        ctx->dFvac = dalloc<FieldDev>(ctx, n);
+        ctx->dbscale = dalloc<double>(ctx, n);
+        ctx->dcnt = dalloc<long long>(ctx, (long long)n * C_NCOUNT);
+        ctx->dtmp = dalloc<long long>(ctx, 64);
+        ctx->tw_n = 2 * ctx->max_nz;
+        ctx->tw = dalloc<double2>(ctx, ctx->tw_n / 2);
+        if (!ctx->dI || !ctx->dF || !ctx->dFvac || !ctx->dbscale || !ctx->dcnt || !ctx->dtmp || !ctx->tw)
+            st = fail(ctx, PIC_ENOMEM, "device allocation of tables failed");
+    }
+    if (st == PIC_OK) {
+        std::vector<double2> tw(ctx->tw_n / 2);
+        for (int k = 0; k < ctx->tw_n / 2; ++k) {
+            double a = 2.0 * kPi * (double)k / (double)ctx->tw_n;
+            tw[k] = make_double2(cos(a), -sin(a));
+        }
+        e = hipMemcpy(ctx->tw, tw.data(), sizeof(double2) * tw.size(), hipMemcpyHostToDevice);
+        if (e != hipSuccess) st = fail(ctx, PIC_EDEVICE, "twiddle upload failed");
+        e = set_field_kernel_attrs(ctx->max_nz);
+        if (e != hipSuccess && st == PIC_OK) st = fail(ctx, PIC_EDEVICE, "LDS attribute failed");
+    }
+    for (int k = 0; k < n && st == PIC_OK; ++k) st = init_instance_storage(ctx, ctx->in[k]);
+    if (st == PIC_OK && ctx->mode == PIC_MODE_FP32_BATCHED) st = f32_init(ctx);
+    if (st == PIC_OK) {
+        std::vector<long long> cnt((size_t)n * C_NCOUNT, 0);
+        for (int k = 0; k < n; ++k) cnt[(size_t)k * C_NCOUNT + C_SLOTS] = ctx->in[k].c.n_init;
+        e = hipMemcpy(ctx->dcnt, cnt.data(), sizeof(long long) * cnt.size(), hipMemcpyHostToDevice);
+        if (e != hipSuccess) st = fail(ctx, PIC_EDEVICE, "counter upload failed");
+        for (int k = 0; k < n; ++k) ctx->in[k].cnt = ctx->dcnt + (long long)k * C_NCOUNT;
+    }
+    if (st == PIC_OK) st = upload_tables(ctx);
+    // vacuum potential
+    if (st == PIC_OK) {
+        e = launch_solve_tab(ctx->dI, ctx->dFvac, 0, n, ctx->max_nr, ctx->max_nz, ctx->tw, ctx->tw_n, 1,
+                             ctx->dbscale, ctx->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+        if (e != hipSuccess) st = fail(ctx, PIC_EDEVICE, std::string("vacuum solve: ") + hipGetErrorString(e));
+    }
+    // initial load
+    for (int k = 0; k < n && st == PIC_OK; ++k) {
+        Inst& in = ctx->in[k];
+        if (ctx->mode == PIC_MODE_FP64_PLAIN) {
+            e = launch_load64(in.I, in.c, in.p64[0], in.c.n_init, ctx->stream);
+            if (e != hipSuccess) st = fail(ctx, PIC_EDEVICE, "load kernel failed");
+        } else {
+            st = f32_load(ctx, k);
+        }
+    }
+    if (st == PIC_OK) st = deposit_and_solve(ctx, -1);
+    if (st == PIC_OK) {
+        e = hipStreamSynchronize(ctx->stream);
+        if (e != hipSuccess) st = fail(ctx, PIC_EDEVICE, std::string("init: ") + hipGetErrorString(e));
+    }
+    if (st != PIC_OK) {
+        g_init_error = ctx->err;
+        destroy_ctx(ctx);
+        return st;
+    }
+    *out = ctx;
+    return PIC_OK;
+}
+
+extern "C" pic_status pic_destroy(pic_ctx* ctx) {
+    if (!ctx) return PIC_EINVAL;
+    destroy_ctx(ctx);
+    return PIC_OK;
+}
+
+extern "C" const char* pic_last_error(const pic_ctx* ctx) {
+    return ctx ? ctx->err.c_str() : g_init_error.c_str();
+}
+
+// ---------------------------------------------------------------------------
+// deposit + field (used at init and after set_particles); k_only < 0: all
+// ---------------------------------------------------------------------------
+
+static pic_status deposit_and_solve(pic_ctx* ctx, int k_only) {
+    hipStream_t s = ctx->stream;
+    for (int k = 0; k < (int)ctx->in.size(); ++k) {
+        if (k_only >= 0 && k != k_only) continue;
+        Inst& in = ctx->in[k];
+        CK(launch_zero_i64(in.Q, in.nodes, s));
+        if (ctx->mode == PIC_MODE_FP64_PLAIN) {
+            CK(launch_deposit64(in.I, in.p64[in.cur], in.Q, in.cnt, in.cap, s));
+        } else {
+            pic_status st = f32_deposit_only(ctx, k);
+            if (st != PIC_OK) return st;
+        }
+    }
+    return pic_solve_all(ctx);
+}
+
+// ---------------------------------------------------------------------------
+// FP64 plain step
+// ---------------------------------------------------------------------------
+
+static pic_status check_counts(pic_ctx* ctx, std::vector<long long>& cnt) {
+    cnt.resize(ctx->in.size() * C_NCOUNT);
+    CK(hipMemcpyAsync(cnt.data(), ctx->dcnt, sizeof(long long) * cnt.size(), hipMemcpyDeviceToHost,
+                      ctx->stream));
+    CK(hipStreamSynchronize(ctx->stream));
+    for (size_t k = 0; k < ctx->in.size(); ++k) {
+        if (cnt[k * C_NCOUNT + C_DROPPED] > 0)
+            return fail(ctx, PIC_ECAPACITY, "instance " + std::to_string(k) + ": new electrons dropped (storage full)");
+        if (cnt[k * C_NCOUNT + C_OVERFLOW] > 0)
+            return fail(ctx, PIC_EOVERFLOW, "instance " + std::to_string(k) + ": fixed-point overflow");
+    }
+    return PIC_OK;
+}
+
+static pic_status compact64(pic_ctx* ctx, int k) {
+    Inst& in = ctx->in[k];
+    hipStream_t s = ctx->stream;
+    CK(hipMemsetAsync(ctx->dtmp, 0, sizeof(long long), s));
+    CK(launch_compact64(in.I, in.p64[in.cur], in.p64[1 - in.cur], in.cnt, ctx->dtmp, in.cap, s));
+    long long live = 0;
+    CK(hipMemcpyAsync(&live, ctx->dtmp, sizeof(long long), hipMemcpyDeviceToHost, s));
+    CK(hipStreamSynchronize(s));
+    in.cur = 1 - in.cur;
+    long long upd[3] = {live, 0, 0};  // slots, spawn, dead
+    CK(hipMemcpyAsync(in.cnt + C_SLOTS, upd, sizeof(upd), hipMemcpyHostToDevice, s));
+    CK(hipStreamSynchronize(s));
+    return PIC_OK;
+}
+
+static pic_status step64(pic_ctx* ctx, int n_steps) {
+    hipStream_t s = ctx->stream;
+    const int check_every = 64;
+    std::vector<long long> cnt;
+    for (int done = 0; done < n_steps;) {
+        pic_status st = check_counts(ctx, cnt);
+        if (st != PIC_OK) return st;
+        for (size_t k = 0; k < ctx->in.size(); ++k) {
+            long long slots = cnt[k * C_NCOUNT + C_SLOTS], dead = cnt[k * C_NCOUNT + C_DEAD];
+            if (slots > (ctx->in[k].cap * 3) / 4 && dead > 0) {
+                st = compact64(ctx, (int)k);
+                if (st != PIC_OK) return st;
+            }
+        }
+        int batch = std::min(check_every, n_steps - done);
+        for (int it = 0; it < batch; ++it) {
+            for (size_t k = 0; k < ctx->in.size(); ++k) {
+                Inst& in = ctx->in[k];
+                P64 p = in.p64[in.cur];
+                CK(launch_zero_i64(in.Q, in.nodes, s));
+                hipEvent_t e0 = nullptr, e1 = nullptr;
+                if (ctx->timing) {
+                    e0 = pic_timing_begin(ctx, &e1);
+                    CK(hipEventRecord(e0, s));
+                }
+                CK(launch_push64(in.I, p, in.Er, in.Ez, in.Br, in.Bz, in.cnt, in.cap, s));
+                if (ctx->timing) CK(hipEventRecord(e1, s));
+                CK(launch_mcc64(in.I, p, in.cnt, in.cap, s));
+                CK(launch_deposit64(in.I, p, in.Q, in.cnt, in.cap, s));
+            }
+            st = pic_solve_all(ctx);
+            if (st == PIC_OK) st = pic_sample_all(ctx);
+            if (st == PIC_OK) st = pic_commit_all(ctx);
+            if (st != PIC_OK) return st;
+            ctx->host_step += 1;
+        }
+        done += batch;
+        if (ctx->timing && ctx->ev_used > 4096) {
+            st = timing_collect(ctx);
+            if (st != PIC_OK) return st;
+        }
+    }
+    return PIC_OK;
+}
+
+extern "C" pic_status pic_step(pic_ctx* ctx, int n_steps) {
+    if (!ctx) return PIC_EINVAL;
+    if (n_steps < 0) return fail(ctx, PIC_EINVAL, "n_steps < 0");
+    if (n_steps == 0) return PIC_OK;
+    if (ctx->mode == PIC_MODE_FP64_PLAIN) return step64(ctx, n_steps);
+    return f32_step(ctx, n_steps);
+}
+
+extern "C" pic_status pic_sync(pic_ctx* ctx) {
+    if (!ctx) return PIC_EINVAL;
+    std::vector<long long> cnt;
+    return check_counts(ctx, cnt);
+}
+
+// ---------------------------------------------------------------------------
+// hooks
+// ---------------------------------------------------------------------------
+
+static pic_status check_inst(pic_ctx* ctx, int k) {
+    if (!ctx) return PIC_EINVAL;
+    if (k < 0 || k >= (int)ctx->in.size()) return fail(ctx, PIC_EINVAL, "instance index out of range");
+    return PIC_OK;
+}
+
+extern "C" pic_status pic_set_particles(pic_ctx* ctx, int k, long long n, const double* r,
+                                        const double* z, const double* vr, const double* vt,
+                                        const double* vz, const double* w,
+                                        const unsigned long long* key) {
+    pic_status st = check_inst(ctx, k);
+    if (st != PIC_OK) return st;
+    Inst& in = ctx->in[k];
+    if (n < 0 || (n > 0 && (!r || !z || !vr || !vt || !vz || !w || !key)))
+        return fail(ctx, PIC_EINVAL, "bad particle arrays");
+    if (n > in.cap / 2 && ctx->mode == PIC_MODE_FP32_BATCHED)
+        return fail(ctx, PIC_ECAPACITY, "more particles than half the slots");
+    if (n > in.cap) return fail(ctx, PIC_ECAPACITY, "more particles than slots");
+    for (long long q = 0; q < n; ++q) {
+        if (!(r[q] > in.c.a && r[q] < in.c.b && z[q] > 0.0 && z[q] < in.c.L))
+            return fail(ctx, PIC_EINVAL, "particle " + std::to_string(q) + " outside a<r<b, 0<z<L");
+        if (!(w[q] > 0.0)) return fail(ctx, PIC_EINVAL, "weights must be > 0");
+        if (w[q] * in.d.two_S > 2147483648.0) return fail(ctx, PIC_EOVERFLOW, "weight * 2^S exceeds 2^31");
+    }
+    hipStream_t s = ctx->stream;
+    CK(hipStreamSynchronize(s));
+    if (ctx->mode == PIC_MODE_FP64_PLAIN) {
+        P64 p = in.p64[in.cur];
+        size_t b = sizeof(double) * (size_t)n;
+        if (n > 0) {
+            CK(hipMemcpy(p.r, r, b, hipMemcpyHostToDevice));
+            CK(hipMemcpy(p.z, z, b, hipMemcpyHostToDevice));
+            CK(hipMemcpy(p.vr, vr, b, hipMemcpyHostToDevice));
+            CK(hipMemcpy(p.vt, vt, b, hipMemcpyHostToDevice));
+            CK(hipMemcpy(p.vz, vz, b, hipMemcpyHostToDevice));
+            CK(hipMemcpy(p.w, w, b, hipMemcpyHostToDevice));
+            CK(hipMemcpy(p.key, key, sizeof(unsigned long long) * n, hipMemcpyHostToDevice));
+        }
+    } else {
+        st = f32_set_particles(ctx, k, n, r, z, vr, vt, vz, w, key);
+        if (st != PIC_OK) return st;
+    }
+    long long upd[3] = {n, 0, 0};
+    CK(hipMemcpy(in.cnt + C_SLOTS, upd, sizeof(upd), hipMemcpyHostToDevice));
+    st = deposit_and_solve(ctx, k);
+    if (st != PIC_OK) return st;
+    CK(hipStreamSynchronize(s));
+    return PIC_OK;
+}
+
+extern "C" pic_status pic_get_particles(pic_ctx* ctx, int k, double* r, double* z, double* vr,
+                                        double* vt, double* vz, double* w, unsigned long long* key,
+                                        long long cap, long long* n_out) {
+    pic_status st = check_inst(ctx, k);
+    if (st != PIC_OK) return st;
+    std::vector<long long> cnt;
+    st = check_counts(ctx, cnt);
+    if (st != PIC_OK && st != PIC_ECAPACITY) return st;
+    Inst& in = ctx->in[k];
+    if (ctx->mode != PIC_MODE_FP64_PLAIN) return f32_get_particles(ctx, k, r, z, vr, vt, vz, w, key, cap, n_out);
+    long long slots = cnt[(size_t)k * C_NCOUNT + C_SLOTS];
+    P64 p = in.p64[in.cur];
+    std::vector<double> hr(slots), hz(slots), hvr(slots), hvt(slots), hvz(slots), hw(slots);
+    std::vector<unsigned long long> hk(slots);
+    size_t b = sizeof(double) * (size_t)slots;
+    if (slots > 0) {
+        CK(hipMemcpy(hr.data(), p.r, b, hipMemcpyDeviceToHost));
+        CK(hipMemcpy(hz.data(), p.z, b, hipMemcpyDeviceToHost));
+        CK(hipMemcpy(hvr.data(), p.vr, b, hipMemcpyDeviceToHost));
+        CK(hipMemcpy(hvt.data(), p.vt, b, hipMemcpyDeviceToHost));
+        CK(hipMemcpy(hvz.data(), p.vz, b, hipMemcpyDeviceToHost));
+        CK(hipMemcpy(hw.data(), p.w, b, hipMemcpyDeviceToHost));
+        CK(hipMemcpy(hk.data(), p.key, sizeof(unsigned long long) * slots, hipMemcpyDeviceToHost));
+    }
+    long long m = 0;
+    for (long long q = 0; q < slots; ++q) {
+        if (hr[q] < 0.0) continue;
+        if (m < cap) {
+            if (r) r[m] = hr[q];
+            if (z) z[m] = hz[q];
+            if (vr) vr[m] = hvr[q];
+            if (vt) vt[m] = hvt[q];
+            if (vz) vz[m] = hvz[q];
+            if (w) w[m] = hw[q];
+            if (key) key[m] = hk[q];
+        }
+        ++m;
+    }
+    if (n_out) *n_out = m;
+    if (m > cap) return fail(ctx, PIC_EINVAL, "cap smaller than the live count");
+    return st;
+}
+
+extern "C" pic_status pic_set_fields(pic_ctx* ctx, int k, const double* Er, const double* Ez,
+                                     const double* Br, const double* Bz, int frozen) {
+    pic_status st = check_inst(ctx, k);
+    if (st != PIC_OK) return st;
+    Inst& in = ctx->in[k];
+    size_t N = (size_t)in.nodes, b = sizeof(double) * N;
+    CK(hipStreamSynchronize(ctx->stream));
+    if (Br) CK(hipMemcpy(in.Br, Br, b, hipMemcpyHostToDevice));
+    if (Bz) CK(hipMemcpy(in.Bz, Bz, b, hipMemcpyHostToDevice));
+    if (ctx->mode == PIC_MODE_FP64_PLAIN) {
+        if (Er) CK(hipMemcpy(in.Er, Er, b, hipMemcpyHostToDevice));
+        if (Ez) CK(hipMemcpy(in.Ez, Ez, b, hipMemcpyHostToDevice));
+    } else {
+        std::vector<float4> eb(N);
+        CK(hipMemcpy(eb.data(), in.EB, sizeof(float4) * N, hipMemcpyDeviceToHost));
+        for (size_t n = 0; n < N; ++n) {
+            if (Er) eb[n].x = (float)Er[n];
+            if (Ez) eb[n].y = (float)Ez[n];
+            if (Br) eb[n].z = (float)Br[n];
+            if (Bz) eb[n].w = (float)Bz[n];
+        }
+        CK(hipMemcpy(in.EB, eb.data(), sizeof(float4) * N, hipMemcpyHostToDevice));
+    }
+    in.frozen = frozen != 0;
+    return upload_tables(ctx);
+}
+
+extern "C" pic_status pic_get_fields(pic_ctx* ctx, int k, double* Er, double* Ez, double* Br,
+                                     double* Bz) {
+    pic_status st = check_inst(ctx, k);
+    if (st != PIC_OK) return st;
+    Inst& in = ctx->in[k];
+    size_t N = (size_t)in.nodes, b = sizeof(double) * N;
+    CK(hipStreamSynchronize(ctx->stream));
+    if (ctx->mode == PIC_MODE_FP64_PLAIN) {
+        if (Er) CK(hipMemcpy(Er, in.Er, b, hipMemcpyDeviceToHost));
+        if (Ez) CK(hipMemcpy(Ez, in.Ez, b, hipMemcpyDeviceToHost));
+        if (Br) CK(hipMemcpy(Br, in.Br, b, hipMemcpyDeviceToHost));
+        if (Bz) CK(hipMemcpy(Bz, in.Bz, b, hipMemcpyDeviceToHost));
+    } else {
+        std::vector<float4> eb(N);
+        CK(hipMemcpy(eb.data(), in.EB, sizeof(float4) * N, hipMemcpyDeviceToHost));
+        for (size_t n = 0; n < N; ++n) {
+            if (Er) Er[n] = eb[n].x;
+            if (Ez) Ez[n] = eb[n].y;
+            if (Br) Br[n] = eb[n].z;
+            if (Bz) Bz[n] = eb[n].w;
+        }
+    }
+    return PIC_OK;
+}
+
+extern "C" pic_status pic_get_charge(pic_ctx* ctx, int k, long long* Q) {
+    pic_status st = check_inst(ctx, k);
+    if (st != PIC_OK) return st;
+    if (!Q) return fail(ctx, PIC_EINVAL, "Q is NULL");
+    CK(hipStreamSynchronize(ctx->stream));
+    CK(hipMemcpy(Q, ctx->in[k].Q, sizeof(long long) * ctx->in[k].nodes, hipMemcpyDeviceToHost));
+    return PIC_OK;
+}
+
+extern "C" pic_status pic_get_phi(pic_ctx* ctx, int k, double* phi) {
+    pic_status st = check_inst(ctx, k);
+    if (st != PIC_OK) return st;
+    if (!phi) return fail(ctx, PIC_EINVAL, "phi is NULL");
+    CK(hipStreamSynchronize(ctx->stream));
+    CK(hipMemcpy(phi, ctx->in[k].phi, sizeof(double) * ctx->in[k].nodes, hipMemcpyDeviceToHost));
+    return PIC_OK;
+}
+
+extern "C" pic_status pic_set_step(pic_ctx* ctx, long long step) {
+    if (!ctx || step < 0) return PIC_EINVAL;
+    CK(hipStreamSynchronize(ctx->stream));
+    for (auto& in : ctx->in) CK(hipMemcpy(in.cnt + C_STEP, &step, sizeof(long long), hipMemcpyHostToDevice));
+    ctx->host_step = step;
+    return PIC_OK;
+}
+
+extern "C" pic_status pic_diag(pic_ctx* ctx, int k, pic_diag_t* out, double* density,
+                               double* time_avg_density) {
+    pic_status st = check_inst(ctx, k);
+    if (st != PIC_OK) return st;
+    if (!out) return fail(ctx, PIC_EINVAL, "out is NULL");
+    std::vector<long long> all;
+    pic_status cs = check_counts(ctx, all);
+    if (cs != PIC_OK && cs != PIC_ECAPACITY && cs != PIC_EOVERFLOW) return cs;
+    Inst& in = ctx->in[k];
+    const long long* c = all.data() + (size_t)k * C_NCOUNT;
+    memset(out, 0, sizeof(*out));
+    out->step = c[C_STEP];
+    out->n_elastic = c[C_ELASTIC];
+    out->n_ioniz = c[C_IONIZ];
+    out->n_null_cand = c[C_CAND];
+    out->n_cap_overflow = c[C_CAPOVER];
+    out->n_spawn_dropped = c[C_DROPPED];
+    for (int w = 0; w < 4; ++w) {
+        out->n_absorbed[w] = c[C_ABS_N + w];
+        out->absorbed_W[w] = c[C_ABS_W + w];
+        long long bits = c[C_IWALL + w];
+        memcpy(&out->I_wall[w], &bits, 8);
+    }
+    memcpy(&out->peak_density, &c[C_PEAK], 8);
+    memcpy(&out->peak_I_outer, &c[C_PEAKI_OUT], 8);
+    memcpy(&out->peak_I_inner, &c[C_PEAKI_IN], 8);
+    out->n_samples = c[C_NSAMP];
+    out->S = in.S;
+    if (ctx->mode == PIC_MODE_FP64_PLAIN) out->n_live = c[C_SLOTS] - c[C_DEAD];
+    else out->n_live = f32_live_count(ctx, k, c);
+    size_t N = (size_t)in.nodes;
+    std::vector<long long> Q(N);
+    std::vector<double> acc(N);
+    CK(hipMemcpy(Q.data(), in.Q, sizeof(long long) * N, hipMemcpyDeviceToHost));
+    CK(hipMemcpy(acc.data(), in.avg_acc, sizeof(double) * N, hipMemcpyDeviceToHost));
+    long long tq = 0;
+    double pk = 0.0;
+    for (size_t n = 0; n < N; ++n) {
+        tq += Q[n];
+        if (density) density[n] = ((double)Q[n] * in.d.inv_two_S) / in.V_host[n];
+        double avg = out->n_samples > 0
+                         ? ((acc[n] * in.d.inv_two_S) / (double)out->n_samples) / in.V_host[n]
+                         : 0.0;
+        if (time_avg_density) time_avg_density[n] = avg;
+        if (avg > pk) pk = avg;
+    }
+    out->total_Q = tq;
+    out->total_charge_C = -kE * ((double)tq * in.d.inv_two_S);
+    out->peak_time_avg_density = pk;
+    return cs;
+}
+
+extern "C" pic_status pic_timing(pic_ctx* ctx, int enable, long long* launches, double* total_ms) {
+    if (!ctx) return PIC_EINVAL;
+    pic_status st = timing_collect(ctx);
+    if (st != PIC_OK) return st;
+    if (launches) *launches = ctx->timed_launches;
+    if (total_ms) *total_ms = ctx->timed_ms;
+    if (enable) {
+        ctx->timed_launches = 0;
+        ctx->timed_ms = 0.0;
+    }
+    ctx->timing = enable != 0;
+    return PIC_OK;
+}
+
+extern "C" pic_status pic_tuning(pic_ctx* ctx, int* tile_r, int* tile_z, int* halo,
+                                 int* sort_interval, int* chunk) {
+    if (!ctx) return PIC_EINVAL;
+    if (ctx->mode != PIC_MODE_FP32_BATCHED) {
+        if (tile_r) *tile_r = 0;
+        if (tile_z) *tile_z = 0;
+        if (halo) *halo = 0;
+        if (sort_interval) *sort_interval = 0;
+        if (chunk) *chunk = 0;
+        return PIC_OK;
+    }
+    return f32_tuning(ctx, tile_r, tile_z, halo, sort_interval, chunk);
+}

@@ -1,0 +1,47 @@
+// fp32.h -- the batched FP32 form: tile-sorted SoA FP32 particles, one fused
+// persistent particle kernel per step with LDS charge accumulation, periodic
+// tile sort, captured step graphs.
+#pragma once
+
+#include <string>
+
+#include "pic_internal.h"
+
+struct F32State;
+
+// accessors of the context (api.hip)
+void* pic_dev_alloc(pic_ctx* ctx, size_t bytes);
+void pic_dev_free(pic_ctx* ctx, void* p);
+hipStream_t pic_stream(pic_ctx* ctx);
+int pic_n_inst(pic_ctx* ctx);
+pic::DevInst& pic_inst_dev(pic_ctx* ctx, int k);
+const pic_instance_cfg& pic_inst_cfg(pic_ctx* ctx, int k);
+long long* pic_counters(pic_ctx* ctx);
+long long* pic_inst_Q(pic_ctx* ctx, int k);
+float4* pic_inst_EB(pic_ctx* ctx, int k);
+pic::DevInst* pic_dev_table(pic_ctx* ctx);
+const pic_run_cfg& pic_run(pic_ctx* ctx);
+void pic_set_error(pic_ctx* ctx, const std::string& m);
+bool pic_timing_on(pic_ctx* ctx);
+hipEvent_t pic_timing_begin(pic_ctx* ctx, hipEvent_t* stop);
+void pic_set_f32(pic_ctx* ctx, F32State* s);
+F32State* pic_get_f32(pic_ctx* ctx);
+pic_status pic_solve_all(pic_ctx* ctx);
+pic_status pic_sample_all(pic_ctx* ctx);
+pic_status pic_commit_all(pic_ctx* ctx);
+
+// the FP32 form (fp32.hip)
+pic_status f32_init(pic_ctx* ctx);
+void f32_destroy(pic_ctx* ctx);
+pic_status f32_load(pic_ctx* ctx, int k);
+pic_status f32_deposit_only(pic_ctx* ctx, int k);
+pic_status f32_step(pic_ctx* ctx, int n_steps);
+pic_status f32_set_particles(pic_ctx* ctx, int k, long long n, const double* r, const double* z,
+                             const double* vr, const double* vt, const double* vz, const double* w,
+                             const unsigned long long* key);
+pic_status f32_get_particles(pic_ctx* ctx, int k, double* r, double* z, double* vr, double* vt,
+                             double* vz, double* w, unsigned long long* key, long long cap,
+                             long long* n_out);
+long long f32_live_count(pic_ctx* ctx, int k, const long long* cnt);
+pic_status f32_tuning(pic_ctx* ctx, int* tile_r, int* tile_z, int* halo, int* sort_interval,
+                      int* chunk);

@@ -1,0 +1,266 @@
+// k_field.hip -- FP64 field stage shared by both forms: fixed-point charge
+// -> order-1 FEM load -> Poisson solve -> nodal E, and the diagnostics
+// sampling.  Instances are batched along gridDim.y through device tables.
+//
+// The interior FEM system (Kr (x) Mz + Mr (x) Kz) phi = b / eps0 with
+// homogeneous Dirichlet data is diagonalised in z by the discrete sine
+// transform (the eigenvectors of Kz and Mz on a uniform mesh), leaving one
+// tridiagonal system in r per sine mode.  The sine transform of two rows at
+// once is one complex FFT of length 2 nz of their odd extensions, done in LDS.
+#include "pic_internal.h"
+
+namespace pic {
+namespace {
+
+constexpr int kFftBlock = 256;
+
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+// Radix-2 decimation-in-time FFT of N = 2^logN points already stored in
+// bit-reversed order in LDS.  tw[k] = exp(-2 pi i k / tw_n), k < tw_n / 2.
+__device__ void fft_lds(double2* y, int N, int logN, const double2* __restrict__ tw, int tw_n) {
+    for (int s = 1; s <= logN; ++s) {
+        const int half = 1 << (s - 1);
+        const int tstride = tw_n >> s;
+        for (int t = threadIdx.x; t < (N >> 1); t += blockDim.x) {
+            int pos = t & (half - 1);
+            int i0 = ((t >> (s - 1)) << s) + pos;
+            int i1 = i0 + half;
+            double2 v = cmul(y[i1], tw[pos * tstride]);
+            double2 u = y[i0];
+            y[i0] = make_double2(u.x + v.x, u.y + v.y);
+            y[i1] = make_double2(u.x - v.x, u.y - v.y);
+        }
+        __syncthreads();
+    }
+}
+
+// Sine transform of interior rows, two per block.
+//   mode 0: rows of Q * bscale            -> rhs (modes)
+//   mode 1: rows of rhs (already scaled)  -> rhs (modes)
+//   mode 2: rows of rhs (solved modes)    -> phi = phi_vac + (2/nz) DST
+__global__ void __launch_bounds__(kFftBlock) kf_dst(const DevInst* __restrict__ It,
+                                                    const FieldDev* __restrict__ Ft, int inst_base,
+                                                    const double2* __restrict__ tw, int tw_n,
+                                                    int mode, const double* __restrict__ bscale) {
+    extern __shared__ double2 y[];
+    const int inst = inst_base + blockIdx.y;
+    const DevInst& I = It[inst];
+    const FieldDev& F = Ft[inst];
+    const int nz = I.nz, W = I.W;
+    const int iA = 1 + 2 * blockIdx.x, iB = iA + 1;
+    if (I.frozen || iA > I.nr - 1) return;
+    const bool hasB = iB <= I.nr - 1;
+    const int N = 2 * nz;
+    const int logN = 31 - __clz(N);
+    const double bs = mode == 0 ? bscale[inst] : 1.0;
+    for (int j = threadIdx.x; j < N; j += blockDim.x) {
+        int jj = j <= nz ? j : N - j;
+        double sg = j <= nz ? 1.0 : -1.0;
+        double va = 0.0, vb = 0.0;
+        if (jj >= 1 && jj <= nz - 1) {
+            if (mode == 0) {
+                va = (double)F.Q[(long long)iA * W + jj] * bs;
+                vb = hasB ? (double)F.Q[(long long)iB * W + jj] * bs : 0.0;
+            } else {
+                va = F.rhs[(long long)iA * W + jj];
+                vb = hasB ? F.rhs[(long long)iB * W + jj] : 0.0;
+            }
+        }
+        int rj = (int)(__brev((unsigned int)j) >> (32 - logN));
+        y[rj] = make_double2(sg * va, sg * vb);
+    }
+    __syncthreads();
+    fft_lds(y, N, logN, tw, tw_n);
+    // y = -2i X_A + 2 X_B for odd real inputs A (real part) and B (imag part)
+    const double sc = 2.0 / (double)nz;
+    for (int k = threadIdx.x + 1; k <= nz - 1; k += blockDim.x) {
+        double XA = -0.5 * y[k].y, XB = 0.5 * y[k].x;
+        long long nA = (long long)iA * W + k, nB = (long long)iB * W + k;
+        if (mode == 2) {
+            F.phi[nA] = F.phi_vac[nA] + sc * XA;
+            if (hasB) F.phi[nB] = F.phi_vac[nB] + sc * XB;
+        } else {
+            F.rhs[nA] = XA;
+            if (hasB) F.rhs[nB] = XB;
+        }
+    }
+}
+
+// Tridiagonal solve in r for every sine mode k (one thread per mode), with
+// the LU factors precomputed on the host: forward d_i = (b_i - lo_i d_{i-1})
+// im_i, backward x_i = d_i - cp_i x_{i+1}.
+__global__ void kf_thomas(const DevInst* __restrict__ It, const FieldDev* __restrict__ Ft,
+                          int inst_base) {
+    const int inst = inst_base + blockIdx.y;
+    const DevInst& I = It[inst];
+    const FieldDev& F = Ft[inst];
+    const int k = 1 + blockIdx.x * blockDim.x + threadIdx.x;
+    if (I.frozen || k > I.nz - 1) return;
+    const int W = I.W, nri = I.nr - 1;
+    double d = 0.0;
+    for (int i = 1; i <= nri; ++i) {
+        long long n = (long long)i * W + k;
+        d = (F.rhs[n] - F.th_lo[n] * d) * F.th_im[n];
+        F.rhs[n] = d;
+    }
+    double x = d;
+    for (int i = nri - 1; i >= 1; --i) {
+        long long n = (long long)i * W + k;
+        x = F.rhs[n] - F.th_cp[n] * x;
+        F.rhs[n] = x;
+    }
+}
+
+// Boundary rows of phi are the electrode data (the solve covers interior rows).
+__global__ void kf_phi_edges(const DevInst* __restrict__ It, const FieldDev* __restrict__ Ft,
+                             int inst_base) {
+    const int inst = inst_base + blockIdx.y;
+    const DevInst& I = It[inst];
+    const FieldDev& F = Ft[inst];
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int W = I.W;
+    if (I.frozen) return;
+    // rows i=0 and i=nr (W entries each), columns j=0 and j=nz (nr+1 entries each)
+    if (t < W) {
+        F.phi[t] = F.phi_vac[t];
+        long long n = (long long)I.nr * W + t;
+        F.phi[n] = F.phi_vac[n];
+    } else if (t < W + I.nr + 1) {
+        long long i = t - W;
+        F.phi[i * W] = F.phi_vac[i * W];
+        F.phi[i * W + I.nz] = F.phi_vac[i * W + I.nz];
+    }
+}
+
+// E = -grad phi at the nodes (central inside, second-order one-sided on the
+// edges); writes FP64 arrays and/or the packed FP32 {Er, Ez, Br, Bz}.
+__global__ void kf_efield(const DevInst* __restrict__ It, const FieldDev* __restrict__ Ft,
+                          int inst_base) {
+    const int inst = inst_base + blockIdx.y;
+    const DevInst& I = It[inst];
+    const FieldDev& F = Ft[inst];
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (I.frozen || n >= I.nodes) return;
+    const int W = I.W, i = n / W, j = n - i * W;
+    const double hr = 0.5 / I.dr, hz = 0.5 / I.dz;
+    const double* P = F.phi;
+    double gr, gz;
+    if (i == 0) gr = (-3.0 * P[j] + 4.0 * P[W + j] - P[2 * W + j]) * hr;
+    else if (i == I.nr) gr = (3.0 * P[n] - 4.0 * P[n - W] + P[n - 2 * W]) * hr;
+    else gr = (P[n + W] - P[n - W]) * hr;
+    if (j == 0) gz = (-3.0 * P[n] + 4.0 * P[n + 1] - P[n + 2]) * hz;
+    else if (j == I.nz) gz = (3.0 * P[n] - 4.0 * P[n - 1] + P[n - 2]) * hz;
+    else gz = (P[n + 1] - P[n - 1]) * hz;
+    if (F.Er) {
+        F.Er[n] = -gr;
+        F.Ez[n] = -gz;
+    }
+    if (F.EB) F.EB[n] = make_float4((float)(-gr), (float)(-gz), (float)F.Br[n], (float)F.Bz[n]);
+}
+
+__global__ void kz_zero(long long* p, long long n) {
+    for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < n;
+         q += (long long)gridDim.x * blockDim.x)
+        p[q] = 0;
+}
+
+// Every D steps: spatial-max density into the running time max, the
+// time-average accumulator, and windowed wall currents.
+__global__ void ks_sample(const DevInst* __restrict__ It, const FieldDev* __restrict__ Ft,
+                          int inst_base, long long* cnt_base) {
+    const int inst = inst_base + blockIdx.y;
+    const DevInst& I = It[inst];
+    const FieldDev& F = Ft[inst];
+    long long* cnt = cnt_base + (long long)inst * C_NCOUNT;
+    const int D = I.diag_D;
+    if ((cnt[C_STEP] + 1) % D != 0) return;
+    __shared__ double red[256];
+    double mx = 0.0;
+    for (int n = blockIdx.x * blockDim.x + threadIdx.x; n < I.nodes; n += gridDim.x * blockDim.x) {
+        double q = (double)F.Q[n];
+        double dens = (q * I.inv_two_S) / F.V[n];
+        mx = dens > mx ? dens : mx;
+        F.avg_acc[n] += q;
+    }
+    red[threadIdx.x] = mx;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && red[0] > 0.0) atomic_max_pos_double(&cnt[C_PEAK], red[0]);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        cnt[C_NSAMP] += 1;
+        double span = (double)D * I.dt;
+        for (int w = 0; w < 4; ++w) {
+            long long dW = cnt[C_ABS_W + w] - cnt[C_WLAST + w];
+            double cur = (((double)dW * kE) * I.inv_two_S) / span;
+            cnt[C_IWALL + w] = __double_as_longlong(cur);
+            cnt[C_WLAST + w] = cnt[C_ABS_W + w];
+        }
+        double io = __longlong_as_double(cnt[C_IWALL + 1]);
+        double ii = __longlong_as_double(cnt[C_IWALL + 0]);
+        if (io > __longlong_as_double(cnt[C_PEAKI_OUT])) cnt[C_PEAKI_OUT] = __double_as_longlong(io);
+        if (ii > __longlong_as_double(cnt[C_PEAKI_IN])) cnt[C_PEAKI_IN] = __double_as_longlong(ii);
+    }
+}
+
+}  // namespace
+
+hipError_t launch_zero_i64(long long* p, long long n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    long long g = (n + 255) / 256;
+    if (g > 4096) g = 4096;
+    hipLaunchKernelGGL(kz_zero, dim3((unsigned)g), dim3(256), 0, s, p, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_solve_tab(const DevInst* It, const FieldDev* Ft, int inst_base, int n_inst,
+                            int max_nr, int max_nz, const double2* tw, int tw_n, int mode,
+                            const double* bscale, hipStream_t s) {
+    if (n_inst <= 0) return hipSuccess;
+    size_t lds = sizeof(double2) * 2 * (size_t)max_nz;
+    dim3 gdst((unsigned)(max_nr / 2), (unsigned)n_inst);
+    hipLaunchKernelGGL(kf_dst, gdst, dim3(kFftBlock), lds, s, It, Ft, inst_base, tw, tw_n, mode,
+                       bscale);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    dim3 gth((unsigned)((max_nz - 1 + 63) / 64), (unsigned)n_inst);
+    hipLaunchKernelGGL(kf_thomas, gth, dim3(64), 0, s, It, Ft, inst_base);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(kf_dst, gdst, dim3(kFftBlock), lds, s, It, Ft, inst_base, tw, tw_n, 2,
+                       bscale);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    dim3 ged((unsigned)((max_nz + 1 + max_nr + 1 + 255) / 256), (unsigned)n_inst);
+    hipLaunchKernelGGL(kf_phi_edges, ged, dim3(256), 0, s, It, Ft, inst_base);
+    return hipGetLastError();
+}
+
+hipError_t launch_efield_tab(const DevInst* It, const FieldDev* Ft, int inst_base, int n_inst,
+                             long long max_nodes, hipStream_t s) {
+    if (n_inst <= 0) return hipSuccess;
+    dim3 g((unsigned)((max_nodes + 255) / 256), (unsigned)n_inst);
+    hipLaunchKernelGGL(kf_efield, g, dim3(256), 0, s, It, Ft, inst_base);
+    return hipGetLastError();
+}
+
+hipError_t launch_sample_tab(const DevInst* It, const FieldDev* Ft, int inst_base, int n_inst,
+                             long long* cnt, hipStream_t s) {
+    if (n_inst <= 0) return hipSuccess;
+    hipLaunchKernelGGL(ks_sample, dim3(64, (unsigned)n_inst), dim3(256), 0, s, It, Ft, inst_base,
+                       cnt);
+    return hipGetLastError();
+}
+
+hipError_t set_field_kernel_attrs(int max_nz) {
+    size_t lds = sizeof(double2) * 2 * (size_t)max_nz;
+    if (lds > 65536)
+        return hipFuncSetAttribute((const void*)kf_dst, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   (int)lds);
+    return hipSuccess;
+}
+
+}  // namespace pic

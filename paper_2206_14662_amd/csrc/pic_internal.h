@@ -1,0 +1,159 @@
+// pic_internal.h -- shared declarations of the gfx950 PIC-MCC library:
+// the per-instance parameter block the kernels read, the device counter
+// layout, the Philox4x32-10 generator and the kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "pic.h"
+
+namespace pic {
+
+// CODATA 2018
+constexpr double kE = 1.602176634e-19;
+constexpr double kMe = 9.1093837015e-31;
+constexpr double kEps0 = 8.8541878128e-12;
+constexpr double kKb = 1.380649e-23;
+constexpr double kAmu = 1.66053906660e-27;
+constexpr double kPi = 3.14159265358979323846;
+
+// Per-instance constants read by the kernels (plain old data, passed by
+// value to the per-instance FP64 kernels and stored as a device table for the
+// batched FP32 kernels).
+struct DevInst {
+    // mesh
+    double a, b, L, dr, dz, inv_dr, inv_dz;
+    int nr, nz, W, nodes;           // W = nz + 1, nodes = (nr+1) W
+    long long node_off;             // offset of this instance in batched node arrays
+    // push
+    double h, dt;
+    // collisions
+    double P_null, nu_prime, nsig_el, n_n, lotz_aq, iz_I, opal_Ebar, okh_xi;
+    double half_me_over_e, two_e_over_me, mass_ratio2, v_cap2;
+    unsigned long long null_k;      // u52 < P_null  <=>  (x >> 12) < null_k
+    unsigned int seed_lo, seed_hi;
+    int collisions;
+    int frozen;
+    // fixed point
+    double two_S, inv_two_S;
+    // particle segment (batched form)
+    long long p_off, p_cap;
+    // single-precision copies for the FP32 form
+    float a_f, b_f, L_f, inv_dr_f, inv_dz_f, h_f, dt_f;
+    float nu_prime_f, nsig_el_f, n_n_f, lotz_aq_f, iz_I_f, opal_Ebar_f, okh_xi_f;
+    float half_me_over_e_f, two_e_over_me_f, mass_ratio2_f, v_cap2_f;
+    // sort tiles (FP32 form)
+    int ntr, ntz;                   // tiles in r and z
+    int tile_off;                   // first global tile id of this instance
+    int diag_D;                     // steps between diagnostic samples
+};
+
+// Device counter block per instance (long long entries).
+enum Counter {
+    C_SLOTS = 0,      // used particle slots (live + dead), at step start
+    C_SPAWN,          // electrons created in the current step
+    C_DEAD,           // dead slots among C_SLOTS
+    C_STEP,           // step counter (Philox counter word 2)
+    C_ELASTIC,
+    C_IONIZ,
+    C_CAND,
+    C_CAPOVER,
+    C_DROPPED,
+    C_ABS_N,          // 4 entries
+    C_ABS_W = C_ABS_N + 4,   // 4 entries
+    C_WLAST = C_ABS_W + 4,   // 4 entries: absorbed_W at the last sample
+    C_IWALL = C_WLAST + 4,   // 4 entries: double bits, last window current
+    C_PEAK = C_IWALL + 4,    // double bits: time max of spatial max density
+    C_PEAKI_OUT,             // double bits
+    C_PEAKI_IN,              // double bits
+    C_NSAMP,
+    C_OVERFLOW,              // fixed-point overflow flag
+    C_LIVE_SORTED,           // live particles in the sorted region (FP32 form)
+    C_NCOUNT = 40
+};
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon et al., SC'11): ten rounds of two 32x32->64 products
+// of counter words 0 and 2 by fixed multipliers, xor-mixed with the key,
+// with the key advanced by two Weyl constants between rounds.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint4 philox4x32_10(uint4 c, unsigned int k0, unsigned int k1) {
+    const unsigned int M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+    const unsigned int W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+#pragma unroll
+    for (int round = 0; round < 10; ++round) {
+        unsigned int hi0 = __umulhi(M0, c.x), lo0 = M0 * c.x;
+        unsigned int hi1 = __umulhi(M1, c.z), lo1 = M1 * c.z;
+        c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
+        k0 += W0;
+        k1 += W1;
+    }
+    return c;
+}
+
+// Open-interval uniform from the top 52 bits of hi:lo (exact in FP64).
+__device__ __forceinline__ double u52(unsigned int hi, unsigned int lo) {
+    unsigned long long x = ((unsigned long long)hi << 32) | (unsigned long long)lo;
+    return ((double)(x >> 12) + 0.5) * 0x1p-52;
+}
+// Open-interval uniform from the top 23 bits of a word (exact in FP32).
+__device__ __forceinline__ float u23(unsigned int w) {
+    return ((float)(w >> 9) + 0.5f) * 0x1p-23f;
+}
+
+// Positive doubles order like their bit patterns.
+__device__ __forceinline__ void atomic_max_pos_double(long long* slot, double v) {
+    atomicMax((unsigned long long*)slot, (unsigned long long)__double_as_longlong(v));
+}
+
+// ---------------------------------------------------------------------------
+// Kernel launchers (defined in the .hip files).
+// ---------------------------------------------------------------------------
+
+// FP64 plain form (k_fp64.hip)
+struct P64 {
+    double *r, *z, *vr, *vt, *vz, *w;
+    unsigned long long* key;
+};
+hipError_t launch_load64(const DevInst& I, const pic_instance_cfg& c, P64 p, long long n,
+                         hipStream_t s);
+hipError_t launch_push64(const DevInst& I, P64 p, const double* Er, const double* Ez,
+                         const double* Br, const double* Bz, long long* cnt, long long grid_cap,
+                         hipStream_t s);
+hipError_t launch_mcc64(const DevInst& I, P64 p, long long* cnt, long long grid_cap,
+                        hipStream_t s);
+hipError_t launch_deposit64(const DevInst& I, P64 p, long long* Q, long long* cnt,
+                            long long grid_cap, hipStream_t s);
+hipError_t launch_commit(const DevInst* I, long long* cnt, int n_inst, hipStream_t s);
+hipError_t launch_compact64(const DevInst& I, P64 src, P64 dst, long long* cnt,
+                            long long* tmp_count, long long grid_cap, hipStream_t s);
+
+// Field solve and diagnostics (k_field.hip), FP64.
+struct FieldDev {
+    long long* Q;          // fixed-point charge (nodes)
+    double* rhs;           // scratch node array: transformed rows / modes
+    double* phi;           // potential (nodes)
+    const double* phi_vac; // vacuum potential (nodes), boundary data on the edges
+    const double* th_cp;   // Thomas factors, [i][k] with row length W
+    const double* th_im;
+    const double* th_lo;
+    double *Er, *Ez;       // FP64 plain form outputs (or null)
+    const double *Br, *Bz;
+    float4* EB;            // FP32 form output (or null)
+    const double* V;       // node volumes
+    double* avg_acc;       // time-average accumulator
+};
+hipError_t launch_zero_i64(long long* p, long long n, hipStream_t s);
+// Poisson solve of instances [inst_base, inst_base+n_inst) of the device
+// tables: mode 0 from Q (scaled by bscale[inst]), mode 1 from rhs.
+hipError_t launch_solve_tab(const DevInst* It, const FieldDev* Ft, int inst_base, int n_inst,
+                            int max_nr, int max_nz, const double2* tw, int tw_n, int mode,
+                            const double* bscale, hipStream_t s);
+hipError_t launch_efield_tab(const DevInst* It, const FieldDev* Ft, int inst_base, int n_inst,
+                             long long max_nodes, hipStream_t s);
+hipError_t launch_sample_tab(const DevInst* It, const FieldDev* Ft, int inst_base, int n_inst,
+                             long long* cnt, hipStream_t s);
+hipError_t set_field_kernel_attrs(int max_nz);
+
+}  // namespace pic

@@ -1,0 +1,70 @@
+"""The C ABI library loads, exports every declared symbol, and its host-only
+logic (derived constants, fixed-point rule, validation) agrees with the
+oracle bit for bit.  No GPU needed."""
+import os
+import re
+
+import pytest
+
+import oracle
+import pic_inputs as pi
+from paper_2206_14662_amd import binding as B
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    text = open(os.path.join(ROOT, "include", "pic.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(pic_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = B.lib()
+    syms = declared_symbols()
+    assert len(syms) >= 17
+    for s in syms:
+        assert hasattr(L, s), s
+    assert set(syms) <= set(B.EXPORTS)
+
+
+def test_struct_sizes_match_header_layout():
+    import ctypes as C
+    # pic_instance_cfg: 3 doubles, 2 ints, 3 doubles, 1 int (+pad), ... computed by ctypes
+    assert C.sizeof(B.pic_instance_cfg) % 8 == 0
+    assert C.sizeof(B.pic_diag_t) % 8 == 0
+
+
+@pytest.mark.parametrize("cfg", [pi.coax64(), pi.coax64hot(), pi.coax256(), pi.coax512()] + pi.scan32()[:4] + pi.batch8()[:3])
+def test_derive_bit_equal_to_oracle(cfg):
+    S = B.pic_auto_shift(cfg["weight"])
+    assert S == oracle.auto_shift(cfg["weight"])
+    lib_d = B.pic_derive(cfg, S)
+    orc_d = oracle.derive(cfg, fx_shift=S)
+    for k, v in orc_d.items():
+        assert lib_d[k] == v, (k, lib_d[k], v)
+
+
+def test_init_rejects_bad_configs_without_touching_a_gpu():
+    bad = [
+        dict(pi.coax64(), nz=100),          # not a power of two
+        dict(pi.coax64(), a=0.02),          # a > b
+        dict(pi.coax64(), dt=0.0),
+        dict(pi.coax64(), okh_xi=1.0),
+        dict(pi.coax64(), r_lo=0.5e-3),     # load box below a
+        dict(pi.coax64(), E_cap_eV=0.0),
+    ]
+    for c in bad:
+        with pytest.raises(B.PicError) as e:
+            B.pic_init([c], use_torch=False)
+        assert e.value.status == B.PIC_EINVAL
+    with pytest.raises(B.PicError) as e:
+        B.pic_init([pi.coax64()], mode=7, use_torch=False)
+    assert e.value.status == B.PIC_EINVAL
+
+
+def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
+    monkeypatch.setattr(B, "_lib", None)
+    monkeypatch.setattr(B, "LIB_PATH", str(tmp_path / "missing.so"))
+    with pytest.raises(RuntimeError):
+        B.lib()
