@@ -124,6 +124,7 @@ typedef struct {
     double peak_density;       /* time max of the spatial max density (m^-3)    */
     double peak_time_avg_density; /* spatial max of the time-averaged density    */
     double peak_I_outer, peak_I_inner; /* max over windows of I_wall[1], I_wall[0] */
+    long long particle_steps;  /* live macro-electrons pushed, summed over steps */
 } pic_diag_t;
 
 /* Host-derived constants of an instance (FP64); see pic_derive. */

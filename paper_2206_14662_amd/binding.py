@@ -70,6 +70,7 @@ class pic_diag_t(C.Structure):
         ("S", C.c_int), ("total_charge_C", C.c_double), ("I_wall", C.c_double * 4),
         ("peak_density", C.c_double), ("peak_time_avg_density", C.c_double),
         ("peak_I_outer", C.c_double), ("peak_I_inner", C.c_double),
+        ("particle_steps", C.c_longlong),
     ]
 
 

@@ -355,6 +355,18 @@ pic_status pic_solve_all(pic_ctx* ctx) {
     return PIC_OK;
 }
 
+pic_status pic_field_stage(pic_ctx* ctx, hipStream_t s) {
+    int n = (int)ctx->in.size();
+    CK(launch_solve_tab(ctx->dI, ctx->dF, 0, n, ctx->max_nr, ctx->max_nz, ctx->tw, ctx->tw_n, 0,
+                        ctx->dbscale, s));
+    CK(launch_efield_tab(ctx->dI, ctx->dF, 0, n, ctx->max_nodes, s));
+    CK(launch_sample_tab(ctx->dI, ctx->dF, 0, n, ctx->dcnt, s));
+    CK(launch_commit(ctx->dI, ctx->dcnt, n, s));
+    return PIC_OK;
+}
+
+FieldDev* pic_field_table(pic_ctx* ctx) { return ctx->dF; }
+
 pic_status pic_sample_all(pic_ctx* ctx) {
     CK(launch_sample_tab(ctx->dI, ctx->dF, 0, (int)ctx->in.size(), ctx->dcnt, ctx->stream));
     return PIC_OK;
@@ -525,10 +537,10 @@ extern "C" pic_status pic_init(const pic_run_cfg* run, const pic_instance_cfg* i
         Inst& in = ctx->in[k];
         in.c = inst[k];
         if (in.c.diag_interval <= 0) in.c.diag_interval = 1;
-        in.S = in.c.fx_shift != 0 ? in.c.fx_shift : pic_auto_shift(in.c.n_init > 0 ? in.c.weight : 1.0);
+        in.S = in.c.fx_shift != 0 ? in.c.fx_shift : pic_auto_shift(in.c.weight > 0.0 ? in.c.weight : 1.0);
         in.c.fx_shift = in.S;
         pic_derive(&in.c, in.S, &in.d);
-        if (in.c.n_init > 0 && ldexp(in.c.weight, in.S) > 2147483648.0)
+        if (in.c.weight > 0.0 && ldexp(in.c.weight, in.S) > 2147483648.0)
             st = fail(ctx, PIC_EOVERFLOW, "weight * 2^S exceeds 2^31");
         in.cap = std::max<long long>(cmin, (long long)ceil(cf * (double)in.c.n_init));
         in.nodes = (long long)(in.c.nr + 1) * (in.c.nz + 1);
@@ -589,6 +601,7 @@ extern "C" pic_status pic_init(const pic_run_cfg* run, const pic_instance_cfg* i
         }
     }
     if (st == PIC_OK) st = deposit_and_solve(ctx, -1);
+    if (st == PIC_OK && ctx->mode == PIC_MODE_FP32_BATCHED) st = f32_sort_now(ctx);
     if (st == PIC_OK) {
         e = hipStreamSynchronize(ctx->stream);
         if (e != hipSuccess) st = fail(ctx, PIC_EDEVICE, std::string("init: ") + hipGetErrorString(e));
@@ -647,6 +660,7 @@ static pic_status check_counts(pic_ctx* ctx, std::vector<long long>& cnt) {
         if (cnt[k * C_NCOUNT + C_OVERFLOW] > 0)
             return fail(ctx, PIC_EOVERFLOW, "instance " + std::to_string(k) + ": fixed-point overflow");
     }
+    if (ctx->mode == PIC_MODE_FP32_BATCHED) return f32_check(ctx);
     return PIC_OK;
 }
 
@@ -695,9 +709,7 @@ static pic_status step64(pic_ctx* ctx, int n_steps) {
                 CK(launch_mcc64(in.I, p, in.cnt, in.cap, s));
                 CK(launch_deposit64(in.I, p, in.Q, in.cnt, in.cap, s));
             }
-            st = pic_solve_all(ctx);
-            if (st == PIC_OK) st = pic_sample_all(ctx);
-            if (st == PIC_OK) st = pic_commit_all(ctx);
+            st = pic_field_stage(ctx, s);
             if (st != PIC_OK) return st;
             ctx->host_step += 1;
         }
@@ -772,8 +784,14 @@ extern "C" pic_status pic_set_particles(pic_ctx* ctx, int k, long long n, const 
     }
     long long upd[3] = {n, 0, 0};
     CK(hipMemcpy(in.cnt + C_SLOTS, upd, sizeof(upd), hipMemcpyHostToDevice));
+    long long zero = 0;
+    CK(hipMemcpy(in.cnt + C_LIVE_SORTED, &zero, sizeof(zero), hipMemcpyHostToDevice));
     st = deposit_and_solve(ctx, k);
     if (st != PIC_OK) return st;
+    if (ctx->mode == PIC_MODE_FP32_BATCHED) {
+        st = f32_sort_now(ctx);
+        if (st != PIC_OK) return st;
+    }
     CK(hipStreamSynchronize(s));
     return PIC_OK;
 }
@@ -926,6 +944,7 @@ extern "C" pic_status pic_diag(pic_ctx* ctx, int k, pic_diag_t* out, double* den
     memcpy(&out->peak_I_outer, &c[C_PEAKI_OUT], 8);
     memcpy(&out->peak_I_inner, &c[C_PEAKI_IN], 8);
     out->n_samples = c[C_NSAMP];
+    out->particle_steps = c[C_PSTEPS];
     out->S = in.S;
     if (ctx->mode == PIC_MODE_FP64_PLAIN) out->n_live = c[C_SLOTS] - c[C_DEAD];
     else out->n_live = f32_live_count(ctx, k, c);

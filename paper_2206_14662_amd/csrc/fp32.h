@@ -29,6 +29,9 @@ F32State* pic_get_f32(pic_ctx* ctx);
 pic_status pic_solve_all(pic_ctx* ctx);
 pic_status pic_sample_all(pic_ctx* ctx);
 pic_status pic_commit_all(pic_ctx* ctx);
+// FP64 field solve, nodal E, diagnostics sample and step commit on stream s
+pic_status pic_field_stage(pic_ctx* ctx, hipStream_t s);
+pic::FieldDev* pic_field_table(pic_ctx* ctx);
 
 // the FP32 form (fp32.hip)
 pic_status f32_init(pic_ctx* ctx);
@@ -36,12 +39,14 @@ void f32_destroy(pic_ctx* ctx);
 pic_status f32_load(pic_ctx* ctx, int k);
 pic_status f32_deposit_only(pic_ctx* ctx, int k);
 pic_status f32_step(pic_ctx* ctx, int n_steps);
+pic_status f32_sort_now(pic_ctx* ctx);
 pic_status f32_set_particles(pic_ctx* ctx, int k, long long n, const double* r, const double* z,
                              const double* vr, const double* vt, const double* vz, const double* w,
                              const unsigned long long* key);
 pic_status f32_get_particles(pic_ctx* ctx, int k, double* r, double* z, double* vr, double* vt,
                              double* vz, double* w, unsigned long long* key, long long cap,
                              long long* n_out);
+pic_status f32_check(pic_ctx* ctx);
 long long f32_live_count(pic_ctx* ctx, int k, const long long* cnt);
 pic_status f32_tuning(pic_ctx* ctx, int* tile_r, int* tile_z, int* halo, int* sort_interval,
                       int* chunk);

@@ -1,20 +1,1250 @@
-// fp32.hip -- placeholder of the batched FP32 form.
+// fp32.hip -- the batched FP32 form of the particle loop.
+//
+// Layout: all instances share one SoA FP32 particle store (r, z, vr, vt, vz,
+// w as float, key as uint64); instance k owns slots [p_off, p_off + p_cap).
+// Two such stores are kept; the tile sort scatters from one to the other.
+// After a sort an instance's slots hold its live particles grouped by tile
+// (a TR x TZ block of cells); electrons created since the sort sit after them
+// (the tail).
+//
+// One step is a fixed launch sequence (captured once as a HIP graph):
+//   zero Q -> plan tail work -> particle kernel -> FP64 field solve -> sample
+//   -> commit
+// and every K steps the tile sort (count -> plan -> scatter -> commit).
+//
+// The particle kernel is persistent: each workgroup pulls work items
+// (a chunk of <= C particles of one tile, or of an instance's tail) from an
+// atomic cursor.  For a tile chunk it stages the tile's field window (tile
+// plus `halo` cells, float4 {Er, Ez, Br, Bz} per node) in LDS, accumulates the
+// chunk's charge in an LDS int64 window, then flushes non-zero window nodes
+// to the global grid with int64 atomics.  Integer sums do not depend on
+// order, so the deposited grid is the same for any schedule.  Per particle:
+// coalesced SoA loads, bilinear gather, Boris, cylindrical remap, absorbing
+// walls, one Philox4x32-10 block for the null-collision test (an integer
+// compare on the top 52 bits, the same decision the FP64 form takes), rarely
+// an elastic or ionising collision, fixed-point deposit, coalesced stores.
+#include <string.h>
+
+#include <algorithm>
+#include <vector>
+
 #include "fp32.h"
 
-struct F32State {};
+// Contraction is off in this file and fused multiply-adds are written out:
+// every instantiation of the particle kernel then evaluates each particle's
+// update with the same operations, so results do not depend on which kernel
+// variant (plain, counting, scattering) advanced a particle.
+#pragma clang fp contract(off)
 
-pic_status f32_init(pic_ctx* ctx) { pic_set_error(ctx, "FP32 form not available"); return PIC_EINVAL; }
-void f32_destroy(pic_ctx*) {}
-pic_status f32_load(pic_ctx*, int) { return PIC_EINVAL; }
-pic_status f32_deposit_only(pic_ctx*, int) { return PIC_EINVAL; }
-pic_status f32_step(pic_ctx*, int) { return PIC_EINVAL; }
-pic_status f32_set_particles(pic_ctx*, int, long long, const double*, const double*, const double*,
-                             const double*, const double*, const double*, const unsigned long long*) {
-    return PIC_EINVAL;
+using namespace pic;
+
+namespace {
+
+constexpr int kWG = 256;
+
+struct PSet {
+    float *r, *z, *vr, *vt, *vz, *w;
+    unsigned long long* key;
+};
+
+struct Chunk {
+    long long start;   // first slot (absolute)
+    int count;         // particles
+    int inst;
+    int tr0, tz0;      // first cell of the tile (r, z); tr0 < 0 for tail chunks
+    int pad0, pad1;
+};
+
+// control block: [0] cursor, [1] total work items, [2] tile chunks,
+// [3] collision candidates queued this step, [4] queue overflow flag,
+// [5 .. 5+n_inst] tail chunk prefix per instance
+enum { CTL_CURSOR = 0, CTL_TOTAL = 1, CTL_SORTED = 2, CTL_QCOUNT = 3, CTL_QOVER = 4, CTL_TAIL = 5 };
+
+struct KArgs {
+    const DevInst* It;
+    const FieldDev* Ft;
+    long long* cnt;
+    PSet p;                        // input store
+    PSet out;                      // output store of a scatter step
+    const Chunk* chunks;
+    long long* ctl;
+    unsigned int* cnt_out;         // per-tile totals being counted (COUNT)
+    unsigned int* tile_fill;       // per-tile ranks handed out (SCATTER)
+    const long long* tile_start;   // first slot of each tile in the output store
+    const long long* new_base;     // per instance: slots of the sorted output
+    unsigned long long* queue;     // collision candidates: (instance << 40) | slot
+    long long qcap;
+    int n_inst, TR, TZ, halo, C, win_max;
+};
+
+// ---- shared device helpers ------------------------------------------------
+
+__device__ __forceinline__ void cell_of(const DevInst& I, float r, float z, int& i, int& j, float& fr,
+                                        float& fz) {
+    float s = (r - I.a_f) * I.inv_dr_f;
+    float t = z * I.inv_dz_f;
+    float si = floorf(s), tj = floorf(t);
+    i = (int)si;
+    j = (int)tj;
+    i = i < 0 ? 0 : (i > I.nr - 1 ? I.nr - 1 : i);
+    j = j < 0 ? 0 : (j > I.nz - 1 ? I.nz - 1 : j);
+    fr = s - (float)i;
+    fz = t - (float)j;
 }
-pic_status f32_get_particles(pic_ctx*, int, double*, double*, double*, double*, double*, double*,
-                             unsigned long long*, long long, long long*) {
-    return PIC_EINVAL;
+
+__device__ __forceinline__ uint4 philox_step(const DevInst& I, unsigned long long key, unsigned int step,
+                                             unsigned int b) {
+    return philox4x32_10(make_uint4((unsigned int)key, (unsigned int)(key >> 32), step, b), I.seed_lo,
+                         I.seed_hi);
 }
-long long f32_live_count(pic_ctx*, int, const long long*) { return 0; }
-pic_status f32_tuning(pic_ctx*, int*, int*, int*, int*, int*) { return PIC_EINVAL; }
+
+__device__ __forceinline__ unsigned long long wave_sum(unsigned long long v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
+
+__device__ __forceinline__ void flush_counter(long long* slot, unsigned long long v) {
+    if (__ballot(v != 0ull) == 0ull) return;
+    v = wave_sum(v);
+    if (__lane_id() == 0) atomicAdd((unsigned long long*)slot, v);
+}
+
+__device__ __forceinline__ float okh_cos_f(float xi, float u) {
+    return ((2.0f * u + xi) - 1.0f) / ((1.0f - xi) + (2.0f * xi) * u);
+}
+
+__device__ __forceinline__ void scatter_f(float ur, float ut, float uz, float cosx, float phi, float* o) {
+    float e1r, e1t, e1z;
+    if (fabsf(uz) < 0.99f) {
+        float nn = rsqrtf(ur * ur + ut * ut);
+        e1r = -ut * nn; e1t = ur * nn; e1z = 0.0f;
+    } else {
+        float nn = rsqrtf(uz * uz + ut * ut);
+        e1r = 0.0f; e1t = -uz * nn; e1z = ut * nn;
+    }
+    float e2r = ut * e1z - uz * e1t;
+    float e2t = uz * e1r - ur * e1z;
+    float e2z = ur * e1t - ut * e1r;
+    float sinx = sqrtf(fmaxf(0.0f, 1.0f - cosx * cosx));
+    float sp, cp;
+    sincosf(phi, &sp, &cp);
+    o[0] = cosx * ur + sinx * (cp * e1r + sp * e2r);
+    o[1] = cosx * ut + sinx * (cp * e1t + sp * e2t);
+    o[2] = cosx * uz + sinx * (cp * e1z + sp * e2z);
+}
+
+// Rare path: the null-collision candidate became a real event (or not).
+// Returns 0 null, 1 elastic, 2 ionisation (child written, or dropped when the
+// instance's slots are full: then 3).
+__device__ __forceinline__ int collide_f(const DevInst& I, long long* cnt, PSet P, unsigned long long key,
+                                      unsigned int step, uint4 b0, float r, float z, float w, float& vr,
+                                      float& vt, float& vz, long long slots) {
+    float u_proc = u23(b0.z);
+    float v2 = (vr * vr + vt * vt) + vz * vz;
+    float v = sqrtf(v2);
+    float E = v2 * I.half_me_over_e_f;
+    float nu_el = I.nsig_el_f * v;
+    float sig = 0.0f;
+    if (E > I.iz_I_f) sig = (I.lotz_aq_f * logf(E / I.iz_I_f)) / (E * I.iz_I_f);
+    float nu_iz = (I.n_n_f * sig) * v;
+    float R = u_proc * I.nu_prime_f;
+    int ev;
+    if (R < nu_el) ev = 1;
+    else if (R < nu_el + nu_iz) ev = 2;
+    else return 0;
+    float inv_v = 1.0f / v;
+    float ur = vr * inv_v, ut = vt * inv_v, uz = vz * inv_v;
+    uint4 b1 = philox_step(I, key, step, 1u);
+    float cos1 = okh_cos_f(I.okh_xi_f, u23(b1.x));
+    float phi1 = 6.28318530717958648f * u23(b1.z);
+    float dir[3];
+    if (ev == 1) {
+        float En = E * (1.0f - I.mass_ratio2_f * (1.0f - cos1));
+        float vn = sqrtf(En * I.two_e_over_me_f);
+        scatter_f(ur, ut, uz, cos1, phi1, dir);
+        vr = vn * dir[0]; vt = vn * dir[1]; vz = vn * dir[2];
+        return 1;
+    }
+    uint4 b2 = philox_step(I, key, step, 2u);
+    uint4 b3 = philox_step(I, key, step, 3u);
+    float E_av = E - I.iz_I_f;
+    float E_s = I.opal_Ebar_f * tanf(u23(b2.x) * atanf(E_av / (2.0f * I.opal_Ebar_f)));
+    float E_p = E_av - E_s;
+    float cos2 = okh_cos_f(I.okh_xi_f, u23(b2.z));
+    float phi2 = 6.28318530717958648f * u23(b3.x);
+    float vp = sqrtf(fmaxf(E_p, 0.0f) * I.two_e_over_me_f);
+    float vs = sqrtf(fmaxf(E_s, 0.0f) * I.two_e_over_me_f);
+    scatter_f(ur, ut, uz, cos1, phi1, dir);
+    vr = vp * dir[0]; vt = vp * dir[1]; vz = vp * dir[2];
+    scatter_f(ur, ut, uz, cos2, phi2, dir);
+    long long k = (long long)atomicAdd((unsigned long long*)&cnt[C_SPAWN], 1ull);
+    long long rel = slots + k;
+    if (rel >= I.p_cap) {
+        atomicAdd((unsigned long long*)&cnt[C_DROPPED], 1ull);
+        return 3;
+    }
+    long long d = I.p_off + rel;
+    P.r[d] = r; P.z[d] = z;
+    P.vr[d] = vs * dir[0]; P.vt[d] = vs * dir[1]; P.vz[d] = vs * dir[2];
+    P.w[d] = w;
+    P.key[d] = ((((unsigned long long)b3.z) << 32) | (unsigned long long)b3.w) | (1ull << 63);
+    return 2;
+}
+
+// Fixed-point charges of one particle with bilinear weights from (fr, fz):
+// W = rint(w 2^S) (exact: a power-of-two scaling of w), three nodes take
+// rint(W w_k) (FP32 product), the fourth the remainder, so every particle
+// adds exactly W.
+__device__ __forceinline__ void node_charges(float w, float two_S, float fr, float fz, long long& q00,
+                                             long long& q10, long long& q01, long long& q11) {
+    const float Wf = rintf(w * two_S);
+    const float gr = 1.0f - fr, gz = 1.0f - fz;
+    const unsigned int Wu = (unsigned int)Wf;
+    const unsigned int a = (unsigned int)rintf(Wf * (gr * gz));
+    const unsigned int b = (unsigned int)rintf(Wf * (fr * gz));
+    const unsigned int c = (unsigned int)rintf(Wf * (gr * fz));
+    q00 = (long long)a;
+    q10 = (long long)b;
+    q01 = (long long)c;
+    q11 = (long long)Wu - (long long)a - (long long)b - (long long)c;
+}
+
+// One atomic per distinct key among the active lanes of the wave (the key's
+// lanes add their count at once); with RET each lane gets its rank: the
+// returned base plus its position among the lanes sharing the key.  Every
+// lane of the wave must call it.
+template <bool RET, typename F>
+__device__ __forceinline__ unsigned int wave_aggregate(bool act, int key, F&& add) {
+    const int lane = __lane_id();
+    unsigned long long todo = __ballot(act);
+    unsigned int rank = 0;
+    while (todo) {
+        const int leader = __ffsll((long long)todo) - 1;
+        const int k = __shfl(key, leader);
+        const unsigned long long m = __ballot(act && key == k) & todo;
+        unsigned int base = 0;
+        if (lane == leader) base = add(k, (unsigned int)__popcll(m));
+        if (RET) {
+            base = __shfl(base, leader);
+            if ((m >> lane) & 1ull) rank = base + (unsigned int)__popcll(m & ((1ull << lane) - 1ull));
+        }
+        todo &= ~m;
+    }
+    return rank;
+}
+
+// chunk-level event counters kept in LDS and their device counter slots
+enum { SC_ABS_N = 0, SC_ABS_W = 4, SC_DEAD = 8, SC_CAND = 9, SC_CAP = 10, SC_N = 11 };
+__constant__ int kCounterOf[SC_N] = {C_ABS_N,     C_ABS_N + 1, C_ABS_N + 2, C_ABS_N + 3, C_ABS_W, C_ABS_W + 1,
+                                     C_ABS_W + 2, C_ABS_W + 3, C_DEAD,      C_CAND,      C_CAPOVER};
+
+// ---- the particle kernel --------------------------------------------------
+//
+// MODE bit 1 (COUNT): after the push, count every survivor (and new
+// electron) in the tile of its new position; these totals size the next
+// sort.  MODE bit 2 (SCATTER): each particle's destination in the other
+// store is fixed by the tile of its position at step start (the totals of
+// the previous COUNT give each tile's first slot); a tile chunk reserves
+// room for its particles per neighbouring destination tile with one atomic
+// each, particles outside the 3x3 neighbourhood and tail particles take
+// single ranks.  The updated particle (or a dead marker if it was absorbed)
+// is written there instead of in place.
+template <int MODE>
+__global__ void __launch_bounds__(kWG) k_particles(KArgs A) {
+    constexpr bool COUNT = (MODE & 1) != 0;
+    constexpr bool SCATTER = (MODE & 2) != 0;
+    extern __shared__ __align__(16) unsigned char smem[];
+    float4* sEB = (float4*)smem;
+    unsigned long long* sQ = (unsigned long long*)(smem + sizeof(float4) * (size_t)A.win_max);
+    __shared__ long long s_start;
+    __shared__ int s_count, s_inst, s_tr0, s_tz0;
+    __shared__ unsigned int s_bcnt[9], s_bbase[9];
+    __shared__ unsigned long long s_ctr[SC_N];
+    const int tid = threadIdx.x;
+    for (;;) {
+        if (tid == 0) {
+            long long c = (long long)atomicAdd((unsigned long long*)&A.ctl[CTL_CURSOR], 1ull);
+            long long total = A.ctl[CTL_TOTAL], nsorted = A.ctl[CTL_SORTED];
+            if (c >= total) {
+                s_count = -1;
+            } else if (c < nsorted) {
+                Chunk ch = A.chunks[c];
+                s_start = ch.start; s_count = ch.count; s_inst = ch.inst; s_tr0 = ch.tr0; s_tz0 = ch.tz0;
+            } else {
+                long long t = c - nsorted;
+                const long long* tb = A.ctl + CTL_TAIL;
+                int lo = 0, hi = A.n_inst;  // tb[lo] <= t < tb[hi]
+                while (hi - lo > 1) {
+                    int mid = (lo + hi) >> 1;
+                    if (tb[mid] <= t) lo = mid; else hi = mid;
+                }
+                const DevInst& J = A.It[lo];
+                const long long* cj = A.cnt + (long long)lo * C_NCOUNT;
+                long long first = cj[C_LIVE_SORTED] + (t - tb[lo]) * A.C;
+                long long end = cj[C_SLOTS];
+                s_start = J.p_off + first;
+                s_count = (int)min((long long)A.C, end - first);
+                s_inst = lo; s_tr0 = -1; s_tz0 = -1;
+            }
+        }
+        if (SCATTER && tid < 9) s_bcnt[tid] = 0u;
+        if (tid < SC_N) s_ctr[tid] = 0ull;
+        __syncthreads();
+        const int count = __builtin_amdgcn_readfirstlane(s_count);
+        if (count < 0) break;
+        const long long start = s_start;
+        const int inst = __builtin_amdgcn_readfirstlane(s_inst);
+        const int tr0 = __builtin_amdgcn_readfirstlane(s_tr0), tz0 = __builtin_amdgcn_readfirstlane(s_tz0);
+        const DevInst& I = A.It[inst];
+        const FieldDev& F = A.Ft[inst];
+        long long* cnt = A.cnt + (long long)inst * C_NCOUNT;
+        const unsigned int step = (unsigned int)cnt[C_STEP];
+        const PSet out = SCATTER ? A.out : A.p;
+        const int W = I.W;
+        const bool win = tr0 >= 0;
+        const int ti_c = win ? tr0 / A.TR : 0, tj_c = win ? tz0 / A.TZ : 0;
+        int i0 = 0, i1 = -1, j0 = 0, j1 = -1, ww = 1;
+        if (win) {
+            i0 = max(tr0 - A.halo, 0);
+            i1 = min(tr0 + A.TR + A.halo, I.nr);
+            j0 = max(tz0 - A.halo, 0);
+            j1 = min(tz0 + A.TZ + A.halo, I.nz);
+            ww = j1 - j0 + 1;
+            const int nwin = (i1 - i0 + 1) * ww;
+            for (int t = tid; t < nwin; t += kWG) {
+                int a = t / ww, b = t - a * ww;
+                sEB[t] = F.EB[(long long)(i0 + a) * W + (j0 + b)];
+                sQ[t] = 0ull;
+            }
+        }
+        if (SCATTER && win) {
+            // pass 1: destinations of this chunk's particles per neighbouring tile
+            for (int base = 0; base < count; base += kWG) {
+                const int q = base + tid;
+                float r = q < count ? A.p.r[start + q] : -1.0f;
+                int bkt = -1;
+                if (r >= 0.0f) {
+                    int i, j;
+                    float fr, fz;
+                    cell_of(I, r, A.p.z[start + q], i, j, fr, fz);
+                    int dr = i / A.TR - ti_c, dz = j / A.TZ - tj_c;
+                    if (dr >= -1 && dr <= 1 && dz >= -1 && dz <= 1) bkt = (dr + 1) * 3 + (dz + 1);
+                }
+                wave_aggregate<false>(bkt >= 0, bkt, [&](int k, unsigned int n) {
+                    atomicAdd(&s_bcnt[k], n);
+                    return 0u;
+                });
+            }
+            __syncthreads();
+            if (tid < 9) {
+                unsigned int n = s_bcnt[tid];
+                if (n) {
+                    int t = I.tile_off + (ti_c + tid / 3 - 1) * I.ntz + (tj_c + tid % 3 - 1);
+                    s_bbase[tid] = atomicAdd(&A.tile_fill[t], n);
+                }
+                s_bcnt[tid] = 0u;
+            }
+        }
+        __syncthreads();
+        unsigned int c_push = 0;
+        const float h = I.h_f, dt = I.dt_f;
+        const float two_S = (float)I.two_S;
+        for (int base = 0; base < count; base += kWG) {
+            const int q = base + tid;
+            const long long p = start + q;
+            float r = q < count ? A.p.r[p] : -1.0f;
+            bool live = r >= 0.0f;
+            float z = 0.0f, vr = 0.0f, vt = 0.0f, vz = 0.0f, w = 0.0f;
+            if (live) {
+                z = A.p.z[p];
+                vr = A.p.vr[p]; vt = A.p.vt[p]; vz = A.p.vz[p];
+                w = A.p.w[p];
+            }
+            int i = 0, j = 0;
+            float fr = 0.0f, fz = 0.0f;
+            if (live) cell_of(I, r, z, i, j, fr, fz);
+            long long dst = p;
+            if (SCATTER) {
+                int dti = i / A.TR, dtj = j / A.TZ;
+                int dr = dti - ti_c, dz = dtj - tj_c;
+                bool near = win && dr >= -1 && dr <= 1 && dz >= -1 && dz <= 1;
+                int bkt = near ? (dr + 1) * 3 + (dz + 1) : -1;
+                int tile = I.tile_off + dti * I.ntz + dtj;
+                unsigned int rn = wave_aggregate<true>(live && near, bkt, [&](int k, unsigned int n) {
+                    return atomicAdd(&s_bcnt[k], n);
+                });
+                unsigned int rf = wave_aggregate<true>(live && !near, tile, [&](int k, unsigned int n) {
+                    return atomicAdd(&A.tile_fill[k], n);
+                });
+                if (live) dst = A.tile_start[tile] + (long long)(near ? s_bbase[bkt] + rn : rf);
+            }
+            bool alive = false;
+            int ni = 0, nj = 0;
+            if (live) {
+                ++c_push;
+                const bool inwin = win && i >= i0 && i + 1 <= i1 && j >= j0 && j + 1 <= j1;
+                float4 f00, f10, f01, f11;
+                if (inwin) {
+                    const int li = (i - i0) * ww + (j - j0);
+                    f00 = sEB[li]; f01 = sEB[li + 1]; f10 = sEB[li + ww]; f11 = sEB[li + ww + 1];
+                } else {
+                    const long long n00 = (long long)i * W + j;
+                    f00 = F.EB[n00]; f01 = F.EB[n00 + 1]; f10 = F.EB[n00 + W]; f11 = F.EB[n00 + W + 1];
+                }
+                const float gr = 1.0f - fr, gz = 1.0f - fz;
+                const float w00 = gr * gz, w10 = fr * gz, w01 = gr * fz, w11 = fr * fz;
+                const float er = fmaf(w11, f11.x, fmaf(w01, f01.x, fmaf(w10, f10.x, w00 * f00.x)));
+                const float ez = fmaf(w11, f11.y, fmaf(w01, f01.y, fmaf(w10, f10.y, w00 * f00.y)));
+                const float br = fmaf(w11, f11.z, fmaf(w01, f01.z, fmaf(w10, f10.z, w00 * f00.z)));
+                const float bz = fmaf(w11, f11.w, fmaf(w01, f01.w, fmaf(w10, f10.w, w00 * f00.w)));
+                // Boris
+                const float mr = fmaf(h, er, vr), mt = vt, mz = fmaf(h, ez, vz);
+                const float tr = h * br, tz = h * bz;
+                const float f = 2.0f * __builtin_amdgcn_rcpf(fmaf(tr, tr, fmaf(tz, tz, 1.0f)));
+                const float sr = f * tr, sz = f * tz;
+                const float pr = fmaf(mt, tz, mr);
+                const float pt = mt + fmaf(mz, tr, -(mr * tz));
+                const float pz = fmaf(-mt, tr, mz);
+                vr = fmaf(h, er, fmaf(pt, sz, mr));
+                vt = mt + fmaf(pz, sr, -(pr * sz));
+                vz = fmaf(h, ez, fmaf(-pt, sr, mz));
+                // move in the Cartesian frame, rotate back to (r, z)
+                const float x = fmaf(vr, dt, r), y = vt * dt;
+                const float zn = fmaf(vz, dt, z);
+                const float rr2 = fmaf(x, x, y * y);
+                const float inv = __builtin_amdgcn_rsqf(rr2);
+                const float rn = rr2 * inv;
+                int wall = -1;
+                if (rn <= I.a_f) wall = 0;
+                else if (rn >= I.b_f) wall = 1;
+                else if (zn <= 0.0f) wall = 2;
+                else if (zn >= I.L_f) wall = 3;
+                if (wall >= 0) {
+                    const unsigned long long Wq = (unsigned long long)(unsigned int)rintf(w * two_S);
+                    atomicAdd(&s_ctr[SC_ABS_N + wall], 1ull);
+                    atomicAdd(&s_ctr[SC_ABS_W + wall], Wq);
+                    atomicAdd(&s_ctr[SC_DEAD], 1ull);
+                    out.r[dst] = -1.0f;
+                } else {
+                    alive = true;
+                    const float cs = x * inv, sn = y * inv;
+                    const float vr2 = fmaf(cs, vr, sn * vt);
+                    vt = fmaf(cs, vt, -(sn * vr));
+                    vr = vr2;
+                    if (fmaf(vz, vz, fmaf(vt, vt, vr * vr)) > I.v_cap2_f) atomicAdd(&s_ctr[SC_CAP], 1ull);
+                    const unsigned long long key = A.p.key[p];
+                    if (I.collisions) {
+                        const uint4 b0 = philox_step(I, key, step, 0u);
+                        const unsigned long long x52 =
+                            ((((unsigned long long)b0.x) << 32) | (unsigned long long)b0.y) >> 12;
+                        if (x52 < I.null_k) {
+                            // rare: the candidate is resolved by k_collide after this kernel
+                            atomicAdd(&s_ctr[SC_CAND], 1ull);
+                            const long long qi = (long long)atomicAdd((unsigned long long*)&A.ctl[CTL_QCOUNT], 1ull);
+                            if (qi < A.qcap) A.queue[qi] = ((unsigned long long)inst << 40) | (unsigned long long)dst;
+                            else A.ctl[CTL_QOVER] = 1;
+                        }
+                    }
+                    out.r[dst] = rn;
+                    out.z[dst] = zn;
+                    out.vr[dst] = vr;
+                    out.vt[dst] = vt;
+                    out.vz[dst] = vz;
+                    if (SCATTER) {
+                        out.w[dst] = w;
+                        out.key[dst] = key;
+                    }
+                    // deposit at the new position
+                    float nfr, nfz;
+                    cell_of(I, rn, zn, ni, nj, nfr, nfz);
+                    long long q00, q10, q01, q11;
+                    node_charges(w, two_S, nfr, nfz, q00, q10, q01, q11);
+                    if (win && ni >= i0 && ni + 1 <= i1 && nj >= j0 && nj + 1 <= j1) {
+                        const int l = (ni - i0) * ww + (nj - j0);
+                        atomicAdd(&sQ[l], (unsigned long long)q00);
+                        atomicAdd(&sQ[l + ww], (unsigned long long)q10);
+                        atomicAdd(&sQ[l + 1], (unsigned long long)q01);
+                        atomicAdd(&sQ[l + ww + 1], (unsigned long long)q11);
+                    } else {
+                        unsigned long long* Qg = (unsigned long long*)F.Q;
+                        const long long n00 = (long long)ni * W + nj;
+                        atomicAdd(&Qg[n00], (unsigned long long)q00);
+                        atomicAdd(&Qg[n00 + W], (unsigned long long)q10);
+                        atomicAdd(&Qg[n00 + 1], (unsigned long long)q01);
+                        atomicAdd(&Qg[n00 + W + 1], (unsigned long long)q11);
+                    }
+                }
+            }
+            if (COUNT) {
+                // survivors and new electrons, by the tile of the new position
+                const int tile = I.tile_off + (ni / A.TR) * I.ntz + (nj / A.TZ);
+                wave_aggregate<false>(alive, tile, [&](int k, unsigned int n) {
+                    atomicAdd(&A.cnt_out[k], n);
+                    return 0u;
+                });
+            }
+        }
+        flush_counter(&cnt[C_PSTEPS], (unsigned long long)c_push);
+        __syncthreads();
+        if (tid < SC_N) {
+            const unsigned long long v = s_ctr[tid];
+            if (v) atomicAdd((unsigned long long*)&cnt[kCounterOf[tid]], v);
+        }
+        __syncthreads();
+        if (win) {
+            const int nwin = (i1 - i0 + 1) * ww;
+            unsigned long long* Qg = (unsigned long long*)F.Q;
+            for (int t = tid; t < nwin; t += kWG) {
+                unsigned long long v = sQ[t];
+                if (v != 0ull) {
+                    int a = t / ww, b = t - a * ww;
+                    atomicAdd(&Qg[(long long)(i0 + a) * W + (j0 + b)], v);
+                }
+            }
+        }
+    }
+}
+
+// Resolve the null-collision candidates queued by the particle kernel:
+// elastic or ionising event or null (FP32), the parent's new velocity, a new
+// electron appended after the instance's slots, deposited at the parent's
+// position and counted for the next sort.
+__global__ void __launch_bounds__(kWG) k_collide(KArgs A, PSet P, int scatter) {
+    const long long nq = min(A.ctl[CTL_QCOUNT], A.qcap);
+    for (long long qi = (long long)blockIdx.x * kWG + threadIdx.x; qi < nq; qi += (long long)gridDim.x * kWG) {
+        const unsigned long long e = A.queue[qi];
+        const int inst = (int)(e >> 40);
+        const long long p = (long long)(e & ((1ull << 40) - 1ull));
+        const DevInst& I = A.It[inst];
+        long long* cnt = A.cnt + (long long)inst * C_NCOUNT;
+        const unsigned int step = (unsigned int)cnt[C_STEP];
+        const unsigned long long key = P.key[p];
+        const uint4 b0 = philox_step(I, key, step, 0u);
+        float vr = P.vr[p], vt = P.vt[p], vz = P.vz[p];
+        const float r = P.r[p], z = P.z[p], w = P.w[p];
+        const long long base = scatter ? A.new_base[inst] : cnt[C_SLOTS];
+        const int ev = collide_f(I, cnt, P, key, step, b0, r, z, w, vr, vt, vz, base);
+        if (ev == 0) continue;
+        P.vr[p] = vr;
+        P.vt[p] = vt;
+        P.vz[p] = vz;
+        atomicAdd((unsigned long long*)&cnt[ev == 1 ? C_ELASTIC : C_IONIZ], 1ull);
+        if (ev != 2) continue;
+        int i, j;
+        float fr, fz;
+        cell_of(I, r, z, i, j, fr, fz);
+        long long q00, q10, q01, q11;
+        node_charges(w, (float)I.two_S, fr, fz, q00, q10, q01, q11);
+        unsigned long long* Qg = (unsigned long long*)A.Ft[inst].Q;
+        const long long n00 = (long long)i * I.W + j;
+        atomicAdd(&Qg[n00], (unsigned long long)q00);
+        atomicAdd(&Qg[n00 + I.W], (unsigned long long)q10);
+        atomicAdd(&Qg[n00 + 1], (unsigned long long)q01);
+        atomicAdd(&Qg[n00 + I.W + 1], (unsigned long long)q11);
+        if (A.cnt_out) atomicAdd(&A.cnt_out[I.tile_off + (i / A.TR) * I.ntz + (j / A.TZ)], 1u);
+    }
+}
+
+// Work plan for the tail (electrons created since the last sort): one item
+// per C of them per instance; resets the work cursor.
+__global__ void k_prep(long long* ctl, const long long* cnt, int n_inst, int C) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    long long* tb = ctl + CTL_TAIL;
+    tb[0] = 0;
+    ctl[CTL_QCOUNT] = 0;
+    for (int k = 0; k < n_inst; ++k) {
+        const long long* c = cnt + (long long)k * C_NCOUNT;
+        long long tail = c[C_SLOTS] - c[C_LIVE_SORTED];
+        long long nch = tail > 0 ? (tail + C - 1) / C : 0;
+        tb[k + 1] = tb[k] + nch;
+    }
+    ctl[CTL_TOTAL] = ctl[CTL_SORTED] + tb[n_inst];
+    ctl[CTL_CURSOR] = 0;
+}
+
+__global__ void k_zero_q(const DevInst* It, const FieldDev* Ft) {
+    const DevInst& I = It[blockIdx.y];
+    long long* Q = Ft[blockIdx.y].Q;
+    for (int n = blockIdx.x * blockDim.x + threadIdx.x; n < I.nodes; n += gridDim.x * blockDim.x) Q[n] = 0;
+}
+
+// ---- tile sort ------------------------------------------------------------
+
+__device__ __forceinline__ int tile_of(const DevInst& I, float r, float z, int TR, int TZ) {
+    int i, j;
+    float fr, fz;
+    cell_of(I, r, z, i, j, fr, fz);
+    return I.tile_off + (i / TR) * I.ntz + (j / TZ);
+}
+
+__global__ void __launch_bounds__(kWG) k_sort_count(KArgs A, unsigned long long* sortkey,
+                                                    unsigned int* tile_count) {
+    const int inst = blockIdx.y;
+    const DevInst& I = A.It[inst];
+    const long long slots = A.cnt[(long long)inst * C_NCOUNT + C_SLOTS];
+    const long long stride = (long long)gridDim.x * kWG;
+    const int lane = __lane_id();
+    for (long long b = (long long)blockIdx.x * kWG; b < slots; b += stride) {
+        long long q = b + threadIdx.x;
+        bool valid = false;
+        int tile = 0;
+        long long p = I.p_off + q;
+        if (q < slots) {
+            float r = A.p.r[p];
+            if (r >= 0.0f) {
+                valid = true;
+                tile = tile_of(I, r, A.p.z[p], A.TR, A.TZ);
+            }
+        }
+        unsigned long long active = __ballot(valid);
+        unsigned int rank = 0;
+        while (active) {
+            int leader = __ffsll((long long)active) - 1;
+            int t = __shfl(tile, leader);
+            unsigned long long m = __ballot(valid && tile == t) & active;
+            unsigned int base = 0;
+            if (lane == leader) base = atomicAdd(&tile_count[t], (unsigned int)__popcll(m));
+            base = __shfl(base, leader);
+            if ((m >> lane) & 1ull) rank = base + (unsigned int)__popcll(m & ((1ull << lane) - 1ull));
+            active &= ~m;
+        }
+        if (q < slots) sortkey[p] = valid ? ((((unsigned long long)tile) << 32) | rank) : ~0ull;
+    }
+}
+
+// Per instance: exclusive scans of tile counts (-> absolute first slot of each
+// tile in the destination store) and of per-tile work items.
+__global__ void __launch_bounds__(1024) k_sort_plan1(const DevInst* It, const unsigned int* tile_count,
+                                                     long long* tile_start, long long* tile_chunk,
+                                                     long long* inst_live, long long* inst_chunks, int C) {
+    __shared__ long long s_cnt[1024], s_chk[1024];
+    const DevInst& I = It[blockIdx.x];
+    const int nt = I.ntr * I.ntz, base = I.tile_off;
+    const int seg = (nt + 1023) / 1024;
+    const int t0 = threadIdx.x * seg, t1 = min(t0 + seg, nt);
+    long long sc = 0, sk = 0;
+    for (int t = t0; t < t1; ++t) {
+        long long c = tile_count[base + t];
+        sc += c;
+        sk += (c + C - 1) / C;
+    }
+    s_cnt[threadIdx.x] = sc;
+    s_chk[threadIdx.x] = sk;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        long long a = 0, b = 0;
+        for (int k = 0; k < 1024; ++k) {
+            long long x = s_cnt[k], y = s_chk[k];
+            s_cnt[k] = a; s_chk[k] = b;
+            a += x; b += y;
+        }
+        inst_live[blockIdx.x] = a;
+        inst_chunks[blockIdx.x] = b;
+    }
+    __syncthreads();
+    long long a = s_cnt[threadIdx.x], b = s_chk[threadIdx.x];
+    for (int t = t0; t < t1; ++t) {
+        long long c = tile_count[base + t];
+        tile_start[base + t] = I.p_off + a;
+        tile_chunk[base + t] = b;
+        a += c;
+        b += (c + C - 1) / C;
+    }
+}
+
+__global__ void k_sort_plan2(const long long* inst_chunks, long long* inst_chunk_off, long long* ctl,
+                             int n_inst) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    long long a = 0;
+    for (int k = 0; k < n_inst; ++k) {
+        inst_chunk_off[k] = a;
+        a += inst_chunks[k];
+    }
+    ctl[CTL_SORTED] = a;
+}
+
+__global__ void k_sort_plan3(const int4* tile_info, int n_tiles, const unsigned int* tile_count,
+                             const long long* tile_start, const long long* tile_chunk,
+                             const long long* inst_chunk_off, Chunk* chunks, int C, int TR, int TZ) {
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n_tiles) return;
+    int4 ti = tile_info[t];  // inst, tile row, tile col
+    long long c = tile_count[t];
+    long long o = inst_chunk_off[ti.x] + tile_chunk[t];
+    for (long long k = 0; k * C < c; ++k) {
+        Chunk ch;
+        ch.start = tile_start[t] + k * C;
+        ch.count = (int)min((long long)C, c - k * C);
+        ch.inst = ti.x;
+        ch.tr0 = ti.y * TR;
+        ch.tz0 = ti.z * TZ;
+        ch.pad0 = ch.pad1 = 0;
+        chunks[o + k] = ch;
+    }
+}
+
+__global__ void __launch_bounds__(kWG) k_sort_scatter(KArgs A, PSet dst, const unsigned long long* sortkey,
+                                                      const long long* tile_start) {
+    const int inst = blockIdx.y;
+    const DevInst& I = A.It[inst];
+    const long long slots = A.cnt[(long long)inst * C_NCOUNT + C_SLOTS];
+    for (long long q = (long long)blockIdx.x * kWG + threadIdx.x; q < slots; q += (long long)gridDim.x * kWG) {
+        long long p = I.p_off + q;
+        unsigned long long k = sortkey[p];
+        if (k == ~0ull) continue;
+        long long d = tile_start[k >> 32] + (long long)(k & 0xffffffffull);
+        dst.r[d] = A.p.r[p];
+        dst.z[d] = A.p.z[p];
+        dst.vr[d] = A.p.vr[p];
+        dst.vt[d] = A.p.vt[p];
+        dst.vz[d] = A.p.vz[p];
+        dst.w[d] = A.p.w[p];
+        dst.key[d] = A.p.key[p];
+    }
+}
+
+__global__ void k_sort_commit(long long* cnt, const long long* inst_live, int n_inst) {
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n_inst) return;
+    long long* c = cnt + (long long)k * C_NCOUNT;
+    c[C_SLOTS] = inst_live[k];
+    c[C_LIVE_SORTED] = inst_live[k];
+    c[C_DEAD] = 0;
+}
+
+// Scatter step: before the particle kernel the old holes are dropped from
+// the dead count; after it the sorted output becomes the slot range.
+__global__ void k_scatter_pre(long long* cnt, int n_inst) {
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n_inst) cnt[(long long)k * C_NCOUNT + C_DEAD] = 0;
+}
+
+__global__ void k_scatter_commit(long long* cnt, const long long* inst_live, int n_inst) {
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n_inst) return;
+    long long* c = cnt + (long long)k * C_NCOUNT;
+    c[C_SLOTS] = inst_live[k];
+    c[C_LIVE_SORTED] = inst_live[k];
+}
+
+__global__ void k_zero_u32(unsigned int* p, int n) {
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) p[t] = 0u;
+}
+
+// ---- load and standalone deposit ------------------------------------------
+
+__global__ void k_load32(DevInst I, double r_lo, double r_hi, double z_lo, double z_hi, double sv, float w0,
+                         int load_mode, PSet p, long long n) {
+    for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < n;
+         q += (long long)gridDim.x * blockDim.x) {
+        unsigned long long key = (unsigned long long)q;
+        uint4 b0 = philox_step(I, key, 0xFFFFFFFFu, 0u);
+        uint4 b1 = philox_step(I, key, 0xFFFFFFFFu, 1u);
+        uint4 b2 = philox_step(I, key, 0xFFFFFFFFu, 2u);
+        double ur = u52(b0.x, b0.y), uz = u52(b0.z, b0.w);
+        double r = load_mode == 1 ? r_lo + ur * (r_hi - r_lo)
+                                  : sqrt(r_lo * r_lo + ur * (r_hi * r_hi - r_lo * r_lo));
+        double z = z_lo + uz * (z_hi - z_lo);
+        double u1 = u52(b1.x, b1.y), u2 = u52(b1.z, b1.w);
+        double u3 = u52(b2.x, b2.y), u4 = u52(b2.z, b2.w);
+        double m1 = sqrt(-2.0 * log(u1)), m3 = sqrt(-2.0 * log(u3));
+        long long d = I.p_off + q;
+        p.r[d] = (float)r;
+        p.z[d] = (float)z;
+        p.vr[d] = (float)(sv * (m1 * cos((2.0 * kPi) * u2)));
+        p.vt[d] = (float)(sv * (m1 * sin((2.0 * kPi) * u2)));
+        p.vz[d] = (float)(sv * (m3 * cos((2.0 * kPi) * u4)));
+        p.w[d] = w0;
+        p.key[d] = key;
+    }
+}
+
+__global__ void k_deposit32(DevInst I, PSet P, long long* Q, const long long* cnt) {
+    const long long slots = cnt[C_SLOTS];
+    for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < slots;
+         q += (long long)gridDim.x * blockDim.x) {
+        long long p = I.p_off + q;
+        float r = P.r[p];
+        if (r < 0.0f) continue;
+        int i, j;
+        float fr, fz;
+        cell_of(I, r, P.z[p], i, j, fr, fz);
+        long long q00, q10, q01, q11;
+        node_charges(P.w[p], (float)I.two_S, fr, fz, q00, q10, q01, q11);
+        unsigned long long* Qg = (unsigned long long*)Q;
+        long long n00 = (long long)i * I.W + j;
+        atomicAdd(&Qg[n00], (unsigned long long)q00);
+        atomicAdd(&Qg[n00 + I.W], (unsigned long long)q10);
+        atomicAdd(&Qg[n00 + 1], (unsigned long long)q01);
+        atomicAdd(&Qg[n00 + I.W + 1], (unsigned long long)q11);
+    }
+}
+
+unsigned int grid_for(long long n, long long cap = 16384) {
+    long long g = (n + kWG - 1) / kWG;
+    return (unsigned int)std::max(1ll, std::min(g, cap));
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+
+struct F32State {
+    int TR = 16, TZ = 16, halo = 4, K = 8, C = 16384, win_max = 0;
+    int cu = 256, wg_per_cu = 4;
+    PSet set[2];
+    int cur = 0;
+    long long total_cap = 0;
+    unsigned long long* sortkey = nullptr;
+    unsigned int* tile_count = nullptr;
+    long long *tile_start = nullptr, *tile_chunk = nullptr;
+    long long *inst_live = nullptr, *inst_chunks = nullptr, *inst_chunk_off = nullptr;
+    int4* tile_info = nullptr;
+    int n_tiles = 0;
+    Chunk* chunks = nullptr;
+    long long max_chunks = 0;
+    long long* ctl = nullptr;
+    unsigned int* cbuf[2] = {nullptr, nullptr};  // per-tile totals counted for the next sort
+    unsigned int* tile_fill = nullptr;
+    unsigned long long* queue = nullptr;  // collision candidates of one step
+    long long qcap = 0;
+    FieldDev* dF = nullptr;  // field table (owned by the context)
+    hipStream_t gstream = nullptr;
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    hipGraphExec_t g_step[4][2] = {{nullptr, nullptr}, {nullptr, nullptr}, {nullptr, nullptr}, {nullptr, nullptr}};
+    hipGraphExec_t g_sort[2] = {nullptr, nullptr};
+    bool graphs = false;
+    int phase = 0;        // steps since the last sort
+    bool counted = false; // the last step counted tile totals for a scatter
+};
+
+static pic_status f32_fail(pic_ctx* ctx, pic_status st, const std::string& m) {
+    pic_set_error(ctx, m);
+    return st;
+}
+
+#define CK32(call)                                                                                   \
+    do {                                                                                             \
+        hipError_t e_ = (call);                                                                      \
+        if (e_ != hipSuccess)                                                                        \
+            return f32_fail(ctx, PIC_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_));   \
+    } while (0)
+
+static KArgs kargs(pic_ctx* ctx, F32State* S, int set) {
+    KArgs A;
+    A.It = pic_dev_table(ctx);
+    A.Ft = S->dF;
+    A.cnt = pic_counters(ctx);
+    A.p = S->set[set];
+    A.out = S->set[1 - set];
+    A.chunks = S->chunks;
+    A.ctl = S->ctl;
+    A.cnt_out = nullptr;
+    A.tile_fill = S->tile_fill;
+    A.tile_start = S->tile_start;
+    A.new_base = S->inst_live;
+    A.queue = S->queue;
+    A.qcap = S->qcap;
+    A.n_inst = pic_n_inst(ctx);
+    A.TR = S->TR;
+    A.TZ = S->TZ;
+    A.halo = S->halo;
+    A.C = S->C;
+    A.win_max = S->win_max;
+    return A;
+}
+
+static PSet alloc_set(pic_ctx* ctx, long long n) {
+    PSet p;
+    p.r = (float*)pic_dev_alloc(ctx, sizeof(float) * n);
+    p.z = (float*)pic_dev_alloc(ctx, sizeof(float) * n);
+    p.vr = (float*)pic_dev_alloc(ctx, sizeof(float) * n);
+    p.vt = (float*)pic_dev_alloc(ctx, sizeof(float) * n);
+    p.vz = (float*)pic_dev_alloc(ctx, sizeof(float) * n);
+    p.w = (float*)pic_dev_alloc(ctx, sizeof(float) * n);
+    p.key = (unsigned long long*)pic_dev_alloc(ctx, sizeof(unsigned long long) * n);
+    return p;
+}
+
+static bool set_ok(const PSet& p) { return p.r && p.z && p.vr && p.vt && p.vz && p.w && p.key; }
+
+pic_status f32_init(pic_ctx* ctx) {
+    F32State* S = new F32State();
+    pic_set_f32(ctx, S);
+    const pic_run_cfg& run = pic_run(ctx);
+    if (run.tile_r > 0) S->TR = run.tile_r;
+    if (run.tile_z > 0) S->TZ = run.tile_z;
+    if (run.halo > 0) S->halo = run.halo;
+    if (run.sort_interval > 0) S->K = run.sort_interval;
+    if (run.chunk > 0) S->C = run.chunk;
+    if (S->TR > 256 || S->TZ > 256 || S->halo > 32 || S->C > (1 << 24))
+        return f32_fail(ctx, PIC_EINVAL, "tile_r/tile_z <= 256, halo <= 32, chunk <= 2^24");
+    S->win_max = (S->TR + 2 * S->halo + 1) * (S->TZ + 2 * S->halo + 1);
+    if ((size_t)S->win_max * 24 > 64 * 1024) return f32_fail(ctx, PIC_EINVAL, "tile window exceeds 64 KiB of LDS");
+    int dev = run.device;
+    (void)hipDeviceGetAttribute(&S->cu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (S->cu <= 0) S->cu = 256;
+    const int n = pic_n_inst(ctx);
+    long long off = 0;
+    int toff = 0;
+    std::vector<int4> tinfo;
+    for (int k = 0; k < n; ++k) {
+        DevInst& I = pic_inst_dev(ctx, k);
+        I.p_off = off;
+        off += (I.p_cap + 63) / 64 * 64;
+        I.ntr = (I.nr + S->TR - 1) / S->TR;
+        I.ntz = (I.nz + S->TZ - 1) / S->TZ;
+        I.tile_off = toff;
+        for (int a = 0; a < I.ntr; ++a)
+            for (int b = 0; b < I.ntz; ++b) tinfo.push_back(make_int4(k, a, b, 0));
+        toff += I.ntr * I.ntz;
+        if (I.ntr * I.ntz > (1 << 22)) return f32_fail(ctx, PIC_EINVAL, "too many tiles");
+    }
+    S->total_cap = off;
+    S->n_tiles = toff;
+    S->set[0] = alloc_set(ctx, off);
+    S->set[1] = alloc_set(ctx, off);
+    if (!set_ok(S->set[0]) || !set_ok(S->set[1])) return f32_fail(ctx, PIC_ENOMEM, "FP32 particle stores");
+    S->sortkey = (unsigned long long*)pic_dev_alloc(ctx, sizeof(unsigned long long) * off);
+    S->tile_count = (unsigned int*)pic_dev_alloc(ctx, sizeof(unsigned int) * toff);
+    S->tile_start = (long long*)pic_dev_alloc(ctx, sizeof(long long) * toff);
+    S->tile_chunk = (long long*)pic_dev_alloc(ctx, sizeof(long long) * toff);
+    S->tile_info = (int4*)pic_dev_alloc(ctx, sizeof(int4) * toff);
+    S->inst_live = (long long*)pic_dev_alloc(ctx, sizeof(long long) * n);
+    S->inst_chunks = (long long*)pic_dev_alloc(ctx, sizeof(long long) * n);
+    S->inst_chunk_off = (long long*)pic_dev_alloc(ctx, sizeof(long long) * n);
+    S->max_chunks = toff + off / S->C + n + 16;
+    S->chunks = (Chunk*)pic_dev_alloc(ctx, sizeof(Chunk) * S->max_chunks);
+    S->ctl = (long long*)pic_dev_alloc(ctx, sizeof(long long) * (CTL_TAIL + n + 1));
+    S->cbuf[0] = (unsigned int*)pic_dev_alloc(ctx, sizeof(unsigned int) * toff);
+    S->cbuf[1] = (unsigned int*)pic_dev_alloc(ctx, sizeof(unsigned int) * toff);
+    S->tile_fill = (unsigned int*)pic_dev_alloc(ctx, sizeof(unsigned int) * toff);
+    if (!S->cbuf[0] || !S->cbuf[1] || !S->tile_fill) return f32_fail(ctx, PIC_ENOMEM, "FP32 sort counters");
+    // collision candidates per step are binomial(N, P_null): size the queue far
+    // above the mean (an overflow is reported, never ignored)
+    double pmax = 0.0;
+    for (int k = 0; k < n; ++k) pmax = std::max(pmax, pic_inst_dev(ctx, k).P_null);
+    S->qcap = std::min<long long>(off, std::max<long long>(1 << 16, (long long)(64.0 * pmax * (double)off)));
+    S->queue = (unsigned long long*)pic_dev_alloc(ctx, sizeof(unsigned long long) * S->qcap);
+    if (!S->queue) return f32_fail(ctx, PIC_ENOMEM, "FP32 collision queue");
+    if (!S->sortkey || !S->tile_count || !S->tile_start || !S->tile_chunk || !S->tile_info || !S->inst_live ||
+        !S->inst_chunks || !S->inst_chunk_off || !S->chunks || !S->ctl)
+        return f32_fail(ctx, PIC_ENOMEM, "FP32 sort buffers");
+    hipStream_t s = pic_stream(ctx);
+    CK32(hipMemcpyAsync(S->tile_info, tinfo.data(), sizeof(int4) * toff, hipMemcpyHostToDevice, s));
+    CK32(hipMemsetAsync(S->ctl, 0, sizeof(long long) * (CTL_TAIL + n + 1), s));
+    CK32(hipStreamSynchronize(s));
+    CK32(hipStreamCreateWithFlags(&S->gstream, hipStreamNonBlocking));
+    CK32(hipEventCreateWithFlags(&S->ev_in, hipEventDisableTiming));
+    CK32(hipEventCreateWithFlags(&S->ev_out, hipEventDisableTiming));
+    size_t lds = (size_t)S->win_max * (sizeof(float4) + sizeof(unsigned long long));
+    CK32(hipFuncSetAttribute((const void*)k_particles<0>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    CK32(hipFuncSetAttribute((const void*)k_particles<1>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    CK32(hipFuncSetAttribute((const void*)k_particles<2>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    CK32(hipFuncSetAttribute((const void*)k_particles<3>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    int occ = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_particles<0>, kWG, lds) == hipSuccess && occ > 0)
+        S->wg_per_cu = occ;
+    S->graphs = run.use_graph != 0;
+    S->dF = pic_field_table(ctx);
+    return PIC_OK;
+}
+
+static void drop_graphs(F32State* S) {
+    for (int k = 0; k < 2; ++k) {
+        for (int m = 0; m < 4; ++m) {
+            if (S->g_step[m][k]) (void)hipGraphExecDestroy(S->g_step[m][k]);
+            S->g_step[m][k] = nullptr;
+        }
+        if (S->g_sort[k]) (void)hipGraphExecDestroy(S->g_sort[k]);
+        S->g_sort[k] = nullptr;
+    }
+}
+
+void f32_destroy(pic_ctx* ctx) {
+    F32State* S = pic_get_f32(ctx);
+    if (!S) return;
+    drop_graphs(S);
+    if (S->gstream) {
+        (void)hipStreamSynchronize(S->gstream);
+        (void)hipStreamDestroy(S->gstream);
+    }
+    if (S->ev_in) (void)hipEventDestroy(S->ev_in);
+    if (S->ev_out) (void)hipEventDestroy(S->ev_out);
+    delete S;
+    pic_set_f32(ctx, nullptr);
+}
+
+static long long max_slots(pic_ctx* ctx) {
+    long long m = 0;
+    for (int k = 0; k < pic_n_inst(ctx); ++k) m = std::max(m, pic_inst_dev(ctx, k).p_cap);
+    return m;
+}
+
+// the launch sequences -------------------------------------------------------
+
+static pic_status launch_step(pic_ctx* ctx, F32State* S, hipStream_t s, bool timed, int mode) {
+    const int n = pic_n_inst(ctx);
+    KArgs A = kargs(ctx, S, S->cur);
+    long long max_nodes = 0;
+    for (int k = 0; k < n; ++k) max_nodes = std::max<long long>(max_nodes, pic_inst_dev(ctx, k).nodes);
+    hipLaunchKernelGGL(k_zero_q, dim3(grid_for(max_nodes, 1024), n), dim3(kWG), 0, s, A.It, A.Ft);
+    CK32(hipGetLastError());
+    hipLaunchKernelGGL(k_prep, dim3(1), dim3(64), 0, s, S->ctl, A.cnt, n, S->C);
+    CK32(hipGetLastError());
+    const unsigned int tgrid = (unsigned int)((S->n_tiles + 255) / 256);
+    if (mode & 2) {
+        hipLaunchKernelGGL(k_zero_u32, dim3(tgrid), dim3(256), 0, s, S->tile_fill, S->n_tiles);
+        CK32(hipGetLastError());
+        hipLaunchKernelGGL(k_sort_plan1, dim3(n), dim3(1024), 0, s, A.It, S->cbuf[S->cur], S->tile_start,
+                           S->tile_chunk, S->inst_live, S->inst_chunks, S->C);
+        CK32(hipGetLastError());
+        hipLaunchKernelGGL(k_scatter_pre, dim3((n + 63) / 64), dim3(64), 0, s, A.cnt, n);
+        CK32(hipGetLastError());
+    }
+    if (mode & 1) {
+        const int oset = (mode & 2) ? 1 - S->cur : S->cur;
+        A.cnt_out = S->cbuf[oset];
+        hipLaunchKernelGGL(k_zero_u32, dim3(tgrid), dim3(256), 0, s, A.cnt_out, S->n_tiles);
+        CK32(hipGetLastError());
+    }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (timed) {
+        e0 = pic_timing_begin(ctx, &e1);
+        if (!e0) return f32_fail(ctx, PIC_EDEVICE, "event pool");
+        CK32(hipEventRecord(e0, s));
+    }
+    const size_t lds = (size_t)S->win_max * (sizeof(float4) + sizeof(unsigned long long));
+    const dim3 grid(S->cu * S->wg_per_cu);
+    switch (mode) {
+        case 0: hipLaunchKernelGGL(k_particles<0>, grid, dim3(kWG), lds, s, A); break;
+        case 1: hipLaunchKernelGGL(k_particles<1>, grid, dim3(kWG), lds, s, A); break;
+        case 2: hipLaunchKernelGGL(k_particles<2>, grid, dim3(kWG), lds, s, A); break;
+        default: hipLaunchKernelGGL(k_particles<3>, grid, dim3(kWG), lds, s, A); break;
+    }
+    CK32(hipGetLastError());
+    if (timed) CK32(hipEventRecord(e1, s));
+    hipLaunchKernelGGL(k_collide, dim3(64), dim3(kWG), 0, s, A, (mode & 2) ? S->set[1 - S->cur] : S->set[S->cur],
+                       (mode & 2) ? 1 : 0);
+    CK32(hipGetLastError());
+    if (mode & 2) {
+        hipLaunchKernelGGL(k_sort_plan2, dim3(1), dim3(64), 0, s, S->inst_chunks, S->inst_chunk_off, S->ctl, n);
+        CK32(hipGetLastError());
+        hipLaunchKernelGGL(k_sort_plan3, dim3(tgrid), dim3(256), 0, s, S->tile_info, S->n_tiles, S->cbuf[S->cur],
+                           S->tile_start, S->tile_chunk, S->inst_chunk_off, S->chunks, S->C, S->TR, S->TZ);
+        CK32(hipGetLastError());
+        hipLaunchKernelGGL(k_scatter_commit, dim3((n + 63) / 64), dim3(64), 0, s, A.cnt, S->inst_live, n);
+        CK32(hipGetLastError());
+    }
+    return PIC_OK;
+}
+
+static pic_status launch_sort(pic_ctx* ctx, F32State* S, hipStream_t s) {
+    const int n = pic_n_inst(ctx);
+    KArgs A = kargs(ctx, S, S->cur);
+    hipLaunchKernelGGL(k_zero_u32, dim3((S->n_tiles + 255) / 256), dim3(256), 0, s, S->tile_count, S->n_tiles);
+    CK32(hipGetLastError());
+    unsigned int gx = grid_for(max_slots(ctx), 2048);
+    hipLaunchKernelGGL(k_sort_count, dim3(gx, n), dim3(kWG), 0, s, A, S->sortkey, S->tile_count);
+    CK32(hipGetLastError());
+    hipLaunchKernelGGL(k_sort_plan1, dim3(n), dim3(1024), 0, s, A.It, S->tile_count, S->tile_start,
+                       S->tile_chunk, S->inst_live, S->inst_chunks, S->C);
+    CK32(hipGetLastError());
+    hipLaunchKernelGGL(k_sort_plan2, dim3(1), dim3(64), 0, s, S->inst_chunks, S->inst_chunk_off, S->ctl, n);
+    CK32(hipGetLastError());
+    hipLaunchKernelGGL(k_sort_plan3, dim3((S->n_tiles + 255) / 256), dim3(256), 0, s, S->tile_info, S->n_tiles,
+                       S->tile_count, S->tile_start, S->tile_chunk, S->inst_chunk_off, S->chunks, S->C, S->TR,
+                       S->TZ);
+    CK32(hipGetLastError());
+    hipLaunchKernelGGL(k_sort_scatter, dim3(gx, n), dim3(kWG), 0, s, A, S->set[1 - S->cur], S->sortkey,
+                       S->tile_start);
+    CK32(hipGetLastError());
+    hipLaunchKernelGGL(k_sort_commit, dim3((n + 63) / 64), dim3(64), 0, s, A.cnt, S->inst_live, n);
+    CK32(hipGetLastError());
+    return PIC_OK;
+}
+
+static pic_status run_step_direct(pic_ctx* ctx, F32State* S, hipStream_t s, bool timed, int mode) {
+    pic_status st = launch_step(ctx, S, s, timed, mode);
+    if (st != PIC_OK) return st;
+    return pic_field_stage(ctx, s);
+}
+
+static pic_status run_sort_direct(pic_ctx* ctx, F32State* S, hipStream_t s) {
+    pic_status st = launch_sort(ctx, S, s);
+    if (st != PIC_OK) return st;
+    S->cur = 1 - S->cur;
+    S->phase = 0;
+    S->counted = false;
+    return PIC_OK;
+}
+
+static pic_status capture_step(pic_ctx* ctx, F32State* S, int mode, int cur) {
+    const int cur0 = S->cur;
+    S->cur = cur;
+    hipGraph_t g = nullptr;
+    CK32(hipStreamBeginCapture(S->gstream, hipStreamCaptureModeThreadLocal));
+    pic_status st = run_step_direct(ctx, S, S->gstream, false, mode);
+    hipError_t e = hipStreamEndCapture(S->gstream, &g);
+    S->cur = cur0;
+    if (st != PIC_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return st;
+    }
+    CK32(e);
+    e = hipGraphInstantiate(&S->g_step[mode][cur], g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    CK32(e);
+    return PIC_OK;
+}
+
+pic_status f32_sort_now(pic_ctx* ctx) {
+    F32State* S = pic_get_f32(ctx);
+    return run_sort_direct(ctx, S, pic_stream(ctx));
+}
+
+// Step kind from the sort schedule: every K steps a scatter (mode bit 2),
+// preceded by a step that counts the tile totals it needs (mode bit 1).
+static int next_mode(const F32State* S) {
+    if (S->K == 1) return S->counted ? 3 : 1;
+    if (S->phase >= S->K - 1) return S->counted ? 2 : 1;
+    if (S->phase == S->K - 2) return 1;
+    return 0;
+}
+
+pic_status f32_step(pic_ctx* ctx, int n_steps) {
+    F32State* S = pic_get_f32(ctx);
+    hipStream_t s = pic_stream(ctx);
+    const bool timed = pic_timing_on(ctx);
+    const bool use_graph = S->graphs && !timed;
+    bool waited = false;
+    for (int it = 0; it < n_steps; ++it) {
+        const int mode = next_mode(S);
+        if (use_graph) {
+            if (!S->g_step[mode][S->cur]) {
+                CK32(hipStreamSynchronize(s));
+                CK32(hipStreamSynchronize(S->gstream));
+                pic_status st = capture_step(ctx, S, mode, S->cur);
+                if (st != PIC_OK) return st;
+            }
+            if (!waited) {
+                CK32(hipEventRecord(S->ev_in, s));
+                CK32(hipStreamWaitEvent(S->gstream, S->ev_in, 0));
+                waited = true;
+            }
+            CK32(hipGraphLaunch(S->g_step[mode][S->cur], S->gstream));
+        } else {
+            pic_status st = run_step_direct(ctx, S, s, timed, mode);
+            if (st != PIC_OK) return st;
+        }
+        S->counted = (mode & 1) != 0;
+        if (mode & 2) {
+            S->cur = 1 - S->cur;
+            S->phase = 0;
+        } else {
+            S->phase += 1;
+        }
+    }
+    if (use_graph && waited) {
+        CK32(hipEventRecord(S->ev_out, S->gstream));
+        CK32(hipStreamWaitEvent(s, S->ev_out, 0));
+    }
+    return PIC_OK;
+}
+
+pic_status f32_load(pic_ctx* ctx, int k) {
+    F32State* S = pic_get_f32(ctx);
+    const pic_instance_cfg& c = pic_inst_cfg(ctx, k);
+    const DevInst& I = pic_inst_dev(ctx, k);
+    if (c.n_init <= 0) return PIC_OK;
+    double sv = sqrt((c.T_init_eV * kE) / kMe);
+    hipLaunchKernelGGL(k_load32, dim3(grid_for(c.n_init)), dim3(kWG), 0, pic_stream(ctx), I, c.r_lo, c.r_hi,
+                       c.z_lo, c.z_hi, sv, (float)c.weight, c.load_mode, S->set[S->cur], (long long)c.n_init);
+    CK32(hipGetLastError());
+    return PIC_OK;
+}
+
+pic_status f32_deposit_only(pic_ctx* ctx, int k) {
+    F32State* S = pic_get_f32(ctx);
+    const DevInst& I = pic_inst_dev(ctx, k);
+    hipLaunchKernelGGL(k_deposit32, dim3(grid_for(I.p_cap)), dim3(kWG), 0, pic_stream(ctx), I, S->set[S->cur],
+                       pic_inst_Q(ctx, k), pic_counters(ctx) + (long long)k * C_NCOUNT);
+    CK32(hipGetLastError());
+    return PIC_OK;
+}
+
+pic_status f32_set_particles(pic_ctx* ctx, int k, long long n, const double* r, const double* z,
+                             const double* vr, const double* vt, const double* vz, const double* w,
+                             const unsigned long long* key) {
+    F32State* S = pic_get_f32(ctx);
+    const DevInst& I = pic_inst_dev(ctx, k);
+    if (n <= 0) return PIC_OK;
+    std::vector<float> buf((size_t)n);
+    const double* src[6] = {r, z, vr, vt, vz, w};
+    float* dst[6] = {S->set[S->cur].r, S->set[S->cur].z, S->set[S->cur].vr,
+                     S->set[S->cur].vt, S->set[S->cur].vz, S->set[S->cur].w};
+    for (int a = 0; a < 6; ++a) {
+        for (long long q = 0; q < n; ++q) buf[q] = (float)src[a][q];
+        CK32(hipMemcpy(dst[a] + I.p_off, buf.data(), sizeof(float) * n, hipMemcpyHostToDevice));
+    }
+    CK32(hipMemcpy(S->set[S->cur].key + I.p_off, key, sizeof(unsigned long long) * n, hipMemcpyHostToDevice));
+    return PIC_OK;
+}
+
+pic_status f32_get_particles(pic_ctx* ctx, int k, double* r, double* z, double* vr, double* vt, double* vz,
+                             double* w, unsigned long long* key, long long cap, long long* n_out) {
+    F32State* S = pic_get_f32(ctx);
+    const DevInst& I = pic_inst_dev(ctx, k);
+    long long slots = 0;
+    CK32(hipMemcpy(&slots, pic_counters(ctx) + (long long)k * C_NCOUNT + C_SLOTS, sizeof(long long),
+                   hipMemcpyDeviceToHost));
+    std::vector<float> a[6];
+    const PSet& P = S->set[S->cur];
+    const float* src[6] = {P.r, P.z, P.vr, P.vt, P.vz, P.w};
+    for (int c = 0; c < 6; ++c) {
+        a[c].resize((size_t)std::max(slots, 1ll));
+        if (slots > 0)
+            CK32(hipMemcpy(a[c].data(), src[c] + I.p_off, sizeof(float) * slots, hipMemcpyDeviceToHost));
+    }
+    std::vector<unsigned long long> kk((size_t)std::max(slots, 1ll));
+    if (slots > 0)
+        CK32(hipMemcpy(kk.data(), P.key + I.p_off, sizeof(unsigned long long) * slots, hipMemcpyDeviceToHost));
+    double* out[6] = {r, z, vr, vt, vz, w};
+    long long m = 0;
+    for (long long q = 0; q < slots; ++q) {
+        if (a[0][q] < 0.0f) continue;
+        if (m < cap) {
+            for (int c = 0; c < 6; ++c)
+                if (out[c]) out[c][m] = (double)a[c][q];
+            if (key) key[m] = kk[q];
+        }
+        ++m;
+    }
+    if (n_out) *n_out = m;
+    if (m > cap) return f32_fail(ctx, PIC_EINVAL, "cap smaller than the live count");
+    return PIC_OK;
+}
+
+long long f32_live_count(pic_ctx*, int, const long long* c) { return c[C_SLOTS] - c[C_DEAD]; }
+
+pic_status f32_check(pic_ctx* ctx) {
+    F32State* S = pic_get_f32(ctx);
+    long long over = 0;
+    CK32(hipMemcpy(&over, S->ctl + CTL_QOVER, sizeof(long long), hipMemcpyDeviceToHost));
+    if (over) return f32_fail(ctx, PIC_ECAPACITY, "collision candidate queue overflowed");
+    return PIC_OK;
+}
+
+pic_status f32_tuning(pic_ctx* ctx, int* tile_r, int* tile_z, int* halo, int* sort_interval, int* chunk) {
+    F32State* S = pic_get_f32(ctx);
+    if (tile_r) *tile_r = S->TR;
+    if (tile_z) *tile_z = S->TZ;
+    if (halo) *halo = S->halo;
+    if (sort_interval) *sort_interval = S->K;
+    if (chunk) *chunk = S->C;
+    return PIC_OK;
+}

@@ -91,7 +91,10 @@ __global__ void __launch_bounds__(kFftBlock) kf_dst(const DevInst* __restrict__ 
 
 // Tridiagonal solve in r for every sine mode k (one thread per mode), with
 // the LU factors precomputed on the host: forward d_i = (b_i - lo_i d_{i-1})
-// im_i, backward x_i = d_i - cp_i x_{i+1}.
+// im_i, backward x_i = d_i - cp_i x_{i+1}.  Loads are issued in batches of
+// kTB rows ahead of the recurrence so their latencies overlap.
+constexpr int kTB = 16;
+
 __global__ void kf_thomas(const DevInst* __restrict__ It, const FieldDev* __restrict__ Ft,
                           int inst_base) {
     const int inst = inst_base + blockIdx.y;
@@ -99,18 +102,54 @@ __global__ void kf_thomas(const DevInst* __restrict__ It, const FieldDev* __rest
     const FieldDev& F = Ft[inst];
     const int k = 1 + blockIdx.x * blockDim.x + threadIdx.x;
     if (I.frozen || k > I.nz - 1) return;
-    const int W = I.W, nri = I.nr - 1;
+    const long long W = I.W;
+    const int nri = I.nr - 1;
+    double* __restrict__ rhs = F.rhs;
+    const double* __restrict__ lo = F.th_lo;
+    const double* __restrict__ im = F.th_im;
+    const double* __restrict__ cp = F.th_cp;
     double d = 0.0;
-    for (int i = 1; i <= nri; ++i) {
-        long long n = (long long)i * W + k;
-        d = (F.rhs[n] - F.th_lo[n] * d) * F.th_im[n];
-        F.rhs[n] = d;
+    int i = 1;
+    for (; i + kTB - 1 <= nri; i += kTB) {
+        double bb[kTB], ll[kTB], mm[kTB];
+#pragma unroll
+        for (int u = 0; u < kTB; ++u) {
+            const long long n = (long long)(i + u) * W + k;
+            bb[u] = rhs[n];
+            ll[u] = lo[n];
+            mm[u] = im[n];
+        }
+#pragma unroll
+        for (int u = 0; u < kTB; ++u) {
+            d = (bb[u] - ll[u] * d) * mm[u];
+            rhs[(long long)(i + u) * W + k] = d;
+        }
+    }
+    for (; i <= nri; ++i) {
+        const long long n = (long long)i * W + k;
+        d = (rhs[n] - lo[n] * d) * im[n];
+        rhs[n] = d;
     }
     double x = d;
-    for (int i = nri - 1; i >= 1; --i) {
-        long long n = (long long)i * W + k;
-        x = F.rhs[n] - F.th_cp[n] * x;
-        F.rhs[n] = x;
+    i = nri - 1;
+    for (; i - kTB + 1 >= 1; i -= kTB) {
+        double dd[kTB], cc[kTB];
+#pragma unroll
+        for (int u = 0; u < kTB; ++u) {
+            const long long n = (long long)(i - u) * W + k;
+            dd[u] = rhs[n];
+            cc[u] = cp[n];
+        }
+#pragma unroll
+        for (int u = 0; u < kTB; ++u) {
+            x = dd[u] - cc[u] * x;
+            rhs[(long long)(i - u) * W + k] = x;
+        }
+    }
+    for (; i >= 1; --i) {
+        const long long n = (long long)i * W + k;
+        x = rhs[n] - cp[n] * x;
+        rhs[n] = x;
     }
 }
 

@@ -80,10 +80,12 @@ __global__ void __launch_bounds__(kBlock) k_push64(DevInst I, P64 p, const doubl
                                                   const double* __restrict__ Bz, long long* cnt) {
     const long long n = cnt[C_SLOTS];
     const double h = I.h, dt = I.dt;
+    unsigned long long pushed = 0;
     for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < n;
          q += (long long)gridDim.x * blockDim.x) {
         double r = p.r[q];
         if (r < 0.0) continue;
+        ++pushed;
         double z = p.z[q], vr = p.vr[q], vt = p.vt[q], vz = p.vz[q];
         Shape sh = shape64(I, r, z);
         double er = gather64(sh, Er, I.W), ez = gather64(sh, Ez, I.W);
@@ -127,6 +129,7 @@ __global__ void __launch_bounds__(kBlock) k_push64(DevInst I, P64 p, const doubl
         p.vt[q] = cs * vt - sn * vr;
         p.vz[q] = vz;
     }
+    if (pushed) atomicAdd((unsigned long long*)&cnt[C_PSTEPS], pushed);
 }
 
 __device__ __forceinline__ double okh_cos(double xi, double u) {

@@ -70,6 +70,7 @@ enum Counter {
     C_NSAMP,
     C_OVERFLOW,              // fixed-point overflow flag
     C_LIVE_SORTED,           // live particles in the sorted region (FP32 form)
+    C_PSTEPS,                // particle-steps pushed so far
     C_NCOUNT = 40
 };
 
@@ -83,9 +84,10 @@ __device__ __forceinline__ uint4 philox4x32_10(uint4 c, unsigned int k0, unsigne
     const unsigned int W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
 #pragma unroll
     for (int round = 0; round < 10; ++round) {
-        unsigned int hi0 = __umulhi(M0, c.x), lo0 = M0 * c.x;
-        unsigned int hi1 = __umulhi(M1, c.z), lo1 = M1 * c.z;
-        c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
+        const unsigned long long p0 = (unsigned long long)M0 * c.x;
+        const unsigned long long p1 = (unsigned long long)M1 * c.z;
+        c = make_uint4((unsigned int)(p1 >> 32) ^ c.y ^ k0, (unsigned int)p1,
+                       (unsigned int)(p0 >> 32) ^ c.w ^ k1, (unsigned int)p0);
         k0 += W0;
         k1 += W1;
     }
