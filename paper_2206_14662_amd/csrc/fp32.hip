@@ -42,6 +42,26 @@ namespace {
 
 constexpr int kWG = 256;
 
+// LDS-qualified pointers: loads and atomics through them compile to ds_*
+// instructions even where a global fallback path sits next to them.
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) v4f lds_float4;
+typedef __attribute__((address_space(3))) unsigned long long lds_u64;
+
+__device__ __forceinline__ void lds_add(lds_u64* p, unsigned long long v) {
+    __atomic_fetch_add(p, v, __ATOMIC_RELAXED);
+}
+
+// Global-qualified views of device pointers read from tables.
+typedef __attribute__((address_space(1))) const v4f gbl_v4f;
+typedef __attribute__((address_space(1))) unsigned long long gbl_u64;
+
+__device__ __forceinline__ gbl_v4f* as_gbl(const float4* p) { return (gbl_v4f*)(const v4f*)p; }
+__device__ __forceinline__ gbl_u64* as_gbl(long long* p) { return (gbl_u64*)(unsigned long long*)p; }
+__device__ __forceinline__ void gbl_add(gbl_u64* p, unsigned long long v) {
+    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 struct PSet {
     float *r, *z, *vr, *vt, *vz, *w;
     unsigned long long* key;
@@ -86,6 +106,49 @@ __device__ __forceinline__ void cell_of(const DevInst& I, float r, float z, int&
     float si = floorf(s), tj = floorf(t);
     i = (int)si;
     j = (int)tj;
+    i = i < 0 ? 0 : (i > I.nr - 1 ? I.nr - 1 : i);
+    j = j < 0 ? 0 : (j > I.nz - 1 ? I.nz - 1 : j);
+    fr = s - (float)i;
+    fz = t - (float)j;
+}
+
+// Per-chunk copy of the instance constants the particle loop reads, kept in
+// registers so stores to the particle arrays never force them to be reloaded.
+struct LocalInst {
+    float a, b, L, inv_dr, inv_dz, h, dt, v_cap2, two_S;
+    int nr, nz, W, ntz, tile_off, collisions;
+    unsigned int seed_lo, seed_hi;
+    unsigned long long null_k;
+};
+
+__device__ __forceinline__ float uniform_f(float x) {
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x)));
+}
+
+__device__ __forceinline__ LocalInst local_inst(const DevInst& I) {
+    LocalInst L;
+    L.a = uniform_f(I.a_f); L.b = uniform_f(I.b_f); L.L = uniform_f(I.L_f);
+    L.inv_dr = uniform_f(I.inv_dr_f); L.inv_dz = uniform_f(I.inv_dz_f);
+    L.h = uniform_f(I.h_f); L.dt = uniform_f(I.dt_f); L.v_cap2 = uniform_f(I.v_cap2_f);
+    L.two_S = uniform_f((float)I.two_S);
+    L.nr = __builtin_amdgcn_readfirstlane(I.nr); L.nz = __builtin_amdgcn_readfirstlane(I.nz);
+    L.W = __builtin_amdgcn_readfirstlane(I.W); L.ntz = __builtin_amdgcn_readfirstlane(I.ntz);
+    L.tile_off = __builtin_amdgcn_readfirstlane(I.tile_off);
+    L.collisions = __builtin_amdgcn_readfirstlane(I.collisions);
+    L.seed_lo = __builtin_amdgcn_readfirstlane(I.seed_lo);
+    L.seed_hi = __builtin_amdgcn_readfirstlane(I.seed_hi);
+    const unsigned long long k = I.null_k;
+    L.null_k = ((unsigned long long)(unsigned int)__builtin_amdgcn_readfirstlane((int)(k >> 32)) << 32) |
+               (unsigned long long)(unsigned int)__builtin_amdgcn_readfirstlane((int)(unsigned int)k);
+    return L;
+}
+
+__device__ __forceinline__ void cell_of(const LocalInst& I, float r, float z, int& i, int& j, float& fr,
+                                        float& fz) {
+    float s = (r - I.a) * I.inv_dr;
+    float t = z * I.inv_dz;
+    i = (int)floorf(s);
+    j = (int)floorf(t);
     i = i < 0 ? 0 : (i > I.nr - 1 ? I.nr - 1 : i);
     j = j < 0 ? 0 : (j > I.nz - 1 ? I.nz - 1 : j);
     fr = s - (float)i;
@@ -255,8 +318,8 @@ __global__ void __launch_bounds__(kWG) k_particles(KArgs A) {
     constexpr bool COUNT = (MODE & 1) != 0;
     constexpr bool SCATTER = (MODE & 2) != 0;
     extern __shared__ __align__(16) unsigned char smem[];
-    float4* sEB = (float4*)smem;
-    unsigned long long* sQ = (unsigned long long*)(smem + sizeof(float4) * (size_t)A.win_max);
+    lds_float4* sEB = (lds_float4*)(v4f*)smem;
+    lds_u64* sQ = (lds_u64*)(unsigned long long*)(smem + sizeof(float4) * (size_t)A.win_max);
     __shared__ long long s_start;
     __shared__ int s_count, s_inst, s_tr0, s_tz0;
     __shared__ unsigned int s_bcnt[9], s_bbase[9];
@@ -314,20 +377,22 @@ __global__ void __launch_bounds__(kWG) k_particles(KArgs A) {
             const int nwin = (i1 - i0 + 1) * ww;
             for (int t = tid; t < nwin; t += kWG) {
                 int a = t / ww, b = t - a * ww;
-                sEB[t] = F.EB[(long long)(i0 + a) * W + (j0 + b)];
+                sEB[t] = as_gbl(F.EB)[(long long)(i0 + a) * W + (j0 + b)];
                 sQ[t] = 0ull;
             }
         }
         if (SCATTER && win) {
             // pass 1: destinations of this chunk's particles per neighbouring tile
+            const LocalInst L1 = local_inst(I);
             for (int base = 0; base < count; base += kWG) {
                 const int q = base + tid;
-                float r = q < count ? A.p.r[start + q] : -1.0f;
+                const long long p = start + (q < count ? q : 0);
+                const float r = A.p.r[p], z = A.p.z[p];
                 int bkt = -1;
-                if (r >= 0.0f) {
+                if (q < count && r >= 0.0f) {
                     int i, j;
                     float fr, fz;
-                    cell_of(I, r, A.p.z[start + q], i, j, fr, fz);
+                    cell_of(L1, r, z, i, j, fr, fz);
                     int dr = i / A.TR - ti_c, dz = j / A.TZ - tj_c;
                     if (dr >= -1 && dr <= 1 && dz >= -1 && dz <= 1) bkt = (dr + 1) * 3 + (dz + 1);
                 }
@@ -348,29 +413,29 @@ __global__ void __launch_bounds__(kWG) k_particles(KArgs A) {
         }
         __syncthreads();
         unsigned int c_push = 0;
-        const float h = I.h_f, dt = I.dt_f;
-        const float two_S = (float)I.two_S;
+        const LocalInst L = local_inst(I);
+        const float h = L.h, dt = L.dt, two_S = L.two_S;
         for (int base = 0; base < count; base += kWG) {
             const int q = base + tid;
-            const long long p = start + q;
-            float r = q < count ? A.p.r[p] : -1.0f;
-            bool live = r >= 0.0f;
-            float z = 0.0f, vr = 0.0f, vt = 0.0f, vz = 0.0f, w = 0.0f;
-            if (live) {
-                z = A.p.z[p];
-                vr = A.p.vr[p]; vt = A.p.vt[p]; vz = A.p.vz[p];
-                w = A.p.w[p];
-            }
+            const bool inr = q < count;
+            const long long p = start + (inr ? q : 0);
+            // every field is loaded at once (no dependence on the liveness test)
+            const float r = A.p.r[p];
+            const float z = A.p.z[p];
+            float vr = A.p.vr[p], vt = A.p.vt[p], vz = A.p.vz[p];
+            const float w = A.p.w[p];
+            const unsigned long long key = A.p.key[p];
+            const bool live = inr && r >= 0.0f;
             int i = 0, j = 0;
             float fr = 0.0f, fz = 0.0f;
-            if (live) cell_of(I, r, z, i, j, fr, fz);
+            cell_of(L, r, z, i, j, fr, fz);
             long long dst = p;
             if (SCATTER) {
                 int dti = i / A.TR, dtj = j / A.TZ;
                 int dr = dti - ti_c, dz = dtj - tj_c;
                 bool near = win && dr >= -1 && dr <= 1 && dz >= -1 && dz <= 1;
                 int bkt = near ? (dr + 1) * 3 + (dz + 1) : -1;
-                int tile = I.tile_off + dti * I.ntz + dtj;
+                int tile = L.tile_off + dti * L.ntz + dtj;
                 unsigned int rn = wave_aggregate<true>(live && near, bkt, [&](int k, unsigned int n) {
                     return atomicAdd(&s_bcnt[k], n);
                 });
@@ -384,13 +449,14 @@ __global__ void __launch_bounds__(kWG) k_particles(KArgs A) {
             if (live) {
                 ++c_push;
                 const bool inwin = win && i >= i0 && i + 1 <= i1 && j >= j0 && j + 1 <= j1;
-                float4 f00, f10, f01, f11;
+                v4f f00, f10, f01, f11;
                 if (inwin) {
                     const int li = (i - i0) * ww + (j - j0);
                     f00 = sEB[li]; f01 = sEB[li + 1]; f10 = sEB[li + ww]; f11 = sEB[li + ww + 1];
                 } else {
-                    const long long n00 = (long long)i * W + j;
-                    f00 = F.EB[n00]; f01 = F.EB[n00 + 1]; f10 = F.EB[n00 + W]; f11 = F.EB[n00 + W + 1];
+                    gbl_v4f* G = as_gbl(F.EB);
+                    const long long n00 = (long long)i * L.W + j;
+                    f00 = G[n00]; f01 = G[n00 + 1]; f10 = G[n00 + L.W]; f11 = G[n00 + L.W + 1];
                 }
                 const float gr = 1.0f - fr, gz = 1.0f - fz;
                 const float w00 = gr * gz, w10 = fr * gz, w01 = gr * fz, w11 = fr * fz;
@@ -416,10 +482,10 @@ __global__ void __launch_bounds__(kWG) k_particles(KArgs A) {
                 const float inv = __builtin_amdgcn_rsqf(rr2);
                 const float rn = rr2 * inv;
                 int wall = -1;
-                if (rn <= I.a_f) wall = 0;
-                else if (rn >= I.b_f) wall = 1;
+                if (rn <= L.a) wall = 0;
+                else if (rn >= L.b) wall = 1;
                 else if (zn <= 0.0f) wall = 2;
-                else if (zn >= I.L_f) wall = 3;
+                else if (zn >= L.L) wall = 3;
                 if (wall >= 0) {
                     const unsigned long long Wq = (unsigned long long)(unsigned int)rintf(w * two_S);
                     atomicAdd(&s_ctr[SC_ABS_N + wall], 1ull);
@@ -432,13 +498,13 @@ __global__ void __launch_bounds__(kWG) k_particles(KArgs A) {
                     const float vr2 = fmaf(cs, vr, sn * vt);
                     vt = fmaf(cs, vt, -(sn * vr));
                     vr = vr2;
-                    if (fmaf(vz, vz, fmaf(vt, vt, vr * vr)) > I.v_cap2_f) atomicAdd(&s_ctr[SC_CAP], 1ull);
-                    const unsigned long long key = A.p.key[p];
-                    if (I.collisions) {
-                        const uint4 b0 = philox_step(I, key, step, 0u);
+                    if (fmaf(vz, vz, fmaf(vt, vt, vr * vr)) > L.v_cap2) atomicAdd(&s_ctr[SC_CAP], 1ull);
+                    if (L.collisions) {
+                        const uint4 b0 = philox4x32_10(make_uint4((unsigned int)key, (unsigned int)(key >> 32),
+                                                                  step, 0u), L.seed_lo, L.seed_hi);
                         const unsigned long long x52 =
                             ((((unsigned long long)b0.x) << 32) | (unsigned long long)b0.y) >> 12;
-                        if (x52 < I.null_k) {
+                        if (x52 < L.null_k) {
                             // rare: the candidate is resolved by k_collide after this kernel
                             atomicAdd(&s_ctr[SC_CAND], 1ull);
                             const long long qi = (long long)atomicAdd((unsigned long long*)&A.ctl[CTL_QCOUNT], 1ull);
@@ -457,28 +523,28 @@ __global__ void __launch_bounds__(kWG) k_particles(KArgs A) {
                     }
                     // deposit at the new position
                     float nfr, nfz;
-                    cell_of(I, rn, zn, ni, nj, nfr, nfz);
+                    cell_of(L, rn, zn, ni, nj, nfr, nfz);
                     long long q00, q10, q01, q11;
                     node_charges(w, two_S, nfr, nfz, q00, q10, q01, q11);
                     if (win && ni >= i0 && ni + 1 <= i1 && nj >= j0 && nj + 1 <= j1) {
                         const int l = (ni - i0) * ww + (nj - j0);
-                        atomicAdd(&sQ[l], (unsigned long long)q00);
-                        atomicAdd(&sQ[l + ww], (unsigned long long)q10);
-                        atomicAdd(&sQ[l + 1], (unsigned long long)q01);
-                        atomicAdd(&sQ[l + ww + 1], (unsigned long long)q11);
+                        lds_add(&sQ[l], (unsigned long long)q00);
+                        lds_add(&sQ[l + ww], (unsigned long long)q10);
+                        lds_add(&sQ[l + 1], (unsigned long long)q01);
+                        lds_add(&sQ[l + ww + 1], (unsigned long long)q11);
                     } else {
-                        unsigned long long* Qg = (unsigned long long*)F.Q;
-                        const long long n00 = (long long)ni * W + nj;
-                        atomicAdd(&Qg[n00], (unsigned long long)q00);
-                        atomicAdd(&Qg[n00 + W], (unsigned long long)q10);
-                        atomicAdd(&Qg[n00 + 1], (unsigned long long)q01);
-                        atomicAdd(&Qg[n00 + W + 1], (unsigned long long)q11);
+                        gbl_u64* Qg = as_gbl(F.Q);
+                        const long long n00 = (long long)ni * L.W + nj;
+                        gbl_add(&Qg[n00], (unsigned long long)q00);
+                        gbl_add(&Qg[n00 + L.W], (unsigned long long)q10);
+                        gbl_add(&Qg[n00 + 1], (unsigned long long)q01);
+                        gbl_add(&Qg[n00 + L.W + 1], (unsigned long long)q11);
                     }
                 }
             }
             if (COUNT) {
-                // survivors and new electrons, by the tile of the new position
-                const int tile = I.tile_off + (ni / A.TR) * I.ntz + (nj / A.TZ);
+                // survivors, by the tile of the new position
+                const int tile = L.tile_off + (ni / A.TR) * L.ntz + (nj / A.TZ);
                 wave_aggregate<false>(alive, tile, [&](int k, unsigned int n) {
                     atomicAdd(&A.cnt_out[k], n);
                     return 0u;
@@ -494,12 +560,12 @@ __global__ void __launch_bounds__(kWG) k_particles(KArgs A) {
         __syncthreads();
         if (win) {
             const int nwin = (i1 - i0 + 1) * ww;
-            unsigned long long* Qg = (unsigned long long*)F.Q;
+            gbl_u64* Qg = as_gbl(F.Q);
             for (int t = tid; t < nwin; t += kWG) {
-                unsigned long long v = sQ[t];
+                const unsigned long long v = sQ[t];
                 if (v != 0ull) {
                     int a = t / ww, b = t - a * ww;
-                    atomicAdd(&Qg[(long long)(i0 + a) * W + (j0 + b)], v);
+                    gbl_add(&Qg[(long long)(i0 + a) * W + (j0 + b)], v);
                 }
             }
         }
