@@ -12,12 +12,13 @@
 //   -> commit
 // and every K steps the tile sort (count -> plan -> scatter -> commit).
 //
-// The particle kernel is persistent: each workgroup pulls work items
-// (a chunk of <= C particles of one tile, or of an instance's tail) from an
-// atomic cursor.  For a tile chunk it stages the tile's field window (tile
-// plus `halo` cells, float4 {Er, Ez, Br, Bz} per node) in LDS, accumulates the
-// chunk's charge in an LDS int64 window, then flushes non-zero window nodes
-// to the global grid with int64 atomics.  Integer sums do not depend on
+// The particle kernel is persistent and statically balanced: workgroup w
+// takes the w-th of gridDim.x equal ranges of the step's particles (the
+// tile-sorted ones of all instances, then their tails) and walks the tile
+// segments the range covers.  For a tile segment it stages the tile's field
+// window (tile plus `halo` cells, float4 {Er, Ez, Br, Bz} per node) in LDS,
+// accumulates the segment's charge in an LDS int64 window, then flushes
+// non-zero window nodes to the global grid with int64 atomics.  Integer sums do not depend on
 // order, so the deposited grid is the same for any schedule.  Per particle:
 // coalesced SoA loads, bilinear gather, Boris, cylindrical remap, absorbing
 // walls, one Philox4x32-10 block for the null-collision test (an integer
@@ -67,18 +68,11 @@ struct PSet {
     unsigned long long* key;
 };
 
-struct Chunk {
-    long long start;   // first slot (absolute)
-    int count;         // particles
-    int inst;
-    int tr0, tz0;      // first cell of the tile (r, z); tr0 < 0 for tail chunks
-    int pad0, pad1;
-};
 
-// control block: [0] cursor, [1] total work items, [2] tile chunks,
-// [3] collision candidates queued this step, [4] queue overflow flag,
-// [5 .. 5+n_inst] tail chunk prefix per instance
-enum { CTL_CURSOR = 0, CTL_TOTAL = 1, CTL_SORTED = 2, CTL_QCOUNT = 3, CTL_QOVER = 4, CTL_TAIL = 5 };
+// control block: [1] particles to push this step (sorted + tails), [2] sorted
+// particles over all instances, [3] collision candidates queued this step,
+// [4] queue overflow flag, [5 .. 5+n_inst] prefix of the instances' tail counts
+enum { CTL_TOTAL = 1, CTL_SORTED = 2, CTL_QCOUNT = 3, CTL_QOVER = 4, CTL_TAIL = 5 };
 
 struct KArgs {
     const DevInst* It;
@@ -86,15 +80,17 @@ struct KArgs {
     long long* cnt;
     PSet p;                        // input store
     PSet out;                      // output store of a scatter step
-    const Chunk* chunks;
+    const long long* vtile;        // prefix of sorted particles over all tiles (n_tiles + 1)
+    const int4* tile_info;         // instance, tile row, tile column
     long long* ctl;
     unsigned int* cnt_out;         // per-tile totals being counted (COUNT)
     unsigned int* tile_fill;       // per-tile ranks handed out (SCATTER)
-    const long long* tile_start;   // first slot of each tile in the output store
+    const long long* tile_start;   // first slot of each tile in the input store
+    const long long* tile_dst;     // first slot of each tile in the output store (SCATTER)
     const long long* new_base;     // per instance: slots of the sorted output
     unsigned long long* queue;     // collision candidates: (instance << 40) | slot
     long long qcap;
-    int n_inst, TR, TZ, halo, C, win_max;
+    int n_inst, n_tiles, TR, TZ, halo, C, win_max;
 };
 
 // ---- shared device helpers ------------------------------------------------
@@ -302,6 +298,180 @@ enum { SC_ABS_N = 0, SC_ABS_W = 4, SC_DEAD = 8, SC_CAND = 9, SC_CAP = 10, SC_N =
 __constant__ int kCounterOf[SC_N] = {C_ABS_N,     C_ABS_N + 1, C_ABS_N + 2, C_ABS_N + 3, C_ABS_W, C_ABS_W + 1,
                                      C_ABS_W + 2, C_ABS_W + 3, C_DEAD,      C_CAND,      C_CAPOVER};
 
+
+// Everything the particle loop needs about the current chunk.
+struct ChunkCtx {
+    LocalInst L;
+    lds_float4* sEB;
+    lds_u64* sQ;
+    unsigned long long* s_ctr;
+    unsigned int* s_bcnt;
+    const unsigned int* s_bbase;
+    PSet out;
+    const float4* EB;
+    long long* Q;
+    int inst, ti_c, tj_c, i0, i1, j0, j1, ww;
+    bool win;
+    unsigned int step;
+};
+
+// One particle: (optional) sort destination, gather, Boris, remap, walls,
+// null-collision test, store, deposit, (optional) destination-tile count.
+// Every lane of the wave calls it (collectives inside).
+template <bool COUNT, bool SCATTER>
+__device__ __forceinline__ void push_particle(const KArgs& A, const ChunkCtx& X, long long p, bool inr, float r,
+                                              float z, float vr, float vt, float vz, float w,
+                                              unsigned long long key, unsigned int& c_push) {
+    const LocalInst& L = X.L;
+    const float h = L.h, dt = L.dt;
+    const bool live = inr && r >= 0.0f;
+    // The arithmetic runs on every lane (cell indices are clamped, so every
+    // address stays inside the mesh); only side effects depend on `live`.
+    // Every loaded field thus has an unconditional use and the loads issue
+    // together instead of waiting on the liveness test.
+    int i, j;
+    float fr, fz;
+    cell_of(L, r, z, i, j, fr, fz);
+    long long dst = p;
+    if (SCATTER) {
+        const int dti = i / A.TR, dtj = j / A.TZ;
+        const int dr = dti - X.ti_c, dz = dtj - X.tj_c;
+        const bool near = X.win && dr >= -1 && dr <= 1 && dz >= -1 && dz <= 1;
+        const int bkt = near ? (dr + 1) * 3 + (dz + 1) : -1;
+        const int tile = L.tile_off + dti * L.ntz + dtj;
+        unsigned int* s_bcnt = X.s_bcnt;
+        const unsigned int rn = wave_aggregate<true>(live && near, bkt, [&](int k, unsigned int n) {
+            return atomicAdd(&s_bcnt[k], n);
+        });
+        const unsigned int rf = wave_aggregate<true>(live && !near, tile, [&](int k, unsigned int n) {
+            return atomicAdd(&A.tile_fill[k], n);
+        });
+        if (live) dst = A.tile_dst[tile] + (long long)(near ? X.s_bbase[bkt] + rn : rf);
+    }
+    // gather (LDS window when the cell is inside it)
+    const bool inwin = X.win && i >= X.i0 && i + 1 <= X.i1 && j >= X.j0 && j + 1 <= X.j1;
+    v4f f00, f10, f01, f11;
+    if (inwin) {
+        const int li = (i - X.i0) * X.ww + (j - X.j0);
+        f00 = X.sEB[li]; f01 = X.sEB[li + 1]; f10 = X.sEB[li + X.ww]; f11 = X.sEB[li + X.ww + 1];
+    } else {
+        gbl_v4f* G = as_gbl(X.EB);
+        const long long n00 = (long long)i * L.W + j;
+        f00 = G[n00]; f01 = G[n00 + 1]; f10 = G[n00 + L.W]; f11 = G[n00 + L.W + 1];
+    }
+    const float gr = 1.0f - fr, gz = 1.0f - fz;
+    const float w00 = gr * gz, w10 = fr * gz, w01 = gr * fz, w11 = fr * fz;
+    const float er = fmaf(w11, f11.x, fmaf(w01, f01.x, fmaf(w10, f10.x, w00 * f00.x)));
+    const float ez = fmaf(w11, f11.y, fmaf(w01, f01.y, fmaf(w10, f10.y, w00 * f00.y)));
+    const float br = fmaf(w11, f11.z, fmaf(w01, f01.z, fmaf(w10, f10.z, w00 * f00.z)));
+    const float bz = fmaf(w11, f11.w, fmaf(w01, f01.w, fmaf(w10, f10.w, w00 * f00.w)));
+    // Boris: half kick, rotation, half kick
+    const float mr = fmaf(h, er, vr), mt = vt, mz = fmaf(h, ez, vz);
+    const float tr = h * br, tz = h * bz;
+    const float f = 2.0f * __builtin_amdgcn_rcpf(fmaf(tr, tr, fmaf(tz, tz, 1.0f)));
+    const float sr = f * tr, sz = f * tz;
+    const float pr = fmaf(mt, tz, mr);
+    const float pt = mt + fmaf(mz, tr, -(mr * tz));
+    const float pz = fmaf(-mt, tr, mz);
+    vr = fmaf(h, er, fmaf(pt, sz, mr));
+    vt = mt + fmaf(pz, sr, -(pr * sz));
+    vz = fmaf(h, ez, fmaf(-pt, sr, mz));
+    // move in the Cartesian frame, rotate back to (r, z)
+    const float x = fmaf(vr, dt, r), y = vt * dt;
+    const float zn = fmaf(vz, dt, z);
+    const float rr2 = fmaf(x, x, y * y);
+    const float inv = __builtin_amdgcn_rsqf(rr2);
+    const float rn = rr2 * inv;
+    int wall = -1;
+    if (rn <= L.a) wall = 0;
+    else if (rn >= L.b) wall = 1;
+    else if (zn <= 0.0f) wall = 2;
+    else if (zn >= L.L) wall = 3;
+    const float cs = x * inv, sn = y * inv;
+    const float vrn = fmaf(cs, vr, sn * vt);
+    const float vtn = fmaf(cs, vt, -(sn * vr));
+    // null-collision test: one Philox block per particle-step
+    const uint4 b0 = philox4x32_10(make_uint4((unsigned int)key, (unsigned int)(key >> 32), X.step, 0u),
+                                   L.seed_lo, L.seed_hi);
+    const unsigned long long x52 = ((((unsigned long long)b0.x) << 32) | (unsigned long long)b0.y) >> 12;
+    const PSet out = X.out;
+    const bool alive = live && wall < 0;
+    if (live) {
+        ++c_push;
+        if (wall >= 0) {
+            const unsigned long long Wq = (unsigned long long)(unsigned int)rintf(w * L.two_S);
+            atomicAdd(&X.s_ctr[SC_ABS_N + wall], 1ull);
+            atomicAdd(&X.s_ctr[SC_ABS_W + wall], Wq);
+            atomicAdd(&X.s_ctr[SC_DEAD], 1ull);
+            out.r[dst] = -1.0f;
+        }
+    }
+    int ni = 0, nj = 0;
+    if (alive) {
+        if (fmaf(vz, vz, fmaf(vtn, vtn, vrn * vrn)) > L.v_cap2) atomicAdd(&X.s_ctr[SC_CAP], 1ull);
+        if (L.collisions && x52 < L.null_k) {
+            // rare: the candidate is resolved by k_collide after this kernel
+            atomicAdd(&X.s_ctr[SC_CAND], 1ull);
+            const long long qi = (long long)atomicAdd((unsigned long long*)&A.ctl[CTL_QCOUNT], 1ull);
+            if (qi < A.qcap) A.queue[qi] = ((unsigned long long)X.inst << 40) | (unsigned long long)dst;
+            else A.ctl[CTL_QOVER] = 1;
+        }
+        out.r[dst] = rn;
+        out.z[dst] = zn;
+        out.vr[dst] = vrn;
+        out.vt[dst] = vtn;
+        out.vz[dst] = vz;
+        if (SCATTER) {
+            out.w[dst] = w;
+            out.key[dst] = key;
+        }
+        // deposit at the new position
+        float nfr, nfz;
+        cell_of(L, rn, zn, ni, nj, nfr, nfz);
+        long long q00, q10, q01, q11;
+        node_charges(w, L.two_S, nfr, nfz, q00, q10, q01, q11);
+        if (X.win && ni >= X.i0 && ni + 1 <= X.i1 && nj >= X.j0 && nj + 1 <= X.j1) {
+            const int l = (ni - X.i0) * X.ww + (nj - X.j0);
+            lds_add(&X.sQ[l], (unsigned long long)q00);
+            lds_add(&X.sQ[l + X.ww], (unsigned long long)q10);
+            lds_add(&X.sQ[l + 1], (unsigned long long)q01);
+            lds_add(&X.sQ[l + X.ww + 1], (unsigned long long)q11);
+        } else {
+            gbl_u64* Qg = as_gbl(X.Q);
+            const long long n00 = (long long)ni * L.W + nj;
+            gbl_add(&Qg[n00], (unsigned long long)q00);
+            gbl_add(&Qg[n00 + L.W], (unsigned long long)q10);
+            gbl_add(&Qg[n00 + 1], (unsigned long long)q01);
+            gbl_add(&Qg[n00 + L.W + 1], (unsigned long long)q11);
+        }
+    }
+    if (COUNT) {
+        // survivors, by the tile of the new position
+        const int tile = L.tile_off + (ni / A.TR) * L.ntz + (nj / A.TZ);
+        wave_aggregate<false>(alive, tile, [&](int k, unsigned int n) {
+            atomicAdd(&A.cnt_out[k], n);
+            return 0u;
+        });
+    }
+}
+
+// Largest t in [0, n) with a[t] <= v for a nondecreasing a with a[0] <= v,
+// by one full wave: 64 probes per round narrow the range 64-fold.
+__device__ __forceinline__ int wave_search(const long long* a, int n, long long v) {
+    const int lane = __lane_id();
+    int lo = 0, hi = n;
+    while (hi - lo > 1) {
+        const int step = (hi - lo + 63) / 64;
+        const int idx = lo + lane * step;
+        const bool ok = idx < hi && a[idx] <= v;
+        const unsigned long long m = __ballot(ok);
+        const int last = 63 - __clzll((long long)m);
+        lo = lo + last * step;
+        hi = min(hi, lo + step);
+    }
+    return lo;
+}
+
 // ---- the particle kernel --------------------------------------------------
 //
 // MODE bit 1 (COUNT): after the push, count every survivor (and new
@@ -325,37 +495,46 @@ __global__ void __launch_bounds__(kWG) k_particles(KArgs A) {
     __shared__ unsigned int s_bcnt[9], s_bbase[9];
     __shared__ unsigned long long s_ctr[SC_N];
     const int tid = threadIdx.x;
-    for (;;) {
-        if (tid == 0) {
-            long long c = (long long)atomicAdd((unsigned long long*)&A.ctl[CTL_CURSOR], 1ull);
-            long long total = A.ctl[CTL_TOTAL], nsorted = A.ctl[CTL_SORTED];
-            if (c >= total) {
-                s_count = -1;
-            } else if (c < nsorted) {
-                Chunk ch = A.chunks[c];
-                s_start = ch.start; s_count = ch.count; s_inst = ch.inst; s_tr0 = ch.tr0; s_tz0 = ch.tz0;
-            } else {
-                long long t = c - nsorted;
-                const long long* tb = A.ctl + CTL_TAIL;
-                int lo = 0, hi = A.n_inst;  // tb[lo] <= t < tb[hi]
-                while (hi - lo > 1) {
-                    int mid = (lo + hi) >> 1;
-                    if (tb[mid] <= t) lo = mid; else hi = mid;
+    // Static balance: workgroup w pushes the w-th of gridDim.x equal ranges of
+    // the step's particles (tile-sorted ones first, then the tails), walking
+    // the tile segments its range covers.
+    const long long total = A.ctl[CTL_TOTAL], nsorted = A.ctl[CTL_SORTED];
+    const long long G = gridDim.x, wg = blockIdx.x;
+    const long long per = total / G, rmd = total % G;
+    long long v = wg * per + min(wg, rmd);
+    const long long vend = v + per + (wg < rmd ? 1 : 0);
+    while (v < vend) {
+        if (tid < 64) {
+            if (v < nsorted) {
+                const int t = wave_search(A.vtile, A.n_tiles, v);
+                if (tid == 0) {
+                    const long long tv = A.vtile[t], tv1 = A.vtile[t + 1];
+                    const int4 ti = A.tile_info[t];
+                    s_start = A.tile_start[t] + (v - tv);
+                    s_count = (int)min(min(vend, tv1) - v, (long long)A.C);
+                    s_inst = ti.x;
+                    s_tr0 = ti.y * A.TR;
+                    s_tz0 = ti.z * A.TZ;
                 }
-                const DevInst& J = A.It[lo];
-                const long long* cj = A.cnt + (long long)lo * C_NCOUNT;
-                long long first = cj[C_LIVE_SORTED] + (t - tb[lo]) * A.C;
-                long long end = cj[C_SLOTS];
-                s_start = J.p_off + first;
-                s_count = (int)min((long long)A.C, end - first);
-                s_inst = lo; s_tr0 = -1; s_tz0 = -1;
+            } else {
+                const long long u = v - nsorted;
+                const long long* tb = A.ctl + CTL_TAIL;
+                const int k = wave_search(tb, A.n_inst, u);
+                if (tid == 0) {
+                    const long long* cj = A.cnt + (long long)k * C_NCOUNT;
+                    s_start = A.It[k].p_off + cj[C_LIVE_SORTED] + (u - tb[k]);
+                    s_count = (int)min(min(vend - v, tb[k + 1] - u), (long long)A.C);
+                    s_inst = k;
+                    s_tr0 = -1;
+                    s_tz0 = -1;
+                }
             }
         }
         if (SCATTER && tid < 9) s_bcnt[tid] = 0u;
         if (tid < SC_N) s_ctr[tid] = 0ull;
         __syncthreads();
         const int count = __builtin_amdgcn_readfirstlane(s_count);
-        if (count < 0) break;
+        v += count;
         const long long start = s_start;
         const int inst = __builtin_amdgcn_readfirstlane(s_inst);
         const int tr0 = __builtin_amdgcn_readfirstlane(s_tr0), tz0 = __builtin_amdgcn_readfirstlane(s_tz0);
@@ -413,143 +592,37 @@ __global__ void __launch_bounds__(kWG) k_particles(KArgs A) {
         }
         __syncthreads();
         unsigned int c_push = 0;
-        const LocalInst L = local_inst(I);
-        const float h = L.h, dt = L.dt, two_S = L.two_S;
-        for (int base = 0; base < count; base += kWG) {
-            const int q = base + tid;
-            const bool inr = q < count;
-            const long long p = start + (inr ? q : 0);
-            // every field is loaded at once (no dependence on the liveness test)
-            const float r = A.p.r[p];
-            const float z = A.p.z[p];
-            float vr = A.p.vr[p], vt = A.p.vt[p], vz = A.p.vz[p];
-            const float w = A.p.w[p];
-            const unsigned long long key = A.p.key[p];
-            const bool live = inr && r >= 0.0f;
-            int i = 0, j = 0;
-            float fr = 0.0f, fz = 0.0f;
-            cell_of(L, r, z, i, j, fr, fz);
-            long long dst = p;
-            if (SCATTER) {
-                int dti = i / A.TR, dtj = j / A.TZ;
-                int dr = dti - ti_c, dz = dtj - tj_c;
-                bool near = win && dr >= -1 && dr <= 1 && dz >= -1 && dz <= 1;
-                int bkt = near ? (dr + 1) * 3 + (dz + 1) : -1;
-                int tile = L.tile_off + dti * L.ntz + dtj;
-                unsigned int rn = wave_aggregate<true>(live && near, bkt, [&](int k, unsigned int n) {
-                    return atomicAdd(&s_bcnt[k], n);
-                });
-                unsigned int rf = wave_aggregate<true>(live && !near, tile, [&](int k, unsigned int n) {
-                    return atomicAdd(&A.tile_fill[k], n);
-                });
-                if (live) dst = A.tile_start[tile] + (long long)(near ? s_bbase[bkt] + rn : rf);
+        ChunkCtx X;
+        X.L = local_inst(I);
+        X.sEB = sEB; X.sQ = sQ; X.s_ctr = s_ctr; X.s_bcnt = s_bcnt; X.s_bbase = s_bbase;
+        X.out = out; X.EB = F.EB; X.Q = F.Q;
+        X.inst = inst; X.ti_c = ti_c; X.tj_c = tj_c; X.i0 = i0; X.i1 = i1; X.j0 = j0; X.j1 = j1; X.ww = ww;
+        X.win = win; X.step = step;
+        // U particles per lane per pass (their loads are all in flight before
+        // any is processed); U = 1 measured fastest on gfx950 (occupancy wins)
+        constexpr int U = 1;
+        for (int base = 0; base < count; base += U * kWG) {
+            long long pp[U];
+            bool inr[U];
+            float r[U], z[U], vr[U], vt[U], vz[U], w[U];
+            unsigned long long key[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int q = base + u * kWG + tid;
+                inr[u] = q < count;
+                pp[u] = start + (inr[u] ? q : 0);
+                r[u] = A.p.r[pp[u]];
+                z[u] = A.p.z[pp[u]];
+                vr[u] = A.p.vr[pp[u]];
+                vt[u] = A.p.vt[pp[u]];
+                vz[u] = A.p.vz[pp[u]];
+                w[u] = A.p.w[pp[u]];
+                key[u] = A.p.key[pp[u]];
             }
-            bool alive = false;
-            int ni = 0, nj = 0;
-            if (live) {
-                ++c_push;
-                const bool inwin = win && i >= i0 && i + 1 <= i1 && j >= j0 && j + 1 <= j1;
-                v4f f00, f10, f01, f11;
-                if (inwin) {
-                    const int li = (i - i0) * ww + (j - j0);
-                    f00 = sEB[li]; f01 = sEB[li + 1]; f10 = sEB[li + ww]; f11 = sEB[li + ww + 1];
-                } else {
-                    gbl_v4f* G = as_gbl(F.EB);
-                    const long long n00 = (long long)i * L.W + j;
-                    f00 = G[n00]; f01 = G[n00 + 1]; f10 = G[n00 + L.W]; f11 = G[n00 + L.W + 1];
-                }
-                const float gr = 1.0f - fr, gz = 1.0f - fz;
-                const float w00 = gr * gz, w10 = fr * gz, w01 = gr * fz, w11 = fr * fz;
-                const float er = fmaf(w11, f11.x, fmaf(w01, f01.x, fmaf(w10, f10.x, w00 * f00.x)));
-                const float ez = fmaf(w11, f11.y, fmaf(w01, f01.y, fmaf(w10, f10.y, w00 * f00.y)));
-                const float br = fmaf(w11, f11.z, fmaf(w01, f01.z, fmaf(w10, f10.z, w00 * f00.z)));
-                const float bz = fmaf(w11, f11.w, fmaf(w01, f01.w, fmaf(w10, f10.w, w00 * f00.w)));
-                // Boris
-                const float mr = fmaf(h, er, vr), mt = vt, mz = fmaf(h, ez, vz);
-                const float tr = h * br, tz = h * bz;
-                const float f = 2.0f * __builtin_amdgcn_rcpf(fmaf(tr, tr, fmaf(tz, tz, 1.0f)));
-                const float sr = f * tr, sz = f * tz;
-                const float pr = fmaf(mt, tz, mr);
-                const float pt = mt + fmaf(mz, tr, -(mr * tz));
-                const float pz = fmaf(-mt, tr, mz);
-                vr = fmaf(h, er, fmaf(pt, sz, mr));
-                vt = mt + fmaf(pz, sr, -(pr * sz));
-                vz = fmaf(h, ez, fmaf(-pt, sr, mz));
-                // move in the Cartesian frame, rotate back to (r, z)
-                const float x = fmaf(vr, dt, r), y = vt * dt;
-                const float zn = fmaf(vz, dt, z);
-                const float rr2 = fmaf(x, x, y * y);
-                const float inv = __builtin_amdgcn_rsqf(rr2);
-                const float rn = rr2 * inv;
-                int wall = -1;
-                if (rn <= L.a) wall = 0;
-                else if (rn >= L.b) wall = 1;
-                else if (zn <= 0.0f) wall = 2;
-                else if (zn >= L.L) wall = 3;
-                if (wall >= 0) {
-                    const unsigned long long Wq = (unsigned long long)(unsigned int)rintf(w * two_S);
-                    atomicAdd(&s_ctr[SC_ABS_N + wall], 1ull);
-                    atomicAdd(&s_ctr[SC_ABS_W + wall], Wq);
-                    atomicAdd(&s_ctr[SC_DEAD], 1ull);
-                    out.r[dst] = -1.0f;
-                } else {
-                    alive = true;
-                    const float cs = x * inv, sn = y * inv;
-                    const float vr2 = fmaf(cs, vr, sn * vt);
-                    vt = fmaf(cs, vt, -(sn * vr));
-                    vr = vr2;
-                    if (fmaf(vz, vz, fmaf(vt, vt, vr * vr)) > L.v_cap2) atomicAdd(&s_ctr[SC_CAP], 1ull);
-                    if (L.collisions) {
-                        const uint4 b0 = philox4x32_10(make_uint4((unsigned int)key, (unsigned int)(key >> 32),
-                                                                  step, 0u), L.seed_lo, L.seed_hi);
-                        const unsigned long long x52 =
-                            ((((unsigned long long)b0.x) << 32) | (unsigned long long)b0.y) >> 12;
-                        if (x52 < L.null_k) {
-                            // rare: the candidate is resolved by k_collide after this kernel
-                            atomicAdd(&s_ctr[SC_CAND], 1ull);
-                            const long long qi = (long long)atomicAdd((unsigned long long*)&A.ctl[CTL_QCOUNT], 1ull);
-                            if (qi < A.qcap) A.queue[qi] = ((unsigned long long)inst << 40) | (unsigned long long)dst;
-                            else A.ctl[CTL_QOVER] = 1;
-                        }
-                    }
-                    out.r[dst] = rn;
-                    out.z[dst] = zn;
-                    out.vr[dst] = vr;
-                    out.vt[dst] = vt;
-                    out.vz[dst] = vz;
-                    if (SCATTER) {
-                        out.w[dst] = w;
-                        out.key[dst] = key;
-                    }
-                    // deposit at the new position
-                    float nfr, nfz;
-                    cell_of(L, rn, zn, ni, nj, nfr, nfz);
-                    long long q00, q10, q01, q11;
-                    node_charges(w, two_S, nfr, nfz, q00, q10, q01, q11);
-                    if (win && ni >= i0 && ni + 1 <= i1 && nj >= j0 && nj + 1 <= j1) {
-                        const int l = (ni - i0) * ww + (nj - j0);
-                        lds_add(&sQ[l], (unsigned long long)q00);
-                        lds_add(&sQ[l + ww], (unsigned long long)q10);
-                        lds_add(&sQ[l + 1], (unsigned long long)q01);
-                        lds_add(&sQ[l + ww + 1], (unsigned long long)q11);
-                    } else {
-                        gbl_u64* Qg = as_gbl(F.Q);
-                        const long long n00 = (long long)ni * L.W + nj;
-                        gbl_add(&Qg[n00], (unsigned long long)q00);
-                        gbl_add(&Qg[n00 + L.W], (unsigned long long)q10);
-                        gbl_add(&Qg[n00 + 1], (unsigned long long)q01);
-                        gbl_add(&Qg[n00 + L.W + 1], (unsigned long long)q11);
-                    }
-                }
-            }
-            if (COUNT) {
-                // survivors, by the tile of the new position
-                const int tile = L.tile_off + (ni / A.TR) * L.ntz + (nj / A.TZ);
-                wave_aggregate<false>(alive, tile, [&](int k, unsigned int n) {
-                    atomicAdd(&A.cnt_out[k], n);
-                    return 0u;
-                });
-            }
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                push_particle<COUNT, SCATTER>(A, X, pp[u], inr[u], r[u], z[u], vr[u], vt[u], vz[u], w[u], key[u],
+                                              c_push);
         }
         flush_counter(&cnt[C_PSTEPS], (unsigned long long)c_push);
         __syncthreads();
@@ -614,19 +687,19 @@ __global__ void __launch_bounds__(kWG) k_collide(KArgs A, PSet P, int scatter) {
 
 // Work plan for the tail (electrons created since the last sort): one item
 // per C of them per instance; resets the work cursor.
-__global__ void k_prep(long long* ctl, const long long* cnt, int n_inst, int C) {
+// Tail counts (electrons created since the last sort) per instance and the
+// step's total; resets the collision-candidate queue.
+__global__ void k_prep(long long* ctl, const long long* cnt, int n_inst) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     long long* tb = ctl + CTL_TAIL;
     tb[0] = 0;
     ctl[CTL_QCOUNT] = 0;
     for (int k = 0; k < n_inst; ++k) {
         const long long* c = cnt + (long long)k * C_NCOUNT;
-        long long tail = c[C_SLOTS] - c[C_LIVE_SORTED];
-        long long nch = tail > 0 ? (tail + C - 1) / C : 0;
-        tb[k + 1] = tb[k] + nch;
+        const long long tail = c[C_SLOTS] - c[C_LIVE_SORTED];
+        tb[k + 1] = tb[k] + (tail > 0 ? tail : 0);
     }
     ctl[CTL_TOTAL] = ctl[CTL_SORTED] + tb[n_inst];
-    ctl[CTL_CURSOR] = 0;
 }
 
 __global__ void k_zero_q(const DevInst* It, const FieldDev* Ft) {
@@ -679,75 +752,58 @@ __global__ void __launch_bounds__(kWG) k_sort_count(KArgs A, unsigned long long*
     }
 }
 
-// Per instance: exclusive scans of tile counts (-> absolute first slot of each
-// tile in the destination store) and of per-tile work items.
+// Per instance: exclusive scan of the tile totals -> each tile's first slot
+// in the destination store (absolute) and its offset among the instance's
+// sorted particles; the instance's sorted total.
 __global__ void __launch_bounds__(1024) k_sort_plan1(const DevInst* It, const unsigned int* tile_count,
-                                                     long long* tile_start, long long* tile_chunk,
-                                                     long long* inst_live, long long* inst_chunks, int C) {
-    __shared__ long long s_cnt[1024], s_chk[1024];
+                                                     long long* tile_start, long long* tile_lpre,
+                                                     long long* inst_live) {
+    __shared__ long long s_cnt[1024];
     const DevInst& I = It[blockIdx.x];
     const int nt = I.ntr * I.ntz, base = I.tile_off;
     const int seg = (nt + 1023) / 1024;
     const int t0 = threadIdx.x * seg, t1 = min(t0 + seg, nt);
-    long long sc = 0, sk = 0;
-    for (int t = t0; t < t1; ++t) {
-        long long c = tile_count[base + t];
-        sc += c;
-        sk += (c + C - 1) / C;
-    }
+    long long sc = 0;
+    for (int t = t0; t < t1; ++t) sc += tile_count[base + t];
     s_cnt[threadIdx.x] = sc;
-    s_chk[threadIdx.x] = sk;
     __syncthreads();
     if (threadIdx.x == 0) {
-        long long a = 0, b = 0;
+        long long a = 0;
         for (int k = 0; k < 1024; ++k) {
-            long long x = s_cnt[k], y = s_chk[k];
-            s_cnt[k] = a; s_chk[k] = b;
-            a += x; b += y;
+            long long x = s_cnt[k];
+            s_cnt[k] = a;
+            a += x;
         }
         inst_live[blockIdx.x] = a;
-        inst_chunks[blockIdx.x] = b;
     }
     __syncthreads();
-    long long a = s_cnt[threadIdx.x], b = s_chk[threadIdx.x];
+    long long a = s_cnt[threadIdx.x];
     for (int t = t0; t < t1; ++t) {
-        long long c = tile_count[base + t];
         tile_start[base + t] = I.p_off + a;
-        tile_chunk[base + t] = b;
-        a += c;
-        b += (c + C - 1) / C;
+        tile_lpre[base + t] = a;
+        a += tile_count[base + t];
     }
 }
 
-__global__ void k_sort_plan2(const long long* inst_chunks, long long* inst_chunk_off, long long* ctl,
-                             int n_inst) {
+// Instances' offsets in the step's particle order; total sorted particles.
+__global__ void k_sort_plan2(const long long* inst_live, long long* inst_voff, long long* ctl, long long* vtile,
+                             int n_inst, int n_tiles) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     long long a = 0;
     for (int k = 0; k < n_inst; ++k) {
-        inst_chunk_off[k] = a;
-        a += inst_chunks[k];
+        inst_voff[k] = a;
+        a += inst_live[k];
     }
     ctl[CTL_SORTED] = a;
+    vtile[n_tiles] = a;
 }
 
-__global__ void k_sort_plan3(const int4* tile_info, int n_tiles, const unsigned int* tile_count,
-                             const long long* tile_start, const long long* tile_chunk,
-                             const long long* inst_chunk_off, Chunk* chunks, int C, int TR, int TZ) {
+// Global prefix of sorted particles over all tiles.
+__global__ void k_sort_plan3(const int4* tile_info, int n_tiles, const long long* tile_lpre,
+                             const long long* inst_voff, long long* vtile) {
     int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n_tiles) return;
-    int4 ti = tile_info[t];  // inst, tile row, tile col
-    long long c = tile_count[t];
-    long long o = inst_chunk_off[ti.x] + tile_chunk[t];
-    for (long long k = 0; k * C < c; ++k) {
-        Chunk ch;
-        ch.start = tile_start[t] + k * C;
-        ch.count = (int)min((long long)C, c - k * C);
-        ch.inst = ti.x;
-        ch.tr0 = ti.y * TR;
-        ch.tz0 = ti.z * TZ;
-        ch.pad0 = ch.pad1 = 0;
-        chunks[o + k] = ch;
-    }
+    vtile[t] = inst_voff[tile_info[t].x] + tile_lpre[t];
 }
 
 __global__ void __launch_bounds__(kWG) k_sort_scatter(KArgs A, PSet dst, const unsigned long long* sortkey,
@@ -860,19 +916,18 @@ unsigned int grid_for(long long n, long long cap = 16384) {
 // ---------------------------------------------------------------------------
 
 struct F32State {
-    int TR = 16, TZ = 16, halo = 4, K = 8, C = 16384, win_max = 0;
+    int TR = 16, TZ = 16, halo = 4, K = 8, C = 1 << 22, win_max = 0;
     int cu = 256, wg_per_cu = 4;
     PSet set[2];
     int cur = 0;
     long long total_cap = 0;
     unsigned long long* sortkey = nullptr;
     unsigned int* tile_count = nullptr;
-    long long *tile_start = nullptr, *tile_chunk = nullptr;
-    long long *inst_live = nullptr, *inst_chunks = nullptr, *inst_chunk_off = nullptr;
+    long long* tstart[2] = {nullptr, nullptr};  // tile starts of the layout held in set[k]
+    long long *tile_lpre = nullptr, *vtile = nullptr;
+    long long *inst_live = nullptr, *inst_voff = nullptr;
     int4* tile_info = nullptr;
     int n_tiles = 0;
-    Chunk* chunks = nullptr;
-    long long max_chunks = 0;
     long long* ctl = nullptr;
     unsigned int* cbuf[2] = {nullptr, nullptr};  // per-tile totals counted for the next sort
     unsigned int* tile_fill = nullptr;
@@ -907,15 +962,18 @@ static KArgs kargs(pic_ctx* ctx, F32State* S, int set) {
     A.cnt = pic_counters(ctx);
     A.p = S->set[set];
     A.out = S->set[1 - set];
-    A.chunks = S->chunks;
+    A.vtile = S->vtile;
+    A.tile_info = S->tile_info;
     A.ctl = S->ctl;
     A.cnt_out = nullptr;
     A.tile_fill = S->tile_fill;
-    A.tile_start = S->tile_start;
+    A.tile_start = S->tstart[set];
+    A.tile_dst = S->tstart[1 - set];
     A.new_base = S->inst_live;
     A.queue = S->queue;
     A.qcap = S->qcap;
     A.n_inst = pic_n_inst(ctx);
+    A.n_tiles = S->n_tiles;
     A.TR = S->TR;
     A.TZ = S->TZ;
     A.halo = S->halo;
@@ -947,8 +1005,8 @@ pic_status f32_init(pic_ctx* ctx) {
     if (run.halo > 0) S->halo = run.halo;
     if (run.sort_interval > 0) S->K = run.sort_interval;
     if (run.chunk > 0) S->C = run.chunk;
-    if (S->TR > 256 || S->TZ > 256 || S->halo > 32 || S->C > (1 << 24))
-        return f32_fail(ctx, PIC_EINVAL, "tile_r/tile_z <= 256, halo <= 32, chunk <= 2^24");
+    if (S->TR > 256 || S->TZ > 256 || S->halo > 32 || S->C > (1 << 30))
+        return f32_fail(ctx, PIC_EINVAL, "tile_r/tile_z <= 256, halo <= 32, chunk <= 2^30");
     S->win_max = (S->TR + 2 * S->halo + 1) * (S->TZ + 2 * S->halo + 1);
     if ((size_t)S->win_max * 24 > 64 * 1024) return f32_fail(ctx, PIC_EINVAL, "tile window exceeds 64 KiB of LDS");
     int dev = run.device;
@@ -977,14 +1035,13 @@ pic_status f32_init(pic_ctx* ctx) {
     if (!set_ok(S->set[0]) || !set_ok(S->set[1])) return f32_fail(ctx, PIC_ENOMEM, "FP32 particle stores");
     S->sortkey = (unsigned long long*)pic_dev_alloc(ctx, sizeof(unsigned long long) * off);
     S->tile_count = (unsigned int*)pic_dev_alloc(ctx, sizeof(unsigned int) * toff);
-    S->tile_start = (long long*)pic_dev_alloc(ctx, sizeof(long long) * toff);
-    S->tile_chunk = (long long*)pic_dev_alloc(ctx, sizeof(long long) * toff);
+    S->tstart[0] = (long long*)pic_dev_alloc(ctx, sizeof(long long) * toff);
+    S->tstart[1] = (long long*)pic_dev_alloc(ctx, sizeof(long long) * toff);
+    S->tile_lpre = (long long*)pic_dev_alloc(ctx, sizeof(long long) * toff);
+    S->vtile = (long long*)pic_dev_alloc(ctx, sizeof(long long) * (toff + 1));
     S->tile_info = (int4*)pic_dev_alloc(ctx, sizeof(int4) * toff);
     S->inst_live = (long long*)pic_dev_alloc(ctx, sizeof(long long) * n);
-    S->inst_chunks = (long long*)pic_dev_alloc(ctx, sizeof(long long) * n);
-    S->inst_chunk_off = (long long*)pic_dev_alloc(ctx, sizeof(long long) * n);
-    S->max_chunks = toff + off / S->C + n + 16;
-    S->chunks = (Chunk*)pic_dev_alloc(ctx, sizeof(Chunk) * S->max_chunks);
+    S->inst_voff = (long long*)pic_dev_alloc(ctx, sizeof(long long) * n);
     S->ctl = (long long*)pic_dev_alloc(ctx, sizeof(long long) * (CTL_TAIL + n + 1));
     S->cbuf[0] = (unsigned int*)pic_dev_alloc(ctx, sizeof(unsigned int) * toff);
     S->cbuf[1] = (unsigned int*)pic_dev_alloc(ctx, sizeof(unsigned int) * toff);
@@ -997,8 +1054,8 @@ pic_status f32_init(pic_ctx* ctx) {
     S->qcap = std::min<long long>(off, std::max<long long>(1 << 16, (long long)(64.0 * pmax * (double)off)));
     S->queue = (unsigned long long*)pic_dev_alloc(ctx, sizeof(unsigned long long) * S->qcap);
     if (!S->queue) return f32_fail(ctx, PIC_ENOMEM, "FP32 collision queue");
-    if (!S->sortkey || !S->tile_count || !S->tile_start || !S->tile_chunk || !S->tile_info || !S->inst_live ||
-        !S->inst_chunks || !S->inst_chunk_off || !S->chunks || !S->ctl)
+    if (!S->sortkey || !S->tile_count || !S->tstart[0] || !S->tstart[1] || !S->tile_lpre || !S->vtile || !S->tile_info ||
+        !S->inst_live || !S->inst_voff || !S->ctl)
         return f32_fail(ctx, PIC_ENOMEM, "FP32 sort buffers");
     hipStream_t s = pic_stream(ctx);
     CK32(hipMemcpyAsync(S->tile_info, tinfo.data(), sizeof(int4) * toff, hipMemcpyHostToDevice, s));
@@ -1012,9 +1069,14 @@ pic_status f32_init(pic_ctx* ctx) {
     CK32(hipFuncSetAttribute((const void*)k_particles<1>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     CK32(hipFuncSetAttribute((const void*)k_particles<2>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     CK32(hipFuncSetAttribute((const void*)k_particles<3>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    int occ = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_particles<0>, kWG, lds) == hipSuccess && occ > 0)
-        S->wg_per_cu = occ;
+    // every workgroup of the statically balanced grid must be resident at once
+    int occ[4] = {0, 0, 0, 0};
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ[0], k_particles<0>, kWG, lds);
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ[1], k_particles<1>, kWG, lds);
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ[2], k_particles<2>, kWG, lds);
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ[3], k_particles<3>, kWG, lds);
+    const int omin = std::min(std::min(occ[0], occ[1]), std::min(occ[2], occ[3]));
+    if (omin > 0) S->wg_per_cu = omin;
     S->graphs = run.use_graph != 0;
     S->dF = pic_field_table(ctx);
     return PIC_OK;
@@ -1060,14 +1122,14 @@ static pic_status launch_step(pic_ctx* ctx, F32State* S, hipStream_t s, bool tim
     for (int k = 0; k < n; ++k) max_nodes = std::max<long long>(max_nodes, pic_inst_dev(ctx, k).nodes);
     hipLaunchKernelGGL(k_zero_q, dim3(grid_for(max_nodes, 1024), n), dim3(kWG), 0, s, A.It, A.Ft);
     CK32(hipGetLastError());
-    hipLaunchKernelGGL(k_prep, dim3(1), dim3(64), 0, s, S->ctl, A.cnt, n, S->C);
+    hipLaunchKernelGGL(k_prep, dim3(1), dim3(64), 0, s, S->ctl, A.cnt, n);
     CK32(hipGetLastError());
     const unsigned int tgrid = (unsigned int)((S->n_tiles + 255) / 256);
     if (mode & 2) {
         hipLaunchKernelGGL(k_zero_u32, dim3(tgrid), dim3(256), 0, s, S->tile_fill, S->n_tiles);
         CK32(hipGetLastError());
-        hipLaunchKernelGGL(k_sort_plan1, dim3(n), dim3(1024), 0, s, A.It, S->cbuf[S->cur], S->tile_start,
-                           S->tile_chunk, S->inst_live, S->inst_chunks, S->C);
+        hipLaunchKernelGGL(k_sort_plan1, dim3(n), dim3(1024), 0, s, A.It, S->cbuf[S->cur], S->tstart[1 - S->cur],
+                           S->tile_lpre, S->inst_live);
         CK32(hipGetLastError());
         hipLaunchKernelGGL(k_scatter_pre, dim3((n + 63) / 64), dim3(64), 0, s, A.cnt, n);
         CK32(hipGetLastError());
@@ -1098,10 +1160,11 @@ static pic_status launch_step(pic_ctx* ctx, F32State* S, hipStream_t s, bool tim
                        (mode & 2) ? 1 : 0);
     CK32(hipGetLastError());
     if (mode & 2) {
-        hipLaunchKernelGGL(k_sort_plan2, dim3(1), dim3(64), 0, s, S->inst_chunks, S->inst_chunk_off, S->ctl, n);
+        hipLaunchKernelGGL(k_sort_plan2, dim3(1), dim3(64), 0, s, S->inst_live, S->inst_voff, S->ctl, S->vtile, n,
+                           S->n_tiles);
         CK32(hipGetLastError());
-        hipLaunchKernelGGL(k_sort_plan3, dim3(tgrid), dim3(256), 0, s, S->tile_info, S->n_tiles, S->cbuf[S->cur],
-                           S->tile_start, S->tile_chunk, S->inst_chunk_off, S->chunks, S->C, S->TR, S->TZ);
+        hipLaunchKernelGGL(k_sort_plan3, dim3(tgrid), dim3(256), 0, s, S->tile_info, S->n_tiles, S->tile_lpre,
+                           S->inst_voff, S->vtile);
         CK32(hipGetLastError());
         hipLaunchKernelGGL(k_scatter_commit, dim3((n + 63) / 64), dim3(64), 0, s, A.cnt, S->inst_live, n);
         CK32(hipGetLastError());
@@ -1117,17 +1180,17 @@ static pic_status launch_sort(pic_ctx* ctx, F32State* S, hipStream_t s) {
     unsigned int gx = grid_for(max_slots(ctx), 2048);
     hipLaunchKernelGGL(k_sort_count, dim3(gx, n), dim3(kWG), 0, s, A, S->sortkey, S->tile_count);
     CK32(hipGetLastError());
-    hipLaunchKernelGGL(k_sort_plan1, dim3(n), dim3(1024), 0, s, A.It, S->tile_count, S->tile_start,
-                       S->tile_chunk, S->inst_live, S->inst_chunks, S->C);
+    hipLaunchKernelGGL(k_sort_plan1, dim3(n), dim3(1024), 0, s, A.It, S->tile_count, S->tstart[1 - S->cur],
+                       S->tile_lpre, S->inst_live);
     CK32(hipGetLastError());
-    hipLaunchKernelGGL(k_sort_plan2, dim3(1), dim3(64), 0, s, S->inst_chunks, S->inst_chunk_off, S->ctl, n);
+    hipLaunchKernelGGL(k_sort_plan2, dim3(1), dim3(64), 0, s, S->inst_live, S->inst_voff, S->ctl, S->vtile, n,
+                       S->n_tiles);
     CK32(hipGetLastError());
     hipLaunchKernelGGL(k_sort_plan3, dim3((S->n_tiles + 255) / 256), dim3(256), 0, s, S->tile_info, S->n_tiles,
-                       S->tile_count, S->tile_start, S->tile_chunk, S->inst_chunk_off, S->chunks, S->C, S->TR,
-                       S->TZ);
+                       S->tile_lpre, S->inst_voff, S->vtile);
     CK32(hipGetLastError());
     hipLaunchKernelGGL(k_sort_scatter, dim3(gx, n), dim3(kWG), 0, s, A, S->set[1 - S->cur], S->sortkey,
-                       S->tile_start);
+                       S->tstart[1 - S->cur]);
     CK32(hipGetLastError());
     hipLaunchKernelGGL(k_sort_commit, dim3((n + 63) / 64), dim3(64), 0, s, A.cnt, S->inst_live, n);
     CK32(hipGetLastError());
