@@ -27,6 +27,7 @@ struct Inst {
     double *rhs = nullptr, *phi = nullptr, *phi_vac = nullptr, *phiB = nullptr;
     double *Er = nullptr, *Ez = nullptr, *Br = nullptr, *Bz = nullptr, *V = nullptr;
     double *avg_acc = nullptr, *th_cp = nullptr, *th_im = nullptr, *th_lo = nullptr;
+    double *th_G = nullptr, *th_H = nullptr;
     float4* EB = nullptr;
     long long* cnt = nullptr;
     std::vector<double> V_host;
@@ -251,7 +252,7 @@ static void host_vacuum_rhs(const pic_instance_cfg& c, std::vector<double>& phiB
 }
 
 static void host_thomas(const pic_instance_cfg& c, std::vector<double>& cp, std::vector<double>& im,
-                        std::vector<double>& lo) {
+                        std::vector<double>& lo, std::vector<double>& G, std::vector<double>& H) {
     const int nr = c.nr, nz = c.nz, W = nz + 1;
     const double dr = (c.b - c.a) / (double)nr, dz = c.L / (double)nz;
     size_t N = (size_t)(nr + 1) * W;
@@ -272,6 +273,26 @@ static void host_thomas(const pic_instance_cfg& c, std::vector<double>& cp, std:
             cprev = cp[n];
         }
     }
+    // homogeneous factors of the partitioned sweeps (same segments as the kernel)
+    G.assign(N, 0.0);
+    H.assign(N, 0.0);
+    const int nri = nr - 1, seg = (nri + kThomasSeg - 1) / kThomasSeg;
+    for (int k = 1; k < nz; ++k)
+        for (int sg = 0; sg < kThomasSeg; ++sg) {
+            const int r0 = 1 + sg * seg, r1 = std::min(r0 + seg, nri + 1);
+            double g = 1.0;
+            for (int i = r0; i < r1; ++i) {
+                size_t n = (size_t)i * W + k;
+                g *= -(lo[n] * im[n]);
+                G[n] = g;
+            }
+            double hh = 1.0;
+            for (int i = r1 - 1; i >= r0; --i) {
+                size_t n = (size_t)i * W + k;
+                hh *= -cp[n];
+                H[n] = hh;
+            }
+        }
 }
 
 static void host_volume(const pic_instance_cfg& c, std::vector<double>& V) {
@@ -327,6 +348,7 @@ static pic_status upload_tables(pic_ctx* ctx) {
         memset(&f, 0, sizeof(f));
         f.Q = in.Q; f.rhs = in.rhs; f.phi = in.phi; f.phi_vac = in.phi_vac;
         f.th_cp = in.th_cp; f.th_im = in.th_im; f.th_lo = in.th_lo;
+        f.th_G = in.th_G; f.th_H = in.th_H;
         f.Er = in.Er; f.Ez = in.Ez; f.Br = in.Br; f.Bz = in.Bz; f.EB = in.EB;
         f.V = in.V; f.avg_acc = in.avg_acc;
         F.push_back(f);
@@ -436,8 +458,10 @@ static pic_status init_instance_storage(pic_ctx* ctx, Inst& in) {
     in.th_cp = dalloc<double>(ctx, N);
     in.th_im = dalloc<double>(ctx, N);
     in.th_lo = dalloc<double>(ctx, N);
+    in.th_G = dalloc<double>(ctx, N);
+    in.th_H = dalloc<double>(ctx, N);
     if (!in.Q || !in.rhs || !in.phi || !in.phi_vac || !in.phiB || !in.Br || !in.Bz || !in.V ||
-        !in.avg_acc || !in.th_cp || !in.th_im || !in.th_lo)
+        !in.avg_acc || !in.th_cp || !in.th_im || !in.th_lo || !in.th_G || !in.th_H)
         return fail(ctx, PIC_ENOMEM, "device allocation of node arrays failed");
     if (ctx->mode == PIC_MODE_FP64_PLAIN) {
         in.Er = dalloc<double>(ctx, N);
@@ -467,10 +491,13 @@ static pic_status init_instance_storage(pic_ctx* ctx, Inst& in) {
     CK(hipStreamSynchronize(s));
     host_volume(in.c, in.V_host);
     CK(hipMemcpyAsync(in.V, in.V_host.data(), sizeof(double) * N, hipMemcpyHostToDevice, s));
-    host_thomas(in.c, a, b, cc);
+    std::vector<double> gg, hh;
+    host_thomas(in.c, a, b, cc, gg, hh);
     CK(hipMemcpyAsync(in.th_cp, a.data(), sizeof(double) * N, hipMemcpyHostToDevice, s));
     CK(hipMemcpyAsync(in.th_im, b.data(), sizeof(double) * N, hipMemcpyHostToDevice, s));
     CK(hipMemcpyAsync(in.th_lo, cc.data(), sizeof(double) * N, hipMemcpyHostToDevice, s));
+    CK(hipMemcpyAsync(in.th_G, gg.data(), sizeof(double) * N, hipMemcpyHostToDevice, s));
+    CK(hipMemcpyAsync(in.th_H, hh.data(), sizeof(double) * N, hipMemcpyHostToDevice, s));
     CK(hipStreamSynchronize(s));
     host_vacuum_rhs(in.c, a, b);
     CK(hipMemcpyAsync(in.phiB, a.data(), sizeof(double) * N, hipMemcpyHostToDevice, s));

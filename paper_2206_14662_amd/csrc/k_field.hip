@@ -89,67 +89,105 @@ __global__ void __launch_bounds__(kFftBlock) kf_dst(const DevInst* __restrict__ 
     }
 }
 
-// Tridiagonal solve in r for every sine mode k (one thread per mode), with
-// the LU factors precomputed on the host: forward d_i = (b_i - lo_i d_{i-1})
-// im_i, backward x_i = d_i - cp_i x_{i+1}.  Loads are issued in batches of
-// kTB rows ahead of the recurrence so their latencies overlap.
-constexpr int kTB = 16;
+// Tridiagonal solve in r for every sine mode k with the LU factors of the
+// matrix precomputed on the host: forward d_i = (b_i - lo_i d_{i-1}) im_i,
+// backward x_i = d_i - cp_i x_{i+1}.  The interior rows are cut into
+// kThomasSeg segments handled by different waves: each sweeps its segment
+// with a zero incoming value, the segment-end values are propagated through
+// LDS, and each row is corrected by its precomputed homogeneous factor
+// (G_i = prod(-lo im) from the segment start, H_i = prod(-cp) to its end).
+// A block covers 64 modes; lane = mode, threadIdx.y = segment.
+constexpr int kTB = 8;
 
-__global__ void kf_thomas(const DevInst* __restrict__ It, const FieldDev* __restrict__ Ft,
-                          int inst_base) {
+__global__ void __launch_bounds__(64 * kThomasSeg) kf_thomas(const DevInst* __restrict__ It,
+                                                             const FieldDev* __restrict__ Ft, int inst_base) {
+    __shared__ double s_val[kThomasSeg][64], s_fac[kThomasSeg][64];
     const int inst = inst_base + blockIdx.y;
     const DevInst& I = It[inst];
     const FieldDev& F = Ft[inst];
-    const int k = 1 + blockIdx.x * blockDim.x + threadIdx.x;
-    if (I.frozen || k > I.nz - 1) return;
+    if (I.frozen) return;
+    const int lane = threadIdx.x, sg = threadIdx.y;
+    const int k = 1 + blockIdx.x * 64 + lane;
+    if (1 + (int)blockIdx.x * 64 > I.nz - 1) return;  // whole block past the modes
+    const bool valid = k <= I.nz - 1;
+    const int kk = valid ? k : 1;
     const long long W = I.W;
     const int nri = I.nr - 1;
+    const int m = (nri + kThomasSeg - 1) / kThomasSeg;
+    const int r0 = 1 + sg * m, r1 = min(r0 + m, nri + 1);
     double* __restrict__ rhs = F.rhs;
     const double* __restrict__ lo = F.th_lo;
     const double* __restrict__ im = F.th_im;
     const double* __restrict__ cp = F.th_cp;
+    const double* __restrict__ G = F.th_G;
+    const double* __restrict__ H = F.th_H;
+    // forward sweep of the segment from zero
     double d = 0.0;
-    int i = 1;
-    for (; i + kTB - 1 <= nri; i += kTB) {
+    int i = r0;
+    for (; i + kTB <= r1; i += kTB) {
         double bb[kTB], ll[kTB], mm[kTB];
 #pragma unroll
         for (int u = 0; u < kTB; ++u) {
-            const long long n = (long long)(i + u) * W + k;
-            bb[u] = rhs[n];
-            ll[u] = lo[n];
-            mm[u] = im[n];
+            const long long n = (long long)(i + u) * W + kk;
+            bb[u] = rhs[n]; ll[u] = lo[n]; mm[u] = im[n];
         }
 #pragma unroll
         for (int u = 0; u < kTB; ++u) {
             d = (bb[u] - ll[u] * d) * mm[u];
-            rhs[(long long)(i + u) * W + k] = d;
+            if (valid) rhs[(long long)(i + u) * W + kk] = d;
         }
     }
-    for (; i <= nri; ++i) {
-        const long long n = (long long)i * W + k;
+    for (; i < r1; ++i) {
+        const long long n = (long long)i * W + kk;
         d = (rhs[n] - lo[n] * d) * im[n];
-        rhs[n] = d;
+        if (valid) rhs[n] = d;
     }
-    double x = d;
-    i = nri - 1;
-    for (; i - kTB + 1 >= 1; i -= kTB) {
-        double dd[kTB], cc[kTB];
+    s_val[sg][lane] = r1 > r0 ? d : 0.0;
+    s_fac[sg][lane] = r1 > r0 ? G[(long long)(r1 - 1) * W + kk] : 1.0;
+    __syncthreads();
+    double din = 0.0;
+    for (int s2 = 0; s2 < sg; ++s2) din = s_val[s2][lane] + s_fac[s2][lane] * din;
+    __syncthreads();
+    // correct the forward values and sweep the segment backward from zero
+    double x = 0.0;
+    i = r1 - 1;
+    for (; i - kTB + 1 >= r0; i -= kTB) {
+        double dd[kTB], gg[kTB], cc[kTB];
 #pragma unroll
         for (int u = 0; u < kTB; ++u) {
-            const long long n = (long long)(i - u) * W + k;
-            dd[u] = rhs[n];
-            cc[u] = cp[n];
+            const long long n = (long long)(i - u) * W + kk;
+            dd[u] = rhs[n]; gg[u] = G[n]; cc[u] = cp[n];
         }
 #pragma unroll
         for (int u = 0; u < kTB; ++u) {
-            x = dd[u] - cc[u] * x;
-            rhs[(long long)(i - u) * W + k] = x;
+            x = (dd[u] + gg[u] * din) - cc[u] * x;
+            if (valid) rhs[(long long)(i - u) * W + kk] = x;
         }
     }
-    for (; i >= 1; --i) {
-        const long long n = (long long)i * W + k;
-        x = rhs[n] - cp[n] * x;
-        rhs[n] = x;
+    for (; i >= r0; --i) {
+        const long long n = (long long)i * W + kk;
+        x = (rhs[n] + G[n] * din) - cp[n] * x;
+        if (valid) rhs[n] = x;
+    }
+    s_val[sg][lane] = r1 > r0 ? x : 0.0;
+    s_fac[sg][lane] = r1 > r0 ? H[(long long)r0 * W + kk] : 1.0;
+    __syncthreads();
+    double xin = 0.0;
+    for (int s2 = kThomasSeg - 1; s2 > sg; --s2) xin = s_val[s2][lane] + s_fac[s2][lane] * xin;
+    if (!valid || xin == 0.0) return;
+    for (i = r0; i + kTB <= r1; i += kTB) {
+        double xx[kTB], hh[kTB];
+#pragma unroll
+        for (int u = 0; u < kTB; ++u) {
+            const long long n = (long long)(i + u) * W + kk;
+            xx[u] = rhs[n]; hh[u] = H[n];
+        }
+#pragma unroll
+        for (int u = 0; u < kTB; ++u) rhs[(long long)(i + u) * W + kk] = xx[u] + hh[u] * xin;
+    }
+    for (; i < r1; ++i) {
+        const long long n = (long long)i * W + kk;
+        rhs[n] = rhs[n] + H[n] * xin;
     }
 }
 
@@ -268,7 +306,7 @@ hipError_t launch_solve_tab(const DevInst* It, const FieldDev* Ft, int inst_base
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     dim3 gth((unsigned)((max_nz - 1 + 63) / 64), (unsigned)n_inst);
-    hipLaunchKernelGGL(kf_thomas, gth, dim3(64), 0, s, It, Ft, inst_base);
+    hipLaunchKernelGGL(kf_thomas, gth, dim3(64, kThomasSeg), 0, s, It, Ft, inst_base);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(kf_dst, gdst, dim3(kFftBlock), lds, s, It, Ft, inst_base, tw, tw_n, 2,
                        bscale);

@@ -132,6 +132,9 @@ hipError_t launch_compact64(const DevInst& I, P64 src, P64 dst, long long* cnt,
                             long long* tmp_count, long long grid_cap, hipStream_t s);
 
 // Field solve and diagnostics (k_field.hip), FP64.
+// The tridiagonal solve in r splits the interior rows into this many
+// segments solved concurrently.
+constexpr int kThomasSeg = 8;
 struct FieldDev {
     long long* Q;          // fixed-point charge (nodes)
     double* rhs;           // scratch node array: transformed rows / modes
@@ -140,6 +143,8 @@ struct FieldDev {
     const double* th_cp;   // Thomas factors, [i][k] with row length W
     const double* th_im;
     const double* th_lo;
+    const double* th_G;    // forward and backward homogeneous factors within
+    const double* th_H;    // the kThomasSeg row segments of the partitioned solve
     double *Er, *Ez;       // FP64 plain form outputs (or null)
     const double *Br, *Bz;
     float4* EB;            // FP32 form output (or null)
