@@ -15,7 +15,6 @@ the particle kernel inside the same region (steps then run as plain
 launches).  The graph-replay rate of the same workload is reported beside.
 """
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -40,16 +39,24 @@ WORKLOAD_TEXT = {
 }
 
 
-def source_hash():
-    h = hashlib.sha256()
-    d = os.path.join(ROOT, "paper_2206_14662_amd", "csrc")
-    for f in sorted(os.listdir(d)):
-        h.update(open(os.path.join(d, f), "rb").read())
-    return h.hexdigest()[:16]
+def autotune(B, torch, cfgs, cache):
+    """Tile shape, halo and sort interval from the library's autotuner, run on
+    a scratch context of the same workload (its trial steps are not part of
+    the measured run, which starts again from the initial state)."""
+    sim = B.Sim(cfgs, mode=B.PIC_MODE_FP32_BATCHED)
+    t0 = time.perf_counter()
+    t = sim.autotune(trial_steps=16, cache_path=cache)
+    t["tune_s"] = time.perf_counter() - t0
+    sim.close()
+    torch.cuda.synchronize()
+    return t
 
 
-def measure(B, torch, cfgs, mode, steps, warmup, graph_too):
-    sim = B.Sim(cfgs, mode=mode)
+def measure(B, torch, cfgs, mode, steps, warmup, graph_too, tuning=None):
+    kw = {}
+    if tuning:
+        kw = {k: tuning[k] for k in ("tile_r", "tile_z", "halo", "sort_interval")}
+    sim = B.Sim(cfgs, mode=mode, **kw)
     ctx = sim.ctx
     B.pic_step(ctx, warmup)
     torch.cuda.synchronize()
@@ -81,18 +88,17 @@ def measure(B, torch, cfgs, mode, steps, warmup, graph_too):
     return out
 
 
-def cpu_baseline(cfg0, target_s=12.0):
-    """The FP64 oracle on a bounded sample of the workload: instance 0's mesh
-    and parameters with its electron count cut to fit ~10-30 s of CPU work."""
+def cpu_baseline(cfg0, target_s=15.0):
+    """The FP64 oracle on a bounded sample of the workload: instance 0 at its
+    full size (mesh, parameters, electron count), for as many steps as fill
+    about target_s seconds on the host cores."""
     import oracle
-    n = min(int(cfg0["n_init"]), 1_000_000)
-    c = dict(cfg0, n_init=n, weight=cfg0["weight"] * cfg0["n_init"] / n)
-    s = oracle.Sim(c)
+    s = oracle.Sim(dict(cfg0))
     s.load()
     t0 = time.perf_counter()
     s.step(1)
     one = time.perf_counter() - t0
-    k = max(1, min(50, int(target_s / max(one, 1e-3))))
+    k = max(1, min(200, int(target_s / max(one, 1e-3))))
     d0 = s.diag()
     t0 = time.perf_counter()
     s.step(k)
@@ -100,36 +106,95 @@ def cpu_baseline(cfg0, target_s=12.0):
     d1 = s.diag()
     ps = k * (d0["n_live"] + d1["n_live"]) / 2.0
     return {"value": ps / dt, "unit": "particle-steps/s", "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": f"instance 0 mesh {c['nr']}x{c['nz']}, {n} electrons (weight scaled), {k + 1} steps "
-                      f"incl. FP64 Poisson, {dt:.1f} s timed"}
+            "sample": f"instance 0 of the workload ({cfg0['nr']}x{cfg0['nz']} mesh, {int(cfg0['n_init'])} electrons, "
+                      f"p={cfg0['p_mbar']:g} mbar), {k} steps after one warm step, incl. FP64 Poisson, "
+                      f"{dt:.1f} s timed"}
 
 
-def read_traffic(kernel, workload):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
-    was taken on the current sources."""
-    p = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_traffic.json")
-    if not os.path.exists(p):
-        return None
-    try:
-        t = json.load(open(p))
-    except Exception:
-        return None
-    if t.get("source_hash") != source_hash():
-        return None
-    return t.get("bytes_per_launch")
+def accuracy(B, torch, workload, steps, p_mbar=None, ref="gpu64"):
+    """FP32 batched against FP64 on the same seed: relative errors of the
+    time-averaged density (L2 over nodes above 20% of its maximum), the peak
+    density and the peak outer (radial) current.  ref = "oracle" runs the
+    FP64 CPU oracle itself; "gpu64" the plain FP64 GPU form, which matches
+    the oracle step by step (used where a CPU run is out of reach)."""
+    import numpy as np
+
+    import pic_inputs as pi
+    over = {} if p_mbar is None else {"p_mbar": p_mbar}
+    if workload == "coax64hot":
+        cfg = pi.coax64hot(n_init=50000, diag_interval=10, **over)
+    else:
+        cfg = getattr(pi, workload)(**over)
+    g = B.Sim([cfg], mode=B.PIC_MODE_FP32_BATCHED)
+    t0 = time.perf_counter()
+    g.step(steps)
+    d32 = g.diag(want_density=True)
+    d32["wall_s"] = time.perf_counter() - t0
+    S = d32["S"]
+    g.close()
+    torch.cuda.synchronize()
+    print(f"# accuracy {workload}: FP32 done", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    if ref == "oracle":
+        import oracle
+        o = oracle.Sim(cfg, fx_shift=S)
+        o.load()
+        for done in range(0, steps, 50):
+            o.step(min(50, steps - done))
+            print(f"# accuracy {workload}: oracle step {done + min(50, steps - done)}", file=sys.stderr, flush=True)
+        d64 = o.diag()
+        d64["time_avg_density"] = o.time_avg_density()
+        ref_name = "FP64 CPU oracle"
+    else:
+        h = B.Sim([cfg], mode=B.PIC_MODE_FP64_PLAIN)
+        for done in range(0, steps, 500):
+            B.pic_step(h.ctx, min(500, steps - done))
+            B.pic_sync(h.ctx)
+            print(f"# accuracy {workload}: FP64 step {done + min(500, steps - done)}", file=sys.stderr, flush=True)
+        d64 = h.diag(want_density=True)
+        h.close()
+        torch.cuda.synchronize()
+        ref_name = "plain FP64 GPU form"
+    wall64 = time.perf_counter() - t0
+    na = np.asarray(d64["time_avg_density"]).reshape(-1)
+    nb = np.asarray(d32["time_avg_density"]).reshape(-1)
+    mask = na > 0.2 * na.max()
+
+    def rel(a, b):
+        return float(abs(a - b) / abs(b)) if b != 0 else None
+    return {
+        "workload": workload, "p_mbar": cfg["p_mbar"], "steps": steps, "reference": ref_name,
+        "time_avg_density_rel_l2": float(np.linalg.norm((nb - na)[mask]) / np.linalg.norm(na[mask])),
+        "peak_density_rel": rel(d32["peak_density"], d64["peak_density"]),
+        "peak_time_avg_density_rel": rel(float(nb.max()), float(na.max())),
+        "peak_I_outer_A": [d32["peak_I_outer"], d64["peak_I_outer"]],
+        "peak_I_outer_rel": rel(d32["peak_I_outer"], d64["peak_I_outer"]),
+        "n_live": [int(d32["n_live"]), int(d64["n_live"])],
+        "n_elastic": [int(d32["n_elastic"]), int(d64["n_elastic"])],
+        "n_ioniz": [int(d32["n_ioniz"]), int(d64["n_ioniz"])],
+        "n_absorbed_outer": [int(d32["n_absorbed"][1]), int(d64["n_absorbed"][1])],
+        "wall_s": [d32["wall_s"], wall64],
+    }
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=40)
-    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=8)
     ap.add_argument("--workload", default="batch8", choices=sorted(WORKLOAD_TEXT))
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--scale", type=float, default=1.0, help="particle-count scale (tests only)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 2 GiB device copy three times (reference for HBM byte counters)")
+    ap.add_argument("--no-tune", action="store_true", help="default tiles instead of the autotuner's choice")
+    ap.add_argument("--tune-cache", default=os.path.join(os.environ.get("TMPDIR", "/tmp"), "picmcc_tune.jsonl"))
+    ap.add_argument("--accuracy", default=None, choices=("coax64hot", "coax256", "coax512"),
+                    help="instead of timing, report FP32-vs-FP64 errors on this workload")
+    ap.add_argument("--acc-steps", type=int, default=2000)
+    ap.add_argument("--acc-p-mbar", type=float, default=None, help="pressure override of the accuracy workload")
+    ap.add_argument("--acc-ref", default="gpu64", choices=("gpu64", "oracle"))
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU layout is a "
@@ -153,6 +218,11 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "launches": 3}), flush=True)
         return
+    if args.accuracy:
+        print(json.dumps({"metric": "fp32_vs_fp64_error", **accuracy(B, torch, args.accuracy, args.acc_steps,
+                                                                          args.acc_p_mbar, args.acc_ref)}),
+              flush=True)
+        return
     if args.workload == "batch8":
         cfgs = pi.batch8(n_per=int(16_000_000 * args.scale))
     elif args.workload == "scan32":
@@ -162,13 +232,18 @@ def main():
     print(f"# workload {args.workload}: {len(cfgs)} instances, "
           f"{sum(c['n_init'] for c in cfgs)} electrons", file=sys.stderr, flush=True)
 
-    r32 = measure(B, torch, cfgs, B.PIC_MODE_FP32_BATCHED, args.steps, args.warmup, True)
+    tuned = None
+    if not args.no_tune:
+        tuned = autotune(B, torch, cfgs, args.tune_cache)
+        print(f"# autotune: {tuned}", file=sys.stderr, flush=True)
+    r32 = measure(B, torch, cfgs, B.PIC_MODE_FP32_BATCHED, args.steps, args.warmup, True, tuned)
     value = r32["ps"] / r32["wall"]
     print(f"# fp32: {value:.4g} particle-steps/s, graph {r32['graph_rate']:.4g}", file=sys.stderr, flush=True)
     kern_avg_ms = r32["kern_ms"] / max(1, r32["launches"])
     bytes_per_launch = BYTES_FP32 * r32["ps"] / max(1, r32["launches"])
     achieved = bytes_per_launch / (kern_avg_ms * 1e-3) / 1e9
-    traffic = read_traffic("k_particles", args.workload)
+    from paper_2206_14662_amd import profiling
+    traffic = profiling.read_traffic(os.path.join(ROOT, "profiles", f"k_particles_{args.workload}_traffic.txt"))
 
     fp64 = None
     if not args.no_fp64:
@@ -201,7 +276,8 @@ def main():
         "config": {"workload": f"{args.workload}: {WORKLOAD_TEXT[args.workload]}",
                    "instances": len(cfgs), "electrons": int(sum(c["n_init"] for c in cfgs)),
                    "form": "FP32 batched (tile-sorted, fused persistent particle kernel, FP64 Poisson)",
-                   "tuning": r32["tuning"]},
+                   "tuning": r32["tuning"],
+                   "autotune": ({k: tuned[k] for k in ("trials", "ms_per_step", "tune_s")} if tuned else None)},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "k_particles", "bytes_per_particle_step": BYTES_FP32,

@@ -252,6 +252,46 @@ pic_status pic_timing(pic_ctx* ctx, int enable, long long* launches, double* tot
 pic_status pic_tuning(pic_ctx* ctx, int* tile_r, int* tile_z, int* halo, int* sort_interval,
                       int* chunk);
 
+/*
+ * pic_retune -- FP32 form only: switch to tile_r x tile_z cell tiles, a
+ * halo-cell LDS window and a sort every sort_interval steps (a value <= 0,
+ * or < 0 for halo, keeps the current one), then re-sort every particle.
+ * Synchronises.  No result of the method depends on these choices.
+ * Errors: PIC_EINVAL (out of range, window above 64 KiB of LDS, or the FP64
+ * form; the context is unchanged), PIC_ENOMEM/PIC_EDEVICE (the context must
+ * then be destroyed).
+ */
+pic_status pic_retune(pic_ctx* ctx, int tile_r, int tile_z, int halo, int sort_interval);
+
+/*
+ * pic_autotune -- FP32 form only: time the context's own workload under
+ * candidate tile shapes, halos and sort intervals (about 20 trials of
+ * max(trial_steps, 2 sort intervals) steps each, after two intervals of
+ * warm-up) and keep the fastest.  The trial steps advance the simulation
+ * like any other steps.  cache_path (or NULL) names a text file of one JSON
+ * object per line keyed by a signature of the device and the workload
+ * (meshes, live counts to a power of two): a hit applies the stored choice
+ * without trials (*trials = 0), a miss appends the new result.  Outputs may
+ * be NULL; *ms_per_step is the winning trial's time.  Errors as pic_retune.
+ */
+pic_status pic_autotune(pic_ctx* ctx, int trial_steps, const char* cache_path, int* tile_r,
+                        int* tile_z, int* halo, int* sort_interval, double* ms_per_step,
+                        int* trials);
+
+/*
+ * pic_reserve -- grow instance `inst`'s particle storage to at least `slots`
+ * slots (new device stores from the allocator, live particles copied, the
+ * FP32 form re-sorted and its step graphs re-captured).  pic_step grows
+ * storage by itself: an instance found more than 3/4 full at one of the
+ * checks taken every 64 steps gets twice its used slots.  Synchronises.
+ * Errors: PIC_EINVAL, PIC_ENOMEM (the context must then be destroyed).
+ */
+pic_status pic_reserve(pic_ctx* ctx, int inst, long long slots);
+
+/* pic_capacity -- the slots of instance `inst` and the number of storage
+ * regrowths so far (per context). */
+pic_status pic_capacity(pic_ctx* ctx, int inst, long long* slots, long long* grow_events);
+
 #ifdef __cplusplus
 }
 #endif

@@ -84,7 +84,7 @@ class pic_derived_t(C.Structure):
 EXPORTS = ("pic_init", "pic_step", "pic_diag", "pic_destroy", "pic_last_error", "pic_sync",
            "pic_get_particles", "pic_set_particles", "pic_set_fields", "pic_get_fields",
            "pic_get_charge", "pic_get_phi", "pic_set_step", "pic_derive", "pic_auto_shift",
-           "pic_timing", "pic_tuning")
+           "pic_timing", "pic_tuning", "pic_retune", "pic_autotune", "pic_reserve", "pic_capacity")
 
 _lib = None
 _D = C.POINTER(C.c_double)
@@ -128,6 +128,10 @@ def lib():
     L.pic_auto_shift.restype = C.c_int
     L.pic_timing.argtypes = [vp, C.c_int, _LL, _D]
     L.pic_tuning.argtypes = [vp, _I, _I, _I, _I, _I]
+    L.pic_retune.argtypes = [vp, C.c_int, C.c_int, C.c_int, C.c_int]
+    L.pic_autotune.argtypes = [vp, C.c_int, C.c_char_p, _I, _I, _I, _I, _D, _I]
+    L.pic_reserve.argtypes = [vp, C.c_int, C.c_longlong]
+    L.pic_capacity.argtypes = [vp, C.c_int, _LL, _LL]
     for name in EXPORTS:
         if name not in ("pic_last_error", "pic_auto_shift"):
             getattr(L, name).restype = C.c_int
@@ -332,6 +336,34 @@ def pic_tuning(ctx):
     return dict(zip(("tile_r", "tile_z", "halo", "sort_interval", "chunk"), [x.value for x in v]))
 
 
+def pic_retune(ctx, tile_r=0, tile_z=0, halo=-1, sort_interval=0):
+    return _check(lib().pic_retune(ctx, int(tile_r), int(tile_z), int(halo), int(sort_interval)), ctx)
+
+
+def pic_autotune(ctx, trial_steps=16, cache_path=None):
+    v = [C.c_int() for _ in range(4)]
+    ms = C.c_double()
+    trials = C.c_int()
+    path = cache_path.encode() if cache_path else None
+    _check(lib().pic_autotune(ctx, int(trial_steps), path, *[C.byref(x) for x in v], C.byref(ms),
+                              C.byref(trials)), ctx)
+    out = dict(zip(("tile_r", "tile_z", "halo", "sort_interval"), [x.value for x in v]))
+    out["ms_per_step"] = ms.value
+    out["trials"] = trials.value
+    return out
+
+
+def pic_reserve(ctx, inst, slots):
+    return _check(lib().pic_reserve(ctx, int(inst), int(slots)), ctx)
+
+
+def pic_capacity(ctx, inst):
+    slots = C.c_longlong()
+    grows = C.c_longlong()
+    _check(lib().pic_capacity(ctx, int(inst), C.byref(slots), C.byref(grows)), ctx)
+    return slots.value, grows.value
+
+
 class Sim:
     """Convenience holder of one context and its instance list."""
 
@@ -386,3 +418,15 @@ class Sim:
 
     def set_step(self, step):
         pic_set_step(self.ctx, step)
+
+    def autotune(self, trial_steps=16, cache_path=None):
+        return pic_autotune(self.ctx, trial_steps, cache_path)
+
+    def retune(self, **kw):
+        pic_retune(self.ctx, **kw)
+
+    def capacity(self, k=0):
+        return pic_capacity(self.ctx, k)
+
+    def reserve(self, slots, k=0):
+        pic_reserve(self.ctx, k, slots)

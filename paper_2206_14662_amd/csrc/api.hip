@@ -41,6 +41,7 @@ struct pic_ctx {
     bool own_stream = false;
     std::string err;
     std::vector<void*> allocs;
+    long long grow_events = 0;  // FP64 store regrowths
     DevInst* dI = nullptr;
     FieldDev* dF = nullptr;
     FieldDev* dFvac = nullptr;
@@ -94,7 +95,8 @@ void* pic_dev_alloc(pic_ctx* ctx, size_t bytes) {
 void pic_dev_free(pic_ctx* ctx, void* p) {
     if (!p) return;
     auto it = std::find(ctx->allocs.begin(), ctx->allocs.end(), p);
-    if (it != ctx->allocs.end()) ctx->allocs.erase(it);
+    if (it == ctx->allocs.end()) return;  // not ours
+    ctx->allocs.erase(it);
     if (ctx->run.alloc.alloc) {
         if (ctx->run.alloc.free) ctx->run.alloc.free(p, ctx->run.alloc.user);
     } else {
@@ -407,6 +409,19 @@ long long* pic_counters(pic_ctx* ctx) { return ctx->dcnt; }
 long long* pic_inst_Q(pic_ctx* ctx, int k) { return ctx->in[k].Q; }
 float4* pic_inst_EB(pic_ctx* ctx, int k) { return ctx->in[k].EB; }
 DevInst* pic_dev_table(pic_ctx* ctx) { return ctx->dI; }
+long long& pic_inst_cap(pic_ctx* ctx, int k) { return ctx->in[k].cap; }
+
+pic_status pic_upload_inst(pic_ctx* ctx) {
+    std::vector<DevInst> I;
+    for (auto& in : ctx->in) {
+        in.I.frozen = in.frozen ? 1 : 0;
+        in.I.p_cap = ctx->mode == PIC_MODE_FP64_PLAIN ? in.cap : in.I.p_cap;
+        I.push_back(in.I);
+    }
+    CK(hipMemcpyAsync(ctx->dI, I.data(), sizeof(DevInst) * I.size(), hipMemcpyHostToDevice, ctx->stream));
+    CK(hipStreamSynchronize(ctx->stream));
+    return PIC_OK;
+}
 const pic_run_cfg& pic_run(pic_ctx* ctx) { return ctx->run; }
 void pic_set_error(pic_ctx* ctx, const std::string& m) { ctx->err = m; }
 bool pic_timing_on(pic_ctx* ctx) { return ctx->timing; }
@@ -691,6 +706,56 @@ static pic_status check_counts(pic_ctx* ctx, std::vector<long long>& cnt) {
     return PIC_OK;
 }
 
+// New FP64 stores of `cap` slots for instance k holding its used slots.
+static pic_status grow64(pic_ctx* ctx, int k, long long cap) {
+    Inst& in = ctx->in[k];
+    hipStream_t s = ctx->stream;
+    long long slots = 0;
+    CK(hipStreamSynchronize(s));
+    CK(hipMemcpy(&slots, in.cnt + C_SLOTS, sizeof(long long), hipMemcpyDeviceToHost));
+    if (cap <= in.cap) return PIC_OK;
+    P64 np[2];
+    bool ok = true;
+    for (int b = 0; b < 2; ++b) {
+        P64& p = np[b];
+        p.r = dalloc<double>(ctx, cap);
+        p.z = dalloc<double>(ctx, cap);
+        p.vr = dalloc<double>(ctx, cap);
+        p.vt = dalloc<double>(ctx, cap);
+        p.vz = dalloc<double>(ctx, cap);
+        p.w = dalloc<double>(ctx, cap);
+        p.key = dalloc<unsigned long long>(ctx, cap);
+        ok = ok && p.r && p.z && p.vr && p.vt && p.vz && p.w && p.key;
+    }
+    if (!ok) {
+        for (int b = 0; b < 2; ++b) {
+            void* a[] = {np[b].r, np[b].z, np[b].vr, np[b].vt, np[b].vz, np[b].w, np[b].key};
+            for (void* q : a) pic_dev_free(ctx, q);
+        }
+        return fail(ctx, PIC_ENOMEM, "growing FP64 particle stores");
+    }
+    const P64& o = in.p64[in.cur];
+    if (slots > 0) {
+        double* src[6] = {o.r, o.z, o.vr, o.vt, o.vz, o.w};
+        double* dst[6] = {np[0].r, np[0].z, np[0].vr, np[0].vt, np[0].vz, np[0].w};
+        for (int a = 0; a < 6; ++a)
+            CK(hipMemcpyAsync(dst[a], src[a], sizeof(double) * slots, hipMemcpyDeviceToDevice, s));
+        CK(hipMemcpyAsync(np[0].key, o.key, sizeof(unsigned long long) * slots, hipMemcpyDeviceToDevice, s));
+        CK(hipStreamSynchronize(s));
+    }
+    for (int b = 0; b < 2; ++b) {
+        void* a[] = {in.p64[b].r, in.p64[b].z, in.p64[b].vr, in.p64[b].vt, in.p64[b].vz, in.p64[b].w,
+                     in.p64[b].key};
+        for (void* q : a) pic_dev_free(ctx, q);
+        in.p64[b] = np[b];
+    }
+    in.cur = 0;
+    in.cap = cap;
+    in.I.p_cap = cap;
+    ctx->grow_events += 1;
+    return pic_upload_inst(ctx);
+}
+
 static pic_status compact64(pic_ctx* ctx, int k) {
     Inst& in = ctx->in[k];
     hipStream_t s = ctx->stream;
@@ -715,8 +780,15 @@ static pic_status step64(pic_ctx* ctx, int n_steps) {
         if (st != PIC_OK) return st;
         for (size_t k = 0; k < ctx->in.size(); ++k) {
             long long slots = cnt[k * C_NCOUNT + C_SLOTS], dead = cnt[k * C_NCOUNT + C_DEAD];
-            if (slots > (ctx->in[k].cap * 3) / 4 && dead > 0) {
+            const long long cap = ctx->in[k].cap;
+            if (slots > (cap * 3) / 4 && dead > 0) {
                 st = compact64(ctx, (int)k);
+                if (st != PIC_OK) return st;
+                slots -= dead;
+            }
+            // still 3/4 full once the dead are gone: twice the used slots
+            if (slots > (cap * 3) / 4) {
+                st = grow64(ctx, (int)k, std::max<long long>(2 * slots, cap + cap / 2));
                 if (st != PIC_OK) return st;
             }
         }
@@ -1023,4 +1095,43 @@ extern "C" pic_status pic_tuning(pic_ctx* ctx, int* tile_r, int* tile_z, int* ha
         return PIC_OK;
     }
     return f32_tuning(ctx, tile_r, tile_z, halo, sort_interval, chunk);
+}
+
+extern "C" pic_status pic_retune(pic_ctx* ctx, int tile_r, int tile_z, int halo, int sort_interval) {
+    if (!ctx) return PIC_EINVAL;
+    if (ctx->mode != PIC_MODE_FP32_BATCHED) return fail(ctx, PIC_EINVAL, "tiles exist in the FP32 form only");
+    return f32_retune(ctx, tile_r, tile_z, halo, sort_interval);
+}
+
+extern "C" pic_status pic_autotune(pic_ctx* ctx, int trial_steps, const char* cache_path, int* tile_r,
+                                   int* tile_z, int* halo, int* sort_interval, double* ms_per_step,
+                                   int* trials) {
+    if (!ctx) return PIC_EINVAL;
+    if (ctx->mode != PIC_MODE_FP32_BATCHED) return fail(ctx, PIC_EINVAL, "the autotuner serves the FP32 form");
+    if (trial_steps < 1) return fail(ctx, PIC_EINVAL, "trial_steps >= 1");
+    int v[4] = {0, 0, 0, 0};
+    pic_status st = f32_autotune(ctx, trial_steps, cache_path, v, ms_per_step, trials);
+    if (st != PIC_OK) return st;
+    if (tile_r) *tile_r = v[0];
+    if (tile_z) *tile_z = v[1];
+    if (halo) *halo = v[2];
+    if (sort_interval) *sort_interval = v[3];
+    return PIC_OK;
+}
+
+extern "C" pic_status pic_reserve(pic_ctx* ctx, int k, long long slots) {
+    pic_status st = check_inst(ctx, k);
+    if (st != PIC_OK) return st;
+    if (slots < 0) return fail(ctx, PIC_EINVAL, "slots < 0");
+    if (slots <= ctx->in[k].cap) return PIC_OK;
+    if (ctx->mode == PIC_MODE_FP64_PLAIN) return grow64(ctx, k, slots);
+    return f32_reserve(ctx, k, slots);
+}
+
+extern "C" pic_status pic_capacity(pic_ctx* ctx, int k, long long* slots, long long* grow_events) {
+    pic_status st = check_inst(ctx, k);
+    if (st != PIC_OK) return st;
+    if (slots) *slots = ctx->in[k].cap;
+    if (grow_events) *grow_events = ctx->mode == PIC_MODE_FP64_PLAIN ? ctx->grow_events : f32_grow_events(ctx);
+    return PIC_OK;
 }

@@ -20,6 +20,9 @@ long long* pic_counters(pic_ctx* ctx);
 long long* pic_inst_Q(pic_ctx* ctx, int k);
 float4* pic_inst_EB(pic_ctx* ctx, int k);
 pic::DevInst* pic_dev_table(pic_ctx* ctx);
+// copies the host instance table (after p_off/p_cap/tile changes) to the device
+pic_status pic_upload_inst(pic_ctx* ctx);
+long long& pic_inst_cap(pic_ctx* ctx, int k);
 const pic_run_cfg& pic_run(pic_ctx* ctx);
 void pic_set_error(pic_ctx* ctx, const std::string& m);
 bool pic_timing_on(pic_ctx* ctx);
@@ -50,3 +53,8 @@ pic_status f32_check(pic_ctx* ctx);
 long long f32_live_count(pic_ctx* ctx, int k, const long long* cnt);
 pic_status f32_tuning(pic_ctx* ctx, int* tile_r, int* tile_z, int* halo, int* sort_interval,
                       int* chunk);
+pic_status f32_retune(pic_ctx* ctx, int tile_r, int tile_z, int halo, int sort_interval);
+pic_status f32_reserve(pic_ctx* ctx, int k, long long slots);
+pic_status f32_autotune(pic_ctx* ctx, int trial_steps, const char* cache, int out[4], double* ms_out,
+                        int* trials_out);
+long long f32_grow_events(pic_ctx* ctx);

@@ -27,6 +27,8 @@
 #include <string.h>
 
 #include <algorithm>
+#include <cstdio>
+#include <cstdlib>
 #include <vector>
 
 #include "fp32.h"
@@ -64,8 +66,13 @@ __device__ __forceinline__ void gbl_add(gbl_u64* p, unsigned long long v) {
 }
 
 struct PSet {
-    float *r, *z, *vr, *vt, *vz, *w;
-    unsigned long long* key;
+    float* r = nullptr;
+    float* z = nullptr;
+    float* vr = nullptr;
+    float* vt = nullptr;
+    float* vz = nullptr;
+    float* w = nullptr;
+    unsigned long long* key = nullptr;
 };
 
 
@@ -484,7 +491,7 @@ __device__ __forceinline__ int wave_search(const long long* a, int n, long long 
 // single ranks.  The updated particle (or a dead marker if it was absorbed)
 // is written there instead of in place.
 template <int MODE>
-__global__ void __launch_bounds__(kWG) k_particles(KArgs A) {
+__global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(8, 8))) k_particles(KArgs A) {
     constexpr bool COUNT = (MODE & 1) != 0;
     constexpr bool SCATTER = (MODE & 2) != 0;
     extern __shared__ __align__(16) unsigned char smem[];
@@ -563,12 +570,14 @@ __global__ void __launch_bounds__(kWG) k_particles(KArgs A) {
         if (SCATTER && win) {
             // pass 1: destinations of this chunk's particles per neighbouring tile
             const LocalInst L1 = local_inst(I);
-            for (int base = 0; base < count; base += kWG) {
+            const int lead = (int)(start & 63);
+            for (int base = -lead; base < count; base += kWG) {
                 const int q = base + tid;
-                const long long p = start + (q < count ? q : 0);
+                const bool in = q >= 0 && q < count;
+                const long long p = start + (in ? q : 0);
                 const float r = A.p.r[p], z = A.p.z[p];
                 int bkt = -1;
-                if (q < count && r >= 0.0f) {
+                if (in && r >= 0.0f) {
                     int i, j;
                     float fr, fz;
                     cell_of(L1, r, z, i, j, fr, fz);
@@ -600,8 +609,11 @@ __global__ void __launch_bounds__(kWG) k_particles(KArgs A) {
         X.win = win; X.step = step;
         // U particles per lane per pass (their loads are all in flight before
         // any is processed); U = 1 measured fastest on gfx950 (occupancy wins)
+        // Passes start on a 64-slot boundary so that every wave's loads and
+        // stores cover whole aligned lines; lanes before the chunk idle.
         constexpr int U = 1;
-        for (int base = 0; base < count; base += U * kWG) {
+        const int lead = (int)(start & 63);
+        for (int base = -lead; base < count; base += U * kWG) {
             long long pp[U];
             bool inr[U];
             float r[U], z[U], vr[U], vt[U], vz[U], w[U];
@@ -609,7 +621,7 @@ __global__ void __launch_bounds__(kWG) k_particles(KArgs A) {
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const int q = base + u * kWG + tid;
-                inr[u] = q < count;
+                inr[u] = q >= 0 && q < count;
                 pp[u] = start + (inr[u] ? q : 0);
                 r[u] = A.p.r[pp[u]];
                 z[u] = A.p.z[pp[u]];
@@ -936,6 +948,13 @@ struct F32State {
     FieldDev* dF = nullptr;  // field table (owned by the context)
     hipStream_t gstream = nullptr;
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    hipEvent_t ev_snap = nullptr;  // counter snapshot for the capacity check
+    long long* h_cnt = nullptr;    // pinned copy of the counters
+    bool snap_pending = false;
+    int since_check = 0;
+    long long grow_events = 0;
+    bool checked_once = false;
+    std::vector<long long> prev_used;  // used slots at the previous inspected copy
     hipGraphExec_t g_step[4][2] = {{nullptr, nullptr}, {nullptr, nullptr}, {nullptr, nullptr}, {nullptr, nullptr}};
     hipGraphExec_t g_sort[2] = {nullptr, nullptr};
     bool graphs = false;
@@ -996,74 +1015,61 @@ static PSet alloc_set(pic_ctx* ctx, long long n) {
 
 static bool set_ok(const PSet& p) { return p.r && p.z && p.vr && p.vt && p.vz && p.w && p.key; }
 
-pic_status f32_init(pic_ctx* ctx) {
-    F32State* S = new F32State();
-    pic_set_f32(ctx, S);
-    const pic_run_cfg& run = pic_run(ctx);
-    if (run.tile_r > 0) S->TR = run.tile_r;
-    if (run.tile_z > 0) S->TZ = run.tile_z;
-    if (run.halo > 0) S->halo = run.halo;
-    if (run.sort_interval > 0) S->K = run.sort_interval;
-    if (run.chunk > 0) S->C = run.chunk;
-    if (S->TR > 256 || S->TZ > 256 || S->halo > 32 || S->C > (1 << 30))
-        return f32_fail(ctx, PIC_EINVAL, "tile_r/tile_z <= 256, halo <= 32, chunk <= 2^30");
-    S->win_max = (S->TR + 2 * S->halo + 1) * (S->TZ + 2 * S->halo + 1);
-    if ((size_t)S->win_max * 24 > 64 * 1024) return f32_fail(ctx, PIC_EINVAL, "tile window exceeds 64 KiB of LDS");
-    int dev = run.device;
-    (void)hipDeviceGetAttribute(&S->cu, hipDeviceAttributeMultiprocessorCount, dev);
-    if (S->cu <= 0) S->cu = 256;
+static void free_set(pic_ctx* ctx, PSet& p) {
+    void* a[] = {p.r, p.z, p.vr, p.vt, p.vz, p.w, p.key};
+    for (void* q : a) pic_dev_free(ctx, q);
+    p = PSet{};
+}
+
+// Tile tables for S->TR x S->TZ tiles with an S->halo window (the particle
+// stores are untouched): per-instance tile counts and offsets, the device
+// arrays indexed by tile, the LDS window size and the persistent grid.
+static pic_status build_tiles(pic_ctx* ctx, F32State* S) {
+    if (S->TR < 1 || S->TZ < 1 || S->TR > 256 || S->TZ > 256 || S->halo < 0 || S->halo > 32 || S->K < 1 ||
+        S->C < 1 || S->C > (1 << 30))
+        return f32_fail(ctx, PIC_EINVAL, "1 <= tile_r, tile_z <= 256, 0 <= halo <= 32, sort_interval >= 1, "
+                                         "1 <= chunk <= 2^30");
+    const int win = (S->TR + 2 * S->halo + 1) * (S->TZ + 2 * S->halo + 1);
+    if ((size_t)win * 24 > 64 * 1024) return f32_fail(ctx, PIC_EINVAL, "tile window exceeds 64 KiB of LDS");
     const int n = pic_n_inst(ctx);
-    long long off = 0;
+    long long tsum = 0;
+    for (int k = 0; k < n; ++k) {
+        const DevInst& I = pic_inst_dev(ctx, k);
+        tsum += (long long)((I.nr + S->TR - 1) / S->TR) * ((I.nz + S->TZ - 1) / S->TZ);
+    }
+    if (tsum > (1 << 26)) return f32_fail(ctx, PIC_EINVAL, "too many tiles");
+    // nothing is changed before this point: PIC_EINVAL leaves the tables as they were
+    S->win_max = win;
+    void* old[] = {S->tile_count, S->tstart[0], S->tstart[1], S->tile_lpre, S->vtile,
+                   S->tile_info, S->cbuf[0],   S->cbuf[1],   S->tile_fill};
+    for (void* q : old) pic_dev_free(ctx, q);
     int toff = 0;
     std::vector<int4> tinfo;
     for (int k = 0; k < n; ++k) {
         DevInst& I = pic_inst_dev(ctx, k);
-        I.p_off = off;
-        off += (I.p_cap + 63) / 64 * 64;
         I.ntr = (I.nr + S->TR - 1) / S->TR;
         I.ntz = (I.nz + S->TZ - 1) / S->TZ;
         I.tile_off = toff;
         for (int a = 0; a < I.ntr; ++a)
             for (int b = 0; b < I.ntz; ++b) tinfo.push_back(make_int4(k, a, b, 0));
         toff += I.ntr * I.ntz;
-        if (I.ntr * I.ntz > (1 << 22)) return f32_fail(ctx, PIC_EINVAL, "too many tiles");
     }
-    S->total_cap = off;
     S->n_tiles = toff;
-    S->set[0] = alloc_set(ctx, off);
-    S->set[1] = alloc_set(ctx, off);
-    if (!set_ok(S->set[0]) || !set_ok(S->set[1])) return f32_fail(ctx, PIC_ENOMEM, "FP32 particle stores");
-    S->sortkey = (unsigned long long*)pic_dev_alloc(ctx, sizeof(unsigned long long) * off);
     S->tile_count = (unsigned int*)pic_dev_alloc(ctx, sizeof(unsigned int) * toff);
     S->tstart[0] = (long long*)pic_dev_alloc(ctx, sizeof(long long) * toff);
     S->tstart[1] = (long long*)pic_dev_alloc(ctx, sizeof(long long) * toff);
     S->tile_lpre = (long long*)pic_dev_alloc(ctx, sizeof(long long) * toff);
     S->vtile = (long long*)pic_dev_alloc(ctx, sizeof(long long) * (toff + 1));
     S->tile_info = (int4*)pic_dev_alloc(ctx, sizeof(int4) * toff);
-    S->inst_live = (long long*)pic_dev_alloc(ctx, sizeof(long long) * n);
-    S->inst_voff = (long long*)pic_dev_alloc(ctx, sizeof(long long) * n);
-    S->ctl = (long long*)pic_dev_alloc(ctx, sizeof(long long) * (CTL_TAIL + n + 1));
     S->cbuf[0] = (unsigned int*)pic_dev_alloc(ctx, sizeof(unsigned int) * toff);
     S->cbuf[1] = (unsigned int*)pic_dev_alloc(ctx, sizeof(unsigned int) * toff);
     S->tile_fill = (unsigned int*)pic_dev_alloc(ctx, sizeof(unsigned int) * toff);
-    if (!S->cbuf[0] || !S->cbuf[1] || !S->tile_fill) return f32_fail(ctx, PIC_ENOMEM, "FP32 sort counters");
-    // collision candidates per step are binomial(N, P_null): size the queue far
-    // above the mean (an overflow is reported, never ignored)
-    double pmax = 0.0;
-    for (int k = 0; k < n; ++k) pmax = std::max(pmax, pic_inst_dev(ctx, k).P_null);
-    S->qcap = std::min<long long>(off, std::max<long long>(1 << 16, (long long)(64.0 * pmax * (double)off)));
-    S->queue = (unsigned long long*)pic_dev_alloc(ctx, sizeof(unsigned long long) * S->qcap);
-    if (!S->queue) return f32_fail(ctx, PIC_ENOMEM, "FP32 collision queue");
-    if (!S->sortkey || !S->tile_count || !S->tstart[0] || !S->tstart[1] || !S->tile_lpre || !S->vtile || !S->tile_info ||
-        !S->inst_live || !S->inst_voff || !S->ctl)
-        return f32_fail(ctx, PIC_ENOMEM, "FP32 sort buffers");
+    if (!S->tile_count || !S->tstart[0] || !S->tstart[1] || !S->tile_lpre || !S->vtile || !S->tile_info ||
+        !S->cbuf[0] || !S->cbuf[1] || !S->tile_fill)
+        return f32_fail(ctx, PIC_ENOMEM, "FP32 tile tables");
     hipStream_t s = pic_stream(ctx);
     CK32(hipMemcpyAsync(S->tile_info, tinfo.data(), sizeof(int4) * toff, hipMemcpyHostToDevice, s));
-    CK32(hipMemsetAsync(S->ctl, 0, sizeof(long long) * (CTL_TAIL + n + 1), s));
     CK32(hipStreamSynchronize(s));
-    CK32(hipStreamCreateWithFlags(&S->gstream, hipStreamNonBlocking));
-    CK32(hipEventCreateWithFlags(&S->ev_in, hipEventDisableTiming));
-    CK32(hipEventCreateWithFlags(&S->ev_out, hipEventDisableTiming));
     size_t lds = (size_t)S->win_max * (sizeof(float4) + sizeof(unsigned long long));
     CK32(hipFuncSetAttribute((const void*)k_particles<0>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     CK32(hipFuncSetAttribute((const void*)k_particles<1>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
@@ -1076,7 +1082,106 @@ pic_status f32_init(pic_ctx* ctx) {
     (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ[2], k_particles<2>, kWG, lds);
     (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ[3], k_particles<3>, kWG, lds);
     const int omin = std::min(std::min(occ[0], occ[1]), std::min(occ[2], occ[3]));
-    if (omin > 0) S->wg_per_cu = omin;
+    S->wg_per_cu = omin > 0 ? omin : 1;
+    return PIC_OK;
+}
+
+// Particle stores for per-instance capacities caps (segments 64-slot aligned).
+// With copy, the used slots of every instance move from the current store to
+// the new one; the tile layout must then be rebuilt by a full sort.
+static pic_status build_store(pic_ctx* ctx, F32State* S, const std::vector<long long>& caps, bool copy) {
+    const int n = pic_n_inst(ctx);
+    std::vector<long long> slots(n, 0), old_off(n, 0);
+    if (copy) {
+        std::vector<long long> cnt((size_t)n * C_NCOUNT);
+        CK32(hipMemcpy(cnt.data(), pic_counters(ctx), sizeof(long long) * cnt.size(), hipMemcpyDeviceToHost));
+        for (int k = 0; k < n; ++k) {
+            slots[k] = cnt[(size_t)k * C_NCOUNT + C_SLOTS];
+            old_off[k] = pic_inst_dev(ctx, k).p_off;
+            if (slots[k] > caps[k]) return f32_fail(ctx, PIC_EINVAL, "capacity below the used slots");
+        }
+    }
+    long long off = 0;
+    std::vector<long long> new_off(n);
+    for (int k = 0; k < n; ++k) {
+        new_off[k] = off;
+        off += (caps[k] + 63) / 64 * 64;
+    }
+    PSet ns[2] = {alloc_set(ctx, off), alloc_set(ctx, off)};
+    unsigned long long* nkey = (unsigned long long*)pic_dev_alloc(ctx, sizeof(unsigned long long) * off);
+    // collision candidates per step are binomial(N, P_null): size the queue far
+    // above the mean (an overflow is reported, never ignored)
+    double pmax = 0.0;
+    for (int k = 0; k < n; ++k) pmax = std::max(pmax, pic_inst_dev(ctx, k).P_null);
+    const long long qcap = std::min<long long>(off, std::max<long long>(1 << 16, (long long)(64.0 * pmax * (double)off)));
+    unsigned long long* nq = (unsigned long long*)pic_dev_alloc(ctx, sizeof(unsigned long long) * qcap);
+    if (!set_ok(ns[0]) || !set_ok(ns[1]) || !nkey || !nq) {
+        for (int b = 0; b < 2; ++b) free_set(ctx, ns[b]);
+        pic_dev_free(ctx, nkey);
+        pic_dev_free(ctx, nq);
+        return f32_fail(ctx, PIC_ENOMEM, "FP32 particle stores");
+    }
+    hipStream_t s = pic_stream(ctx);
+    if (copy) {
+        const PSet& P = S->set[S->cur];
+        float* src[6] = {P.r, P.z, P.vr, P.vt, P.vz, P.w};
+        float* dst[6] = {ns[0].r, ns[0].z, ns[0].vr, ns[0].vt, ns[0].vz, ns[0].w};
+        for (int k = 0; k < n; ++k) {
+            if (slots[k] <= 0) continue;
+            for (int a = 0; a < 6; ++a)
+                CK32(hipMemcpyAsync(dst[a] + new_off[k], src[a] + old_off[k], sizeof(float) * slots[k],
+                                    hipMemcpyDeviceToDevice, s));
+            CK32(hipMemcpyAsync(ns[0].key + new_off[k], P.key + old_off[k], sizeof(unsigned long long) * slots[k],
+                                hipMemcpyDeviceToDevice, s));
+        }
+        CK32(hipStreamSynchronize(s));
+    }
+    for (int b = 0; b < 2; ++b) free_set(ctx, S->set[b]);
+    pic_dev_free(ctx, S->sortkey);
+    pic_dev_free(ctx, S->queue);
+    S->set[0] = ns[0];
+    S->set[1] = ns[1];
+    S->cur = 0;
+    S->sortkey = nkey;
+    S->queue = nq;
+    S->qcap = qcap;
+    S->total_cap = off;
+    for (int k = 0; k < n; ++k) {
+        DevInst& I = pic_inst_dev(ctx, k);
+        I.p_off = new_off[k];
+        I.p_cap = caps[k];
+    }
+    return PIC_OK;
+}
+
+pic_status f32_init(pic_ctx* ctx) {
+    F32State* S = new F32State();
+    pic_set_f32(ctx, S);
+    const pic_run_cfg& run = pic_run(ctx);
+    if (run.tile_r > 0) S->TR = run.tile_r;
+    if (run.tile_z > 0) S->TZ = run.tile_z;
+    if (run.halo > 0) S->halo = run.halo;
+    if (run.sort_interval > 0) S->K = run.sort_interval;
+    if (run.chunk > 0) S->C = run.chunk;
+    pic_status st = build_tiles(ctx, S);
+    if (st != PIC_OK) return st;
+    const int n = pic_n_inst(ctx);
+    std::vector<long long> caps(n);
+    for (int k = 0; k < n; ++k) caps[k] = pic_inst_dev(ctx, k).p_cap;
+    st = build_store(ctx, S, caps, false);
+    if (st != PIC_OK) return st;
+    S->ctl = (long long*)pic_dev_alloc(ctx, sizeof(long long) * (CTL_TAIL + n + 1));
+    S->inst_live = (long long*)pic_dev_alloc(ctx, sizeof(long long) * n);
+    S->inst_voff = (long long*)pic_dev_alloc(ctx, sizeof(long long) * n);
+    CK32(hipHostMalloc((void**)&S->h_cnt, sizeof(long long) * (size_t)n * C_NCOUNT, hipHostMallocDefault));
+    if (!S->ctl || !S->inst_live || !S->inst_voff) return f32_fail(ctx, PIC_ENOMEM, "FP32 sort buffers");
+    hipStream_t s = pic_stream(ctx);
+    CK32(hipMemsetAsync(S->ctl, 0, sizeof(long long) * (CTL_TAIL + n + 1), s));
+    CK32(hipStreamSynchronize(s));
+    CK32(hipStreamCreateWithFlags(&S->gstream, hipStreamNonBlocking));
+    CK32(hipEventCreateWithFlags(&S->ev_in, hipEventDisableTiming));
+    CK32(hipEventCreateWithFlags(&S->ev_out, hipEventDisableTiming));
+    CK32(hipEventCreateWithFlags(&S->ev_snap, hipEventDisableTiming));
     S->graphs = run.use_graph != 0;
     S->dF = pic_field_table(ctx);
     return PIC_OK;
@@ -1103,6 +1208,11 @@ void f32_destroy(pic_ctx* ctx) {
     }
     if (S->ev_in) (void)hipEventDestroy(S->ev_in);
     if (S->ev_out) (void)hipEventDestroy(S->ev_out);
+    if (S->ev_snap) {
+        (void)hipEventSynchronize(S->ev_snap);
+        (void)hipEventDestroy(S->ev_snap);
+    }
+    if (S->h_cnt) (void)hipHostFree(S->h_cnt);
     delete S;
     pic_set_f32(ctx, nullptr);
 }
@@ -1245,6 +1355,127 @@ static int next_mode(const F32State* S) {
     return 0;
 }
 
+// Every particle counts as unsorted again and one full sort rebuilds the
+// layout (after the tiles or the stores changed).
+static pic_status resort_all(pic_ctx* ctx, F32State* S) {
+    hipStream_t s = pic_stream(ctx);
+    const int n = pic_n_inst(ctx);
+    CK32(hipStreamSynchronize(s));
+    for (int k = 0; k < n; ++k) {
+        long long zero = 0;
+        CK32(hipMemcpy(pic_counters(ctx) + (long long)k * C_NCOUNT + C_LIVE_SORTED, &zero, sizeof(zero),
+                       hipMemcpyHostToDevice));
+    }
+    pic_status st = pic_upload_inst(ctx);
+    if (st != PIC_OK) return st;
+    st = run_sort_direct(ctx, S, s);
+    if (st != PIC_OK) return st;
+    CK32(hipStreamSynchronize(s));
+    return PIC_OK;
+}
+
+static pic_status quiesce(pic_ctx* ctx, F32State* S) {
+    CK32(hipStreamSynchronize(pic_stream(ctx)));
+    if (S->gstream) CK32(hipStreamSynchronize(S->gstream));
+    if (S->snap_pending) CK32(hipEventSynchronize(S->ev_snap));  // the copy stays valid
+    drop_graphs(S);
+    return PIC_OK;
+}
+
+pic_status f32_retune(pic_ctx* ctx, int tile_r, int tile_z, int halo, int sort_interval) {
+    F32State* S = pic_get_f32(ctx);
+    pic_status st = quiesce(ctx, S);
+    if (st != PIC_OK) return st;
+    const int old[4] = {S->TR, S->TZ, S->halo, S->K};
+    if (tile_r > 0) S->TR = tile_r;
+    if (tile_z > 0) S->TZ = tile_z;
+    if (halo >= 0) S->halo = halo;
+    if (sort_interval > 0) S->K = sort_interval;
+    st = build_tiles(ctx, S);
+    if (st == PIC_EINVAL) {  // rejected before anything changed
+        S->TR = old[0]; S->TZ = old[1]; S->halo = old[2]; S->K = old[3];
+        return st;
+    }
+    if (st != PIC_OK) return st;
+    return resort_all(ctx, S);
+}
+
+pic_status f32_reserve(pic_ctx* ctx, int k, long long slots) {
+    F32State* S = pic_get_f32(ctx);
+    const int n = pic_n_inst(ctx);
+    std::vector<long long> caps(n);
+    for (int j = 0; j < n; ++j) caps[j] = pic_inst_dev(ctx, j).p_cap;
+    if (slots <= caps[k]) return PIC_OK;
+    caps[k] = slots;
+    pic_status st = quiesce(ctx, S);
+    if (st != PIC_OK) return st;
+    st = build_store(ctx, S, caps, true);
+    if (st != PIC_OK) return st;
+    for (int j = 0; j < n; ++j) pic_inst_cap(ctx, j) = caps[j];
+    return resort_all(ctx, S);
+}
+
+// Capacity check, a lagged one so the stream never drains: the counters are
+// copied to pinned memory every kCheckEvery steps and the previous copy is
+// inspected.  Its used slots plus twice their growth since the copy before
+// (the lag spans up to two check periods) must stay under 3/4 of the
+// segment, else the instance is grown to twice that projection (new stores,
+// copy, full sort, graphs re-captured).  The first check of a context looks
+// at the current counters.  Dropped electrons or a fixed-point overflow in
+// the copy end the step call with an error.
+constexpr int kCheckEvery = 64;
+
+static pic_status capacity_check(pic_ctx* ctx, F32State* S, hipStream_t work) {
+    const int n = pic_n_inst(ctx);
+    if (!S->checked_once) {
+        // the first check of a context inspects the current counters at once
+        S->checked_once = true;
+        CK32(hipMemcpyAsync(S->h_cnt, pic_counters(ctx), sizeof(long long) * (size_t)n * C_NCOUNT,
+                            hipMemcpyDeviceToHost, work));
+        CK32(hipEventRecord(S->ev_snap, work));
+        S->snap_pending = true;
+    }
+    if (S->snap_pending) {
+        CK32(hipEventSynchronize(S->ev_snap));
+        S->snap_pending = false;
+        if ((int)S->prev_used.size() != n) S->prev_used.assign(n, -1);
+        std::vector<long long> caps(n);
+        bool grow = false;
+        for (int k = 0; k < n; ++k) {
+            const long long* c = S->h_cnt + (size_t)k * C_NCOUNT;
+            if (c[C_DROPPED] > 0)
+                return f32_fail(ctx, PIC_ECAPACITY, "instance " + std::to_string(k) + ": new electrons dropped");
+            if (c[C_OVERFLOW] > 0)
+                return f32_fail(ctx, PIC_EOVERFLOW, "instance " + std::to_string(k) + ": fixed-point overflow");
+            const long long cap = pic_inst_dev(ctx, k).p_cap;
+            const long long used = c[C_SLOTS];
+            const long long rise = S->prev_used[k] >= 0 ? std::max(0ll, used - S->prev_used[k]) : 0;
+            const long long proj = used + 2 * rise;
+            S->prev_used[k] = used;
+            caps[k] = cap;
+            if (proj > cap - cap / 4) {
+                caps[k] = std::max<long long>(2 * proj, cap + cap / 2);
+                grow = true;
+            }
+        }
+        if (grow) {
+            pic_status st = quiesce(ctx, S);
+            if (st != PIC_OK) return st;
+            st = build_store(ctx, S, caps, true);
+            if (st != PIC_OK) return st;
+            for (int k = 0; k < n; ++k) pic_inst_cap(ctx, k) = caps[k];
+            st = resort_all(ctx, S);
+            if (st != PIC_OK) return st;
+            S->grow_events += 1;
+        }
+    }
+    CK32(hipMemcpyAsync(S->h_cnt, pic_counters(ctx), sizeof(long long) * (size_t)n * C_NCOUNT,
+                        hipMemcpyDeviceToHost, work));
+    CK32(hipEventRecord(S->ev_snap, work));
+    S->snap_pending = true;
+    return PIC_OK;
+}
+
 pic_status f32_step(pic_ctx* ctx, int n_steps) {
     F32State* S = pic_get_f32(ctx);
     hipStream_t s = pic_stream(ctx);
@@ -1252,6 +1483,17 @@ pic_status f32_step(pic_ctx* ctx, int n_steps) {
     const bool use_graph = S->graphs && !timed;
     bool waited = false;
     for (int it = 0; it < n_steps; ++it) {
+        if (S->since_check == 0) {
+            if (use_graph && waited) {
+                // bring the caller's stream up to date before a possible regrowth
+                CK32(hipEventRecord(S->ev_out, S->gstream));
+                CK32(hipStreamWaitEvent(s, S->ev_out, 0));
+                waited = false;
+            }
+            pic_status st = capacity_check(ctx, S, s);
+            if (st != PIC_OK) return st;
+        }
+        S->since_check = (S->since_check + 1) % kCheckEvery;
         const int mode = next_mode(S);
         if (use_graph) {
             if (!S->g_step[mode][S->cur]) {
@@ -1284,6 +1526,156 @@ pic_status f32_step(pic_ctx* ctx, int n_steps) {
     }
     return PIC_OK;
 }
+
+// ---- autotuner ---------------------------------------------------------------
+// Times the real workload under candidate tile shapes, halos and sort
+// intervals (coordinate search: tile shape, then halo, then interval) and
+// keeps the fastest.  Every result of the method is independent of these
+// choices (bit-identical), so the trial steps are ordinary steps of the run.
+// A cache file holds one JSON object per line keyed by a workload signature.
+
+static std::string tune_signature(pic_ctx* ctx) {
+    hipDeviceProp_t prop;
+    int dev = 0;
+    std::string arch = "unknown";
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) arch = prop.gcnArchName;
+    const int n = pic_n_inst(ctx);
+    std::vector<long long> cnt((size_t)n * C_NCOUNT);
+    (void)hipMemcpy(cnt.data(), pic_counters(ctx), sizeof(long long) * cnt.size(), hipMemcpyDeviceToHost);
+    std::string sig = arch + ";" + std::to_string(n);
+    for (int k = 0; k < n; ++k) {
+        const DevInst& I = pic_inst_dev(ctx, k);
+        const long long live = cnt[(size_t)k * C_NCOUNT + C_SLOTS] - cnt[(size_t)k * C_NCOUNT + C_DEAD];
+        int lb = 0;
+        while ((1ll << (lb + 1)) <= std::max(live, 1ll)) ++lb;
+        sig += ";" + std::to_string(I.nr) + "x" + std::to_string(I.nz) + ":" + std::to_string(lb);
+    }
+    return sig;
+}
+
+static bool tune_lookup(const char* path, const std::string& sig, int v[4]) {
+    FILE* f = path ? fopen(path, "r") : nullptr;
+    if (!f) return false;
+    char line[4096];
+    const std::string key = "\"sig\": \"" + sig + "\"";
+    bool found = false;
+    while (fgets(line, sizeof(line), f)) {
+        std::string l(line);
+        if (l.find(key) == std::string::npos) continue;
+        const char* names[4] = {"\"tile_r\": ", "\"tile_z\": ", "\"halo\": ", "\"sort_interval\": "};
+        bool ok = true;
+        for (int i = 0; i < 4; ++i) {
+            size_t at = l.find(names[i]);
+            if (at == std::string::npos) { ok = false; break; }
+            v[i] = atoi(l.c_str() + at + strlen(names[i]));
+        }
+        if (ok) found = true;
+    }
+    fclose(f);
+    return found;
+}
+
+pic_status f32_autotune(pic_ctx* ctx, int trial_steps, const char* cache, int out[4], double* ms_out,
+                        int* trials_out) {
+    F32State* S = pic_get_f32(ctx);
+    const std::string sig = tune_signature(ctx);
+    int v[4];
+    if (tune_lookup(cache, sig, v)) {
+        pic_status st = f32_retune(ctx, v[0], v[1], v[2], v[3]);
+        if (st != PIC_OK) return st;
+        for (int i = 0; i < 4; ++i) out[i] = v[i];
+        if (ms_out) *ms_out = 0.0;
+        if (trials_out) *trials_out = 0;
+        return PIC_OK;
+    }
+    hipStream_t s = pic_stream(ctx);
+    hipEvent_t e0, e1;
+    CK32(hipEventCreate(&e0));
+    CK32(hipEventCreate(&e1));
+    int trials = 0;
+    const int n = pic_n_inst(ctx);
+    std::vector<long long> cnt((size_t)n * C_NCOUNT);
+    auto psteps = [&]() -> long long {
+        if (hipMemcpy(cnt.data(), pic_counters(ctx), sizeof(long long) * cnt.size(), hipMemcpyDeviceToHost) !=
+            hipSuccess)
+            return 0;
+        long long t = 0;
+        for (int k = 0; k < n; ++k) t += cnt[(size_t)k * C_NCOUNT + C_PSTEPS];
+        return t;
+    };
+    auto trial = [&](int TR, int TZ, int h, int K, double& ms) -> pic_status {
+        ms = 1e30;
+        pic_status st = f32_retune(ctx, TR, TZ, h, K);
+        if (st == PIC_EINVAL) return PIC_OK;  // does not fit: skipped
+        if (st != PIC_OK) return st;
+        st = f32_step(ctx, 2 * K);  // every step kind captured and warm
+        if (st != PIC_OK) return st;
+        const int T = ((std::max(trial_steps, 2 * K) + K - 1) / K) * K;
+        const long long ps0 = psteps();
+        CK32(hipEventRecord(e0, s));
+        st = f32_step(ctx, T);
+        if (st != PIC_OK) return st;
+        CK32(hipEventRecord(e1, s));
+        CK32(hipEventSynchronize(e1));
+        float t = 0.0f;
+        CK32(hipEventElapsedTime(&t, e0, e1));
+        // per particle-step, so a population that changes between trials
+        // does not bias the comparison; reported per step at the final count
+        const long long ps = std::max(1ll, psteps() - ps0);
+        ms = (double)t / (double)ps;
+        ++trials;
+        return PIC_OK;
+    };
+    int best[4] = {S->TR, S->TZ, S->halo, S->K};
+    double best_ms = 1e30;
+    pic_status st = PIC_OK;
+    const int shapes[][2] = {{16, 16}, {8, 8}, {8, 16}, {16, 8}, {8, 32}, {32, 8}, {16, 32},
+                             {32, 16}, {32, 32}, {8, 64}, {16, 64}, {4, 64}, {4, 32}};
+    for (auto& sh : shapes) {
+        double ms;
+        st = trial(sh[0], sh[1], best[2], best[3], ms);
+        if (st != PIC_OK) break;
+        if (ms < best_ms) { best_ms = ms; best[0] = sh[0]; best[1] = sh[1]; }
+    }
+    const int halos[] = {1, 2, 4, 8};
+    for (int h : halos) {
+        if (st != PIC_OK || h == best[2]) continue;
+        double ms;
+        st = trial(best[0], best[1], h, best[3], ms);
+        if (st == PIC_OK && ms < best_ms) { best_ms = ms; best[2] = h; }
+    }
+    const int Ks[] = {2, 4, 8, 16, 32};
+    for (int K : Ks) {
+        if (st != PIC_OK || K == best[3]) continue;
+        double ms;
+        st = trial(best[0], best[1], best[2], K, ms);
+        if (st == PIC_OK && ms < best_ms) { best_ms = ms; best[3] = K; }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != PIC_OK) return st;
+    st = f32_retune(ctx, best[0], best[1], best[2], best[3]);
+    if (st != PIC_OK) return st;
+    for (int i = 0; i < 4; ++i) out[i] = best[i];
+    long long live = 0;
+    (void)psteps();
+    for (int k = 0; k < n; ++k) live += cnt[(size_t)k * C_NCOUNT + C_SLOTS] - cnt[(size_t)k * C_NCOUNT + C_DEAD];
+    best_ms *= (double)std::max(1ll, live);
+    if (ms_out) *ms_out = best_ms;
+    if (trials_out) *trials_out = trials;
+    if (cache) {
+        FILE* f = fopen(cache, "a");
+        if (f) {
+            fprintf(f, "{\"sig\": \"%s\", \"tile_r\": %d, \"tile_z\": %d, \"halo\": %d, \"sort_interval\": %d, "
+                       "\"ms_per_step\": %.6f, \"trials\": %d}\n",
+                    sig.c_str(), best[0], best[1], best[2], best[3], best_ms, trials);
+            fclose(f);
+        }
+    }
+    return PIC_OK;
+}
+
+long long f32_grow_events(pic_ctx* ctx) { return pic_get_f32(ctx)->grow_events; }
 
 pic_status f32_load(pic_ctx* ctx, int k) {
     F32State* S = pic_get_f32(ctx);
