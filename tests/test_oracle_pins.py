@@ -43,9 +43,17 @@ def frozen_sim(c, fields, state):
 
 
 # --------------------------------------------------------------------------
-# Philox and uniforms (statistical pins only: no published answer vectors are
-# available here, so the generator's constants are pinned by behaviour).
+# Philox and uniforms: the generator against its published known-answer
+# vectors, the uniforms by behaviour.
 # --------------------------------------------------------------------------
+
+def test_philox_known_answer_vectors():
+    kat = json.load(open(os.path.join(GOLD, "philox4x32_10_kat.json")))
+    for v in kat["vectors"]:
+        ctr = [int(x, 16) for x in v["ctr"]]
+        key = [int(x, 16) for x in v["key"]]
+        assert [int(x) for x in oracle.philox(ctr, key)] == [int(x, 16) for x in v["out"]]
+
 
 def test_philox_uniform_and_bit_balance():
     n = 1 << 14
