@@ -45,7 +45,7 @@ def autotune(B, torch, cfgs, cache):
     the measured run, which starts again from the initial state)."""
     sim = B.Sim(cfgs, mode=B.PIC_MODE_FP32_BATCHED)
     t0 = time.perf_counter()
-    t = sim.autotune(trial_steps=16, cache_path=cache)
+    t = sim.autotune(trial_steps=48, cache_path=cache)
     t["tune_s"] = time.perf_counter() - t0
     sim.close()
     torch.cuda.synchronize()
@@ -60,7 +60,9 @@ def measure(B, torch, cfgs, mode, steps, warmup, graph_too, tuning=None):
     ctx = sim.ctx
     B.pic_step(ctx, warmup)
     torch.cuda.synchronize()
-    before = sum(B.pic_diag(ctx, k)["particle_steps"] for k in range(len(cfgs)))
+    d0 = [B.pic_diag(ctx, k) for k in range(len(cfgs))]
+    before = sum(d["particle_steps"] for d in d0)
+    far0 = sum(d["n_far_deposit"] for d in d0)
     B.pic_timing(ctx, 1)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -69,8 +71,11 @@ def measure(B, torch, cfgs, mode, steps, warmup, graph_too, tuning=None):
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     launches, kern_ms = B.pic_timing(ctx, 0)
-    after = sum(B.pic_diag(ctx, k)["particle_steps"] for k in range(len(cfgs)))
-    out = dict(ps=after - before, wall=t1 - t0, launches=launches, kern_ms=kern_ms)
+    d1 = [B.pic_diag(ctx, k) for k in range(len(cfgs))]
+    after = sum(d["particle_steps"] for d in d1)
+    far = sum(d["n_far_deposit"] for d in d1) - far0
+    out = dict(ps=after - before, wall=t1 - t0, launches=launches, kern_ms=kern_ms,
+               far_frac=far / max(1, after - before))
     if graph_too:
         before = after
         torch.cuda.synchronize()
@@ -189,6 +194,7 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 2 GiB device copy three times (reference for HBM byte counters)")
     ap.add_argument("--no-tune", action="store_true", help="default tiles instead of the autotuner's choice")
+    ap.add_argument("--tiles", default=None, help="TR,TZ,HALO,K instead of the autotuner")
     ap.add_argument("--tune-cache", default=os.path.join(os.environ.get("TMPDIR", "/tmp"), "picmcc_tune.jsonl"))
     ap.add_argument("--accuracy", default=None, choices=("coax64hot", "coax256", "coax512"),
                     help="instead of timing, report FP32-vs-FP64 errors on this workload")
@@ -233,7 +239,10 @@ def main():
           f"{sum(c['n_init'] for c in cfgs)} electrons", file=sys.stderr, flush=True)
 
     tuned = None
-    if not args.no_tune:
+    if args.tiles:
+        v = [int(x) for x in args.tiles.split(",")]
+        tuned = dict(zip(("tile_r", "tile_z", "halo", "sort_interval"), v), trials=0, ms_per_step=0.0, tune_s=0.0)
+    elif not args.no_tune:
         tuned = autotune(B, torch, cfgs, args.tune_cache)
         print(f"# autotune: {tuned}", file=sys.stderr, flush=True)
     r32 = measure(B, torch, cfgs, B.PIC_MODE_FP32_BATCHED, args.steps, args.warmup, True, tuned)
@@ -281,7 +290,8 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "k_particles", "bytes_per_particle_step": BYTES_FP32,
-                     "avg_launch_ms": kern_avg_ms, "launches": r32["launches"]},
+                     "avg_launch_ms": kern_avg_ms, "launches": r32["launches"],
+                     "far_deposit_fraction": r32["far_frac"]},
         "cpu_baseline": cpu,
         "graph_replay_value": r32["graph_rate"],
         "fp64_plain": fp64,

@@ -125,6 +125,7 @@ typedef struct {
     double peak_time_avg_density; /* spatial max of the time-averaged density    */
     double peak_I_outer, peak_I_inner; /* max over windows of I_wall[1], I_wall[0] */
     long long particle_steps;  /* live macro-electrons pushed, summed over steps */
+    long long n_far_deposit;   /* FP32 form: deposits that missed the LDS window */
 } pic_diag_t;
 
 /* Host-derived constants of an instance (FP64); see pic_derive. */

@@ -71,6 +71,7 @@ class pic_diag_t(C.Structure):
         ("peak_density", C.c_double), ("peak_time_avg_density", C.c_double),
         ("peak_I_outer", C.c_double), ("peak_I_inner", C.c_double),
         ("particle_steps", C.c_longlong),
+        ("n_far_deposit", C.c_longlong),
     ]
 
 

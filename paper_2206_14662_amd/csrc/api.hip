@@ -253,7 +253,7 @@ static void host_vacuum_rhs(const pic_instance_cfg& c, std::vector<double>& phiB
         }
 }
 
-static void host_thomas(const pic_instance_cfg& c, std::vector<double>& cp, std::vector<double>& im,
+static void host_thomas(const pic_instance_cfg& c, int nseg, std::vector<double>& cp, std::vector<double>& im,
                         std::vector<double>& lo, std::vector<double>& G, std::vector<double>& H) {
     const int nr = c.nr, nz = c.nz, W = nz + 1;
     const double dr = (c.b - c.a) / (double)nr, dz = c.L / (double)nz;
@@ -278,9 +278,9 @@ static void host_thomas(const pic_instance_cfg& c, std::vector<double>& cp, std:
     // homogeneous factors of the partitioned sweeps (same segments as the kernel)
     G.assign(N, 0.0);
     H.assign(N, 0.0);
-    const int nri = nr - 1, seg = (nri + kThomasSeg - 1) / kThomasSeg;
+    const int nri = nr - 1, seg = (nri + nseg - 1) / nseg;
     for (int k = 1; k < nz; ++k)
-        for (int sg = 0; sg < kThomasSeg; ++sg) {
+        for (int sg = 0; sg < nseg; ++sg) {
             const int r0 = 1 + sg * seg, r1 = std::min(r0 + seg, nri + 1);
             double g = 1.0;
             for (int i = r0; i < r1; ++i) {
@@ -507,7 +507,7 @@ static pic_status init_instance_storage(pic_ctx* ctx, Inst& in) {
     host_volume(in.c, in.V_host);
     CK(hipMemcpyAsync(in.V, in.V_host.data(), sizeof(double) * N, hipMemcpyHostToDevice, s));
     std::vector<double> gg, hh;
-    host_thomas(in.c, a, b, cc, gg, hh);
+    host_thomas(in.c, thomas_segments(ctx->max_nr), a, b, cc, gg, hh);
     CK(hipMemcpyAsync(in.th_cp, a.data(), sizeof(double) * N, hipMemcpyHostToDevice, s));
     CK(hipMemcpyAsync(in.th_im, b.data(), sizeof(double) * N, hipMemcpyHostToDevice, s));
     CK(hipMemcpyAsync(in.th_lo, cc.data(), sizeof(double) * N, hipMemcpyHostToDevice, s));
@@ -1044,6 +1044,7 @@ extern "C" pic_status pic_diag(pic_ctx* ctx, int k, pic_diag_t* out, double* den
     memcpy(&out->peak_I_inner, &c[C_PEAKI_IN], 8);
     out->n_samples = c[C_NSAMP];
     out->particle_steps = c[C_PSTEPS];
+    out->n_far_deposit = c[C_FARDEP];
     out->S = in.S;
     if (ctx->mode == PIC_MODE_FP64_PLAIN) out->n_live = c[C_SLOTS] - c[C_DEAD];
     else out->n_live = f32_live_count(ctx, k, c);

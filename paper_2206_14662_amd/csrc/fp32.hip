@@ -301,9 +301,10 @@ __device__ __forceinline__ unsigned int wave_aggregate(bool act, int key, F&& ad
 }
 
 // chunk-level event counters kept in LDS and their device counter slots
-enum { SC_ABS_N = 0, SC_ABS_W = 4, SC_DEAD = 8, SC_CAND = 9, SC_CAP = 10, SC_N = 11 };
+enum { SC_ABS_N = 0, SC_ABS_W = 4, SC_DEAD = 8, SC_CAND = 9, SC_CAP = 10, SC_FAR = 11, SC_N = 12 };
 __constant__ int kCounterOf[SC_N] = {C_ABS_N,     C_ABS_N + 1, C_ABS_N + 2, C_ABS_N + 3, C_ABS_W, C_ABS_W + 1,
-                                     C_ABS_W + 2, C_ABS_W + 3, C_DEAD,      C_CAND,      C_CAPOVER};
+                                     C_ABS_W + 2, C_ABS_W + 3, C_DEAD,      C_CAND,      C_CAPOVER,
+                                     C_FARDEP};
 
 
 // Everything the particle loop needs about the current chunk.
@@ -444,6 +445,7 @@ __device__ __forceinline__ void push_particle(const KArgs& A, const ChunkCtx& X,
             lds_add(&X.sQ[l + 1], (unsigned long long)q01);
             lds_add(&X.sQ[l + X.ww + 1], (unsigned long long)q11);
         } else {
+            atomicAdd(&X.s_ctr[SC_FAR], 1ull);
             gbl_u64* Qg = as_gbl(X.Q);
             const long long n00 = (long long)ni * L.W + nj;
             gbl_add(&Qg[n00], (unsigned long long)q00);

@@ -106,7 +106,7 @@ __global__ void __launch_bounds__(64 * kThomasSeg) kf_thomas(const DevInst* __re
     const DevInst& I = It[inst];
     const FieldDev& F = Ft[inst];
     if (I.frozen) return;
-    const int lane = threadIdx.x, sg = threadIdx.y;
+    const int lane = threadIdx.x, sg = __builtin_amdgcn_readfirstlane(threadIdx.y);  // one wave per segment
     const int k = 1 + blockIdx.x * 64 + lane;
     if (1 + (int)blockIdx.x * 64 > I.nz - 1) return;  // whole block past the modes
     const bool valid = k <= I.nz - 1;
@@ -188,6 +188,96 @@ __global__ void __launch_bounds__(64 * kThomasSeg) kf_thomas(const DevInst* __re
     for (; i < r1; ++i) {
         const long long n = (long long)i * W + kk;
         rhs[n] = rhs[n] + H[n] * xin;
+    }
+}
+
+// The same partitioned solve with kThomasSegReg segments of at most R rows
+// whose values stay in registers between the sweeps: the right-hand side is
+// read once and the solution written once.
+template <int R>
+__global__ void __launch_bounds__(64 * kThomasSegReg) kf_thomas_reg(const DevInst* __restrict__ It,
+                                                                    const FieldDev* __restrict__ Ft,
+                                                                    int inst_base) {
+    constexpr int P = kThomasSegReg;
+    constexpr int B = R < 8 ? R : 8;  // rows whose loads are issued together
+    __shared__ double s_val[P][64], s_fac[P][64];
+    const int inst = inst_base + blockIdx.y;
+    const DevInst& I = It[inst];
+    const FieldDev& F = Ft[inst];
+    if (I.frozen) return;
+    // one wave per segment: the segment index and all row offsets are
+    // wave-uniform (scalar registers); only the mode column varies by lane
+    const int lane = threadIdx.x, sg = __builtin_amdgcn_readfirstlane(threadIdx.y);
+    const int k = 1 + blockIdx.x * 64 + lane;
+    if (1 + (int)blockIdx.x * 64 > I.nz - 1) return;  // whole block past the modes
+    const bool valid = k <= I.nz - 1;
+    const int kk = valid ? k : 1;
+    const int W = I.W;  // node offsets fit 32 bits ((nr+1)(nz+1) < 2^31)
+    const int nri = I.nr - 1;
+    const int m = (nri + P - 1) / P;  // <= R (checked by the launcher)
+    const int r0 = 1 + sg * m;
+    const int cnt = max(0, min(m, nri + 1 - r0));
+    double* __restrict__ rhs = F.rhs;
+    const double* __restrict__ lo = F.th_lo;
+    const double* __restrict__ im = F.th_im;
+    const double* __restrict__ cp = F.th_cp;
+    const double* __restrict__ G = F.th_G;
+    const double* __restrict__ H = F.th_H;
+    // rows past the segment read a valid row (clamped) and are not used
+    auto node = [&](int u) { return min(r0 + u, nri) * W + kk; };  // row part is uniform
+    double v[R];
+    double d = 0.0;
+#pragma unroll
+    for (int b = 0; b < R; b += B) {
+        double bb[B], ll[B], mm[B];
+#pragma unroll
+        for (int u = 0; u < B; ++u) {
+            const int n = node(b + u);
+            bb[u] = rhs[n]; ll[u] = lo[n]; mm[u] = im[n];
+        }
+#pragma unroll
+        for (int u = 0; u < B; ++u) {
+            const double dn = (bb[u] - ll[u] * d) * mm[u];
+            d = b + u < cnt ? dn : d;
+            v[b + u] = d;
+        }
+    }
+    s_val[sg][lane] = cnt > 0 ? d : 0.0;
+    s_fac[sg][lane] = cnt > 0 ? G[node(cnt - 1)] : 1.0;
+    __syncthreads();
+    double din = 0.0;
+    for (int s2 = 0; s2 < sg; ++s2) din = s_val[s2][lane] + s_fac[s2][lane] * din;
+    __syncthreads();
+    double x = 0.0;
+#pragma unroll
+    for (int b = R - B; b >= 0; b -= B) {
+        double gg[B], cc[B];
+#pragma unroll
+        for (int u = 0; u < B; ++u) {
+            const int n = node(b + u);
+            gg[u] = G[n]; cc[u] = cp[n];
+        }
+#pragma unroll
+        for (int u = B - 1; u >= 0; --u) {
+            const double xn = (v[b + u] + gg[u] * din) - cc[u] * x;
+            x = b + u < cnt ? xn : x;
+            v[b + u] = x;
+        }
+    }
+    s_val[sg][lane] = cnt > 0 ? x : 0.0;
+    s_fac[sg][lane] = cnt > 0 ? H[node(0)] : 1.0;
+    __syncthreads();
+    double xin = 0.0;
+    for (int s2 = P - 1; s2 > sg; --s2) xin = s_val[s2][lane] + s_fac[s2][lane] * xin;
+    if (!valid) return;
+#pragma unroll
+    for (int b = 0; b < R; b += B) {
+        double hh[B];
+#pragma unroll
+        for (int u = 0; u < B; ++u) hh[u] = H[node(b + u)];
+#pragma unroll
+        for (int u = 0; u < B; ++u)
+            if (b + u < cnt) rhs[node(b + u)] = v[b + u] + hh[u] * xin;
     }
 }
 
@@ -306,7 +396,14 @@ hipError_t launch_solve_tab(const DevInst* It, const FieldDev* Ft, int inst_base
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     dim3 gth((unsigned)((max_nz - 1 + 63) / 64), (unsigned)n_inst);
-    hipLaunchKernelGGL(kf_thomas, gth, dim3(64, kThomasSeg), 0, s, It, Ft, inst_base);
+    if (thomas_segments(max_nr) == kThomasSegReg) {
+        const int rows = (max_nr - 1 + kThomasSegReg - 1) / kThomasSegReg;
+        const dim3 blk(64, kThomasSegReg);
+        if (rows <= 8) hipLaunchKernelGGL(kf_thomas_reg<8>, gth, blk, 0, s, It, Ft, inst_base);
+        else hipLaunchKernelGGL(kf_thomas_reg<16>, gth, blk, 0, s, It, Ft, inst_base);
+    } else {
+        hipLaunchKernelGGL(kf_thomas, gth, dim3(64, kThomasSeg), 0, s, It, Ft, inst_base);
+    }
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(kf_dst, gdst, dim3(kFftBlock), lds, s, It, Ft, inst_base, tw, tw_n, 2,
                        bscale);

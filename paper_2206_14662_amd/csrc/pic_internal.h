@@ -71,6 +71,7 @@ enum Counter {
     C_OVERFLOW,              // fixed-point overflow flag
     C_LIVE_SORTED,           // live particles in the sorted region (FP32 form)
     C_PSTEPS,                // particle-steps pushed so far
+    C_FARDEP,                // deposits outside the LDS window (FP32 form)
     C_NCOUNT = 40
 };
 
@@ -132,9 +133,17 @@ hipError_t launch_compact64(const DevInst& I, P64 src, P64 dst, long long* cnt,
                             long long* tmp_count, long long grid_cap, hipStream_t s);
 
 // Field solve and diagnostics (k_field.hip), FP64.
-// The tridiagonal solve in r splits the interior rows into this many
-// segments solved concurrently.
+// The tridiagonal solve in r splits the interior rows into segments solved
+// concurrently: 16 segments held in registers while every segment of the
+// largest mesh has at most kThomasRegRows rows, else kThomasSeg segments
+// streamed through memory.  Host factors and kernels take the count from
+// thomas_segments(largest nr of the context).
 constexpr int kThomasSeg = 8;
+constexpr int kThomasSegReg = 16;
+constexpr int kThomasRegRows = 16;
+inline int thomas_segments(int max_nr) {
+    return (max_nr - 1 + kThomasSegReg - 1) / kThomasSegReg <= kThomasRegRows ? kThomasSegReg : kThomasSeg;
+}
 struct FieldDev {
     long long* Q;          // fixed-point charge (nodes)
     double* rhs;           // scratch node array: transformed rows / modes
