@@ -185,8 +185,8 @@ def accuracy(B, torch, workload, steps, p_mbar=None, ref="gpu64"):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=40)
-    ap.add_argument("--warmup", type=int, default=8)
+    ap.add_argument("--steps", type=int, default=48)
+    ap.add_argument("--warmup", type=int, default=16)
     ap.add_argument("--workload", default="batch8", choices=sorted(WORKLOAD_TEXT))
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
