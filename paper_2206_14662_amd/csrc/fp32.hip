@@ -27,6 +27,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <array>
 #include <cstdio>
 #include <cstdlib>
 #include <vector>
@@ -44,6 +45,9 @@ using namespace pic;
 namespace {
 
 constexpr int kWG = 256;
+// workgroup of the particle kernel: 16 waves share one LDS window, so large
+// windows (wide halos) still leave room for 8 waves per SIMD
+constexpr int kPWG = 1024;
 
 // LDS-qualified pointers: loads and atomics through them compile to ds_*
 // instructions even where a global fallback path sits next to them.
@@ -493,7 +497,7 @@ __device__ __forceinline__ int wave_search(const long long* a, int n, long long 
 // single ranks.  The updated particle (or a dead marker if it was absorbed)
 // is written there instead of in place.
 template <int MODE>
-__global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(8, 8))) k_particles(KArgs A) {
+__global__ void __launch_bounds__(kPWG) __attribute__((amdgpu_waves_per_eu(8, 8))) k_particles(KArgs A) {
     constexpr bool COUNT = (MODE & 1) != 0;
     constexpr bool SCATTER = (MODE & 2) != 0;
     extern __shared__ __align__(16) unsigned char smem[];
@@ -563,7 +567,7 @@ __global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(8, 8))
             j1 = min(tz0 + A.TZ + A.halo, I.nz);
             ww = j1 - j0 + 1;
             const int nwin = (i1 - i0 + 1) * ww;
-            for (int t = tid; t < nwin; t += kWG) {
+            for (int t = tid; t < nwin; t += kPWG) {
                 int a = t / ww, b = t - a * ww;
                 sEB[t] = as_gbl(F.EB)[(long long)(i0 + a) * W + (j0 + b)];
                 sQ[t] = 0ull;
@@ -573,7 +577,7 @@ __global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(8, 8))
             // pass 1: destinations of this chunk's particles per neighbouring tile
             const LocalInst L1 = local_inst(I);
             const int lead = (int)(start & 63);
-            for (int base = -lead; base < count; base += kWG) {
+            for (int base = -lead; base < count; base += kPWG) {
                 const int q = base + tid;
                 const bool in = q >= 0 && q < count;
                 const long long p = start + (in ? q : 0);
@@ -615,14 +619,14 @@ __global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(8, 8))
         // stores cover whole aligned lines; lanes before the chunk idle.
         constexpr int U = 1;
         const int lead = (int)(start & 63);
-        for (int base = -lead; base < count; base += U * kWG) {
+        for (int base = -lead; base < count; base += U * kPWG) {
             long long pp[U];
             bool inr[U];
             float r[U], z[U], vr[U], vt[U], vz[U], w[U];
             unsigned long long key[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                const int q = base + u * kWG + tid;
+                const int q = base + u * kPWG + tid;
                 inr[u] = q >= 0 && q < count;
                 pp[u] = start + (inr[u] ? q : 0);
                 r[u] = A.p.r[pp[u]];
@@ -648,7 +652,7 @@ __global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(8, 8))
         if (win) {
             const int nwin = (i1 - i0 + 1) * ww;
             gbl_u64* Qg = as_gbl(F.Q);
-            for (int t = tid; t < nwin; t += kWG) {
+            for (int t = tid; t < nwin; t += kPWG) {
                 const unsigned long long v = sQ[t];
                 if (v != 0ull) {
                     int a = t / ww, b = t - a * ww;
@@ -930,7 +934,7 @@ unsigned int grid_for(long long n, long long cap = 16384) {
 // ---------------------------------------------------------------------------
 
 struct F32State {
-    int TR = 16, TZ = 16, halo = 4, K = 8, C = 1 << 22, win_max = 0;
+    int TR = 8, TZ = 32, halo = 8, K = 16, C = 1 << 22, win_max = 0;
     int cu = 256, wg_per_cu = 4;
     PSet set[2];
     int cur = 0;
@@ -1079,10 +1083,10 @@ static pic_status build_tiles(pic_ctx* ctx, F32State* S) {
     CK32(hipFuncSetAttribute((const void*)k_particles<3>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     // every workgroup of the statically balanced grid must be resident at once
     int occ[4] = {0, 0, 0, 0};
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ[0], k_particles<0>, kWG, lds);
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ[1], k_particles<1>, kWG, lds);
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ[2], k_particles<2>, kWG, lds);
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ[3], k_particles<3>, kWG, lds);
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ[0], k_particles<0>, kPWG, lds);
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ[1], k_particles<1>, kPWG, lds);
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ[2], k_particles<2>, kPWG, lds);
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ[3], k_particles<3>, kPWG, lds);
     const int omin = std::min(std::min(occ[0], occ[1]), std::min(occ[2], occ[3]));
     S->wg_per_cu = omin > 0 ? omin : 1;
     return PIC_OK;
@@ -1261,10 +1265,10 @@ static pic_status launch_step(pic_ctx* ctx, F32State* S, hipStream_t s, bool tim
     const size_t lds = (size_t)S->win_max * (sizeof(float4) + sizeof(unsigned long long));
     const dim3 grid(S->cu * S->wg_per_cu);
     switch (mode) {
-        case 0: hipLaunchKernelGGL(k_particles<0>, grid, dim3(kWG), lds, s, A); break;
-        case 1: hipLaunchKernelGGL(k_particles<1>, grid, dim3(kWG), lds, s, A); break;
-        case 2: hipLaunchKernelGGL(k_particles<2>, grid, dim3(kWG), lds, s, A); break;
-        default: hipLaunchKernelGGL(k_particles<3>, grid, dim3(kWG), lds, s, A); break;
+        case 0: hipLaunchKernelGGL(k_particles<0>, grid, dim3(kPWG), lds, s, A); break;
+        case 1: hipLaunchKernelGGL(k_particles<1>, grid, dim3(kPWG), lds, s, A); break;
+        case 2: hipLaunchKernelGGL(k_particles<2>, grid, dim3(kPWG), lds, s, A); break;
+        default: hipLaunchKernelGGL(k_particles<3>, grid, dim3(kPWG), lds, s, A); break;
     }
     CK32(hipGetLastError());
     if (timed) CK32(hipEventRecord(e1, s));
@@ -1631,27 +1635,30 @@ pic_status f32_autotune(pic_ctx* ctx, int trial_steps, const char* cache, int ou
     int best[4] = {S->TR, S->TZ, S->halo, S->K};
     double best_ms = 1e30;
     pic_status st = PIC_OK;
-    const int shapes[][2] = {{16, 16}, {8, 8}, {8, 16}, {16, 8}, {8, 32}, {32, 8}, {16, 32},
+    const bool verbose = getenv("PICMCC_TUNE_LOG") != nullptr;  // trial log on stderr
+    std::vector<std::array<int, 4>> tried;
+    auto consider = [&](int TR, int TZ, int h, int K) {
+        const std::array<int, 4> c = {TR, TZ, h, K};
+        if (st != PIC_OK || std::find(tried.begin(), tried.end(), c) != tried.end()) return;
+        tried.push_back(c);
+        double ms;
+        st = trial(TR, TZ, h, K, ms);
+        if (verbose)
+            fprintf(stderr, "autotune: tile %dx%d halo %d sort %d: %.4g ps per particle-step%s\n", TR, TZ, h, K,
+                    ms * 1e9, ms >= 1e29 ? " (does not fit)" : "");
+        if (st == PIC_OK && ms < best_ms) {
+            best_ms = ms;
+            best[0] = TR; best[1] = TZ; best[2] = h; best[3] = K;
+        }
+    };
+    const int shapes[][2] = {{8, 32}, {8, 8}, {8, 16}, {16, 8}, {16, 16}, {32, 8}, {16, 32},
                              {32, 16}, {32, 32}, {8, 64}, {16, 64}, {4, 64}, {4, 32}};
-    for (auto& sh : shapes) {
-        double ms;
-        st = trial(sh[0], sh[1], best[2], best[3], ms);
-        if (st != PIC_OK) break;
-        if (ms < best_ms) { best_ms = ms; best[0] = sh[0]; best[1] = sh[1]; }
-    }
-    const int halos[] = {1, 2, 4, 8};
-    for (int h : halos) {
-        if (st != PIC_OK || h == best[2]) continue;
-        double ms;
-        st = trial(best[0], best[1], h, best[3], ms);
-        if (st == PIC_OK && ms < best_ms) { best_ms = ms; best[2] = h; }
-    }
-    const int Ks[] = {2, 4, 8, 16, 32};
-    for (int K : Ks) {
-        if (st != PIC_OK || K == best[3]) continue;
-        double ms;
-        st = trial(best[0], best[1], best[2], K, ms);
-        if (st == PIC_OK && ms < best_ms) { best_ms = ms; best[3] = K; }
+    const int halos[] = {2, 4, 8, 12};
+    const int Ks[] = {4, 8, 16, 32};
+    for (int round = 0; round < 2; ++round) {  // coordinate search, twice
+        for (auto& sh : shapes) consider(sh[0], sh[1], best[2], best[3]);
+        for (int h : halos) consider(best[0], best[1], h, best[3]);
+        for (int K : Ks) consider(best[0], best[1], best[2], K);
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
