@@ -47,6 +47,7 @@ struct pic_ctx {
     FieldDev* dFvac = nullptr;
     double* dbscale = nullptr;
     long long* dcnt = nullptr;
+    long long* prep_ctl = nullptr;  // FP32 step plan the end-of-step kernel refreshes
     long long* dtmp = nullptr;
     double2* tw = nullptr;
     int tw_n = 0;
@@ -374,32 +375,25 @@ pic_status pic_solve_all(pic_ctx* ctx) {
     int n = (int)ctx->in.size();
     hipStream_t s = ctx->stream;
     CK(launch_solve_tab(ctx->dI, ctx->dF, 0, n, ctx->max_nr, ctx->max_nz, ctx->tw, ctx->tw_n, 0,
-                        ctx->dbscale, s));
-    CK(launch_efield_tab(ctx->dI, ctx->dF, 0, n, ctx->max_nodes, s));
+                        ctx->dbscale, true, s));
+    CK(launch_efield_tab(ctx->dI, ctx->dF, 0, n, ctx->max_nodes, true, s));
     return PIC_OK;
 }
 
 pic_status pic_field_stage(pic_ctx* ctx, hipStream_t s) {
     int n = (int)ctx->in.size();
+    // per step: the electrode rows of phi and the static B half of EB keep
+    // the values the initial solve (or pic_set_fields) gave them
     CK(launch_solve_tab(ctx->dI, ctx->dF, 0, n, ctx->max_nr, ctx->max_nz, ctx->tw, ctx->tw_n, 0,
-                        ctx->dbscale, s));
-    CK(launch_efield_tab(ctx->dI, ctx->dF, 0, n, ctx->max_nodes, s));
-    CK(launch_sample_tab(ctx->dI, ctx->dF, 0, n, ctx->dcnt, s));
-    CK(launch_commit(ctx->dI, ctx->dcnt, n, s));
+                        ctx->dbscale, false, s));
+    CK(launch_efield_tab(ctx->dI, ctx->dF, 0, n, ctx->max_nodes, false, s));
+    CK(launch_sample_tab(ctx->dI, ctx->dF, n, ctx->dcnt, ctx->prep_ctl, s));
     return PIC_OK;
 }
 
 FieldDev* pic_field_table(pic_ctx* ctx) { return ctx->dF; }
 
-pic_status pic_sample_all(pic_ctx* ctx) {
-    CK(launch_sample_tab(ctx->dI, ctx->dF, 0, (int)ctx->in.size(), ctx->dcnt, ctx->stream));
-    return PIC_OK;
-}
-
-pic_status pic_commit_all(pic_ctx* ctx) {
-    CK(launch_commit(ctx->dI, ctx->dcnt, (int)ctx->in.size(), ctx->stream));
-    return PIC_OK;
-}
+void pic_set_prep_ctl(pic_ctx* ctx, long long* ctl) { ctx->prep_ctl = ctl; }
 
 // Accessors used by the FP32 form (fp32.hip).
 int pic_n_inst(pic_ctx* ctx) { return (int)ctx->in.size(); }
@@ -628,7 +622,7 @@ extern "C" pic_status pic_init(const pic_run_cfg* run, const pic_instance_cfg* i
     // vacuum potential
     if (st == PIC_OK) {
         e = launch_solve_tab(ctx->dI, ctx->dFvac, 0, n, ctx->max_nr, ctx->max_nz, ctx->tw, ctx->tw_n, 1,
-                             ctx->dbscale, ctx->stream);
+                             ctx->dbscale, true, ctx->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
         if (e != hipSuccess) st = fail(ctx, PIC_EDEVICE, std::string("vacuum solve: ") + hipGetErrorString(e));
     }

@@ -30,8 +30,8 @@ hipEvent_t pic_timing_begin(pic_ctx* ctx, hipEvent_t* stop);
 void pic_set_f32(pic_ctx* ctx, F32State* s);
 F32State* pic_get_f32(pic_ctx* ctx);
 pic_status pic_solve_all(pic_ctx* ctx);
-pic_status pic_sample_all(pic_ctx* ctx);
-pic_status pic_commit_all(pic_ctx* ctx);
+// the FP32 step plan (control words) the end-of-step kernel refreshes
+void pic_set_prep_ctl(pic_ctx* ctx, long long* ctl);
 // FP64 field solve, nodal E, diagnostics sample and step commit on stream s
 pic_status pic_field_stage(pic_ctx* ctx, hipStream_t s);
 pic::FieldDev* pic_field_table(pic_ctx* ctx);

@@ -83,7 +83,6 @@ struct PSet {
 // control block: [1] particles to push this step (sorted + tails), [2] sorted
 // particles over all instances, [3] collision candidates queued this step,
 // [4] queue overflow flag, [5 .. 5+n_inst] prefix of the instances' tail counts
-enum { CTL_TOTAL = 1, CTL_SORTED = 2, CTL_QCOUNT = 3, CTL_QOVER = 4, CTL_TAIL = 5 };
 
 struct KArgs {
     const DevInst* It;
@@ -703,21 +702,11 @@ __global__ void __launch_bounds__(kWG) k_collide(KArgs A, PSet P, int scatter) {
     }
 }
 
-// Work plan for the tail (electrons created since the last sort): one item
-// per C of them per instance; resets the work cursor.
-// Tail counts (electrons created since the last sort) per instance and the
-// step's total; resets the collision-candidate queue.
+// Tail plan of the coming step (see prep_tails) when no field stage ran
+// since the counters changed (after a full sort).
 __global__ void k_prep(long long* ctl, const long long* cnt, int n_inst) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    long long* tb = ctl + CTL_TAIL;
-    tb[0] = 0;
-    ctl[CTL_QCOUNT] = 0;
-    for (int k = 0; k < n_inst; ++k) {
-        const long long* c = cnt + (long long)k * C_NCOUNT;
-        const long long tail = c[C_SLOTS] - c[C_LIVE_SORTED];
-        tb[k + 1] = tb[k] + (tail > 0 ? tail : 0);
-    }
-    ctl[CTL_TOTAL] = ctl[CTL_SORTED] + tb[n_inst];
+    prep_tails(ctl, cnt, n_inst);
 }
 
 __global__ void k_zero_q(const DevInst* It, const FieldDev* Ft) {
@@ -1177,6 +1166,7 @@ pic_status f32_init(pic_ctx* ctx) {
     st = build_store(ctx, S, caps, false);
     if (st != PIC_OK) return st;
     S->ctl = (long long*)pic_dev_alloc(ctx, sizeof(long long) * (CTL_TAIL + n + 1));
+    pic_set_prep_ctl(ctx, S->ctl);
     S->inst_live = (long long*)pic_dev_alloc(ctx, sizeof(long long) * n);
     S->inst_voff = (long long*)pic_dev_alloc(ctx, sizeof(long long) * n);
     CK32(hipHostMalloc((void**)&S->h_cnt, sizeof(long long) * (size_t)n * C_NCOUNT, hipHostMallocDefault));
@@ -1237,8 +1227,6 @@ static pic_status launch_step(pic_ctx* ctx, F32State* S, hipStream_t s, bool tim
     long long max_nodes = 0;
     for (int k = 0; k < n; ++k) max_nodes = std::max<long long>(max_nodes, pic_inst_dev(ctx, k).nodes);
     hipLaunchKernelGGL(k_zero_q, dim3(grid_for(max_nodes, 1024), n), dim3(kWG), 0, s, A.It, A.Ft);
-    CK32(hipGetLastError());
-    hipLaunchKernelGGL(k_prep, dim3(1), dim3(64), 0, s, S->ctl, A.cnt, n);
     CK32(hipGetLastError());
     const unsigned int tgrid = (unsigned int)((S->n_tiles + 255) / 256);
     if (mode & 2) {
@@ -1309,6 +1297,8 @@ static pic_status launch_sort(pic_ctx* ctx, F32State* S, hipStream_t s) {
                        S->tstart[1 - S->cur]);
     CK32(hipGetLastError());
     hipLaunchKernelGGL(k_sort_commit, dim3((n + 63) / 64), dim3(64), 0, s, A.cnt, S->inst_live, n);
+    CK32(hipGetLastError());
+    hipLaunchKernelGGL(k_prep, dim3(1), dim3(64), 0, s, S->ctl, A.cnt, n);
     CK32(hipGetLastError());
     return PIC_OK;
 }

@@ -303,9 +303,10 @@ __global__ void kf_phi_edges(const DevInst* __restrict__ It, const FieldDev* __r
 }
 
 // E = -grad phi at the nodes (central inside, second-order one-sided on the
-// edges); writes FP64 arrays and/or the packed FP32 {Er, Ez, Br, Bz}.
+// edges); writes FP64 arrays and/or the packed FP32 {Er, Ez, Br, Bz} (the
+// static B half only with with_B).
 __global__ void kf_efield(const DevInst* __restrict__ It, const FieldDev* __restrict__ Ft,
-                          int inst_base) {
+                          int inst_base, int with_B) {
     const int inst = inst_base + blockIdx.y;
     const DevInst& I = It[inst];
     const FieldDev& F = Ft[inst];
@@ -325,7 +326,10 @@ __global__ void kf_efield(const DevInst* __restrict__ It, const FieldDev* __rest
         F.Er[n] = -gr;
         F.Ez[n] = -gz;
     }
-    if (F.EB) F.EB[n] = make_float4((float)(-gr), (float)(-gz), (float)F.Br[n], (float)F.Bz[n]);
+    if (F.EB) {
+        if (with_B) F.EB[n] = make_float4((float)(-gr), (float)(-gz), (float)F.Br[n], (float)F.Bz[n]);
+        else *reinterpret_cast<float2*>(&F.EB[n]) = make_float2((float)(-gr), (float)(-gz));
+    }
 }
 
 __global__ void kz_zero(long long* p, long long n) {
@@ -336,9 +340,8 @@ __global__ void kz_zero(long long* p, long long n) {
 
 // Every D steps: spatial-max density into the running time max, the
 // time-average accumulator, and windowed wall currents.
-__global__ void ks_sample(const DevInst* __restrict__ It, const FieldDev* __restrict__ Ft,
-                          int inst_base, long long* cnt_base) {
-    const int inst = inst_base + blockIdx.y;
+__global__ void ks_sample(const DevInst* __restrict__ It, const FieldDev* __restrict__ Ft, long long* cnt_base) {
+    const int inst = blockIdx.y;
     const DevInst& I = It[inst];
     const FieldDev& F = Ft[inst];
     long long* cnt = cnt_base + (long long)inst * C_NCOUNT;
@@ -375,6 +378,21 @@ __global__ void ks_sample(const DevInst* __restrict__ It, const FieldDev* __rest
     }
 }
 
+// End of step, one block: fold each instance's new electrons into its slot
+// count and advance its step counter, then (FP32 form, ctl != NULL) plan
+// the next step.
+__global__ void ks_commit(const DevInst* __restrict__ It, long long* cnt_base, long long* ctl, int n_inst) {
+    for (int k = threadIdx.x; k < n_inst; k += blockDim.x) {
+        long long* c = cnt_base + (long long)k * C_NCOUNT;
+        const long long sl = c[C_SLOTS] + c[C_SPAWN];
+        c[C_SLOTS] = sl < It[k].p_cap ? sl : It[k].p_cap;
+        c[C_SPAWN] = 0;
+        c[C_STEP] += 1;
+    }
+    __syncthreads();
+    if (ctl && threadIdx.x == 0) prep_tails(ctl, cnt_base, n_inst);
+}
+
 }  // namespace
 
 hipError_t launch_zero_i64(long long* p, long long n, hipStream_t s) {
@@ -387,7 +405,7 @@ hipError_t launch_zero_i64(long long* p, long long n, hipStream_t s) {
 
 hipError_t launch_solve_tab(const DevInst* It, const FieldDev* Ft, int inst_base, int n_inst,
                             int max_nr, int max_nz, const double2* tw, int tw_n, int mode,
-                            const double* bscale, hipStream_t s) {
+                            const double* bscale, bool edges, hipStream_t s) {
     if (n_inst <= 0) return hipSuccess;
     size_t lds = sizeof(double2) * 2 * (size_t)max_nz;
     dim3 gdst((unsigned)(max_nr / 2), (unsigned)n_inst);
@@ -408,24 +426,27 @@ hipError_t launch_solve_tab(const DevInst* It, const FieldDev* Ft, int inst_base
     hipLaunchKernelGGL(kf_dst, gdst, dim3(kFftBlock), lds, s, It, Ft, inst_base, tw, tw_n, 2,
                        bscale);
     if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (!edges) return hipSuccess;  // the electrode rows of phi keep their values
     dim3 ged((unsigned)((max_nz + 1 + max_nr + 1 + 255) / 256), (unsigned)n_inst);
     hipLaunchKernelGGL(kf_phi_edges, ged, dim3(256), 0, s, It, Ft, inst_base);
     return hipGetLastError();
 }
 
 hipError_t launch_efield_tab(const DevInst* It, const FieldDev* Ft, int inst_base, int n_inst,
-                             long long max_nodes, hipStream_t s) {
+                             long long max_nodes, bool with_B, hipStream_t s) {
     if (n_inst <= 0) return hipSuccess;
     dim3 g((unsigned)((max_nodes + 255) / 256), (unsigned)n_inst);
-    hipLaunchKernelGGL(kf_efield, g, dim3(256), 0, s, It, Ft, inst_base);
+    hipLaunchKernelGGL(kf_efield, g, dim3(256), 0, s, It, Ft, inst_base, with_B ? 1 : 0);
     return hipGetLastError();
 }
 
-hipError_t launch_sample_tab(const DevInst* It, const FieldDev* Ft, int inst_base, int n_inst,
-                             long long* cnt, hipStream_t s) {
+hipError_t launch_sample_tab(const DevInst* It, const FieldDev* Ft, int n_inst, long long* cnt, long long* ctl,
+                             hipStream_t s) {
     if (n_inst <= 0) return hipSuccess;
-    hipLaunchKernelGGL(ks_sample, dim3(64, (unsigned)n_inst), dim3(256), 0, s, It, Ft, inst_base,
-                       cnt);
+    hipLaunchKernelGGL(ks_sample, dim3(64, (unsigned)n_inst), dim3(256), 0, s, It, Ft, cnt);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(ks_commit, dim3(1), dim3(256), 0, s, It, cnt, ctl, n_inst);
     return hipGetLastError();
 }
 

@@ -262,18 +262,6 @@ __global__ void __launch_bounds__(kBlock) k_deposit64(DevInst I, P64 p, long lon
     }
 }
 
-// End of step: fold this step's new electrons into the slot count, advance
-// the step counter.
-__global__ void k_commit(const DevInst* I, long long* cnt, int n_inst) {
-    int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= n_inst) return;
-    long long* c = cnt + (long long)k * C_NCOUNT;
-    long long s = c[C_SLOTS] + c[C_SPAWN];
-    c[C_SLOTS] = s < I[k].p_cap ? s : I[k].p_cap;
-    c[C_SPAWN] = 0;
-    c[C_STEP] += 1;
-}
-
 // Out-of-place removal of dead slots (order not kept; results do not depend
 // on particle order).
 __global__ void k_compact64(P64 src, P64 dst, const long long* cnt, unsigned long long* out_n) {
@@ -331,10 +319,6 @@ hipError_t launch_deposit64(const DevInst& I, P64 p, long long* Q, long long* cn
     return hipGetLastError();
 }
 
-hipError_t launch_commit(const DevInst* I, long long* cnt, int n_inst, hipStream_t s) {
-    hipLaunchKernelGGL(k_commit, dim3((n_inst + 63) / 64), dim3(64), 0, s, I, cnt, n_inst);
-    return hipGetLastError();
-}
 
 hipError_t launch_compact64(const DevInst& I, P64 src, P64 dst, long long* cnt,
                             long long* tmp_count, long long grid_cap, hipStream_t s) {

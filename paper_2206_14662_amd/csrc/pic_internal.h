@@ -75,6 +75,26 @@ enum Counter {
     C_NCOUNT = 40
 };
 
+// Control words of the batched FP32 step (device array, FP32 form only):
+// particles pushed this step, of which tile-sorted, collision candidates
+// queued, queue overflow flag, then per-instance exclusive prefix of the
+// tail counts (electrons created since the last sort).
+enum { CTL_TOTAL = 1, CTL_SORTED = 2, CTL_QCOUNT = 3, CTL_QOVER = 4, CTL_TAIL = 5 };
+
+// Plan of the coming step from the committed counters: tail prefix, total,
+// an empty collision queue.  One thread.
+__device__ inline void prep_tails(long long* ctl, const long long* cnt, int n_inst) {
+    long long* tb = ctl + CTL_TAIL;
+    tb[0] = 0;
+    ctl[CTL_QCOUNT] = 0;
+    for (int k = 0; k < n_inst; ++k) {
+        const long long* c = cnt + (long long)k * C_NCOUNT;
+        const long long tail = c[C_SLOTS] - c[C_LIVE_SORTED];
+        tb[k + 1] = tb[k] + (tail > 0 ? tail : 0);
+    }
+    ctl[CTL_TOTAL] = ctl[CTL_SORTED] + tb[n_inst];
+}
+
 // ---------------------------------------------------------------------------
 // Philox4x32-10 (Salmon et al., SC'11): ten rounds of two 32x32->64 products
 // of counter words 0 and 2 by fixed multipliers, xor-mixed with the key,
@@ -128,7 +148,6 @@ hipError_t launch_mcc64(const DevInst& I, P64 p, long long* cnt, long long grid_
                         hipStream_t s);
 hipError_t launch_deposit64(const DevInst& I, P64 p, long long* Q, long long* cnt,
                             long long grid_cap, hipStream_t s);
-hipError_t launch_commit(const DevInst* I, long long* cnt, int n_inst, hipStream_t s);
 hipError_t launch_compact64(const DevInst& I, P64 src, P64 dst, long long* cnt,
                             long long* tmp_count, long long grid_cap, hipStream_t s);
 
@@ -165,11 +184,14 @@ hipError_t launch_zero_i64(long long* p, long long n, hipStream_t s);
 // tables: mode 0 from Q (scaled by bscale[inst]), mode 1 from rhs.
 hipError_t launch_solve_tab(const DevInst* It, const FieldDev* Ft, int inst_base, int n_inst,
                             int max_nr, int max_nz, const double2* tw, int tw_n, int mode,
-                            const double* bscale, hipStream_t s);
+                            const double* bscale, bool edges, hipStream_t s);
 hipError_t launch_efield_tab(const DevInst* It, const FieldDev* Ft, int inst_base, int n_inst,
-                             long long max_nodes, hipStream_t s);
-hipError_t launch_sample_tab(const DevInst* It, const FieldDev* Ft, int inst_base, int n_inst,
-                             long long* cnt, hipStream_t s);
+                             long long max_nodes, bool with_B, hipStream_t s);
+// Diagnostics sample (every D steps), then the end of the step: counters
+// committed (slots += spawned, step += 1) and, when ctl is given, the next
+// FP32 step planned.
+hipError_t launch_sample_tab(const DevInst* It, const FieldDev* Ft, int n_inst, long long* cnt, long long* ctl,
+                             hipStream_t s);
 hipError_t set_field_kernel_attrs(int max_nz);
 
 }  // namespace pic
