@@ -594,13 +594,13 @@ extern "C" pic_status pic_init(const pic_run_cfg* run, const pic_instance_cfg* i
         ctx->dcnt = dalloc<long long>(ctx, (long long)n * C_NCOUNT);
         ctx->dtmp = dalloc<long long>(ctx, 64);
         ctx->tw_n = 2 * ctx->max_nz;
-        ctx->tw = dalloc<double2>(ctx, ctx->tw_n / 2);
+        ctx->tw = dalloc<double2>(ctx, ctx->tw_n);
         if (!ctx->dI || !ctx->dF || !ctx->dFvac || !ctx->dbscale || !ctx->dcnt || !ctx->dtmp || !ctx->tw)
             st = fail(ctx, PIC_ENOMEM, "device allocation of tables failed");
     }
     if (st == PIC_OK) {
-        std::vector<double2> tw(ctx->tw_n / 2);
-        for (int k = 0; k < ctx->tw_n / 2; ++k) {
+        std::vector<double2> tw(ctx->tw_n);  // the full circle
+        for (int k = 0; k < ctx->tw_n; ++k) {
             double a = 2.0 * kPi * (double)k / (double)ctx->tw_n;
             tw[k] = make_double2(cos(a), -sin(a));
         }

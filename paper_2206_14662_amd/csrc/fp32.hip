@@ -318,6 +318,7 @@ struct ChunkCtx {
     unsigned long long* s_ctr;
     unsigned int* s_bcnt;
     const unsigned int* s_bbase;
+    unsigned int* s_ccnt;
     PSet out;
     const float4* EB;
     long long* Q;
@@ -458,9 +459,17 @@ __device__ __forceinline__ void push_particle(const KArgs& A, const ChunkCtx& X,
         }
     }
     if (COUNT) {
-        // survivors, by the tile of the new position
-        const int tile = L.tile_off + (ni / A.TR) * L.ntz + (nj / A.TZ);
-        wave_aggregate<false>(alive, tile, [&](int k, unsigned int n) {
+        // survivors, by the tile of the new position: tiles next to the
+        // chunk's own are counted in LDS and flushed once per chunk
+        const int ti = ni / A.TR, tj = nj / A.TZ;
+        const int dr = ti - X.ti_c, dz = tj - X.tj_c;
+        const bool near = X.win && dr >= -1 && dr <= 1 && dz >= -1 && dz <= 1;
+        unsigned int* s_ccnt = X.s_ccnt;
+        wave_aggregate<false>(alive && near, (dr + 1) * 3 + (dz + 1), [&](int k, unsigned int n) {
+            atomicAdd(&s_ccnt[k], n);
+            return 0u;
+        });
+        wave_aggregate<false>(alive && !near, L.tile_off + ti * L.ntz + tj, [&](int k, unsigned int n) {
             atomicAdd(&A.cnt_out[k], n);
             return 0u;
         });
@@ -504,7 +513,7 @@ __global__ void __launch_bounds__(kPWG) __attribute__((amdgpu_waves_per_eu(8, 8)
     lds_u64* sQ = (lds_u64*)(unsigned long long*)(smem + sizeof(float4) * (size_t)A.win_max);
     __shared__ long long s_start;
     __shared__ int s_count, s_inst, s_tr0, s_tz0;
-    __shared__ unsigned int s_bcnt[9], s_bbase[9];
+    __shared__ unsigned int s_bcnt[9], s_bbase[9], s_ccnt[9];
     __shared__ unsigned long long s_ctr[SC_N];
     const int tid = threadIdx.x;
     // Static balance: workgroup w pushes the w-th of gridDim.x equal ranges of
@@ -543,6 +552,7 @@ __global__ void __launch_bounds__(kPWG) __attribute__((amdgpu_waves_per_eu(8, 8)
             }
         }
         if (SCATTER && tid < 9) s_bcnt[tid] = 0u;
+        if (COUNT && tid < 9) s_ccnt[tid] = 0u;
         if (tid < SC_N) s_ctr[tid] = 0ull;
         __syncthreads();
         const int count = __builtin_amdgcn_readfirstlane(s_count);
@@ -608,7 +618,7 @@ __global__ void __launch_bounds__(kPWG) __attribute__((amdgpu_waves_per_eu(8, 8)
         unsigned int c_push = 0;
         ChunkCtx X;
         X.L = local_inst(I);
-        X.sEB = sEB; X.sQ = sQ; X.s_ctr = s_ctr; X.s_bcnt = s_bcnt; X.s_bbase = s_bbase;
+        X.sEB = sEB; X.sQ = sQ; X.s_ctr = s_ctr; X.s_bcnt = s_bcnt; X.s_bbase = s_bbase; X.s_ccnt = s_ccnt;
         X.out = out; X.EB = F.EB; X.Q = F.Q;
         X.inst = inst; X.ti_c = ti_c; X.tj_c = tj_c; X.i0 = i0; X.i1 = i1; X.j0 = j0; X.j1 = j1; X.ww = ww;
         X.win = win; X.step = step;
@@ -646,6 +656,10 @@ __global__ void __launch_bounds__(kPWG) __attribute__((amdgpu_waves_per_eu(8, 8)
         if (tid < SC_N) {
             const unsigned long long v = s_ctr[tid];
             if (v) atomicAdd((unsigned long long*)&cnt[kCounterOf[tid]], v);
+        }
+        if (COUNT && win && tid < 9) {
+            const unsigned int v = s_ccnt[tid];
+            if (v) atomicAdd(&A.cnt_out[I.tile_off + (ti_c + tid / 3 - 1) * I.ntz + (tj_c + tid % 3 - 1)], v);
         }
         __syncthreads();
         if (win) {

@@ -12,36 +12,103 @@
 namespace pic {
 namespace {
 
-constexpr int kFftBlock = 256;
+// The FFT block has N/8 threads for the largest N = 2 nz of the batch (at
+// least 64): every thread holds 8 points per pass.
+constexpr int kFftMaxBlock = 1024;
+inline int fft_block(int max_nz) { return 2 * max_nz / 8 > 64 ? 2 * max_nz / 8 : 64; }
 
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
     return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ double2 mul_mi(double2 a) { return make_double2(a.y, -a.x); }  // times -i
 
-// Radix-2 decimation-in-time FFT of N = 2^logN points already stored in
-// bit-reversed order in LDS.  tw[k] = exp(-2 pi i k / tw_n), k < tw_n / 2.
-__device__ void fft_lds(double2* y, int N, int logN, const double2* __restrict__ tw, int tw_n) {
-    for (int s = 1; s <= logN; ++s) {
-        const int half = 1 << (s - 1);
-        const int tstride = tw_n >> s;
-        for (int t = threadIdx.x; t < (N >> 1); t += blockDim.x) {
-            int pos = t & (half - 1);
-            int i0 = ((t >> (s - 1)) << s) + pos;
-            int i1 = i0 + half;
-            double2 v = cmul(y[i1], tw[pos * tstride]);
-            double2 u = y[i0];
-            y[i0] = make_double2(u.x + v.x, u.y + v.y);
-            y[i1] = make_double2(u.x - v.x, u.y - v.y);
+// Forward DFTs of 2, 4 and 8 points in registers (natural order in and out,
+// kernel exp(-2 pi i r m / R)).
+__device__ __forceinline__ void dft2(double2* v) {
+    const double2 a = v[0], b = v[1];
+    v[0] = cadd(a, b);
+    v[1] = csub(a, b);
+}
+__device__ __forceinline__ void dft4(double2& a0, double2& a1, double2& a2, double2& a3) {
+    const double2 t0 = cadd(a0, a2), t1 = csub(a0, a2), t2 = cadd(a1, a3), t3 = mul_mi(csub(a1, a3));
+    a0 = cadd(t0, t2);
+    a2 = csub(t0, t2);
+    a1 = cadd(t1, t3);
+    a3 = csub(t1, t3);
+}
+__device__ __forceinline__ void dft8(double2* v) {
+    double2 e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6];
+    double2 o0 = v[1], o1 = v[3], o2 = v[5], o3 = v[7];
+    dft4(e0, e1, e2, e3);
+    dft4(o0, o1, o2, o3);
+    const double c = 0.70710678118654752440;  // sqrt(1/2)
+    o1 = make_double2(c * (o1.x + o1.y), c * (o1.y - o1.x));    // times (1 - i)/sqrt 2
+    o2 = mul_mi(o2);                                            // times -i
+    o3 = make_double2(c * (o3.y - o3.x), -c * (o3.x + o3.y));   // times (-1 - i)/sqrt 2
+    v[0] = cadd(e0, o0); v[4] = csub(e0, o0);
+    v[1] = cadd(e1, o1); v[5] = csub(e1, o1);
+    v[2] = cadd(e2, o2); v[6] = csub(e2, o2);
+    v[3] = cadd(e3, o3); v[7] = csub(e3, o3);
+}
+
+// One Stockham pass of radix R over N points in LDS (in place: every
+// thread reads its 8 / R butterflies' inputs, barrier, writes).  Butterfly
+// j of span Ns reads y[j + r N/R], twiddles input r by exp(-2 pi i r k /
+// (Ns R)) with k = j mod Ns, and writes output m to y[(j/Ns) Ns R + k + m Ns].
+// tw[t] = exp(-2 pi i t / tw_n) over the full circle, tw_n a multiple of N.
+template <int R>
+__device__ __forceinline__ void fft_pass(double2* y, int N, int Ns, const double2* __restrict__ tw, int tw_n) {
+    constexpr int PER = 8 / R;
+    const int nb = N / R;
+    double2 v[8];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int j = threadIdx.x + q * blockDim.x;
+        if (j < nb) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[q * R + r] = y[j + r * nb];
         }
-        __syncthreads();
     }
+    __syncthreads();
+    const int tscale = (tw_n / N) * (N / (Ns * R));
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int j = threadIdx.x + q * blockDim.x;
+        if (j < nb) {
+            const int k = j & (Ns - 1);
+            double2* w = v + q * R;
+#pragma unroll
+            for (int r = 1; r < R; ++r) w[r] = cmul(w[r], tw[r * k * tscale]);
+            if (R == 8) dft8(w);
+            else if (R == 4) dft4(w[0], w[1], w[2], w[3]);
+            else dft2(w);
+            const int d = (j - k) * R + k;
+#pragma unroll
+            for (int m = 0; m < R; ++m) y[d + m * Ns] = w[m];
+        }
+    }
+    __syncthreads();
+}
+
+// Forward FFT of N = 2^n points (N >= 2) in natural order in LDS, radix 8
+// passes then one of radix 4 or 2.
+__device__ void fft_lds(double2* y, int N, const double2* __restrict__ tw, int tw_n) {
+    int Ns = 1;
+    while (N / Ns >= 8) {
+        fft_pass<8>(y, N, Ns, tw, tw_n);
+        Ns *= 8;
+    }
+    if (N / Ns == 4) fft_pass<4>(y, N, Ns, tw, tw_n);
+    else if (N / Ns == 2) fft_pass<2>(y, N, Ns, tw, tw_n);
 }
 
 // Sine transform of interior rows, two per block.
 //   mode 0: rows of Q * bscale            -> rhs (modes)
 //   mode 1: rows of rhs (already scaled)  -> rhs (modes)
 //   mode 2: rows of rhs (solved modes)    -> phi = phi_vac + (2/nz) DST
-__global__ void __launch_bounds__(kFftBlock) kf_dst(const DevInst* __restrict__ It,
+__global__ void __launch_bounds__(kFftMaxBlock) kf_dst(const DevInst* __restrict__ It,
                                                     const FieldDev* __restrict__ Ft, int inst_base,
                                                     const double2* __restrict__ tw, int tw_n,
                                                     int mode, const double* __restrict__ bscale) {
@@ -54,7 +121,6 @@ __global__ void __launch_bounds__(kFftBlock) kf_dst(const DevInst* __restrict__ 
     if (I.frozen || iA > I.nr - 1) return;
     const bool hasB = iB <= I.nr - 1;
     const int N = 2 * nz;
-    const int logN = 31 - __clz(N);
     const double bs = mode == 0 ? bscale[inst] : 1.0;
     for (int j = threadIdx.x; j < N; j += blockDim.x) {
         int jj = j <= nz ? j : N - j;
@@ -69,11 +135,10 @@ __global__ void __launch_bounds__(kFftBlock) kf_dst(const DevInst* __restrict__ 
                 vb = hasB ? F.rhs[(long long)iB * W + jj] : 0.0;
             }
         }
-        int rj = (int)(__brev((unsigned int)j) >> (32 - logN));
-        y[rj] = make_double2(sg * va, sg * vb);
+        y[j] = make_double2(sg * va, sg * vb);
     }
     __syncthreads();
-    fft_lds(y, N, logN, tw, tw_n);
+    fft_lds(y, N, tw, tw_n);
     // y = -2i X_A + 2 X_B for odd real inputs A (real part) and B (imag part)
     const double sc = 2.0 / (double)nz;
     for (int k = threadIdx.x + 1; k <= nz - 1; k += blockDim.x) {
@@ -409,8 +474,8 @@ hipError_t launch_solve_tab(const DevInst* It, const FieldDev* Ft, int inst_base
     if (n_inst <= 0) return hipSuccess;
     size_t lds = sizeof(double2) * 2 * (size_t)max_nz;
     dim3 gdst((unsigned)(max_nr / 2), (unsigned)n_inst);
-    hipLaunchKernelGGL(kf_dst, gdst, dim3(kFftBlock), lds, s, It, Ft, inst_base, tw, tw_n, mode,
-                       bscale);
+    const dim3 fb((unsigned)fft_block(max_nz));
+    hipLaunchKernelGGL(kf_dst, gdst, fb, lds, s, It, Ft, inst_base, tw, tw_n, mode, bscale);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     dim3 gth((unsigned)((max_nz - 1 + 63) / 64), (unsigned)n_inst);
@@ -423,8 +488,7 @@ hipError_t launch_solve_tab(const DevInst* It, const FieldDev* Ft, int inst_base
         hipLaunchKernelGGL(kf_thomas, gth, dim3(64, kThomasSeg), 0, s, It, Ft, inst_base);
     }
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(kf_dst, gdst, dim3(kFftBlock), lds, s, It, Ft, inst_base, tw, tw_n, 2,
-                       bscale);
+    hipLaunchKernelGGL(kf_dst, gdst, fb, lds, s, It, Ft, inst_base, tw, tw_n, 2, bscale);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (!edges) return hipSuccess;  // the electrode rows of phi keep their values
     dim3 ged((unsigned)((max_nz + 1 + max_nr + 1 + 255) / 256), (unsigned)n_inst);
