@@ -29,6 +29,7 @@ class OrcCfg(C.Structure):
         ("weight", C.c_double), ("load_mode", C.c_int),
         ("seed", C.c_uint64), ("dt", C.c_double),
         ("fx_shift", C.c_int), ("diag_interval", C.c_int), ("collisions", C.c_int),
+        ("src_rate", C.c_double), ("src_T_eV", C.c_double),
     ]
 
 
@@ -48,6 +49,7 @@ class OrcDiag(C.Structure):
         ("total_Q", C.c_int64), ("n_samples", C.c_int64),
         ("I_wall", C.c_double * 4), ("peak_density", C.c_double),
         ("peak_I_outer", C.c_double), ("peak_I_inner", C.c_double),
+        ("n_source", C.c_int64),
     ]
 
 

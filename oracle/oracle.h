@@ -56,6 +56,8 @@ typedef struct {
     int fx_shift;              /* S: fixed-point charge scale 2^S               */
     int diag_interval;         /* D: steps per density / current sample         */
     int collisions;            /* 0 switches the MCC stage off                  */
+    double src_rate;           /* seed source: macro-electrons per step (0 off)  */
+    double src_T_eV;           /* its Maxwellian temperature (0: T_init_eV)     */
 } orc_cfg;
 
 /* Host-derived constants (all FP64). */
@@ -84,6 +86,7 @@ typedef struct {
     double I_wall[4];          /* last window currents (A), electron flux >0    */
     double peak_density;       /* time max of the spatial max (m^-3)            */
     double peak_I_outer, peak_I_inner;
+    int64_t n_source;          /* electrons created by the seed source          */
 } orc_diag;
 
 typedef struct orc_sim orc_sim;

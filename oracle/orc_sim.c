@@ -9,6 +9,7 @@
  *      move to x^{n+1} in the local Cartesian frame and rotate back to (r,z),
  *      remove it if it reached an electrode or an end;
  *   2. null-collision test for every survivor, elastic or ionising event;
+ *   2b. the volumetric seed source adds its electrons (when switched on);
  *   3. deposit survivors and newly created electrons at x^{n+1};
  *   4. field solve for E^{n+1} (unless the field is frozen);
  *   5. every D steps: density and current samples.
@@ -392,6 +393,48 @@ static void sample_diag(orc_sim* s) {
     if (s->dg.I_wall[0] > s->dg.peak_I_inner) s->dg.peak_I_inner = s->dg.I_wall[0];
 }
 
+/*
+ * Volumetric seed source (Sec. II.A: a weak source over the whole domain,
+ * uniform in space, Maxwellian in velocity).  With R = src_rate electrons per
+ * step, step n creates floor((n+1) R) - floor(n R) of them, so that
+ * floor(n R) exist after n steps; the j-th of step n has key
+ * 2^62 + floor(n R) + j.  Each draws three Philox blocks of its key at the
+ * step word 0xFFFFFFFE: r uniform in volume over (a, b), z uniform over
+ * (0, L), Box-Muller velocity components at src_T_eV (T_init_eV if 0).
+ */
+static void seed_source(orc_sim* s) {
+    const orc_cfg* c = &s->c;
+    if (!(c->src_rate > 0.0)) return;
+    const double n0 = floor((double)s->step * c->src_rate);
+    const double n1 = floor((double)(s->step + 1) * c->src_rate);
+    const int64_t count = (int64_t)(n1 - n0), first = (int64_t)n0;
+    if (count <= 0) return;
+    const double T = c->src_T_eV > 0.0 ? c->src_T_eV : c->T_init_eV;
+    const double sv = sqrt((T * ORC_E) / 9.1093837015e-31);
+    sim_reserve(s, s->n + count);
+    for (int64_t j = 0; j < count; ++j) {
+        const uint64_t key = (UINT64_C(1) << 62) + (uint64_t)(first + j);
+        uint32_t b0[4], b1[4], b2[4];
+        philox_blk(s, key, 0xFFFFFFFEu, 0u, b0);
+        philox_blk(s, key, 0xFFFFFFFEu, 1u, b1);
+        philox_blk(s, key, 0xFFFFFFFEu, 2u, b2);
+        const double ur = orc_u52(b0[0], b0[1]), uz = orc_u52(b0[2], b0[3]);
+        const double u1 = orc_u52(b1[0], b1[1]), u2 = orc_u52(b1[2], b1[3]);
+        const double u3 = orc_u52(b2[0], b2[1]), u4 = orc_u52(b2[2], b2[3]);
+        const double m1 = sqrt(-2.0 * log(u1)), m3 = sqrt(-2.0 * log(u3));
+        const int64_t q = s->n + j;
+        s->r[q] = sqrt(c->a * c->a + ur * (c->b * c->b - c->a * c->a));
+        s->z[q] = uz * c->L;
+        s->vr[q] = sv * (m1 * cos((2.0 * M_PI) * u2));
+        s->vt[q] = sv * (m1 * sin((2.0 * M_PI) * u2));
+        s->vz[q] = sv * (m3 * cos((2.0 * M_PI) * u4));
+        s->w[q] = c->weight;
+        s->key[q] = key;
+    }
+    s->n += count;
+    s->dg.n_source += count;
+}
+
 int orc_step(orc_sim* s, int n_steps) {
     const double vcap2 = s->d.v_cap * s->d.v_cap;
     for (int it = 0; it < n_steps; ++it) {
@@ -467,6 +510,7 @@ int orc_step(orc_sim* s, int n_steps) {
             s->n = q;
             free(kids); free(nk); free(ck);
         }
+        seed_source(s);
         /* 3. deposit, 4. field */
         deposit_all(s);
         solve_fields(s);

@@ -34,6 +34,7 @@ _BASE = dict(
     n_init=50000, r_lo=3.0e-3, r_hi=7.0e-3, z_lo=20.0e-3, z_hi=40.0e-3,
     T_init_eV=1.0, weight=1.0e5, load_mode=1,
     seed=0, dt=1.0e-12, fx_shift=0, diag_interval=10, collisions=1,
+    src_rate=0.0, src_T_eV=0.0,
 )
 
 # Total seed charge of the small case (50k x 1e5 electrons) is kept for the

@@ -552,3 +552,52 @@ def test_absorbing_walls_and_current():
     assert dg["n_absorbed"] == [0, n, 0, 0] and dg["n_live"] == 0
     assert dg["I_wall"][1] == pytest.approx(n * c["weight"] * E / (50 * c["dt"]), rel=1e-12)
     assert dg["peak_I_outer"] == dg["I_wall"][1]
+
+
+# --------------------------------------------------------------------------
+# Volumetric seed source (Sec. II.A): uniform in space, Maxwellian in velocity
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("rate", [0.3, 37.5, 1000.0])
+def test_seed_source_count_and_keys(rate):
+    c = pi.coax64(n_init=0, src_rate=rate, collisions=0, p_mbar=1e-12)
+    s = oracle.Sim(c, capacity=4096)
+    s.load()
+    for n in (1, 7, 20):
+        s.step(n - s.diag()["step"])
+        d = s.diag()
+        assert d["n_source"] == math.floor(n * rate)
+    st = s.get_particles()
+    d = s.diag()
+    # survivors carry distinct keys 2^62 + i, i < floor(20 R); the rest reached a wall
+    keys = np.sort(st["key"])
+    want = np.uint64(1 << 62) + np.arange(math.floor(20 * rate), dtype=np.uint64)
+    assert len(np.unique(keys)) == len(keys) and np.all(np.isin(keys, want))
+    assert len(keys) + sum(d["n_absorbed"]) == len(want)
+    W = round(c["weight"] * 2.0 ** s.S)
+    assert d["total_Q"] == len(keys) * W
+
+
+def test_seed_source_uniform_in_volume_and_maxwellian():
+    T = 3.0
+    c = pi.coax64(n_init=0, src_rate=40000.0, src_T_eV=T, collisions=0, p_mbar=1e-12)
+    s = oracle.Sim(c, capacity=65536)
+    s.load()
+    s.step(1)  # created after the push of step 0: still at their drawn state
+    st = s.get_particles()
+    a, b, L = c["a"], c["b"], c["L"]
+    assert len(st["r"]) == 40000
+    assert np.all((st["r"] > a) & (st["r"] <= b) & (st["z"] > 0) & (st["z"] < L))
+    u = (st["r"] ** 2 - a * a) / (b * b - a * a)
+    assert stats.kstest(u, "uniform").pvalue > 1e-4
+    assert stats.kstest(st["z"] / L, "uniform").pvalue > 1e-4
+    sv = math.sqrt(T * E / ME)
+    for k in ("vr", "vt", "vz"):
+        assert stats.kstest(st[k] / sv, "norm").pvalue > 1e-4, k
+    # src_T_eV = 0 takes the load temperature
+    c0 = dict(c, src_T_eV=0.0, T_init_eV=0.5)
+    s0 = oracle.Sim(c0, capacity=65536)
+    s0.load()
+    s0.step(1)
+    v = s0.get_particles()["vz"]
+    assert np.std(v) == pytest.approx(math.sqrt(0.5 * E / ME), rel=0.02)
