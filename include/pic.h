@@ -89,6 +89,12 @@ typedef struct {
     int fx_shift;              /* S of the 2^S fixed-point charge; 0 = automatic */
     int diag_interval;         /* D: steps between density/current samples      */
     int collisions;            /* 0 switches the MCC stage off                   */
+    /* Volumetric seed source (Sec. II.A): a weak source over the whole domain,
+     * uniform in volume over a<r<b, 0<z<L, Maxwellian in velocity.  Step n
+     * creates floor((n+1) src_rate) - floor(n src_rate) electrons after the
+     * collisions (keys 2^62 + running index, Philox step word 0xFFFFFFFE). */
+    double src_rate;           /* macro-electrons per step, >= 0 (0: off)        */
+    double src_T_eV;           /* source temperature (eV); 0 takes T_init_eV     */
 } pic_instance_cfg;
 
 typedef struct {
@@ -126,6 +132,7 @@ typedef struct {
     double peak_I_outer, peak_I_inner; /* max over windows of I_wall[1], I_wall[0] */
     long long particle_steps;  /* live macro-electrons pushed, summed over steps */
     long long n_far_deposit;   /* FP32 form: deposits that missed the LDS window */
+    long long n_source;        /* electrons created by the seed source           */
 } pic_diag_t;
 
 /* Host-derived constants of an instance (FP64); see pic_derive. */

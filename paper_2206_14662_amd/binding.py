@@ -49,6 +49,7 @@ class pic_instance_cfg(C.Structure):
         ("weight", C.c_double), ("load_mode", C.c_int),
         ("seed", C.c_ulonglong), ("dt", C.c_double),
         ("fx_shift", C.c_int), ("diag_interval", C.c_int), ("collisions", C.c_int),
+        ("src_rate", C.c_double), ("src_T_eV", C.c_double),
     ]
 
 
@@ -72,6 +73,7 @@ class pic_diag_t(C.Structure):
         ("peak_I_outer", C.c_double), ("peak_I_inner", C.c_double),
         ("particle_steps", C.c_longlong),
         ("n_far_deposit", C.c_longlong),
+        ("n_source", C.c_longlong),
     ]
 
 

@@ -178,6 +178,8 @@ static std::string validate(const pic_instance_cfg& c) {
         if (!(c.r_lo >= c.a && c.r_hi <= c.b && c.r_lo < c.r_hi)) return "load box must satisfy a <= r_lo < r_hi <= b";
         if (!(c.z_lo >= 0.0 && c.z_hi <= c.L && c.z_lo < c.z_hi)) return "load box must satisfy 0 <= z_lo < z_hi <= L";
         if (!(c.T_init_eV >= 0.0) || !(c.weight > 0.0)) return "need T_init_eV >= 0 and weight > 0";
+        if (!(c.src_rate >= 0.0 && c.src_rate <= 1e9) || !(c.src_T_eV >= 0.0))
+            return "need 0 <= src_rate <= 1e9 per step and src_T_eV >= 0";
     }
     if (c.load_mode != 0 && c.load_mode != 1) return "load_mode must be 0 or 1";
     if (c.end_mode != 0 && c.end_mode != 1) return "end_mode must be 0 or 1";
@@ -338,6 +340,9 @@ static void fill_devinst(Inst& in) {
     I.two_e_over_me_f = (float)d.two_e_over_me; I.mass_ratio2_f = (float)d.mass_ratio2;
     I.v_cap2_f = (float)(d.v_cap * d.v_cap);
     I.diag_D = c.diag_interval > 0 ? c.diag_interval : 1;
+    I.src_rate = c.src_rate;
+    I.src_sv = sqrt(((c.src_T_eV > 0.0 ? c.src_T_eV : c.T_init_eV) * kE) / kMe);
+    I.weight = c.weight;
 }
 
 static pic_status upload_tables(pic_ctx* ctx) {
@@ -780,9 +785,11 @@ static pic_status step64(pic_ctx* ctx, int n_steps) {
                 if (st != PIC_OK) return st;
                 slots -= dead;
             }
-            // still 3/4 full once the dead are gone: twice the used slots
-            if (slots > (cap * 3) / 4) {
-                st = grow64(ctx, (int)k, std::max<long long>(2 * slots, cap + cap / 2));
+            // still 3/4 full once the dead are gone (counting what the seed
+            // source adds before the next check): twice that
+            const long long need = slots + (long long)ceil(ctx->in[k].c.src_rate) * check_every;
+            if (need > (cap * 3) / 4) {
+                st = grow64(ctx, (int)k, std::max<long long>(2 * need, cap + cap / 2));
                 if (st != PIC_OK) return st;
             }
         }
@@ -800,6 +807,7 @@ static pic_status step64(pic_ctx* ctx, int n_steps) {
                 CK(launch_push64(in.I, p, in.Er, in.Ez, in.Br, in.Bz, in.cnt, in.cap, s));
                 if (ctx->timing) CK(hipEventRecord(e1, s));
                 CK(launch_mcc64(in.I, p, in.cnt, in.cap, s));
+                if (in.c.src_rate > 0.0) CK(launch_source64(in.I, p, in.cnt, s));
                 CK(launch_deposit64(in.I, p, in.Q, in.cnt, in.cap, s));
             }
             st = pic_field_stage(ctx, s);
@@ -1039,6 +1047,7 @@ extern "C" pic_status pic_diag(pic_ctx* ctx, int k, pic_diag_t* out, double* den
     out->n_samples = c[C_NSAMP];
     out->particle_steps = c[C_PSTEPS];
     out->n_far_deposit = c[C_FARDEP];
+    out->n_source = c[C_SOURCE];
     out->S = in.S;
     if (ctx->mode == PIC_MODE_FP64_PLAIN) out->n_live = c[C_SLOTS] - c[C_DEAD];
     else out->n_live = f32_live_count(ctx, k, c);

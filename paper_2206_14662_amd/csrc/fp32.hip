@@ -716,6 +716,53 @@ __global__ void __launch_bounds__(kWG) k_collide(KArgs A, PSet P, int scatter) {
     }
 }
 
+// Volumetric seed source (Sec. II.A): this step's new electrons of every
+// instance (blockIdx.y), appended to the tail like the ionisation products
+// (after the sorted block of the output store in a sorting step), deposited
+// with global atomics and, in a counting step, counted in their tiles.
+__global__ void __launch_bounds__(kWG) k_source32(KArgs A, PSet P, int scatter) {
+    const int inst = blockIdx.y;
+    const DevInst& I = A.It[inst];
+    if (!(I.src_rate > 0.0)) return;
+    long long* cnt = A.cnt + (long long)inst * C_NCOUNT;
+    long long first, count;
+    source_count(I, cnt[C_STEP], first, count);
+    const long long base = scatter ? A.new_base[inst] : cnt[C_SLOTS];
+    unsigned long long* Qg = (unsigned long long*)A.Ft[inst].Q;
+    const float wf = (float)I.weight;
+    for (long long j = (long long)blockIdx.x * kWG + threadIdx.x; j < count; j += (long long)gridDim.x * kWG) {
+        unsigned long long key;
+        double rd, zd, vr, vt, vz;
+        source_draw(I, first + j, key, rd, zd, vr, vt, vz);
+        const long long rel = base + (long long)atomicAdd((unsigned long long*)&cnt[C_SPAWN], 1ull);
+        if (rel >= I.p_cap) {
+            atomicAdd((unsigned long long*)&cnt[C_DROPPED], 1ull);
+            continue;
+        }
+        const long long d = I.p_off + rel;
+        const float r = (float)rd, z = (float)zd;
+        P.r[d] = r;
+        P.z[d] = z;
+        P.vr[d] = (float)vr;
+        P.vt[d] = (float)vt;
+        P.vz[d] = (float)vz;
+        P.w[d] = wf;
+        P.key[d] = key;
+        int i, jj;
+        float fr, fz;
+        cell_of(I, r, z, i, jj, fr, fz);
+        long long q00, q10, q01, q11;
+        node_charges(wf, (float)I.two_S, fr, fz, q00, q10, q01, q11);
+        const long long n00 = (long long)i * I.W + jj;
+        atomicAdd(&Qg[n00], (unsigned long long)q00);
+        atomicAdd(&Qg[n00 + I.W], (unsigned long long)q10);
+        atomicAdd(&Qg[n00 + 1], (unsigned long long)q01);
+        atomicAdd(&Qg[n00 + I.W + 1], (unsigned long long)q11);
+        if (A.cnt_out) atomicAdd(&A.cnt_out[I.tile_off + (i / A.TR) * I.ntz + (jj / A.TZ)], 1u);
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0 && count > 0) atomicAdd((unsigned long long*)&cnt[C_SOURCE], count);
+}
+
 // Tail plan of the coming step (see prep_tails) when no field stage ran
 // since the counters changed (after a full sort).
 __global__ void k_prep(long long* ctl, const long long* cnt, int n_inst) {
@@ -1277,6 +1324,13 @@ static pic_status launch_step(pic_ctx* ctx, F32State* S, hipStream_t s, bool tim
     hipLaunchKernelGGL(k_collide, dim3(64), dim3(kWG), 0, s, A, (mode & 2) ? S->set[1 - S->cur] : S->set[S->cur],
                        (mode & 2) ? 1 : 0);
     CK32(hipGetLastError());
+    double src_max = 0.0;
+    for (int k = 0; k < n; ++k) src_max = std::max(src_max, pic_inst_dev(ctx, k).src_rate);
+    if (src_max > 0.0) {
+        hipLaunchKernelGGL(k_source32, dim3(grid_for((long long)ceil(src_max) + 1, 256), n), dim3(kWG), 0, s, A,
+                           (mode & 2) ? S->set[1 - S->cur] : S->set[S->cur], (mode & 2) ? 1 : 0);
+        CK32(hipGetLastError());
+    }
     if (mode & 2) {
         hipLaunchKernelGGL(k_sort_plan2, dim3(1), dim3(64), 0, s, S->inst_live, S->inst_voff, S->ctl, S->vtile, n,
                            S->n_tiles);
@@ -1486,7 +1540,9 @@ static pic_status capacity_check(pic_ctx* ctx, F32State* S, hipStream_t work) {
             const long long cap = pic_inst_dev(ctx, k).p_cap;
             const long long used = c[C_SLOTS];
             const long long rise = S->prev_used[k] >= 0 ? std::max(0ll, used - S->prev_used[k]) : 0;
-            const long long proj = used + 2 * rise;
+            // the lag spans up to two check periods; the seed source adds at a known rate
+            const long long proj =
+                used + 2 * std::max(rise, (long long)ceil(pic_inst_dev(ctx, k).src_rate) * kCheckEvery);
             S->prev_used[k] = used;
             caps[k] = cap;
             if (proj > cap - cap / 4) {

@@ -235,6 +235,33 @@ __global__ void __launch_bounds__(kBlock) k_mcc64(DevInst I, P64 p, long long* c
     if (n_cap) atomicAdd((unsigned long long*)&cnt[C_CAPOVER], n_cap);
 }
 
+// Volumetric seed source (Sec. II.A): this step's new electrons, appended
+// after the slots like the ionisation products; deposited with them.
+__global__ void __launch_bounds__(kBlock) k_source64(DevInst I, P64 p, long long* cnt) {
+    long long first, count;
+    source_count(I, cnt[C_STEP], first, count);
+    const long long n = cnt[C_SLOTS];
+    for (long long j = (long long)blockIdx.x * blockDim.x + threadIdx.x; j < count;
+         j += (long long)gridDim.x * blockDim.x) {
+        unsigned long long key;
+        double r, z, vr, vt, vz;
+        source_draw(I, first + j, key, r, z, vr, vt, vz);
+        const long long slot = n + (long long)atomicAdd((unsigned long long*)&cnt[C_SPAWN], 1ull);
+        if (slot >= I.p_cap) {
+            atomicAdd((unsigned long long*)&cnt[C_DROPPED], 1ull);
+            continue;
+        }
+        p.r[slot] = r;
+        p.z[slot] = z;
+        p.vr[slot] = vr;
+        p.vt[slot] = vt;
+        p.vz[slot] = vz;
+        p.w[slot] = I.weight;
+        p.key[slot] = key;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0 && count > 0) atomicAdd((unsigned long long*)&cnt[C_SOURCE], count);
+}
+
 // Fixed-point deposit: node charges rint(W w_k) for three nodes, the fourth
 // takes the remainder so every particle adds exactly W.
 __global__ void __launch_bounds__(kBlock) k_deposit64(DevInst I, P64 p, long long* __restrict__ Q,
@@ -310,6 +337,12 @@ hipError_t launch_push64(const DevInst& I, P64 p, const double* Er, const double
 hipError_t launch_mcc64(const DevInst& I, P64 p, long long* cnt, long long grid_cap,
                         hipStream_t s) {
     hipLaunchKernelGGL(k_mcc64, dim3(grid_for(grid_cap)), dim3(kBlock), 0, s, I, p, cnt);
+    return hipGetLastError();
+}
+
+hipError_t launch_source64(const DevInst& I, P64 p, long long* cnt, hipStream_t s) {
+    const long long most = (long long)ceil(I.src_rate) + 1;
+    hipLaunchKernelGGL(k_source64, dim3(grid_for(most)), dim3(kBlock), 0, s, I, p, cnt);
     return hipGetLastError();
 }
 

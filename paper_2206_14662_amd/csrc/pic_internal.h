@@ -47,6 +47,10 @@ struct DevInst {
     int ntr, ntz;                   // tiles in r and z
     int tile_off;                   // first global tile id of this instance
     int diag_D;                     // steps between diagnostic samples
+    // volumetric seed source
+    double src_rate;                // macro-electrons per step (0: off)
+    double src_sv;                  // its thermal speed sqrt(T e / m)
+    double weight;                  // electrons per macro-electron of new source electrons
 };
 
 // Device counter block per instance (long long entries).
@@ -72,6 +76,7 @@ enum Counter {
     C_LIVE_SORTED,           // live particles in the sorted region (FP32 form)
     C_PSTEPS,                // particle-steps pushed so far
     C_FARDEP,                // deposits outside the LDS window (FP32 form)
+    C_SOURCE,                // electrons created by the seed source
     C_NCOUNT = 40
 };
 
@@ -120,6 +125,38 @@ __device__ __forceinline__ double u52(unsigned int hi, unsigned int lo) {
     unsigned long long x = ((unsigned long long)hi << 32) | (unsigned long long)lo;
     return ((double)(x >> 12) + 0.5) * 0x1p-52;
 }
+
+// Seed source of step `step`: how many electrons it creates and the running
+// index of the first (floor((n+1) R) - floor(n R) and floor(n R), R per step).
+__device__ __forceinline__ void source_count(const DevInst& I, long long step, long long& first, long long& count) {
+#pragma clang fp contract(off)
+    const double n0 = floor((double)step * I.src_rate);
+    const double n1 = floor((double)(step + 1) * I.src_rate);
+    first = (long long)n0;
+    count = (long long)(n1 - n0);
+}
+
+// The state of the seed-source electron with running index idx: key
+// 2^62 + idx, three Philox blocks at step word 0xFFFFFFFE, r uniform in volume
+// over (a, b), z uniform over (0, L), Box-Muller velocities (FP64).
+__device__ inline void source_draw(const DevInst& I, long long idx, unsigned long long& key, double& r, double& z,
+                                   double& vr, double& vt, double& vz) {
+#pragma clang fp contract(off)
+    key = (1ull << 62) + (unsigned long long)idx;
+    const uint4 c0 = make_uint4((unsigned int)key, (unsigned int)(key >> 32), 0xFFFFFFFEu, 0u);
+    const uint4 b0 = philox4x32_10(c0, I.seed_lo, I.seed_hi);
+    const uint4 b1 = philox4x32_10(make_uint4(c0.x, c0.y, c0.z, 1u), I.seed_lo, I.seed_hi);
+    const uint4 b2 = philox4x32_10(make_uint4(c0.x, c0.y, c0.z, 2u), I.seed_lo, I.seed_hi);
+    const double ur = u52(b0.x, b0.y), uz = u52(b0.z, b0.w);
+    const double u1 = u52(b1.x, b1.y), u2 = u52(b1.z, b1.w);
+    const double u3 = u52(b2.x, b2.y), u4 = u52(b2.z, b2.w);
+    const double m1 = sqrt(-2.0 * log(u1)), m3 = sqrt(-2.0 * log(u3));
+    r = sqrt(I.a * I.a + ur * (I.b * I.b - I.a * I.a));
+    z = uz * I.L;
+    vr = I.src_sv * (m1 * cos((2.0 * kPi) * u2));
+    vt = I.src_sv * (m1 * sin((2.0 * kPi) * u2));
+    vz = I.src_sv * (m3 * cos((2.0 * kPi) * u4));
+}
 // Open-interval uniform from the top 23 bits of a word (exact in FP32).
 __device__ __forceinline__ float u23(unsigned int w) {
     return ((float)(w >> 9) + 0.5f) * 0x1p-23f;
@@ -144,6 +181,8 @@ hipError_t launch_load64(const DevInst& I, const pic_instance_cfg& c, P64 p, lon
 hipError_t launch_push64(const DevInst& I, P64 p, const double* Er, const double* Ez,
                          const double* Br, const double* Bz, long long* cnt, long long grid_cap,
                          hipStream_t s);
+// Seed-source electrons of the step appended after the slots (FP64 form).
+hipError_t launch_source64(const DevInst& I, P64 p, long long* cnt, hipStream_t s);
 hipError_t launch_mcc64(const DevInst& I, P64 p, long long* cnt, long long grid_cap,
                         hipStream_t s);
 hipError_t launch_deposit64(const DevInst& I, P64 p, long long* Q, long long* cnt,
