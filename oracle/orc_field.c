@@ -13,6 +13,15 @@
  * a discrete sine transform in z, which diagonalises Kz and Mz, followed by a
  * tridiagonal solve in r per sine mode.  The sine transform is written as the
  * plain sum with a table; no fast transform.
+ *
+ * Open ends (end_mode 2, the Neumann condition d(phi)/dz = 0 of Sec. II.A):
+ * the end nodes z = 0, L are unknowns and the natural boundary condition
+ * halves the end rows of Kz and Mz; with D = diag(1/2, 1, ..., 1, 1/2) both
+ * satisfy A v_k = eig_k D v_k for the cosine vectors v_k(j) = cos(pi j k / nz),
+ * k = 0..nz (same eigenvalues as the sine modes), and v_m^T D v_k = c_k
+ * delta_mk with c_k = nz for k = 0, nz and nz/2 otherwise.  So each mode k
+ * solves (mu_k Kr + lam_k Mr) x_k = (sum_j b_j v_k(j)) / c_k and
+ * phi_j = sum_k x_k v_k(j).
  */
 #include "oracle.h"
 
@@ -65,13 +74,28 @@ static double Mr_ent(const orc_cfg* c, double dr, int i, int di) {
 }
 static double Kz_ent(double dz, int di) { return di == 0 ? 2.0 / dz : -1.0 / dz; }
 static double Mz_ent(double dz, int di) { return di == 0 ? 4.0 * dz / 6.0 : dz / 6.0; }
+/* the same at node j of an open-ended column: one element on the end nodes */
+static double Kz_at(const orc_cfg* c, double dz, int j, int dj) {
+    if (c->end_mode == 2 && dj == 0 && (j == 0 || j == c->nz)) return 1.0 / dz;
+    return Kz_ent(dz, dj);
+}
+static double Mz_at(const orc_cfg* c, double dz, int j, int dj) {
+    if (c->end_mode == 2 && dj == 0 && (j == 0 || j == c->nz)) return 2.0 * dz / 6.0;
+    return Mz_ent(dz, dj);
+}
 
 /*
  * Solve (Kr (x) Mz + Mr (x) Kz) x = rhs on the interior nodes with x = 0 on
  * the boundary.  rhs and phi are full node arrays; boundary entries of rhs are
  * ignored and boundary entries of phi are set to 0.
  */
+static void solve_neumann(const orc_cfg* c, const double* rhs, double* phi);
+
 void orc_solve(const orc_cfg* c, const double* rhs, double* phi) {
+    if (c->end_mode == 2) {
+        solve_neumann(c, rhs, phi);
+        return;
+    }
     const int nr = c->nr, nz = c->nz, W = nz + 1;
     const double dr = (c->b - c->a) / (double)nr, dz = c->L / (double)nz;
     const int nri = nr - 1, nzi = nz - 1;
@@ -137,6 +161,70 @@ void orc_solve(const orc_cfg* c, const double* rhs, double* phi) {
     free(S); free(bh); free(xh);
 }
 
+/* The open-ended system: interior rows in r, all nodes j = 0..nz in z,
+ * solved by the cosine modes (plain sums with a table). */
+static void solve_neumann(const orc_cfg* c, const double* rhs, double* phi) {
+    const int nr = c->nr, nz = c->nz, W = nz + 1;
+    const double dr = (c->b - c->a) / (double)nr, dz = c->L / (double)nz;
+    const int nri = nr - 1;
+    double* Ct = (double*)malloc(sizeof(double) * (size_t)W * W);  /* cos(pi j k / nz) */
+    for (int j = 0; j <= nz; ++j)
+        for (int k = 0; k <= nz; ++k)
+            Ct[(size_t)j * W + k] = cos(M_PI * (double)((j * k) % (2 * nz)) / (double)nz);
+    double* bh = (double*)calloc((size_t)(nr + 1) * W, sizeof(double));
+#pragma omp parallel for schedule(static)
+    for (int i = 1; i <= nri; ++i) {
+        double* out = bh + (size_t)i * W;
+        for (int j = 0; j <= nz; ++j) {
+            double v = rhs[(size_t)i * W + j];
+            const double* Cj = Ct + (size_t)j * W;
+            for (int k = 0; k <= nz; ++k) out[k] += v * Cj[k];
+        }
+        for (int k = 0; k <= nz; ++k) out[k] /= (k == 0 || k == nz) ? (double)nz : 0.5 * (double)nz;
+    }
+    double* xh = (double*)calloc((size_t)(nr + 1) * W, sizeof(double));
+#pragma omp parallel
+    {
+        double* cp = (double*)malloc(sizeof(double) * (size_t)(nr + 1));
+        double* dp = (double*)malloc(sizeof(double) * (size_t)(nr + 1));
+#pragma omp for schedule(static)
+        for (int k = 0; k <= nz; ++k) {
+            double ck = cos(M_PI * (double)k / (double)nz);
+            double mu = (dz / 3.0) * (2.0 + ck);
+            double lam = (2.0 / dz) * (1.0 - ck);
+            for (int i = 1; i <= nri; ++i) {
+                double diag = mu * Kr_ent(c, dr, i, 0) + lam * Mr_ent(c, dr, i, 0);
+                double up = mu * Kr_ent(c, dr, i, +1) + lam * Mr_ent(c, dr, i, +1);
+                double lo = mu * Kr_ent(c, dr, i, -1) + lam * Mr_ent(c, dr, i, -1);
+                double b = bh[(size_t)i * W + k];
+                if (i == 1) {
+                    cp[i] = up / diag;
+                    dp[i] = b / diag;
+                } else {
+                    double m = diag - lo * cp[i - 1];
+                    cp[i] = up / m;
+                    dp[i] = (b - lo * dp[i - 1]) / m;
+                }
+            }
+            xh[(size_t)nri * W + k] = dp[nri];
+            for (int i = nri - 1; i >= 1; --i)
+                xh[(size_t)i * W + k] = dp[i] - cp[i] * xh[(size_t)(i + 1) * W + k];
+        }
+        free(cp); free(dp);
+    }
+    memset(phi, 0, sizeof(double) * (size_t)(nr + 1) * W);
+#pragma omp parallel for schedule(static)
+    for (int i = 1; i <= nri; ++i) {
+        double* out = phi + (size_t)i * W;
+        for (int k = 0; k <= nz; ++k) {
+            double v = xh[(size_t)i * W + k];
+            const double* Ck = Ct + (size_t)k * W;
+            for (int j = 0; j <= nz; ++j) out[j] += v * Ck[j];
+        }
+    }
+    free(Ct); free(bh); free(xh);
+}
+
 /* Dirichlet data on the electrodes.  r=a: V_inner; r=b: V_outer (corners
  * belong to the radial electrodes); ends z=0,L: end_mode 0 gives the coaxial
  * vacuum profile shifted by V_end, end_mode 1 a flat V_end. */
@@ -151,6 +239,7 @@ static double boundary_value(const orc_cfg* c, double dr, int i, int j) {
 }
 
 static int is_boundary(const orc_cfg* c, int i, int j) {
+    if (c->end_mode == 2) return i == 0 || i == c->nr;  /* open ends: z nodes are unknowns */
     return i == 0 || i == c->nr || j == 0 || j == c->nz;
 }
 
@@ -161,15 +250,16 @@ void orc_vacuum(const orc_cfg* c, double* phi_vac) {
     size_t N = (size_t)(nr + 1) * W;
     double* rhs = (double*)calloc(N, sizeof(double));
     double* x = (double*)calloc(N, sizeof(double));
+    const int j0 = c->end_mode == 2 ? 0 : 1, j1 = c->end_mode == 2 ? nz : nz - 1;
     for (int i = 1; i < nr; ++i)
-        for (int j = 1; j < nz; ++j) {
+        for (int j = j0; j <= j1; ++j) {
             double s = 0.0;
             for (int di = -1; di <= 1; ++di)
                 for (int dj = -1; dj <= 1; ++dj) {
                     int ii = i + di, jj = j + dj;
-                    if (!is_boundary(c, ii, jj)) continue;
-                    double A = Kr_ent(c, dr, i, di) * Mz_ent(dz, dj) +
-                               Mr_ent(c, dr, i, di) * Kz_ent(dz, dj);
+                    if (jj < 0 || jj > nz || !is_boundary(c, ii, jj)) continue;
+                    double A = Kr_ent(c, dr, i, di) * Mz_at(c, dz, j, dj) +
+                               Mr_ent(c, dr, i, di) * Kz_at(c, dz, j, dj);
                     s -= A * boundary_value(c, dr, ii, jj);
                 }
             rhs[(size_t)i * W + j] = s;

@@ -601,3 +601,76 @@ def test_seed_source_uniform_in_volume_and_maxwellian():
     s0.step(1)
     v = s0.get_particles()["vz"]
     assert np.std(v) == pytest.approx(math.sqrt(0.5 * E / ME), rel=0.02)
+
+
+# --------------------------------------------------------------------------
+# Open (Neumann) ends, end_mode 2 (Sec. II.A: d(phi)/dz = 0 on the open
+# boundaries)
+# --------------------------------------------------------------------------
+
+def test_neumann_vacuum_is_the_coaxial_log_at_second_order():
+    errs = []
+    for nr in (16, 32, 64):
+        c = pi.coax64(nr=nr, nz=32, end_mode=2)
+        v = oracle.vacuum(c)
+        # no axial structure at all with open ends
+        assert np.max(np.abs(v - v[:, :1])) <= 1e-12 * abs(c["V_inner"])
+        a, b = c["a"], c["b"]
+        r = a + (b - a) / nr * np.arange(nr + 1)
+        exact = c["V_inner"] + (c["V_outer"] - c["V_inner"]) * np.log(r / a) / math.log(b / a)
+        errs.append(np.max(np.abs(v[:, 7] - exact)) / abs(c["V_inner"]))
+    orders = [math.log2(errs[i] / errs[i + 1]) for i in range(2)]
+    assert min(orders) > 1.8, (errs, orders)
+
+
+def test_neumann_uniform_column_is_z_independent_closed_form():
+    """A uniform density filling a < r < b, 0 <= z <= L with phi = 0 on the
+    electrodes and open ends: phi depends on r only and follows
+    (e n0 / 4 eps0) r^2 + C1 ln r + C2 at second order, at every z."""
+    n0 = 1e15
+    errs = []
+    for nr in (16, 32, 64):
+        c = pi.coax64(nr=nr, nz=64, end_mode=2)
+        S = 10
+        V = oracle.node_volume(c)
+        Q = np.rint(n0 * V * 2.0**S).astype(np.int64)
+        phi = oracle.poisson_charge(c, Q, fx_shift=S)
+        d = oracle.derive(c)
+        r = c["a"] + d["dr"] * np.arange(nr + 1)
+        k = E * n0 / (4 * EPS0)
+        a, b = c["a"], c["b"]
+        C1 = -k * (b * b - a * a) / math.log(b / a)
+        C2 = -k * a * a - C1 * math.log(a)
+        exact = (k * r * r + C1 * np.log(r) + C2)[:, None]
+        # z independence up to the rounding of the fixed-point charges
+        assert np.max(np.abs(phi - phi[:, 32:33])) <= 1e-6 * np.max(np.abs(exact))
+        errs.append(np.max(np.abs(phi - exact)) / np.max(np.abs(exact)))
+    orders = [math.log2(errs[i] / errs[i + 1]) for i in range(2)]
+    assert errs[-1] < 1e-3 and min(orders) > 1.7, (errs, orders)
+
+
+def test_neumann_green_reciprocity_and_end_nodes():
+    c = pi.coax64(nr=12, nz=20, end_mode=2)
+    rng = np.random.default_rng(3)
+    for _ in range(6):
+        # sources anywhere in z, the end columns included
+        p = (int(rng.integers(1, 12)), int(rng.integers(0, 21)))
+        q = (int(rng.integers(1, 12)), int(rng.integers(0, 21)))
+        rp = np.zeros((13, 21)); rp[p] = 1.0
+        rq = np.zeros((13, 21)); rq[q] = 1.0
+        gp, gq = oracle.solve(c, rp), oracle.solve(c, rq)
+        assert gp[q] == pytest.approx(gq[p], rel=1e-12)
+        assert gp[p] > 0 and gq[q] > 0
+        assert np.all(gp[0] == 0) and np.all(gp[-1] == 0)  # electrodes stay at 0
+    # a cosine profile in z is an eigenvector of the open-ended z operators:
+    # the response keeps exactly that profile
+    jz = np.arange(21)
+    rhs = np.zeros((13, 21))
+    rhs[5] = np.cos(np.pi * 3 * jz / 20)
+    rhs[5, 0] *= 0.5  # the natural boundary halves the end rows (load of a half element)
+    rhs[5, -1] *= 0.5
+    g = oracle.solve(c, rhs)
+    prof = np.cos(np.pi * 3 * jz / 20)
+    for i in (3, 5, 9):
+        coef = g[i, 1] / prof[1]
+        assert np.allclose(g[i], coef * prof, rtol=0, atol=1e-12 * abs(coef))
