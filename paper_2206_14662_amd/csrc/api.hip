@@ -182,7 +182,7 @@ static std::string validate(const pic_instance_cfg& c) {
             return "need 0 <= src_rate <= 1e9 per step and src_T_eV >= 0";
     }
     if (c.load_mode != 0 && c.load_mode != 1) return "load_mode must be 0 or 1";
-    if (c.end_mode != 0 && c.end_mode != 1) return "end_mode must be 0 or 1";
+    if (c.end_mode < 0 || c.end_mode > 2) return "end_mode must be 0, 1 or 2";
     if (c.diag_interval < 0) return "diag_interval must be >= 0";
     return "";
 }
@@ -223,8 +223,15 @@ static double mr(const pic_instance_cfg& c, double dr, int i, int di) {
         return (i > 0 ? dr * (rm + 3.0 * r0) / 12.0 : 0.0) + (i < c.nr ? dr * (3.0 * r0 + rp) / 12.0 : 0.0);
     return di < 0 ? dr * (rm + r0) / 12.0 : dr * (r0 + rp) / 12.0;
 }
-static double kz(double dz, int dj) { return dj == 0 ? 2.0 / dz : -1.0 / dz; }
-static double mz(double dz, int dj) { return dj == 0 ? 4.0 * dz / 6.0 : dz / 6.0; }
+// z entries at node j; with open ends (end_mode 2) the end nodes carry one element
+static double kz(const pic_instance_cfg& c, double dz, int j, int dj) {
+    if (dj != 0) return -1.0 / dz;
+    return (c.end_mode == 2 && (j == 0 || j == c.nz)) ? 1.0 / dz : 2.0 / dz;
+}
+static double mz(const pic_instance_cfg& c, double dz, int j, int dj) {
+    if (dj != 0) return dz / 6.0;
+    return (c.end_mode == 2 && (j == 0 || j == c.nz)) ? 2.0 * dz / 6.0 : 4.0 * dz / 6.0;
+}
 
 static double edge_value(const pic_instance_cfg& c, double dr, int i) {
     if (i == 0) return c.V_inner;
@@ -239,17 +246,20 @@ static void host_vacuum_rhs(const pic_instance_cfg& c, std::vector<double>& phiB
     const double dr = (c.b - c.a) / (double)nr, dz = c.L / (double)nz;
     phiB.assign((size_t)(nr + 1) * W, 0.0);
     rhs.assign((size_t)(nr + 1) * W, 0.0);
-    auto edge = [&](int i, int j) { return i == 0 || i == nr || j == 0 || j == nz; };
+    // Dirichlet nodes: the radial electrodes, and the end plates unless the ends are open
+    const bool open_ends = c.end_mode == 2;
+    auto edge = [&](int i, int j) { return i == 0 || i == nr || (!open_ends && (j == 0 || j == nz)); };
     for (int i = 0; i <= nr; ++i)
         for (int j = 0; j <= nz; ++j)
             if (edge(i, j)) phiB[(size_t)i * W + j] = edge_value(c, dr, i);
+    const int j0 = open_ends ? 0 : 1, j1 = open_ends ? nz : nz - 1;
     for (int i = 1; i < nr; ++i)
-        for (int j = 1; j < nz; ++j) {
+        for (int j = j0; j <= j1; ++j) {
             double s = 0.0;
             for (int di = -1; di <= 1; ++di)
                 for (int dj = -1; dj <= 1; ++dj) {
-                    if (!edge(i + di, j + dj)) continue;
-                    double A = kr(c, dr, i, di) * mz(dz, dj) + mr(c, dr, i, di) * kz(dz, dj);
+                    if (j + dj < 0 || j + dj > nz || !edge(i + di, j + dj)) continue;
+                    double A = kr(c, dr, i, di) * mz(c, dz, j, dj) + mr(c, dr, i, di) * kz(c, dz, j, dj);
                     s -= A * phiB[(size_t)(i + di) * W + (j + dj)];
                 }
             rhs[(size_t)i * W + j] = s;
@@ -262,7 +272,9 @@ static void host_thomas(const pic_instance_cfg& c, int nseg, std::vector<double>
     const double dr = (c.b - c.a) / (double)nr, dz = c.L / (double)nz;
     size_t N = (size_t)(nr + 1) * W;
     cp.assign(N, 0.0); im.assign(N, 0.0); lo.assign(N, 0.0);
-    for (int k = 1; k < nz; ++k) {
+    // sine modes 1..nz-1 with Dirichlet ends, cosine modes 0..nz with open ends
+    const int k0 = c.end_mode == 2 ? 0 : 1, k1 = c.end_mode == 2 ? nz : nz - 1;
+    for (int k = k0; k <= k1; ++k) {
         double ck = cos(kPi * (double)k / (double)nz);
         double mu = (dz / 3.0) * (2.0 + ck), lam = (2.0 / dz) * (1.0 - ck);
         double cprev = 0.0;
@@ -282,7 +294,7 @@ static void host_thomas(const pic_instance_cfg& c, int nseg, std::vector<double>
     G.assign(N, 0.0);
     H.assign(N, 0.0);
     const int nri = nr - 1, seg = (nri + nseg - 1) / nseg;
-    for (int k = 1; k < nz; ++k)
+    for (int k = k0; k <= k1; ++k)
         for (int sg = 0; sg < nseg; ++sg) {
             const int r0 = 1 + sg * seg, r1 = std::min(r0 + seg, nri + 1);
             double g = 1.0;
@@ -340,6 +352,7 @@ static void fill_devinst(Inst& in) {
     I.two_e_over_me_f = (float)d.two_e_over_me; I.mass_ratio2_f = (float)d.mass_ratio2;
     I.v_cap2_f = (float)(d.v_cap * d.v_cap);
     I.diag_D = c.diag_interval > 0 ? c.diag_interval : 1;
+    I.open_ends = c.end_mode == 2 ? 1 : 0;
     I.src_rate = c.src_rate;
     I.src_sv = sqrt(((c.src_T_eV > 0.0 ? c.src_T_eV : c.T_init_eV) * kE) / kMe);
     I.weight = c.weight;

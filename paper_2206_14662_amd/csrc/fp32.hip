@@ -1507,8 +1507,8 @@ pic_status f32_reserve(pic_ctx* ctx, int k, long long slots) {
 
 // Capacity check, a lagged one so the stream never drains: the counters are
 // copied to pinned memory every kCheckEvery steps and the previous copy is
-// inspected.  Its used slots plus twice their growth since the copy before
-// (the lag spans up to two check periods) must stay under 3/4 of the
+// inspected.  Its used slots, grown for two check periods at the rate seen
+// since the copy before (and by the seed source), must stay under 3/4 of the
 // segment, else the instance is grown to twice that projection (new stores,
 // copy, full sort, graphs re-captured).  The first check of a context looks
 // at the current counters.  Dropped electrons or a fixed-point overflow in
@@ -1539,10 +1539,12 @@ static pic_status capacity_check(pic_ctx* ctx, F32State* S, hipStream_t work) {
                 return f32_fail(ctx, PIC_EOVERFLOW, "instance " + std::to_string(k) + ": fixed-point overflow");
             const long long cap = pic_inst_dev(ctx, k).p_cap;
             const long long used = c[C_SLOTS];
-            const long long rise = S->prev_used[k] >= 0 ? std::max(0ll, used - S->prev_used[k]) : 0;
-            // the lag spans up to two check periods; the seed source adds at a known rate
+            // the lag spans up to two check periods: growth at the rate seen
+            // between the last two copies (compounded), at least the seed source's
+            const double f = S->prev_used[k] > 0 ? std::min(4.0, std::max(1.0, (double)used / S->prev_used[k])) : 1.0;
             const long long proj =
-                used + 2 * std::max(rise, (long long)ceil(pic_inst_dev(ctx, k).src_rate) * kCheckEvery);
+                std::max((long long)((double)used * f * f),
+                         used + 2 * (long long)ceil(pic_inst_dev(ctx, k).src_rate) * kCheckEvery);
             S->prev_used[k] = used;
             caps[k] = cap;
             if (proj > cap - cap / 4) {

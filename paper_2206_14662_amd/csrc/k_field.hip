@@ -104,15 +104,19 @@ __device__ void fft_lds(double2* y, int N, const double2* __restrict__ tw, int t
     else if (N / Ns == 2) fft_pass<2>(y, N, Ns, tw, tw_n);
 }
 
-// Sine transform of interior rows, two per block.
-//   mode 0: rows of Q * bscale            -> rhs (modes)
-//   mode 1: rows of rhs (already scaled)  -> rhs (modes)
-//   mode 2: rows of rhs (solved modes)    -> phi = phi_vac + (2/nz) DST
+// z transform of interior rows, two per block.  Dirichlet ends: sine
+// transform of the interior nodes through the FFT of the odd extension;
+// open ends: cosine sums over all nodes 0..nz through the FFT of the even
+// extension, S_k = (Y_k + x_0 + (-1)^k x_nz) / 2.
+//   mode 0: rows of Q * bscale            -> rhs (modes; divided by c_k when open)
+//   mode 1: rows of rhs (already scaled)  -> rhs (modes; divided by c_k when open)
+//   mode 2: rows of rhs (solved modes)    -> phi = phi_vac + (2/nz) DST, or + S
 __global__ void __launch_bounds__(kFftMaxBlock) kf_dst(const DevInst* __restrict__ It,
                                                     const FieldDev* __restrict__ Ft, int inst_base,
                                                     const double2* __restrict__ tw, int tw_n,
                                                     int mode, const double* __restrict__ bscale) {
     extern __shared__ double2 y[];
+    __shared__ double2 ends[2];  // (A, B) at j = 0 and j = nz, open ends
     const int inst = inst_base + blockIdx.y;
     const DevInst& I = It[inst];
     const FieldDev& F = Ft[inst];
@@ -120,13 +124,14 @@ __global__ void __launch_bounds__(kFftMaxBlock) kf_dst(const DevInst* __restrict
     const int iA = 1 + 2 * blockIdx.x, iB = iA + 1;
     if (I.frozen || iA > I.nr - 1) return;
     const bool hasB = iB <= I.nr - 1;
+    const bool open = I.open_ends != 0;
     const int N = 2 * nz;
     const double bs = mode == 0 ? bscale[inst] : 1.0;
     for (int j = threadIdx.x; j < N; j += blockDim.x) {
         int jj = j <= nz ? j : N - j;
-        double sg = j <= nz ? 1.0 : -1.0;
+        double sg = (open || j <= nz) ? 1.0 : -1.0;
         double va = 0.0, vb = 0.0;
-        if (jj >= 1 && jj <= nz - 1) {
+        if (open || (jj >= 1 && jj <= nz - 1)) {
             if (mode == 0) {
                 va = (double)F.Q[(long long)iA * W + jj] * bs;
                 vb = hasB ? (double)F.Q[(long long)iB * W + jj] * bs : 0.0;
@@ -136,9 +141,29 @@ __global__ void __launch_bounds__(kFftMaxBlock) kf_dst(const DevInst* __restrict
             }
         }
         y[j] = make_double2(sg * va, sg * vb);
+        if (open && j == 0) ends[0] = make_double2(va, vb);
+        if (open && j == nz) ends[1] = make_double2(va, vb);
     }
     __syncthreads();
     fft_lds(y, N, tw, tw_n);
+    if (open) {
+        const double2 e0 = ends[0], e1 = ends[1];
+        for (int k = threadIdx.x; k <= nz; k += blockDim.x) {
+            const double sgn = (k & 1) ? -1.0 : 1.0;
+            double SA = 0.5 * (y[k].x + (e0.x + sgn * e1.x));
+            double SB = 0.5 * (y[k].y + (e0.y + sgn * e1.y));
+            const long long nA = (long long)iA * W + k, nB = (long long)iB * W + k;
+            if (mode == 2) {
+                F.phi[nA] = F.phi_vac[nA] + SA;
+                if (hasB) F.phi[nB] = F.phi_vac[nB] + SB;
+            } else {
+                const double ck = (k == 0 || k == nz) ? (double)nz : 0.5 * (double)nz;
+                F.rhs[nA] = SA / ck;
+                if (hasB) F.rhs[nB] = SB / ck;
+            }
+        }
+        return;
+    }
     // y = -2i X_A + 2 X_B for odd real inputs A (real part) and B (imag part)
     const double sc = 2.0 / (double)nz;
     for (int k = threadIdx.x + 1; k <= nz - 1; k += blockDim.x) {
@@ -172,10 +197,12 @@ __global__ void __launch_bounds__(64 * kThomasSeg) kf_thomas(const DevInst* __re
     const FieldDev& F = Ft[inst];
     if (I.frozen) return;
     const int lane = threadIdx.x, sg = __builtin_amdgcn_readfirstlane(threadIdx.y);  // one wave per segment
-    const int k = 1 + blockIdx.x * 64 + lane;
-    if (1 + (int)blockIdx.x * 64 > I.nz - 1) return;  // whole block past the modes
-    const bool valid = k <= I.nz - 1;
-    const int kk = valid ? k : 1;
+    // modes 1..nz-1 (sine, Dirichlet ends) or 0..nz (cosine, open ends)
+    const int kfirst = I.open_ends ? 0 : 1, klast = I.open_ends ? I.nz : I.nz - 1;
+    const int k = kfirst + blockIdx.x * 64 + lane;
+    if (kfirst + (int)blockIdx.x * 64 > klast) return;  // whole block past the modes
+    const bool valid = k <= klast;
+    const int kk = valid ? k : kfirst;
     const long long W = I.W;
     const int nri = I.nr - 1;
     const int m = (nri + kThomasSeg - 1) / kThomasSeg;
@@ -273,10 +300,12 @@ __global__ void __launch_bounds__(64 * kThomasSegReg) kf_thomas_reg(const DevIns
     // one wave per segment: the segment index and all row offsets are
     // wave-uniform (scalar registers); only the mode column varies by lane
     const int lane = threadIdx.x, sg = __builtin_amdgcn_readfirstlane(threadIdx.y);
-    const int k = 1 + blockIdx.x * 64 + lane;
-    if (1 + (int)blockIdx.x * 64 > I.nz - 1) return;  // whole block past the modes
-    const bool valid = k <= I.nz - 1;
-    const int kk = valid ? k : 1;
+    // modes 1..nz-1 (sine, Dirichlet ends) or 0..nz (cosine, open ends)
+    const int kfirst = I.open_ends ? 0 : 1, klast = I.open_ends ? I.nz : I.nz - 1;
+    const int k = kfirst + blockIdx.x * 64 + lane;
+    if (kfirst + (int)blockIdx.x * 64 > klast) return;  // whole block past the modes
+    const bool valid = k <= klast;
+    const int kk = valid ? k : kfirst;
     const int W = I.W;  // node offsets fit 32 bits ((nr+1)(nz+1) < 2^31)
     const int nri = I.nr - 1;
     const int m = (nri + P - 1) / P;  // <= R (checked by the launcher)
@@ -355,12 +384,13 @@ __global__ void kf_phi_edges(const DevInst* __restrict__ It, const FieldDev* __r
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     const int W = I.W;
     if (I.frozen) return;
-    // rows i=0 and i=nr (W entries each), columns j=0 and j=nz (nr+1 entries each)
+    // rows i=0 and i=nr (W entries each), columns j=0 and j=nz (nr+1 entries
+    // each; with open ends the columns are solved, not given)
     if (t < W) {
         F.phi[t] = F.phi_vac[t];
         long long n = (long long)I.nr * W + t;
         F.phi[n] = F.phi_vac[n];
-    } else if (t < W + I.nr + 1) {
+    } else if (!I.open_ends && t < W + I.nr + 1) {
         long long i = t - W;
         F.phi[i * W] = F.phi_vac[i * W];
         F.phi[i * W + I.nz] = F.phi_vac[i * W + I.nz];
@@ -478,7 +508,7 @@ hipError_t launch_solve_tab(const DevInst* It, const FieldDev* Ft, int inst_base
     hipLaunchKernelGGL(kf_dst, gdst, fb, lds, s, It, Ft, inst_base, tw, tw_n, mode, bscale);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    dim3 gth((unsigned)((max_nz - 1 + 63) / 64), (unsigned)n_inst);
+    dim3 gth((unsigned)((max_nz + 1 + 63) / 64), (unsigned)n_inst);  // up to nz + 1 modes
     if (thomas_segments(max_nr) == kThomasSegReg) {
         const int rows = (max_nr - 1 + kThomasSegReg - 1) / kThomasSegReg;
         const dim3 blk(64, kThomasSegReg);

@@ -47,6 +47,7 @@ struct DevInst {
     int ntr, ntz;                   // tiles in r and z
     int tile_off;                   // first global tile id of this instance
     int diag_D;                     // steps between diagnostic samples
+    int open_ends;                  // 1: d(phi)/dz = 0 at z = 0, L (cosine modes)
     // volumetric seed source
     double src_rate;                // macro-electrons per step (0: off)
     double src_sv;                  // its thermal speed sqrt(T e / m)

@@ -84,8 +84,9 @@ def test_several_steps_with_collisions_frozen():
     assert rel_vec_err(gp, op).max() <= 1e-11
 
 
-def test_vacuum_potential():
-    cfg = pi.coax64(mirror_k=0.3)
+@pytest.mark.parametrize("end_mode", [0, 1, 2])
+def test_vacuum_potential(end_mode):
+    cfg = pi.coax64(mirror_k=0.3, end_mode=end_mode)
     g = B.Sim([dict(cfg, n_init=0)])
     ref = oracle.vacuum(cfg)
     assert np.max(np.abs(g.phi() - ref)) <= 1e-10 * np.max(np.abs(ref))
@@ -97,9 +98,9 @@ def test_vacuum_potential():
     assert np.array_equal(f["Br"], Br) and np.array_equal(f["Bz"], Bz)
 
 
-@pytest.mark.parametrize("maker", [pi.coax64, pi.coax256])
-def test_poisson_solve_matches_oracle(maker):
-    cfg = maker()
+@pytest.mark.parametrize("maker,end_mode", [(pi.coax64, 0), (pi.coax256, 0), (pi.coax64, 2), (pi.coax256, 2)])
+def test_poisson_solve_matches_oracle(maker, end_mode):
+    cfg = maker(end_mode=end_mode)
     st = pi.cloud_state(cfg, 50000, seed=11)
     g, o = gpu_and_oracle(cfg, st, fields=None)
     assert np.array_equal(g.charge(), o.charge())

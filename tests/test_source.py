@@ -112,3 +112,28 @@ def test_fp32_source_invariant_to_tiles_graph_and_resume():
     for k in ("key", "r", "z", "vr", "vt", "vz"):
         assert np.array_equal(ref[0][k], got[k]), k
     h.close()
+
+
+@pytest.mark.parametrize("mode", [F64, F32])
+def test_open_ends_self_consistent_run(mode):
+    """Open (Neumann) ends with the seed source and collisions, 200 steps
+    self-consistent: counts and the time-averaged density follow the oracle."""
+    cfg = seeded(n_init=30000, end_mode=2, p_mbar=10.0, E_cap_eV=3000.0, diag_interval=10)
+    S = B.pic_auto_shift(cfg["weight"])
+    g = B.Sim([dict(cfg, fx_shift=S)], mode=mode, capacity_factor=6.0)
+    o = oracle.Sim(cfg, fx_shift=S)
+    o.load()
+    if mode == F64:
+        g.set_particles(o.get_particles())
+    g.step(200)
+    o.step(200)
+    gd, od = g.diag(want_density=True), o.diag()
+    assert gd["n_ioniz"] > 100 and gd["n_source"] == od["n_source"]
+    tol = 0.002 if mode == F64 else 0.02
+    for k in ("n_live", "n_ioniz"):
+        assert abs(gd[k] - od[k]) <= tol * od[k], k
+    na = o.time_avg_density()
+    mask = na > 0.2 * na.max()
+    rel = np.linalg.norm((gd["time_avg_density"] - na)[mask]) / np.linalg.norm(na[mask])
+    assert rel < tol, rel
+    g.close()
