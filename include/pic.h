@@ -68,7 +68,8 @@ typedef struct {
     int nr, nz;                /* cells in r and z; nz a power of two >= 4       */
     double V_inner, V_outer;   /* electrode potentials at r=a, r=b (V)           */
     double V_end;              /* end electrodes at z=0,L (V), see end_mode      */
-    int end_mode;              /* 0: phi_end(r) = phi_coax(r) + V_end; 1: V_end  */
+    int end_mode;              /* 0: phi_end(r) = phi_coax(r) + V_end; 1: V_end;
+                                  2: open ends, d(phi)/dz = 0 (Sec. II.A)        */
     double B0, mirror_k;       /* Bz = B0 (1 + k zeta^2), zeta = (z-L/2)/(L/2),
                                   Br = -(r/2) dBz/dz                             */
     double p_mbar, T_gas_K;    /* neutral pressure and temperature: n = p/(kT)   */

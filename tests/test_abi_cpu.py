@@ -28,11 +28,30 @@ def test_library_exports_every_declared_symbol():
     assert set(syms) <= set(B.EXPORTS)
 
 
-def test_struct_sizes_match_header_layout():
+def test_struct_layouts_match_the_header(tmp_path):
+    """The binding's ctypes mirrors have the C compiler's size and field
+    offsets for every struct of pic.h (a C program built from the header
+    prints them)."""
     import ctypes as C
-    # pic_instance_cfg: 3 doubles, 2 ints, 3 doubles, 1 int (+pad), ... computed by ctypes
-    assert C.sizeof(B.pic_instance_cfg) % 8 == 0
-    assert C.sizeof(B.pic_diag_t) % 8 == 0
+    import subprocess
+    structs = {"pic_instance_cfg": B.pic_instance_cfg, "pic_run_cfg": B.pic_run_cfg,
+               "pic_diag_t": B.pic_diag_t, "pic_derived_t": B.pic_derived_t, "pic_allocator": B.pic_allocator}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "pic.h"', "int main(void) {"]
+    for name, cls in structs.items():
+        lines.append(f'printf("{name} %zu\\n", sizeof({name}));')
+        for f, _ in cls._fields_:
+            lines.append(f'printf("{name}.{f} %zu\\n", offsetof({name}, {f}));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = dict(l.rsplit(" ", 1) for l in subprocess.run([str(exe)], capture_output=True, text=True,
+                                                          check=True).stdout.split("\n") if l)
+    for name, cls in structs.items():
+        assert int(out[name]) == C.sizeof(cls), name
+        for f, _ in cls._fields_:
+            assert int(out[f"{name}.{f}"]) == getattr(cls, f).offset, (name, f)
 
 
 @pytest.mark.parametrize("cfg", [pi.coax64(), pi.coax64hot(), pi.coax256(), pi.coax512()] + pi.scan32()[:4] + pi.batch8()[:3])
