@@ -101,6 +101,7 @@ def lib():
         L.orc_get_phi.argtypes = [C.c_void_p, _D]
         L.orc_get_diag.argtypes = [C.c_void_p, C.POINTER(OrcDiag)]
         L.orc_get_time_avg_density.argtypes = [C.c_void_p, _D]
+        L.orc_moments.argtypes = [C.c_void_p, _D]
         L.orc_num_threads.restype = C.c_int
         _lib = L
     return _lib
@@ -309,6 +310,13 @@ class Sim:
             v = getattr(dg, name)
             out[name] = list(v) if hasattr(v, "__len__") else v
         return out
+
+    def moments(self):
+        """ORC_NMOM (11) node arrays: n, n u_r, n u_t, n u_z, the six
+        second moments (rr, rt, rz, tt, tz, zz) and sum w nu_m / V."""
+        out = np.zeros(11 * self.nodes)
+        lib().orc_moments(self.h, _dp(out))
+        return out.reshape((11,) + self.shape)
 
     def time_avg_density(self):
         n = np.zeros(self.nodes)

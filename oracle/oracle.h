@@ -110,6 +110,12 @@ void orc_efield(const orc_cfg* c, const double* phi, double* Er, double* Ez);
 void orc_node_volume(const orc_cfg* c, double* V);
 void orc_deposit_one(const orc_cfg* c, double r, double z, double w, int64_t* Q);
 
+/* Fluid moments (Sec. IV: force terms from moments of the distribution):
+ * number of channels and their order in orc_moments' output. */
+#define ORC_NMOM 11
+/* n, n u_r, n u_t, n u_z, then sum w v_a v_b / V for (rr, rt, rz, tt, tz, zz),
+ * then sum w nu_m(v) / V with nu_m = n_n (sigma_el + sigma_iz(E)) |v|. */
+
 /* ---- simulation object ---- */
 orc_sim* orc_create(const orc_cfg* c, int64_t capacity);
 void     orc_destroy(orc_sim* s);
@@ -119,6 +125,10 @@ int      orc_set_particles(orc_sim* s, int64_t n, const double* r, const double*
                            const double* w, const uint64_t* key);
 int64_t  orc_get_particles(const orc_sim* s, int64_t cap, double* r, double* z,
                            double* vr, double* vt, double* vz, double* w, uint64_t* key);
+/* ORC_NMOM channel-major node arrays (channel c at out + c * nodes): the
+ * bilinear (hat-function) sums of w times each quantity, divided by the node
+ * volume, i.e. densities in m^-3 times the quantity's unit. */
+void     orc_moments(const orc_sim* s, double* out);
 void     orc_set_fields(orc_sim* s, const double* Er, const double* Ez,
                         const double* Br, const double* Bz, int frozen);
 void     orc_get_fields(const orc_sim* s, double* Er, double* Ez, double* Br, double* Bz);

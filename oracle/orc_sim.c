@@ -522,6 +522,30 @@ int orc_step(orc_sim* s, int n_steps) {
     return 0;
 }
 
+/* Fluid moments of the particle distribution on the nodes (Sec. IV "Prevalent
+ * force terms" evaluates its force terms from these): each particle adds
+ * w * N_i(x) * {1, v_r, v_t, v_z, v_a v_b, nu_m(v)} to node i; the sums are
+ * divided by the node volume.  Plain sequential loop. */
+void orc_moments(const orc_sim* s, double* out) {
+    const int W = s->c.nz + 1, N = s->nodes;
+    memset(out, 0, sizeof(double) * (size_t)ORC_NMOM * N);
+    for (int64_t p = 0; p < s->n; ++p) {
+        orc_shape sh = shape_at(&s->c, &s->d, s->r[p], s->z[p]);
+        const double vr = s->vr[p], vt = s->vt[p], vz = s->vz[p], w = s->w[p];
+        const double v2 = (vr * vr + vt * vt) + vz * vz, v = sqrt(v2);
+        const double E = v2 * s->d.half_me_over_e;
+        const double nu = (s->d.nsig_el + s->d.n_n * orc_sigma_iz(&s->c, E)) * v;
+        const double q[ORC_NMOM] = {1.0, vr, vt, vz, vr * vr, vr * vt, vr * vz, vt * vt, vt * vz, vz * vz, nu};
+        const size_t n00 = (size_t)sh.i * W + sh.j;
+        const size_t node[4] = {n00, n00 + W, n00 + 1, n00 + W + 1};
+        const double sw[4] = {sh.w00, sh.w10, sh.w01, sh.w11};
+        for (int c = 0; c < ORC_NMOM; ++c)
+            for (int k = 0; k < 4; ++k) out[(size_t)c * N + node[k]] += (w * sw[k]) * q[c];
+    }
+    for (int c = 0; c < ORC_NMOM; ++c)
+        for (int k = 0; k < N; ++k) out[(size_t)c * N + k] /= s->V[k];
+}
+
 void orc_get_charge(const orc_sim* s, int64_t* Q) { memcpy(Q, s->Q, sizeof(int64_t) * s->nodes); }
 void orc_get_phi(const orc_sim* s, double* phi) { memcpy(phi, s->phi, sizeof(double) * s->nodes); }
 

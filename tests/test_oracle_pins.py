@@ -674,3 +674,78 @@ def test_neumann_green_reciprocity_and_end_nodes():
     for i in (3, 5, 9):
         coef = g[i, 1] / prof[1]
         assert np.allclose(g[i], coef * prof, rtol=0, atol=1e-12 * abs(coef))
+
+
+# --------------------------------------------------------------------------
+# Fluid moments (Sec. IV: force terms from moments of the distribution)
+# --------------------------------------------------------------------------
+
+def test_moments_conserve_the_particle_sums():
+    c = pi.coax64()
+    st = pi.cloud_state(c, 3000, seed=4)
+    o = oracle.Sim(c, capacity=4096)
+    o.set_particles(st)
+    m = o.moments()
+    V = oracle.node_volume(c).reshape(m.shape[1:])
+    w, vr, vt, vz = st["w"], st["vr"], st["vt"], st["vz"]
+    want = [w.sum(), (w * vr).sum(), (w * vt).sum(), (w * vz).sum(), (w * vr * vr).sum(), (w * vr * vt).sum(),
+            (w * vr * vz).sum(), (w * vt * vt).sum(), (w * vt * vz).sum(), (w * vz * vz).sum()]
+    for ch, x in enumerate(want):
+        assert (m[ch] * V).sum() == pytest.approx(x, rel=1e-12, abs=1e-9 * abs(want[ch] if ch else 1.0)), ch
+
+
+def test_moments_single_particle_brute_force():
+    c = pi.coax64(nr=8, nz=8, lotz_a=0.0)
+    d = oracle.derive(c)
+    r, z = c["a"] + 2.3 * d["dr"], 5.6 * d["dz"]
+    st = dict(r=np.array([r]), z=np.array([z]), vr=np.array([3e5]), vt=np.array([-1e6]), vz=np.array([2e5]),
+              w=np.array([7.0]), key=np.array([1], dtype=np.uint64))
+    o = oracle.Sim(c, capacity=16)
+    o.set_particles(st)
+    m = o.moments()
+    V = oracle.node_volume(c).reshape(m.shape[1:])
+    fr, fz = 0.3, 0.6
+    weights = {(2, 5): (1 - fr) * (1 - fz), (3, 5): fr * (1 - fz), (2, 6): (1 - fr) * fz, (3, 6): fr * fz}
+    vr, vt, vz = 3e5, -1e6, 2e5
+    v = math.sqrt(vr * vr + vt * vt + vz * vz)
+    q = [1, vr, vt, vz, vr * vr, vr * vt, vr * vz, vt * vt, vt * vz, vz * vz, d["nsig_el"] * v]
+    for ch in range(11):
+        got = m[ch] * V
+        for (i, j), wk in weights.items():
+            assert got[i, j] == pytest.approx(7.0 * wk * q[ch], rel=1e-9), (ch, i, j)
+        assert np.count_nonzero(got) <= 4
+
+
+def test_moments_drifting_maxwellian_pressure_and_drag():
+    """Particles with a drift u and temperature T in a box: n u / n = u and the
+    pressure tensor m (M2 - n u u) = n k T (isotropic); monoenergetic
+    particles with a constant sigma give nu_m = n_n sigma v0 times n."""
+    rng = np.random.default_rng(9)
+    c = pi.coax64(nr=4, nz=4, lotz_a=0.0)
+    N = 200000
+    u = np.array([2e5, -5e5, 1e5])
+    T = 5.0
+    sv = math.sqrt(T * E / ME)
+    st = dict(r=rng.uniform(c["a"], c["b"], N), z=rng.uniform(0, c["L"], N),
+              vr=u[0] + sv * rng.normal(size=N), vt=u[1] + sv * rng.normal(size=N), vz=u[2] + sv * rng.normal(size=N),
+              w=np.full(N, 1.0), key=np.arange(N, dtype=np.uint64))
+    o = oracle.Sim(c, capacity=N)
+    o.set_particles(st)
+    m = o.moments()
+    n = m[0][2, 2]
+    flux = m[1:4, 2, 2]
+    np.testing.assert_allclose(flux / n, u, atol=0.02 * sv)
+    M2 = np.array([[m[4], m[5], m[6]], [m[5], m[7], m[8]], [m[6], m[8], m[9]]])[:, :, 2, 2]
+    P = ME * (M2 - np.outer(flux, flux) / n)
+    np.testing.assert_allclose(np.diag(P) / (n * T * E), 1.0, atol=0.03)
+    assert abs(P[0, 1]) < 0.03 * n * T * E
+    # monoenergetic
+    v0 = 3e6
+    dirs = rng.normal(size=(N, 3))
+    dirs /= np.linalg.norm(dirs, axis=1)[:, None]
+    st2 = dict(st, vr=v0 * dirs[:, 0], vt=v0 * dirs[:, 1], vz=v0 * dirs[:, 2])
+    o2 = oracle.Sim(c, capacity=N)
+    o2.set_particles(st2)
+    m2 = o2.moments()
+    d = oracle.derive(c)
+    np.testing.assert_allclose(m2[10], d["nsig_el"] * v0 * m2[0], rtol=1e-12, atol=0)
