@@ -297,6 +297,21 @@ pic_status pic_autotune(pic_ctx* ctx, int trial_steps, const char* cache_path, i
  */
 pic_status pic_reserve(pic_ctx* ctx, int inst, long long slots);
 
+/*
+ * pic_moments -- fluid moments of instance `inst`'s electrons on the nodes
+ * (Sec. IV evaluates its force terms from moments of the distribution):
+ * 11 channel-major node arrays of (nr+1)(nz+1) doubles written to the host
+ * array out (channel c at out + c (nr+1)(nz+1)): n; n u_r, n u_theta, n u_z;
+ * the second moments sum w v_a v_b / V for (rr, r theta, rz, theta theta,
+ * theta z, zz); and sum w nu_m / V with nu_m = n_n (sigma_el + sigma_iz(E)) |v|
+ * (collisional drag weight).  Each is the bilinear (hat-function) node sum of
+ * the particles' weight times the quantity, divided by the node volume V;
+ * the pressure tensor is m_e (second moments - n u u), the radial current
+ * density -e n u_r.  Synchronises; allocates a temporary device buffer.
+ * Errors: PIC_EINVAL, PIC_ENOMEM, PIC_EDEVICE.
+ */
+pic_status pic_moments(pic_ctx* ctx, int inst, double* out);
+
 /* pic_capacity -- the slots of instance `inst` and the number of storage
  * regrowths so far (per context). */
 pic_status pic_capacity(pic_ctx* ctx, int inst, long long* slots, long long* grow_events);

@@ -87,7 +87,8 @@ class pic_derived_t(C.Structure):
 EXPORTS = ("pic_init", "pic_step", "pic_diag", "pic_destroy", "pic_last_error", "pic_sync",
            "pic_get_particles", "pic_set_particles", "pic_set_fields", "pic_get_fields",
            "pic_get_charge", "pic_get_phi", "pic_set_step", "pic_derive", "pic_auto_shift",
-           "pic_timing", "pic_tuning", "pic_retune", "pic_autotune", "pic_reserve", "pic_capacity")
+           "pic_timing", "pic_tuning", "pic_retune", "pic_autotune", "pic_reserve", "pic_capacity",
+           "pic_moments")
 
 _lib = None
 _D = C.POINTER(C.c_double)
@@ -135,6 +136,7 @@ def lib():
     L.pic_autotune.argtypes = [vp, C.c_int, C.c_char_p, _I, _I, _I, _I, _D, _I]
     L.pic_reserve.argtypes = [vp, C.c_int, C.c_longlong]
     L.pic_capacity.argtypes = [vp, C.c_int, _LL, _LL]
+    L.pic_moments.argtypes = [vp, C.c_int, _D]
     for name in EXPORTS:
         if name not in ("pic_last_error", "pic_auto_shift"):
             getattr(L, name).restype = C.c_int
@@ -367,6 +369,12 @@ def pic_capacity(ctx, inst):
     return slots.value, grows.value
 
 
+def pic_moments(ctx, inst, nodes):
+    out = np.zeros(11 * nodes)
+    _check(lib().pic_moments(ctx, int(inst), out.ctypes.data_as(_D)), ctx)
+    return out
+
+
 class Sim:
     """Convenience holder of one context and its instance list."""
 
@@ -427,6 +435,11 @@ class Sim:
 
     def retune(self, **kw):
         pic_retune(self.ctx, **kw)
+
+    def moments(self, k=0):
+        """(11, nr+1, nz+1): n, n u_r, n u_t, n u_z, second moments (rr, rt, rz,
+        tt, tz, zz), sum w nu_m / V."""
+        return pic_moments(self.ctx, k, self.nodes(k)).reshape((11,) + self.shapes[k])
 
     def capacity(self, k=0):
         return pic_capacity(self.ctx, k)

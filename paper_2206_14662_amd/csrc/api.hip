@@ -1152,3 +1152,28 @@ extern "C" pic_status pic_capacity(pic_ctx* ctx, int k, long long* slots, long l
     if (grow_events) *grow_events = ctx->mode == PIC_MODE_FP64_PLAIN ? ctx->grow_events : f32_grow_events(ctx);
     return PIC_OK;
 }
+
+extern "C" pic_status pic_moments(pic_ctx* ctx, int k, double* out) {
+    pic_status st = check_inst(ctx, k);
+    if (st != PIC_OK) return st;
+    if (!out) return fail(ctx, PIC_EINVAL, "out is NULL");
+    Inst& in = ctx->in[k];
+    const long long N = in.nodes;
+    hipStream_t s = ctx->stream;
+    CK(hipStreamSynchronize(s));
+    double* acc = dalloc<double>(ctx, kMoments * N);
+    if (!acc) return fail(ctx, PIC_ENOMEM, "moment accumulators");
+    hipError_t e = hipMemsetAsync(acc, 0, sizeof(double) * kMoments * N, s);
+    if (e == hipSuccess) {
+        if (ctx->mode == PIC_MODE_FP64_PLAIN) e = launch_moments64(in.I, in.p64[in.cur], in.cnt, acc, s);
+        else st = f32_moments(ctx, k, acc);
+    }
+    if (e == hipSuccess && st == PIC_OK) e = hipMemcpyAsync(out, acc, sizeof(double) * kMoments * N, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess && st == PIC_OK) e = hipStreamSynchronize(s);
+    pic_dev_free(ctx, acc);
+    if (st != PIC_OK) return st;
+    if (e != hipSuccess) return fail(ctx, PIC_EDEVICE, std::string("moments: ") + hipGetErrorString(e));
+    for (int c = 0; c < kMoments; ++c)
+        for (long long n = 0; n < N; ++n) out[c * N + n] /= in.V_host[n];
+    return PIC_OK;
+}

@@ -58,3 +58,5 @@ pic_status f32_reserve(pic_ctx* ctx, int k, long long slots);
 pic_status f32_autotune(pic_ctx* ctx, int trial_steps, const char* cache, int out[4], double* ms_out,
                         int* trials_out);
 long long f32_grow_events(pic_ctx* ctx);
+// fluid-moment node sums of instance k into acc (kMoments x nodes, zeroed)
+pic_status f32_moments(pic_ctx* ctx, int k, double* acc);

@@ -763,6 +763,19 @@ __global__ void __launch_bounds__(kWG) k_source32(KArgs A, PSet P, int scatter) 
     if (blockIdx.x == 0 && threadIdx.x == 0 && count > 0) atomicAdd((unsigned long long*)&cnt[C_SOURCE], count);
 }
 
+// Fluid-moment node sums of one instance's live particles (diagnostic),
+// from the FP32 state widened to FP64.
+__global__ void __launch_bounds__(kWG) k_moments32(DevInst I, PSet P, const long long* cnt, double* acc) {
+    const long long slots = cnt[C_SLOTS];
+    for (long long q = (long long)blockIdx.x * kWG + threadIdx.x; q < slots; q += (long long)gridDim.x * kWG) {
+        const long long p = I.p_off + q;
+        const float r = P.r[p];
+        if (r < 0.0f) continue;
+        moments_add(I, (double)r, (double)P.z[p], (double)P.vr[p], (double)P.vt[p], (double)P.vz[p], (double)P.w[p],
+                    acc);
+    }
+}
+
 // Tail plan of the coming step (see prep_tails) when no field stage ran
 // since the counters changed (after a full sort).
 __global__ void k_prep(long long* ctl, const long long* cnt, int n_inst) {
@@ -1910,5 +1923,14 @@ pic_status f32_tuning(pic_ctx* ctx, int* tile_r, int* tile_z, int* halo, int* so
     if (halo) *halo = S->halo;
     if (sort_interval) *sort_interval = S->K;
     if (chunk) *chunk = S->C;
+    return PIC_OK;
+}
+
+pic_status f32_moments(pic_ctx* ctx, int k, double* acc) {
+    F32State* S = pic_get_f32(ctx);
+    const DevInst& I = pic_inst_dev(ctx, k);
+    hipLaunchKernelGGL(k_moments32, dim3(grid_for(I.p_cap)), dim3(kWG), 0, pic_stream(ctx), I, S->set[S->cur],
+                       pic_counters(ctx) + (long long)k * C_NCOUNT, acc);
+    CK32(hipGetLastError());
     return PIC_OK;
 }

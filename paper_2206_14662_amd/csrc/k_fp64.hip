@@ -262,6 +262,17 @@ __global__ void __launch_bounds__(kBlock) k_source64(DevInst I, P64 p, long long
     if (blockIdx.x == 0 && threadIdx.x == 0 && count > 0) atomicAdd((unsigned long long*)&cnt[C_SOURCE], count);
 }
 
+// Fluid-moment node sums of every live particle (diagnostic).
+__global__ void __launch_bounds__(kBlock) k_moments64(DevInst I, P64 p, const long long* cnt, double* acc) {
+    const long long n = cnt[C_SLOTS];
+    for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < n;
+         q += (long long)gridDim.x * blockDim.x) {
+        const double r = p.r[q];
+        if (r < 0.0) continue;
+        moments_add(I, r, p.z[q], p.vr[q], p.vt[q], p.vz[q], p.w[q], acc);
+    }
+}
+
 // Fixed-point deposit: node charges rint(W w_k) for three nodes, the fourth
 // takes the remainder so every particle adds exactly W.
 __global__ void __launch_bounds__(kBlock) k_deposit64(DevInst I, P64 p, long long* __restrict__ Q,
@@ -343,6 +354,11 @@ hipError_t launch_mcc64(const DevInst& I, P64 p, long long* cnt, long long grid_
 hipError_t launch_source64(const DevInst& I, P64 p, long long* cnt, hipStream_t s) {
     const long long most = (long long)ceil(I.src_rate) + 1;
     hipLaunchKernelGGL(k_source64, dim3(grid_for(most)), dim3(kBlock), 0, s, I, p, cnt);
+    return hipGetLastError();
+}
+
+hipError_t launch_moments64(const DevInst& I, P64 p, const long long* cnt, double* acc, hipStream_t s) {
+    hipLaunchKernelGGL(k_moments64, dim3(grid_for(I.p_cap)), dim3(kBlock), 0, s, I, p, cnt, acc);
     return hipGetLastError();
 }
 

@@ -127,6 +127,35 @@ __device__ __forceinline__ double u52(unsigned int hi, unsigned int lo) {
     return ((double)(x >> 12) + 0.5) * 0x1p-52;
 }
 
+// Fluid moments: channels n, n u (r, t, z), sum w v_a v_b (rr, rt, rz, tt,
+// tz, zz) and sum w nu_m with nu_m = n_n (sigma_el + sigma_iz(E)) |v|, each as
+// a bilinear (hat-function) node sum; divided by the node volume afterwards.
+constexpr int kMoments = 11;
+
+__device__ inline void moments_add(const DevInst& I, double r, double z, double vr, double vt, double vz, double w,
+                                   double* __restrict__ acc) {
+#pragma clang fp contract(off)
+    double s = (r - I.a) * I.inv_dr;
+    int i = (int)floor(s);
+    i = i < 0 ? 0 : (i > I.nr - 1 ? I.nr - 1 : i);
+    const double fr = s - (double)i;
+    double t = z * I.inv_dz;
+    int j = (int)floor(t);
+    j = j < 0 ? 0 : (j > I.nz - 1 ? I.nz - 1 : j);
+    const double fz = t - (double)j;
+    const double sw[4] = {(1.0 - fr) * (1.0 - fz), fr * (1.0 - fz), (1.0 - fr) * fz, fr * fz};
+    const long long n00 = (long long)i * I.W + j;
+    const long long node[4] = {n00, n00 + I.W, n00 + 1, n00 + I.W + 1};
+    const double v2 = (vr * vr + vt * vt) + vz * vz, v = sqrt(v2);
+    const double E = v2 * I.half_me_over_e;
+    const double sig_iz = E > I.iz_I ? (I.lotz_aq * log(E / I.iz_I)) / (E * I.iz_I) : 0.0;
+    const double nu = (I.nsig_el + I.n_n * sig_iz) * v;
+    const double q[kMoments] = {1.0, vr, vt, vz, vr * vr, vr * vt, vr * vz, vt * vt, vt * vz, vz * vz, nu};
+    const long long N = I.nodes;
+    for (int c = 0; c < kMoments; ++c)
+        for (int k = 0; k < 4; ++k) atomicAdd(&acc[c * N + node[k]], (w * sw[k]) * q[c]);
+}
+
 // Seed source of step `step`: how many electrons it creates and the running
 // index of the first (floor((n+1) R) - floor(n R) and floor(n R), R per step).
 __device__ __forceinline__ void source_count(const DevInst& I, long long step, long long& first, long long& count) {
@@ -184,6 +213,8 @@ hipError_t launch_push64(const DevInst& I, P64 p, const double* Er, const double
                          hipStream_t s);
 // Seed-source electrons of the step appended after the slots (FP64 form).
 hipError_t launch_source64(const DevInst& I, P64 p, long long* cnt, hipStream_t s);
+// Fluid-moment node sums of the FP64 store into acc (kMoments x nodes, zeroed).
+hipError_t launch_moments64(const DevInst& I, P64 p, const long long* cnt, double* acc, hipStream_t s);
 hipError_t launch_mcc64(const DevInst& I, P64 p, long long* cnt, long long grid_cap,
                         hipStream_t s);
 hipError_t launch_deposit64(const DevInst& I, P64 p, long long* Q, long long* cnt,
