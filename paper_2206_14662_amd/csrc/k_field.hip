@@ -283,27 +283,30 @@ __global__ void __launch_bounds__(64 * kThomasSeg) kf_thomas(const DevInst* __re
     }
 }
 
-// The same partitioned solve with kThomasSegReg segments of at most R rows
-// whose values stay in registers between the sweeps: the right-hand side is
-// read once and the solution written once.
-template <int R>
+// The same partitioned solve with segments of at most R rows whose values
+// stay in registers between the sweeps: the right-hand side is read once and
+// the solution written once.  SPLIT = 1: one wave per segment, 64 modes per
+// block, kThomasSegReg segments; SPLIT = 2: each half wave takes a segment,
+// 32 modes per block, 2 kThomasSegReg segments (meshes up to twice as tall).
+template <int R, int SPLIT>
 __global__ void __launch_bounds__(64 * kThomasSegReg) kf_thomas_reg(const DevInst* __restrict__ It,
                                                                     const FieldDev* __restrict__ Ft,
                                                                     int inst_base) {
-    constexpr int P = kThomasSegReg;
+    constexpr int P = kThomasSegReg * SPLIT;
+    constexpr int MB = 64 / SPLIT;  // modes per block
     constexpr int B = R < 8 ? R : 8;  // rows whose loads are issued together
-    __shared__ double s_val[P][64], s_fac[P][64];
+    __shared__ double s_val[P][MB], s_fac[P][MB];
     const int inst = inst_base + blockIdx.y;
     const DevInst& I = It[inst];
     const FieldDev& F = Ft[inst];
     if (I.frozen) return;
-    // one wave per segment: the segment index and all row offsets are
-    // wave-uniform (scalar registers); only the mode column varies by lane
-    const int lane = threadIdx.x, sg = __builtin_amdgcn_readfirstlane(threadIdx.y);
+    // SPLIT = 1: the segment index and the row offsets are wave-uniform
+    const int lane = threadIdx.x % MB;
+    const int sg = SPLIT == 1 ? __builtin_amdgcn_readfirstlane(threadIdx.y) : threadIdx.y * SPLIT + threadIdx.x / MB;
     // modes 1..nz-1 (sine, Dirichlet ends) or 0..nz (cosine, open ends)
     const int kfirst = I.open_ends ? 0 : 1, klast = I.open_ends ? I.nz : I.nz - 1;
-    const int k = kfirst + blockIdx.x * 64 + lane;
-    if (kfirst + (int)blockIdx.x * 64 > klast) return;  // whole block past the modes
+    const int k = kfirst + blockIdx.x * MB + lane;
+    if (kfirst + (int)blockIdx.x * MB > klast) return;  // whole block past the modes
     const bool valid = k <= klast;
     const int kk = valid ? k : kfirst;
     const int W = I.W;  // node offsets fit 32 bits ((nr+1)(nz+1) < 2^31)
@@ -318,7 +321,7 @@ __global__ void __launch_bounds__(64 * kThomasSegReg) kf_thomas_reg(const DevIns
     const double* __restrict__ G = F.th_G;
     const double* __restrict__ H = F.th_H;
     // rows past the segment read a valid row (clamped) and are not used
-    auto node = [&](int u) { return min(r0 + u, nri) * W + kk; };  // row part is uniform
+    auto node = [&](int u) { return min(r0 + u, nri) * W + kk; };
     double v[R];
     double d = 0.0;
 #pragma unroll
@@ -509,11 +512,18 @@ hipError_t launch_solve_tab(const DevInst* It, const FieldDev* Ft, int inst_base
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     dim3 gth((unsigned)((max_nz + 1 + 63) / 64), (unsigned)n_inst);  // up to nz + 1 modes
-    if (thomas_segments(max_nr) == kThomasSegReg) {
-        const int rows = (max_nr - 1 + kThomasSegReg - 1) / kThomasSegReg;
+    const int nseg = thomas_segments(max_nr);
+    if (nseg == kThomasSegReg || nseg == 2 * kThomasSegReg) {
+        const int rows = (max_nr - 1 + nseg - 1) / nseg;
         const dim3 blk(64, kThomasSegReg);
-        if (rows <= 8) hipLaunchKernelGGL(kf_thomas_reg<8>, gth, blk, 0, s, It, Ft, inst_base);
-        else hipLaunchKernelGGL(kf_thomas_reg<16>, gth, blk, 0, s, It, Ft, inst_base);
+        if (nseg == 2 * kThomasSegReg) {
+            const dim3 g2((unsigned)((max_nz + 1 + 31) / 32), (unsigned)n_inst);
+            hipLaunchKernelGGL((kf_thomas_reg<16, 2>), g2, blk, 0, s, It, Ft, inst_base);
+        } else if (rows <= 8) {
+            hipLaunchKernelGGL((kf_thomas_reg<8, 1>), gth, blk, 0, s, It, Ft, inst_base);
+        } else {
+            hipLaunchKernelGGL((kf_thomas_reg<16, 1>), gth, blk, 0, s, It, Ft, inst_base);
+        }
     } else {
         hipLaunchKernelGGL(kf_thomas, gth, dim3(64, kThomasSeg), 0, s, It, Ft, inst_base);
     }

@@ -31,14 +31,14 @@ def kernel_source_hash():
 
 
 def short_name(name):
-    m = re.search(r"((?:k|kf|ks|kz)_[A-Za-z0-9_]+(?:<\d+>)?)\(", name)
+    m = re.search(r"((?:k|kf|ks|kz)_[A-Za-z0-9_]+(?:<[0-9, ]+>)?)\(", name)
     if m:
         return m.group(1)
     return name.split("(")[0][:48]
 
 
 def family(name):
-    return re.sub(r"<\d+>$", "", name)
+    return re.sub(r"<[0-9, ]+>$", "", name)
 
 
 def stats(csv_path, out_path, command):

@@ -98,7 +98,14 @@ def test_vacuum_potential(end_mode):
     assert np.array_equal(f["Br"], Br) and np.array_equal(f["Bz"], Bz)
 
 
-@pytest.mark.parametrize("maker,end_mode", [(pi.coax64, 0), (pi.coax256, 0), (pi.coax64, 2), (pi.coax256, 2)])
+def tall(**kw):
+    """A mesh taller than 257 cells in r (the tridiagonal solve then holds two
+    row segments per wave)."""
+    return pi.coax64(nr=400, nz=256, **kw)
+
+
+@pytest.mark.parametrize("maker,end_mode", [(pi.coax64, 0), (pi.coax256, 0), (tall, 0), (pi.coax64, 2),
+                                            (pi.coax256, 2), (tall, 2)])
 def test_poisson_solve_matches_oracle(maker, end_mode):
     cfg = maker(end_mode=end_mode)
     st = pi.cloud_state(cfg, 50000, seed=11)
