@@ -102,6 +102,7 @@ def lib():
         L.orc_get_diag.argtypes = [C.c_void_p, C.POINTER(OrcDiag)]
         L.orc_get_time_avg_density.argtypes = [C.c_void_p, _D]
         L.orc_moments.argtypes = [C.c_void_p, _D]
+        L.orc_well_depth.argtypes = [C.POINTER(OrcCfg), _D, C.c_int, _D, _D, _D]
         L.orc_num_threads.restype = C.c_int
         _lib = L
     return _lib
@@ -225,6 +226,18 @@ def deposit_one(d, r, z, w, fx_shift=None):
     Q = np.zeros(_nodes(d), dtype=np.int64)
     lib().orc_deposit_one(C.byref(c), float(r), float(z), float(w), Q.ctypes.data_as(_I64))
     return Q.reshape(_shape(d))
+
+
+def well_depth(d, phi, r_mid):
+    """Well depth (V) and the position of the potential maximum along the
+    field lines through r_mid at the midplane."""
+    c = make_cfg(d)
+    phi = np.ascontiguousarray(phi, dtype=np.float64).reshape(-1)
+    r = np.ascontiguousarray(r_mid, dtype=np.float64)
+    dep = np.zeros(len(r))
+    zm = np.zeros(len(r))
+    lib().orc_well_depth(C.byref(c), _dp(phi), len(r), _dp(r), _dp(dep), _dp(zm))
+    return dep, zm
 
 
 def num_threads():

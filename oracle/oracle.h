@@ -109,6 +109,14 @@ void orc_poisson_charge(const orc_cfg* c, const int64_t* Q, double* phi_sc);
 void orc_efield(const orc_cfg* c, const double* phi, double* Er, double* Ez);
 void orc_node_volume(const orc_cfg* c, double* V);
 void orc_deposit_one(const orc_cfg* c, double r, double z, double w, int64_t* Q);
+/* Potential-well depth along the configured magnetic field lines (Sec. II.B):
+ * line l passes r_mid[l] at z = L/2 and keeps r^2 Bz(z) constant; phi is
+ * sampled (bilinearly) at every node column inside a < r < b; depth[l] =
+ * max phi - max(min phi left of it, min phi right of it) in volts (eV for an
+ * electron), z_max[l] the position of the maximum (-1 and 0 when the line
+ * leaves the domain at the midplane). */
+void orc_well_depth(const orc_cfg* c, const double* phi, int n_lines, const double* r_mid, double* depth,
+                    double* z_max);
 
 /* Fluid moments (Sec. IV: force terms from moments of the distribution):
  * number of channels and their order in orc_moments' output. */

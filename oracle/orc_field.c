@@ -321,3 +321,54 @@ void orc_node_volume(const orc_cfg* c, double* V) {
         }
     }
 }
+
+/*
+ * Potential-well depth along magnetic field lines, as the paper defines it
+ * after Pagonakis et al. (Sec. II.B): along a field line the electrons'
+ * trap is a local maximum of phi (a minimum of their potential energy); its
+ * depth is that maximum less the higher of the lowest values on either side.
+ * Field lines of Bz = B0 (1 + k zeta^2), Br = -(r/2) dBz/dz conserve r^2 Bz.
+ */
+void orc_well_depth(const orc_cfg* c, const double* phi, int n_lines, const double* r_mid, double* depth,
+                    double* z_max) {
+    const int nr = c->nr, nz = c->nz, W = nz + 1;
+    const double dr = (c->b - c->a) / (double)nr, dz = c->L / (double)nz, halfL = 0.5 * c->L;
+    double* U = (double*)malloc(sizeof(double) * (size_t)W);
+    int* in = (int*)malloc(sizeof(int) * (size_t)W);
+    for (int l = 0; l < n_lines; ++l) {
+        const double Bmid = c->B0;  /* zeta = 0 */
+        for (int j = 0; j <= nz; ++j) {
+            const double z = (double)j * dz, zeta = (z - halfL) / halfL;
+            const double Bz = c->B0 * (1.0 + c->mirror_k * (zeta * zeta));
+            const double r = r_mid[l] * sqrt(Bmid / Bz);
+            in[j] = r > c->a && r < c->b;
+            U[j] = 0.0;
+            if (!in[j]) continue;
+            double s = (r - c->a) / dr;
+            int i = (int)floor(s);
+            if (i > nr - 1) i = nr - 1;
+            const double fr = s - (double)i;
+            int jj = j < nz ? j : nz - 1;
+            const double fz = (z - (double)jj * dz) / dz;
+            const double* P = phi + (size_t)i * W + jj;
+            U[j] = ((1.0 - fr) * (1.0 - fz) * P[0] + fr * (1.0 - fz) * P[W]) + ((1.0 - fr) * fz * P[1] + fr * fz * P[W + 1]);
+        }
+        const int jm = nz / 2;
+        depth[l] = 0.0;
+        z_max[l] = -1.0;
+        if (!in[jm]) continue;
+        int lo = jm, hi = jm;
+        while (lo > 0 && in[lo - 1]) --lo;
+        while (hi < nz && in[hi + 1]) ++hi;
+        int jx = lo;
+        for (int j = lo; j <= hi; ++j)
+            if (U[j] > U[jx]) jx = j;
+        double left = U[jx], right = U[jx];
+        for (int j = lo; j <= jx; ++j) left = U[j] < left ? U[j] : left;
+        for (int j = jx; j <= hi; ++j) right = U[j] < right ? U[j] : right;
+        depth[l] = U[jx] - (left > right ? left : right);
+        z_max[l] = (double)jx * dz;
+    }
+    free(U);
+    free(in);
+}

@@ -749,3 +749,41 @@ def test_moments_drifting_maxwellian_pressure_and_drag():
     m2 = o2.moments()
     d = oracle.derive(c)
     np.testing.assert_allclose(m2[10], d["nsig_el"] * v0 * m2[0], rtol=1e-12, atol=0)
+
+
+# --------------------------------------------------------------------------
+# Potential-well depth along field lines (Sec. II.B)
+# --------------------------------------------------------------------------
+
+def test_well_depth_of_the_relative_end_plates_is_the_end_bias():
+    """Uniform B: field lines are r = const.  With end plates at the coaxial
+    profile + V_end the vacuum well on every line is |V_end| deep (the trap is
+    long compared with b - a, so the middle sits at the coaxial profile), its
+    maximum at mid-length; open ends give no well."""
+    c = pi.coax64(nr=64, nz=128, mirror_k=0.0)
+    r = np.array([2e-3, 4e-3, 6e-3, 8e-3])
+    dep, zm = oracle.well_depth(c, oracle.vacuum(c), r)
+    np.testing.assert_allclose(dep, abs(c["V_end"]), rtol=5e-3)
+    np.testing.assert_allclose(zm, c["L"] / 2)
+    c2 = dict(c, end_mode=2)
+    dep2, _ = oracle.well_depth(c2, oracle.vacuum(c2), r)
+    assert np.max(np.abs(dep2)) <= 1e-9 * abs(c["V_inner"])
+
+
+def test_well_depth_brute_force_on_a_given_profile():
+    """On lines through node radii (uniform B) phi is sampled at the nodes
+    exactly: the depth is the brute-force max minus the higher side minimum;
+    lines leaving the domain at the midplane report none."""
+    c = pi.coax64(nr=8, nz=16, mirror_k=0.0)
+    d = oracle.derive(c)
+    z = np.arange(17) * d["dz"]
+    rng = np.random.default_rng(5)
+    prof = rng.normal(size=17) * 100.0
+    phi = np.tile(prof, (9, 1))
+    r_nodes = c["a"] + d["dr"] * np.array([1.0, 3.0, 6.0])
+    dep, zm = oracle.well_depth(c, phi, np.append(r_nodes, c["b"] + 1e-3))
+    jx = int(np.argmax(prof))
+    want = prof[jx] - max(prof[:jx + 1].min(), prof[jx:].min())
+    np.testing.assert_allclose(dep[:3], want, rtol=1e-12)
+    np.testing.assert_allclose(zm[:3], z[jx])
+    assert dep[3] == 0.0 and zm[3] == -1.0
