@@ -312,6 +312,19 @@ pic_status pic_reserve(pic_ctx* ctx, int inst, long long slots);
  */
 pic_status pic_moments(pic_ctx* ctx, int inst, double* out);
 
+/*
+ * pic_well_depth -- depth (V; eV for an electron) of the potential well along
+ * n_lines magnetic field lines of instance `inst` (Sec. II.B defines the well
+ * along field lines): line l passes radius r_mid[l] at z = L/2 and follows the
+ * configured field (r^2 Bz conserved); phi is interpolated at every node
+ * column the line crosses inside a < r < b.  depth[l] = max phi - max(lowest
+ * phi before it, lowest phi after it); z_max[l] = position of the maximum,
+ * -1 (and depth 0) if the line is outside the domain at mid-length.  Host
+ * arrays of n_lines doubles; synchronises.  Errors: PIC_EINVAL, PIC_EDEVICE.
+ */
+pic_status pic_well_depth(pic_ctx* ctx, int inst, int n_lines, const double* r_mid, double* depth,
+                          double* z_max);
+
 /* pic_capacity -- the slots of instance `inst` and the number of storage
  * regrowths so far (per context). */
 pic_status pic_capacity(pic_ctx* ctx, int inst, long long* slots, long long* grow_events);

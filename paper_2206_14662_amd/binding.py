@@ -88,7 +88,7 @@ EXPORTS = ("pic_init", "pic_step", "pic_diag", "pic_destroy", "pic_last_error", 
            "pic_get_particles", "pic_set_particles", "pic_set_fields", "pic_get_fields",
            "pic_get_charge", "pic_get_phi", "pic_set_step", "pic_derive", "pic_auto_shift",
            "pic_timing", "pic_tuning", "pic_retune", "pic_autotune", "pic_reserve", "pic_capacity",
-           "pic_moments")
+           "pic_moments", "pic_well_depth")
 
 _lib = None
 _D = C.POINTER(C.c_double)
@@ -137,6 +137,7 @@ def lib():
     L.pic_reserve.argtypes = [vp, C.c_int, C.c_longlong]
     L.pic_capacity.argtypes = [vp, C.c_int, _LL, _LL]
     L.pic_moments.argtypes = [vp, C.c_int, _D]
+    L.pic_well_depth.argtypes = [vp, C.c_int, C.c_int, _D, _D, _D]
     for name in EXPORTS:
         if name not in ("pic_last_error", "pic_auto_shift"):
             getattr(L, name).restype = C.c_int
@@ -375,6 +376,15 @@ def pic_moments(ctx, inst, nodes):
     return out
 
 
+def pic_well_depth(ctx, inst, r_mid):
+    r = np.ascontiguousarray(r_mid, dtype=np.float64)
+    dep = np.zeros(len(r))
+    zm = np.zeros(len(r))
+    _check(lib().pic_well_depth(ctx, int(inst), len(r), r.ctypes.data_as(_D), dep.ctypes.data_as(_D),
+                                zm.ctypes.data_as(_D)), ctx)
+    return dep, zm
+
+
 class Sim:
     """Convenience holder of one context and its instance list."""
 
@@ -440,6 +450,9 @@ class Sim:
         """(11, nr+1, nz+1): n, n u_r, n u_t, n u_z, second moments (rr, rt, rz,
         tt, tz, zz), sum w nu_m / V."""
         return pic_moments(self.ctx, k, self.nodes(k)).reshape((11,) + self.shapes[k])
+
+    def well_depth(self, r_mid, k=0):
+        return pic_well_depth(self.ctx, k, r_mid)
 
     def capacity(self, k=0):
         return pic_capacity(self.ctx, k)

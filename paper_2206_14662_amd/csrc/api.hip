@@ -1177,3 +1177,54 @@ extern "C" pic_status pic_moments(pic_ctx* ctx, int k, double* out) {
         for (long long n = 0; n < N; ++n) out[c * N + n] /= in.V_host[n];
     return PIC_OK;
 }
+
+// Potential-well depth along the configured field lines (Sec. II.B): the
+// trap of an electron on a line is a maximum of phi; its depth is that
+// maximum less the higher of the lowest values on its two sides.  Lines of
+// Bz = B0 (1 + k zeta^2), Br = -(r/2) Bz' keep r^2 Bz fixed.  Host work on a
+// copy of the solved potential.
+extern "C" pic_status pic_well_depth(pic_ctx* ctx, int k, int n_lines, const double* r_mid, double* depth,
+                                     double* z_max) {
+    pic_status st = check_inst(ctx, k);
+    if (st != PIC_OK) return st;
+    if (n_lines < 0 || (n_lines > 0 && (!r_mid || !depth || !z_max))) return fail(ctx, PIC_EINVAL, "bad line arrays");
+    Inst& in = ctx->in[k];
+    const pic_instance_cfg& c = in.c;
+    const int nr = c.nr, nz = c.nz, W = nz + 1;
+    std::vector<double> phi((size_t)in.nodes);
+    CK(hipStreamSynchronize(ctx->stream));
+    CK(hipMemcpy(phi.data(), in.phi, sizeof(double) * phi.size(), hipMemcpyDeviceToHost));
+    const double dr = (c.b - c.a) / (double)nr, dz = c.L / (double)nz, halfL = 0.5 * c.L;
+    std::vector<double> U((size_t)W);
+    std::vector<char> inside((size_t)W);
+    for (int l = 0; l < n_lines; ++l) {
+        for (int j = 0; j <= nz; ++j) {
+            const double z = (double)j * dz, zeta = (z - halfL) / halfL;
+            const double r = r_mid[l] * sqrt(c.B0 / (c.B0 * (1.0 + c.mirror_k * (zeta * zeta))));
+            inside[j] = r > c.a && r < c.b;
+            U[j] = 0.0;
+            if (!inside[j]) continue;
+            const double s = (r - c.a) / dr;
+            const int i = std::min((int)floor(s), nr - 1);
+            const double fr = s - (double)i;
+            const int jc = std::min(j, nz - 1);
+            const double fz = (z - (double)jc * dz) / dz;
+            const double* P = phi.data() + (size_t)i * W + jc;
+            U[j] = ((1.0 - fr) * (1.0 - fz) * P[0] + fr * (1.0 - fz) * P[W]) +
+                   ((1.0 - fr) * fz * P[1] + fr * fz * P[W + 1]);
+        }
+        depth[l] = 0.0;
+        z_max[l] = -1.0;
+        const int mid = nz / 2;
+        if (!inside[mid]) continue;
+        int lo = mid, hi = mid;
+        while (lo > 0 && inside[lo - 1]) --lo;
+        while (hi < nz && inside[hi + 1]) ++hi;
+        const int top = (int)(std::max_element(U.begin() + lo, U.begin() + hi + 1) - U.begin());
+        const double left = *std::min_element(U.begin() + lo, U.begin() + top + 1);
+        const double right = *std::min_element(U.begin() + top, U.begin() + hi + 1);
+        depth[l] = U[top] - std::max(left, right);
+        z_max[l] = (double)top * dz;
+    }
+    return PIC_OK;
+}

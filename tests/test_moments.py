@@ -35,3 +35,18 @@ def test_moments_match_the_oracle(mode):
     V = oracle.node_volume(cfg).reshape(mg.shape[1:])
     assert (mg[0] * V).sum() == pytest.approx(g.diag()["n_live"] * cfg["weight"], rel=1e-12)
     g.close()
+
+
+@pytest.mark.parametrize("end_mode,mirror", [(0, 0.0), (0, 0.3), (2, 0.3)])
+def test_well_depth_matches_the_oracle(end_mode, mirror):
+    cfg = pi.coax64(end_mode=end_mode, mirror_k=mirror, p_mbar=10.0, E_cap_eV=3000.0)
+    g = B.Sim([cfg], mode=B.PIC_MODE_FP64_PLAIN)
+    r = np.linspace(1.5e-3, 9.5e-3, 17)
+    # the library's depth on its own potential equals the oracle's on the same array
+    for steps in (0, 20):
+        g.step(steps)
+        dep, zm = g.well_depth(r)
+        dep_o, zm_o = oracle.well_depth(cfg, g.phi(), r)
+        np.testing.assert_allclose(dep, dep_o, rtol=1e-12, atol=1e-9)
+        np.testing.assert_array_equal(zm, zm_o)
+    g.close()
