@@ -27,9 +27,11 @@ sys.path.insert(0, ROOT)
 
 METRIC = "particle-steps/s (push+gather+deposit+MCC), batched FP32 vs plain FP64, 1 GPU"
 HBM_PEAK_GBS = 8000.0
-# algorithmic bytes per particle-step of the fused FP32 kernel:
-# read r, z, vr, vt, vz, w (6 x 4 B) + key (8 B), write r, z, vr, vt, vz (5 x 4 B)
-BYTES_FP32 = 52
+# algorithmic bytes per particle-step of the fused FP32 kernel: read r, z, vr,
+# vt, vz (5 x 4 B) + key (8 B), write r, z, vr, vt, vz (5 x 4 B); every electron
+# of these workloads carries its instance's macro-weight, so the weight array
+# is not read (a per-particle weight would add 4 B)
+BYTES_FP32 = 48
 # plain FP64 push kernel: read r, z, vr, vt, vz (5 x 8 B) + w on absorption only, write 5 x 8 B
 BYTES_FP64_PUSH = 80
 

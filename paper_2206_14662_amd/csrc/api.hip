@@ -356,6 +356,7 @@ static void fill_devinst(Inst& in) {
     I.src_rate = c.src_rate;
     I.src_sv = sqrt(((c.src_T_eV > 0.0 ? c.src_T_eV : c.T_init_eV) * kE) / kMe);
     I.weight = c.weight;
+    I.w_uni = (float)c.weight;
 }
 
 static pic_status upload_tables(pic_ctx* ctx) {

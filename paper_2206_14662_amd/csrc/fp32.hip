@@ -105,6 +105,12 @@ struct KArgs {
 
 // ---- shared device helpers ------------------------------------------------
 
+// Weight of the particle in slot p: the instance's common weight when it has
+// one, else the per-particle array.
+__device__ __forceinline__ float weight_at(const DevInst& I, const PSet& P, long long p) {
+    return I.w_uni != 0.0f ? I.w_uni : P.w[p];
+}
+
 __device__ __forceinline__ void cell_of(const DevInst& I, float r, float z, int& i, int& j, float& fr,
                                         float& fz) {
     float s = (r - I.a_f) * I.inv_dr_f;
@@ -121,7 +127,7 @@ __device__ __forceinline__ void cell_of(const DevInst& I, float r, float z, int&
 // Per-chunk copy of the instance constants the particle loop reads, kept in
 // registers so stores to the particle arrays never force them to be reloaded.
 struct LocalInst {
-    float a, b, L, inv_dr, inv_dz, h, dt, v_cap2, two_S;
+    float a, b, L, inv_dr, inv_dz, h, dt, v_cap2, two_S, w_uni;
     int nr, nz, W, ntz, tile_off, collisions;
     unsigned int seed_lo, seed_hi;
     unsigned long long null_k;
@@ -137,6 +143,7 @@ __device__ __forceinline__ LocalInst local_inst(const DevInst& I) {
     L.inv_dr = uniform_f(I.inv_dr_f); L.inv_dz = uniform_f(I.inv_dz_f);
     L.h = uniform_f(I.h_f); L.dt = uniform_f(I.dt_f); L.v_cap2 = uniform_f(I.v_cap2_f);
     L.two_S = uniform_f((float)I.two_S);
+    L.w_uni = uniform_f(I.w_uni);
     L.nr = __builtin_amdgcn_readfirstlane(I.nr); L.nz = __builtin_amdgcn_readfirstlane(I.nz);
     L.W = __builtin_amdgcn_readfirstlane(I.W); L.ntz = __builtin_amdgcn_readfirstlane(I.ntz);
     L.tile_off = __builtin_amdgcn_readfirstlane(I.tile_off);
@@ -434,7 +441,7 @@ __device__ __forceinline__ void push_particle(const KArgs& A, const ChunkCtx& X,
         out.vt[dst] = vtn;
         out.vz[dst] = vz;
         if (SCATTER) {
-            out.w[dst] = w;
+            if (L.w_uni == 0.0f) out.w[dst] = w;
             out.key[dst] = key;
         }
         // deposit at the new position
@@ -628,6 +635,7 @@ __global__ void __launch_bounds__(kPWG) __attribute__((amdgpu_waves_per_eu(8, 8)
         // stores cover whole aligned lines; lanes before the chunk idle.
         constexpr int U = 1;
         const int lead = (int)(start & 63);
+        const float wu = X.L.w_uni;
         for (int base = -lead; base < count; base += U * kPWG) {
             long long pp[U];
             bool inr[U];
@@ -643,7 +651,7 @@ __global__ void __launch_bounds__(kPWG) __attribute__((amdgpu_waves_per_eu(8, 8)
                 vr[u] = A.p.vr[pp[u]];
                 vt[u] = A.p.vt[pp[u]];
                 vz[u] = A.p.vz[pp[u]];
-                w[u] = A.p.w[pp[u]];
+                w[u] = wu != 0.0f ? wu : A.p.w[pp[u]];
                 key[u] = A.p.key[pp[u]];
             }
 #pragma unroll
@@ -692,7 +700,7 @@ __global__ void __launch_bounds__(kWG) k_collide(KArgs A, PSet P, int scatter) {
         const unsigned long long key = P.key[p];
         const uint4 b0 = philox_step(I, key, step, 0u);
         float vr = P.vr[p], vt = P.vt[p], vz = P.vz[p];
-        const float r = P.r[p], z = P.z[p], w = P.w[p];
+        const float r = P.r[p], z = P.z[p], w = weight_at(I, P, p);
         const long long base = scatter ? A.new_base[inst] : cnt[C_SLOTS];
         const int ev = collide_f(I, cnt, P, key, step, b0, r, z, w, vr, vt, vz, base);
         if (ev == 0) continue;
@@ -771,8 +779,8 @@ __global__ void __launch_bounds__(kWG) k_moments32(DevInst I, PSet P, const long
         const long long p = I.p_off + q;
         const float r = P.r[p];
         if (r < 0.0f) continue;
-        moments_add(I, (double)r, (double)P.z[p], (double)P.vr[p], (double)P.vt[p], (double)P.vz[p], (double)P.w[p],
-                    acc);
+        moments_add(I, (double)r, (double)P.z[p], (double)P.vr[p], (double)P.vt[p], (double)P.vz[p],
+                    (double)weight_at(I, P, p), acc);
     }
 }
 
@@ -902,7 +910,7 @@ __global__ void __launch_bounds__(kWG) k_sort_scatter(KArgs A, PSet dst, const u
         dst.vr[d] = A.p.vr[p];
         dst.vt[d] = A.p.vt[p];
         dst.vz[d] = A.p.vz[p];
-        dst.w[d] = A.p.w[p];
+        if (I.w_uni == 0.0f) dst.w[d] = A.p.w[p];
         dst.key[d] = A.p.key[p];
     }
 }
@@ -975,7 +983,7 @@ __global__ void k_deposit32(DevInst I, PSet P, long long* Q, const long long* cn
         float fr, fz;
         cell_of(I, r, P.z[p], i, j, fr, fz);
         long long q00, q10, q01, q11;
-        node_charges(P.w[p], (float)I.two_S, fr, fz, q00, q10, q01, q11);
+        node_charges(weight_at(I, P, p), (float)I.two_S, fr, fz, q00, q10, q01, q11);
         unsigned long long* Qg = (unsigned long long*)Q;
         long long n00 = (long long)i * I.W + j;
         atomicAdd(&Qg[n00], (unsigned long long)q00);
@@ -1859,7 +1867,10 @@ pic_status f32_set_particles(pic_ctx* ctx, int k, long long n, const double* r, 
                              const unsigned long long* key) {
     F32State* S = pic_get_f32(ctx);
     const DevInst& I = pic_inst_dev(ctx, k);
-    if (n <= 0) return PIC_OK;
+    if (n <= 0) {
+        pic_inst_dev(ctx, k).w_uni = (float)I.weight;
+        return pic_upload_inst(ctx);
+    }
     std::vector<float> buf((size_t)n);
     const double* src[6] = {r, z, vr, vt, vz, w};
     float* dst[6] = {S->set[S->cur].r, S->set[S->cur].z, S->set[S->cur].vr,
@@ -1869,7 +1880,14 @@ pic_status f32_set_particles(pic_ctx* ctx, int k, long long n, const double* r, 
         CK32(hipMemcpy(dst[a] + I.p_off, buf.data(), sizeof(float) * n, hipMemcpyHostToDevice));
     }
     CK32(hipMemcpy(S->set[S->cur].key + I.p_off, key, sizeof(unsigned long long) * n, hipMemcpyHostToDevice));
-    return PIC_OK;
+    // a common weight lets the particle loop skip the weight array; the seed
+    // source adds electrons of the configured weight, so with the source on
+    // the common weight must be that one
+    const float w0 = (float)w[0];
+    bool uni = !(I.src_rate > 0.0) || w0 == (float)I.weight;
+    for (long long q = 1; q < n && uni; ++q) uni = (float)w[q] == w0;
+    pic_inst_dev(ctx, k).w_uni = uni ? w0 : 0.0f;
+    return pic_upload_inst(ctx);
 }
 
 pic_status f32_get_particles(pic_ctx* ctx, int k, double* r, double* z, double* vr, double* vt, double* vz,
@@ -1890,6 +1908,7 @@ pic_status f32_get_particles(pic_ctx* ctx, int k, double* r, double* z, double* 
     std::vector<unsigned long long> kk((size_t)std::max(slots, 1ll));
     if (slots > 0)
         CK32(hipMemcpy(kk.data(), P.key + I.p_off, sizeof(unsigned long long) * slots, hipMemcpyDeviceToHost));
+    if (I.w_uni != 0.0f) std::fill(a[5].begin(), a[5].end(), I.w_uni);
     double* out[6] = {r, z, vr, vt, vz, w};
     long long m = 0;
     for (long long q = 0; q < slots; ++q) {

@@ -52,6 +52,10 @@ struct DevInst {
     double src_rate;                // macro-electrons per step (0: off)
     double src_sv;                  // its thermal speed sqrt(T e / m)
     double weight;                  // electrons per macro-electron of new source electrons
+    // FP32 form: the weight every particle of the instance carries, so the
+    // per-particle weight array is neither read nor kept up to date; 0 when
+    // weights differ between particles (the array is then authoritative)
+    float w_uni;
 };
 
 // Device counter block per instance (long long entries).

@@ -44,7 +44,48 @@ def trap(p_mbar, nr=128, nz=256, n0=1.0e15, weight=2.0e4, src_per_step=2.0, E_re
     return c, tau_d
 
 
-def run(pressures, taud=20.0, every=100, out=None, log=sys.stderr, **over):
+def force_balance(g, k, cfg, samples=64, gap=16):
+    """Sec. IV force terms of the electron fluid from the moments, averaged
+    over `samples` snapshots `gap` steps apart (several cyclotron periods),
+    in the cloud (n > 0.2 n_max).  With T = m_e sum w v v / V the full second
+    moment (inertia plus pressure), the momentum balance in (r, theta, z) reads
+        r:     -(dT_rr/dr + (T_rr - T_tt)/r + dT_rz/dz) + q n E_r + q G_t B_z - m D_r = 0
+        theta: -(dT_rt/dr + 2 T_rt/r + dT_tz/dz) + q (G_z B_r - G_r B_z) - m D_t = 0
+    with G = n u and D = (sum w nu_m / V) u the collisional drag.  Returns the
+    median over cloud nodes of |sum| / (sum of |terms|) for both equations,
+    and the median of the azimuthal drag-to-Lorentz ratio m D_t / (q G_r B_z)."""
+    import numpy as np
+    acc = None
+    for _ in range(samples):
+        g.step(gap)
+        m = g.moments(k)
+        acc = m if acc is None else acc + m
+    m = acc / samples
+    f = g.fields(k)
+    n, Gr, Gt, Gz = m[0], m[1], m[2], m[3]
+    Trr, Trt, Trz, Ttt, Ttz = (ME * m[i] for i in (4, 5, 6, 7, 8))
+    nu = m[10]
+    d = (cfg["b"] - cfg["a"]) / cfg["nr"], cfg["L"] / cfg["nz"]
+    r = (cfg["a"] + d[0] * np.arange(cfg["nr"] + 1))[:, None]
+    q = -E
+    safe = np.where(n > 0, n, 1.0)
+    Dr, Dt = nu * Gr / safe, nu * Gt / safe
+    grad = lambda a, ax: np.gradient(a, d[ax], axis=ax)
+    radial = [-grad(Trr, 0), -(Trr - Ttt) / r, -grad(Trz, 1), q * n * f["Er"], q * Gt * f["Bz"], -ME * Dr]
+    azim = [-grad(Trt, 0), -2.0 * Trt / r, -grad(Ttz, 1), q * Gz * f["Br"], -q * Gr * f["Bz"], -ME * Dt]
+    cloud = n > 0.2 * n.max()
+    cloud[0, :] = cloud[-1, :] = cloud[:, 0] = cloud[:, -1] = False
+
+    def resid(terms):
+        tot = np.abs(sum(terms))[cloud]
+        mag = sum(np.abs(t) for t in terms)[cloud]
+        return float(np.median(tot / np.maximum(mag, 1e-300)))
+    ratio = (ME * Dt) / np.where(np.abs(q * Gr * f["Bz"]) > 0, q * Gr * f["Bz"], 1.0)
+    return {"radial_residual": resid(radial), "azimuthal_residual": resid(azim),
+            "drag_over_radial_lorentz_theta": float(np.median(ratio[cloud])), "cloud_nodes": int(cloud.sum())}
+
+
+def run(pressures, taud=20.0, every=100, out=None, log=sys.stderr, balance=True, **over):
     import numpy as np
     import torch
 
@@ -73,6 +114,7 @@ def run(pressures, taud=20.0, every=100, out=None, log=sys.stderr, **over):
                   flush=True)
     wall = time.perf_counter() - t0
     final = [g.diag(k) for k in range(len(cfgs))]
+    forces = [force_balance(g, k, cfgs[k]) if balance else None for k in range(len(cfgs))]
     g.close()
     torch.cuda.synchronize()
     B0 = cfgs[0]["B0"]
@@ -91,6 +133,7 @@ def run(pressures, taud=20.0, every=100, out=None, log=sys.stderr, **over):
             "n_live_end": tr["n_live"][-1],
             "n_ioniz": int(final[k]["n_ioniz"]), "n_source": int(final[k]["n_source"]),
             "peak_over_brillouin": max(tr["n_peak"]) / n_brillouin,
+            "force_balance": forces[k],
         })
     res = {"pressures_mbar": pressures, "brillouin_density": n_brillouin, "wall_s": wall, "summary": summary,
            "traces": traces}

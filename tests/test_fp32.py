@@ -138,3 +138,65 @@ def test_fp32_tracks_fp64_over_a_run():
     assert gd["peak_density"] == pytest.approx(od["peak_density"], rel=0.02)
     assert gd["n_live"] == pytest.approx(od["n_live"], rel=0.02)
     assert gd["n_elastic"] == pytest.approx(od["n_elastic"], rel=0.05)
+
+
+def _weighted_runs(extra_w):
+    """The same cloud under frozen fields, plus one electron of weight
+    `extra_w` x the macro-weight that the outer wall absorbs in the first
+    step: with extra_w = 1 every weight is equal (the common-weight path),
+    otherwise the per-particle weight array is used."""
+    cfg = hot(n_init=0, p_mbar=10.0)
+    st = pi.cloud_state(cfg, 30000, seed=31)
+    st = {k: (v.astype(np.float32).astype(np.float64) if v.dtype == np.float64 else v) for k, v in st.items()}
+    doomed = np.uint64((1 << 62) - 1)
+    add = dict(r=cfg["b"] - 1e-6, z=cfg["L"] / 2, vr=1e7, vt=0.0, vz=0.0, w=extra_w * st["w"][0], key=doomed)
+    st = {k: np.append(v, np.asarray(add[k], dtype=v.dtype)) for k, v in st.items()}
+    f = {k: v.astype(np.float32).astype(np.float64) for k, v in pi.random_fields(cfg, 32).items()}
+    g = B.Sim([cfg], mode=F32, capacity_min=8 * len(st["r"]))
+    g.set_fields(frozen=1, **f)
+    g.set_particles(st)
+    g.step(30)
+    out = (by_key(g.get_particles()), g.charge(), g.diag())
+    g.close()
+    return out, doomed
+
+
+def test_per_particle_weights_match_the_common_weight_path():
+    (pu, qu, du), doomed = _weighted_runs(1.0)
+    (pw, qw, dw), _ = _weighted_runs(0.5)
+    assert du["n_ioniz"] > 50 and du["n_elastic"] > 100
+    assert doomed not in pu["key"] and doomed not in pw["key"]
+    for k in ("key", "r", "z", "vr", "vt", "vz", "w"):
+        assert np.array_equal(pu[k], pw[k]), k
+    assert np.array_equal(qu, qw)
+    for k in ("n_live", "n_elastic", "n_ioniz", "n_null_cand", "total_Q"):
+        assert du[k] == dw[k], k
+    # the doomed electron is absorbed at the outer wall in both runs, with its own weight
+    S = du["S"]
+    w_full = float(np.float32(hot()["weight"]))
+    w_half = float(np.float32(0.5 * w_full))
+    assert dw["n_absorbed"] == du["n_absorbed"] and du["n_absorbed"][1] >= 1
+    assert du["absorbed_W"][1] - dw["absorbed_W"][1] == round(w_full * 2.0 ** S) - round(w_half * 2.0 ** S)
+
+
+def test_per_particle_weights_are_deposited_and_inherited():
+    cfg = hot(n_init=0, p_mbar=10.0)
+    st = pi.cloud_state(cfg, 30000, seed=33)
+    rng = np.random.default_rng(34)
+    st["w"] = np.float32(cfg["weight"]) * rng.choice(np.array([0.25, 0.5, 0.75, 1.0], dtype=np.float32), len(st["r"]))
+    st = {k: (v.astype(np.float32).astype(np.float64) if v.dtype.kind == "f" else v) for k, v in st.items()}
+    g = B.Sim([cfg], mode=F32, capacity_min=8 * len(st["r"]))
+    g.set_particles(st)
+    S = g.diag()["S"]
+    g.step(20)
+    p, d = g.get_particles(), g.diag()
+    assert d["n_ioniz"] > 20
+    # every electron deposits rint(w 2^S); ionisation children carry the parent's weight
+    assert d["total_Q"] == int(np.sum(np.rint(p["w"] * 2.0 ** S)))
+    assert set(np.unique(p["w"])) <= set(np.unique(st["w"]))
+    # initial weights kept per key
+    pk, sk = by_key(p), by_key(st)
+    keep = np.intersect1d(pk["key"], sk["key"])
+    assert len(keep) > 20000
+    assert np.array_equal(pk["w"][np.searchsorted(pk["key"], keep)], sk["w"][np.searchsorted(sk["key"], keep)])
+    g.close()
