@@ -96,6 +96,19 @@ typedef struct {
      * collisions (keys 2^62 + running index, Philox step word 0xFFFFFFFE). */
     double src_rate;           /* macro-electrons per step, >= 0 (0: off)        */
     double src_T_eV;           /* source temperature (eV); 0 takes T_init_eV     */
+    /* Elliptic insert on the outer electrode (Sec. III: the gun geometry, a
+     * filled ellipse on the outer cylinder): metal at V_outer where
+     * ((r-ins_r0)/ins_er)^2 + ((z-ins_z0)/ins_ez)^2 <= 1.  The space-charge
+     * potential uses weighted extended B-splines of degree 1 (Sec. II.A):
+     * hat functions times a weight function that vanishes on the ellipse and
+     * is 1 beyond a band of about ins_band cells.  Particles entering it are
+     * absorbed as at r = b; seed-source electrons drawn inside it are not
+     * created.  The band must keep 3 cells from r = a and from end plates,
+     * and the load box must lie outside the ellipse (PIC_EINVAL otherwise).
+     * ins_er = ins_ez = 0: no insert. */
+    double ins_r0, ins_z0;     /* centre (m)                                     */
+    double ins_er, ins_ez;     /* semi-axes in r and z (m), > 0 with an insert   */
+    double ins_band;           /* weight band in cells, 0 takes 3; at most 64    */
 } pic_instance_cfg;
 
 typedef struct {
@@ -228,6 +241,20 @@ pic_status pic_get_fields(pic_ctx* ctx, int inst, double* Er, double* Ez, double
 /* pic_get_charge -- copy the last deposited fixed-point grid (units 2^-S
  * electrons, FEM-weighted node charge) of instance `inst`. */
 pic_status pic_get_charge(pic_ctx* ctx, int inst, long long* Q);
+
+/* pic_get_band_charge -- with the elliptic insert (Sec. II.A web-splines):
+ * copy the fixed-point node charges of q (w(x_p) - 1) that the particles
+ * inside the weight function's band deposit next to Q (node array, units
+ * 2^-S electrons; all zero without an insert).  The load of the Poisson
+ * system is Q + Qw carried through the web-spline extension. */
+pic_status pic_get_band_charge(pic_ctx* ctx, int inst, long long* Qw);
+
+/* pic_insert_layout -- host-only check of an instance's elliptic insert
+ * (no device work): node counts by class (counts[0] not an unknown, [1]
+ * inner, [2] outer, [3] inside the metal), the m nodes whose rows differ
+ * from the plain grid's, and the entries of that difference.  PIC_EINVAL
+ * when the instance is invalid or has no insert. */
+pic_status pic_insert_layout(const pic_instance_cfg* inst, int counts[4], int* m, long long* entries);
 
 /* pic_get_phi -- copy the last solved potential (V) of instance `inst`. */
 pic_status pic_get_phi(pic_ctx* ctx, int inst, double* phi);

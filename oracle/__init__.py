@@ -30,6 +30,8 @@ class OrcCfg(C.Structure):
         ("seed", C.c_uint64), ("dt", C.c_double),
         ("fx_shift", C.c_int), ("diag_interval", C.c_int), ("collisions", C.c_int),
         ("src_rate", C.c_double), ("src_T_eV", C.c_double),
+        ("ins_r0", C.c_double), ("ins_z0", C.c_double), ("ins_er", C.c_double), ("ins_ez", C.c_double),
+        ("ins_band", C.c_double),
     ]
 
 
@@ -98,14 +100,35 @@ def lib():
         L.orc_set_step.argtypes = [C.c_void_p, C.c_int64]
         L.orc_step.argtypes = [C.c_void_p, C.c_int]
         L.orc_get_charge.argtypes = [C.c_void_p, _I64]
+        L.orc_get_charge_w.argtypes = [C.c_void_p, _I64]
         L.orc_get_phi.argtypes = [C.c_void_p, _D]
         L.orc_get_diag.argtypes = [C.c_void_p, C.POINTER(OrcDiag)]
         L.orc_get_time_avg_density.argtypes = [C.c_void_p, _D]
         L.orc_moments.argtypes = [C.c_void_p, _D]
         L.orc_well_depth.argtypes = [C.POINTER(OrcCfg), _D, C.c_int, _D, _D, _D]
         L.orc_num_threads.restype = C.c_int
+        L.orc_load.restype = C.c_int
+        L.orc_ins_g.argtypes = [C.POINTER(OrcCfg), C.c_double, C.c_double]
+        L.orc_ins_g.restype = C.c_double
+        L.orc_ins_gamma.argtypes = [C.POINTER(OrcCfg)]
+        L.orc_ins_gamma.restype = C.c_double
+        L.orc_ins_wp.argtypes = [C.POINTER(OrcCfg), C.c_double, C.c_double]
+        L.orc_ins_wp.restype = C.c_double
+        L.orc_ins_weight.argtypes = [C.POINTER(OrcCfg), C.c_double, C.c_double, _D, _D]
+        L.orc_ins_weight.restype = C.c_double
+        L.orc_ins_check.argtypes = [C.POINTER(OrcCfg)]
+        L.orc_ins_check.restype = C.c_int
+        L.orc_ins_classify.argtypes = [C.POINTER(OrcCfg), C.POINTER(C.c_int)]
+        L.orc_ins_classify.restype = C.c_int
+        L.orc_ins_info.argtypes = [C.POINTER(OrcCfg), C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)]
+        L.orc_ins_info.restype = C.c_int
+        L.orc_ins_poisson_fn.argtypes = [C.POINTER(OrcCfg), _FN, C.c_void_p, _D]
+        L.orc_ins_poisson_fn.restype = C.c_int
         _lib = L
     return _lib
+
+
+_FN = C.CFUNCTYPE(C.c_double, C.c_double, C.c_double, C.c_void_p)
 
 
 def _dp(a):
@@ -240,6 +263,48 @@ def well_depth(d, phi, r_mid):
     return dep, zm
 
 
+# ---- elliptic insert ------------------------------------------------------
+
+def ins_g(d, r, z):
+    return lib().orc_ins_g(C.byref(make_cfg(d)), float(r), float(z))
+
+
+def ins_gamma(d):
+    return lib().orc_ins_gamma(C.byref(make_cfg(d)))
+
+
+def ins_weight(d, r, z):
+    """Weight function value and gradient (w, dw/dr, dw/dz)."""
+    wr = np.zeros(1); wz = np.zeros(1)
+    w = lib().orc_ins_weight(C.byref(make_cfg(d)), float(r), float(z), _dp(wr), _dp(wz))
+    return w, float(wr[0]), float(wz[0])
+
+
+def ins_classify(d):
+    """Node classes: 0 not an unknown, 1 inner, 2 outer, 3 exterior."""
+    cls = np.zeros(_nodes(d), dtype=np.int32)
+    if lib().orc_ins_classify(C.byref(make_cfg(d)), cls.ctypes.data_as(C.POINTER(C.c_int))) != 0:
+        raise ValueError("insert configuration refused")
+    return cls.reshape(_shape(d))
+
+
+def ins_info(d):
+    n = C.c_int(); bw = C.c_int(); cnt = (C.c_int * 4)()
+    if lib().orc_ins_info(C.byref(make_cfg(d)), C.byref(n), C.byref(bw), cnt) != 0:
+        raise ValueError("insert configuration refused")
+    return {"unknowns": n.value, "bandwidth": bw.value, "counts": list(cnt)}
+
+
+def ins_poisson_fn(d, f):
+    """Nodal web-spline solution of -lap(phi) = f(r, z) with phi = 0 on every
+    electrode (the manufactured-solution hook)."""
+    cb = _FN(lambda r, z, u: float(f(r, z)))
+    phi = np.zeros(_nodes(d))
+    if lib().orc_ins_poisson_fn(C.byref(make_cfg(d)), cb, None, _dp(phi)) != 0:
+        raise ValueError("insert configuration refused")
+    return phi.reshape(_shape(d))
+
+
 def num_threads():
     return lib().orc_num_threads()
 
@@ -256,6 +321,8 @@ class Sim:
         self.nodes = _nodes(d)
         self.shape = _shape(d)
         self.h = lib().orc_create(C.byref(self.cfg), int(capacity or d.get("n_init", 1024)))
+        if not self.h:
+            raise ValueError("oracle refused the configuration")
 
     def close(self):
         if self.h:
@@ -269,7 +336,8 @@ class Sim:
             pass
 
     def load(self):
-        lib().orc_load(self.h)
+        if lib().orc_load(self.h) != 0:
+            raise ValueError("load box intersects the insert")
 
     def set_particles(self, st):
         n = len(st["r"])
@@ -308,6 +376,11 @@ class Sim:
     def charge(self):
         Q = np.zeros(self.nodes, dtype=np.int64)
         lib().orc_get_charge(self.h, Q.ctypes.data_as(_I64))
+        return Q.reshape(self.shape)
+
+    def band_charge(self):
+        Q = np.zeros(self.nodes, dtype=np.int64)
+        lib().orc_get_charge_w(self.h, Q.ctypes.data_as(_I64))
         return Q.reshape(self.shape)
 
     def phi(self):

@@ -58,6 +58,10 @@ typedef struct {
     int collisions;            /* 0 switches the MCC stage off                  */
     double src_rate;           /* seed source: macro-electrons per step (0 off)  */
     double src_T_eV;           /* its Maxwellian temperature (0: T_init_eV)     */
+    /* elliptic insert on the outer electrode (metal, at V_outer) where
+     * ((r-ins_r0)/ins_er)^2 + ((z-ins_z0)/ins_ez)^2 <= 1; ins_er = 0: none */
+    double ins_r0, ins_z0, ins_er, ins_ez;
+    double ins_band;           /* weight-function band in cells (0: 3)          */
 } orc_cfg;
 
 /* Host-derived constants (all FP64). */
@@ -124,6 +128,25 @@ void orc_well_depth(const orc_cfg* c, const double* phi, int n_lines, const doub
 /* n, n u_r, n u_t, n u_z, then sum w v_a v_b / V for (rr, rt, rz, tt, tz, zz),
  * then sum w nu_m(v) / V with nu_m = n_n (sigma_el + sigma_iz(E)) |v|. */
 
+/* ---- elliptic insert (web-splines of degree 1), orc_insert.c ---- */
+typedef struct orc_ins orc_ins;
+int      orc_has_insert(const orc_cfg* c);
+double   orc_ins_g(const orc_cfg* c, double r, double z);
+double   orc_ins_gamma(const orc_cfg* c);
+double   orc_ins_wp(const orc_cfg* c, double r, double z);
+double   orc_ins_weight(const orc_cfg* c, double r, double z, double* wr, double* wz);
+int      orc_ins_box_hits(const orc_cfg* c, double rl, double rh, double zl, double zh);
+int      orc_ins_check(const orc_cfg* c);
+orc_ins* orc_ins_create(const orc_cfg* c);
+void     orc_ins_destroy(orc_ins* I);
+void     orc_ins_solve_loads(const orc_ins* I, const orc_cfg* c, const double* load, double* phi);
+void     orc_ins_solve_rows(const orc_ins* I, const orc_cfg* c, const double* rhs, double* phi);
+void     orc_ins_poisson_charge(const orc_ins* I, const orc_cfg* c, const int64_t* Q, const int64_t* Qw,
+                                double* phi_sc);
+int      orc_ins_poisson_fn(const orc_cfg* c, double (*f)(double, double, void*), void* user, double* phi);
+int      orc_ins_classify(const orc_cfg* c, int* cls);
+int      orc_ins_info(const orc_cfg* c, int* n_unknowns, int* bandwidth, int counts[4]);
+
 /* ---- simulation object ---- */
 orc_sim* orc_create(const orc_cfg* c, int64_t capacity);
 void     orc_destroy(orc_sim* s);
@@ -143,6 +166,7 @@ void     orc_get_fields(const orc_sim* s, double* Er, double* Ez, double* Br, do
 void     orc_set_step(orc_sim* s, int64_t step);
 int      orc_step(orc_sim* s, int n_steps);
 void     orc_get_charge(const orc_sim* s, int64_t* Q);
+void     orc_get_charge_w(const orc_sim* s, int64_t* Qw);   /* insert: band charges (else 0) */
 void     orc_get_phi(const orc_sim* s, double* phi);
 void     orc_get_diag(const orc_sim* s, orc_diag* d);
 void     orc_get_time_avg_density(const orc_sim* s, double* n_avg);

@@ -243,11 +243,17 @@ static int is_boundary(const orc_cfg* c, int i, int j) {
     return i == 0 || i == c->nr || j == 0 || j == c->nz;
 }
 
-/* Vacuum potential: discrete Laplace solution with the electrode data. */
+/* Vacuum potential: discrete Laplace solution with the electrode data.  With
+ * the elliptic insert the data are taken relative to V_outer (the insert's
+ * potential), so that the weighted basis, which vanishes on the insert, holds
+ * the solution; the lift of the remaining data lives on the hats next to the
+ * inner electrode and the ends, away from the insert. */
 void orc_vacuum(const orc_cfg* c, double* phi_vac) {
     const int nr = c->nr, nz = c->nz, W = nz + 1;
     const double dr = (c->b - c->a) / (double)nr, dz = c->L / (double)nz;
     size_t N = (size_t)(nr + 1) * W;
+    const int ins = orc_has_insert(c);
+    const double shift = ins ? c->V_outer : 0.0;
     double* rhs = (double*)calloc(N, sizeof(double));
     double* x = (double*)calloc(N, sizeof(double));
     const int j0 = c->end_mode == 2 ? 0 : 1, j1 = c->end_mode == 2 ? nz : nz - 1;
@@ -260,15 +266,23 @@ void orc_vacuum(const orc_cfg* c, double* phi_vac) {
                     if (jj < 0 || jj > nz || !is_boundary(c, ii, jj)) continue;
                     double A = Kr_ent(c, dr, i, di) * Mz_at(c, dz, j, dj) +
                                Mr_ent(c, dr, i, di) * Kz_at(c, dz, j, dj);
-                    s -= A * boundary_value(c, dr, ii, jj);
+                    s -= A * (boundary_value(c, dr, ii, jj) - shift);
                 }
             rhs[(size_t)i * W + j] = s;
         }
-    orc_solve(c, rhs, x);
+    if (ins) {
+        orc_ins* I = orc_ins_create(c);
+        if (I) {
+            orc_ins_solve_rows(I, c, rhs, x);
+            orc_ins_destroy(I);
+        }
+    } else {
+        orc_solve(c, rhs, x);
+    }
     for (int i = 0; i <= nr; ++i)
         for (int j = 0; j <= nz; ++j) {
             size_t n = (size_t)i * W + j;
-            phi_vac[n] = is_boundary(c, i, j) ? boundary_value(c, dr, i, j) : x[n];
+            phi_vac[n] = is_boundary(c, i, j) ? boundary_value(c, dr, i, j) : x[n] + shift;
         }
     free(rhs); free(x);
 }

@@ -33,6 +33,8 @@ struct orc_sim {
     uint64_t* key;
     int nodes;
     int64_t* Q;
+    int64_t* Qw;               /* insert: deposit of q (w(x_p) - 1) (else NULL) */
+    orc_ins* ins;              /* insert: factorised web-spline system          */
     double *phi_vac, *phi, *Er, *Ez, *Br, *Bz, *V, *avg_acc;
     int frozen;
     int64_t step;
@@ -150,6 +152,7 @@ static inline int push_one(const orc_sim* s, int64_t p, double* rr, double* zz,
     int wall = -1;
     if (rn <= c->a) wall = 0;
     else if (rn >= c->b) wall = 1;
+    else if (s->ins && orc_ins_g(c, rn, zn) <= 0.0) wall = 1;   /* the insert is part of the outer electrode */
     else if (zn <= 0.0) wall = 2;
     else if (zn >= c->L) wall = 3;
     if (wall >= 0) return wall;
@@ -227,27 +230,43 @@ static inline int mcc_one(const orc_sim* s, int64_t p, orc_part* child) {
 }
 
 /* ---- deposit of all particles into s->Q (per-thread grids, exact sums) ---- */
+/* With the insert, a particle inside the weight function's band also
+ * deposits rint(Wq (w(x_p) - 1)) into Qw by the same exact-sum rule. */
 static void deposit_all(orc_sim* s) {
     const int W = s->c.nz + 1;
     const int N = s->nodes;
+    const double gam = s->ins ? orc_ins_gamma(&s->c) : 0.0;
     memset(s->Q, 0, sizeof(int64_t) * N);
+    if (s->Qw) memset(s->Qw, 0, sizeof(int64_t) * N);
 #pragma omp parallel
     {
         int64_t* loc = (int64_t*)calloc(N, sizeof(int64_t));
+        int64_t* locw = s->Qw ? (int64_t*)calloc(N, sizeof(int64_t)) : NULL;
 #pragma omp for schedule(static)
         for (int64_t p = 0; p < s->n; ++p) {
             orc_shape sh = shape_at(&s->c, &s->d, s->r[p], s->z[p]);
-            deposit_shape(&sh, (int64_t)rint(s->w[p] * s->d.two_S), loc, W);
+            int64_t Wq = (int64_t)rint(s->w[p] * s->d.two_S);
+            deposit_shape(&sh, Wq, loc, W);
+            if (locw && orc_ins_g(&s->c, s->r[p], s->z[p]) < gam) {
+                double wp = orc_ins_wp(&s->c, s->r[p], s->z[p]);
+                deposit_shape(&sh, (int64_t)rint((double)Wq * (wp - 1.0)), locw, W);
+            }
         }
 #pragma omp critical
-        for (int k = 0; k < N; ++k) s->Q[k] += loc[k];
+        {
+            for (int k = 0; k < N; ++k) s->Q[k] += loc[k];
+            if (locw)
+                for (int k = 0; k < N; ++k) s->Qw[k] += locw[k];
+        }
         free(loc);
+        free(locw);
     }
 }
 
 static void solve_fields(orc_sim* s) {
     if (s->frozen) return;
-    orc_poisson_charge(&s->c, s->Q, s->phi);
+    if (s->ins) orc_ins_poisson_charge(s->ins, &s->c, s->Q, s->Qw, s->phi);
+    else orc_poisson_charge(&s->c, s->Q, s->phi);
     for (int k = 0; k < s->nodes; ++k) s->phi[k] += s->phi_vac[k];
     orc_efield(&s->c, s->phi, s->Er, s->Ez);
 }
@@ -269,6 +288,14 @@ orc_sim* orc_create(const orc_cfg* c, int64_t capacity) {
     s->Bz = (double*)calloc(s->nodes, sizeof(double));
     s->V = (double*)calloc(s->nodes, sizeof(double));
     s->avg_acc = (double*)calloc(s->nodes, sizeof(double));
+    if (orc_has_insert(&s->c)) {
+        s->ins = orc_ins_create(&s->c);
+        if (!s->ins) {
+            orc_destroy(s);
+            return NULL;
+        }
+        s->Qw = (int64_t*)calloc(s->nodes, sizeof(int64_t));
+    }
     orc_bfield(&s->c, s->Br, s->Bz);
     orc_vacuum(&s->c, s->phi_vac);
     memcpy(s->phi, s->phi_vac, sizeof(double) * s->nodes);
@@ -282,6 +309,8 @@ void orc_destroy(orc_sim* s) {
     free(s->r); free(s->z); free(s->vr); free(s->vt); free(s->vz); free(s->w); free(s->key);
     free(s->Q); free(s->phi_vac); free(s->phi); free(s->Er); free(s->Ez);
     free(s->Br); free(s->Bz); free(s->V); free(s->avg_acc);
+    free(s->Qw);
+    orc_ins_destroy(s->ins);
     free(s);
 }
 
@@ -294,6 +323,7 @@ void orc_destroy(orc_sim* s) {
 int orc_load(orc_sim* s) {
     const orc_cfg* c = &s->c;
     int64_t n = c->n_init;
+    if (s->ins && n > 0 && orc_ins_box_hits(c, c->r_lo, c->r_hi, c->z_lo, c->z_hi)) return -1;
     sim_reserve(s, n);
     double sv = sqrt((c->T_init_eV * ORC_E) / 9.1093837015e-31);
 #pragma omp parallel for schedule(static)
@@ -400,7 +430,9 @@ static void sample_diag(orc_sim* s) {
  * floor(n R) exist after n steps; the j-th of step n has key
  * 2^62 + floor(n R) + j.  Each draws three Philox blocks of its key at the
  * step word 0xFFFFFFFE: r uniform in volume over (a, b), z uniform over
- * (0, L), Box-Muller velocity components at src_T_eV (T_init_eV if 0).
+ * (0, L), Box-Muller velocity components at src_T_eV (T_init_eV if 0).  An
+ * electron drawn inside the elliptic insert lies outside the domain and is
+ * not created (its key is skipped).
  */
 static void seed_source(orc_sim* s) {
     const orc_cfg* c = &s->c;
@@ -412,6 +444,7 @@ static void seed_source(orc_sim* s) {
     const double T = c->src_T_eV > 0.0 ? c->src_T_eV : c->T_init_eV;
     const double sv = sqrt((T * ORC_E) / 9.1093837015e-31);
     sim_reserve(s, s->n + count);
+    int64_t made = 0;
     for (int64_t j = 0; j < count; ++j) {
         const uint64_t key = (UINT64_C(1) << 62) + (uint64_t)(first + j);
         uint32_t b0[4], b1[4], b2[4];
@@ -422,17 +455,20 @@ static void seed_source(orc_sim* s) {
         const double u1 = orc_u52(b1[0], b1[1]), u2 = orc_u52(b1[2], b1[3]);
         const double u3 = orc_u52(b2[0], b2[1]), u4 = orc_u52(b2[2], b2[3]);
         const double m1 = sqrt(-2.0 * log(u1)), m3 = sqrt(-2.0 * log(u3));
-        const int64_t q = s->n + j;
-        s->r[q] = sqrt(c->a * c->a + ur * (c->b * c->b - c->a * c->a));
-        s->z[q] = uz * c->L;
+        const double r = sqrt(c->a * c->a + ur * (c->b * c->b - c->a * c->a)), z = uz * c->L;
+        if (s->ins && orc_ins_g(c, r, z) <= 0.0) continue;   /* inside the insert: not in the domain */
+        const int64_t q = s->n + made;
+        s->r[q] = r;
+        s->z[q] = z;
         s->vr[q] = sv * (m1 * cos((2.0 * M_PI) * u2));
         s->vt[q] = sv * (m1 * sin((2.0 * M_PI) * u2));
         s->vz[q] = sv * (m3 * cos((2.0 * M_PI) * u4));
         s->w[q] = c->weight;
         s->key[q] = key;
+        ++made;
     }
-    s->n += count;
-    s->dg.n_source += count;
+    s->n += made;
+    s->dg.n_source += made;
 }
 
 int orc_step(orc_sim* s, int n_steps) {
@@ -547,6 +583,10 @@ void orc_moments(const orc_sim* s, double* out) {
 }
 
 void orc_get_charge(const orc_sim* s, int64_t* Q) { memcpy(Q, s->Q, sizeof(int64_t) * s->nodes); }
+void orc_get_charge_w(const orc_sim* s, int64_t* Qw) {
+    if (s->Qw) memcpy(Qw, s->Qw, sizeof(int64_t) * s->nodes);
+    else memset(Qw, 0, sizeof(int64_t) * s->nodes);
+}
 void orc_get_phi(const orc_sim* s, double* phi) { memcpy(phi, s->phi, sizeof(double) * s->nodes); }
 
 void orc_get_diag(const orc_sim* s, orc_diag* d) {

@@ -50,6 +50,8 @@ class pic_instance_cfg(C.Structure):
         ("seed", C.c_ulonglong), ("dt", C.c_double),
         ("fx_shift", C.c_int), ("diag_interval", C.c_int), ("collisions", C.c_int),
         ("src_rate", C.c_double), ("src_T_eV", C.c_double),
+        ("ins_r0", C.c_double), ("ins_z0", C.c_double), ("ins_er", C.c_double), ("ins_ez", C.c_double),
+        ("ins_band", C.c_double),
     ]
 
 
@@ -88,7 +90,7 @@ EXPORTS = ("pic_init", "pic_step", "pic_diag", "pic_destroy", "pic_last_error", 
            "pic_get_particles", "pic_set_particles", "pic_set_fields", "pic_get_fields",
            "pic_get_charge", "pic_get_phi", "pic_set_step", "pic_derive", "pic_auto_shift",
            "pic_timing", "pic_tuning", "pic_retune", "pic_autotune", "pic_reserve", "pic_capacity",
-           "pic_moments", "pic_well_depth")
+           "pic_moments", "pic_well_depth", "pic_get_band_charge", "pic_insert_layout")
 
 _lib = None
 _D = C.POINTER(C.c_double)
@@ -138,6 +140,8 @@ def lib():
     L.pic_capacity.argtypes = [vp, C.c_int, _LL, _LL]
     L.pic_moments.argtypes = [vp, C.c_int, _D]
     L.pic_well_depth.argtypes = [vp, C.c_int, C.c_int, _D, _D, _D]
+    L.pic_get_band_charge.argtypes = [vp, C.c_int, _LL]
+    L.pic_insert_layout.argtypes = [C.POINTER(pic_instance_cfg), _I, _I, _LL]
     for name in EXPORTS:
         if name not in ("pic_last_error", "pic_auto_shift"):
             getattr(L, name).restype = C.c_int
@@ -164,6 +168,18 @@ def make_instance_cfg(d):
 
 def pic_auto_shift(w_max):
     return lib().pic_auto_shift(float(w_max))
+
+
+def pic_insert_layout(inst):
+    """Host-only set-up of an instance's elliptic insert: node counts by
+    class (not an unknown, inner, outer, inside the metal), the size m of the
+    corrected node set and the entries of the correction."""
+    c = make_instance_cfg(inst)
+    counts = (C.c_int * 4)()
+    m = C.c_int()
+    nnz = C.c_longlong()
+    _check(lib().pic_insert_layout(C.byref(c), counts, C.byref(m), C.byref(nnz)))
+    return {"counts": list(counts), "m": m.value, "entries": nnz.value}
 
 
 def pic_derive(inst, S=0):
@@ -319,6 +335,12 @@ def pic_get_charge(ctx, inst, nodes):
     return Q
 
 
+def pic_get_band_charge(ctx, inst, nodes):
+    Qw = np.zeros(nodes, dtype=np.int64)
+    _check(lib().pic_get_band_charge(ctx, int(inst), Qw.ctypes.data_as(_LL)), ctx)
+    return Qw
+
+
 def pic_get_phi(ctx, inst, nodes):
     phi = np.zeros(nodes)
     _check(lib().pic_get_phi(ctx, int(inst), phi.ctypes.data_as(_D)), ctx)
@@ -433,6 +455,9 @@ class Sim:
 
     def charge(self, k=0):
         return pic_get_charge(self.ctx, k, self.nodes(k)).reshape(self.shapes[k])
+
+    def band_charge(self, k=0):
+        return pic_get_band_charge(self.ctx, k, self.nodes(k)).reshape(self.shapes[k])
 
     def phi(self, k=0):
         return pic_get_phi(self.ctx, k, self.nodes(k)).reshape(self.shapes[k])

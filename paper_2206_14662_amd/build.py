@@ -22,6 +22,7 @@ SOURCES = {
     "k_fp64.hip": ["-ffp-contract=off"],
     "k_field.hip": [],
     "fp32.hip": [],
+    "insert.hip": ["-ffp-contract=off"],
 }
 
 COMMON = [

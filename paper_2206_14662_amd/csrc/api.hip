@@ -4,6 +4,8 @@
 #include <math.h>
 #include <string.h>
 
+#include <cmath>
+
 #include <algorithm>
 #include <string>
 #include <vector>
@@ -31,6 +33,11 @@ struct Inst {
     float4* EB = nullptr;
     long long* cnt = nullptr;
     std::vector<double> V_host;
+    // elliptic insert
+    bool has_ins = false;
+    InsHost ih;
+    InsDev idev;              // device pointers of the corrected solve
+    long long* Qw = nullptr;
 };
 
 struct pic_ctx {
@@ -46,6 +53,14 @@ struct pic_ctx {
     FieldDev* dF = nullptr;
     FieldDev* dFvac = nullptr;
     double* dbscale = nullptr;
+    // elliptic insert: the instances that have one, their corrected-solve
+    // tables and the field tables of the two fast solves
+    std::vector<int> ins_list;
+    int max_m = 0;
+    InsDev* dIns = nullptr;
+    DevInst* dIins = nullptr;     // DevInst of the insert instances, in ins_list order
+    FieldDev *dF1 = nullptr, *dF1v = nullptr;   // first solve (step / vacuum): phi -> ybuf
+    FieldDev *dF2 = nullptr, *dF2v = nullptr;   // second solve, insert instances only
     long long* dcnt = nullptr;
     long long* prep_ctl = nullptr;  // FP32 step plan the end-of-step kernel refreshes
     long long* dtmp = nullptr;
@@ -178,12 +193,30 @@ static std::string validate(const pic_instance_cfg& c) {
         if (!(c.r_lo >= c.a && c.r_hi <= c.b && c.r_lo < c.r_hi)) return "load box must satisfy a <= r_lo < r_hi <= b";
         if (!(c.z_lo >= 0.0 && c.z_hi <= c.L && c.z_lo < c.z_hi)) return "load box must satisfy 0 <= z_lo < z_hi <= L";
         if (!(c.T_init_eV >= 0.0) || !(c.weight > 0.0)) return "need T_init_eV >= 0 and weight > 0";
-        if (!(c.src_rate >= 0.0 && c.src_rate <= 1e9) || !(c.src_T_eV >= 0.0))
-            return "need 0 <= src_rate <= 1e9 per step and src_T_eV >= 0";
     }
+    if (!(c.src_rate >= 0.0 && c.src_rate <= 1e9) || !(c.src_T_eV >= 0.0))
+        return "need 0 <= src_rate <= 1e9 per step and src_T_eV >= 0";
     if (c.load_mode != 0 && c.load_mode != 1) return "load_mode must be 0 or 1";
     if (c.end_mode < 0 || c.end_mode > 2) return "end_mode must be 0, 1 or 2";
     if (c.diag_interval < 0) return "diag_interval must be >= 0";
+    if (c.ins_er != 0.0 || c.ins_ez != 0.0) {
+        if (!(c.ins_er > 0.0 && c.ins_ez > 0.0 && std::isfinite(c.ins_r0) && std::isfinite(c.ins_z0)))
+            return "insert: need ins_er > 0, ins_ez > 0 and a finite centre";
+        if (!(c.ins_band >= 0.0 && c.ins_band <= 64.0)) return "insert: ins_band must be in [0, 64] cells";
+        const double dr = (c.b - c.a) / (double)c.nr, dz = c.L / (double)c.nz;
+        const double band = c.ins_band > 0.0 ? c.ins_band : 3.0;
+        const double sg = sqrt(1.0 + 2.0 * band * std::max(dr / c.ins_er, dz / c.ins_ez));
+        if (c.ins_r0 - c.ins_er * sg < c.a + 3.0 * dr) return "insert: its weight band reaches the inner electrode";
+        if (c.end_mode != 2 && (c.ins_z0 - c.ins_ez * sg < 3.0 * dz || c.ins_z0 + c.ins_ez * sg > c.L - 3.0 * dz))
+            return "insert: its weight band reaches an end electrode";
+        if (c.n_init > 0) {
+            // the load box must lie outside the metal: the least g over the box
+            const double rc = std::min(std::max(c.ins_r0, c.r_lo), c.r_hi);
+            const double zc = std::min(std::max(c.ins_z0, c.z_lo), c.z_hi);
+            const double u = (rc - c.ins_r0) / c.ins_er, v = (zc - c.ins_z0) / c.ins_ez;
+            if ((u * u + v * v) - 1.0 <= 0.0) return "insert: the load box reaches into the insert";
+        }
+    }
     return "";
 }
 
@@ -241,7 +274,13 @@ static double edge_value(const pic_instance_cfg& c, double dr, int i) {
     return c.V_inner + (c.V_outer - c.V_inner) * (log(r / c.a) / log(c.b / c.a)) + c.V_end;
 }
 
-static void host_vacuum_rhs(const pic_instance_cfg& c, std::vector<double>& phiB, std::vector<double>& rhs) {
+// Vacuum right-hand side from the electrode data, taken relative to `shift`
+// (V_outer with the elliptic insert: the insert's potential, so that the
+// weighted basis, which vanishes on the insert, holds the solution).  phiB
+// gets the data on the electrode nodes and `shift` elsewhere: the base the
+// solution is added to.
+static void host_vacuum_rhs(const pic_instance_cfg& c, double shift, std::vector<double>& phiB,
+                            std::vector<double>& rhs) {
     const int nr = c.nr, nz = c.nz, W = nz + 1;
     const double dr = (c.b - c.a) / (double)nr, dz = c.L / (double)nz;
     phiB.assign((size_t)(nr + 1) * W, 0.0);
@@ -251,7 +290,7 @@ static void host_vacuum_rhs(const pic_instance_cfg& c, std::vector<double>& phiB
     auto edge = [&](int i, int j) { return i == 0 || i == nr || (!open_ends && (j == 0 || j == nz)); };
     for (int i = 0; i <= nr; ++i)
         for (int j = 0; j <= nz; ++j)
-            if (edge(i, j)) phiB[(size_t)i * W + j] = edge_value(c, dr, i);
+            if (edge(i, j)) phiB[(size_t)i * W + j] = edge_value(c, dr, i) - shift;
     const int j0 = open_ends ? 0 : 1, j1 = open_ends ? nz : nz - 1;
     for (int i = 1; i < nr; ++i)
         for (int j = j0; j <= j1; ++j) {
@@ -264,6 +303,7 @@ static void host_vacuum_rhs(const pic_instance_cfg& c, std::vector<double>& phiB
                 }
             rhs[(size_t)i * W + j] = s;
         }
+    for (size_t n = 0; n < phiB.size(); ++n) phiB[n] += shift;
 }
 
 static void host_thomas(const pic_instance_cfg& c, int nseg, std::vector<double>& cp, std::vector<double>& im,
@@ -357,11 +397,29 @@ static void fill_devinst(Inst& in) {
     I.src_sv = sqrt(((c.src_T_eV > 0.0 ? c.src_T_eV : c.T_init_eV) * kE) / kMe);
     I.weight = c.weight;
     I.w_uni = (float)c.weight;
+    I.has_ins = (c.ins_er > 0.0 && c.ins_ez > 0.0) ? 1 : 0;
+    if (I.has_ins) {
+        const double band = c.ins_band > 0.0 ? c.ins_band : 3.0;
+        I.ins_r0 = c.ins_r0; I.ins_z0 = c.ins_z0; I.ins_er = c.ins_er; I.ins_ez = c.ins_ez;
+        I.ins_gam = 2.0 * band * std::max(d.dr / c.ins_er, d.dz / c.ins_ez);
+        I.ins_r0_f = (float)c.ins_r0; I.ins_z0_f = (float)c.ins_z0;
+        I.ins_inv_er_f = (float)(1.0 / c.ins_er); I.ins_inv_ez_f = (float)(1.0 / c.ins_ez);
+        I.ins_gam_f = (float)I.ins_gam;
+    }
+}
+
+static pic_status upload_insert_inst(pic_ctx* ctx) {
+    if (ctx->ins_list.empty()) return PIC_OK;
+    std::vector<DevInst> Ii;
+    for (int k : ctx->ins_list) Ii.push_back(ctx->in[k].I);
+    CK(hipMemcpyAsync(ctx->dIins, Ii.data(), sizeof(DevInst) * Ii.size(), hipMemcpyHostToDevice, ctx->stream));
+    return PIC_OK;
 }
 
 static pic_status upload_tables(pic_ctx* ctx) {
     std::vector<DevInst> I;
-    std::vector<FieldDev> F, Fv;
+    std::vector<FieldDev> F, Fv, F1, F1v, F2, F2v;
+    std::vector<InsDev> D;
     std::vector<double> bs;
     for (auto& in : ctx->in) {
         in.I.frozen = in.frozen ? 1 : 0;
@@ -373,11 +431,28 @@ static pic_status upload_tables(pic_ctx* ctx) {
         f.th_G = in.th_G; f.th_H = in.th_H;
         f.Er = in.Er; f.Ez = in.Ez; f.Br = in.Br; f.Bz = in.Bz; f.EB = in.EB;
         f.V = in.V; f.avg_acc = in.avg_acc;
+        f.Qw = in.Qw;
         F.push_back(f);
         FieldDev v = f;  // vacuum solve: boundary data in, phi_vac out
         v.phi_vac = in.phiB;
         v.phi = in.phi_vac;
         Fv.push_back(v);
+        // first of the two solves of an insert instance: phi goes to ybuf
+        FieldDev f1 = f, f1v = v;
+        if (in.has_ins) {
+            f1.phi = in.idev.ybuf;
+            f1v.phi = in.idev.ybuf;
+            FieldDev f2 = f, f2v = v;  // second: the correction's modes, on top of ybuf
+            f2.rhs = in.idev.rhs2;
+            f2.phi_vac = in.idev.ybuf;
+            f2v.rhs = in.idev.rhs2;
+            f2v.phi_vac = in.idev.ybuf;
+            F2.push_back(f2);
+            F2v.push_back(f2v);
+            D.push_back(in.idev);
+        }
+        F1.push_back(f1);
+        F1v.push_back(f1v);
         bs.push_back(in.d.bscale);
     }
     hipStream_t s = ctx->stream;
@@ -385,7 +460,40 @@ static pic_status upload_tables(pic_ctx* ctx) {
     CK(hipMemcpyAsync(ctx->dF, F.data(), sizeof(FieldDev) * F.size(), hipMemcpyHostToDevice, s));
     CK(hipMemcpyAsync(ctx->dFvac, Fv.data(), sizeof(FieldDev) * Fv.size(), hipMemcpyHostToDevice, s));
     CK(hipMemcpyAsync(ctx->dbscale, bs.data(), sizeof(double) * bs.size(), hipMemcpyHostToDevice, s));
+    if (!ctx->ins_list.empty()) {
+        CK(hipMemcpyAsync(ctx->dF1, F1.data(), sizeof(FieldDev) * F1.size(), hipMemcpyHostToDevice, s));
+        CK(hipMemcpyAsync(ctx->dF1v, F1v.data(), sizeof(FieldDev) * F1v.size(), hipMemcpyHostToDevice, s));
+        CK(hipMemcpyAsync(ctx->dF2, F2.data(), sizeof(FieldDev) * F2.size(), hipMemcpyHostToDevice, s));
+        CK(hipMemcpyAsync(ctx->dF2v, F2v.data(), sizeof(FieldDev) * F2v.size(), hipMemcpyHostToDevice, s));
+        CK(hipMemcpyAsync(ctx->dIns, D.data(), sizeof(InsDev) * D.size(), hipMemcpyHostToDevice, s));
+        pic_status st = upload_insert_inst(ctx);
+        if (st != PIC_OK) return st;
+    }
     CK(hipStreamSynchronize(s));
+    return PIC_OK;
+}
+
+// One Poisson solve of every instance into the field table `fin` (the main
+// table, or the vacuum table).  Instances with the elliptic insert take the
+// corrected two-solve path: first into ybuf, the M correction, the second
+// solve on top of ybuf, then the basis evaluated at the nodes of M.
+static pic_status solve_tables(pic_ctx* ctx, bool vac, bool from_q, bool edges, hipStream_t s) {
+    const int n = (int)ctx->in.size(), ni = (int)ctx->ins_list.size();
+    FieldDev* fin = vac ? ctx->dFvac : ctx->dF;
+    if (ni == 0) {
+        CK(launch_solve_tab(ctx->dI, fin, 0, n, ctx->max_nr, ctx->max_nz, ctx->tw, ctx->tw_n, from_q ? 0 : 1,
+                            ctx->dbscale, edges, s));
+        return PIC_OK;
+    }
+    FieldDev* f1 = vac ? ctx->dF1v : ctx->dF1;
+    FieldDev* f2 = vac ? ctx->dF2v : ctx->dF2;
+    if (from_q) CK(launch_ins_rhs(ctx->dI, ctx->dIns, ni, ctx->max_nodes, ctx->dF, ctx->dbscale, s));
+    CK(launch_solve_tab(ctx->dI, f1, 0, n, ctx->max_nr, ctx->max_nz, ctx->tw, ctx->tw_n, from_q ? 0 : 1,
+                        ctx->dbscale, edges, s));
+    CK(launch_ins_correct(ctx->dI, ctx->dIns, ni, ctx->max_m, ctx->max_nodes, f1, s));
+    CK(launch_solve_tab(ctx->dIins, f2, 0, ni, ctx->max_nr, ctx->max_nz, ctx->tw, ctx->tw_n, 1, ctx->dbscale,
+                        edges, s));
+    CK(launch_ins_fix(ctx->dI, ctx->dIns, ni, ctx->max_m, fin, s));
     return PIC_OK;
 }
 
@@ -393,8 +501,8 @@ static pic_status upload_tables(pic_ctx* ctx) {
 pic_status pic_solve_all(pic_ctx* ctx) {
     int n = (int)ctx->in.size();
     hipStream_t s = ctx->stream;
-    CK(launch_solve_tab(ctx->dI, ctx->dF, 0, n, ctx->max_nr, ctx->max_nz, ctx->tw, ctx->tw_n, 0,
-                        ctx->dbscale, true, s));
+    pic_status st = solve_tables(ctx, false, true, true, s);
+    if (st != PIC_OK) return st;
     CK(launch_efield_tab(ctx->dI, ctx->dF, 0, n, ctx->max_nodes, true, s));
     return PIC_OK;
 }
@@ -403,8 +511,8 @@ pic_status pic_field_stage(pic_ctx* ctx, hipStream_t s) {
     int n = (int)ctx->in.size();
     // per step: the electrode rows of phi and the static B half of EB keep
     // the values the initial solve (or pic_set_fields) gave them
-    CK(launch_solve_tab(ctx->dI, ctx->dF, 0, n, ctx->max_nr, ctx->max_nz, ctx->tw, ctx->tw_n, 0,
-                        ctx->dbscale, false, s));
+    pic_status st = solve_tables(ctx, false, true, false, s);
+    if (st != PIC_OK) return st;
     CK(launch_efield_tab(ctx->dI, ctx->dF, 0, n, ctx->max_nodes, false, s));
     CK(launch_sample_tab(ctx->dI, ctx->dF, n, ctx->dcnt, ctx->prep_ctl, s));
     return PIC_OK;
@@ -420,6 +528,7 @@ DevInst& pic_inst_dev(pic_ctx* ctx, int k) { return ctx->in[k].I; }
 const pic_instance_cfg& pic_inst_cfg(pic_ctx* ctx, int k) { return ctx->in[k].c; }
 long long* pic_counters(pic_ctx* ctx) { return ctx->dcnt; }
 long long* pic_inst_Q(pic_ctx* ctx, int k) { return ctx->in[k].Q; }
+long long* pic_inst_Qw(pic_ctx* ctx, int k) { return ctx->in[k].Qw; }
 float4* pic_inst_EB(pic_ctx* ctx, int k) { return ctx->in[k].EB; }
 DevInst* pic_dev_table(pic_ctx* ctx) { return ctx->dI; }
 long long& pic_inst_cap(pic_ctx* ctx, int k) { return ctx->in[k].cap; }
@@ -432,6 +541,8 @@ pic_status pic_upload_inst(pic_ctx* ctx) {
         I.push_back(in.I);
     }
     CK(hipMemcpyAsync(ctx->dI, I.data(), sizeof(DevInst) * I.size(), hipMemcpyHostToDevice, ctx->stream));
+    pic_status st = upload_insert_inst(ctx);
+    if (st != PIC_OK) return st;
     CK(hipStreamSynchronize(ctx->stream));
     return PIC_OK;
 }
@@ -471,6 +582,144 @@ static pic_status timing_collect(pic_ctx* ctx) {
 // ---------------------------------------------------------------------------
 // init / destroy
 // ---------------------------------------------------------------------------
+
+template <typename T>
+static T* upload_vec(pic_ctx* ctx, const std::vector<T>& v, hipStream_t s, bool& ok) {
+    T* p = dalloc<T>(ctx, std::max<long long>(1, (long long)v.size()));
+    if (!p) {
+        ok = false;
+        return nullptr;
+    }
+    if (!v.empty() && hipMemcpyAsync(p, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice, s) != hipSuccess)
+        ok = false;
+    return p;
+}
+
+// Device arrays of an instance's insert (H is filled by setup_insert).
+static pic_status init_insert_storage(pic_ctx* ctx, Inst& in) {
+    const InsHost& h = in.ih;
+    InsDev& D = in.idev;
+    hipStream_t s = ctx->stream;
+    bool ok = true;
+    const long long N = in.nodes, m = std::max(1, h.m);
+    D.m = h.m;
+    D.nodes = N;
+    D.Mnode = upload_vec(ctx, h.Mnode, s, ok);
+    D.map = upload_vec(ctx, h.map, s, ok);
+    D.rp = upload_vec(ctx, h.rp, s, ok);
+    D.rk = upload_vec(ctx, h.rk, s, ok);
+    D.rf = upload_vec(ctx, h.rf, s, ok);
+    D.typ = upload_vec(ctx, h.typ, s, ok);
+    D.wn = upload_vec(ctx, h.wn, s, ok);
+    D.ek = upload_vec(ctx, h.ek, s, ok);
+    D.ef = upload_vec(ctx, h.ef, s, ok);
+    double* H = dalloc<double>(ctx, m * m);
+    D.H = H;
+    D.ybuf = dalloc<double>(ctx, N);
+    D.rhs2 = dalloc<double>(ctx, N);
+    D.yM = dalloc<double>(ctx, m);
+    D.sM = dalloc<double>(ctx, m);
+    D.val = dalloc<double>(ctx, m);
+    in.Qw = dalloc<long long>(ctx, N);
+    if (!ok || !H || !D.ybuf || !D.rhs2 || !D.yM || !D.sM || !D.val || !in.Qw)
+        return fail(ctx, PIC_ENOMEM, "device allocation of the insert arrays failed");
+    CK(hipMemsetAsync(H, 0, sizeof(double) * m * m, s));
+    CK(hipMemsetAsync(D.ybuf, 0, sizeof(double) * N, s));
+    CK(hipMemsetAsync(D.rhs2, 0, sizeof(double) * N, s));
+    CK(hipMemsetAsync(in.Qw, 0, sizeof(long long) * N, s));
+    CK(hipStreamSynchronize(s));
+    return PIC_OK;
+}
+
+// H = (I + D G)^-1 D with G = (A_rect^-1)_MM from m unit solves of the
+// rectangle system (batched as copies of the instance), Gauss-Jordan on the
+// device.
+static pic_status setup_insert(pic_ctx* ctx, Inst& in) {
+    const int m = in.ih.m;
+    if (m == 0) return PIC_OK;
+    hipStream_t s = ctx->stream;
+    const long long N = in.nodes;
+    const int B = std::min(64, m);
+    double* rhsT = dalloc<double>(ctx, (long long)B * N);
+    double* phiT = dalloc<double>(ctx, (long long)B * N);
+    double* zeros = dalloc<double>(ctx, N);
+    DevInst* It = dalloc<DevInst>(ctx, B);
+    FieldDev* Ftab = dalloc<FieldDev>(ctx, B);
+    double* Gd = dalloc<double>(ctx, (long long)m * m);
+    double* CDd = dalloc<double>(ctx, (long long)m * 2 * m);
+    double* fcol = dalloc<double>(ctx, m);
+    double* pval = dalloc<double>(ctx, m);
+    int* piv = dalloc<int>(ctx, 1);
+    auto release = [&]() {
+        void* ps[] = {rhsT, phiT, zeros, It, Ftab, Gd, CDd, fcol, pval, piv};
+        for (void* p : ps)
+            if (p) pic_dev_free(ctx, p);
+    };
+    if (!rhsT || !phiT || !zeros || !It || !Ftab || !Gd || !CDd || !fcol || !pval || !piv) {
+        release();
+        return fail(ctx, PIC_ENOMEM, "device allocation for the insert set-up failed");
+    }
+    DevInst I = in.I;
+    I.frozen = 0;
+    I.has_ins = 0;
+    std::vector<DevInst> Iv(B, I);
+    std::vector<FieldDev> Fv(B);
+    for (int t = 0; t < B; ++t) {
+        FieldDev f;
+        memset(&f, 0, sizeof(f));
+        f.Q = in.Q;
+        f.rhs = rhsT + (long long)t * N;
+        f.phi = phiT + (long long)t * N;
+        f.phi_vac = zeros;
+        f.th_cp = in.th_cp; f.th_im = in.th_im; f.th_lo = in.th_lo; f.th_G = in.th_G; f.th_H = in.th_H;
+        Fv[t] = f;
+    }
+    hipError_t e = hipMemsetAsync(zeros, 0, sizeof(double) * N, s);
+    if (e == hipSuccess) e = hipMemsetAsync(phiT, 0, sizeof(double) * B * N, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(It, Iv.data(), sizeof(DevInst) * B, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(Ftab, Fv.data(), sizeof(FieldDev) * B, hipMemcpyHostToDevice, s);
+    for (int b0 = 0; b0 < m && e == hipSuccess; b0 += B) {
+        const int cnt = std::min(B, m - b0);
+        e = launch_ins_units(rhsT, N, N, in.idev.Mnode, b0, cnt, s);
+        if (e == hipSuccess)
+            e = launch_solve_tab(It, Ftab, 0, cnt, ctx->max_nr, ctx->max_nz, ctx->tw, ctx->tw_n, 1, ctx->dbscale,
+                                 false, s);
+        if (e == hipSuccess) e = launch_ins_collect(phiT, N, in.idev.Mnode, m, b0, cnt, Gd, s);
+    }
+    std::vector<double> G((size_t)m * m);
+    if (e == hipSuccess) e = hipMemcpyAsync(G.data(), Gd, sizeof(double) * G.size(), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        release();
+        return fail(ctx, PIC_EDEVICE, std::string("insert set-up solves: ") + hipGetErrorString(e));
+    }
+    // [C | D] with C = I + D G
+    std::vector<double> CD((size_t)m * 2 * m, 0.0);
+    for (int a = 0; a < m; ++a) CD[(size_t)a * 2 * m + a] = 1.0;
+    const InsHost& h = in.ih;
+    for (size_t t = 0; t < h.Dv.size(); ++t) {
+        const int a = h.Dr[t], c = h.Dc[t];
+        const double v = h.Dv[t];
+        double* row = &CD[(size_t)a * 2 * m];
+        const double* gr = &G[(size_t)c * m];
+        for (int j = 0; j < m; ++j) row[j] += v * gr[j];
+        row[m + c] += v;
+    }
+    e = hipMemcpyAsync(CDd, CD.data(), sizeof(double) * CD.size(), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = launch_ins_gauss_jordan(CDd, m, fcol, piv, pval, s);
+    std::vector<double> pv(m);
+    if (e == hipSuccess) e = hipMemcpyAsync(pv.data(), pval, sizeof(double) * m, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+        e = hipMemcpy2DAsync((void*)in.idev.H, sizeof(double) * m, CDd + m, sizeof(double) * 2 * m,
+                             sizeof(double) * m, m, hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    release();
+    if (e != hipSuccess) return fail(ctx, PIC_EDEVICE, std::string("insert set-up: ") + hipGetErrorString(e));
+    for (int a = 0; a < m; ++a)
+        if (!(std::fabs(pv[a]) > 0.0) || !std::isfinite(pv[a]))
+            return fail(ctx, PIC_EINVAL, "insert: the corrected system is singular");
+    return PIC_OK;
+}
 
 static pic_status init_instance_storage(pic_ctx* ctx, Inst& in) {
     const long long N = in.nodes;
@@ -527,7 +776,16 @@ static pic_status init_instance_storage(pic_ctx* ctx, Inst& in) {
     CK(hipMemcpyAsync(in.th_G, gg.data(), sizeof(double) * N, hipMemcpyHostToDevice, s));
     CK(hipMemcpyAsync(in.th_H, hh.data(), sizeof(double) * N, hipMemcpyHostToDevice, s));
     CK(hipStreamSynchronize(s));
-    host_vacuum_rhs(in.c, a, b);
+    if (in.has_ins) {
+        std::string m = ins_build(in.c, in.ih);
+        if (!m.empty()) return fail(ctx, PIC_EINVAL, "insert: " + m);
+        pic_status st = init_insert_storage(ctx, in);
+        if (st != PIC_OK) return st;
+    }
+    host_vacuum_rhs(in.c, in.has_ins ? in.c.V_outer : 0.0, a, b);
+    if (in.has_ins)
+        for (int t = 0; t < in.ih.m; ++t)
+            if (in.ih.typ[t] != 1) b[in.ih.Mnode[t]] = 0.0;  // outer and metal rows hold no load
     CK(hipMemcpyAsync(in.phiB, a.data(), sizeof(double) * N, hipMemcpyHostToDevice, s));
     CK(hipMemcpyAsync(in.rhs, b.data(), sizeof(double) * N, hipMemcpyHostToDevice, s));
     CK(hipMemsetAsync(in.avg_acc, 0, sizeof(double) * N, s));
@@ -600,6 +858,9 @@ extern "C" pic_status pic_init(const pic_run_cfg* run, const pic_instance_cfg* i
         in.cap = std::max<long long>(cmin, (long long)ceil(cf * (double)in.c.n_init));
         in.nodes = (long long)(in.c.nr + 1) * (in.c.nz + 1);
         fill_devinst(in);
+        in.has_ins = in.I.has_ins != 0;
+        in.idev.inst = k;
+        if (in.has_ins) ctx->ins_list.push_back(k);
         ctx->max_nr = std::max(ctx->max_nr, in.c.nr);
         ctx->max_nz = std::max(ctx->max_nz, in.c.nz);
         ctx->max_nodes = std::max(ctx->max_nodes, in.nodes);
@@ -616,6 +877,17 @@ extern "C" pic_status pic_init(const pic_run_cfg* run, const pic_instance_cfg* i
         ctx->tw = dalloc<double2>(ctx, ctx->tw_n);
         if (!ctx->dI || !ctx->dF || !ctx->dFvac || !ctx->dbscale || !ctx->dcnt || !ctx->dtmp || !ctx->tw)
             st = fail(ctx, PIC_ENOMEM, "device allocation of tables failed");
+        const int ni = (int)ctx->ins_list.size();
+        if (st == PIC_OK && ni > 0) {
+            ctx->dIns = dalloc<InsDev>(ctx, ni);
+            ctx->dIins = dalloc<DevInst>(ctx, ni);
+            ctx->dF1 = dalloc<FieldDev>(ctx, n);
+            ctx->dF1v = dalloc<FieldDev>(ctx, n);
+            ctx->dF2 = dalloc<FieldDev>(ctx, ni);
+            ctx->dF2v = dalloc<FieldDev>(ctx, ni);
+            if (!ctx->dIns || !ctx->dIins || !ctx->dF1 || !ctx->dF1v || !ctx->dF2 || !ctx->dF2v)
+                st = fail(ctx, PIC_ENOMEM, "device allocation of insert tables failed");
+        }
     }
     if (st == PIC_OK) {
         std::vector<double2> tw(ctx->tw_n);  // the full circle
@@ -629,6 +901,7 @@ extern "C" pic_status pic_init(const pic_run_cfg* run, const pic_instance_cfg* i
         if (e != hipSuccess && st == PIC_OK) st = fail(ctx, PIC_EDEVICE, "LDS attribute failed");
     }
     for (int k = 0; k < n && st == PIC_OK; ++k) st = init_instance_storage(ctx, ctx->in[k]);
+    for (int k : ctx->ins_list) ctx->max_m = std::max(ctx->max_m, ctx->in[k].ih.m);
     if (st == PIC_OK && ctx->mode == PIC_MODE_FP32_BATCHED) st = f32_init(ctx);
     if (st == PIC_OK) {
         std::vector<long long> cnt((size_t)n * C_NCOUNT, 0);
@@ -638,11 +911,11 @@ extern "C" pic_status pic_init(const pic_run_cfg* run, const pic_instance_cfg* i
         for (int k = 0; k < n; ++k) ctx->in[k].cnt = ctx->dcnt + (long long)k * C_NCOUNT;
     }
     if (st == PIC_OK) st = upload_tables(ctx);
+    for (size_t t = 0; t < ctx->ins_list.size() && st == PIC_OK; ++t) st = setup_insert(ctx, ctx->in[ctx->ins_list[t]]);
     // vacuum potential
+    if (st == PIC_OK) st = solve_tables(ctx, true, false, true, ctx->stream);
     if (st == PIC_OK) {
-        e = launch_solve_tab(ctx->dI, ctx->dFvac, 0, n, ctx->max_nr, ctx->max_nz, ctx->tw, ctx->tw_n, 1,
-                             ctx->dbscale, true, ctx->stream);
-        if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+        e = hipStreamSynchronize(ctx->stream);
         if (e != hipSuccess) st = fail(ctx, PIC_EDEVICE, std::string("vacuum solve: ") + hipGetErrorString(e));
     }
     // initial load
@@ -690,8 +963,9 @@ static pic_status deposit_and_solve(pic_ctx* ctx, int k_only) {
         if (k_only >= 0 && k != k_only) continue;
         Inst& in = ctx->in[k];
         CK(launch_zero_i64(in.Q, in.nodes, s));
+        if (in.Qw) CK(launch_zero_i64(in.Qw, in.nodes, s));
         if (ctx->mode == PIC_MODE_FP64_PLAIN) {
-            CK(launch_deposit64(in.I, in.p64[in.cur], in.Q, in.cnt, in.cap, s));
+            CK(launch_deposit64(in.I, in.p64[in.cur], in.Q, in.Qw, in.cnt, in.cap, s));
         } else {
             pic_status st = f32_deposit_only(ctx, k);
             if (st != PIC_OK) return st;
@@ -813,6 +1087,7 @@ static pic_status step64(pic_ctx* ctx, int n_steps) {
                 Inst& in = ctx->in[k];
                 P64 p = in.p64[in.cur];
                 CK(launch_zero_i64(in.Q, in.nodes, s));
+                if (in.Qw) CK(launch_zero_i64(in.Qw, in.nodes, s));
                 hipEvent_t e0 = nullptr, e1 = nullptr;
                 if (ctx->timing) {
                     e0 = pic_timing_begin(ctx, &e1);
@@ -822,7 +1097,7 @@ static pic_status step64(pic_ctx* ctx, int n_steps) {
                 if (ctx->timing) CK(hipEventRecord(e1, s));
                 CK(launch_mcc64(in.I, p, in.cnt, in.cap, s));
                 if (in.c.src_rate > 0.0) CK(launch_source64(in.I, p, in.cnt, s));
-                CK(launch_deposit64(in.I, p, in.Q, in.cnt, in.cap, s));
+                CK(launch_deposit64(in.I, p, in.Q, in.Qw, in.cnt, in.cap, s));
             }
             st = pic_field_stage(ctx, s);
             if (st != PIC_OK) return st;
@@ -1012,6 +1287,34 @@ extern "C" pic_status pic_get_charge(pic_ctx* ctx, int k, long long* Q) {
     if (!Q) return fail(ctx, PIC_EINVAL, "Q is NULL");
     CK(hipStreamSynchronize(ctx->stream));
     CK(hipMemcpy(Q, ctx->in[k].Q, sizeof(long long) * ctx->in[k].nodes, hipMemcpyDeviceToHost));
+    return PIC_OK;
+}
+
+extern "C" pic_status pic_get_band_charge(pic_ctx* ctx, int k, long long* Qw) {
+    pic_status st = check_inst(ctx, k);
+    if (st != PIC_OK) return st;
+    if (!Qw) return fail(ctx, PIC_EINVAL, "Qw is NULL");
+    CK(hipStreamSynchronize(ctx->stream));
+    if (!ctx->in[k].Qw) {
+        memset(Qw, 0, sizeof(long long) * ctx->in[k].nodes);
+        return PIC_OK;
+    }
+    CK(hipMemcpy(Qw, ctx->in[k].Qw, sizeof(long long) * ctx->in[k].nodes, hipMemcpyDeviceToHost));
+    return PIC_OK;
+}
+
+extern "C" pic_status pic_insert_layout(const pic_instance_cfg* inst, int counts[4], int* m, long long* entries) {
+    if (!inst) return fail(nullptr, PIC_EINVAL, "inst is NULL");
+    std::string msg = validate(*inst);
+    if (!msg.empty()) return fail(nullptr, PIC_EINVAL, msg);
+    if (!(inst->ins_er > 0.0 && inst->ins_ez > 0.0)) return fail(nullptr, PIC_EINVAL, "no insert");
+    InsHost h;
+    msg = ins_build(*inst, h);
+    if (!msg.empty()) return fail(nullptr, PIC_EINVAL, "insert: " + msg);
+    if (counts)
+        for (int t = 0; t < 4; ++t) counts[t] = h.counts[t];
+    if (m) *m = h.m;
+    if (entries) *entries = (long long)h.Dv.size();
     return PIC_OK;
 }
 

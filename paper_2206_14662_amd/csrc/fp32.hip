@@ -128,7 +128,8 @@ __device__ __forceinline__ void cell_of(const DevInst& I, float r, float z, int&
 // registers so stores to the particle arrays never force them to be reloaded.
 struct LocalInst {
     float a, b, L, inv_dr, inv_dz, h, dt, v_cap2, two_S, w_uni;
-    int nr, nz, W, ntz, tile_off, collisions;
+    float ins_r0, ins_z0, ins_inv_er, ins_inv_ez, ins_gam;
+    int nr, nz, W, ntz, tile_off, collisions, has_ins;
     unsigned int seed_lo, seed_hi;
     unsigned long long null_k;
 };
@@ -144,6 +145,10 @@ __device__ __forceinline__ LocalInst local_inst(const DevInst& I) {
     L.h = uniform_f(I.h_f); L.dt = uniform_f(I.dt_f); L.v_cap2 = uniform_f(I.v_cap2_f);
     L.two_S = uniform_f((float)I.two_S);
     L.w_uni = uniform_f(I.w_uni);
+    L.ins_r0 = uniform_f(I.ins_r0_f); L.ins_z0 = uniform_f(I.ins_z0_f);
+    L.ins_inv_er = uniform_f(I.ins_inv_er_f); L.ins_inv_ez = uniform_f(I.ins_inv_ez_f);
+    L.ins_gam = uniform_f(I.ins_gam_f);
+    L.has_ins = __builtin_amdgcn_readfirstlane(I.has_ins);
     L.nr = __builtin_amdgcn_readfirstlane(I.nr); L.nz = __builtin_amdgcn_readfirstlane(I.nz);
     L.W = __builtin_amdgcn_readfirstlane(I.W); L.ntz = __builtin_amdgcn_readfirstlane(I.ntz);
     L.tile_off = __builtin_amdgcn_readfirstlane(I.tile_off);
@@ -286,6 +291,37 @@ __device__ __forceinline__ void node_charges(float w, float two_S, float fr, flo
     q11 = (long long)Wu - (long long)a - (long long)b - (long long)c;
 }
 
+// Elliptic insert in FP32: g <= 0 in the metal; in the weight function's
+// band (0 < g < gam) a particle adds its charge times (w(x_p) - 1) to Qw,
+// rint(W (w - 1)) split over the four nodes by the same exact-sum rule.
+__device__ __forceinline__ float ins_g_f(const DevInst& I, float r, float z) {
+    const float u = (r - I.ins_r0_f) * I.ins_inv_er_f, v = (z - I.ins_z0_f) * I.ins_inv_ez_f;
+    return fmaf(u, u, v * v) - 1.0f;
+}
+
+__device__ __forceinline__ void deposit_qw(const DevInst& I, long long* Qw, float w, float r, float z) {
+    const float g = ins_g_f(I, r, z);
+    if (!(g < I.ins_gam_f)) return;
+    float s = 1.0f - g / I.ins_gam_f;
+    s = g <= 0.0f ? 1.0f : s;
+    const float wp = 1.0f - s * s * s;
+    const float Wt = rintf(rintf(w * (float)I.two_S) * (wp - 1.0f));
+    int i, j;
+    float fr, fz;
+    cell_of(I, r, z, i, j, fr, fz);
+    const float gr = 1.0f - fr, gz = 1.0f - fz;
+    const long long a = (long long)rintf(Wt * (gr * gz));
+    const long long b = (long long)rintf(Wt * (fr * gz));
+    const long long c = (long long)rintf(Wt * (gr * fz));
+    const long long d = (long long)Wt - a - b - c;
+    unsigned long long* Q = (unsigned long long*)Qw;
+    const long long n00 = (long long)i * I.W + j;
+    atomicAdd(&Q[n00], (unsigned long long)a);
+    atomicAdd(&Q[n00 + I.W], (unsigned long long)b);
+    atomicAdd(&Q[n00 + 1], (unsigned long long)c);
+    atomicAdd(&Q[n00 + I.W + 1], (unsigned long long)d);
+}
+
 // One atomic per distinct key among the active lanes of the wave (the key's
 // lanes add their count at once); with RET each lane gets its rank: the
 // returned base plus its position among the lanes sharing the key.  Every
@@ -329,6 +365,7 @@ struct ChunkCtx {
     PSet out;
     const float4* EB;
     long long* Q;
+    long long* Qw;
     int inst, ti_c, tj_c, i0, i1, j0, j1, ww;
     bool win;
     unsigned int step;
@@ -404,6 +441,9 @@ __device__ __forceinline__ void push_particle(const KArgs& A, const ChunkCtx& X,
     int wall = -1;
     if (rn <= L.a) wall = 0;
     else if (rn >= L.b) wall = 1;
+    else if (L.has_ins && fmaf((rn - L.ins_r0) * L.ins_inv_er, (rn - L.ins_r0) * L.ins_inv_er,
+                               ((zn - L.ins_z0) * L.ins_inv_ez) * ((zn - L.ins_z0) * L.ins_inv_ez)) - 1.0f <= 0.0f)
+        wall = 1;  // the insert is outer-electrode metal
     else if (zn <= 0.0f) wall = 2;
     else if (zn >= L.L) wall = 3;
     const float cs = x * inv, sn = y * inv;
@@ -464,6 +504,7 @@ __device__ __forceinline__ void push_particle(const KArgs& A, const ChunkCtx& X,
             gbl_add(&Qg[n00 + 1], (unsigned long long)q01);
             gbl_add(&Qg[n00 + L.W + 1], (unsigned long long)q11);
         }
+        if (L.has_ins) deposit_qw(A.It[X.inst], X.Qw, w, rn, zn);
     }
     if (COUNT) {
         // survivors, by the tile of the new position: tiles next to the
@@ -626,7 +667,7 @@ __global__ void __launch_bounds__(kPWG) __attribute__((amdgpu_waves_per_eu(8, 8)
         ChunkCtx X;
         X.L = local_inst(I);
         X.sEB = sEB; X.sQ = sQ; X.s_ctr = s_ctr; X.s_bcnt = s_bcnt; X.s_bbase = s_bbase; X.s_ccnt = s_ccnt;
-        X.out = out; X.EB = F.EB; X.Q = F.Q;
+        X.out = out; X.EB = F.EB; X.Q = F.Q; X.Qw = F.Qw;
         X.inst = inst; X.ti_c = ti_c; X.tj_c = tj_c; X.i0 = i0; X.i1 = i1; X.j0 = j0; X.j1 = j1; X.ww = ww;
         X.win = win; X.step = step;
         // U particles per lane per pass (their loads are all in flight before
@@ -720,6 +761,7 @@ __global__ void __launch_bounds__(kWG) k_collide(KArgs A, PSet P, int scatter) {
         atomicAdd(&Qg[n00 + I.W], (unsigned long long)q10);
         atomicAdd(&Qg[n00 + 1], (unsigned long long)q01);
         atomicAdd(&Qg[n00 + I.W + 1], (unsigned long long)q11);
+        if (I.has_ins) deposit_qw(I, A.Ft[inst].Qw, w, r, z);
         if (A.cnt_out) atomicAdd(&A.cnt_out[I.tile_off + (i / A.TR) * I.ntz + (j / A.TZ)], 1u);
     }
 }
@@ -742,6 +784,8 @@ __global__ void __launch_bounds__(kWG) k_source32(KArgs A, PSet P, int scatter) 
         unsigned long long key;
         double rd, zd, vr, vt, vz;
         source_draw(I, first + j, key, rd, zd, vr, vt, vz);
+        if (I.has_ins && ins_g(I, rd, zd) <= 0.0) continue;  // inside the insert: outside the domain
+        atomicAdd((unsigned long long*)&cnt[C_SOURCE], 1ull);
         const long long rel = base + (long long)atomicAdd((unsigned long long*)&cnt[C_SPAWN], 1ull);
         if (rel >= I.p_cap) {
             atomicAdd((unsigned long long*)&cnt[C_DROPPED], 1ull);
@@ -766,9 +810,9 @@ __global__ void __launch_bounds__(kWG) k_source32(KArgs A, PSet P, int scatter) 
         atomicAdd(&Qg[n00 + I.W], (unsigned long long)q10);
         atomicAdd(&Qg[n00 + 1], (unsigned long long)q01);
         atomicAdd(&Qg[n00 + I.W + 1], (unsigned long long)q11);
+        if (I.has_ins) deposit_qw(I, A.Ft[inst].Qw, wf, r, z);
         if (A.cnt_out) atomicAdd(&A.cnt_out[I.tile_off + (i / A.TR) * I.ntz + (jj / A.TZ)], 1u);
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0 && count > 0) atomicAdd((unsigned long long*)&cnt[C_SOURCE], count);
 }
 
 // Fluid-moment node sums of one instance's live particles (diagnostic),
@@ -794,7 +838,11 @@ __global__ void k_prep(long long* ctl, const long long* cnt, int n_inst) {
 __global__ void k_zero_q(const DevInst* It, const FieldDev* Ft) {
     const DevInst& I = It[blockIdx.y];
     long long* Q = Ft[blockIdx.y].Q;
-    for (int n = blockIdx.x * blockDim.x + threadIdx.x; n < I.nodes; n += gridDim.x * blockDim.x) Q[n] = 0;
+    long long* Qw = Ft[blockIdx.y].Qw;
+    for (int n = blockIdx.x * blockDim.x + threadIdx.x; n < I.nodes; n += gridDim.x * blockDim.x) {
+        Q[n] = 0;
+        if (Qw) Qw[n] = 0;
+    }
 }
 
 // ---- tile sort ------------------------------------------------------------
@@ -972,7 +1020,7 @@ __global__ void k_load32(DevInst I, double r_lo, double r_hi, double z_lo, doubl
     }
 }
 
-__global__ void k_deposit32(DevInst I, PSet P, long long* Q, const long long* cnt) {
+__global__ void k_deposit32(DevInst I, PSet P, long long* Q, long long* Qw, const long long* cnt) {
     const long long slots = cnt[C_SLOTS];
     for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < slots;
          q += (long long)gridDim.x * blockDim.x) {
@@ -990,6 +1038,7 @@ __global__ void k_deposit32(DevInst I, PSet P, long long* Q, const long long* cn
         atomicAdd(&Qg[n00 + I.W], (unsigned long long)q10);
         atomicAdd(&Qg[n00 + 1], (unsigned long long)q01);
         atomicAdd(&Qg[n00 + I.W + 1], (unsigned long long)q11);
+        if (Qw) deposit_qw(I, Qw, weight_at(I, P, p), r, P.z[p]);
     }
 }
 
@@ -1857,7 +1906,8 @@ pic_status f32_deposit_only(pic_ctx* ctx, int k) {
     F32State* S = pic_get_f32(ctx);
     const DevInst& I = pic_inst_dev(ctx, k);
     hipLaunchKernelGGL(k_deposit32, dim3(grid_for(I.p_cap)), dim3(kWG), 0, pic_stream(ctx), I, S->set[S->cur],
-                       pic_inst_Q(ctx, k), pic_counters(ctx) + (long long)k * C_NCOUNT);
+                       pic_inst_Q(ctx, k), I.has_ins ? pic_inst_Qw(ctx, k) : nullptr,
+                       pic_counters(ctx) + (long long)k * C_NCOUNT);
     CK32(hipGetLastError());
     return PIC_OK;
 }

@@ -126,13 +126,15 @@ __global__ void __launch_bounds__(kFftMaxBlock) kf_dst(const DevInst* __restrict
     const bool hasB = iB <= I.nr - 1;
     const bool open = I.open_ends != 0;
     const int N = 2 * nz;
-    const double bs = mode == 0 ? bscale[inst] : 1.0;
+    // an instance with the elliptic insert has its load in rhs already
+    const bool from_q = mode == 0 && !I.has_ins;
+    const double bs = from_q ? bscale[inst] : 1.0;
     for (int j = threadIdx.x; j < N; j += blockDim.x) {
         int jj = j <= nz ? j : N - j;
         double sg = (open || j <= nz) ? 1.0 : -1.0;
         double va = 0.0, vb = 0.0;
         if (open || (jj >= 1 && jj <= nz - 1)) {
-            if (mode == 0) {
+            if (from_q) {
                 va = (double)F.Q[(long long)iA * W + jj] * bs;
                 vb = hasB ? (double)F.Q[(long long)iB * W + jj] * bs : 0.0;
             } else {

@@ -112,6 +112,7 @@ __global__ void __launch_bounds__(kBlock) k_push64(DevInst I, P64 p, const doubl
         int wall = -1;
         if (rn <= I.a) wall = 0;
         else if (rn >= I.b) wall = 1;
+        else if (I.has_ins && ins_g(I, rn, zn) <= 0.0) wall = 1;  // the insert is outer-electrode metal
         else if (zn <= 0.0) wall = 2;
         else if (zn >= I.L) wall = 3;
         if (wall >= 0) {
@@ -246,6 +247,8 @@ __global__ void __launch_bounds__(kBlock) k_source64(DevInst I, P64 p, long long
         unsigned long long key;
         double r, z, vr, vt, vz;
         source_draw(I, first + j, key, r, z, vr, vt, vz);
+        if (I.has_ins && ins_g(I, r, z) <= 0.0) continue;  // inside the insert: outside the domain
+        atomicAdd((unsigned long long*)&cnt[C_SOURCE], 1ull);
         const long long slot = n + (long long)atomicAdd((unsigned long long*)&cnt[C_SPAWN], 1ull);
         if (slot >= I.p_cap) {
             atomicAdd((unsigned long long*)&cnt[C_DROPPED], 1ull);
@@ -259,7 +262,6 @@ __global__ void __launch_bounds__(kBlock) k_source64(DevInst I, P64 p, long long
         p.w[slot] = I.weight;
         p.key[slot] = key;
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0 && count > 0) atomicAdd((unsigned long long*)&cnt[C_SOURCE], count);
 }
 
 // Fluid-moment node sums of every live particle (diagnostic).
@@ -274,9 +276,24 @@ __global__ void __launch_bounds__(kBlock) k_moments64(DevInst I, P64 p, const lo
 }
 
 // Fixed-point deposit: node charges rint(W w_k) for three nodes, the fourth
-// takes the remainder so every particle adds exactly W.
+// takes the remainder so every particle adds exactly W.  With the insert, a
+// particle in the weight function's band also deposits rint(W (w(x_p) - 1))
+// into Qw by the same rule.
+__device__ __forceinline__ void deposit4(long long* Q, const Shape& sh, int W, long long Wq) {
+    const double Wd = (double)Wq;
+    const long long q00 = (long long)rint(Wd * sh.w00);
+    const long long q10 = (long long)rint(Wd * sh.w10);
+    const long long q01 = (long long)rint(Wd * sh.w01);
+    const long long q11 = Wq - q00 - q10 - q01;
+    const long long n00 = (long long)sh.i * W + sh.j;
+    atomicAdd((unsigned long long*)&Q[n00], (unsigned long long)q00);
+    atomicAdd((unsigned long long*)&Q[n00 + W], (unsigned long long)q10);
+    atomicAdd((unsigned long long*)&Q[n00 + 1], (unsigned long long)q01);
+    atomicAdd((unsigned long long*)&Q[n00 + W + 1], (unsigned long long)q11);
+}
+
 __global__ void __launch_bounds__(kBlock) k_deposit64(DevInst I, P64 p, long long* __restrict__ Q,
-                                                     long long* cnt) {
+                                                     long long* __restrict__ Qw, long long* cnt) {
     long long n = cnt[C_SLOTS] + cnt[C_SPAWN];
     if (n > I.p_cap) n = I.p_cap;
     for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < n;
@@ -287,16 +304,11 @@ __global__ void __launch_bounds__(kBlock) k_deposit64(DevInst I, P64 p, long lon
         double wq = p.w[q] * I.two_S;
         long long Wq = (long long)rint(wq);
         if (wq > 2147483648.0) atomicMax((unsigned long long*)&cnt[C_OVERFLOW], 1ull);
-        double Wd = (double)Wq;
-        long long q00 = (long long)rint(Wd * sh.w00);
-        long long q10 = (long long)rint(Wd * sh.w10);
-        long long q01 = (long long)rint(Wd * sh.w01);
-        long long q11 = Wq - q00 - q10 - q01;
-        long long n00 = (long long)sh.i * I.W + sh.j;
-        atomicAdd((unsigned long long*)&Q[n00], (unsigned long long)q00);
-        atomicAdd((unsigned long long*)&Q[n00 + I.W], (unsigned long long)q10);
-        atomicAdd((unsigned long long*)&Q[n00 + 1], (unsigned long long)q01);
-        atomicAdd((unsigned long long*)&Q[n00 + I.W + 1], (unsigned long long)q11);
+        deposit4(Q, sh, I.W, Wq);
+        if (Qw) {
+            const double g = ins_g(I, r, p.z[q]);
+            if (g < I.ins_gam) deposit4(Qw, sh, I.W, (long long)rint((double)Wq * (ins_w(I, g) - 1.0)));
+        }
     }
 }
 
@@ -362,9 +374,10 @@ hipError_t launch_moments64(const DevInst& I, P64 p, const long long* cnt, doubl
     return hipGetLastError();
 }
 
-hipError_t launch_deposit64(const DevInst& I, P64 p, long long* Q, long long* cnt,
+hipError_t launch_deposit64(const DevInst& I, P64 p, long long* Q, long long* Qw, long long* cnt,
                             long long grid_cap, hipStream_t s) {
-    hipLaunchKernelGGL(k_deposit64, dim3(grid_for(grid_cap)), dim3(kBlock), 0, s, I, p, Q, cnt);
+    hipLaunchKernelGGL(k_deposit64, dim3(grid_for(grid_cap)), dim3(kBlock), 0, s, I, p, Q, I.has_ins ? Qw : nullptr,
+                       cnt);
     return hipGetLastError();
 }
 

@@ -6,6 +6,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <string>
+#include <vector>
+
 #include "pic.h"
 
 namespace pic {
@@ -56,7 +59,28 @@ struct DevInst {
     // per-particle weight array is neither read nor kept up to date; 0 when
     // weights differ between particles (the array is then authoritative)
     float w_uni;
+    // elliptic insert on the outer electrode (has_ins = 0: none): metal where
+    // ins_g <= 0; web-spline weight band up to g = ins_gam
+    int has_ins;
+    double ins_r0, ins_z0, ins_er, ins_ez, ins_gam;
+    float ins_r0_f, ins_z0_f, ins_inv_er_f, ins_inv_ez_f, ins_gam_f;
 };
+
+// Elliptic insert (Sec. III gun geometry): g = ((r-r0)/er)^2 + ((z-z0)/ez)^2 - 1,
+// g <= 0 inside the metal.  Web-spline weight function of the space-charge
+// basis: 0 in the metal, 1 - (1 - g/gam)^3 in the band 0 < g < gam, 1 beyond.
+__host__ __device__ inline double ins_g(const DevInst& I, double r, double z) {
+#pragma clang fp contract(off)
+    const double u = (r - I.ins_r0) / I.ins_er, v = (z - I.ins_z0) / I.ins_ez;
+    return (u * u + v * v) - 1.0;
+}
+__host__ __device__ inline double ins_w(const DevInst& I, double g) {
+#pragma clang fp contract(off)
+    if (g <= 0.0) return 0.0;
+    if (g >= I.ins_gam) return 1.0;
+    const double s = 1.0 - g / I.ins_gam;
+    return 1.0 - s * s * s;
+}
 
 // Device counter block per instance (long long entries).
 enum Counter {
@@ -221,7 +245,8 @@ hipError_t launch_source64(const DevInst& I, P64 p, long long* cnt, hipStream_t 
 hipError_t launch_moments64(const DevInst& I, P64 p, const long long* cnt, double* acc, hipStream_t s);
 hipError_t launch_mcc64(const DevInst& I, P64 p, long long* cnt, long long grid_cap,
                         hipStream_t s);
-hipError_t launch_deposit64(const DevInst& I, P64 p, long long* Q, long long* cnt,
+// Qw (insert instances, else null): the band particles' q (w(x_p) - 1)
+hipError_t launch_deposit64(const DevInst& I, P64 p, long long* Q, long long* Qw, long long* cnt,
                             long long grid_cap, hipStream_t s);
 hipError_t launch_compact64(const DevInst& I, P64 src, P64 dst, long long* cnt,
                             long long* tmp_count, long long grid_cap, hipStream_t s);
@@ -256,6 +281,44 @@ struct FieldDev {
     float4* EB;            // FP32 form output (or null)
     const double* V;       // node volumes
     double* avg_acc;       // time-average accumulator
+    long long* Qw;         // insert: node charges of q (w(x_p) - 1) of the particles in the weight band
+};
+
+// Elliptic insert, device side of the corrected solve (insert.hip).  The
+// instance's Galerkin system differs from the rectangle's only in the rows
+// and columns of the m nodes of M (next to the insert): A = A_rect + E D E^T.
+// A step solves y = A_rect^-1 b, s = H y_M with H = (I + D G)^-1 D and
+// G = (A_rect^-1)_MM, then x = y - A_rect^-1 E s, and evaluates the basis at
+// the nodes of M.
+struct InsDev {
+    int inst;              // instance in the main tables
+    int m;                 // nodes in M
+    long long nodes;
+    const int* Mnode;      // [m] node index of each M entry
+    const int* map;        // [nodes] index in M or -1
+    const int* rp;         // [m+1] load of M entry a: sum_t rf[t] (Q + Qw)[rk[t]]
+    const int* rk;
+    const double* rf;
+    const double* H;       // [m x m] row-major
+    const int* typ;        // [m] basis at the node: 1 w c, 2 w * extension, 0 zero
+    const double* wn;      // [m] weight function at the node
+    const int* ek;         // [4m] extension block of an outer node
+    const double* ef;      // [4m] its factors
+    double* ybuf;          // [nodes] phi_base + A_rect^-1 b
+    double* rhs2;          // [nodes] load of the correction, then its modes
+    double* yM;            // [m]
+    double* sM;            // [m]
+    double* val;           // [m]
+};
+
+// Host set-up of one instance's insert (independent of the device).
+struct InsHost {
+    int m = 0;
+    std::vector<int> Mnode, map, rp, rk, typ, ek;
+    std::vector<double> rf, wn, ef;
+    std::vector<int> Dr, Dc;          // correction matrix D (entries by M index)
+    std::vector<double> Dv;
+    int counts[4] = {0, 0, 0, 0};     // nodes: not unknown, inner, outer, exterior
 };
 hipError_t launch_zero_i64(long long* p, long long n, hipStream_t s);
 // Poisson solve of instances [inst_base, inst_base+n_inst) of the device
@@ -271,5 +334,28 @@ hipError_t launch_efield_tab(const DevInst* It, const FieldDev* Ft, int inst_bas
 hipError_t launch_sample_tab(const DevInst* It, const FieldDev* Ft, int n_inst, long long* cnt, long long* ctl,
                              hipStream_t s);
 hipError_t set_field_kernel_attrs(int max_nz);
+
+// Elliptic insert (insert.hip).  ins_build classifies the nodes, attaches
+// the outer hats, and assembles D on the host; an empty string means success.
+std::string ins_build(const pic_instance_cfg& c, InsHost& h);
+// per step (or for the vacuum): the load of every insert instance's nodes
+// from Q and Qw (scaled by bscale) into rhs
+hipError_t launch_ins_rhs(const DevInst* It, const InsDev* D, int n_ins, long long max_nodes, const FieldDev* Ft,
+                          const double* bscale, hipStream_t s);
+// y_M = ybuf - base at M, s = H y_M, rhs2 = -E s (every node written)
+hipError_t launch_ins_correct(const DevInst* It, const InsDev* D, int n_ins, int max_m, long long max_nodes,
+                              const FieldDev* Fbase, hipStream_t s);
+// the basis evaluated at the nodes of M: phi = base + (w c | w ext c | 0)
+hipError_t launch_ins_fix(const DevInst* It, const InsDev* D, int n_ins, int max_m, const FieldDev* Fout,
+                          hipStream_t s);
+// set-up: unit right-hand sides e_{Mnode[b0+t]} in rhs + t * stride, and the
+// M entries of the solutions into G[:, b0+t]
+hipError_t launch_ins_units(double* rhs, long long stride, long long nodes, const int* Mnode, int b0, int cnt,
+                            hipStream_t s);
+hipError_t launch_ins_collect(const double* phi, long long stride, const int* Mnode, int m, int b0, int cnt,
+                              double* G, hipStream_t s);
+// set-up: Gauss-Jordan elimination with partial pivoting of [C | D] (m x 2m,
+// row-major) into [I | C^-1 D]; *singular set when a pivot vanishes
+hipError_t launch_ins_gauss_jordan(double* CD, int m, double* fcol, int* piv, double* pval, hipStream_t s);
 
 }  // namespace pic

@@ -18,6 +18,9 @@ coaxial traps stand in for them:
     coax512    512x2048 mesh, 64M electrons, mirror B, -30 kV        (FP32)
     scan32     32 instances on 128x512, p/V/B scan, 0.5M-8M each     (FP32)
     batch8     8 instances on 256x1024, 16M each, mirror B           (FP32)
+    gun        the paper's own geometry: coax with the elliptic insert, open
+               ends, 30 kV, 64x128 mesh (both forms)
+    gun8       8 gun instances on 256x512, 16M each                  (FP32)
 """
 import math
 
@@ -35,6 +38,7 @@ _BASE = dict(
     T_init_eV=1.0, weight=1.0e5, load_mode=1,
     seed=0, dt=1.0e-12, fx_shift=0, diag_interval=10, collisions=1,
     src_rate=0.0, src_T_eV=0.0,
+    ins_r0=0.0, ins_z0=0.0, ins_er=0.0, ins_ez=0.0, ins_band=0.0,
 )
 
 # Total seed charge of the small case (50k x 1e5 electrons) is kept for the
@@ -112,6 +116,37 @@ def batch8(n_per=16_000_000):
     return out
 
 
+def gun(**over):
+    """The paper's geometry (Sec. III, the corona-ring region of the gun): a
+    coax with r_a = 63.75 mm and r_b = 81 mm between open ends (d(phi)/dz = 0)
+    at z = -10 mm and 34 mm, here shifted to 0 .. 44 mm, with a filled
+    elliptic insert on the outer cylinder centred at r = 81 mm, z = 12 mm
+    (here 22 mm), semi-axes 3 mm in r and 14 mm in z.  Bias 30 kV (inner
+    conductor at -30 kV), B ~ 0.28 T (uniform here: the paper's field map is
+    not available), the raised pressure 1e-1 mbar, a 1 eV seed cloud of
+    ~1e15 m^-3 in a load box clear of the insert (Sec. III.A)."""
+    c = dict(_BASE, a=63.75e-3, b=81.0e-3, L=44.0e-3, nr=64, nz=128,
+             V_inner=-30000.0, V_outer=0.0, V_end=0.0, end_mode=2, B0=0.28, mirror_k=0.0,
+             p_mbar=1.0e-1, n_init=50000, r_lo=66.0e-3, r_hi=76.0e-3, z_lo=2.0e-3, z_hi=42.0e-3,
+             load_mode=0, weight=3.6e6, seed=5,
+             ins_r0=81.0e-3, ins_z0=22.0e-3, ins_er=3.0e-3, ins_ez=14.0e-3)
+    c.update(over)
+    return _finish(c)
+
+
+def gun8(n_per=16_000_000, nr=256, nz=512):
+    """8 gun instances (pressures 2.5e-2 .. 1e-1 mbar and biases 20 .. 40 kV)
+    on nr x nz meshes, n_per electrons each, the seed weight kept at the
+    1e15 m^-3 density of the small case."""
+    out = []
+    press = (2.5e-2, 5.0e-2, 1.0e-1, 1.0e-1)
+    bias = (-30000.0, -30000.0, -30000.0, -20000.0, -40000.0)
+    for i in range(8):
+        out.append(gun(nr=nr, nz=nz, n_init=n_per, weight=3.6e6 * 50000 / n_per, p_mbar=press[i % 4],
+                       V_inner=bias[i % 5], E_cap_eV=0.0, seed=(6 << 32) | i))
+    return out
+
+
 WORKLOADS = {
     "coax64": lambda: [coax64()],
     "coax64hot": lambda: [coax64hot()],
@@ -119,6 +154,8 @@ WORKLOADS = {
     "coax512": lambda: [coax512()],
     "scan32": scan32,
     "batch8": batch8,
+    "gun": lambda: [gun()],
+    "gun8": gun8,
 }
 
 

@@ -1,0 +1,332 @@
+"""The elliptic insert on the outer electrode (the paper's gun geometry,
+Sec. III) with weighted extended B-splines of degree 1 (Sec. II.A).
+
+CPU: the oracle's web-spline solver pinned by the plain solver (an insert
+outside the domain), by the analytic coaxial potential with a flat insert
+whose wall lies off the mesh lines, and by a manufactured solution on a true
+ellipse; the weight function; the library's host set-up against the oracle's
+node classes.  GPU: the corrected two-solve path against the oracle's banded
+factorisation, the band charges, absorption on the insert, the seed source.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import pic_inputs as pi
+from helpers import by_key, gpu_and_oracle, rel_vec_err
+from paper_2206_14662_amd import binding as B
+
+F32 = B.PIC_MODE_FP32_BATCHED
+F64 = B.PIC_MODE_FP64_PLAIN
+
+
+def ellipse(nr=32, nz=64, end_mode=0, band=0.0, **over):
+    """A coax (a = 1 mm, b = 10 mm, L = 30 mm) with an elliptic insert on the
+    outer wall, semi-axes 3.1 mm (r) and 7.3 mm (z)."""
+    kw = dict(a=1e-3, b=10e-3, L=30e-3, nr=nr, nz=nz, end_mode=end_mode, n_init=0, ins_r0=10e-3, ins_z0=15e-3,
+              ins_er=3.1e-3, ins_ez=7.3e-3, ins_band=band)
+    kw.update(over)
+    return pi.coax64(**kw)
+
+
+# ---------------------------------------------------------------------------
+# oracle pins (CPU)
+# ---------------------------------------------------------------------------
+
+def test_insert_outside_the_domain_is_the_plain_solver():
+    """No node meets the band: every row is the plain grid's, so the banded
+    factorisation of the assembled matrix must give the sine-transform
+    solver's answer (vacuum and space charge)."""
+    for end_mode in (0, 2):
+        c = pi.coax64(nr=32, nz=64, end_mode=end_mode, ins_r0=0.05, ins_z0=0.03, ins_er=1e-3, ins_ez=5e-3)
+        info = oracle.ins_info(c)
+        assert info["counts"][2] == info["counts"][3] == 0
+        plain = dict(c, ins_er=0.0, ins_ez=0.0)
+        p0, p1 = oracle.vacuum(plain), oracle.vacuum(c)
+        assert np.abs(p0 - p1).max() <= 1e-12 * np.abs(p0).max()
+        st = pi.particle_state(c, 3000, seed=4)
+        a, b = oracle.Sim(plain), oracle.Sim(c)
+        a.set_particles(st)
+        b.set_particles(st)
+        assert np.array_equal(a.charge(), b.charge())
+        assert np.array_equal(b.band_charge(), np.zeros_like(b.charge()))
+        sa, sb = a.phi() - p0, b.phi() - p1
+        assert np.abs(sa - sb).max() <= 1e-11 * np.abs(sa).max()
+
+
+def _flat_error(nr, band):
+    """Vacuum potential of a coax whose outer wall is a flat insert at
+    r_w = b - er (the ellipse stretched far beyond L), open ends: the exact
+    solution is the coaxial log profile between a and r_w(z)."""
+    a, b, L, er = 1e-3, 10e-3, 60e-3, 2.37e-3
+    c = pi.coax64(nr=nr, nz=8, end_mode=2, V_end=0.0, n_init=0, ins_r0=b, ins_z0=L / 2, ins_er=er, ins_ez=200 * L,
+                  ins_band=band)
+    phi = oracle.vacuum(c)
+    r = a + (b - a) * np.arange(nr + 1) / nr
+    z = L * np.arange(9) / 8
+    rw = b - er * np.sqrt(1.0 - ((z - L / 2) / c["ins_ez"]) ** 2)
+    ex = c["V_inner"] + (c["V_outer"] - c["V_inner"]) * np.log(r[:, None] / a) / np.log(rw[None, :] / a)
+    ex = np.where(r[:, None] < rw[None, :], ex, c["V_outer"])
+    return np.abs(phi - ex).max() / abs(c["V_inner"])
+
+
+def test_flat_insert_converges_to_the_coaxial_log_profile():
+    """The wall sits between mesh lines (at 0.74 of the gap).  With a weight
+    band of fixed width (3 cells of the coarsest mesh) the error falls as h^2,
+    like the plain Q1 solver's with the wall on a mesh line; with the default
+    band of 3 cells it stays within a few times the plain error."""
+    fixed = [_flat_error(nr, 3.0 * nr / 16) for nr in (16, 32, 64, 128)]
+    for e0, e1 in zip(fixed, fixed[1:]):
+        assert e0 / e1 > 3.0, fixed
+    assert fixed[-1] < 5e-5
+    assert _flat_error(128, 0.0) < 1e-4
+
+
+def _manufactured(c):
+    """phi* = g (r - a)(b - r) sin(pi z / L) / (b - a)^2 vanishes on the
+    electrodes, on the ends and on the insert (g = 0); f = -lap(phi*)."""
+    a, b, L = c["a"], c["b"], c["L"]
+    er, ez, r0, z0 = c["ins_er"], c["ins_ez"], c["ins_r0"], c["ins_z0"]
+    k = 1.0 / (b - a) ** 2
+
+    def parts(r, z):
+        u, v = (r - r0) / er, (z - z0) / ez
+        G, Gr, Grr, Gz, Gzz = u * u + v * v - 1, 2 * u / er, 2 / er ** 2, 2 * v / ez, 2 / ez ** 2
+        P, Pr, Prr = (r - a) * (b - r) * k, (a + b - 2 * r) * k, -2 * k
+        S, Sz, Szz = np.sin(np.pi * z / L), np.pi / L * np.cos(np.pi * z / L), -(np.pi / L) ** 2 * np.sin(np.pi * z / L)
+        return G, Gr, Grr, Gz, Gzz, P, Pr, Prr, S, Sz, Szz
+
+    def phi(r, z):
+        G, _, _, _, _, P, _, _, S, _, _ = parts(r, z)
+        return G * P * S
+
+    def f(r, z):
+        G, Gr, Grr, Gz, Gzz, P, Pr, Prr, S, Sz, Szz = parts(r, z)
+        phr = (Gr * P + G * Pr) * S
+        phrr = (Grr * P + 2 * Gr * Pr + G * Prr) * S
+        phzz = P * (Gzz * S + 2 * Gz * Sz + G * Szz)
+        return -(phrr + phr / r + phzz)
+    return phi, f
+
+
+def test_manufactured_solution_on_the_ellipse():
+    c0 = ellipse()
+    phi, f = _manufactured(c0)
+    # the source is -lap(phi*): check it against finite differences first
+    r, z, h = 4.3e-3, 11.1e-3, 1e-6
+    lap = ((phi(r + h, z) - 2 * phi(r, z) + phi(r - h, z)) / h ** 2 + (phi(r + h, z) - phi(r - h, z)) / (2 * h) / r
+           + (phi(r, z + h) - 2 * phi(r, z) + phi(r, z - h)) / h ** 2)
+    assert abs(f(r, z) + lap) <= 1e-5 * abs(lap)
+    rms = []
+    for nr, nz in ((16, 32), (32, 64), (64, 128)):
+        c = ellipse(nr, nz)
+        got = oracle.ins_poisson_fn(c, f)
+        R, Z = np.meshgrid(c["a"] + (c["b"] - c["a"]) * np.arange(nr + 1) / nr, c["L"] * np.arange(nz + 1) / nz,
+                           indexing="ij")
+        g = ((R - c["ins_r0"]) / c["ins_er"]) ** 2 + ((Z - c["ins_z0"]) / c["ins_ez"]) ** 2 - 1
+        ex = np.where(g > 0, phi(R, Z), 0.0)
+        err = got - ex
+        rms.append(np.sqrt(np.mean(err ** 2)) / np.abs(ex).max())
+        if nr == 64:
+            assert np.abs(err).max() / np.abs(ex).max() < 1.5e-3
+    assert rms[0] / rms[1] > 2.8 and rms[1] / rms[2] > 2.8, rms
+
+
+def test_weight_function():
+    c = ellipse(64, 128)
+    gam = oracle.ins_gamma(c)
+    dr, dz = (c["b"] - c["a"]) / 64, c["L"] / 128
+    assert gam == pytest.approx(2 * 3 * max(dr / c["ins_er"], dz / c["ins_ez"]))
+    rng = np.random.default_rng(3)
+    for _ in range(200):
+        r = rng.uniform(c["a"], c["b"])
+        z = rng.uniform(0, c["L"])
+        g = oracle.ins_g(c, r, z)
+        w, wr, wz = oracle.ins_weight(c, r, z)
+        if g <= 0:
+            assert w == 0 and wr == 0 and wz == 0
+        elif g >= gam:
+            assert w == 1 and wr == 0 and wz == 0
+        else:
+            s = 1 - g / gam
+            assert w == pytest.approx(1 - s ** 3, rel=1e-14)
+            h = 1e-9
+            fr = (oracle.ins_weight(c, r + h, z)[0] - oracle.ins_weight(c, r - h, z)[0]) / (2 * h)
+            fz = (oracle.ins_weight(c, r, z + h)[0] - oracle.ins_weight(c, r, z - h)[0]) / (2 * h)
+            assert wr == pytest.approx(fr, rel=1e-5, abs=1e-3 * abs(wr) + 1e-6)
+            assert wz == pytest.approx(fz, rel=1e-5, abs=1e-3 * abs(wz) + 1e-6)
+    # on the ellipse w vanishes linearly: w ~ 3 g / gam
+    r = c["ins_r0"] - c["ins_er"] * math.sqrt(1 + 1e-6)
+    assert oracle.ins_weight(c, r, c["ins_z0"])[0] == pytest.approx(3e-6 / gam, rel=1e-4)
+
+
+@pytest.mark.parametrize("end_mode", [0, 2])
+def test_library_setup_matches_the_oracle_node_classes(end_mode):
+    for nr, nz in ((32, 64), (64, 128)):
+        c = ellipse(nr, nz, end_mode)
+        lib = B.pic_insert_layout(c)
+        assert lib["counts"] == oracle.ins_info(c)["counts"]
+        assert 0 < lib["m"] < 0.2 * (nr + 1) * (nz + 1)
+    g = pi.gun()
+    assert B.pic_insert_layout(g)["counts"] == oracle.ins_info(g)["counts"]
+
+
+def test_refused_configurations():
+    bad = [ellipse(ins_r0=4.5e-3),                       # band reaches the inner electrode
+           ellipse(ins_z0=6e-3),                         # band reaches an end plate
+           ellipse(ins_er=-1e-3),
+           dict(ellipse(), n_init=100, r_lo=5e-3, r_hi=9e-3, z_lo=10e-3, z_hi=20e-3)]  # load box in the metal
+    for c in bad:
+        with pytest.raises(B.PicError):
+            B.pic_insert_layout(c)
+    with pytest.raises(ValueError):
+        oracle.Sim(ellipse(ins_r0=4.5e-3))
+
+
+def test_oracle_band_charge_and_absorption():
+    c = ellipse(64, 128, collisions=0)
+    S = oracle.auto_shift(c["weight"])
+    W = round(c["weight"] * 2.0 ** S)
+    gam = oracle.ins_gamma(c)
+    # one electron in the band, one outside, one that flies into the insert
+    r_band = c["ins_r0"] - c["ins_er"] * math.sqrt(1 + 0.3 * gam)
+    st = dict(r=np.array([r_band, 4e-3, c["ins_r0"] - c["ins_er"] - 1e-5]),
+              z=np.array([c["ins_z0"], 5e-3, c["ins_z0"]]),
+              vr=np.array([0.0, 0.0, 5e7]), vt=np.zeros(3), vz=np.zeros(3), w=np.full(3, c["weight"]),
+              key=np.arange(3, dtype=np.uint64))
+    o = oracle.Sim(c, fx_shift=S, capacity=64)
+    o.set_fields(**pi.uniform_fields(c), frozen=1)
+    o.set_particles(st)
+    wp = oracle.ins_weight(c, r_band, c["ins_z0"])[0]
+    qw = o.band_charge()
+    band_total = round(W * (wp - 1.0)) + round(W * (oracle.ins_weight(c, st["r"][2], st["z"][2])[0] - 1.0))
+    assert qw.sum() == band_total and qw.sum() < 0
+    assert o.charge().sum() == 3 * W
+    o.step(1)
+    d = o.diag()
+    assert d["n_absorbed"] == [0, 1, 0, 0] and d["n_live"] == 2 and d["absorbed_W"][1] == W
+
+
+def test_oracle_source_skips_the_insert():
+    c = ellipse(32, 64, src_rate=5000.0, collisions=0, p_mbar=0.0)
+    o = oracle.Sim(c, capacity=1 << 16)
+    o.set_fields(**pi.uniform_fields(c), frozen=1)
+    o.step(1)
+    p = o.get_particles()
+    assert 0 < len(p["r"]) < 5000
+    g = ((p["r"] - c["ins_r0"]) / c["ins_er"]) ** 2 + ((p["z"] - c["ins_z0"]) / c["ins_ez"]) ** 2 - 1
+    assert (g > 0).all()
+    # the skipped keys are those of draws inside the ellipse: about its volume fraction
+    frac = 1 - len(p["r"]) / 5000
+    vol = np.pi * (c["b"] ** 2 - c["a"] ** 2) * c["L"]
+    zz = np.linspace(c["ins_z0"] - c["ins_ez"], c["ins_z0"] + c["ins_ez"], 20001)
+    rin = c["ins_r0"] - c["ins_er"] * np.sqrt(np.clip(1 - ((zz - c["ins_z0"]) / c["ins_ez"]) ** 2, 0, 1))
+    metal = np.trapezoid(np.pi * (c["b"] ** 2 - rin ** 2), zz)
+    assert abs(frac - metal / vol) < 0.02
+
+
+# ---------------------------------------------------------------------------
+# GPU parity
+# ---------------------------------------------------------------------------
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("mode", [F64, F32])
+@pytest.mark.parametrize("case", ["ellipse0", "ellipse2", "gun"])
+def test_vacuum_with_insert_matches_the_oracle(mode, case):
+    c = {"ellipse0": ellipse(64, 128, 0), "ellipse2": ellipse(64, 128, 2), "gun": pi.gun(n_init=0)}[case]
+    g = B.Sim([c], mode=mode)
+    ref = oracle.vacuum(c)
+    assert np.abs(g.phi() - ref).max() <= 1e-9 * np.abs(ref).max()
+    g.close()
+
+
+@pytest.mark.gpu
+def test_charge_solve_with_insert_matches_the_oracle():
+    """Particles over the whole domain and in the band: Q and Qw bit-exact,
+    the space-charge potential to solver rounding."""
+    c = pi.gun(n_init=0)
+    st = pi.particle_state(c, 40000, seed=9)
+    gg = ((st["r"] - c["ins_r0"]) / c["ins_er"]) ** 2 + ((st["z"] - c["ins_z0"]) / c["ins_ez"]) ** 2 - 1
+    st = {k: v[gg > 0] for k, v in st.items()}
+    g, o = gpu_and_oracle(c, st, frozen=0)
+    assert np.array_equal(g.charge(), o.charge())
+    assert np.array_equal(g.band_charge(), o.band_charge())
+    assert (o.band_charge() != 0).sum() > 50
+    vac = oracle.vacuum(c)
+    sg, so = g.phi() - vac, o.phi() - vac
+    assert np.abs(sg - so).max() <= 1e-9 * np.abs(so).max()
+    g.close()
+
+
+@pytest.mark.gpu
+def test_fp64_steps_with_insert_match_the_oracle():
+    """Self-consistent steps of the gun cloud at the raised pressure with
+    collisions: the same absorptions (including on the insert) and states to
+    FP64 rounding."""
+    c = pi.gun(n_init=0, collisions=0)
+    st = pi.particle_state(c, 20000, seed=11, v_scale=3e6)
+    gg = ((st["r"] - c["ins_r0"]) / c["ins_er"]) ** 2 + ((st["z"] - c["ins_z0"]) / c["ins_ez"]) ** 2 - 1
+    st = {k: v[gg > 0] for k, v in st.items()}
+    g, o = gpu_and_oracle(c, st, frozen=0)
+    g.step(30)
+    o.step(30)
+    gd, od = g.diag(), o.diag()
+    assert gd["n_absorbed"] == od["n_absorbed"] and gd["n_absorbed"][1] > 0
+    gp, op = by_key(g.get_particles()), by_key(o.get_particles())
+    assert np.array_equal(gp["key"], op["key"])
+    np.testing.assert_allclose(gp["r"], op["r"], rtol=1e-11)
+    np.testing.assert_allclose(gp["z"], op["z"], rtol=1e-11)
+    assert rel_vec_err(gp, op).max() <= 1e-9
+    assert np.array_equal(g.band_charge(), o.band_charge())
+    g.close()
+
+
+@pytest.mark.gpu
+def test_fp32_with_insert_is_invariant_and_tracks_the_oracle():
+    c = pi.gun(E_cap_eV=33020.0)
+    ref = None
+    for kw in (dict(tile_r=8, tile_z=32, sort_interval=8, use_graph=1),
+               dict(tile_r=4, tile_z=16, sort_interval=3, halo=1, use_graph=0)):
+        g = B.Sim([c], mode=F32, **kw)
+        g.step(40)
+        out = (by_key(g.get_particles()), g.charge(), g.band_charge(), g.diag())
+        g.close()
+        if ref is None:
+            ref = out
+            continue
+        for k in ("key", "r", "z", "vr", "vt", "vz"):
+            assert np.array_equal(ref[0][k], out[0][k]), k
+        assert np.array_equal(ref[1], out[1]) and np.array_equal(ref[2], out[2])
+    d = ref[3]
+    assert d["n_ioniz"] > 0
+    assert d["n_live"] + sum(d["n_absorbed"]) == c["n_init"] + d["n_ioniz"]
+    # against the oracle: counts and the cloud's density within FP32 drift
+    o = oracle.Sim(c, fx_shift=d["S"])
+    o.load()
+    o.step(40)
+    od = o.diag()
+    assert abs(d["n_live"] - od["n_live"]) <= 0.01 * od["n_live"]
+    assert abs(d["n_ioniz"] - od["n_ioniz"]) <= 0.1 * od["n_ioniz"] + 5
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("mode", [F64, F32])
+def test_source_with_insert_matches_the_oracle(mode):
+    c = ellipse(64, 128, 2, src_rate=2000.0, collisions=0, p_mbar=0.0)
+    S = B.pic_auto_shift(c["weight"])
+    g = B.Sim([dict(c, fx_shift=S)], mode=mode, capacity_min=1 << 16)
+    o = oracle.Sim(c, fx_shift=S, capacity=1 << 16)
+    f = {k: v.astype(np.float32).astype(np.float64) for k, v in pi.uniform_fields(c, Bz=0.2).items()}
+    g.set_fields(frozen=1, **f)
+    o.set_fields(**f, frozen=1)
+    g.step(3)
+    o.step(3)
+    gd, od = g.diag(), o.diag()
+    assert gd["n_source"] == od["n_source"] < 6000
+    gp, op = by_key(g.get_particles()), by_key(o.get_particles())
+    assert np.array_equal(gp["key"], op["key"])
+    tol = 1e-12 if mode == F64 else 2e-6
+    np.testing.assert_allclose(gp["r"], op["r"], rtol=tol)
+    g.close()
