@@ -40,6 +40,8 @@ WORKLOAD_TEXT = {
     "scan32": "32 instances x 128x512 mesh, 0.5M-8M electrons each, p/V/B scan",
     "coax512": "1 instance x 512x2048 mesh x 64M electrons, mirror B, -30 kV",
     "coax256": "1 instance x 256x1024 mesh x 4M electrons, mirror B, 1e-5 mbar",
+    "gun8": "8 instances of the paper's gun geometry (coax with the elliptic insert, open ends) x 256x512 mesh "
+            "x 16M electrons (128M), 20-40 kV, 2.5e-2..1e-1 mbar",
 }
 
 
@@ -242,6 +244,8 @@ def main():
         cfgs = pi.batch8(n_per=int(16_000_000 * args.scale))
     elif args.workload == "scan32":
         cfgs = pi.scan32(n_scale=args.scale)
+    elif args.workload == "gun8":
+        cfgs = pi.gun8(n_per=int(16_000_000 * args.scale))
     else:
         cfgs = [getattr(pi, args.workload)(n_init=int(getattr(pi, args.workload)()["n_init"] * args.scale))]
     print(f"# workload {args.workload}: {len(cfgs)} instances, "

@@ -215,12 +215,12 @@ __device__ __forceinline__ void scatter_f(float ur, float ut, float uz, float co
     o[2] = cosx * uz + sinx * (cp * e1z + sp * e2z);
 }
 
-// Rare path: the null-collision candidate became a real event (or not).
-// Returns 0 null, 1 elastic, 2 ionisation (child written, or dropped when the
-// instance's slots are full: then 3).
-__device__ __forceinline__ int collide_f(const DevInst& I, long long* cnt, PSet P, unsigned long long key,
-                                      unsigned int step, uint4 b0, float r, float z, float w, float& vr,
-                                      float& vt, float& vz, long long slots) {
+// The null-collision candidate becomes a real event (or not).  Returns 0
+// null, 1 elastic, 2 ionisation; sets the parent's new velocity and, for an
+// ionisation, the new electron's velocity and key.
+__device__ __forceinline__ int collide_f(const DevInst& I, unsigned long long key, unsigned int step, uint4 b0,
+                                      float& vr, float& vt, float& vz, float& cvr, float& cvt, float& cvz,
+                                      unsigned long long& ckey) {
     float u_proc = u23(b0.z);
     float v2 = (vr * vr + vt * vt) + vz * vz;
     float v = sqrtf(v2);
@@ -259,17 +259,8 @@ __device__ __forceinline__ int collide_f(const DevInst& I, long long* cnt, PSet 
     scatter_f(ur, ut, uz, cos1, phi1, dir);
     vr = vp * dir[0]; vt = vp * dir[1]; vz = vp * dir[2];
     scatter_f(ur, ut, uz, cos2, phi2, dir);
-    long long k = (long long)atomicAdd((unsigned long long*)&cnt[C_SPAWN], 1ull);
-    long long rel = slots + k;
-    if (rel >= I.p_cap) {
-        atomicAdd((unsigned long long*)&cnt[C_DROPPED], 1ull);
-        return 3;
-    }
-    long long d = I.p_off + rel;
-    P.r[d] = r; P.z[d] = z;
-    P.vr[d] = vs * dir[0]; P.vt[d] = vs * dir[1]; P.vz[d] = vs * dir[2];
-    P.w[d] = w;
-    P.key[d] = ((((unsigned long long)b3.z) << 32) | (unsigned long long)b3.w) | (1ull << 63);
+    cvr = vs * dir[0]; cvt = vs * dir[1]; cvz = vs * dir[2];
+    ckey = ((((unsigned long long)b3.z) << 32) | (unsigned long long)b3.w) | (1ull << 63);
     return 2;
 }
 
@@ -346,6 +337,9 @@ __device__ __forceinline__ unsigned int wave_aggregate(bool act, int key, F&& ad
     return rank;
 }
 
+// LDS queue of null-collision candidates per workgroup and chunk
+constexpr int kLQ = 512;
+
 // chunk-level event counters kept in LDS and their device counter slots
 enum { SC_ABS_N = 0, SC_ABS_W = 4, SC_DEAD = 8, SC_CAND = 9, SC_CAP = 10, SC_FAR = 11, SC_N = 12 };
 __constant__ int kCounterOf[SC_N] = {C_ABS_N,     C_ABS_N + 1, C_ABS_N + 2, C_ABS_N + 3, C_ABS_W, C_ABS_W + 1,
@@ -362,6 +356,8 @@ struct ChunkCtx {
     unsigned int* s_bcnt;
     const unsigned int* s_bbase;
     unsigned int* s_ccnt;
+    unsigned int* s_qn;
+    unsigned long long* s_q;
     PSet out;
     const float4* EB;
     long long* Q;
@@ -374,7 +370,7 @@ struct ChunkCtx {
 // One particle: (optional) sort destination, gather, Boris, remap, walls,
 // null-collision test, store, deposit, (optional) destination-tile count.
 // Every lane of the wave calls it (collectives inside).
-template <bool COUNT, bool SCATTER>
+template <bool COUNT, bool SCATTER, bool INS>
 __device__ __forceinline__ void push_particle(const KArgs& A, const ChunkCtx& X, long long p, bool inr, float r,
                                               float z, float vr, float vt, float vz, float w,
                                               unsigned long long key, unsigned int& c_push) {
@@ -441,7 +437,7 @@ __device__ __forceinline__ void push_particle(const KArgs& A, const ChunkCtx& X,
     int wall = -1;
     if (rn <= L.a) wall = 0;
     else if (rn >= L.b) wall = 1;
-    else if (L.has_ins && fmaf((rn - L.ins_r0) * L.ins_inv_er, (rn - L.ins_r0) * L.ins_inv_er,
+    else if (INS && L.has_ins && fmaf((rn - L.ins_r0) * L.ins_inv_er, (rn - L.ins_r0) * L.ins_inv_er,
                                ((zn - L.ins_z0) * L.ins_inv_ez) * ((zn - L.ins_z0) * L.ins_inv_ez)) - 1.0f <= 0.0f)
         wall = 1;  // the insert is outer-electrode metal
     else if (zn <= 0.0f) wall = 2;
@@ -469,11 +465,18 @@ __device__ __forceinline__ void push_particle(const KArgs& A, const ChunkCtx& X,
     if (alive) {
         if (fmaf(vz, vz, fmaf(vtn, vtn, vrn * vrn)) > L.v_cap2) atomicAdd(&X.s_ctr[SC_CAP], 1ull);
         if (L.collisions && x52 < L.null_k) {
-            // rare: the candidate is resolved by k_collide after this kernel
-            atomicAdd(&X.s_ctr[SC_CAND], 1ull);
-            const long long qi = (long long)atomicAdd((unsigned long long*)&A.ctl[CTL_QCOUNT], 1ull);
-            if (qi < A.qcap) A.queue[qi] = ((unsigned long long)X.inst << 40) | (unsigned long long)dst;
-            else A.ctl[CTL_QOVER] = 1;
+            // a null-collision candidate, resolved by k_collide after this
+            // kernel: into the workgroup's LDS queue (flushed to the device
+            // queue once per chunk), beyond its size straight to the device
+            const unsigned int qr = atomicAdd(X.s_qn, 1u);
+            const unsigned long long e = ((unsigned long long)X.inst << 40) | (unsigned long long)dst;
+            if (qr < (unsigned int)kLQ) {
+                X.s_q[qr] = e;
+            } else {
+                const long long qi = (long long)atomicAdd((unsigned long long*)&A.ctl[CTL_QCOUNT], 1ull);
+                if (qi < A.qcap) A.queue[qi] = e;
+                else A.ctl[CTL_QOVER] = 1;
+            }
         }
         out.r[dst] = rn;
         out.z[dst] = zn;
@@ -504,7 +507,7 @@ __device__ __forceinline__ void push_particle(const KArgs& A, const ChunkCtx& X,
             gbl_add(&Qg[n00 + 1], (unsigned long long)q01);
             gbl_add(&Qg[n00 + L.W + 1], (unsigned long long)q11);
         }
-        if (L.has_ins) deposit_qw(A.It[X.inst], X.Qw, w, rn, zn);
+        if (INS && L.has_ins) deposit_qw(A.It[X.inst], X.Qw, w, rn, zn);
     }
     if (COUNT) {
         // survivors, by the tile of the new position: tiles next to the
@@ -552,10 +555,13 @@ __device__ __forceinline__ int wave_search(const long long* a, int n, long long 
 // each, particles outside the 3x3 neighbourhood and tail particles take
 // single ranks.  The updated particle (or a dead marker if it was absorbed)
 // is written there instead of in place.
+// MODE bit 0: counting step, bit 1: sorting step, bit 2: a context with the
+// elliptic insert (absorption on it and the band charges compiled in).
 template <int MODE>
 __global__ void __launch_bounds__(kPWG) __attribute__((amdgpu_waves_per_eu(8, 8))) k_particles(KArgs A) {
     constexpr bool COUNT = (MODE & 1) != 0;
     constexpr bool SCATTER = (MODE & 2) != 0;
+    constexpr bool INS = (MODE & 4) != 0;
     extern __shared__ __align__(16) unsigned char smem[];
     lds_float4* sEB = (lds_float4*)(v4f*)smem;
     lds_u64* sQ = (lds_u64*)(unsigned long long*)(smem + sizeof(float4) * (size_t)A.win_max);
@@ -563,6 +569,9 @@ __global__ void __launch_bounds__(kPWG) __attribute__((amdgpu_waves_per_eu(8, 8)
     __shared__ int s_count, s_inst, s_tr0, s_tz0;
     __shared__ unsigned int s_bcnt[9], s_bbase[9], s_ccnt[9];
     __shared__ unsigned long long s_ctr[SC_N];
+    __shared__ unsigned long long s_q[kLQ];
+    __shared__ unsigned int s_qn;
+    __shared__ long long s_qbase;
     const int tid = threadIdx.x;
     // Static balance: workgroup w pushes the w-th of gridDim.x equal ranges of
     // the step's particles (tile-sorted ones first, then the tails), walking
@@ -602,6 +611,7 @@ __global__ void __launch_bounds__(kPWG) __attribute__((amdgpu_waves_per_eu(8, 8)
         if (SCATTER && tid < 9) s_bcnt[tid] = 0u;
         if (COUNT && tid < 9) s_ccnt[tid] = 0u;
         if (tid < SC_N) s_ctr[tid] = 0ull;
+        if (tid == SC_N) s_qn = 0u;
         __syncthreads();
         const int count = __builtin_amdgcn_readfirstlane(s_count);
         v += count;
@@ -667,6 +677,7 @@ __global__ void __launch_bounds__(kPWG) __attribute__((amdgpu_waves_per_eu(8, 8)
         ChunkCtx X;
         X.L = local_inst(I);
         X.sEB = sEB; X.sQ = sQ; X.s_ctr = s_ctr; X.s_bcnt = s_bcnt; X.s_bbase = s_bbase; X.s_ccnt = s_ccnt;
+        X.s_qn = &s_qn; X.s_q = s_q;
         X.out = out; X.EB = F.EB; X.Q = F.Q; X.Qw = F.Qw;
         X.inst = inst; X.ti_c = ti_c; X.tj_c = tj_c; X.i0 = i0; X.i1 = i1; X.j0 = j0; X.j1 = j1; X.ww = ww;
         X.win = win; X.step = step;
@@ -697,7 +708,7 @@ __global__ void __launch_bounds__(kPWG) __attribute__((amdgpu_waves_per_eu(8, 8)
             }
 #pragma unroll
             for (int u = 0; u < U; ++u)
-                push_particle<COUNT, SCATTER>(A, X, pp[u], inr[u], r[u], z[u], vr[u], vt[u], vz[u], w[u], key[u],
+                push_particle<COUNT, SCATTER, INS>(A, X, pp[u], inr[u], r[u], z[u], vr[u], vt[u], vz[u], w[u], key[u],
                                               c_push);
         }
         flush_counter(&cnt[C_PSTEPS], (unsigned long long)c_push);
@@ -706,11 +717,24 @@ __global__ void __launch_bounds__(kPWG) __attribute__((amdgpu_waves_per_eu(8, 8)
             const unsigned long long v = s_ctr[tid];
             if (v) atomicAdd((unsigned long long*)&cnt[kCounterOf[tid]], v);
         }
+        // the chunk's queued candidates: one device reservation
+        const unsigned int q_all = s_qn;
+        const unsigned int q_lds = min(q_all, (unsigned int)kLQ);
+        if (tid == SC_N) {
+            if (q_all) atomicAdd((unsigned long long*)&cnt[C_CAND], (unsigned long long)q_all);
+            s_qbase = q_lds ? (long long)atomicAdd((unsigned long long*)&A.ctl[CTL_QCOUNT], (unsigned long long)q_lds)
+                            : 0ll;
+        }
         if (COUNT && win && tid < 9) {
             const unsigned int v = s_ccnt[tid];
             if (v) atomicAdd(&A.cnt_out[I.tile_off + (ti_c + tid / 3 - 1) * I.ntz + (tj_c + tid % 3 - 1)], v);
         }
         __syncthreads();
+        for (unsigned int t = tid; t < q_lds; t += kPWG) {
+            const long long qi = s_qbase + t;
+            if (qi < A.qcap) A.queue[qi] = s_q[t];
+            else A.ctl[CTL_QOVER] = 1;
+        }
         if (win) {
             const int nwin = (i1 - i0 + 1) * ww;
             gbl_u64* Qg = as_gbl(F.Q);
@@ -731,25 +755,55 @@ __global__ void __launch_bounds__(kPWG) __attribute__((amdgpu_waves_per_eu(8, 8)
 // position and counted for the next sort.
 __global__ void __launch_bounds__(kWG) k_collide(KArgs A, PSet P, int scatter) {
     const long long nq = min(A.ctl[CTL_QCOUNT], A.qcap);
-    for (long long qi = (long long)blockIdx.x * kWG + threadIdx.x; qi < nq; qi += (long long)gridDim.x * kWG) {
-        const unsigned long long e = A.queue[qi];
-        const int inst = (int)(e >> 40);
-        const long long p = (long long)(e & ((1ull << 40) - 1ull));
+    // the loop is uniform per workgroup so that each wave's event counts and
+    // new-electron slots take one atomic per instance present in the wave
+    for (long long b0q = (long long)blockIdx.x * kWG; b0q < nq; b0q += (long long)gridDim.x * kWG) {
+        const long long qi = b0q + threadIdx.x;
+        int inst = 0, ev = 0;
+        long long p = 0;
+        float r = 0.0f, z = 0.0f, w = 0.0f, cvr = 0.0f, cvt = 0.0f, cvz = 0.0f;
+        unsigned long long ckey = 0ull;
+        if (qi < nq) {
+            const unsigned long long e = A.queue[qi];
+            inst = (int)(e >> 40);
+            p = (long long)(e & ((1ull << 40) - 1ull));
+            const DevInst& I = A.It[inst];
+            const unsigned int step = (unsigned int)A.cnt[(long long)inst * C_NCOUNT + C_STEP];
+            const unsigned long long key = P.key[p];
+            const uint4 b0 = philox_step(I, key, step, 0u);
+            float vr = P.vr[p], vt = P.vt[p], vz = P.vz[p];
+            r = P.r[p];
+            z = P.z[p];
+            w = weight_at(I, P, p);
+            ev = collide_f(I, key, step, b0, vr, vt, vz, cvr, cvt, cvz, ckey);
+            if (ev != 0) {
+                P.vr[p] = vr;
+                P.vt[p] = vt;
+                P.vz[p] = vz;
+            }
+        }
+        wave_aggregate<false>(ev == 1, inst, [&](int k, unsigned int n) {
+            atomicAdd((unsigned long long*)&A.cnt[(long long)k * C_NCOUNT + C_ELASTIC], (unsigned long long)n);
+            return 0u;
+        });
+        const unsigned int rank = wave_aggregate<true>(ev == 2, inst, [&](int k, unsigned int n) {
+            long long* c = A.cnt + (long long)k * C_NCOUNT;
+            atomicAdd((unsigned long long*)&c[C_IONIZ], (unsigned long long)n);
+            return (unsigned int)atomicAdd((unsigned long long*)&c[C_SPAWN], (unsigned long long)n);
+        });
+        if (ev != 2) continue;
         const DevInst& I = A.It[inst];
         long long* cnt = A.cnt + (long long)inst * C_NCOUNT;
-        const unsigned int step = (unsigned int)cnt[C_STEP];
-        const unsigned long long key = P.key[p];
-        const uint4 b0 = philox_step(I, key, step, 0u);
-        float vr = P.vr[p], vt = P.vt[p], vz = P.vz[p];
-        const float r = P.r[p], z = P.z[p], w = weight_at(I, P, p);
-        const long long base = scatter ? A.new_base[inst] : cnt[C_SLOTS];
-        const int ev = collide_f(I, cnt, P, key, step, b0, r, z, w, vr, vt, vz, base);
-        if (ev == 0) continue;
-        P.vr[p] = vr;
-        P.vt[p] = vt;
-        P.vz[p] = vz;
-        atomicAdd((unsigned long long*)&cnt[ev == 1 ? C_ELASTIC : C_IONIZ], 1ull);
-        if (ev != 2) continue;
+        const long long rel = (scatter ? A.new_base[inst] : cnt[C_SLOTS]) + (long long)rank;
+        if (rel >= I.p_cap) {
+            atomicAdd((unsigned long long*)&cnt[C_DROPPED], 1ull);
+            continue;
+        }
+        const long long d = I.p_off + rel;
+        P.r[d] = r; P.z[d] = z;
+        P.vr[d] = cvr; P.vt[d] = cvt; P.vz[d] = cvz;
+        P.w[d] = w;
+        P.key[d] = ckey;
         int i, j;
         float fr, fz;
         cell_of(I, r, z, i, j, fr, fz);
@@ -1042,6 +1096,20 @@ __global__ void k_deposit32(DevInst I, PSet P, long long* Q, long long* Qw, cons
     }
 }
 
+typedef void (*ParticleKernel)(KArgs);
+ParticleKernel particle_kernel(int v) {
+    switch (v) {
+        case 0: return k_particles<0>;
+        case 1: return k_particles<1>;
+        case 2: return k_particles<2>;
+        case 3: return k_particles<3>;
+        case 4: return k_particles<4>;
+        case 5: return k_particles<5>;
+        case 6: return k_particles<6>;
+        default: return k_particles<7>;
+    }
+}
+
 unsigned int grid_for(long long n, long long cap = 16384) {
     long long g = (n + kWG - 1) / kWG;
     return (unsigned int)std::max(1ll, std::min(g, cap));
@@ -1055,6 +1123,8 @@ unsigned int grid_for(long long n, long long cap = 16384) {
 
 struct F32State {
     int TR = 8, TZ = 32, halo = 8, K = 16, C = 1 << 22, win_max = 0;
+    bool ins = false;  // some instance has the elliptic insert
+    int coll_grid = 64;   // workgroups of k_collide
     int cu = 256, wg_per_cu = 4;
     PSet set[2];
     int cur = 0;
@@ -1197,17 +1267,15 @@ static pic_status build_tiles(pic_ctx* ctx, F32State* S) {
     CK32(hipMemcpyAsync(S->tile_info, tinfo.data(), sizeof(int4) * toff, hipMemcpyHostToDevice, s));
     CK32(hipStreamSynchronize(s));
     size_t lds = (size_t)S->win_max * (sizeof(float4) + sizeof(unsigned long long));
-    CK32(hipFuncSetAttribute((const void*)k_particles<0>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    CK32(hipFuncSetAttribute((const void*)k_particles<1>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    CK32(hipFuncSetAttribute((const void*)k_particles<2>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    CK32(hipFuncSetAttribute((const void*)k_particles<3>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     // every workgroup of the statically balanced grid must be resident at once
-    int occ[4] = {0, 0, 0, 0};
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ[0], k_particles<0>, kPWG, lds);
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ[1], k_particles<1>, kPWG, lds);
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ[2], k_particles<2>, kPWG, lds);
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ[3], k_particles<3>, kPWG, lds);
-    const int omin = std::min(std::min(occ[0], occ[1]), std::min(occ[2], occ[3]));
+    int omin = 1 << 30;
+    for (int v = 0; v < 8; ++v) {
+        const void* f = (const void*)particle_kernel(v);
+        CK32(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        int occ = 0;
+        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, f, kPWG, lds);
+        omin = std::min(omin, occ);
+    }
     S->wg_per_cu = omin > 0 ? omin : 1;
     return PIC_OK;
 }
@@ -1240,6 +1308,8 @@ static pic_status build_store(pic_ctx* ctx, F32State* S, const std::vector<long 
     double pmax = 0.0;
     for (int k = 0; k < n; ++k) pmax = std::max(pmax, pic_inst_dev(ctx, k).P_null);
     const long long qcap = std::min<long long>(off, std::max<long long>(1 << 16, (long long)(64.0 * pmax * (double)off)));
+    // collision kernel grid: about four expected candidates per thread
+    S->coll_grid = (int)std::min<double>(4096.0, std::max(64.0, std::ceil(pmax * (double)off / (4.0 * kWG))));
     unsigned long long* nq = (unsigned long long*)pic_dev_alloc(ctx, sizeof(unsigned long long) * qcap);
     if (!set_ok(ns[0]) || !set_ok(ns[1]) || !nkey || !nq) {
         for (int b = 0; b < 2; ++b) free_set(ctx, ns[b]);
@@ -1289,6 +1359,7 @@ pic_status f32_init(pic_ctx* ctx) {
     if (run.halo > 0) S->halo = run.halo;
     if (run.sort_interval > 0) S->K = run.sort_interval;
     if (run.chunk > 0) S->C = run.chunk;
+    for (int k = 0; k < pic_n_inst(ctx); ++k) S->ins = S->ins || pic_inst_dev(ctx, k).has_ins != 0;
     pic_status st = build_tiles(ctx, S);
     if (st != PIC_OK) return st;
     const int n = pic_n_inst(ctx);
@@ -1383,15 +1454,10 @@ static pic_status launch_step(pic_ctx* ctx, F32State* S, hipStream_t s, bool tim
     }
     const size_t lds = (size_t)S->win_max * (sizeof(float4) + sizeof(unsigned long long));
     const dim3 grid(S->cu * S->wg_per_cu);
-    switch (mode) {
-        case 0: hipLaunchKernelGGL(k_particles<0>, grid, dim3(kPWG), lds, s, A); break;
-        case 1: hipLaunchKernelGGL(k_particles<1>, grid, dim3(kPWG), lds, s, A); break;
-        case 2: hipLaunchKernelGGL(k_particles<2>, grid, dim3(kPWG), lds, s, A); break;
-        default: hipLaunchKernelGGL(k_particles<3>, grid, dim3(kPWG), lds, s, A); break;
-    }
+    hipLaunchKernelGGL(particle_kernel((mode & 3) | (S->ins ? 4 : 0)), grid, dim3(kPWG), lds, s, A);
     CK32(hipGetLastError());
     if (timed) CK32(hipEventRecord(e1, s));
-    hipLaunchKernelGGL(k_collide, dim3(64), dim3(kWG), 0, s, A, (mode & 2) ? S->set[1 - S->cur] : S->set[S->cur],
+    hipLaunchKernelGGL(k_collide, dim3(S->coll_grid), dim3(kWG), 0, s, A, (mode & 2) ? S->set[1 - S->cur] : S->set[S->cur],
                        (mode & 2) ? 1 : 0);
     CK32(hipGetLastError());
     double src_max = 0.0;
