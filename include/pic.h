@@ -109,6 +109,15 @@ typedef struct {
     double ins_r0, ins_z0;     /* centre (m)                                     */
     double ins_er, ins_ez;     /* semi-axes in r and z (m), > 0 with an insert   */
     double ins_band;           /* weight band in cells, 0 takes 3; at most 64    */
+    /* Order of the space-charge splines (Sec. II.A: B-spline FEM of any
+     * order): 1 (or 0) bilinear shapes and Q1 FEM; 3 cubic B-spline particle
+     * shapes (16 nodes), cubic FEM for the space-charge potential with the
+     * walls' Dirichlet conditions built in by odd reflection, and the
+     * space-charge field -grad phi_sc evaluated at each particle from the
+     * spline coefficients (the vacuum field stays the order-1 nodal field).
+     * Order 3 needs PIC_MODE_FP64_PLAIN, end_mode 0 or 1, no insert, and the
+     * same order for every instance of the context. */
+    int spline_order;
 } pic_instance_cfg;
 
 typedef struct {
@@ -242,12 +251,32 @@ pic_status pic_get_fields(pic_ctx* ctx, int inst, double* Er, double* Ez, double
  * electrons, FEM-weighted node charge) of instance `inst`. */
 pic_status pic_get_charge(pic_ctx* ctx, int inst, long long* Q);
 
+/* pic_set_cross_sections -- tabulated electron-neutral cross sections for
+ * instance `inst` (Sec. II.A: the MCC module reads the gas's cross sections;
+ * LXCat-style energy / cross-section pairs): n >= 2 strictly increasing
+ * energies E_eV (eV) with the elastic momentum-transfer and ionisation cross
+ * sections (m^2), linear in E between the points, the end values held outside
+ * the table, ionisation zero at or below iz_I_eV.  The null-collision bound
+ * becomes n_n max (sigma_el + sigma_iz)(E) v(E) over 0 <= E <= E_cap_eV
+ * (widened by 2^-20).  n = 0 returns to the constant sigma_el and the Lotz
+ * formula.  The arrays are copied (host pointers); at most 4096 points;
+ * PIC_EINVAL for a bad table.  Call between steps. */
+pic_status pic_set_cross_sections(pic_ctx* ctx, int inst, int n, const double* E_eV, const double* sigma_el,
+                                  const double* sigma_iz);
+
 /* pic_get_band_charge -- with the elliptic insert (Sec. II.A web-splines):
  * copy the fixed-point node charges of q (w(x_p) - 1) that the particles
  * inside the weight function's band deposit next to Q (node array, units
  * 2^-S electrons; all zero without an insert).  The load of the Poisson
  * system is Q + Qw carried through the web-spline extension. */
 pic_status pic_get_band_charge(pic_ctx* ctx, int inst, long long* Qw);
+
+/* pic_get_spline3 -- with cubic shapes: copy the ghosted cubic deposit Qx
+ * (fixed point, node (i, j) for -1 <= i <= nr+1, -1 <= j <= nz+1 at
+ * (i+1)(nz+3) + (j+1)) and the space-charge coefficients cx of the last
+ * solve in the same layout (reflections filled).  Either pointer may be NULL.
+ * PIC_EINVAL when the instance does not use cubic shapes. */
+pic_status pic_get_spline3(pic_ctx* ctx, int inst, long long* Qx, double* cx);
 
 /* pic_insert_layout -- host-only check of an instance's elliptic insert
  * (no device work): node counts by class (counts[0] not an unknown, [1]

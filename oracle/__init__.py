@@ -31,7 +31,7 @@ class OrcCfg(C.Structure):
         ("fx_shift", C.c_int), ("diag_interval", C.c_int), ("collisions", C.c_int),
         ("src_rate", C.c_double), ("src_T_eV", C.c_double),
         ("ins_r0", C.c_double), ("ins_z0", C.c_double), ("ins_er", C.c_double), ("ins_ez", C.c_double),
-        ("ins_band", C.c_double),
+        ("ins_band", C.c_double), ("spline_order", C.c_int),
     ]
 
 
@@ -108,6 +108,22 @@ def lib():
         L.orc_well_depth.argtypes = [C.POINTER(OrcCfg), _D, C.c_int, _D, _D, _D]
         L.orc_num_threads.restype = C.c_int
         L.orc_load.restype = C.c_int
+        L.orc_set_cross_sections.argtypes = [C.c_void_p, C.c_int, _D, _D, _D]
+        L.orc_set_cross_sections.restype = C.c_int
+        L.orc_get_charge3.argtypes = [C.c_void_p, _I64]
+        L.orc_get_coef3.argtypes = [C.c_void_p, _D]
+        L.orc_s3_weights.argtypes = [C.c_double, _D, _D]
+        L.orc_s3_poisson_fn.argtypes = [C.POINTER(OrcCfg), _FN, C.c_void_p, _D]
+        L.orc_s3_poisson_fn.restype = C.c_int
+        L.orc_s3_phi_at.argtypes = [C.POINTER(OrcCfg), _D, C.c_double, C.c_double]
+        L.orc_s3_phi_at.restype = C.c_double
+        L.orc_s3_field.argtypes = [C.POINTER(OrcCfg), _D, C.c_double, C.c_double, _D, _D]
+        L.orc_s3_deposit.argtypes = [C.POINTER(OrcCfg), C.c_double, C.c_double, C.c_int64, _I64]
+        L.orc_sim_derived.argtypes = [C.c_void_p, C.POINTER(OrcDerived)]
+        L.orc_xs_at.argtypes = [C.c_int, _D, _D, C.c_double]
+        L.orc_xs_at.restype = C.c_double
+        L.orc_xs_sigv_max.argtypes = [C.POINTER(OrcCfg), C.c_int, _D, _D, _D]
+        L.orc_xs_sigv_max.restype = C.c_double
         L.orc_ins_g.argtypes = [C.POINTER(OrcCfg), C.c_double, C.c_double]
         L.orc_ins_g.restype = C.c_double
         L.orc_ins_gamma.argtypes = [C.POINTER(OrcCfg)]
@@ -305,6 +321,58 @@ def ins_poisson_fn(d, f):
     return phi.reshape(_shape(d))
 
 
+def xs_at(E, s, x):
+    E = np.ascontiguousarray(E, dtype=np.float64)
+    s = np.ascontiguousarray(s, dtype=np.float64)
+    return lib().orc_xs_at(len(E), _dp(E), _dp(s), float(x))
+
+
+def xs_sigv_max(d, E, el, iz):
+    a = [np.ascontiguousarray(x, dtype=np.float64) for x in (E, el, iz)]
+    return lib().orc_xs_sigv_max(C.byref(make_cfg(d)), len(a[0]), *[_dp(x) for x in a])
+
+
+# ---- cubic B-spline shapes --------------------------------------------------
+
+def _ext(d):
+    return (d["nr"] + 3) * (d["nz"] + 3)
+
+
+def s3_weights(f):
+    w = np.zeros(4); dw = np.zeros(4)
+    lib().orc_s3_weights(float(f), _dp(w), _dp(dw))
+    return w, dw
+
+
+def s3_deposit(d, r, z, Wq):
+    """Ghosted ((nr+3) x (nz+3)) cubic deposit of one particle of Wq units."""
+    Qx = np.zeros(_ext(d), dtype=np.int64)
+    lib().orc_s3_deposit(C.byref(make_cfg(d)), float(r), float(z), int(Wq), Qx.ctypes.data_as(_I64))
+    return Qx.reshape(d["nr"] + 3, d["nz"] + 3)
+
+
+def s3_poisson_fn(d, f):
+    """Ghosted cubic coefficients of the solution of -lap(phi) = f with phi = 0
+    on the four walls (manufactured-solution hook)."""
+    cb = _FN(lambda r, z, u: float(f(r, z)))
+    cx = np.zeros(_ext(d))
+    if lib().orc_s3_poisson_fn(C.byref(make_cfg(d)), cb, None, _dp(cx)) != 0:
+        raise ValueError("cubic configuration refused")
+    return cx
+
+
+def s3_phi_at(d, cx, r, z):
+    cx = np.ascontiguousarray(cx, dtype=np.float64).reshape(-1)
+    return lib().orc_s3_phi_at(C.byref(make_cfg(d)), _dp(cx), float(r), float(z))
+
+
+def s3_field(d, cx, r, z):
+    cx = np.ascontiguousarray(cx, dtype=np.float64).reshape(-1)
+    a = np.zeros(1); b = np.zeros(1)
+    lib().orc_s3_field(C.byref(make_cfg(d)), _dp(cx), float(r), float(z), _dp(a), _dp(b))
+    return float(a[0]), float(b[0])
+
+
 def num_threads():
     return lib().orc_num_threads()
 
@@ -367,6 +435,22 @@ class Sim:
         lib().orc_get_fields(self.h, *[_dp(x) for x in a])
         return {k: v.reshape(self.shape) for k, v in zip(("Er", "Ez", "Br", "Bz"), a)}
 
+    def set_cross_sections(self, E=None, sigma_el=None, sigma_iz=None):
+        """Tabulated cross sections (m^2) at increasing energies (eV); None
+        returns to the constant elastic and Lotz ionisation model."""
+        if E is None:
+            st = lib().orc_set_cross_sections(self.h, 0, None, None, None)
+        else:
+            self._xs = [np.ascontiguousarray(a, dtype=np.float64) for a in (E, sigma_el, sigma_iz)]
+            st = lib().orc_set_cross_sections(self.h, len(self._xs[0]), *[_dp(a) for a in self._xs])
+        if st != 0:
+            raise ValueError("cross-section table refused")
+
+    def derived(self):
+        out = OrcDerived()
+        lib().orc_sim_derived(self.h, C.byref(out))
+        return {n: getattr(out, n) for n, _ in OrcDerived._fields_}
+
     def set_step(self, step):
         lib().orc_set_step(self.h, int(step))
 
@@ -377,6 +461,16 @@ class Sim:
         Q = np.zeros(self.nodes, dtype=np.int64)
         lib().orc_get_charge(self.h, Q.ctypes.data_as(_I64))
         return Q.reshape(self.shape)
+
+    def charge3(self):
+        Q = np.zeros(_ext(self.d), dtype=np.int64)
+        lib().orc_get_charge3(self.h, Q.ctypes.data_as(_I64))
+        return Q.reshape(self.d["nr"] + 3, self.d["nz"] + 3)
+
+    def coef3(self):
+        c = np.zeros(_ext(self.d))
+        lib().orc_get_coef3(self.h, _dp(c))
+        return c.reshape(self.d["nr"] + 3, self.d["nz"] + 3)
 
     def band_charge(self):
         Q = np.zeros(self.nodes, dtype=np.int64)

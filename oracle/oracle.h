@@ -62,6 +62,7 @@ typedef struct {
      * ((r-ins_r0)/ins_er)^2 + ((z-ins_z0)/ins_ez)^2 <= 1; ins_er = 0: none */
     double ins_r0, ins_z0, ins_er, ins_ez;
     double ins_band;           /* weight-function band in cells (0: 3)          */
+    int spline_order;          /* space-charge shapes and FEM: 1 (0) bilinear/Q1, 3 cubic */
 } orc_cfg;
 
 /* Host-derived constants (all FP64). */
@@ -104,6 +105,8 @@ double orc_okh_cos(double xi, double u);
 double orc_opal_split(double Ebar, double E_av, double u);
 void   orc_scatter(double ur, double ut, double uz, double cosx, double phi, double out[3]);
 double orc_sigma_iz(const orc_cfg* c, double E_eV);
+double orc_xs_at(int n, const double* E, const double* s, double x);
+double orc_xs_sigv_max(const orc_cfg* c, int n, const double* E, const double* el, const double* iz);
 
 /* Node arrays are r-major: node (i,j) at i*(nz+1)+j, i in [0,nr], j in [0,nz]. */
 void orc_bfield(const orc_cfg* c, double* Br, double* Bz);
@@ -147,6 +150,18 @@ int      orc_ins_poisson_fn(const orc_cfg* c, double (*f)(double, double, void*)
 int      orc_ins_classify(const orc_cfg* c, int* cls);
 int      orc_ins_info(const orc_cfg* c, int* n_unknowns, int* bandwidth, int counts[4]);
 
+/* ---- cubic B-spline shapes and space charge, orc_spline3.c ---- */
+typedef struct orc_s3 orc_s3;
+void     orc_s3_weights(double f, double w[4], double dw[4]);
+int      orc_s3_ext(const orc_cfg* c);              /* (nr+3)(nz+3): ghosted grid */
+void     orc_s3_deposit(const orc_cfg* c, double r, double z, int64_t Wq, int64_t* Qx);
+orc_s3*  orc_s3_create(const orc_cfg* c);
+void     orc_s3_destroy(orc_s3* S);
+void     orc_s3_solve(const orc_s3* S, const orc_cfg* c, const int64_t* Qx, double* cx, double* phi_sc);
+void     orc_s3_field(const orc_cfg* c, const double* cx, double r, double z, double* Er, double* Ez);
+double   orc_s3_phi_at(const orc_cfg* c, const double* cx, double r, double z);
+int      orc_s3_poisson_fn(const orc_cfg* c, double (*f)(double, double, void*), void* user, double* cx);
+
 /* ---- simulation object ---- */
 orc_sim* orc_create(const orc_cfg* c, int64_t capacity);
 void     orc_destroy(orc_sim* s);
@@ -164,9 +179,19 @@ void     orc_set_fields(orc_sim* s, const double* Er, const double* Ez,
                         const double* Br, const double* Bz, int frozen);
 void     orc_get_fields(const orc_sim* s, double* Er, double* Ez, double* Br, double* Bz);
 void     orc_set_step(orc_sim* s, int64_t step);
+/* Tabulated elastic and ionisation cross sections (m^2) at n >= 2 strictly
+ * increasing energies (eV), linear in E between them; n = 0 returns to the
+ * constant elastic and Lotz ionisation cross sections.  The null-collision
+ * bound becomes n_n max (sigma_el + sigma_iz) v over 0 <= E <= E_cap. */
+int      orc_set_cross_sections(orc_sim* s, int n, const double* E, const double* el, const double* iz);
+void     orc_sim_derived(const orc_sim* s, orc_derived* d);   /* the constants in use */
 int      orc_step(orc_sim* s, int n_steps);
 void     orc_get_charge(const orc_sim* s, int64_t* Q);
 void     orc_get_charge_w(const orc_sim* s, int64_t* Qw);   /* insert: band charges (else 0) */
+/* cubic shapes: the ghosted cubic deposit and the space-charge coefficients
+ * ((nr+3)(nz+3) arrays, ghost layer included; zeros for order 1) */
+void     orc_get_charge3(const orc_sim* s, int64_t* Qx);
+void     orc_get_coef3(const orc_sim* s, double* cx);
 void     orc_get_phi(const orc_sim* s, double* phi);
 void     orc_get_diag(const orc_sim* s, orc_diag* d);
 void     orc_get_time_avg_density(const orc_sim* s, double* n_avg);

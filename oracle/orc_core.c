@@ -132,6 +132,69 @@ void orc_scatter(double ur, double ut, double uz, double cosx, double phi, doubl
     out[2] = cosx * uz + sinx * (cp * e1z + sp * e2z);
 }
 
+/*
+ * Tabulated cross sections (energy / cross-section pairs as in LXCat files):
+ * linear interpolation in E between the tabulated points, the end values held
+ * outside the table.  Ionisation is zero at or below the threshold.
+ */
+double orc_xs_at(int n, const double* E, const double* s, double x) {
+    if (x <= E[0]) return s[0];
+    if (x >= E[n - 1]) return s[n - 1];
+    int lo = 0, hi = n - 1;
+    while (hi - lo > 1) {
+        int mid = (lo + hi) / 2;
+        if (E[mid] <= x) lo = mid;
+        else hi = mid;
+    }
+    return s[lo] + (s[lo + 1] - s[lo]) * ((x - E[lo]) / (E[lo + 1] - E[lo]));
+}
+
+static double xs_total(const orc_cfg* c, int n, const double* E, const double* el, const double* iz, double x,
+                       int above) {
+    double t = orc_xs_at(n, E, el, x);
+    if (x > c->iz_I_eV || (above && x == c->iz_I_eV)) t += orc_xs_at(n, E, iz, x);
+    return t;
+}
+
+/* max over 0 <= E <= E_cap of (sigma_el + sigma_iz)(E) v(E): the pieces
+ * between table points, the threshold and E_cap are linear in E, so
+ * (alpha + beta E) sqrt(E) peaks at an end or at E = -alpha / (3 beta). */
+double orc_xs_sigv_max(const orc_cfg* c, int n, const double* E, const double* el, const double* iz) {
+    const double two_e_over_me = (2.0 * 1.602176634e-19) / 9.1093837015e-31;
+    const double Ecap = c->E_cap_eV;
+    double cut[4096 + 3];
+    int m = 0;
+    cut[m++] = 0.0;
+    for (int k = 0; k < n && m < 4096 + 1; ++k)
+        if (E[k] > 0.0 && E[k] < Ecap) cut[m++] = E[k];
+    if (c->iz_I_eV > 0.0 && c->iz_I_eV < Ecap) cut[m++] = c->iz_I_eV;
+    cut[m++] = Ecap;
+    /* sort the cut points (insertion; the table is already increasing) */
+    for (int i = 1; i < m; ++i)
+        for (int j = i; j > 0 && cut[j - 1] > cut[j]; --j) {
+            double t = cut[j]; cut[j] = cut[j - 1]; cut[j - 1] = t;
+        }
+    double best = 0.0;
+    for (int i = 0; i + 1 < m; ++i) {
+        const double p = cut[i], q = cut[i + 1];
+        if (!(q > p)) continue;
+        const double sp = xs_total(c, n, E, el, iz, p, 1), sq = xs_total(c, n, E, el, iz, q, 0);
+        double f = sp * sqrt(p * two_e_over_me);
+        if (f > best) best = f;
+        f = sq * sqrt(q * two_e_over_me);
+        if (f > best) best = f;
+        const double beta = (sq - sp) / (q - p), alpha = sp - beta * p;
+        if (beta < 0.0 && alpha > 0.0) {
+            const double x = -alpha / (3.0 * beta);
+            if (x > p && x < q) {
+                f = (alpha + beta * x) * sqrt(x * two_e_over_me);
+                if (f > best) best = f;
+            }
+        }
+    }
+    return best;
+}
+
 /* Single-shell Lotz ionisation cross section (m^2) at energy E (eV). */
 double orc_sigma_iz(const orc_cfg* c, double E_eV) {
     if (!(E_eV > c->iz_I_eV)) return 0.0;

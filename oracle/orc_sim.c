@@ -34,6 +34,11 @@ struct orc_sim {
     int nodes;
     int64_t* Q;
     int64_t* Qw;               /* insert: deposit of q (w(x_p) - 1) (else NULL) */
+    int64_t* Qx;               /* cubic shapes: ghosted cubic deposit (else NULL) */
+    double* cx;                /* cubic shapes: ghosted space-charge coefficients */
+    orc_s3* s3;                /* cubic shapes: factorised Galerkin system      */
+    int xs_n;                  /* tabulated cross sections (0: constant / Lotz) */
+    double *xs_E, *xs_el, *xs_iz;
     orc_ins* ins;              /* insert: factorised web-spline system          */
     double *phi_vac, *phi, *Er, *Ez, *Br, *Bz, *V, *avg_acc;
     int frozen;
@@ -126,6 +131,14 @@ static inline int push_one(const orc_sim* s, int64_t p, double* rr, double* zz,
     double r = rr[p], z = zz[p], vr = vrr[p], vt = vtt[p], vz = vzz[p];
     orc_shape sh = shape_at(c, d, r, z);
     double Er = gather(&sh, s->Er, W), Ez = gather(&sh, s->Ez, W);
+    if (s->s3) {
+        /* cubic shapes: the nodal arrays hold the vacuum field; the space
+         * charge's comes from the spline coefficients at the particle */
+        double er, ez;
+        orc_s3_field(c, s->cx, r, z, &er, &ez);
+        Er += er;
+        Ez += ez;
+    }
     double Br = gather(&sh, s->Br, W), Bz = gather(&sh, s->Bz, W);
     const double h = d->h;
     /* half electric kick */
@@ -187,9 +200,14 @@ static inline int mcc_one(const orc_sim* s, int64_t p, orc_part* child) {
     double v2 = (vr * vr + vt * vt) + vz * vz;
     double v = sqrt(v2);
     double E = v2 * d->half_me_over_e;
-    double nu_el = d->nsig_el * v;
-    double sig_iz = 0.0;
-    if (E > c->iz_I_eV) sig_iz = (d->lotz_aq * log(E / c->iz_I_eV)) / (E * c->iz_I_eV);
+    double nu_el, sig_iz = 0.0;
+    if (s->xs_n > 0) {
+        nu_el = (d->n_n * orc_xs_at(s->xs_n, s->xs_E, s->xs_el, E)) * v;
+        if (E > c->iz_I_eV) sig_iz = orc_xs_at(s->xs_n, s->xs_E, s->xs_iz, E);
+    } else {
+        nu_el = d->nsig_el * v;
+        if (E > c->iz_I_eV) sig_iz = (d->lotz_aq * log(E / c->iz_I_eV)) / (E * c->iz_I_eV);
+    }
     double nu_iz = (d->n_n * sig_iz) * v;
     double R = u_proc * d->nu_prime;
     int ev;
@@ -236,12 +254,15 @@ static void deposit_all(orc_sim* s) {
     const int W = s->c.nz + 1;
     const int N = s->nodes;
     const double gam = s->ins ? orc_ins_gamma(&s->c) : 0.0;
+    const int NX = s->Qx ? orc_s3_ext(&s->c) : 0;
     memset(s->Q, 0, sizeof(int64_t) * N);
     if (s->Qw) memset(s->Qw, 0, sizeof(int64_t) * N);
+    if (s->Qx) memset(s->Qx, 0, sizeof(int64_t) * NX);
 #pragma omp parallel
     {
         int64_t* loc = (int64_t*)calloc(N, sizeof(int64_t));
         int64_t* locw = s->Qw ? (int64_t*)calloc(N, sizeof(int64_t)) : NULL;
+        int64_t* locx = s->Qx ? (int64_t*)calloc(NX, sizeof(int64_t)) : NULL;
 #pragma omp for schedule(static)
         for (int64_t p = 0; p < s->n; ++p) {
             orc_shape sh = shape_at(&s->c, &s->d, s->r[p], s->z[p]);
@@ -251,20 +272,30 @@ static void deposit_all(orc_sim* s) {
                 double wp = orc_ins_wp(&s->c, s->r[p], s->z[p]);
                 deposit_shape(&sh, (int64_t)rint((double)Wq * (wp - 1.0)), locw, W);
             }
+            if (locx) orc_s3_deposit(&s->c, s->r[p], s->z[p], Wq, locx);
         }
 #pragma omp critical
         {
             for (int k = 0; k < N; ++k) s->Q[k] += loc[k];
             if (locw)
                 for (int k = 0; k < N; ++k) s->Qw[k] += locw[k];
+            if (locx)
+                for (int k = 0; k < NX; ++k) s->Qx[k] += locx[k];
         }
         free(loc);
         free(locw);
+        free(locx);
     }
 }
 
 static void solve_fields(orc_sim* s) {
     if (s->frozen) return;
+    if (s->s3) {
+        /* cubic shapes: the nodal E stays the vacuum field */
+        orc_s3_solve(s->s3, &s->c, s->Qx, s->cx, s->phi);
+        for (int k = 0; k < s->nodes; ++k) s->phi[k] += s->phi_vac[k];
+        return;
+    }
     if (s->ins) orc_ins_poisson_charge(s->ins, &s->c, s->Q, s->Qw, s->phi);
     else orc_poisson_charge(&s->c, s->Q, s->phi);
     for (int k = 0; k < s->nodes; ++k) s->phi[k] += s->phi_vac[k];
@@ -288,6 +319,22 @@ orc_sim* orc_create(const orc_cfg* c, int64_t capacity) {
     s->Bz = (double*)calloc(s->nodes, sizeof(double));
     s->V = (double*)calloc(s->nodes, sizeof(double));
     s->avg_acc = (double*)calloc(s->nodes, sizeof(double));
+    if (s->c.spline_order == 3) {
+        if (orc_has_insert(&s->c)) {
+            orc_destroy(s);
+            return NULL;
+        }
+        s->s3 = orc_s3_create(&s->c);
+        if (!s->s3) {
+            orc_destroy(s);
+            return NULL;
+        }
+        s->Qx = (int64_t*)calloc((size_t)orc_s3_ext(&s->c), sizeof(int64_t));
+        s->cx = (double*)calloc((size_t)orc_s3_ext(&s->c), sizeof(double));
+    } else if (s->c.spline_order != 0 && s->c.spline_order != 1) {
+        orc_destroy(s);
+        return NULL;
+    }
     if (orc_has_insert(&s->c)) {
         s->ins = orc_ins_create(&s->c);
         if (!s->ins) {
@@ -310,6 +357,9 @@ void orc_destroy(orc_sim* s) {
     free(s->Q); free(s->phi_vac); free(s->phi); free(s->Er); free(s->Ez);
     free(s->Br); free(s->Bz); free(s->V); free(s->avg_acc);
     free(s->Qw);
+    free(s->Qx); free(s->cx);
+    orc_s3_destroy(s->s3);
+    free(s->xs_E); free(s->xs_el); free(s->xs_iz);
     orc_ins_destroy(s->ins);
     free(s);
 }
@@ -391,6 +441,15 @@ void orc_set_fields(orc_sim* s, const double* Er, const double* Ez,
     if (Br) memcpy(s->Br, Br, b);
     if (Bz) memcpy(s->Bz, Bz, b);
     s->frozen = frozen;
+    if (s->s3) {
+        /* cubic shapes: a frozen field is the given nodal one alone; back to
+         * the self-consistent field, the nodal arrays hold the vacuum field */
+        memset(s->cx, 0, sizeof(double) * (size_t)orc_s3_ext(&s->c));
+        if (!frozen) {
+            orc_efield(&s->c, s->phi_vac, s->Er, s->Ez);
+            solve_fields(s);
+        }
+    }
 }
 
 void orc_get_fields(const orc_sim* s, double* Er, double* Ez, double* Br, double* Bz) {
@@ -402,6 +461,31 @@ void orc_get_fields(const orc_sim* s, double* Er, double* Ez, double* Br, double
 }
 
 void orc_set_step(orc_sim* s, int64_t step) { s->step = step; }
+
+void orc_sim_derived(const orc_sim* s, orc_derived* d) { *d = s->d; }
+
+int orc_set_cross_sections(orc_sim* s, int n, const double* E, const double* el, const double* iz) {
+    if (n != 0 && (n < 2 || n > 4096)) return -1;
+    for (int k = 0; k < n; ++k) {
+        if (!(E[k] >= 0.0) || !(el[k] >= 0.0) || !(iz[k] >= 0.0)) return -1;
+        if (k > 0 && !(E[k] > E[k - 1])) return -1;
+    }
+    free(s->xs_E); free(s->xs_el); free(s->xs_iz);
+    s->xs_E = s->xs_el = s->xs_iz = NULL;
+    s->xs_n = n;
+    orc_derive(&s->c, &s->d);
+    if (n == 0) return 0;
+    s->xs_E = (double*)malloc(sizeof(double) * n);
+    s->xs_el = (double*)malloc(sizeof(double) * n);
+    s->xs_iz = (double*)malloc(sizeof(double) * n);
+    memcpy(s->xs_E, E, sizeof(double) * n);
+    memcpy(s->xs_el, el, sizeof(double) * n);
+    memcpy(s->xs_iz, iz, sizeof(double) * n);
+    /* the bound, widened by 2^-20 against rounding */
+    s->d.nu_prime = (s->d.n_n * orc_xs_sigv_max(&s->c, n, E, el, iz)) * (1.0 + 0x1p-20);
+    s->d.P_null = -expm1(-(s->d.nu_prime * s->c.dt));
+    return 0;
+}
 
 static void sample_diag(orc_sim* s) {
     const int D = s->c.diag_interval;
@@ -570,7 +654,13 @@ void orc_moments(const orc_sim* s, double* out) {
         const double vr = s->vr[p], vt = s->vt[p], vz = s->vz[p], w = s->w[p];
         const double v2 = (vr * vr + vt * vt) + vz * vz, v = sqrt(v2);
         const double E = v2 * s->d.half_me_over_e;
-        const double nu = (s->d.nsig_el + s->d.n_n * orc_sigma_iz(&s->c, E)) * v;
+        double nu;
+        if (s->xs_n > 0) {
+            const double siz = E > s->c.iz_I_eV ? orc_xs_at(s->xs_n, s->xs_E, s->xs_iz, E) : 0.0;
+            nu = (s->d.n_n * orc_xs_at(s->xs_n, s->xs_E, s->xs_el, E) + s->d.n_n * siz) * v;
+        } else {
+            nu = (s->d.nsig_el + s->d.n_n * orc_sigma_iz(&s->c, E)) * v;
+        }
         const double q[ORC_NMOM] = {1.0, vr, vt, vz, vr * vr, vr * vt, vr * vz, vt * vt, vt * vz, vz * vz, nu};
         const size_t n00 = (size_t)sh.i * W + sh.j;
         const size_t node[4] = {n00, n00 + W, n00 + 1, n00 + W + 1};
@@ -583,6 +673,14 @@ void orc_moments(const orc_sim* s, double* out) {
 }
 
 void orc_get_charge(const orc_sim* s, int64_t* Q) { memcpy(Q, s->Q, sizeof(int64_t) * s->nodes); }
+void orc_get_charge3(const orc_sim* s, int64_t* Qx) {
+    if (s->Qx) memcpy(Qx, s->Qx, sizeof(int64_t) * (size_t)orc_s3_ext(&s->c));
+    else memset(Qx, 0, sizeof(int64_t) * (size_t)orc_s3_ext(&s->c));
+}
+void orc_get_coef3(const orc_sim* s, double* cx) {
+    if (s->cx) memcpy(cx, s->cx, sizeof(double) * (size_t)orc_s3_ext(&s->c));
+    else memset(cx, 0, sizeof(double) * (size_t)orc_s3_ext(&s->c));
+}
 void orc_get_charge_w(const orc_sim* s, int64_t* Qw) {
     if (s->Qw) memcpy(Qw, s->Qw, sizeof(int64_t) * s->nodes);
     else memset(Qw, 0, sizeof(int64_t) * s->nodes);

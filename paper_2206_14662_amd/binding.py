@@ -51,7 +51,7 @@ class pic_instance_cfg(C.Structure):
         ("fx_shift", C.c_int), ("diag_interval", C.c_int), ("collisions", C.c_int),
         ("src_rate", C.c_double), ("src_T_eV", C.c_double),
         ("ins_r0", C.c_double), ("ins_z0", C.c_double), ("ins_er", C.c_double), ("ins_ez", C.c_double),
-        ("ins_band", C.c_double),
+        ("ins_band", C.c_double), ("spline_order", C.c_int),
     ]
 
 
@@ -90,7 +90,8 @@ EXPORTS = ("pic_init", "pic_step", "pic_diag", "pic_destroy", "pic_last_error", 
            "pic_get_particles", "pic_set_particles", "pic_set_fields", "pic_get_fields",
            "pic_get_charge", "pic_get_phi", "pic_set_step", "pic_derive", "pic_auto_shift",
            "pic_timing", "pic_tuning", "pic_retune", "pic_autotune", "pic_reserve", "pic_capacity",
-           "pic_moments", "pic_well_depth", "pic_get_band_charge", "pic_insert_layout")
+           "pic_moments", "pic_well_depth", "pic_get_band_charge", "pic_insert_layout",
+           "pic_set_cross_sections", "pic_get_spline3")
 
 _lib = None
 _D = C.POINTER(C.c_double)
@@ -142,6 +143,8 @@ def lib():
     L.pic_well_depth.argtypes = [vp, C.c_int, C.c_int, _D, _D, _D]
     L.pic_get_band_charge.argtypes = [vp, C.c_int, _LL]
     L.pic_insert_layout.argtypes = [C.POINTER(pic_instance_cfg), _I, _I, _LL]
+    L.pic_set_cross_sections.argtypes = [vp, C.c_int, C.c_int, _D, _D, _D]
+    L.pic_get_spline3.argtypes = [vp, C.c_int, _LL, _D]
     for name in EXPORTS:
         if name not in ("pic_last_error", "pic_auto_shift"):
             getattr(L, name).restype = C.c_int
@@ -335,6 +338,22 @@ def pic_get_charge(ctx, inst, nodes):
     return Q
 
 
+def pic_set_cross_sections(ctx, inst, E=None, sigma_el=None, sigma_iz=None):
+    if E is None:
+        _check(lib().pic_set_cross_sections(ctx, int(inst), 0, None, None, None), ctx)
+        return
+    a = [np.ascontiguousarray(x, dtype=np.float64) for x in (E, sigma_el, sigma_iz)]
+    _check(lib().pic_set_cross_sections(ctx, int(inst), len(a[0]), *[x.ctypes.data_as(_D) for x in a]), ctx)
+
+
+def pic_get_spline3(ctx, inst, nr, nz):
+    n = (nr + 3) * (nz + 3)
+    Qx = np.zeros(n, dtype=np.int64)
+    cx = np.zeros(n)
+    _check(lib().pic_get_spline3(ctx, int(inst), Qx.ctypes.data_as(_LL), cx.ctypes.data_as(_D)), ctx)
+    return Qx.reshape(nr + 3, nz + 3), cx.reshape(nr + 3, nz + 3)
+
+
 def pic_get_band_charge(ctx, inst, nodes):
     Qw = np.zeros(nodes, dtype=np.int64)
     _check(lib().pic_get_band_charge(ctx, int(inst), Qw.ctypes.data_as(_LL)), ctx)
@@ -455,6 +474,13 @@ class Sim:
 
     def charge(self, k=0):
         return pic_get_charge(self.ctx, k, self.nodes(k)).reshape(self.shapes[k])
+
+    def set_cross_sections(self, k=0, E=None, sigma_el=None, sigma_iz=None):
+        pic_set_cross_sections(self.ctx, k, E, sigma_el, sigma_iz)
+
+    def spline3(self, k=0):
+        d = self.instances[k]
+        return pic_get_spline3(self.ctx, k, d["nr"], d["nz"])
 
     def band_charge(self, k=0):
         return pic_get_band_charge(self.ctx, k, self.nodes(k)).reshape(self.shapes[k])

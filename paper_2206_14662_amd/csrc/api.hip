@@ -38,6 +38,10 @@ struct Inst {
     InsHost ih;
     InsDev idev;              // device pointers of the corrected solve
     long long* Qw = nullptr;
+    // cubic shapes
+    long long* Qx = nullptr;
+    double *cx = nullptr, *cbuf = nullptr, *zeros = nullptr;
+    double *s3_L1 = nullptr, *s3_L2 = nullptr, *s3_L3 = nullptr, *s3_Dinv = nullptr;
 };
 
 struct pic_ctx {
@@ -61,6 +65,10 @@ struct pic_ctx {
     DevInst* dIins = nullptr;     // DevInst of the insert instances, in ins_list order
     FieldDev *dF1 = nullptr, *dF1v = nullptr;   // first solve (step / vacuum): phi -> ybuf
     FieldDev *dF2 = nullptr, *dF2v = nullptr;   // second solve, insert instances only
+    // cubic shapes (every instance of the context)
+    bool s3 = false;
+    long long max_ext = 0;
+    FieldDev* dF3 = nullptr;                    // coefficient solve: rhs, phi -> cbuf, phi_vac -> zeros
     long long* dcnt = nullptr;
     long long* prep_ctl = nullptr;  // FP32 step plan the end-of-step kernel refreshes
     long long* dtmp = nullptr;
@@ -199,6 +207,9 @@ static std::string validate(const pic_instance_cfg& c) {
     if (c.load_mode != 0 && c.load_mode != 1) return "load_mode must be 0 or 1";
     if (c.end_mode < 0 || c.end_mode > 2) return "end_mode must be 0, 1 or 2";
     if (c.diag_interval < 0) return "diag_interval must be >= 0";
+    if (c.spline_order != 0 && c.spline_order != 1 && c.spline_order != 3) return "spline_order must be 1 or 3";
+    if (c.spline_order == 3 && c.end_mode == 2) return "cubic shapes need end_mode 0 or 1";
+    if (c.spline_order == 3 && (c.ins_er != 0.0 || c.ins_ez != 0.0)) return "cubic shapes do not take the insert";
     if (c.ins_er != 0.0 || c.ins_ez != 0.0) {
         if (!(c.ins_er > 0.0 && c.ins_ez > 0.0 && std::isfinite(c.ins_r0) && std::isfinite(c.ins_z0)))
             return "insert: need ins_er > 0, ins_ez > 0 and a finite centre";
@@ -352,6 +363,80 @@ static void host_thomas(const pic_instance_cfg& c, int nseg, std::vector<double>
         }
 }
 
+// Cubic shapes: per sine mode k the 7-band r system (mu_k Kr + kappa_k Mr),
+// Kr = int r psi_i' psi_i'' dr, Mr = int r psi_i psi_i' dr over the
+// odd-reflected cubic B-splines of the unknowns 1 .. nr-1 (4-point Gauss per
+// cell, exact), mu_k and kappa_k the sine-transform eigenvalues of the
+// reflected cubic mass and stiffness in z (autocorrelations of the cubic
+// B-spline and of its derivative); factored as L D L^T, stored [i][k].
+static void host_spline3(const pic_instance_cfg& c, std::vector<double>& L1, std::vector<double>& L2,
+                         std::vector<double>& L3, std::vector<double>& Dinv) {
+    const int nr = c.nr, nz = c.nz, W = nz + 1, m = nr - 1;
+    const double dr = (c.b - c.a) / (double)nr, dz = c.L / (double)nz;
+    const size_t N = (size_t)(nr + 1) * W;
+    L1.assign(N, 0.0); L2.assign(N, 0.0); L3.assign(N, 0.0); Dinv.assign(N, 0.0);
+    const double gx[4] = {-0.86113631159405257522, -0.33998104358485626480, 0.33998104358485626480,
+                          0.86113631159405257522};
+    const double gw[4] = {0.34785484513745385737, 0.65214515486254614263, 0.65214515486254614263,
+                          0.34785484513745385737};
+    // band storage [i][d] for (i, i - d), i = 1 .. m
+    std::vector<double> K((size_t)(m + 1) * 4, 0.0), M((size_t)(m + 1) * 4, 0.0);
+    auto fold = [&](int i, int& u) {
+        if (i >= 1 && i <= nr - 1) { u = i; return 1; }
+        if (i == -1) { u = 1; return -1; }
+        if (i == nr + 1) { u = nr - 1; return -1; }
+        return 0;
+    };
+    for (int cell = 0; cell < nr; ++cell)
+        for (int q = 0; q < 4; ++q) {
+            const double f = 0.5 * (1.0 + gx[q]);
+            const double r = c.a + ((double)cell + f) * dr, wt = 0.5 * dr * gw[q] * r;
+            double w[4], dw[4];
+            bspline3(f, w, dw);
+            for (int p1 = 0; p1 < 4; ++p1)
+                for (int p2 = 0; p2 < 4; ++p2) {
+                    int u1, u2;
+                    const int s1 = fold(cell - 1 + p1, u1), s2 = fold(cell - 1 + p2, u2);
+                    if (!s1 || !s2 || u2 > u1) continue;
+                    const double sg = (double)(s1 * s2);
+                    K[(size_t)u1 * 4 + (u1 - u2)] += sg * ((dw[p1] / dr) * (dw[p2] / dr)) * wt;
+                    M[(size_t)u1 * 4 + (u1 - u2)] += sg * (w[p1] * w[p2]) * wt;
+                }
+        }
+    const double mm[4] = {151.0 / 315.0, 397.0 / 1680.0, 1.0 / 42.0, 1.0 / 5040.0};
+    const double kk[4] = {2.0 / 3.0, -1.0 / 8.0, -1.0 / 5.0, -1.0 / 120.0};
+    std::vector<double> A((size_t)(m + 1) * 4), Lr((size_t)(m + 1) * 4, 0.0), D(m + 1, 0.0);
+    for (int k = 1; k <= nz - 1; ++k) {
+        const double th = kPi * (double)k / (double)nz;
+        double mu = mm[0], ka = kk[0];
+        for (int l = 1; l <= 3; ++l) {
+            mu += 2.0 * mm[l] * cos((double)l * th);
+            ka += 2.0 * kk[l] * cos((double)l * th);
+        }
+        mu *= dz;
+        ka /= dz;
+        for (size_t t = 0; t < A.size(); ++t) A[t] = mu * K[t] + ka * M[t];
+        for (int i = 1; i <= m; ++i) {
+            for (int d = 3; d >= 1; --d) {
+                const int j = i - d;
+                if (j < 1) continue;
+                double v = A[(size_t)i * 4 + d];
+                for (int t = std::max(1, i - 3); t < j; ++t)
+                    v -= Lr[(size_t)i * 4 + (i - t)] * Lr[(size_t)j * 4 + (j - t)] * D[t];
+                Lr[(size_t)i * 4 + d] = v / D[j];
+            }
+            double dd = A[(size_t)i * 4];
+            for (int t = std::max(1, i - 3); t < i; ++t) dd -= Lr[(size_t)i * 4 + (i - t)] * Lr[(size_t)i * 4 + (i - t)] * D[t];
+            D[i] = dd;
+            const size_t n = (size_t)i * W + k;
+            L1[n] = Lr[(size_t)i * 4 + 1];
+            L2[n] = Lr[(size_t)i * 4 + 2];
+            L3[n] = Lr[(size_t)i * 4 + 3];
+            Dinv[n] = 1.0 / dd;
+        }
+    }
+}
+
 static void host_volume(const pic_instance_cfg& c, std::vector<double>& V) {
     const int nr = c.nr, nz = c.nz, W = nz + 1;
     const double dr = (c.b - c.a) / (double)nr, dz = c.L / (double)nz;
@@ -398,6 +483,7 @@ static void fill_devinst(Inst& in) {
     I.weight = c.weight;
     I.w_uni = (float)c.weight;
     I.has_ins = (c.ins_er > 0.0 && c.ins_ez > 0.0) ? 1 : 0;
+    I.spline3 = c.spline_order == 3 ? 1 : 0;
     if (I.has_ins) {
         const double band = c.ins_band > 0.0 ? c.ins_band : 3.0;
         I.ins_r0 = c.ins_r0; I.ins_z0 = c.ins_z0; I.ins_er = c.ins_er; I.ins_ez = c.ins_ez;
@@ -418,7 +504,7 @@ static pic_status upload_insert_inst(pic_ctx* ctx) {
 
 static pic_status upload_tables(pic_ctx* ctx) {
     std::vector<DevInst> I;
-    std::vector<FieldDev> F, Fv, F1, F1v, F2, F2v;
+    std::vector<FieldDev> F, Fv, F1, F1v, F2, F2v, F3;
     std::vector<InsDev> D;
     std::vector<double> bs;
     for (auto& in : ctx->in) {
@@ -432,6 +518,8 @@ static pic_status upload_tables(pic_ctx* ctx) {
         f.Er = in.Er; f.Ez = in.Ez; f.Br = in.Br; f.Bz = in.Bz; f.EB = in.EB;
         f.V = in.V; f.avg_acc = in.avg_acc;
         f.Qw = in.Qw;
+        f.Qx = in.Qx;
+        f.cx = in.cx;
         F.push_back(f);
         FieldDev v = f;  // vacuum solve: boundary data in, phi_vac out
         v.phi_vac = in.phiB;
@@ -454,12 +542,20 @@ static pic_status upload_tables(pic_ctx* ctx) {
         F1.push_back(f1);
         F1v.push_back(f1v);
         bs.push_back(in.d.bscale);
+        if (ctx->s3) {
+            FieldDev f3 = f;
+            f3.phi = in.cbuf;
+            f3.phi_vac = in.zeros;
+            f3.s3_L1 = in.s3_L1; f3.s3_L2 = in.s3_L2; f3.s3_L3 = in.s3_L3; f3.s3_Dinv = in.s3_Dinv;
+            F3.push_back(f3);
+        }
     }
     hipStream_t s = ctx->stream;
     CK(hipMemcpyAsync(ctx->dI, I.data(), sizeof(DevInst) * I.size(), hipMemcpyHostToDevice, s));
     CK(hipMemcpyAsync(ctx->dF, F.data(), sizeof(FieldDev) * F.size(), hipMemcpyHostToDevice, s));
     CK(hipMemcpyAsync(ctx->dFvac, Fv.data(), sizeof(FieldDev) * Fv.size(), hipMemcpyHostToDevice, s));
     CK(hipMemcpyAsync(ctx->dbscale, bs.data(), sizeof(double) * bs.size(), hipMemcpyHostToDevice, s));
+    if (ctx->s3) CK(hipMemcpyAsync(ctx->dF3, F3.data(), sizeof(FieldDev) * F3.size(), hipMemcpyHostToDevice, s));
     if (!ctx->ins_list.empty()) {
         CK(hipMemcpyAsync(ctx->dF1, F1.data(), sizeof(FieldDev) * F1.size(), hipMemcpyHostToDevice, s));
         CK(hipMemcpyAsync(ctx->dF1v, F1v.data(), sizeof(FieldDev) * F1v.size(), hipMemcpyHostToDevice, s));
@@ -501,6 +597,11 @@ static pic_status solve_tables(pic_ctx* ctx, bool vac, bool from_q, bool edges, 
 pic_status pic_solve_all(pic_ctx* ctx) {
     int n = (int)ctx->in.size();
     hipStream_t s = ctx->stream;
+    if (ctx->s3) {  // the nodal E arrays keep the vacuum field
+        CK(launch_solve3_tab(ctx->dI, ctx->dF, ctx->dF3, n, ctx->max_nr, ctx->max_nz, ctx->max_ext, ctx->tw,
+                             ctx->tw_n, ctx->dbscale, s));
+        return PIC_OK;
+    }
     pic_status st = solve_tables(ctx, false, true, true, s);
     if (st != PIC_OK) return st;
     CK(launch_efield_tab(ctx->dI, ctx->dF, 0, n, ctx->max_nodes, true, s));
@@ -511,6 +612,12 @@ pic_status pic_field_stage(pic_ctx* ctx, hipStream_t s) {
     int n = (int)ctx->in.size();
     // per step: the electrode rows of phi and the static B half of EB keep
     // the values the initial solve (or pic_set_fields) gave them
+    if (ctx->s3) {
+        CK(launch_solve3_tab(ctx->dI, ctx->dF, ctx->dF3, n, ctx->max_nr, ctx->max_nz, ctx->max_ext, ctx->tw,
+                             ctx->tw_n, ctx->dbscale, s));
+        CK(launch_sample_tab(ctx->dI, ctx->dF, n, ctx->dcnt, ctx->prep_ctl, s));
+        return PIC_OK;
+    }
     pic_status st = solve_tables(ctx, false, true, false, s);
     if (st != PIC_OK) return st;
     CK(launch_efield_tab(ctx->dI, ctx->dF, 0, n, ctx->max_nodes, false, s));
@@ -776,6 +883,30 @@ static pic_status init_instance_storage(pic_ctx* ctx, Inst& in) {
     CK(hipMemcpyAsync(in.th_G, gg.data(), sizeof(double) * N, hipMemcpyHostToDevice, s));
     CK(hipMemcpyAsync(in.th_H, hh.data(), sizeof(double) * N, hipMemcpyHostToDevice, s));
     CK(hipStreamSynchronize(s));
+    if (in.I.spline3) {
+        const long long X = (long long)(in.c.nr + 3) * (in.c.nz + 3);
+        in.Qx = dalloc<long long>(ctx, X);
+        in.cx = dalloc<double>(ctx, X);
+        in.cbuf = dalloc<double>(ctx, N);
+        in.zeros = dalloc<double>(ctx, N);
+        in.s3_L1 = dalloc<double>(ctx, N);
+        in.s3_L2 = dalloc<double>(ctx, N);
+        in.s3_L3 = dalloc<double>(ctx, N);
+        in.s3_Dinv = dalloc<double>(ctx, N);
+        if (!in.Qx || !in.cx || !in.cbuf || !in.zeros || !in.s3_L1 || !in.s3_L2 || !in.s3_L3 || !in.s3_Dinv)
+            return fail(ctx, PIC_ENOMEM, "device allocation of the cubic-shape arrays failed");
+        std::vector<double> l1, l2, l3, di;
+        host_spline3(in.c, l1, l2, l3, di);
+        CK(hipMemcpyAsync(in.s3_L1, l1.data(), sizeof(double) * N, hipMemcpyHostToDevice, s));
+        CK(hipMemcpyAsync(in.s3_L2, l2.data(), sizeof(double) * N, hipMemcpyHostToDevice, s));
+        CK(hipMemcpyAsync(in.s3_L3, l3.data(), sizeof(double) * N, hipMemcpyHostToDevice, s));
+        CK(hipMemcpyAsync(in.s3_Dinv, di.data(), sizeof(double) * N, hipMemcpyHostToDevice, s));
+        CK(hipMemsetAsync(in.Qx, 0, sizeof(long long) * X, s));
+        CK(hipMemsetAsync(in.cx, 0, sizeof(double) * X, s));
+        CK(hipMemsetAsync(in.cbuf, 0, sizeof(double) * N, s));
+        CK(hipMemsetAsync(in.zeros, 0, sizeof(double) * N, s));
+        CK(hipStreamSynchronize(s));
+    }
     if (in.has_ins) {
         std::string m = ins_build(in.c, in.ih);
         if (!m.empty()) return fail(ctx, PIC_EINVAL, "insert: " + m);
@@ -866,6 +997,14 @@ extern "C" pic_status pic_init(const pic_run_cfg* run, const pic_instance_cfg* i
         ctx->max_nodes = std::max(ctx->max_nodes, in.nodes);
     }
     int n = run->n_instances;
+    ctx->s3 = n > 0 && ctx->in[0].I.spline3 != 0;
+    for (int k = 0; k < n && st == PIC_OK; ++k) {
+        if ((ctx->in[k].I.spline3 != 0) != ctx->s3)
+            st = fail(ctx, PIC_EINVAL, "every instance of a context needs the same spline_order");
+        ctx->max_ext = std::max<long long>(ctx->max_ext, (long long)(ctx->in[k].c.nr + 3) * (ctx->in[k].c.nz + 3));
+    }
+    if (st == PIC_OK && ctx->s3 && ctx->mode != PIC_MODE_FP64_PLAIN)
+        st = fail(ctx, PIC_EINVAL, "cubic shapes (spline_order 3) run in PIC_MODE_FP64_PLAIN");
     if (st == PIC_OK) {
         ctx->dI = dalloc<DevInst>(ctx, n);
         ctx->dF = dalloc<FieldDev>(ctx, n);
@@ -887,6 +1026,10 @@ extern "C" pic_status pic_init(const pic_run_cfg* run, const pic_instance_cfg* i
             ctx->dF2v = dalloc<FieldDev>(ctx, ni);
             if (!ctx->dIns || !ctx->dIins || !ctx->dF1 || !ctx->dF1v || !ctx->dF2 || !ctx->dF2v)
                 st = fail(ctx, PIC_ENOMEM, "device allocation of insert tables failed");
+        }
+        if (st == PIC_OK && ctx->s3) {
+            ctx->dF3 = dalloc<FieldDev>(ctx, n);
+            if (!ctx->dF3) st = fail(ctx, PIC_ENOMEM, "device allocation of the cubic table failed");
         }
     }
     if (st == PIC_OK) {
@@ -914,6 +1057,11 @@ extern "C" pic_status pic_init(const pic_run_cfg* run, const pic_instance_cfg* i
     for (size_t t = 0; t < ctx->ins_list.size() && st == PIC_OK; ++t) st = setup_insert(ctx, ctx->in[ctx->ins_list[t]]);
     // vacuum potential
     if (st == PIC_OK) st = solve_tables(ctx, true, false, true, ctx->stream);
+    if (st == PIC_OK && ctx->s3) {
+        // cubic shapes: the nodal E arrays hold the vacuum field for good
+        e = launch_efield_tab(ctx->dI, ctx->dFvac, 0, n, ctx->max_nodes, true, ctx->stream);
+        if (e != hipSuccess) st = fail(ctx, PIC_EDEVICE, "vacuum field");
+    }
     if (st == PIC_OK) {
         e = hipStreamSynchronize(ctx->stream);
         if (e != hipSuccess) st = fail(ctx, PIC_EDEVICE, std::string("vacuum solve: ") + hipGetErrorString(e));
@@ -964,8 +1112,9 @@ static pic_status deposit_and_solve(pic_ctx* ctx, int k_only) {
         Inst& in = ctx->in[k];
         CK(launch_zero_i64(in.Q, in.nodes, s));
         if (in.Qw) CK(launch_zero_i64(in.Qw, in.nodes, s));
+        if (in.Qx) CK(launch_zero_i64(in.Qx, (long long)(in.c.nr + 3) * (in.c.nz + 3), s));
         if (ctx->mode == PIC_MODE_FP64_PLAIN) {
-            CK(launch_deposit64(in.I, in.p64[in.cur], in.Q, in.Qw, in.cnt, in.cap, s));
+            CK(launch_deposit64(in.I, in.p64[in.cur], in.Q, in.Qw, in.Qx, in.cnt, in.cap, s));
         } else {
             pic_status st = f32_deposit_only(ctx, k);
             if (st != PIC_OK) return st;
@@ -1088,16 +1237,17 @@ static pic_status step64(pic_ctx* ctx, int n_steps) {
                 P64 p = in.p64[in.cur];
                 CK(launch_zero_i64(in.Q, in.nodes, s));
                 if (in.Qw) CK(launch_zero_i64(in.Qw, in.nodes, s));
+                if (in.Qx) CK(launch_zero_i64(in.Qx, (long long)(in.c.nr + 3) * (in.c.nz + 3), s));
                 hipEvent_t e0 = nullptr, e1 = nullptr;
                 if (ctx->timing) {
                     e0 = pic_timing_begin(ctx, &e1);
                     CK(hipEventRecord(e0, s));
                 }
-                CK(launch_push64(in.I, p, in.Er, in.Ez, in.Br, in.Bz, in.cnt, in.cap, s));
+                CK(launch_push64(in.I, p, in.Er, in.Ez, in.Br, in.Bz, in.cx, in.cnt, in.cap, s));
                 if (ctx->timing) CK(hipEventRecord(e1, s));
                 CK(launch_mcc64(in.I, p, in.cnt, in.cap, s));
                 if (in.c.src_rate > 0.0) CK(launch_source64(in.I, p, in.cnt, s));
-                CK(launch_deposit64(in.I, p, in.Q, in.Qw, in.cnt, in.cap, s));
+                CK(launch_deposit64(in.I, p, in.Q, in.Qw, in.Qx, in.cnt, in.cap, s));
             }
             st = pic_field_stage(ctx, s);
             if (st != PIC_OK) return st;
@@ -1253,7 +1403,17 @@ extern "C" pic_status pic_set_fields(pic_ctx* ctx, int k, const double* Er, cons
         CK(hipMemcpy(in.EB, eb.data(), sizeof(float4) * N, hipMemcpyHostToDevice));
     }
     in.frozen = frozen != 0;
-    return upload_tables(ctx);
+    st = upload_tables(ctx);
+    if (st != PIC_OK || !ctx->s3) return st;
+    // cubic shapes: a frozen field is the given nodal one alone; back to the
+    // self-consistent field, the nodal arrays hold the vacuum field again
+    CK(hipMemsetAsync(in.cx, 0, sizeof(double) * (size_t)(in.c.nr + 3) * (in.c.nz + 3), ctx->stream));
+    if (!in.frozen) {
+        CK(launch_efield_tab(ctx->dI, ctx->dFvac, k, 1, in.nodes, false, ctx->stream));
+        st = pic_solve_all(ctx);
+    }
+    CK(hipStreamSynchronize(ctx->stream));
+    return st;
 }
 
 extern "C" pic_status pic_get_fields(pic_ctx* ctx, int k, double* Er, double* Ez, double* Br,
@@ -1290,6 +1450,18 @@ extern "C" pic_status pic_get_charge(pic_ctx* ctx, int k, long long* Q) {
     return PIC_OK;
 }
 
+extern "C" pic_status pic_get_spline3(pic_ctx* ctx, int k, long long* Qx, double* cx) {
+    pic_status st = check_inst(ctx, k);
+    if (st != PIC_OK) return st;
+    Inst& in = ctx->in[k];
+    if (!in.Qx) return fail(ctx, PIC_EINVAL, "the instance does not use cubic shapes");
+    const size_t X = (size_t)(in.c.nr + 3) * (in.c.nz + 3);
+    CK(hipStreamSynchronize(ctx->stream));
+    if (Qx) CK(hipMemcpy(Qx, in.Qx, sizeof(long long) * X, hipMemcpyDeviceToHost));
+    if (cx) CK(hipMemcpy(cx, in.cx, sizeof(double) * X, hipMemcpyDeviceToHost));
+    return PIC_OK;
+}
+
 extern "C" pic_status pic_get_band_charge(pic_ctx* ctx, int k, long long* Qw) {
     pic_status st = check_inst(ctx, k);
     if (st != PIC_OK) return st;
@@ -1300,6 +1472,96 @@ extern "C" pic_status pic_get_band_charge(pic_ctx* ctx, int k, long long* Qw) {
         return PIC_OK;
     }
     CK(hipMemcpy(Qw, ctx->in[k].Qw, sizeof(long long) * ctx->in[k].nodes, hipMemcpyDeviceToHost));
+    return PIC_OK;
+}
+
+// max over 0 <= E <= E_cap of (sigma_el + sigma_iz)(E) v(E) for a table:
+// every piece between table points, the threshold and E_cap is linear in E,
+// so (alpha + beta E) sqrt(E) peaks at an end or at E = -alpha / (3 beta).
+static double table_sigv_max(const pic_instance_cfg& c, int n, const double* E, const double* el,
+                             const double* iz) {
+    const double two_e_over_me = (2.0 * kE) / kMe;
+    auto total = [&](double x, bool above) {
+        double t = xs_interp(n, E, el, x);
+        if (x > c.iz_I_eV || (above && x == c.iz_I_eV)) t += xs_interp(n, E, iz, x);
+        return t;
+    };
+    std::vector<double> cut;
+    cut.push_back(0.0);
+    for (int k = 0; k < n; ++k)
+        if (E[k] > 0.0 && E[k] < c.E_cap_eV) cut.push_back(E[k]);
+    if (c.iz_I_eV > 0.0 && c.iz_I_eV < c.E_cap_eV) cut.push_back(c.iz_I_eV);
+    cut.push_back(c.E_cap_eV);
+    std::sort(cut.begin(), cut.end());
+    double best = 0.0;
+    for (size_t i = 0; i + 1 < cut.size(); ++i) {
+        const double p = cut[i], q = cut[i + 1];
+        if (!(q > p)) continue;
+        const double sp = total(p, true), sq = total(q, false);
+        best = std::max(best, sp * sqrt(p * two_e_over_me));
+        best = std::max(best, sq * sqrt(q * two_e_over_me));
+        const double beta = (sq - sp) / (q - p), alpha = sp - beta * p;
+        if (beta < 0.0 && alpha > 0.0) {
+            const double x = -alpha / (3.0 * beta);
+            if (x > p && x < q) best = std::max(best, (alpha + beta * x) * sqrt(x * two_e_over_me));
+        }
+    }
+    return best;
+}
+
+extern "C" pic_status pic_set_cross_sections(pic_ctx* ctx, int k, int n, const double* E_eV,
+                                             const double* sigma_el, const double* sigma_iz) {
+    pic_status st = check_inst(ctx, k);
+    if (st != PIC_OK) return st;
+    if (n != 0 && (n < 2 || n > 4096)) return fail(ctx, PIC_EINVAL, "need 2 <= n <= 4096 table points (or 0)");
+    if (n > 0 && (!E_eV || !sigma_el || !sigma_iz)) return fail(ctx, PIC_EINVAL, "table arrays are NULL");
+    for (int t = 0; t < n; ++t) {
+        if (!(E_eV[t] >= 0.0) || !(sigma_el[t] >= 0.0) || !(sigma_iz[t] >= 0.0))
+            return fail(ctx, PIC_EINVAL, "energies and cross sections must be >= 0");
+        if (t > 0 && !(E_eV[t] > E_eV[t - 1])) return fail(ctx, PIC_EINVAL, "energies must increase strictly");
+    }
+    CK(hipStreamSynchronize(ctx->stream));
+    Inst& in = ctx->in[k];
+    DevInst& I = in.I;
+    const void* old[6] = {I.xs_E, I.xs_el, I.xs_iz, I.xs_Ef, I.xs_elf, I.xs_izf};
+    for (const void* p : old)
+        if (p) pic_dev_free(ctx, const_cast<void*>(p));
+    I.xs_n = 0;
+    I.xs_E = I.xs_el = I.xs_iz = nullptr;
+    I.xs_Ef = I.xs_elf = I.xs_izf = nullptr;
+    pic_derived_t d;
+    pic_derive(&in.c, in.S, &d);
+    if (n > 0) {
+        bool ok = true;
+        std::vector<double> vE(E_eV, E_eV + n), vel(sigma_el, sigma_el + n), viz(sigma_iz, sigma_iz + n);
+        std::vector<float> fE(n), fel(n), fiz(n);
+        for (int t = 0; t < n; ++t) {
+            fE[t] = (float)E_eV[t];
+            fel[t] = (float)sigma_el[t];
+            fiz[t] = (float)sigma_iz[t];
+        }
+        I.xs_E = upload_vec(ctx, vE, ctx->stream, ok);
+        I.xs_el = upload_vec(ctx, vel, ctx->stream, ok);
+        I.xs_iz = upload_vec(ctx, viz, ctx->stream, ok);
+        I.xs_Ef = upload_vec(ctx, fE, ctx->stream, ok);
+        I.xs_elf = upload_vec(ctx, fel, ctx->stream, ok);
+        I.xs_izf = upload_vec(ctx, fiz, ctx->stream, ok);
+        CK(hipStreamSynchronize(ctx->stream));
+        if (!ok) return fail(ctx, PIC_ENOMEM, "device allocation of the cross-section table failed");
+        I.xs_n = n;
+        // the bound, widened by 2^-20 against rounding
+        d.nu_prime = (d.n_n * table_sigv_max(in.c, n, E_eV, sigma_el, sigma_iz)) * (1.0 + 0x1p-20);
+        d.P_null = -expm1(-(d.nu_prime * in.c.dt));
+    }
+    in.d.nu_prime = d.nu_prime;
+    in.d.P_null = d.P_null;
+    I.nu_prime = d.nu_prime;
+    I.P_null = d.P_null;
+    I.null_k = null_threshold(d.P_null);
+    I.nu_prime_f = (float)d.nu_prime;
+    st = pic_upload_inst(ctx);
+    if (st != PIC_OK) return st;
+    if (ctx->mode == PIC_MODE_FP32_BATCHED) return f32_rates_changed(ctx);
     return PIC_OK;
 }
 

@@ -225,9 +225,14 @@ __device__ __forceinline__ int collide_f(const DevInst& I, unsigned long long ke
     float v2 = (vr * vr + vt * vt) + vz * vz;
     float v = sqrtf(v2);
     float E = v2 * I.half_me_over_e_f;
-    float nu_el = I.nsig_el_f * v;
-    float sig = 0.0f;
-    if (E > I.iz_I_f) sig = (I.lotz_aq_f * logf(E / I.iz_I_f)) / (E * I.iz_I_f);
+    float nu_el, sig = 0.0f;
+    if (I.xs_n > 0) {
+        nu_el = (I.n_n_f * xs_interp(I.xs_n, I.xs_Ef, I.xs_elf, E)) * v;
+        if (E > I.iz_I_f) sig = xs_interp(I.xs_n, I.xs_Ef, I.xs_izf, E);
+    } else {
+        nu_el = I.nsig_el_f * v;
+        if (E > I.iz_I_f) sig = (I.lotz_aq_f * logf(E / I.iz_I_f)) / (E * I.iz_I_f);
+    }
     float nu_iz = (I.n_n_f * sig) * v;
     float R = u_proc * I.nu_prime_f;
     int ev;
@@ -1607,6 +1612,28 @@ static pic_status quiesce(pic_ctx* ctx, F32State* S) {
     drop_graphs(S);
     return PIC_OK;
 }
+
+// The null-collision probability of an instance changed (tabulated cross
+// sections): size the candidate queue and the collision grid again.
+pic_status f32_rates_changed(pic_ctx* ctx) {
+    F32State* S = pic_get_f32(ctx);
+    pic_status st = quiesce(ctx, S);
+    if (st != PIC_OK) return st;
+    double pmax = 0.0;
+    for (int k = 0; k < pic_n_inst(ctx); ++k) pmax = std::max(pmax, pic_inst_dev(ctx, k).P_null);
+    const long long off = S->total_cap;
+    const long long qcap = std::min<long long>(off, std::max<long long>(1 << 16, (long long)(64.0 * pmax * (double)off)));
+    if (qcap > S->qcap) {
+        unsigned long long* nq = (unsigned long long*)pic_dev_alloc(ctx, sizeof(unsigned long long) * qcap);
+        if (!nq) return f32_fail(ctx, PIC_ENOMEM, "collision queue");
+        pic_dev_free(ctx, S->queue);
+        S->queue = nq;
+        S->qcap = qcap;
+    }
+    S->coll_grid = (int)std::min<double>(4096.0, std::max(64.0, std::ceil(pmax * (double)off / (4.0 * kWG))));
+    return PIC_OK;
+}
+
 
 pic_status f32_retune(pic_ctx* ctx, int tile_r, int tile_z, int halo, int sort_interval) {
     F32State* S = pic_get_f32(ctx);

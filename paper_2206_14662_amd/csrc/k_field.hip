@@ -493,7 +493,129 @@ __global__ void ks_commit(const DevInst* __restrict__ It, long long* cnt_base, l
     if (ctl && threadIdx.x == 0) prep_tails(ctl, cnt_base, n_inst);
 }
 
+// ---- cubic B-spline space charge ------------------------------------------
+// Unknown coefficients at 1 <= i <= nr-1, 1 <= j <= nz-1; the ghost nodes
+// -1 and nr+1 (nz+1) hold minus the reflected coefficient, the wall nodes 0.
+
+// raw index in [-1, n+1] -> unknown index and sign (0: fixed at 0)
+__device__ __forceinline__ int fold3(int i, int n, int& u) {
+    if (i >= 1 && i <= n - 1) {
+        u = i;
+        return 1;
+    }
+    u = i < 0 ? 1 : n - 1;
+    return (i == -1 || i == n + 1) ? -1 : 0;
+}
+
+// load of the unknowns: the ghosted deposit folded with the reflection signs
+__global__ void k3_fold(const DevInst* __restrict__ It, const FieldDev* __restrict__ F3,
+                        const double* __restrict__ bscale) {
+    const DevInst& I = It[blockIdx.y];
+    const FieldDev& F = F3[blockIdx.y];
+    if (I.frozen) return;
+    const int W = I.W, WX = I.nz + 3;
+    const double bs = bscale[blockIdx.y];
+    for (int n = blockIdx.x * blockDim.x + threadIdx.x; n < I.nodes; n += gridDim.x * blockDim.x) {
+        const int i = n / W, j = n - i * W;
+        if (i < 1 || i > I.nr - 1 || j < 1 || j > I.nz - 1) continue;
+        const int ri[2] = {i, i == 1 ? -1 : (i == I.nr - 1 ? I.nr + 1 : -100)};
+        const int rj[2] = {j, j == 1 ? -1 : (j == I.nz - 1 ? I.nz + 1 : -100)};
+        double v = 0.0;
+        for (int a = 0; a < 2; ++a)
+            for (int b = 0; b < 2; ++b) {
+                if (ri[a] == -100 || rj[b] == -100) continue;
+                const double sg = (a == 0 ? 1.0 : -1.0) * (b == 0 ? 1.0 : -1.0);
+                v += sg * (double)F.Qx[(long long)(ri[a] + 1) * WX + (rj[b] + 1)];
+            }
+        F.rhs[n] = v * bs;
+    }
+}
+
+// per sine mode k (one lane each): the 7-band r system, L D L^T factors
+// precomputed on the host; in place in rhs
+__global__ void __launch_bounds__(64) k3_band(const DevInst* __restrict__ It, const FieldDev* __restrict__ F3) {
+    const DevInst& I = It[blockIdx.y];
+    const FieldDev& F = F3[blockIdx.y];
+    const int k = blockIdx.x * 64 + threadIdx.x;
+    if (I.frozen || k < 1 || k > I.nz - 1) return;
+    const int W = I.W, m = I.nr - 1;
+    double* x = F.rhs;
+    double y1 = 0.0, y2 = 0.0, y3 = 0.0;  // y at rows i-1, i-2, i-3
+    for (int i = 1; i <= m; ++i) {
+        const long long n = (long long)i * W + k;
+        const double y = ((x[n] - F.s3_L1[n] * y1) - F.s3_L2[n] * y2) - F.s3_L3[n] * y3;
+        x[n] = y;
+        y3 = y2;
+        y2 = y1;
+        y1 = y;
+    }
+    double x1 = 0.0, x2 = 0.0, x3 = 0.0;  // x at rows i+1, i+2, i+3
+    for (int i = m; i >= 1; --i) {
+        const long long n = (long long)i * W + k;
+        const double l1 = i + 1 <= m ? F.s3_L1[n + W] : 0.0;
+        const double l2 = i + 2 <= m ? F.s3_L2[n + 2 * W] : 0.0;
+        const double l3 = i + 3 <= m ? F.s3_L3[n + 3 * W] : 0.0;
+        const double v = ((x[n] * F.s3_Dinv[n] - l1 * x1) - l2 * x2) - l3 * x3;
+        x[n] = v;
+        x3 = x2;
+        x2 = x1;
+        x1 = v;
+    }
+}
+
+// ghosted coefficients from the solved ones (the table's phi), and the
+// potential phi = phi_vac + sum of the 3x3 neighbouring coefficients with
+// B(0) = 4/6, B(+-1) = 1/6
+__global__ void k3_post(const DevInst* __restrict__ It, const FieldDev* __restrict__ Ft,
+                        const FieldDev* __restrict__ F3) {
+    const DevInst& I = It[blockIdx.y];
+    const FieldDev& F = Ft[blockIdx.y];
+    if (I.frozen) return;
+    const double* c = F3[blockIdx.y].phi;
+    const int W = I.W, WX = I.nz + 3;
+    const long long ext = (long long)(I.nr + 3) * WX;
+    auto coef = [&](int ri, int rj) {
+        int ui, uj;
+        const int si = fold3(ri, I.nr, ui), sj = fold3(rj, I.nz, uj);
+        return (si && sj) ? (double)(si * sj) * c[(long long)ui * W + uj] : 0.0;
+    };
+    for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < ext;
+         t += (long long)gridDim.x * blockDim.x) {
+        const int gi = (int)(t / WX), gj = (int)(t - (long long)gi * WX);
+        F.cx[t] = coef(gi - 1, gj - 1);
+        if (gi > I.nr || gj > I.nz) continue;
+        // node (gi, gj)
+        const double nb[3] = {1.0 / 6.0, 4.0 / 6.0, 1.0 / 6.0};
+        double v = 0.0;
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) v += (nb[a] * nb[b]) * coef(gi - 1 + a, gj - 1 + b);
+        const long long n = (long long)gi * W + gj;
+        F.phi[n] = F.phi_vac[n] + v;
+    }
+}
+
 }  // namespace
+
+hipError_t launch_solve3_tab(const DevInst* It, const FieldDev* Ft, const FieldDev* F3, int n_inst, int max_nr,
+                             int max_nz, long long max_ext, const double2* tw, int tw_n, const double* bscale,
+                             hipStream_t s) {
+    if (n_inst <= 0) return hipSuccess;
+    const long long max_nodes = (long long)(max_nr + 1) * (max_nz + 1);
+    hipLaunchKernelGGL(k3_fold, dim3((unsigned)((max_nodes + 255) / 256), n_inst), dim3(256), 0, s, It, F3, bscale);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    size_t lds = sizeof(double2) * 2 * (size_t)max_nz;
+    dim3 gdst((unsigned)(max_nr / 2), (unsigned)n_inst);
+    const dim3 fb((unsigned)fft_block(max_nz));
+    hipLaunchKernelGGL(kf_dst, gdst, fb, lds, s, It, F3, 0, tw, tw_n, 1, bscale);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k3_band, dim3((unsigned)((max_nz + 63) / 64), n_inst), dim3(64), 0, s, It, F3);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(kf_dst, gdst, fb, lds, s, It, F3, 0, tw, tw_n, 2, bscale);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k3_post, dim3((unsigned)((max_ext + 255) / 256), n_inst), dim3(256), 0, s, It, Ft, F3);
+    return hipGetLastError();
+}
 
 hipError_t launch_zero_i64(long long* p, long long n, hipStream_t s) {
     if (n <= 0) return hipSuccess;

@@ -41,6 +41,36 @@ __device__ __forceinline__ Shape shape64(const DevInst& I, double r, double z) {
     return sh;
 }
 
+// Cubic shapes: base node i0 (clamped) and offset of a coordinate.
+__device__ __forceinline__ void base3(double s, int n, int& i0, double& f) {
+    int i = (int)floor(s);
+    i = i < 0 ? 0 : (i > n - 1 ? n - 1 : i);
+    i0 = i;
+    f = s - (double)i;
+}
+
+// Space-charge field -grad phi_sc at (r, z) from the ghosted cubic
+// coefficients (nodes i0-1 .. i0+2 at ghosted rows i0 .. i0+3).
+__device__ __forceinline__ void field3(const DevInst& I, const double* cx, double r, double z, double& er,
+                                       double& ez) {
+    int i0, j0;
+    double fr, fz, wr[4], dwr[4], wz[4], dwz[4];
+    base3((r - I.a) / I.dr, I.nr, i0, fr);
+    base3(z / I.dz, I.nz, j0, fz);
+    bspline3(fr, wr, dwr);
+    bspline3(fz, wz, dwz);
+    const int WX = I.nz + 3;
+    double gr = 0.0, gz = 0.0;
+    for (int a = 0; a < 4; ++a)
+        for (int b = 0; b < 4; ++b) {
+            const double v = cx[(long long)(i0 + a) * WX + (j0 + b)];
+            gr += v * (dwr[a] * wz[b]);
+            gz += v * (wr[a] * dwz[b]);
+        }
+    er = -(gr / I.dr);
+    ez = -(gz / I.dz);
+}
+
 __device__ __forceinline__ double gather64(const Shape& sh, const double* F, int W) {
     long long n00 = (long long)sh.i * W + sh.j;
     return ((sh.w00 * F[n00] + sh.w10 * F[n00 + W]) + sh.w01 * F[n00 + 1]) + sh.w11 * F[n00 + W + 1];
@@ -77,7 +107,8 @@ __global__ void k_load64(DevInst I, double r_lo, double r_hi, double z_lo, doubl
 __global__ void __launch_bounds__(kBlock) k_push64(DevInst I, P64 p, const double* __restrict__ Er,
                                                   const double* __restrict__ Ez,
                                                   const double* __restrict__ Br,
-                                                  const double* __restrict__ Bz, long long* cnt) {
+                                                  const double* __restrict__ Bz,
+                                                  const double* __restrict__ cx, long long* cnt) {
     const long long n = cnt[C_SLOTS];
     const double h = I.h, dt = I.dt;
     unsigned long long pushed = 0;
@@ -90,6 +121,14 @@ __global__ void __launch_bounds__(kBlock) k_push64(DevInst I, P64 p, const doubl
         Shape sh = shape64(I, r, z);
         double er = gather64(sh, Er, I.W), ez = gather64(sh, Ez, I.W);
         double br = gather64(sh, Br, I.W), bz = gather64(sh, Bz, I.W);
+        if (cx) {
+            // cubic shapes: the nodal arrays hold the vacuum field; the space
+            // charge's comes from the spline coefficients at the particle
+            double e3r, e3z;
+            field3(I, cx, r, z, e3r, e3z);
+            er += e3r;
+            ez += e3z;
+        }
         double hEr = h * er, hEz = h * ez;
         double mr = vr + hEr, mt = vt, mz = vz + hEz;
         double tr = h * br, tz = h * bz;
@@ -178,9 +217,14 @@ __global__ void __launch_bounds__(kBlock) k_mcc64(DevInst I, P64 p, long long* c
         double u_proc = u52(b0.z, b0.w);
         double v = sqrt(v2);
         double E = v2 * I.half_me_over_e;
-        double nu_el = I.nsig_el * v;
-        double sig_iz = 0.0;
-        if (E > I.iz_I) sig_iz = (I.lotz_aq * log(E / I.iz_I)) / (E * I.iz_I);
+        double nu_el, sig_iz = 0.0;
+        if (I.xs_n > 0) {
+            nu_el = (I.n_n * xs_interp(I.xs_n, I.xs_E, I.xs_el, E)) * v;
+            if (E > I.iz_I) sig_iz = xs_interp(I.xs_n, I.xs_E, I.xs_iz, E);
+        } else {
+            nu_el = I.nsig_el * v;
+            if (E > I.iz_I) sig_iz = (I.lotz_aq * log(E / I.iz_I)) / (E * I.iz_I);
+        }
         double nu_iz = (I.n_n * sig_iz) * v;
         double R = u_proc * I.nu_prime;
         int ev;
@@ -292,8 +336,29 @@ __device__ __forceinline__ void deposit4(long long* Q, const Shape& sh, int W, l
     atomicAdd((unsigned long long*)&Q[n00 + W + 1], (unsigned long long)q11);
 }
 
+// Cubic shapes: the 16 node charges of one particle (rint(W w) for 15, the
+// last the remainder) into the ghosted grid Qx.
+__device__ __forceinline__ void deposit16(const DevInst& I, long long* Qx, double r, double z, long long Wq) {
+    int i0, j0;
+    double fr, fz, wr[4], dwr[4], wz[4], dwz[4];
+    base3((r - I.a) / I.dr, I.nr, i0, fr);
+    base3(z / I.dz, I.nz, j0, fz);
+    bspline3(fr, wr, dwr);
+    bspline3(fz, wz, dwz);
+    const int WX = I.nz + 3;
+    const double Wd = (double)Wq;
+    long long sum = 0;
+    for (int a = 0; a < 4; ++a)
+        for (int b = 0; b < 4; ++b) {
+            const long long q = (a == 3 && b == 3) ? Wq - sum : (long long)rint(Wd * (wr[a] * wz[b]));
+            sum += q;
+            atomicAdd((unsigned long long*)&Qx[(long long)(i0 + a) * WX + (j0 + b)], (unsigned long long)q);
+        }
+}
+
 __global__ void __launch_bounds__(kBlock) k_deposit64(DevInst I, P64 p, long long* __restrict__ Q,
-                                                     long long* __restrict__ Qw, long long* cnt) {
+                                                     long long* __restrict__ Qw, long long* __restrict__ Qx,
+                                                     long long* cnt) {
     long long n = cnt[C_SLOTS] + cnt[C_SPAWN];
     if (n > I.p_cap) n = I.p_cap;
     for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < n;
@@ -309,6 +374,7 @@ __global__ void __launch_bounds__(kBlock) k_deposit64(DevInst I, P64 p, long lon
             const double g = ins_g(I, r, p.z[q]);
             if (g < I.ins_gam) deposit4(Qw, sh, I.W, (long long)rint((double)Wq * (ins_w(I, g) - 1.0)));
         }
+        if (Qx) deposit16(I, Qx, r, p.z[q], Wq);
     }
 }
 
@@ -350,10 +416,10 @@ hipError_t launch_load64(const DevInst& I, const pic_instance_cfg& c, P64 p, lon
 }
 
 hipError_t launch_push64(const DevInst& I, P64 p, const double* Er, const double* Ez,
-                         const double* Br, const double* Bz, long long* cnt, long long grid_cap,
+                         const double* Br, const double* Bz, const double* cx, long long* cnt, long long grid_cap,
                          hipStream_t s) {
     hipLaunchKernelGGL(k_push64, dim3(grid_for(grid_cap)), dim3(kBlock), 0, s, I, p, Er, Ez, Br, Bz,
-                       cnt);
+                       I.spline3 ? cx : nullptr, cnt);
     return hipGetLastError();
 }
 
@@ -374,10 +440,10 @@ hipError_t launch_moments64(const DevInst& I, P64 p, const long long* cnt, doubl
     return hipGetLastError();
 }
 
-hipError_t launch_deposit64(const DevInst& I, P64 p, long long* Q, long long* Qw, long long* cnt,
+hipError_t launch_deposit64(const DevInst& I, P64 p, long long* Q, long long* Qw, long long* Qx, long long* cnt,
                             long long grid_cap, hipStream_t s) {
     hipLaunchKernelGGL(k_deposit64, dim3(grid_for(grid_cap)), dim3(kBlock), 0, s, I, p, Q, I.has_ins ? Qw : nullptr,
-                       cnt);
+                       I.spline3 ? Qx : nullptr, cnt);
     return hipGetLastError();
 }
 

@@ -64,7 +64,29 @@ struct DevInst {
     int has_ins;
     double ins_r0, ins_z0, ins_er, ins_ez, ins_gam;
     float ins_r0_f, ins_z0_f, ins_inv_er_f, ins_inv_ez_f, ins_gam_f;
+    // cubic space-charge shapes (0: bilinear / Q1)
+    int spline3;
+    // tabulated cross sections (xs_n = 0: constant elastic, Lotz ionisation)
+    int xs_n;
+    const double *xs_E, *xs_el, *xs_iz;
+    const float *xs_Ef, *xs_elf, *xs_izf;
 };
+
+// Tabulated cross section at energy x: linear in E between the tabulated
+// points, the end values held outside the table (LXCat-style pairs).
+template <typename T>
+__host__ __device__ inline T xs_interp(int n, const T* E, const T* s, T x) {
+#pragma clang fp contract(off)
+    if (x <= E[0]) return s[0];
+    if (x >= E[n - 1]) return s[n - 1];
+    int lo = 0, hi = n - 1;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) / 2;
+        if (E[mid] <= x) lo = mid;
+        else hi = mid;
+    }
+    return s[lo] + (s[lo + 1] - s[lo]) * ((x - E[lo]) / (E[lo + 1] - E[lo]));
+}
 
 // Elliptic insert (Sec. III gun geometry): g = ((r-r0)/er)^2 + ((z-z0)/ez)^2 - 1,
 // g <= 0 inside the metal.  Web-spline weight function of the space-charge
@@ -176,8 +198,14 @@ __device__ inline void moments_add(const DevInst& I, double r, double z, double 
     const long long node[4] = {n00, n00 + I.W, n00 + 1, n00 + I.W + 1};
     const double v2 = (vr * vr + vt * vt) + vz * vz, v = sqrt(v2);
     const double E = v2 * I.half_me_over_e;
-    const double sig_iz = E > I.iz_I ? (I.lotz_aq * log(E / I.iz_I)) / (E * I.iz_I) : 0.0;
-    const double nu = (I.nsig_el + I.n_n * sig_iz) * v;
+    double nu;
+    if (I.xs_n > 0) {
+        const double siz = E > I.iz_I ? xs_interp(I.xs_n, I.xs_E, I.xs_iz, E) : 0.0;
+        nu = (I.n_n * xs_interp(I.xs_n, I.xs_E, I.xs_el, E) + I.n_n * siz) * v;
+    } else {
+        const double sig_iz = E > I.iz_I ? (I.lotz_aq * log(E / I.iz_I)) / (E * I.iz_I) : 0.0;
+        nu = (I.nsig_el + I.n_n * sig_iz) * v;
+    }
     const double q[kMoments] = {1.0, vr, vt, vz, vr * vr, vr * vt, vr * vz, vt * vt, vt * vz, vz * vz, nu};
     const long long N = I.nodes;
     for (int c = 0; c < kMoments; ++c)
@@ -236,8 +264,9 @@ struct P64 {
 };
 hipError_t launch_load64(const DevInst& I, const pic_instance_cfg& c, P64 p, long long n,
                          hipStream_t s);
+// cx: cubic shapes' ghosted space-charge coefficients (else null)
 hipError_t launch_push64(const DevInst& I, P64 p, const double* Er, const double* Ez,
-                         const double* Br, const double* Bz, long long* cnt, long long grid_cap,
+                         const double* Br, const double* Bz, const double* cx, long long* cnt, long long grid_cap,
                          hipStream_t s);
 // Seed-source electrons of the step appended after the slots (FP64 form).
 hipError_t launch_source64(const DevInst& I, P64 p, long long* cnt, hipStream_t s);
@@ -246,7 +275,8 @@ hipError_t launch_moments64(const DevInst& I, P64 p, const long long* cnt, doubl
 hipError_t launch_mcc64(const DevInst& I, P64 p, long long* cnt, long long grid_cap,
                         hipStream_t s);
 // Qw (insert instances, else null): the band particles' q (w(x_p) - 1)
-hipError_t launch_deposit64(const DevInst& I, P64 p, long long* Q, long long* Qw, long long* cnt,
+// Qx (cubic shapes, else null): the ghosted cubic deposit
+hipError_t launch_deposit64(const DevInst& I, P64 p, long long* Q, long long* Qw, long long* Qx, long long* cnt,
                             long long grid_cap, hipStream_t s);
 hipError_t launch_compact64(const DevInst& I, P64 src, P64 dst, long long* cnt,
                             long long* tmp_count, long long grid_cap, hipStream_t s);
@@ -282,7 +312,27 @@ struct FieldDev {
     const double* V;       // node volumes
     double* avg_acc;       // time-average accumulator
     long long* Qw;         // insert: node charges of q (w(x_p) - 1) of the particles in the weight band
+    // cubic shapes: ghosted deposit and coefficients ((nr+3) x (nz+3)), the
+    // per-mode LDL^T factors of the 7-band r systems ([i][k], row length W)
+    long long* Qx;
+    double* cx;
+    const double *s3_L1, *s3_L2, *s3_L3, *s3_Dinv;
 };
+
+// Cubic B-spline weights of the nodes i0-1 .. i0+2 at offset f in [0, 1)
+// from i0, and their derivatives.
+__host__ __device__ inline void bspline3(double f, double w[4], double dw[4]) {
+#pragma clang fp contract(off)
+    const double g = 1.0 - f;
+    w[0] = (g * g * g) / 6.0;
+    w[1] = ((3.0 * f - 6.0) * f * f + 4.0) / 6.0;
+    w[2] = (((-3.0 * f + 3.0) * f + 3.0) * f + 1.0) / 6.0;
+    w[3] = (f * f * f) / 6.0;
+    dw[0] = -(g * g) / 2.0;
+    dw[1] = ((3.0 * f - 4.0) * f) / 2.0;
+    dw[2] = ((-3.0 * f + 2.0) * f + 1.0) / 2.0;
+    dw[3] = (f * f) / 2.0;
+}
 
 // Elliptic insert, device side of the corrected solve (insert.hip).  The
 // instance's Galerkin system differs from the rectangle's only in the rows
@@ -338,6 +388,12 @@ hipError_t set_field_kernel_attrs(int max_nz);
 // Elliptic insert (insert.hip).  ins_build classifies the nodes, attaches
 // the outer hats, and assembles D on the host; an empty string means success.
 std::string ins_build(const pic_instance_cfg& c, InsHost& h);
+// Cubic shapes (k_field.hip): load folded from Qx, sine transform, the
+// 7-band solves, inverse transform into the coefficient buffer (the table's
+// phi), then the ghosted coefficients and phi = phi_vac + nodal value.
+hipError_t launch_solve3_tab(const DevInst* It, const FieldDev* Ft, const FieldDev* F3, int n_inst, int max_nr,
+                             int max_nz, long long max_ext, const double2* tw, int tw_n, const double* bscale,
+                             hipStream_t s);
 // per step (or for the vacuum): the load of every insert instance's nodes
 // from Q and Qw (scaled by bscale) into rhs
 hipError_t launch_ins_rhs(const DevInst* It, const InsDev* D, int n_ins, long long max_nodes, const FieldDev* Ft,

@@ -38,7 +38,7 @@ _BASE = dict(
     T_init_eV=1.0, weight=1.0e5, load_mode=1,
     seed=0, dt=1.0e-12, fx_shift=0, diag_interval=10, collisions=1,
     src_rate=0.0, src_T_eV=0.0,
-    ins_r0=0.0, ins_z0=0.0, ins_er=0.0, ins_ez=0.0, ins_band=0.0,
+    ins_r0=0.0, ins_z0=0.0, ins_er=0.0, ins_ez=0.0, ins_band=0.0, spline_order=1,
 )
 
 # Total seed charge of the small case (50k x 1e5 electrons) is kept for the
@@ -145,6 +145,19 @@ def gun8(n_per=16_000_000, nr=256, nz=512):
         out.append(gun(nr=nr, nz=nz, n_init=n_per, weight=3.6e6 * 50000 / n_per, p_mbar=press[i % 4],
                        V_inner=bias[i % 5], E_cap_eV=0.0, seed=(6 << 32) | i))
     return out
+
+
+def synthetic_xs(cfg, n=200, E_max=1.0e5):
+    """A synthetic cross-section table in LXCat layout (the paper's Ne data
+    are not available): n log-spaced energies 1e-2 .. E_max eV, an elastic
+    momentum-transfer cross section falling from ~2e-19 m^2 at low energy to
+    ~2e-21 m^2 at 10 keV, and the Lotz ionisation formula of the
+    configuration sampled at the same energies (zero below threshold)."""
+    E = np.geomspace(1.0e-2, E_max, n)
+    el = 2.0e-19 / (1.0 + E / 50.0) ** 0.75 + 2.0e-22
+    I = cfg["iz_I_eV"]
+    iz = np.where(E > I, cfg["lotz_a"] * cfg["lotz_q"] * np.log(np.maximum(E, I) / I) / (E * I), 0.0)
+    return E, el, iz
 
 
 WORKLOADS = {

@@ -1,0 +1,165 @@
+"""Cubic B-spline particle shapes and space-charge FEM (the paper's spline FEM
+of higher order, Sec. II.A).  CPU: the oracle's cubic weights, deposit and
+Galerkin solve pinned by the B-spline identities, a manufactured solution at
+fourth order (third for the field) and Green reciprocity of the deposit /
+gather pair.  GPU: the FP64 form's transform-based cubic solve against the
+oracle's assembled one, and steps against the oracle."""
+import numpy as np
+import pytest
+
+import oracle
+import pic_inputs as pi
+from helpers import by_key, gpu_and_oracle, rel_vec_err
+from paper_2206_14662_amd import binding as B
+
+F32 = B.PIC_MODE_FP32_BATCHED
+F64 = B.PIC_MODE_FP64_PLAIN
+
+
+def cubic(**over):
+    kw = dict(spline_order=3, n_init=0)
+    kw.update(over)
+    return pi.coax64(**kw)
+
+
+def test_cubic_weights():
+    for f in (0.0, 0.13, 0.5, 0.77, 0.999):
+        w, dw = oracle.s3_weights(f)
+        off = np.array([-1.0, 0.0, 1.0, 2.0])
+        assert w.sum() == pytest.approx(1.0, abs=1e-15)
+        assert (w * off).sum() == pytest.approx(f, abs=1e-15)          # reproduces linear functions
+        assert (w * off ** 2).sum() == pytest.approx(f * f + 1.0 / 3.0, abs=1e-14)  # B-spline variance 1/3
+        assert dw.sum() == pytest.approx(0.0, abs=1e-15)
+        assert (dw * off).sum() == pytest.approx(1.0, abs=1e-14)
+        h = 1e-6
+        wp, _ = oracle.s3_weights(f + h) if f + h < 1 else oracle.s3_weights(f)
+        wm, _ = oracle.s3_weights(f - h) if f - h >= 0 else oracle.s3_weights(f)
+        if 0 < f - h and f + h < 1:
+            np.testing.assert_allclose((wp - wm) / (2 * h), dw, atol=1e-8)
+    w, _ = oracle.s3_weights(0.0)
+    np.testing.assert_allclose(w, [1 / 6, 4 / 6, 1 / 6, 0.0], atol=1e-16)
+
+
+def test_cubic_deposit_is_exact():
+    c = cubic()
+    S = oracle.auto_shift(c["weight"])
+    W = round(c["weight"] * 2.0 ** S)
+    rng = np.random.default_rng(2)
+    for _ in range(20):
+        r, z = rng.uniform(c["a"], c["b"]), rng.uniform(0, c["L"])
+        Qx = oracle.s3_deposit(c, r, z, W)
+        assert Qx.sum() == W and (Qx != 0).sum() <= 16
+        # the node charges are W times the weight products but for the last (the remainder)
+        dr, dz = (c["b"] - c["a"]) / c["nr"], c["L"] / c["nz"]
+        i0, j0 = int((r - c["a"]) / dr), int(z / dz)
+        wr, _ = oracle.s3_weights((r - c["a"]) / dr - i0)
+        wz, _ = oracle.s3_weights(z / dz - j0)
+        blk = Qx[i0:i0 + 4, j0:j0 + 4]
+        want = np.rint(W * np.outer(wr, wz))
+        assert np.array_equal(blk.ravel()[:15], want.ravel()[:15].astype(np.int64))
+
+
+def _manufactured(c):
+    a, b, L = c["a"], c["b"], c["L"]
+    kr, kz = np.pi / (b - a), np.pi / L
+    phi = lambda r, z: np.sin(kr * (r - a)) * np.sin(kz * z)
+    f = lambda r, z: (kr ** 2 + kz ** 2) * phi(r, z) - kr * np.cos(kr * (r - a)) * np.sin(kz * z) / r
+    return phi, f
+
+
+def test_manufactured_solution_fourth_order():
+    """phi* = sin(pi (r-a)/(b-a)) sin(pi z/L) is odd about every wall, so the
+    reflected cubic space holds it to fourth order (its gradient to third)."""
+    rng = np.random.default_rng(1)
+    errs, ferrs = [], []
+    for nr, nz in ((8, 16), (16, 32), (32, 64)):
+        c = cubic(nr=nr, nz=nz)
+        phi, f = _manufactured(c)
+        cx = oracle.s3_poisson_fn(c, f)
+        pts = [(rng.uniform(c["a"], c["b"]), rng.uniform(0, c["L"])) for _ in range(200)]
+        errs.append(max(abs(oracle.s3_phi_at(c, cx, r, z) - phi(r, z)) for r, z in pts))
+        e = 0.0
+        for r, z in pts[:60]:
+            er, ez = oracle.s3_field(c, cx, r, z)
+            h = 1e-7
+            e = max(e, abs(er + (phi(r + h, z) - phi(r - h, z)) / (2 * h)),
+                    abs(ez + (phi(r, z + h) - phi(r, z - h)) / (2 * h)))
+        ferrs.append(e)
+    assert errs[0] / errs[1] > 12 and errs[1] / errs[2] > 12, errs
+    assert ferrs[0] / ferrs[1] > 6 and ferrs[1] / ferrs[2] > 6, ferrs
+    assert errs[-1] < 2e-7
+
+
+def test_green_reciprocity_of_deposit_and_gather():
+    """The potential of charge 1 read with the cubic basis at x2 equals that
+    of charge 2 at x1 (symmetric system, the same basis for load and read)."""
+    c = cubic(nr=32, nz=64)
+    x1, x2 = (3.3e-3, 17.2e-3), (7.9e-3, 41.7e-3)
+    vals = []
+    for src, at in ((x1, x2), (x2, x1)):
+        o = oracle.Sim(c, capacity=16)
+        st = dict(r=np.array([src[0]]), z=np.array([src[1]]), vr=np.zeros(1), vt=np.zeros(1), vz=np.zeros(1),
+                  w=np.array([c["weight"]]), key=np.zeros(1, dtype=np.uint64))
+        o.set_particles(st)
+        vals.append(oracle.s3_phi_at(c, o.coef3(), *at))
+        o.close()
+    assert vals[0] == pytest.approx(vals[1], rel=1e-9) and vals[0] != 0.0
+
+
+def test_cubic_and_bilinear_agree_on_a_smooth_cloud():
+    """Both discretise the same continuum problem: on a smooth cloud their
+    space-charge potentials agree to the discretisation error."""
+    c1 = pi.coax64(nr=64, nz=128, n_init=0)
+    c3 = dict(c1, spline_order=3)
+    st = pi.cloud_state(c1, 200000, seed=3)
+    phis = []
+    for c in (c1, c3):
+        o = oracle.Sim(c, capacity=250000)
+        o.set_particles(st)
+        phis.append(o.phi() - oracle.vacuum(c))
+        o.close()
+    d = np.abs(phis[0] - phis[1]).max() / np.abs(phis[0]).max()
+    assert d < 0.05, d
+
+
+@pytest.mark.gpu
+def test_gpu_cubic_solve_matches_the_oracle():
+    c = cubic(nr=64, nz=128)
+    st = pi.particle_state(c, 40000, seed=12)
+    g, o = gpu_and_oracle(c, st, frozen=0)
+    Qx, cx = g.spline3()
+    assert np.array_equal(Qx, o.charge3())
+    assert np.array_equal(g.charge(), o.charge())
+    ocx = o.coef3()
+    assert np.abs(cx - ocx).max() <= 1e-11 * np.abs(ocx).max()
+    vac = oracle.vacuum(c)
+    sg, so = g.phi() - vac, o.phi() - vac
+    assert np.abs(sg - so).max() <= 1e-11 * np.abs(so).max()
+    g.close()
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("collisions", [0, 1])
+def test_gpu_cubic_steps_match_the_oracle(collisions):
+    c = cubic(nr=64, nz=128, p_mbar=30.0 if collisions else 1e-6, E_cap_eV=3000.0, collisions=collisions)
+    st = pi.cloud_state(c, 30000, seed=13)
+    g, o = gpu_and_oracle(c, st, frozen=0)
+    g.step(15)
+    o.step(15)
+    gd, od = g.diag(), o.diag()
+    for k in ("n_live", "n_absorbed", "n_elastic", "n_ioniz"):
+        assert gd[k] == od[k], k
+    gp, op = by_key(g.get_particles()), by_key(o.get_particles())
+    assert np.array_equal(gp["key"], op["key"])
+    np.testing.assert_allclose(gp["r"], op["r"], rtol=1e-11)
+    np.testing.assert_allclose(gp["z"], op["z"], rtol=1e-11)
+    assert rel_vec_err(gp, op).max() <= 1e-9
+    g.close()
+
+
+@pytest.mark.gpu
+def test_cubic_configurations_refused():
+    for cfgs, mode in (([cubic()], F32), ([cubic(), pi.coax64(n_init=0)], F64), ([cubic(end_mode=2)], F64)):
+        with pytest.raises(B.PicError) as e:
+            B.Sim(cfgs, mode=mode)
+        assert e.value.status == B.PIC_EINVAL
