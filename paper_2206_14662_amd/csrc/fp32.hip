@@ -13,9 +13,9 @@
 // and every K steps the tile sort (count -> plan -> scatter -> commit).
 //
 // The particle kernel is persistent and statically balanced: workgroup w
-// takes the w-th of gridDim.x equal ranges of the step's particles (the
-// tile-sorted ones of all instances, then their tails) and walks the tile
-// segments the range covers.  For a tile segment it stages the tile's field
+// takes the w-th of gridDim.x equal ranges of the step's tile-sorted
+// particles of all instances and walks the tile segments the range covers,
+// then the w-th of gridDim.x equal ranges of the instances' tails.  For a tile segment it stages the tile's field
 // window (tile plus `halo` cells, float4 {Er, Ez, Br, Bz} per node) in LDS,
 // accumulates the segment's charge in an LDS int64 window, then flushes
 // non-zero window nodes to the global grid with int64 atomics.  Integer sums do not depend on
@@ -215,16 +215,18 @@ __device__ __forceinline__ void scatter_f(float ur, float ut, float uz, float co
     o[2] = cosx * uz + sinx * (cp * e1z + sp * e2z);
 }
 
-// The null-collision candidate becomes a real event (or not).  Returns 0
-// null, 1 elastic, 2 ionisation; sets the parent's new velocity and, for an
-// ionisation, the new electron's velocity and key.
-__device__ __forceinline__ int collide_f(const DevInst& I, unsigned long long key, unsigned int step, uint4 b0,
-                                      float& vr, float& vt, float& vz, float& cvr, float& cvt, float& cvz,
-                                      unsigned long long& ckey) {
-    float u_proc = u23(b0.z);
-    float v2 = (vr * vr + vt * vt) + vz * vz;
-    float v = sqrtf(v2);
-    float E = v2 * I.half_me_over_e_f;
+// Which process a null-collision candidate undergoes at its post-push
+// velocity (FP32): the process uniform scaled by nu' against nu_el and
+// nu_el + nu_iz.  Returns 0 null, 1 elastic, 2 ionisation, with the speed and
+// energy it used.  The particle kernel calls it to queue only real events;
+// the collision kernel calls it again on the same stored velocity, so both
+// take the same decision.
+__device__ __forceinline__ int event_kind_f(const DevInst& I, unsigned int bits, float vr, float vt, float vz,
+                                            float& v, float& E) {
+    const float u_proc = u23(bits);
+    const float v2 = (vr * vr + vt * vt) + vz * vz;
+    v = sqrtf(v2);
+    E = v2 * I.half_me_over_e_f;
     float nu_el, sig = 0.0f;
     if (I.xs_n > 0) {
         nu_el = (I.n_n_f * xs_interp(I.xs_n, I.xs_Ef, I.xs_elf, E)) * v;
@@ -233,12 +235,22 @@ __device__ __forceinline__ int collide_f(const DevInst& I, unsigned long long ke
         nu_el = I.nsig_el_f * v;
         if (E > I.iz_I_f) sig = (I.lotz_aq_f * logf(E / I.iz_I_f)) / (E * I.iz_I_f);
     }
-    float nu_iz = (I.n_n_f * sig) * v;
-    float R = u_proc * I.nu_prime_f;
-    int ev;
-    if (R < nu_el) ev = 1;
-    else if (R < nu_el + nu_iz) ev = 2;
-    else return 0;
+    const float nu_iz = (I.n_n_f * sig) * v;
+    const float R = u_proc * I.nu_prime_f;
+    if (R < nu_el) return 1;
+    if (R < nu_el + nu_iz) return 2;
+    return 0;
+}
+
+// The real event of a queued candidate.  Returns 0 null, 1 elastic, 2
+// ionisation; sets the parent's new velocity and, for an ionisation, the new
+// electron's velocity and key.
+__device__ __forceinline__ int collide_f(const DevInst& I, unsigned long long key, unsigned int step, uint4 b0,
+                                      float& vr, float& vt, float& vz, float& cvr, float& cvt, float& cvz,
+                                      unsigned long long& ckey) {
+    float v, E;
+    const int ev = event_kind_f(I, b0.z, vr, vt, vz, v, E);
+    if (ev == 0) return 0;
     float inv_v = 1.0f / v;
     float ur = vr * inv_v, ut = vt * inv_v, uz = vz * inv_v;
     uint4 b1 = philox_step(I, key, step, 1u);
@@ -470,17 +482,22 @@ __device__ __forceinline__ void push_particle(const KArgs& A, const ChunkCtx& X,
     if (alive) {
         if (fmaf(vz, vz, fmaf(vtn, vtn, vrn * vrn)) > L.v_cap2) atomicAdd(&X.s_ctr[SC_CAP], 1ull);
         if (L.collisions && x52 < L.null_k) {
-            // a null-collision candidate, resolved by k_collide after this
-            // kernel: into the workgroup's LDS queue (flushed to the device
-            // queue once per chunk), beyond its size straight to the device
-            const unsigned int qr = atomicAdd(X.s_qn, 1u);
-            const unsigned long long e = ((unsigned long long)X.inst << 40) | (unsigned long long)dst;
-            if (qr < (unsigned int)kLQ) {
-                X.s_q[qr] = e;
-            } else {
-                const long long qi = (long long)atomicAdd((unsigned long long*)&A.ctl[CTL_QCOUNT], 1ull);
-                if (qi < A.qcap) A.queue[qi] = e;
-                else A.ctl[CTL_QOVER] = 1;
+            // a null-collision candidate; a real event is resolved by
+            // k_collide after this kernel: into the workgroup's LDS queue
+            // (flushed to the device queue once per chunk), beyond its size
+            // straight to the device
+            atomicAdd(&X.s_ctr[SC_CAND], 1ull);
+            float sp, en;
+            if (event_kind_f(A.It[X.inst], b0.z, vrn, vtn, vz, sp, en) != 0) {
+                const unsigned int qr = atomicAdd(X.s_qn, 1u);
+                const unsigned long long e = ((unsigned long long)X.inst << 40) | (unsigned long long)dst;
+                if (qr < (unsigned int)kLQ) {
+                    X.s_q[qr] = e;
+                } else {
+                    const long long qi = (long long)atomicAdd((unsigned long long*)&A.ctl[CTL_QCOUNT], 1ull);
+                    if (qi < A.qcap) A.queue[qi] = e;
+                    else A.ctl[CTL_QOVER] = 1;
+                }
             }
         }
         out.r[dst] = rn;
@@ -579,175 +596,180 @@ __global__ void __launch_bounds__(kPWG) __attribute__((amdgpu_waves_per_eu(8, 8)
     __shared__ long long s_qbase;
     const int tid = threadIdx.x;
     // Static balance: workgroup w pushes the w-th of gridDim.x equal ranges of
-    // the step's particles (tile-sorted ones first, then the tails), walking
-    // the tile segments its range covers.
+    // the step's tile-sorted particles, walking the tile segments its range
+    // covers, then the w-th of gridDim.x equal ranges of the tails.  The
+    // tails (electrons created since the sort) have no LDS window and deposit
+    // with device atomics, so they are spread over every workgroup rather
+    // than left to the last ones.
     const long long total = A.ctl[CTL_TOTAL], nsorted = A.ctl[CTL_SORTED];
     const long long G = gridDim.x, wg = blockIdx.x;
-    const long long per = total / G, rmd = total % G;
-    long long v = wg * per + min(wg, rmd);
-    const long long vend = v + per + (wg < rmd ? 1 : 0);
-    while (v < vend) {
-        if (tid < 64) {
-            if (v < nsorted) {
-                const int t = wave_search(A.vtile, A.n_tiles, v);
-                if (tid == 0) {
-                    const long long tv = A.vtile[t], tv1 = A.vtile[t + 1];
-                    const int4 ti = A.tile_info[t];
-                    s_start = A.tile_start[t] + (v - tv);
-                    s_count = (int)min(min(vend, tv1) - v, (long long)A.C);
-                    s_inst = ti.x;
-                    s_tr0 = ti.y * A.TR;
-                    s_tz0 = ti.z * A.TZ;
-                }
-            } else {
-                const long long u = v - nsorted;
-                const long long* tb = A.ctl + CTL_TAIL;
-                const int k = wave_search(tb, A.n_inst, u);
-                if (tid == 0) {
-                    const long long* cj = A.cnt + (long long)k * C_NCOUNT;
-                    s_start = A.It[k].p_off + cj[C_LIVE_SORTED] + (u - tb[k]);
-                    s_count = (int)min(min(vend - v, tb[k + 1] - u), (long long)A.C);
-                    s_inst = k;
-                    s_tr0 = -1;
-                    s_tz0 = -1;
+    for (int part = 0; part < 2; ++part) {
+        const long long n_part = part ? total - nsorted : nsorted;
+        const long long per = n_part / G, rmd = n_part % G;
+        long long v = (part ? nsorted : 0ll) + wg * per + min(wg, rmd);
+        const long long vend = v + per + (wg < rmd ? 1 : 0);
+        while (v < vend) {
+            if (tid < 64) {
+                if (v < nsorted) {
+                    const int t = wave_search(A.vtile, A.n_tiles, v);
+                    if (tid == 0) {
+                        const long long tv = A.vtile[t], tv1 = A.vtile[t + 1];
+                        const int4 ti = A.tile_info[t];
+                        s_start = A.tile_start[t] + (v - tv);
+                        s_count = (int)min(min(vend, tv1) - v, (long long)A.C);
+                        s_inst = ti.x;
+                        s_tr0 = ti.y * A.TR;
+                        s_tz0 = ti.z * A.TZ;
+                    }
+                } else {
+                    const long long u = v - nsorted;
+                    const long long* tb = A.ctl + CTL_TAIL;
+                    const int k = wave_search(tb, A.n_inst, u);
+                    if (tid == 0) {
+                        const long long* cj = A.cnt + (long long)k * C_NCOUNT;
+                        s_start = A.It[k].p_off + cj[C_LIVE_SORTED] + (u - tb[k]);
+                        s_count = (int)min(min(vend - v, tb[k + 1] - u), (long long)A.C);
+                        s_inst = k;
+                        s_tr0 = -1;
+                        s_tz0 = -1;
+                    }
                 }
             }
-        }
-        if (SCATTER && tid < 9) s_bcnt[tid] = 0u;
-        if (COUNT && tid < 9) s_ccnt[tid] = 0u;
-        if (tid < SC_N) s_ctr[tid] = 0ull;
-        if (tid == SC_N) s_qn = 0u;
-        __syncthreads();
-        const int count = __builtin_amdgcn_readfirstlane(s_count);
-        v += count;
-        const long long start = s_start;
-        const int inst = __builtin_amdgcn_readfirstlane(s_inst);
-        const int tr0 = __builtin_amdgcn_readfirstlane(s_tr0), tz0 = __builtin_amdgcn_readfirstlane(s_tz0);
-        const DevInst& I = A.It[inst];
-        const FieldDev& F = A.Ft[inst];
-        long long* cnt = A.cnt + (long long)inst * C_NCOUNT;
-        const unsigned int step = (unsigned int)cnt[C_STEP];
-        const PSet out = SCATTER ? A.out : A.p;
-        const int W = I.W;
-        const bool win = tr0 >= 0;
-        const int ti_c = win ? tr0 / A.TR : 0, tj_c = win ? tz0 / A.TZ : 0;
-        int i0 = 0, i1 = -1, j0 = 0, j1 = -1, ww = 1;
-        if (win) {
-            i0 = max(tr0 - A.halo, 0);
-            i1 = min(tr0 + A.TR + A.halo, I.nr);
-            j0 = max(tz0 - A.halo, 0);
-            j1 = min(tz0 + A.TZ + A.halo, I.nz);
-            ww = j1 - j0 + 1;
-            const int nwin = (i1 - i0 + 1) * ww;
-            for (int t = tid; t < nwin; t += kPWG) {
-                int a = t / ww, b = t - a * ww;
-                sEB[t] = as_gbl(F.EB)[(long long)(i0 + a) * W + (j0 + b)];
-                sQ[t] = 0ull;
-            }
-        }
-        if (SCATTER && win) {
-            // pass 1: destinations of this chunk's particles per neighbouring tile
-            const LocalInst L1 = local_inst(I);
-            const int lead = (int)(start & 63);
-            for (int base = -lead; base < count; base += kPWG) {
-                const int q = base + tid;
-                const bool in = q >= 0 && q < count;
-                const long long p = start + (in ? q : 0);
-                const float r = A.p.r[p], z = A.p.z[p];
-                int bkt = -1;
-                if (in && r >= 0.0f) {
-                    int i, j;
-                    float fr, fz;
-                    cell_of(L1, r, z, i, j, fr, fz);
-                    int dr = i / A.TR - ti_c, dz = j / A.TZ - tj_c;
-                    if (dr >= -1 && dr <= 1 && dz >= -1 && dz <= 1) bkt = (dr + 1) * 3 + (dz + 1);
+            if (SCATTER && tid < 9) s_bcnt[tid] = 0u;
+            if (COUNT && tid < 9) s_ccnt[tid] = 0u;
+            if (tid < SC_N) s_ctr[tid] = 0ull;
+            if (tid == SC_N) s_qn = 0u;
+            __syncthreads();
+            const int count = __builtin_amdgcn_readfirstlane(s_count);
+            v += count;
+            const long long start = s_start;
+            const int inst = __builtin_amdgcn_readfirstlane(s_inst);
+            const int tr0 = __builtin_amdgcn_readfirstlane(s_tr0), tz0 = __builtin_amdgcn_readfirstlane(s_tz0);
+            const DevInst& I = A.It[inst];
+            const FieldDev& F = A.Ft[inst];
+            long long* cnt = A.cnt + (long long)inst * C_NCOUNT;
+            const unsigned int step = (unsigned int)cnt[C_STEP];
+            const PSet out = SCATTER ? A.out : A.p;
+            const int W = I.W;
+            const bool win = tr0 >= 0;
+            const int ti_c = win ? tr0 / A.TR : 0, tj_c = win ? tz0 / A.TZ : 0;
+            int i0 = 0, i1 = -1, j0 = 0, j1 = -1, ww = 1;
+            if (win) {
+                i0 = max(tr0 - A.halo, 0);
+                i1 = min(tr0 + A.TR + A.halo, I.nr);
+                j0 = max(tz0 - A.halo, 0);
+                j1 = min(tz0 + A.TZ + A.halo, I.nz);
+                ww = j1 - j0 + 1;
+                const int nwin = (i1 - i0 + 1) * ww;
+                for (int t = tid; t < nwin; t += kPWG) {
+                    int a = t / ww, b = t - a * ww;
+                    sEB[t] = as_gbl(F.EB)[(long long)(i0 + a) * W + (j0 + b)];
+                    sQ[t] = 0ull;
                 }
-                wave_aggregate<false>(bkt >= 0, bkt, [&](int k, unsigned int n) {
-                    atomicAdd(&s_bcnt[k], n);
-                    return 0u;
-                });
+            }
+            if (SCATTER && win) {
+                // pass 1: destinations of this chunk's particles per neighbouring tile
+                const LocalInst L1 = local_inst(I);
+                const int lead = (int)(start & 63);
+                for (int base = -lead; base < count; base += kPWG) {
+                    const int q = base + tid;
+                    const bool in = q >= 0 && q < count;
+                    const long long p = start + (in ? q : 0);
+                    const float r = A.p.r[p], z = A.p.z[p];
+                    int bkt = -1;
+                    if (in && r >= 0.0f) {
+                        int i, j;
+                        float fr, fz;
+                        cell_of(L1, r, z, i, j, fr, fz);
+                        int dr = i / A.TR - ti_c, dz = j / A.TZ - tj_c;
+                        if (dr >= -1 && dr <= 1 && dz >= -1 && dz <= 1) bkt = (dr + 1) * 3 + (dz + 1);
+                    }
+                    wave_aggregate<false>(bkt >= 0, bkt, [&](int k, unsigned int n) {
+                        atomicAdd(&s_bcnt[k], n);
+                        return 0u;
+                    });
+                }
+                __syncthreads();
+                if (tid < 9) {
+                    unsigned int n = s_bcnt[tid];
+                    if (n) {
+                        int t = I.tile_off + (ti_c + tid / 3 - 1) * I.ntz + (tj_c + tid % 3 - 1);
+                        s_bbase[tid] = atomicAdd(&A.tile_fill[t], n);
+                    }
+                    s_bcnt[tid] = 0u;
+                }
             }
             __syncthreads();
-            if (tid < 9) {
-                unsigned int n = s_bcnt[tid];
-                if (n) {
-                    int t = I.tile_off + (ti_c + tid / 3 - 1) * I.ntz + (tj_c + tid % 3 - 1);
-                    s_bbase[tid] = atomicAdd(&A.tile_fill[t], n);
+            unsigned int c_push = 0;
+            ChunkCtx X;
+            X.L = local_inst(I);
+            X.sEB = sEB; X.sQ = sQ; X.s_ctr = s_ctr; X.s_bcnt = s_bcnt; X.s_bbase = s_bbase; X.s_ccnt = s_ccnt;
+            X.s_qn = &s_qn; X.s_q = s_q;
+            X.out = out; X.EB = F.EB; X.Q = F.Q; X.Qw = F.Qw;
+            X.inst = inst; X.ti_c = ti_c; X.tj_c = tj_c; X.i0 = i0; X.i1 = i1; X.j0 = j0; X.j1 = j1; X.ww = ww;
+            X.win = win; X.step = step;
+            // U particles per lane per pass (their loads are all in flight before
+            // any is processed); U = 1 measured fastest on gfx950 (occupancy wins)
+            // Passes start on a 64-slot boundary so that every wave's loads and
+            // stores cover whole aligned lines; lanes before the chunk idle.
+            constexpr int U = 1;
+            const int lead = (int)(start & 63);
+            const float wu = X.L.w_uni;
+            for (int base = -lead; base < count; base += U * kPWG) {
+                long long pp[U];
+                bool inr[U];
+                float r[U], z[U], vr[U], vt[U], vz[U], w[U];
+                unsigned long long key[U];
+    #pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int q = base + u * kPWG + tid;
+                    inr[u] = q >= 0 && q < count;
+                    pp[u] = start + (inr[u] ? q : 0);
+                    r[u] = A.p.r[pp[u]];
+                    z[u] = A.p.z[pp[u]];
+                    vr[u] = A.p.vr[pp[u]];
+                    vt[u] = A.p.vt[pp[u]];
+                    vz[u] = A.p.vz[pp[u]];
+                    w[u] = wu != 0.0f ? wu : A.p.w[pp[u]];
+                    key[u] = A.p.key[pp[u]];
                 }
-                s_bcnt[tid] = 0u;
+    #pragma unroll
+                for (int u = 0; u < U; ++u)
+                    push_particle<COUNT, SCATTER, INS>(A, X, pp[u], inr[u], r[u], z[u], vr[u], vt[u], vz[u], w[u], key[u],
+                                                  c_push);
             }
-        }
-        __syncthreads();
-        unsigned int c_push = 0;
-        ChunkCtx X;
-        X.L = local_inst(I);
-        X.sEB = sEB; X.sQ = sQ; X.s_ctr = s_ctr; X.s_bcnt = s_bcnt; X.s_bbase = s_bbase; X.s_ccnt = s_ccnt;
-        X.s_qn = &s_qn; X.s_q = s_q;
-        X.out = out; X.EB = F.EB; X.Q = F.Q; X.Qw = F.Qw;
-        X.inst = inst; X.ti_c = ti_c; X.tj_c = tj_c; X.i0 = i0; X.i1 = i1; X.j0 = j0; X.j1 = j1; X.ww = ww;
-        X.win = win; X.step = step;
-        // U particles per lane per pass (their loads are all in flight before
-        // any is processed); U = 1 measured fastest on gfx950 (occupancy wins)
-        // Passes start on a 64-slot boundary so that every wave's loads and
-        // stores cover whole aligned lines; lanes before the chunk idle.
-        constexpr int U = 1;
-        const int lead = (int)(start & 63);
-        const float wu = X.L.w_uni;
-        for (int base = -lead; base < count; base += U * kPWG) {
-            long long pp[U];
-            bool inr[U];
-            float r[U], z[U], vr[U], vt[U], vz[U], w[U];
-            unsigned long long key[U];
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int q = base + u * kPWG + tid;
-                inr[u] = q >= 0 && q < count;
-                pp[u] = start + (inr[u] ? q : 0);
-                r[u] = A.p.r[pp[u]];
-                z[u] = A.p.z[pp[u]];
-                vr[u] = A.p.vr[pp[u]];
-                vt[u] = A.p.vt[pp[u]];
-                vz[u] = A.p.vz[pp[u]];
-                w[u] = wu != 0.0f ? wu : A.p.w[pp[u]];
-                key[u] = A.p.key[pp[u]];
+            flush_counter(&cnt[C_PSTEPS], (unsigned long long)c_push);
+            __syncthreads();
+            if (tid < SC_N) {
+                const unsigned long long v = s_ctr[tid];
+                if (v) atomicAdd((unsigned long long*)&cnt[kCounterOf[tid]], v);
             }
-#pragma unroll
-            for (int u = 0; u < U; ++u)
-                push_particle<COUNT, SCATTER, INS>(A, X, pp[u], inr[u], r[u], z[u], vr[u], vt[u], vz[u], w[u], key[u],
-                                              c_push);
-        }
-        flush_counter(&cnt[C_PSTEPS], (unsigned long long)c_push);
-        __syncthreads();
-        if (tid < SC_N) {
-            const unsigned long long v = s_ctr[tid];
-            if (v) atomicAdd((unsigned long long*)&cnt[kCounterOf[tid]], v);
-        }
-        // the chunk's queued candidates: one device reservation
-        const unsigned int q_all = s_qn;
-        const unsigned int q_lds = min(q_all, (unsigned int)kLQ);
-        if (tid == SC_N) {
-            if (q_all) atomicAdd((unsigned long long*)&cnt[C_CAND], (unsigned long long)q_all);
-            s_qbase = q_lds ? (long long)atomicAdd((unsigned long long*)&A.ctl[CTL_QCOUNT], (unsigned long long)q_lds)
-                            : 0ll;
-        }
-        if (COUNT && win && tid < 9) {
-            const unsigned int v = s_ccnt[tid];
-            if (v) atomicAdd(&A.cnt_out[I.tile_off + (ti_c + tid / 3 - 1) * I.ntz + (tj_c + tid % 3 - 1)], v);
-        }
-        __syncthreads();
-        for (unsigned int t = tid; t < q_lds; t += kPWG) {
-            const long long qi = s_qbase + t;
-            if (qi < A.qcap) A.queue[qi] = s_q[t];
-            else A.ctl[CTL_QOVER] = 1;
-        }
-        if (win) {
-            const int nwin = (i1 - i0 + 1) * ww;
-            gbl_u64* Qg = as_gbl(F.Q);
-            for (int t = tid; t < nwin; t += kPWG) {
-                const unsigned long long v = sQ[t];
-                if (v != 0ull) {
-                    int a = t / ww, b = t - a * ww;
-                    gbl_add(&Qg[(long long)(i0 + a) * W + (j0 + b)], v);
+            // the chunk's queued candidates: one device reservation
+            const unsigned int q_all = s_qn;
+            const unsigned int q_lds = min(q_all, (unsigned int)kLQ);
+            if (tid == SC_N) {
+                s_qbase = q_lds ? (long long)atomicAdd((unsigned long long*)&A.ctl[CTL_QCOUNT], (unsigned long long)q_lds)
+                                : 0ll;
+            }
+            if (COUNT && win && tid < 9) {
+                const unsigned int v = s_ccnt[tid];
+                if (v) atomicAdd(&A.cnt_out[I.tile_off + (ti_c + tid / 3 - 1) * I.ntz + (tj_c + tid % 3 - 1)], v);
+            }
+            __syncthreads();
+            for (unsigned int t = tid; t < q_lds; t += kPWG) {
+                const long long qi = s_qbase + t;
+                if (qi < A.qcap) A.queue[qi] = s_q[t];
+                else A.ctl[CTL_QOVER] = 1;
+            }
+            if (win) {
+                const int nwin = (i1 - i0 + 1) * ww;
+                gbl_u64* Qg = as_gbl(F.Q);
+                for (int t = tid; t < nwin; t += kPWG) {
+                    const unsigned long long v = sQ[t];
+                    if (v != 0ull) {
+                        int a = t / ww, b = t - a * ww;
+                        gbl_add(&Qg[(long long)(i0 + a) * W + (j0 + b)], v);
+                    }
                 }
             }
         }
