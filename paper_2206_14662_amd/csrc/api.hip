@@ -37,6 +37,7 @@ struct Inst {
     bool has_ins = false;
     InsHost ih;
     InsDev idev;              // device pointers of the corrected solve
+    int h_owner = -1;         // an earlier instance with the same corrected system: its H is used
     long long* Qw = nullptr;
     // cubic shapes
     long long* Qx = nullptr;
@@ -63,6 +64,9 @@ struct pic_ctx {
     int max_m = 0;
     InsDev* dIns = nullptr;
     DevInst* dIins = nullptr;     // DevInst of the insert instances, in ins_list order
+    int n_grp = 0;                // groups of insert instances sharing one H
+    std::vector<int> h_goff, h_gmem;
+    int *dGoff = nullptr, *dGmem = nullptr;  // group g: dIns entries dGmem[dGoff[g] .. dGoff[g+1])
     FieldDev *dF1 = nullptr, *dF1v = nullptr;   // first solve (step / vacuum): phi -> ybuf
     FieldDev *dF2 = nullptr, *dF2v = nullptr;   // second solve, insert instances only
     // cubic shapes (every instance of the context)
@@ -562,6 +566,28 @@ static pic_status upload_tables(pic_ctx* ctx) {
         CK(hipMemcpyAsync(ctx->dF2, F2.data(), sizeof(FieldDev) * F2.size(), hipMemcpyHostToDevice, s));
         CK(hipMemcpyAsync(ctx->dF2v, F2v.data(), sizeof(FieldDev) * F2v.size(), hipMemcpyHostToDevice, s));
         CK(hipMemcpyAsync(ctx->dIns, D.data(), sizeof(InsDev) * D.size(), hipMemcpyHostToDevice, s));
+        // groups of insert instances by their H (shared between equal corrected systems)
+        std::vector<const double*> hs;
+        std::vector<std::vector<int>> mem;
+        for (size_t t = 0; t < D.size(); ++t) {
+            size_t g = std::find(hs.begin(), hs.end(), D[t].H) - hs.begin();
+            if (g == hs.size()) {
+                hs.push_back(D[t].H);
+                mem.emplace_back();
+            }
+            mem[g].push_back((int)t);
+        }
+        ctx->h_goff.assign(1, 0);
+        ctx->h_gmem.clear();
+        for (auto& v : mem) {
+            ctx->h_gmem.insert(ctx->h_gmem.end(), v.begin(), v.end());
+            ctx->h_goff.push_back((int)ctx->h_gmem.size());
+        }
+        ctx->n_grp = (int)mem.size();
+        CK(hipMemcpyAsync(ctx->dGoff, ctx->h_goff.data(), sizeof(int) * ctx->h_goff.size(), hipMemcpyHostToDevice,
+                          s));
+        CK(hipMemcpyAsync(ctx->dGmem, ctx->h_gmem.data(), sizeof(int) * ctx->h_gmem.size(), hipMemcpyHostToDevice,
+                          s));
         pic_status st = upload_insert_inst(ctx);
         if (st != PIC_OK) return st;
     }
@@ -586,7 +612,8 @@ static pic_status solve_tables(pic_ctx* ctx, bool vac, bool from_q, bool edges, 
     if (from_q) CK(launch_ins_rhs(ctx->dI, ctx->dIns, ni, ctx->max_nodes, ctx->dF, ctx->dbscale, s));
     CK(launch_solve_tab(ctx->dI, f1, 0, n, ctx->max_nr, ctx->max_nz, ctx->tw, ctx->tw_n, from_q ? 0 : 1,
                         ctx->dbscale, edges, s));
-    CK(launch_ins_correct(ctx->dI, ctx->dIns, ni, ctx->max_m, ctx->max_nodes, f1, s));
+    CK(launch_ins_correct(ctx->dI, ctx->dIns, ni, ctx->dGoff, ctx->dGmem, ctx->n_grp, ctx->max_m, ctx->max_nodes,
+                          f1, s));
     CK(launch_solve_tab(ctx->dIins, f2, 0, ni, ctx->max_nr, ctx->max_nz, ctx->tw, ctx->tw_n, 1, ctx->dbscale,
                         edges, s));
     CK(launch_ins_fix(ctx->dI, ctx->dIns, ni, ctx->max_m, fin, s));
@@ -702,7 +729,17 @@ static T* upload_vec(pic_ctx* ctx, const std::vector<T>& v, hipStream_t s, bool&
     return p;
 }
 
-// Device arrays of an instance's insert (H is filled by setup_insert).
+// Whether two insert instances have the same corrected system (mesh, end
+// conditions, node set M and correction entries D), so that one H serves both.
+static bool same_insert_system(const Inst& x, const Inst& y) {
+    const pic_instance_cfg &a = x.c, &b = y.c;
+    return a.nr == b.nr && a.nz == b.nz && a.a == b.a && a.b == b.b && a.L == b.L && a.end_mode == b.end_mode &&
+           x.ih.m == y.ih.m && x.ih.Mnode == y.ih.Mnode && x.ih.Dr == y.ih.Dr && x.ih.Dc == y.ih.Dc &&
+           x.ih.Dv == y.ih.Dv;
+}
+
+// Device arrays of an instance's insert.  H is filled by setup_insert, or is
+// that of an earlier instance with the same corrected system.
 static pic_status init_insert_storage(pic_ctx* ctx, Inst& in) {
     const InsHost& h = in.ih;
     InsDev& D = in.idev;
@@ -720,7 +757,15 @@ static pic_status init_insert_storage(pic_ctx* ctx, Inst& in) {
     D.wn = upload_vec(ctx, h.wn, s, ok);
     D.ek = upload_vec(ctx, h.ek, s, ok);
     D.ef = upload_vec(ctx, h.ef, s, ok);
-    double* H = dalloc<double>(ctx, m * m);
+    in.h_owner = -1;
+    for (size_t k = 0; k < ctx->in.size() && &ctx->in[k] != &in; ++k) {
+        const Inst& o = ctx->in[k];
+        if (o.has_ins && o.h_owner < 0 && o.idev.H && same_insert_system(o, in)) {
+            in.h_owner = (int)k;
+            break;
+        }
+    }
+    double* H = in.h_owner >= 0 ? const_cast<double*>(ctx->in[in.h_owner].idev.H) : dalloc<double>(ctx, m * m);
     D.H = H;
     D.ybuf = dalloc<double>(ctx, N);
     D.rhs2 = dalloc<double>(ctx, N);
@@ -730,7 +775,7 @@ static pic_status init_insert_storage(pic_ctx* ctx, Inst& in) {
     in.Qw = dalloc<long long>(ctx, N);
     if (!ok || !H || !D.ybuf || !D.rhs2 || !D.yM || !D.sM || !D.val || !in.Qw)
         return fail(ctx, PIC_ENOMEM, "device allocation of the insert arrays failed");
-    CK(hipMemsetAsync(H, 0, sizeof(double) * m * m, s));
+    if (in.h_owner < 0) CK(hipMemsetAsync(H, 0, sizeof(double) * m * m, s));
     CK(hipMemsetAsync(D.ybuf, 0, sizeof(double) * N, s));
     CK(hipMemsetAsync(D.rhs2, 0, sizeof(double) * N, s));
     CK(hipMemsetAsync(in.Qw, 0, sizeof(long long) * N, s));
@@ -743,7 +788,7 @@ static pic_status init_insert_storage(pic_ctx* ctx, Inst& in) {
 // device.
 static pic_status setup_insert(pic_ctx* ctx, Inst& in) {
     const int m = in.ih.m;
-    if (m == 0) return PIC_OK;
+    if (m == 0 || in.h_owner >= 0) return PIC_OK;
     hipStream_t s = ctx->stream;
     const long long N = in.nodes;
     const int B = std::min(64, m);
@@ -1024,7 +1069,10 @@ extern "C" pic_status pic_init(const pic_run_cfg* run, const pic_instance_cfg* i
             ctx->dF1v = dalloc<FieldDev>(ctx, n);
             ctx->dF2 = dalloc<FieldDev>(ctx, ni);
             ctx->dF2v = dalloc<FieldDev>(ctx, ni);
-            if (!ctx->dIns || !ctx->dIins || !ctx->dF1 || !ctx->dF1v || !ctx->dF2 || !ctx->dF2v)
+            ctx->dGoff = dalloc<int>(ctx, ni + 1);
+            ctx->dGmem = dalloc<int>(ctx, ni);
+            if (!ctx->dIns || !ctx->dIins || !ctx->dF1 || !ctx->dF1v || !ctx->dF2 || !ctx->dF2v || !ctx->dGoff ||
+                !ctx->dGmem)
                 st = fail(ctx, PIC_ENOMEM, "device allocation of insert tables failed");
         }
         if (st == PIC_OK && ctx->s3) {

@@ -358,10 +358,12 @@ __device__ __forceinline__ unsigned int wave_aggregate(bool act, int key, F&& ad
 constexpr int kLQ = 512;
 
 // chunk-level event counters kept in LDS and their device counter slots
-enum { SC_ABS_N = 0, SC_ABS_W = 4, SC_DEAD = 8, SC_CAND = 9, SC_CAP = 10, SC_FAR = 11, SC_N = 12 };
-__constant__ int kCounterOf[SC_N] = {C_ABS_N,     C_ABS_N + 1, C_ABS_N + 2, C_ABS_N + 3, C_ABS_W, C_ABS_W + 1,
-                                     C_ABS_W + 2, C_ABS_W + 3, C_DEAD,      C_CAND,      C_CAPOVER,
-                                     C_FARDEP};
+enum {
+    SC_ABS_N = 0, SC_ABS_W = 4, SC_DEAD = 8, SC_CAND = 9, SC_CAP = 10, SC_FAR = 11, SC_EL = 12, SC_IZ = 13, SC_N = 14
+};
+__constant__ int kCounterOf[SC_N] = {C_ABS_N,     C_ABS_N + 1, C_ABS_N + 2, C_ABS_N + 3, C_ABS_W,   C_ABS_W + 1,
+                                     C_ABS_W + 2, C_ABS_W + 3, C_DEAD,      C_CAND,      C_CAPOVER, C_FARDEP,
+                                     C_ELASTIC,   C_IONIZ};
 
 
 // Everything the particle loop needs about the current chunk.
@@ -488,7 +490,9 @@ __device__ __forceinline__ void push_particle(const KArgs& A, const ChunkCtx& X,
             // straight to the device
             atomicAdd(&X.s_ctr[SC_CAND], 1ull);
             float sp, en;
-            if (event_kind_f(A.It[X.inst], b0.z, vrn, vtn, vz, sp, en) != 0) {
+            const int kind = event_kind_f(A.It[X.inst], b0.z, vrn, vtn, vz, sp, en);
+            if (kind != 0) {
+                atomicAdd(&X.s_ctr[kind == 1 ? SC_EL : SC_IZ], 1ull);
                 const unsigned int qr = atomicAdd(X.s_qn, 1u);
                 const unsigned long long e = ((unsigned long long)X.inst << 40) | (unsigned long long)dst;
                 if (qr < (unsigned int)kLQ) {
@@ -776,24 +780,29 @@ __global__ void __launch_bounds__(kPWG) __attribute__((amdgpu_waves_per_eu(8, 8)
     }
 }
 
-// Resolve the null-collision candidates queued by the particle kernel:
-// elastic or ionising event or null (FP32), the parent's new velocity, a new
-// electron appended after the instance's slots, deposited at the parent's
-// position and counted for the next sort.
+// Resolve the collision events queued by the particle kernel (which took
+// the null-or-real decision and counted the events): the parent's new
+// velocity (FP32) and, for an ionisation, a new electron appended after the
+// instance's slots, deposited at the parent's position and counted for the
+// next sort.  The new electrons' slots are reserved per workgroup pass and
+// instance: LDS ranks, then one device atomic per instance present.
 __global__ void __launch_bounds__(kWG) k_collide(KArgs A, PSet P, int scatter) {
+    extern __shared__ unsigned int s_coll[];
+    unsigned int* s_niz = s_coll;             // [n_inst] ionisations in this pass
+    unsigned int* s_base = s_coll + A.n_inst;  // [n_inst] their first spawn rank
     const long long nq = min(A.ctl[CTL_QCOUNT], A.qcap);
-    // the loop is uniform per workgroup so that each wave's event counts and
-    // new-electron slots take one atomic per instance present in the wave
     for (long long b0q = (long long)blockIdx.x * kWG; b0q < nq; b0q += (long long)gridDim.x * kWG) {
+        for (int k = threadIdx.x; k < A.n_inst; k += kWG) s_niz[k] = 0u;
+        __syncthreads();
         const long long qi = b0q + threadIdx.x;
         int inst = 0, ev = 0;
-        long long p = 0;
+        unsigned int local = 0u;
         float r = 0.0f, z = 0.0f, w = 0.0f, cvr = 0.0f, cvt = 0.0f, cvz = 0.0f;
         unsigned long long ckey = 0ull;
         if (qi < nq) {
             const unsigned long long e = A.queue[qi];
             inst = (int)(e >> 40);
-            p = (long long)(e & ((1ull << 40) - 1ull));
+            const long long p = (long long)(e & ((1ull << 40) - 1ull));
             const DevInst& I = A.It[inst];
             const unsigned int step = (unsigned int)A.cnt[(long long)inst * C_NCOUNT + C_STEP];
             const unsigned long long key = P.key[p];
@@ -808,20 +817,20 @@ __global__ void __launch_bounds__(kWG) k_collide(KArgs A, PSet P, int scatter) {
                 P.vt[p] = vt;
                 P.vz[p] = vz;
             }
+            if (ev == 2) local = atomicAdd(&s_niz[inst], 1u);
         }
-        wave_aggregate<false>(ev == 1, inst, [&](int k, unsigned int n) {
-            atomicAdd((unsigned long long*)&A.cnt[(long long)k * C_NCOUNT + C_ELASTIC], (unsigned long long)n);
-            return 0u;
-        });
-        const unsigned int rank = wave_aggregate<true>(ev == 2, inst, [&](int k, unsigned int n) {
-            long long* c = A.cnt + (long long)k * C_NCOUNT;
-            atomicAdd((unsigned long long*)&c[C_IONIZ], (unsigned long long)n);
-            return (unsigned int)atomicAdd((unsigned long long*)&c[C_SPAWN], (unsigned long long)n);
-        });
+        __syncthreads();
+        for (int k = threadIdx.x; k < A.n_inst; k += kWG) {
+            const unsigned int n = s_niz[k];
+            if (n)
+                s_base[k] = (unsigned int)atomicAdd((unsigned long long*)&A.cnt[(long long)k * C_NCOUNT + C_SPAWN],
+                                                    (unsigned long long)n);
+        }
+        __syncthreads();
         if (ev != 2) continue;
         const DevInst& I = A.It[inst];
         long long* cnt = A.cnt + (long long)inst * C_NCOUNT;
-        const long long rel = (scatter ? A.new_base[inst] : cnt[C_SLOTS]) + (long long)rank;
+        const long long rel = (scatter ? A.new_base[inst] : cnt[C_SLOTS]) + (long long)(s_base[inst] + local);
         if (rel >= I.p_cap) {
             atomicAdd((unsigned long long*)&cnt[C_DROPPED], 1ull);
             continue;
@@ -1484,8 +1493,8 @@ static pic_status launch_step(pic_ctx* ctx, F32State* S, hipStream_t s, bool tim
     hipLaunchKernelGGL(particle_kernel((mode & 3) | (S->ins ? 4 : 0)), grid, dim3(kPWG), lds, s, A);
     CK32(hipGetLastError());
     if (timed) CK32(hipEventRecord(e1, s));
-    hipLaunchKernelGGL(k_collide, dim3(S->coll_grid), dim3(kWG), 0, s, A, (mode & 2) ? S->set[1 - S->cur] : S->set[S->cur],
-                       (mode & 2) ? 1 : 0);
+    hipLaunchKernelGGL(k_collide, dim3(S->coll_grid), dim3(kWG), sizeof(unsigned int) * 2 * (size_t)n, s, A,
+                       (mode & 2) ? S->set[1 - S->cur] : S->set[S->cur], (mode & 2) ? 1 : 0);
     CK32(hipGetLastError());
     double src_max = 0.0;
     for (int k = 0; k < n; ++k) src_max = std::max(src_max, pic_inst_dev(ctx, k).src_rate);

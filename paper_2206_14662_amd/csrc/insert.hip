@@ -414,17 +414,82 @@ __global__ void ki_gather(const DevInst* It, const InsDev* Dt, const FieldDev* F
     }
 }
 
-// s = H y_M: one wave per row, lanes over the columns (fixed summation order)
-__global__ void __launch_bounds__(256) ki_matvec(const DevInst* It, const InsDev* Dt) {
-    const InsDev& D = Dt[blockIdx.y];
-    if (It[D.inst].frozen) return;
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    for (int a = blockIdx.x * 4 + wv; a < D.m; a += gridDim.x * 4) {
-        const double* row = D.H + (size_t)a * D.m;
-        double s = 0.0;
-        for (int b = lane; b < D.m; b += 64) s += row[b] * D.yM[b];
-        for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
-        if (lane == 0) D.sM[a] = s;
+// s = H y_M for NC instances sharing H, rows a0 .. a0 + kRows - 1: the
+// workgroup's 256 threads over the columns, each column's y values loaded
+// once for all the rows, then the four waves' sums added in a fixed order.
+// Every (row, instance) sum has the same order for any NC.
+// (The operands are read through global-address-space pointers: generic
+// pointers taken from a table make every load wait for the previous one.)
+typedef __attribute__((address_space(1))) const double gbl_f64;
+constexpr int kGrp = 8, kRows = 4;
+
+template <int NC>
+__device__ __forceinline__ void matvec_rows(const DevInst* It, const InsDev* Dt, const int* mem, gbl_f64* H, int m,
+                                            int a0, double (*s_part)[kRows][kGrp]) {
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    gbl_f64* y[NC];
+    gbl_f64* row[kRows];
+    double s[kRows][NC];
+#pragma unroll
+    for (int t = 0; t < NC; ++t) y[t] = (gbl_f64*)Dt[mem[t]].yM;
+#pragma unroll
+    for (int r = 0; r < kRows; ++r) {
+        row[r] = H + (size_t)min(a0 + r, m - 1) * m;
+#pragma unroll
+        for (int t = 0; t < NC; ++t) s[r][t] = 0.0;
+    }
+    for (int b = tid; b < m; b += 256) {
+        double yv[NC], h[kRows];
+#pragma unroll
+        for (int t = 0; t < NC; ++t) yv[t] = y[t][b];
+#pragma unroll
+        for (int r = 0; r < kRows; ++r) h[r] = row[r][b];
+#pragma unroll
+        for (int r = 0; r < kRows; ++r)
+#pragma unroll
+            for (int t = 0; t < NC; ++t) s[r][t] += h[r] * yv[t];
+    }
+#pragma unroll
+    for (int r = 0; r < kRows; ++r)
+#pragma unroll
+        for (int t = 0; t < NC; ++t) {
+            double v = s[r][t];
+            for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+            if (lane == 0) s_part[wv][r][t] = v;
+        }
+    __syncthreads();
+    if (tid < kRows * NC) {
+        const int r = tid / NC, t = tid - r * NC;
+        const double v = ((s_part[0][r][t] + s_part[1][r][t]) + s_part[2][r][t]) + s_part[3][r][t];
+        const InsDev& D = Dt[mem[t]];
+        if (a0 + r < m && !It[D.inst].frozen) D.sM[a0 + r] = v;
+    }
+    __syncthreads();
+}
+
+// s = H y_M for every instance of a group sharing H (blockIdx.y): kRows rows
+// per workgroup pass; each row is read once for up to kGrp instances.
+__global__ void __launch_bounds__(256) ki_matvec(const DevInst* It, const InsDev* Dt, const int* goff,
+                                                 const int* gmem) {
+    __shared__ double s_part[4][kRows][kGrp];
+    const int g0 = goff[blockIdx.y], g1 = goff[blockIdx.y + 1];
+    const InsDev& D0 = Dt[gmem[g0]];
+    const int m = D0.m;
+    gbl_f64* H = (gbl_f64*)D0.H;
+    for (int a0 = blockIdx.x * kRows; a0 < m; a0 += gridDim.x * kRows) {
+        for (int c0 = g0; c0 < g1; c0 += kGrp) {
+            const int* mem = gmem + c0;
+            switch (min(kGrp, g1 - c0)) {
+                case 1: matvec_rows<1>(It, Dt, mem, H, m, a0, s_part); break;
+                case 2: matvec_rows<2>(It, Dt, mem, H, m, a0, s_part); break;
+                case 3: matvec_rows<3>(It, Dt, mem, H, m, a0, s_part); break;
+                case 4: matvec_rows<4>(It, Dt, mem, H, m, a0, s_part); break;
+                case 5: matvec_rows<5>(It, Dt, mem, H, m, a0, s_part); break;
+                case 6: matvec_rows<6>(It, Dt, mem, H, m, a0, s_part); break;
+                case 7: matvec_rows<7>(It, Dt, mem, H, m, a0, s_part); break;
+                default: matvec_rows<8>(It, Dt, mem, H, m, a0, s_part); break;
+            }
+        }
     }
 }
 
@@ -557,14 +622,14 @@ hipError_t launch_ins_rhs(const DevInst* It, const InsDev* D, int n_ins, long lo
     return hipGetLastError();
 }
 
-hipError_t launch_ins_correct(const DevInst* It, const InsDev* D, int n_ins, int max_m, long long max_nodes,
-                              const FieldDev* Fbase, hipStream_t s) {
+hipError_t launch_ins_correct(const DevInst* It, const InsDev* D, int n_ins, const int* goff, const int* gmem,
+                              int n_grp, int max_m, long long max_nodes, const FieldDev* Fbase, hipStream_t s) {
     if (n_ins <= 0) return hipSuccess;
     hipLaunchKernelGGL(ki_gather, dim3(blocks_for(max_m), n_ins), dim3(256), 0, s, It, D, Fbase);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(ki_matvec, dim3((unsigned)std::max(1, std::min((max_m + 3) / 4, 2048)), n_ins), dim3(256),
-                       0, s, It, D);
+    hipLaunchKernelGGL(ki_matvec, dim3((unsigned)std::max(1, std::min((max_m + 3) / 4, 4096)), n_grp), dim3(256), 0,
+                       s, It, D, goff, gmem);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(ki_scatter, dim3(blocks_for(max_nodes), n_ins), dim3(256), 0, s, It, D);
     return hipGetLastError();

@@ -398,9 +398,10 @@ hipError_t launch_solve3_tab(const DevInst* It, const FieldDev* Ft, const FieldD
 // from Q and Qw (scaled by bscale) into rhs
 hipError_t launch_ins_rhs(const DevInst* It, const InsDev* D, int n_ins, long long max_nodes, const FieldDev* Ft,
                           const double* bscale, hipStream_t s);
-// y_M = ybuf - base at M, s = H y_M, rhs2 = -E s (every node written)
-hipError_t launch_ins_correct(const DevInst* It, const InsDev* D, int n_ins, int max_m, long long max_nodes,
-                              const FieldDev* Fbase, hipStream_t s);
+// y_M = ybuf - base at M, s = H y_M, rhs2 = -E s (every node written); the
+// instances sharing one H form the n_grp groups goff / gmem (entries of D)
+hipError_t launch_ins_correct(const DevInst* It, const InsDev* D, int n_ins, const int* goff, const int* gmem,
+                              int n_grp, int max_m, long long max_nodes, const FieldDev* Fbase, hipStream_t s);
 // the basis evaluated at the nodes of M: phi = base + (w c | w ext c | 0)
 hipError_t launch_ins_fix(const DevInst* It, const InsDev* D, int n_ins, int max_m, const FieldDev* Fout,
                           hipStream_t s);

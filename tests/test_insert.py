@@ -330,3 +330,34 @@ def test_source_with_insert_matches_the_oracle(mode):
     tol = 1e-12 if mode == F64 else 2e-6
     np.testing.assert_allclose(gp["r"], op["r"], rtol=tol)
     g.close()
+
+
+@pytest.mark.gpu
+def test_batch_sharing_one_correction_matrix():
+    """Instances with the same mesh and insert share one corrected-system
+    matrix (one set-up, one read per row for all of them): every instance's
+    potential, vacuum and with charge, equals that of the instance run alone,
+    in a batch that also holds a different insert and a plain coax."""
+    cfgs = [pi.gun(n_init=0), pi.gun(n_init=0, V_inner=-20000.0, p_mbar=0.05),
+            ellipse(64, 128, 0), pi.gun(n_init=0, V_inner=-40000.0), pi.coax64(n_init=0)]
+    S = B.pic_auto_shift(max(c["weight"] for c in cfgs))
+    cfgs = [dict(c, fx_shift=S) for c in cfgs]
+    states = [pi.particle_state(c, 20000, seed=40 + k) for k, c in enumerate(cfgs)]
+    for k, c in enumerate(cfgs):
+        if c["ins_er"] > 0:
+            st = states[k]
+            gg = ((st["r"] - c["ins_r0"]) / c["ins_er"]) ** 2 + ((st["z"] - c["ins_z0"]) / c["ins_ez"]) ** 2 - 1
+            states[k] = {kk: v[gg > 0] for kk, v in st.items()}
+    g = B.Sim(cfgs, mode=F64, capacity_min=100000)
+    vac = [g.phi(k) for k in range(len(cfgs))]
+    for k in range(len(cfgs)):
+        g.set_particles(states[k], k)
+    full = [g.phi(k) for k in range(len(cfgs))]
+    g.close()
+    for k, c in enumerate(cfgs):
+        a = B.Sim([c], mode=F64, capacity_min=100000)
+        assert np.array_equal(a.phi(), vac[k]), k
+        a.set_particles(states[k])
+        assert np.array_equal(a.phi(), full[k]), k
+        a.close()
+    assert not np.array_equal(full[0], full[3])
