@@ -124,6 +124,20 @@ __device__ __forceinline__ void cell_of(const DevInst& I, float r, float z, int&
     fz = t - (float)j;
 }
 
+// The collision constants of an instance the event decision reads (FP32),
+// copied once per chunk in the particle kernel.
+struct EvConst {
+    float half_me_over_e, nsig_el, iz_I, lotz_aq, n_n, nu_prime;
+    int xs_n;
+};
+
+__device__ __forceinline__ EvConst ev_const(const DevInst& I) {
+    EvConst c;
+    c.half_me_over_e = I.half_me_over_e_f; c.nsig_el = I.nsig_el_f; c.iz_I = I.iz_I_f;
+    c.lotz_aq = I.lotz_aq_f; c.n_n = I.n_n_f; c.nu_prime = I.nu_prime_f; c.xs_n = I.xs_n;
+    return c;
+}
+
 // Per-chunk copy of the instance constants the particle loop reads, kept in
 // registers so stores to the particle arrays never force them to be reloaded.
 struct LocalInst {
@@ -132,6 +146,7 @@ struct LocalInst {
     int nr, nz, W, ntz, tile_off, collisions, has_ins;
     unsigned int seed_lo, seed_hi;
     unsigned long long null_k;
+    EvConst ev;
 };
 
 __device__ __forceinline__ float uniform_f(float x) {
@@ -158,6 +173,9 @@ __device__ __forceinline__ LocalInst local_inst(const DevInst& I) {
     const unsigned long long k = I.null_k;
     L.null_k = ((unsigned long long)(unsigned int)__builtin_amdgcn_readfirstlane((int)(k >> 32)) << 32) |
                (unsigned long long)(unsigned int)__builtin_amdgcn_readfirstlane((int)(unsigned int)k);
+    L.ev.half_me_over_e = uniform_f(I.half_me_over_e_f); L.ev.nsig_el = uniform_f(I.nsig_el_f);
+    L.ev.iz_I = uniform_f(I.iz_I_f); L.ev.lotz_aq = uniform_f(I.lotz_aq_f); L.ev.n_n = uniform_f(I.n_n_f);
+    L.ev.nu_prime = uniform_f(I.nu_prime_f); L.ev.xs_n = __builtin_amdgcn_readfirstlane(I.xs_n);
     return L;
 }
 
@@ -220,23 +238,23 @@ __device__ __forceinline__ void scatter_f(float ur, float ut, float uz, float co
 // nu_el + nu_iz.  Returns 0 null, 1 elastic, 2 ionisation, with the speed and
 // energy it used.  The particle kernel calls it to queue only real events;
 // the collision kernel calls it again on the same stored velocity, so both
-// take the same decision.
-__device__ __forceinline__ int event_kind_f(const DevInst& I, unsigned int bits, float vr, float vt, float vz,
-                                            float& v, float& E) {
+// take the same decision.  I supplies the cross-section tables only.
+__device__ __forceinline__ int event_kind_f(const EvConst& c, const DevInst& I, unsigned int bits, float vr,
+                                            float vt, float vz, float& v, float& E) {
     const float u_proc = u23(bits);
     const float v2 = (vr * vr + vt * vt) + vz * vz;
     v = sqrtf(v2);
-    E = v2 * I.half_me_over_e_f;
+    E = v2 * c.half_me_over_e;
     float nu_el, sig = 0.0f;
-    if (I.xs_n > 0) {
-        nu_el = (I.n_n_f * xs_interp(I.xs_n, I.xs_Ef, I.xs_elf, E)) * v;
-        if (E > I.iz_I_f) sig = xs_interp(I.xs_n, I.xs_Ef, I.xs_izf, E);
+    if (c.xs_n > 0) {
+        nu_el = (c.n_n * xs_interp(c.xs_n, I.xs_Ef, I.xs_elf, E)) * v;
+        if (E > c.iz_I) sig = xs_interp(c.xs_n, I.xs_Ef, I.xs_izf, E);
     } else {
-        nu_el = I.nsig_el_f * v;
-        if (E > I.iz_I_f) sig = (I.lotz_aq_f * logf(E / I.iz_I_f)) / (E * I.iz_I_f);
+        nu_el = c.nsig_el * v;
+        if (E > c.iz_I) sig = (c.lotz_aq * logf(E / c.iz_I)) / (E * c.iz_I);
     }
-    const float nu_iz = (I.n_n_f * sig) * v;
-    const float R = u_proc * I.nu_prime_f;
+    const float nu_iz = (c.n_n * sig) * v;
+    const float R = u_proc * c.nu_prime;
     if (R < nu_el) return 1;
     if (R < nu_el + nu_iz) return 2;
     return 0;
@@ -249,7 +267,7 @@ __device__ __forceinline__ int collide_f(const DevInst& I, unsigned long long ke
                                       float& vr, float& vt, float& vz, float& cvr, float& cvt, float& cvz,
                                       unsigned long long& ckey) {
     float v, E;
-    const int ev = event_kind_f(I, b0.z, vr, vt, vz, v, E);
+    const int ev = event_kind_f(ev_const(I), I, b0.z, vr, vt, vz, v, E);
     if (ev == 0) return 0;
     float inv_v = 1.0f / v;
     float ur = vr * inv_v, ut = vt * inv_v, uz = vz * inv_v;
@@ -490,7 +508,7 @@ __device__ __forceinline__ void push_particle(const KArgs& A, const ChunkCtx& X,
             // straight to the device
             atomicAdd(&X.s_ctr[SC_CAND], 1ull);
             float sp, en;
-            const int kind = event_kind_f(A.It[X.inst], b0.z, vrn, vtn, vz, sp, en);
+            const int kind = event_kind_f(L.ev, A.It[X.inst], b0.z, vrn, vtn, vz, sp, en);
             if (kind != 0) {
                 atomicAdd(&X.s_ctr[kind == 1 ? SC_EL : SC_IZ], 1ull);
                 const unsigned int qr = atomicAdd(X.s_qn, 1u);
@@ -533,7 +551,13 @@ __device__ __forceinline__ void push_particle(const KArgs& A, const ChunkCtx& X,
             gbl_add(&Qg[n00 + 1], (unsigned long long)q01);
             gbl_add(&Qg[n00 + L.W + 1], (unsigned long long)q11);
         }
-        if (INS && L.has_ins) deposit_qw(A.It[X.inst], X.Qw, w, rn, zn);
+        if (INS && L.has_ins) {
+            // the band test from the chunk's copy of the insert constants (the
+            // same arithmetic as ins_g_f): the instance table is read only in
+            // the band
+            const float gu = (rn - L.ins_r0) * L.ins_inv_er, gv = (zn - L.ins_z0) * L.ins_inv_ez;
+            if (fmaf(gu, gu, gv * gv) - 1.0f < L.ins_gam) deposit_qw(A.It[X.inst], X.Qw, w, rn, zn);
+        }
     }
     if (COUNT) {
         // survivors, by the tile of the new position: tiles next to the
