@@ -287,9 +287,9 @@ __global__ void __launch_bounds__(64 * kThomasSeg) kf_thomas(const DevInst* __re
 
 // The same partitioned solve with segments of at most R rows whose values
 // stay in registers between the sweeps: the right-hand side is read once and
-// the solution written once.  SPLIT = 1: one wave per segment, 64 modes per
-// block, kThomasSegReg segments; SPLIT = 2: each half wave takes a segment,
-// 32 modes per block, 2 kThomasSegReg segments (meshes up to twice as tall).
+// the solution written once.  With SPLIT = 2 (the form launched) each half
+// wave takes a segment: 32 modes per block and 2 kThomasSegReg segments;
+// SPLIT = 1 takes one segment per wave and 64 modes per block.
 template <int R, int SPLIT>
 __global__ void __launch_bounds__(64 * kThomasSegReg) kf_thomas_reg(const DevInst* __restrict__ It,
                                                                     const FieldDev* __restrict__ Ft,
@@ -637,17 +637,14 @@ hipError_t launch_solve_tab(const DevInst* It, const FieldDev* Ft, int inst_base
     if (e != hipSuccess) return e;
     dim3 gth((unsigned)((max_nz + 1 + 63) / 64), (unsigned)n_inst);  // up to nz + 1 modes
     const int nseg = thomas_segments(max_nr);
-    if (nseg == kThomasSegReg || nseg == 2 * kThomasSegReg) {
+    if (nseg == 2 * kThomasSegReg) {
         const int rows = (max_nr - 1 + nseg - 1) / nseg;
         const dim3 blk(64, kThomasSegReg);
-        if (nseg == 2 * kThomasSegReg) {
-            const dim3 g2((unsigned)((max_nz + 1 + 31) / 32), (unsigned)n_inst);
+        const dim3 g2((unsigned)((max_nz + 1 + 31) / 32), (unsigned)n_inst);
+        if (rows <= 8)
+            hipLaunchKernelGGL((kf_thomas_reg<8, 2>), g2, blk, 0, s, It, Ft, inst_base);
+        else
             hipLaunchKernelGGL((kf_thomas_reg<16, 2>), g2, blk, 0, s, It, Ft, inst_base);
-        } else if (rows <= 8) {
-            hipLaunchKernelGGL((kf_thomas_reg<8, 1>), gth, blk, 0, s, It, Ft, inst_base);
-        } else {
-            hipLaunchKernelGGL((kf_thomas_reg<16, 1>), gth, blk, 0, s, It, Ft, inst_base);
-        }
     } else {
         hipLaunchKernelGGL(kf_thomas, gth, dim3(64, kThomasSeg), 0, s, It, Ft, inst_base);
     }

@@ -283,16 +283,15 @@ hipError_t launch_compact64(const DevInst& I, P64 src, P64 dst, long long* cnt,
 
 // Field solve and diagnostics (k_field.hip), FP64.
 // The tridiagonal solve in r splits the interior rows into segments solved
-// concurrently: 16 register-held segments of at most kThomasRegRows rows, or
-// 32 such segments (two per wave) for meshes up to twice as tall, else
-// kThomasSeg segments streamed through memory.  Host factors and kernels take
-// the count from thomas_segments(largest nr of the context).
+// concurrently: 32 register-held segments (two per wave, 32 modes per
+// workgroup, so that a batch fills the chip) of at most kThomasRegRows rows,
+// else kThomasSeg segments streamed through memory.  Host factors and kernels
+// take the count from thomas_segments(largest nr of the context).
 constexpr int kThomasSeg = 8;
 constexpr int kThomasSegReg = 16;
 constexpr int kThomasRegRows = 16;
 inline int thomas_segments(int max_nr) {
     const int rows = max_nr - 1;
-    if ((rows + kThomasSegReg - 1) / kThomasSegReg <= kThomasRegRows) return kThomasSegReg;
     if ((rows + 2 * kThomasSegReg - 1) / (2 * kThomasSegReg) <= kThomasRegRows) return 2 * kThomasSegReg;
     return kThomasSeg;
 }
