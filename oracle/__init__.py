@@ -110,6 +110,8 @@ def lib():
         L.orc_load.restype = C.c_int
         L.orc_set_cross_sections.argtypes = [C.c_void_p, C.c_int, _D, _D, _D]
         L.orc_set_cross_sections.restype = C.c_int
+        L.orc_set_anisotropy.argtypes = [C.c_void_p, C.c_int, _D, _D]
+        L.orc_set_anisotropy.restype = C.c_int
         L.orc_get_charge3.argtypes = [C.c_void_p, _I64]
         L.orc_get_coef3.argtypes = [C.c_void_p, _D]
         L.orc_s3_weights.argtypes = [C.c_double, _D, _D]
@@ -445,6 +447,17 @@ class Sim:
             st = lib().orc_set_cross_sections(self.h, len(self._xs[0]), *[_dp(a) for a in self._xs])
         if st != 0:
             raise ValueError("cross-section table refused")
+
+    def set_anisotropy(self, E=None, xi=None):
+        """Tabulated anisotropy xi(E) of the scattering law at increasing
+        energies (eV); None returns to the constant okh_xi."""
+        if E is None:
+            st = lib().orc_set_anisotropy(self.h, 0, None, None)
+        else:
+            self._xi = [np.ascontiguousarray(a, dtype=np.float64) for a in (E, xi)]
+            st = lib().orc_set_anisotropy(self.h, len(self._xi[0]), *[_dp(a) for a in self._xi])
+        if st != 0:
+            raise ValueError("anisotropy table refused")
 
     def derived(self):
         out = OrcDerived()

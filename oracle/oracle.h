@@ -184,6 +184,10 @@ void     orc_set_step(orc_sim* s, int64_t step);
  * constant elastic and Lotz ionisation cross sections.  The null-collision
  * bound becomes n_n max (sigma_el + sigma_iz) v over 0 <= E <= E_cap. */
 int      orc_set_cross_sections(orc_sim* s, int n, const double* E, const double* el, const double* iz);
+/* xi(E) of the Okhrimovskyy scattering law at n increasing energies (eV),
+ * linear in E and held at the ends; n = 0 returns to the constant okh_xi.
+ * Returns -1 for a refused table (n, order, xi outside (-1, 1)). */
+int      orc_set_anisotropy(orc_sim* s, int n, const double* E, const double* xi);
 void     orc_sim_derived(const orc_sim* s, orc_derived* d);   /* the constants in use */
 int      orc_step(orc_sim* s, int n_steps);
 void     orc_get_charge(const orc_sim* s, int64_t* Q);

@@ -39,6 +39,8 @@ struct orc_sim {
     orc_s3* s3;                /* cubic shapes: factorised Galerkin system      */
     int xs_n;                  /* tabulated cross sections (0: constant / Lotz) */
     double *xs_E, *xs_el, *xs_iz;
+    int xi_n;                  /* tabulated anisotropy xi(E) (0: the constant okh_xi) */
+    double *xi_E, *xi_v;
     orc_ins* ins;              /* insert: factorised web-spline system          */
     double *phi_vac, *phi, *Er, *Ez, *Br, *Bz, *V, *avg_acc;
     int frozen;
@@ -186,7 +188,16 @@ static inline void philox_blk(const orc_sim* s, uint64_t key, uint32_t step, uin
     orc_philox4x32_10(ctr, k, o);
 }
 
-/* event: 0 none, 1 elastic, 2 ionisation (child filled), 3 candidate rejected */
+/* Anisotropy of the scattering of an electron of energy E (eV): the table
+ * xi(E), linear in E and held at its ends, else the constant okh_xi. */
+static inline double xi_at(const orc_sim* s, double E) {
+    return s->xi_n > 0 ? orc_xs_at(s->xi_n, s->xi_E, s->xi_v, E) : s->c.okh_xi;
+}
+
+/* event: 0 none, 1 elastic, 2 ionisation (child filled), 3 candidate rejected.
+ * The elastically scattered electron takes xi at its incoming energy; after
+ * an ionisation the primary and the freed electron are scattered with xi at
+ * their own energies after the split. */
 static inline int mcc_one(const orc_sim* s, int64_t p, orc_part* child) {
     const orc_cfg* c = &s->c;
     const orc_derived* d = &s->d;
@@ -217,10 +228,10 @@ static inline int mcc_one(const orc_sim* s, int64_t p, orc_part* child) {
     double ur = vr / v, ut = vt / v, uz = vz / v;
     uint32_t b1[4];
     philox_blk(s, s->key[p], step, 1u, b1);
-    double cos1 = orc_okh_cos(c->okh_xi, orc_u52(b1[0], b1[1]));
     double phi1 = (2.0 * M_PI) * orc_u52(b1[2], b1[3]);
     double dir[3];
     if (ev == 1) {
+        double cos1 = orc_okh_cos(xi_at(s, E), orc_u52(b1[0], b1[1]));
         double En = E * (1.0 - d->mass_ratio2 * (1.0 - cos1));
         double vn = sqrt(En * d->two_e_over_me);
         orc_scatter(ur, ut, uz, cos1, phi1, dir);
@@ -233,7 +244,8 @@ static inline int mcc_one(const orc_sim* s, int64_t p, orc_part* child) {
     double E_av = E - c->iz_I_eV;
     double E_s = orc_opal_split(c->opal_Ebar_eV, E_av, orc_u52(b2[0], b2[1]));
     double E_p = E_av - E_s;
-    double cos2 = orc_okh_cos(c->okh_xi, orc_u52(b2[2], b2[3]));
+    double cos1 = orc_okh_cos(xi_at(s, E_p), orc_u52(b1[0], b1[1]));
+    double cos2 = orc_okh_cos(xi_at(s, E_s), orc_u52(b2[2], b2[3]));
     double phi2 = (2.0 * M_PI) * orc_u52(b3[0], b3[1]);
     double vp = sqrt(E_p * d->two_e_over_me);
     double vs = sqrt(E_s * d->two_e_over_me);
@@ -360,6 +372,7 @@ void orc_destroy(orc_sim* s) {
     free(s->Qx); free(s->cx);
     orc_s3_destroy(s->s3);
     free(s->xs_E); free(s->xs_el); free(s->xs_iz);
+    free(s->xi_E); free(s->xi_v);
     orc_ins_destroy(s->ins);
     free(s);
 }
@@ -484,6 +497,23 @@ int orc_set_cross_sections(orc_sim* s, int n, const double* E, const double* el,
     /* the bound, widened by 2^-20 against rounding */
     s->d.nu_prime = (s->d.n_n * orc_xs_sigv_max(&s->c, n, E, el, iz)) * (1.0 + 0x1p-20);
     s->d.P_null = -expm1(-(s->d.nu_prime * s->c.dt));
+    return 0;
+}
+
+int orc_set_anisotropy(orc_sim* s, int n, const double* E, const double* xi) {
+    if (n != 0 && (n < 2 || n > 4096)) return -1;
+    for (int k = 0; k < n; ++k) {
+        if (!(E[k] >= 0.0) || !(xi[k] > -1.0 && xi[k] < 1.0)) return -1;
+        if (k > 0 && !(E[k] > E[k - 1])) return -1;
+    }
+    free(s->xi_E); free(s->xi_v);
+    s->xi_E = s->xi_v = NULL;
+    s->xi_n = n;
+    if (n == 0) return 0;
+    s->xi_E = (double*)malloc(sizeof(double) * n);
+    s->xi_v = (double*)malloc(sizeof(double) * n);
+    memcpy(s->xi_E, E, sizeof(double) * n);
+    memcpy(s->xi_v, xi, sizeof(double) * n);
     return 0;
 }
 
