@@ -264,6 +264,18 @@ pic_status pic_get_charge(pic_ctx* ctx, int inst, long long* Q);
 pic_status pic_set_cross_sections(pic_ctx* ctx, int inst, int n, const double* E_eV, const double* sigma_el,
                                   const double* sigma_iz);
 
+/* pic_set_anisotropy -- energy-dependent anisotropy of the scattering law
+ * for instance `inst` (Sec. II.A: the scattering angle follows the analytic
+ * differential cross section of Okhrimovskyy et al., whose parameter xi
+ * depends on the electron's energy): n >= 2 strictly increasing energies
+ * E_eV (eV) with xi in (-1, 1), linear in E between the points and held
+ * outside.  An elastically scattered electron takes xi at its incoming
+ * energy; after an ionisation the primary and the freed electron take xi at
+ * their own energies after the split.  n = 0 returns to the constant okh_xi.
+ * The arrays are copied (host pointers); at most 4096 points; PIC_EINVAL for
+ * a bad table.  Call between steps. */
+pic_status pic_set_anisotropy(pic_ctx* ctx, int inst, int n, const double* E_eV, const double* xi);
+
 /* pic_get_band_charge -- with the elliptic insert (Sec. II.A web-splines):
  * copy the fixed-point node charges of q (w(x_p) - 1) that the particles
  * inside the weight function's band deposit next to Q (node array, units

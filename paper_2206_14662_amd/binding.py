@@ -91,7 +91,7 @@ EXPORTS = ("pic_init", "pic_step", "pic_diag", "pic_destroy", "pic_last_error", 
            "pic_get_charge", "pic_get_phi", "pic_set_step", "pic_derive", "pic_auto_shift",
            "pic_timing", "pic_tuning", "pic_retune", "pic_autotune", "pic_reserve", "pic_capacity",
            "pic_moments", "pic_well_depth", "pic_get_band_charge", "pic_insert_layout",
-           "pic_set_cross_sections", "pic_get_spline3")
+           "pic_set_cross_sections", "pic_get_spline3", "pic_set_anisotropy")
 
 _lib = None
 _D = C.POINTER(C.c_double)
@@ -145,6 +145,7 @@ def lib():
     L.pic_insert_layout.argtypes = [C.POINTER(pic_instance_cfg), _I, _I, _LL]
     L.pic_set_cross_sections.argtypes = [vp, C.c_int, C.c_int, _D, _D, _D]
     L.pic_get_spline3.argtypes = [vp, C.c_int, _LL, _D]
+    L.pic_set_anisotropy.argtypes = [vp, C.c_int, C.c_int, _D, _D]
     for name in EXPORTS:
         if name not in ("pic_last_error", "pic_auto_shift"):
             getattr(L, name).restype = C.c_int
@@ -346,6 +347,14 @@ def pic_set_cross_sections(ctx, inst, E=None, sigma_el=None, sigma_iz=None):
     _check(lib().pic_set_cross_sections(ctx, int(inst), len(a[0]), *[x.ctypes.data_as(_D) for x in a]), ctx)
 
 
+def pic_set_anisotropy(ctx, inst, E=None, xi=None):
+    if E is None:
+        _check(lib().pic_set_anisotropy(ctx, int(inst), 0, None, None), ctx)
+        return
+    a = [np.ascontiguousarray(x, dtype=np.float64) for x in (E, xi)]
+    _check(lib().pic_set_anisotropy(ctx, int(inst), len(a[0]), *[x.ctypes.data_as(_D) for x in a]), ctx)
+
+
 def pic_get_spline3(ctx, inst, nr, nz):
     n = (nr + 3) * (nz + 3)
     Qx = np.zeros(n, dtype=np.int64)
@@ -477,6 +486,9 @@ class Sim:
 
     def set_cross_sections(self, k=0, E=None, sigma_el=None, sigma_iz=None):
         pic_set_cross_sections(self.ctx, k, E, sigma_el, sigma_iz)
+
+    def set_anisotropy(self, k=0, E=None, xi=None):
+        pic_set_anisotropy(self.ctx, k, E, xi)
 
     def spline3(self, k=0):
         d = self.instances[k]

@@ -1613,6 +1613,43 @@ extern "C" pic_status pic_set_cross_sections(pic_ctx* ctx, int k, int n, const d
     return PIC_OK;
 }
 
+extern "C" pic_status pic_set_anisotropy(pic_ctx* ctx, int k, int n, const double* E_eV, const double* xi) {
+    pic_status st = check_inst(ctx, k);
+    if (st != PIC_OK) return st;
+    if (n != 0 && (n < 2 || n > 4096)) return fail(ctx, PIC_EINVAL, "need 2 <= n <= 4096 table points (or 0)");
+    if (n > 0 && (!E_eV || !xi)) return fail(ctx, PIC_EINVAL, "table arrays are NULL");
+    for (int t = 0; t < n; ++t) {
+        if (!(E_eV[t] >= 0.0)) return fail(ctx, PIC_EINVAL, "energies must be >= 0");
+        if (!(xi[t] > -1.0 && xi[t] < 1.0)) return fail(ctx, PIC_EINVAL, "xi must be in (-1, 1)");
+        if (t > 0 && !(E_eV[t] > E_eV[t - 1])) return fail(ctx, PIC_EINVAL, "energies must increase strictly");
+    }
+    CK(hipStreamSynchronize(ctx->stream));
+    DevInst& I = ctx->in[k].I;
+    const void* old[4] = {I.xi_E, I.xi_v, I.xi_Ef, I.xi_vf};
+    for (const void* p : old)
+        if (p) pic_dev_free(ctx, const_cast<void*>(p));
+    I.xi_n = 0;
+    I.xi_E = I.xi_v = nullptr;
+    I.xi_Ef = I.xi_vf = nullptr;
+    if (n > 0) {
+        bool ok = true;
+        std::vector<double> vE(E_eV, E_eV + n), vx(xi, xi + n);
+        std::vector<float> fE(n), fx(n);
+        for (int t = 0; t < n; ++t) {
+            fE[t] = (float)E_eV[t];
+            fx[t] = (float)xi[t];
+        }
+        I.xi_E = upload_vec(ctx, vE, ctx->stream, ok);
+        I.xi_v = upload_vec(ctx, vx, ctx->stream, ok);
+        I.xi_Ef = upload_vec(ctx, fE, ctx->stream, ok);
+        I.xi_vf = upload_vec(ctx, fx, ctx->stream, ok);
+        CK(hipStreamSynchronize(ctx->stream));
+        if (!ok) return fail(ctx, PIC_ENOMEM, "device allocation of the anisotropy table failed");
+        I.xi_n = n;
+    }
+    return pic_upload_inst(ctx);
+}
+
 extern "C" pic_status pic_insert_layout(const pic_instance_cfg* inst, int counts[4], int* m, long long* entries) {
     if (!inst) return fail(nullptr, PIC_EINVAL, "inst is NULL");
     std::string msg = validate(*inst);

@@ -209,6 +209,12 @@ __device__ __forceinline__ void flush_counter(long long* slot, unsigned long lon
     if (__lane_id() == 0) atomicAdd((unsigned long long*)slot, v);
 }
 
+// Anisotropy of the scattering law for an electron of energy E (eV), FP32:
+// the table xi(E) when the instance has one, else the constant okh_xi.
+__device__ __forceinline__ float xi_at_f(const DevInst& I, float E) {
+    return I.xi_n > 0 ? xs_interp(I.xi_n, I.xi_Ef, I.xi_vf, E) : I.okh_xi_f;
+}
+
 __device__ __forceinline__ float okh_cos_f(float xi, float u) {
     return ((2.0f * u + xi) - 1.0f) / ((1.0f - xi) + (2.0f * xi) * u);
 }
@@ -272,10 +278,10 @@ __device__ __forceinline__ int collide_f(const DevInst& I, unsigned long long ke
     float inv_v = 1.0f / v;
     float ur = vr * inv_v, ut = vt * inv_v, uz = vz * inv_v;
     uint4 b1 = philox_step(I, key, step, 1u);
-    float cos1 = okh_cos_f(I.okh_xi_f, u23(b1.x));
     float phi1 = 6.28318530717958648f * u23(b1.z);
     float dir[3];
     if (ev == 1) {
+        const float cos1 = okh_cos_f(xi_at_f(I, E), u23(b1.x));
         float En = E * (1.0f - I.mass_ratio2_f * (1.0f - cos1));
         float vn = sqrtf(En * I.two_e_over_me_f);
         scatter_f(ur, ut, uz, cos1, phi1, dir);
@@ -287,7 +293,8 @@ __device__ __forceinline__ int collide_f(const DevInst& I, unsigned long long ke
     float E_av = E - I.iz_I_f;
     float E_s = I.opal_Ebar_f * tanf(u23(b2.x) * atanf(E_av / (2.0f * I.opal_Ebar_f)));
     float E_p = E_av - E_s;
-    float cos2 = okh_cos_f(I.okh_xi_f, u23(b2.z));
+    const float cos1 = okh_cos_f(xi_at_f(I, E_p), u23(b1.x));
+    float cos2 = okh_cos_f(xi_at_f(I, E_s), u23(b2.z));
     float phi2 = 6.28318530717958648f * u23(b3.x);
     float vp = sqrtf(fmaxf(E_p, 0.0f) * I.two_e_over_me_f);
     float vs = sqrtf(fmaxf(E_s, 0.0f) * I.two_e_over_me_f);

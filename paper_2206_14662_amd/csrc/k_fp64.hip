@@ -172,6 +172,12 @@ __global__ void __launch_bounds__(kBlock) k_push64(DevInst I, P64 p, const doubl
     if (pushed) atomicAdd((unsigned long long*)&cnt[C_PSTEPS], pushed);
 }
 
+// Anisotropy of the scattering law for an electron of energy E (eV): the
+// table xi(E) when the instance has one, else the constant okh_xi.
+__device__ __forceinline__ double xi_at(const DevInst& I, double E) {
+    return I.xi_n > 0 ? xs_interp(I.xi_n, I.xi_E, I.xi_v, E) : I.okh_xi;
+}
+
 __device__ __forceinline__ double okh_cos(double xi, double u) {
     return ((2.0 * u + xi) - 1.0) / ((1.0 - xi) + (2.0 * xi) * u);
 }
@@ -233,10 +239,10 @@ __global__ void __launch_bounds__(kBlock) k_mcc64(DevInst I, P64 p, long long* c
         else continue;
         double ur = vr / v, ut = vt / v, uz = vz / v;
         uint4 b1 = blk(I, key, step, 1u);
-        double cos1 = okh_cos(I.okh_xi, u52(b1.x, b1.y));
         double phi1 = (2.0 * kPi) * u52(b1.z, b1.w);
         double dir[3];
         if (ev == 1) {
+            const double cos1 = okh_cos(xi_at(I, E), u52(b1.x, b1.y));
             ++n_el;
             double En = E * (1.0 - I.mass_ratio2 * (1.0 - cos1));
             double vn = sqrt(En * I.two_e_over_me);
@@ -252,7 +258,8 @@ __global__ void __launch_bounds__(kBlock) k_mcc64(DevInst I, P64 p, long long* c
         double E_av = E - I.iz_I;
         double E_s = I.opal_Ebar * tan(u52(b2.x, b2.y) * atan(E_av / (2.0 * I.opal_Ebar)));
         double E_p = E_av - E_s;
-        double cos2 = okh_cos(I.okh_xi, u52(b2.z, b2.w));
+        const double cos1 = okh_cos(xi_at(I, E_p), u52(b1.x, b1.y));
+        double cos2 = okh_cos(xi_at(I, E_s), u52(b2.z, b2.w));
         double phi2 = (2.0 * kPi) * u52(b3.x, b3.y);
         double vp = sqrt(E_p * I.two_e_over_me);
         double vs = sqrt(E_s * I.two_e_over_me);

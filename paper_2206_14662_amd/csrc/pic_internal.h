@@ -70,6 +70,10 @@ struct DevInst {
     int xs_n;
     const double *xs_E, *xs_el, *xs_iz;
     const float *xs_Ef, *xs_elf, *xs_izf;
+    // tabulated anisotropy xi(E) of the scattering law (xi_n = 0: okh_xi)
+    int xi_n;
+    const double *xi_E, *xi_v;
+    const float *xi_Ef, *xi_vf;
 };
 
 // Tabulated cross section at energy x: linear in E between the tabulated
