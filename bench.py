@@ -213,7 +213,7 @@ def main():
     ap.add_argument("--acc-p-mbar", type=float, default=None, help="pressure override of the accuracy workload")
     ap.add_argument("--acc-ref", default="gpu64", choices=("gpu64", "oracle"))
     ap.add_argument("--shapes", action="store_true",
-                    help="the plain FP64 form with cubic against bilinear shapes on the workload's instance 0")
+                    help="cubic against bilinear shapes in both forms on the workload's instance 0")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU layout is a "
@@ -240,19 +240,24 @@ def main():
     if args.shapes:
         c0 = (pi.batch8(n_per=int(16_000_000 * args.scale)) if args.workload == "batch8"
               else [getattr(pi, args.workload)(n_init=int(getattr(pi, args.workload)()["n_init"] * args.scale))])[0]
-        res = {}
-        for order in (1, 3):
-            c = dict(c0, spline_order=order)
-            r = measure(B, torch, [c], B.PIC_MODE_FP64_PLAIN, max(4, args.steps // 4), max(2, args.warmup // 4),
-                        False)["events"]
-            res[order] = {"particle_steps_per_s": r["ps"] / r["wall"], "ms_per_step": 1e3 * r["wall"] /
-                          max(4, args.steps // 4), "push_kernel_avg_ms": r["kern_ms"] / max(1, r["launches"])}
-        print(json.dumps({"metric": "particle-steps/s of the plain FP64 form, cubic vs bilinear shapes",
+        out = {}
+        for form, mode, graph in (("fp64_plain", B.PIC_MODE_FP64_PLAIN, False),
+                                  ("fp32_batched", B.PIC_MODE_FP32_BATCHED, True)):
+            steps = max(4, args.steps // 4) if not graph else args.steps
+            res = {}
+            for order in (1, 3):
+                c = dict(c0, spline_order=order)
+                m = measure(B, torch, [c], mode, steps, max(2, args.warmup // 4) if not graph else args.warmup, graph)
+                r, e = m["run"], m["events"]
+                res["bilinear" if order == 1 else "cubic"] = {
+                    "particle_steps_per_s": r["ps"] / r["wall"], "ms_per_step": 1e3 * r["wall"] / steps,
+                    "push_kernel_avg_ms": e["kern_ms"] / max(1, e["launches"])}
+            res["cubic_over_bilinear"] = res["cubic"]["particle_steps_per_s"] / res["bilinear"]["particle_steps_per_s"]
+            out[form] = res
+        print(json.dumps({"metric": "particle-steps/s with cubic against bilinear shapes, both forms",
                           "config": {"workload": args.workload, "instance": 0, "electrons": int(c0["n_init"]),
-                                     "mesh": [c0["nr"], c0["nz"]]},
-                          "bilinear": res[1], "cubic": res[3],
-                          "cubic_over_bilinear": res[3]["particle_steps_per_s"] / res[1]["particle_steps_per_s"]}),
-              flush=True)
+                                     "mesh": [c0["nr"], c0["nz"]], "fp32_tiles": "default (8x32, halo 8, sort 16)"},
+                          **out}), flush=True)
         return
     if args.accuracy:
         print(json.dumps({"metric": "fp32_vs_fp64_error", **accuracy(B, torch, args.accuracy, args.acc_steps,

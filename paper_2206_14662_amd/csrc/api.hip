@@ -42,6 +42,7 @@ struct Inst {
     // cubic shapes
     long long* Qx = nullptr;
     double *cx = nullptr, *cbuf = nullptr, *zeros = nullptr;
+    float* cxf = nullptr;     // FP32 copy of cx (batched form)
     double *s3_L1 = nullptr, *s3_L2 = nullptr, *s3_L3 = nullptr, *s3_Dinv = nullptr;
 };
 
@@ -524,6 +525,7 @@ static pic_status upload_tables(pic_ctx* ctx) {
         f.Qw = in.Qw;
         f.Qx = in.Qx;
         f.cx = in.cx;
+        f.cxf = in.cxf;
         F.push_back(f);
         FieldDev v = f;  // vacuum solve: boundary data in, phi_vac out
         v.phi_vac = in.phiB;
@@ -663,6 +665,7 @@ const pic_instance_cfg& pic_inst_cfg(pic_ctx* ctx, int k) { return ctx->in[k].c;
 long long* pic_counters(pic_ctx* ctx) { return ctx->dcnt; }
 long long* pic_inst_Q(pic_ctx* ctx, int k) { return ctx->in[k].Q; }
 long long* pic_inst_Qw(pic_ctx* ctx, int k) { return ctx->in[k].Qw; }
+long long* pic_inst_Qx(pic_ctx* ctx, int k) { return ctx->in[k].Qx; }
 float4* pic_inst_EB(pic_ctx* ctx, int k) { return ctx->in[k].EB; }
 DevInst* pic_dev_table(pic_ctx* ctx) { return ctx->dI; }
 long long& pic_inst_cap(pic_ctx* ctx, int k) { return ctx->in[k].cap; }
@@ -938,6 +941,11 @@ static pic_status init_instance_storage(pic_ctx* ctx, Inst& in) {
         in.s3_L2 = dalloc<double>(ctx, N);
         in.s3_L3 = dalloc<double>(ctx, N);
         in.s3_Dinv = dalloc<double>(ctx, N);
+        if (ctx->mode == PIC_MODE_FP32_BATCHED) {
+            in.cxf = dalloc<float>(ctx, X);
+            if (!in.cxf) return fail(ctx, PIC_ENOMEM, "device allocation of the cubic-shape arrays failed");
+            CK(hipMemsetAsync(in.cxf, 0, sizeof(float) * X, s));
+        }
         if (!in.Qx || !in.cx || !in.cbuf || !in.zeros || !in.s3_L1 || !in.s3_L2 || !in.s3_L3 || !in.s3_Dinv)
             return fail(ctx, PIC_ENOMEM, "device allocation of the cubic-shape arrays failed");
         std::vector<double> l1, l2, l3, di;
@@ -1048,8 +1056,6 @@ extern "C" pic_status pic_init(const pic_run_cfg* run, const pic_instance_cfg* i
             st = fail(ctx, PIC_EINVAL, "every instance of a context needs the same spline_order");
         ctx->max_ext = std::max<long long>(ctx->max_ext, (long long)(ctx->in[k].c.nr + 3) * (ctx->in[k].c.nz + 3));
     }
-    if (st == PIC_OK && ctx->s3 && ctx->mode != PIC_MODE_FP64_PLAIN)
-        st = fail(ctx, PIC_EINVAL, "cubic shapes (spline_order 3) run in PIC_MODE_FP64_PLAIN");
     if (st == PIC_OK) {
         ctx->dI = dalloc<DevInst>(ctx, n);
         ctx->dF = dalloc<FieldDev>(ctx, n);
@@ -1456,6 +1462,7 @@ extern "C" pic_status pic_set_fields(pic_ctx* ctx, int k, const double* Er, cons
     // cubic shapes: a frozen field is the given nodal one alone; back to the
     // self-consistent field, the nodal arrays hold the vacuum field again
     CK(hipMemsetAsync(in.cx, 0, sizeof(double) * (size_t)(in.c.nr + 3) * (in.c.nz + 3), ctx->stream));
+    if (in.cxf) CK(hipMemsetAsync(in.cxf, 0, sizeof(float) * (size_t)(in.c.nr + 3) * (in.c.nz + 3), ctx->stream));
     if (!in.frozen) {
         CK(launch_efield_tab(ctx->dI, ctx->dFvac, k, 1, in.nodes, false, ctx->stream));
         st = pic_solve_all(ctx);

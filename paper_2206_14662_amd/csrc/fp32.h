@@ -23,6 +23,7 @@ pic::DevInst* pic_dev_table(pic_ctx* ctx);
 // copies the host instance table (after p_off/p_cap/tile changes) to the device
 pic_status pic_upload_inst(pic_ctx* ctx);
 long long* pic_inst_Qw(pic_ctx* ctx, int k);
+long long* pic_inst_Qx(pic_ctx* ctx, int k);
 pic_status f32_rates_changed(pic_ctx* ctx);
 long long& pic_inst_cap(pic_ctx* ctx, int k);
 const pic_run_cfg& pic_run(pic_ctx* ctx);

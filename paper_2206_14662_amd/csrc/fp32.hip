@@ -54,6 +54,8 @@ constexpr int kPWG = 1024;
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef __attribute__((address_space(3))) v4f lds_float4;
 typedef __attribute__((address_space(3))) unsigned long long lds_u64;
+typedef __attribute__((address_space(3))) float lds_f32;
+typedef __attribute__((address_space(1))) const float gbl_f32;
 
 __device__ __forceinline__ void lds_add(lds_u64* p, unsigned long long v) {
     __atomic_fetch_add(p, v, __ATOMIC_RELAXED);
@@ -101,6 +103,7 @@ struct KArgs {
     unsigned long long* queue;     // collision candidates: (instance << 40) | slot
     long long qcap;
     int n_inst, n_tiles, TR, TZ, halo, C, win_max;
+    int win3_max;                  // ghosted cubic window nodes (even; 0 without cubic shapes)
 };
 
 // ---- shared device helpers ------------------------------------------------
@@ -391,6 +394,52 @@ __constant__ int kCounterOf[SC_N] = {C_ABS_N,     C_ABS_N + 1, C_ABS_N + 2, C_AB
                                      C_ELASTIC,   C_IONIZ};
 
 
+// Cubic B-spline weights of the nodes i-1 .. i+2 at offset f in [0, 1) from
+// i, and their derivatives in units of the cell (FP32).
+__device__ __forceinline__ void bspline3_f(float f, float w[4], float dw[4]) {
+    const float g = 1.0f - f;
+    w[0] = (g * g * g) / 6.0f;
+    w[1] = fmaf(fmaf(3.0f, f, -6.0f) * f, f, 4.0f) / 6.0f;
+    w[2] = fmaf(fmaf(fmaf(-3.0f, f, 3.0f), f, 3.0f), f, 1.0f) / 6.0f;
+    w[3] = (f * f * f) / 6.0f;
+    dw[0] = -(g * g) / 2.0f;
+    dw[1] = (fmaf(3.0f, f, -4.0f) * f) / 2.0f;
+    dw[2] = fmaf(fmaf(-3.0f, f, 2.0f), f, 1.0f) / 2.0f;
+    dw[3] = (f * f) / 2.0f;
+}
+
+// Fixed-point cubic charges of one particle whose cell is (i, j) with
+// offsets (fr, fz): the node (i-1+a, j-1+b) takes rint(W w_a w_b) for fifteen
+// nodes and the remainder for the last, so the particle adds exactly W.
+// add(a, b, q) receives them.
+template <typename F>
+__device__ __forceinline__ void cubic_charges(float w, float two_S, float fr, float fz, F&& add) {
+    float wr[4], dwr[4], wz[4], dwz[4];
+    bspline3_f(fr, wr, dwr);
+    bspline3_f(fz, wz, dwz);
+    const float Wf = rintf(w * two_S);
+    long long sum = 0;
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const long long q = (a == 3 && b == 3) ? (long long)(unsigned int)Wf - sum
+                                                   : (long long)(unsigned int)rintf(Wf * (wr[a] * wz[b]));
+            sum += q;
+            add(a, b, q);
+        }
+}
+
+// The same charges into the ghosted grid of the device (new electrons and
+// particles outside the LDS window).
+__device__ __forceinline__ void deposit_cubic_gbl(long long* Qx, int WX, int i, int j, float w, float two_S,
+                                                  float fr, float fz) {
+    gbl_u64* Q = as_gbl(Qx);
+    cubic_charges(w, two_S, fr, fz, [&](int a, int b, long long q) {
+        gbl_add(&Q[(long long)(i + a) * WX + (j + b)], (unsigned long long)q);
+    });
+}
+
 // Everything the particle loop needs about the current chunk.
 struct ChunkCtx {
     LocalInst L;
@@ -409,12 +458,19 @@ struct ChunkCtx {
     int inst, ti_c, tj_c, i0, i1, j0, j1, ww;
     bool win;
     unsigned int step;
+    // cubic shapes: the ghosted coefficient and charge windows (rows of ww + 2
+    // nodes from ghosted node (i0, j0)) and the device arrays (rows of WX)
+    lds_f32* sC;
+    lds_u64* sQx;
+    const float* cxf;
+    long long* Qx;
+    int WX;
 };
 
 // One particle: (optional) sort destination, gather, Boris, remap, walls,
 // null-collision test, store, deposit, (optional) destination-tile count.
 // Every lane of the wave calls it (collectives inside).
-template <bool COUNT, bool SCATTER, bool INS>
+template <bool COUNT, bool SCATTER, bool INS, bool CUB>
 __device__ __forceinline__ void push_particle(const KArgs& A, const ChunkCtx& X, long long p, bool inr, float r,
                                               float z, float vr, float vt, float vz, float w,
                                               unsigned long long key, unsigned int& c_push) {
@@ -457,8 +513,36 @@ __device__ __forceinline__ void push_particle(const KArgs& A, const ChunkCtx& X,
     }
     const float gr = 1.0f - fr, gz = 1.0f - fz;
     const float w00 = gr * gz, w10 = fr * gz, w01 = gr * fz, w11 = fr * fz;
-    const float er = fmaf(w11, f11.x, fmaf(w01, f01.x, fmaf(w10, f10.x, w00 * f00.x)));
-    const float ez = fmaf(w11, f11.y, fmaf(w01, f01.y, fmaf(w10, f10.y, w00 * f00.y)));
+    float er = fmaf(w11, f11.x, fmaf(w01, f01.x, fmaf(w10, f10.x, w00 * f00.x)));
+    float ez = fmaf(w11, f11.y, fmaf(w01, f01.y, fmaf(w10, f10.y, w00 * f00.y)));
+    if (CUB) {
+        // cubic shapes: the nodal field is the vacuum field; add the space
+        // charge's -grad of the cubic expansion at the particle
+        float wr[4], dwr[4], wz[4], dwz[4];
+        bspline3_f(fr, wr, dwr);
+        bspline3_f(fz, wz, dwz);
+        float gr3 = 0.0f, gz3 = 0.0f;
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+            float c[4];
+            if (inwin) {
+                const int l = (i - X.i0 + a) * (X.ww + 2) + (j - X.j0);
+#pragma unroll
+                for (int b = 0; b < 4; ++b) c[b] = X.sC[l + b];
+            } else {
+                gbl_f32* C = (gbl_f32*)X.cxf;
+                const long long n = (long long)(i + a) * X.WX + j;
+#pragma unroll
+                for (int b = 0; b < 4; ++b) c[b] = C[n + b];
+            }
+            const float sz = fmaf(c[3], wz[3], fmaf(c[2], wz[2], fmaf(c[1], wz[1], c[0] * wz[0])));
+            const float dz = fmaf(c[3], dwz[3], fmaf(c[2], dwz[2], fmaf(c[1], dwz[1], c[0] * dwz[0])));
+            gr3 = fmaf(dwr[a], sz, gr3);
+            gz3 = fmaf(wr[a], dz, gz3);
+        }
+        er = fmaf(-gr3, L.inv_dr, er);
+        ez = fmaf(-gz3, L.inv_dz, ez);
+    }
     const float br = fmaf(w11, f11.z, fmaf(w01, f01.z, fmaf(w10, f10.z, w00 * f00.z)));
     const float bz = fmaf(w11, f11.w, fmaf(w01, f01.w, fmaf(w10, f10.w, w00 * f00.w)));
     // Boris: half kick, rotation, half kick
@@ -558,6 +642,16 @@ __device__ __forceinline__ void push_particle(const KArgs& A, const ChunkCtx& X,
             gbl_add(&Qg[n00 + 1], (unsigned long long)q01);
             gbl_add(&Qg[n00 + L.W + 1], (unsigned long long)q11);
         }
+        if (CUB) {
+            if (X.win && ni >= X.i0 && ni + 1 <= X.i1 && nj >= X.j0 && nj + 1 <= X.j1) {
+                const int l = (ni - X.i0) * (X.ww + 2) + (nj - X.j0);
+                cubic_charges(w, L.two_S, nfr, nfz, [&](int a, int b, long long q) {
+                    lds_add(&X.sQx[l + a * (X.ww + 2) + b], (unsigned long long)q);
+                });
+            } else {
+                deposit_cubic_gbl(X.Qx, X.WX, ni, nj, w, L.two_S, nfr, nfz);
+            }
+        }
         if (INS && L.has_ins) {
             // the band test from the chunk's copy of the insert constants (the
             // same arithmetic as ins_g_f): the instance table is read only in
@@ -603,25 +697,30 @@ __device__ __forceinline__ int wave_search(const long long* a, int n, long long 
 
 // ---- the particle kernel --------------------------------------------------
 //
-// MODE bit 1 (COUNT): after the push, count every survivor (and new
+// MODE bit 0 (COUNT): after the push, count every survivor (and new
 // electron) in the tile of its new position; these totals size the next
-// sort.  MODE bit 2 (SCATTER): each particle's destination in the other
+// sort.  MODE bit 1 (SCATTER): each particle's destination in the other
 // store is fixed by the tile of its position at step start (the totals of
 // the previous COUNT give each tile's first slot); a tile chunk reserves
 // room for its particles per neighbouring destination tile with one atomic
 // each, particles outside the 3x3 neighbourhood and tail particles take
 // single ranks.  The updated particle (or a dead marker if it was absorbed)
-// is written there instead of in place.
-// MODE bit 0: counting step, bit 1: sorting step, bit 2: a context with the
+// is written there instead of in place.  MODE bit 2: a context with the
 // elliptic insert (absorption on it and the band charges compiled in).
+// MODE bit 3: cubic shapes (the space-charge field from the cubic
+// coefficients, the cubic deposit into the ghosted grid beside Q).
 template <int MODE>
-__global__ void __launch_bounds__(kPWG) __attribute__((amdgpu_waves_per_eu(8, 8))) k_particles(KArgs A) {
+__device__ __forceinline__ void particles_body(const KArgs& A) {
     constexpr bool COUNT = (MODE & 1) != 0;
     constexpr bool SCATTER = (MODE & 2) != 0;
     constexpr bool INS = (MODE & 4) != 0;
+    constexpr bool CUB = (MODE & 8) != 0;
     extern __shared__ __align__(16) unsigned char smem[];
     lds_float4* sEB = (lds_float4*)(v4f*)smem;
     lds_u64* sQ = (lds_u64*)(unsigned long long*)(smem + sizeof(float4) * (size_t)A.win_max);
+    // cubic shapes: coefficient and charge windows after them
+    lds_f32* sC = (lds_f32*)(float*)(smem + 24 * (size_t)A.win_max);
+    lds_u64* sQx = (lds_u64*)(unsigned long long*)(smem + 24 * (size_t)A.win_max + 4 * (size_t)A.win3_max);
     __shared__ long long s_start;
     __shared__ int s_count, s_inst, s_tr0, s_tz0;
     __shared__ unsigned int s_bcnt[9], s_bbase[9], s_ccnt[9];
@@ -701,6 +800,15 @@ __global__ void __launch_bounds__(kPWG) __attribute__((amdgpu_waves_per_eu(8, 8)
                     sEB[t] = as_gbl(F.EB)[(long long)(i0 + a) * W + (j0 + b)];
                     sQ[t] = 0ull;
                 }
+                if (CUB) {
+                    // ghosted nodes i0 .. i1 + 2, j0 .. j1 + 2 (physical i - 1)
+                    const int w3 = ww + 2, nwin3 = (i1 - i0 + 3) * w3, WX = I.nz + 3;
+                    for (int t = tid; t < nwin3; t += kPWG) {
+                        int a = t / w3, b = t - a * w3;
+                        sC[t] = ((gbl_f32*)F.cxf)[(long long)(i0 + a) * WX + (j0 + b)];
+                        sQx[t] = 0ull;
+                    }
+                }
             }
             if (SCATTER && win) {
                 // pass 1: destinations of this chunk's particles per neighbouring tile
@@ -743,6 +851,7 @@ __global__ void __launch_bounds__(kPWG) __attribute__((amdgpu_waves_per_eu(8, 8)
             X.out = out; X.EB = F.EB; X.Q = F.Q; X.Qw = F.Qw;
             X.inst = inst; X.ti_c = ti_c; X.tj_c = tj_c; X.i0 = i0; X.i1 = i1; X.j0 = j0; X.j1 = j1; X.ww = ww;
             X.win = win; X.step = step;
+            X.sC = sC; X.sQx = sQx; X.cxf = F.cxf; X.Qx = F.Qx; X.WX = I.nz + 3;
             // U particles per lane per pass (their loads are all in flight before
             // any is processed); U = 1 measured fastest on gfx950 (occupancy wins)
             // Passes start on a 64-slot boundary so that every wave's loads and
@@ -770,7 +879,7 @@ __global__ void __launch_bounds__(kPWG) __attribute__((amdgpu_waves_per_eu(8, 8)
                 }
     #pragma unroll
                 for (int u = 0; u < U; ++u)
-                    push_particle<COUNT, SCATTER, INS>(A, X, pp[u], inr[u], r[u], z[u], vr[u], vt[u], vz[u], w[u], key[u],
+                    push_particle<COUNT, SCATTER, INS, CUB>(A, X, pp[u], inr[u], r[u], z[u], vr[u], vt[u], vz[u], w[u], key[u],
                                                   c_push);
             }
             flush_counter(&cnt[C_PSTEPS], (unsigned long long)c_push);
@@ -806,9 +915,33 @@ __global__ void __launch_bounds__(kPWG) __attribute__((amdgpu_waves_per_eu(8, 8)
                         gbl_add(&Qg[(long long)(i0 + a) * W + (j0 + b)], v);
                     }
                 }
+                if (CUB) {
+                    const int w3 = ww + 2, nwin3 = (i1 - i0 + 3) * w3, WX = I.nz + 3;
+                    gbl_u64* Qx = as_gbl(F.Qx);
+                    for (int t = tid; t < nwin3; t += kPWG) {
+                        const unsigned long long v = sQx[t];
+                        if (v != 0ull) {
+                            int a = t / w3, b = t - a * w3;
+                            gbl_add(&Qx[(long long)(i0 + a) * WX + (j0 + b)], v);
+                        }
+                    }
+                }
             }
         }
     }
+}
+
+// The bilinear forms keep 64 registers so two workgroups share a CU.
+template <int MODE>
+__global__ void __launch_bounds__(kPWG) __attribute__((amdgpu_waves_per_eu(8, 8))) k_particles(KArgs A) {
+    particles_body<MODE>(A);
+}
+
+// Cubic shapes: the 16-node gather and deposit keep their values in up to
+// 128 registers (one workgroup per CU) instead of spilling.
+template <int MODE>
+__global__ void __launch_bounds__(kPWG) k_particles3(KArgs A) {
+    particles_body<MODE | 8>(A);
 }
 
 // Resolve the collision events queued by the particle kernel (which took
@@ -883,6 +1016,7 @@ __global__ void __launch_bounds__(kWG) k_collide(KArgs A, PSet P, int scatter) {
         atomicAdd(&Qg[n00 + 1], (unsigned long long)q01);
         atomicAdd(&Qg[n00 + I.W + 1], (unsigned long long)q11);
         if (I.has_ins) deposit_qw(I, A.Ft[inst].Qw, w, r, z);
+        if (I.spline3) deposit_cubic_gbl(A.Ft[inst].Qx, I.nz + 3, i, j, w, (float)I.two_S, fr, fz);
         if (A.cnt_out) atomicAdd(&A.cnt_out[I.tile_off + (i / A.TR) * I.ntz + (j / A.TZ)], 1u);
     }
 }
@@ -932,6 +1066,7 @@ __global__ void __launch_bounds__(kWG) k_source32(KArgs A, PSet P, int scatter) 
         atomicAdd(&Qg[n00 + 1], (unsigned long long)q01);
         atomicAdd(&Qg[n00 + I.W + 1], (unsigned long long)q11);
         if (I.has_ins) deposit_qw(I, A.Ft[inst].Qw, wf, r, z);
+        if (I.spline3) deposit_cubic_gbl(A.Ft[inst].Qx, I.nz + 3, i, jj, wf, (float)I.two_S, fr, fz);
         if (A.cnt_out) atomicAdd(&A.cnt_out[I.tile_off + (i / A.TR) * I.ntz + (jj / A.TZ)], 1u);
     }
 }
@@ -963,6 +1098,11 @@ __global__ void k_zero_q(const DevInst* It, const FieldDev* Ft) {
     for (int n = blockIdx.x * blockDim.x + threadIdx.x; n < I.nodes; n += gridDim.x * blockDim.x) {
         Q[n] = 0;
         if (Qw) Qw[n] = 0;
+    }
+    if (I.spline3) {  // the ghosted cubic grid
+        long long* Qx = Ft[blockIdx.y].Qx;
+        const int ext = (I.nr + 3) * (I.nz + 3);
+        for (int n = blockIdx.x * blockDim.x + threadIdx.x; n < ext; n += gridDim.x * blockDim.x) Qx[n] = 0;
     }
 }
 
@@ -1141,7 +1281,7 @@ __global__ void k_load32(DevInst I, double r_lo, double r_hi, double z_lo, doubl
     }
 }
 
-__global__ void k_deposit32(DevInst I, PSet P, long long* Q, long long* Qw, const long long* cnt) {
+__global__ void k_deposit32(DevInst I, PSet P, long long* Q, long long* Qw, long long* Qx, const long long* cnt) {
     const long long slots = cnt[C_SLOTS];
     for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < slots;
          q += (long long)gridDim.x * blockDim.x) {
@@ -1160,10 +1300,13 @@ __global__ void k_deposit32(DevInst I, PSet P, long long* Q, long long* Qw, cons
         atomicAdd(&Qg[n00 + 1], (unsigned long long)q01);
         atomicAdd(&Qg[n00 + I.W + 1], (unsigned long long)q11);
         if (Qw) deposit_qw(I, Qw, weight_at(I, P, p), r, P.z[p]);
+        if (Qx) deposit_cubic_gbl(Qx, I.nz + 3, i, j, weight_at(I, P, p), (float)I.two_S, fr, fz);
     }
 }
 
 typedef void (*ParticleKernel)(KArgs);
+// Variant v = step kind (bits 0-1) | insert (4) | cubic shapes (8); the
+// cubic shapes are not combined with the insert.
 ParticleKernel particle_kernel(int v) {
     switch (v) {
         case 0: return k_particles<0>;
@@ -1173,9 +1316,17 @@ ParticleKernel particle_kernel(int v) {
         case 4: return k_particles<4>;
         case 5: return k_particles<5>;
         case 6: return k_particles<6>;
-        default: return k_particles<7>;
+        case 7: return k_particles<7>;
+        case 8: return k_particles3<0>;
+        case 9: return k_particles3<1>;
+        case 10: return k_particles3<2>;
+        default: return k_particles3<3>;
     }
 }
+
+// LDS bytes of the particle kernel's windows: fields and charge per window
+// node, with cubic shapes the ghosted coefficient and charge windows.
+size_t particle_lds(int win, int win3) { return (size_t)win * 24 + (size_t)win3 * 12; }
 
 unsigned int grid_for(long long n, long long cap = 16384) {
     long long g = (n + kWG - 1) / kWG;
@@ -1189,8 +1340,9 @@ unsigned int grid_for(long long n, long long cap = 16384) {
 // ---------------------------------------------------------------------------
 
 struct F32State {
-    int TR = 8, TZ = 32, halo = 8, K = 16, C = 1 << 22, win_max = 0;
+    int TR = 8, TZ = 32, halo = 8, K = 16, C = 1 << 22, win_max = 0, win3_max = 0;
     bool ins = false;  // some instance has the elliptic insert
+    bool cub = false;  // the instances use cubic shapes
     int coll_grid = 64;   // workgroups of k_collide
     int cu = 256, wg_per_cu = 4;
     PSet set[2];
@@ -1261,6 +1413,7 @@ static KArgs kargs(pic_ctx* ctx, F32State* S, int set) {
     A.halo = S->halo;
     A.C = S->C;
     A.win_max = S->win_max;
+    A.win3_max = S->win3_max;
     return A;
 }
 
@@ -1293,7 +1446,8 @@ static pic_status build_tiles(pic_ctx* ctx, F32State* S) {
         return f32_fail(ctx, PIC_EINVAL, "1 <= tile_r, tile_z <= 256, 0 <= halo <= 32, sort_interval >= 1, "
                                          "1 <= chunk <= 2^30");
     const int win = (S->TR + 2 * S->halo + 1) * (S->TZ + 2 * S->halo + 1);
-    if ((size_t)win * 24 > 64 * 1024) return f32_fail(ctx, PIC_EINVAL, "tile window exceeds 64 KiB of LDS");
+    const int win3 = S->cub ? ((S->TR + 2 * S->halo + 3) * (S->TZ + 2 * S->halo + 3) + 1) / 2 * 2 : 0;
+    if (particle_lds(win, win3) > 64 * 1024) return f32_fail(ctx, PIC_EINVAL, "tile window exceeds 64 KiB of LDS");
     const int n = pic_n_inst(ctx);
     long long tsum = 0;
     for (int k = 0; k < n; ++k) {
@@ -1303,6 +1457,7 @@ static pic_status build_tiles(pic_ctx* ctx, F32State* S) {
     if (tsum > (1 << 26)) return f32_fail(ctx, PIC_EINVAL, "too many tiles");
     // nothing is changed before this point: PIC_EINVAL leaves the tables as they were
     S->win_max = win;
+    S->win3_max = win3;
     void* old[] = {S->tile_count, S->tstart[0], S->tstart[1], S->tile_lpre, S->vtile,
                    S->tile_info, S->cbuf[0],   S->cbuf[1],   S->tile_fill};
     for (void* q : old) pic_dev_free(ctx, q);
@@ -1333,10 +1488,10 @@ static pic_status build_tiles(pic_ctx* ctx, F32State* S) {
     hipStream_t s = pic_stream(ctx);
     CK32(hipMemcpyAsync(S->tile_info, tinfo.data(), sizeof(int4) * toff, hipMemcpyHostToDevice, s));
     CK32(hipStreamSynchronize(s));
-    size_t lds = (size_t)S->win_max * (sizeof(float4) + sizeof(unsigned long long));
+    const size_t lds = particle_lds(S->win_max, S->win3_max);
     // every workgroup of the statically balanced grid must be resident at once
     int omin = 1 << 30;
-    for (int v = 0; v < 8; ++v) {
+    for (int v = S->cub ? 8 : 0; v < (S->cub ? 12 : 8); ++v) {
         const void* f = (const void*)particle_kernel(v);
         CK32(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
         int occ = 0;
@@ -1427,6 +1582,7 @@ pic_status f32_init(pic_ctx* ctx) {
     if (run.sort_interval > 0) S->K = run.sort_interval;
     if (run.chunk > 0) S->C = run.chunk;
     for (int k = 0; k < pic_n_inst(ctx); ++k) S->ins = S->ins || pic_inst_dev(ctx, k).has_ins != 0;
+    S->cub = pic_inst_dev(ctx, 0).spline3 != 0;  // every instance of a context has the same shapes
     pic_status st = build_tiles(ctx, S);
     if (st != PIC_OK) return st;
     const int n = pic_n_inst(ctx);
@@ -1519,9 +1675,10 @@ static pic_status launch_step(pic_ctx* ctx, F32State* S, hipStream_t s, bool tim
         if (!e0) return f32_fail(ctx, PIC_EDEVICE, "event pool");
         CK32(hipEventRecord(e0, s));
     }
-    const size_t lds = (size_t)S->win_max * (sizeof(float4) + sizeof(unsigned long long));
+    const size_t lds = particle_lds(S->win_max, S->win3_max);
     const dim3 grid(S->cu * S->wg_per_cu);
-    hipLaunchKernelGGL(particle_kernel((mode & 3) | (S->ins ? 4 : 0)), grid, dim3(kPWG), lds, s, A);
+    hipLaunchKernelGGL(particle_kernel((mode & 3) | (S->ins ? 4 : 0) | (S->cub ? 8 : 0)), grid, dim3(kPWG), lds, s,
+                       A);
     CK32(hipGetLastError());
     if (timed) CK32(hipEventRecord(e1, s));
     hipLaunchKernelGGL(k_collide, dim3(S->coll_grid), dim3(kWG), sizeof(unsigned int) * 2 * (size_t)n, s, A,
@@ -2062,7 +2219,7 @@ pic_status f32_deposit_only(pic_ctx* ctx, int k) {
     const DevInst& I = pic_inst_dev(ctx, k);
     hipLaunchKernelGGL(k_deposit32, dim3(grid_for(I.p_cap)), dim3(kWG), 0, pic_stream(ctx), I, S->set[S->cur],
                        pic_inst_Q(ctx, k), I.has_ins ? pic_inst_Qw(ctx, k) : nullptr,
-                       pic_counters(ctx) + (long long)k * C_NCOUNT);
+                       I.spline3 ? pic_inst_Qx(ctx, k) : nullptr, pic_counters(ctx) + (long long)k * C_NCOUNT);
     CK32(hipGetLastError());
     return PIC_OK;
 }

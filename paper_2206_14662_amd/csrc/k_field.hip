@@ -532,34 +532,64 @@ __global__ void k3_fold(const DevInst* __restrict__ It, const FieldDev* __restri
 }
 
 // per sine mode k (one lane each): the 7-band r system, L D L^T factors
-// precomputed on the host; in place in rhs
+// precomputed on the host; in place in rhs.  The sweeps are sequential in r,
+// so the rows' operands are loaded kB3 rows at a time (their loads in flight
+// together) before the recurrence consumes them.
+constexpr int kB3 = 16;
+
 __global__ void __launch_bounds__(64) k3_band(const DevInst* __restrict__ It, const FieldDev* __restrict__ F3) {
     const DevInst& I = It[blockIdx.y];
     const FieldDev& F = F3[blockIdx.y];
     const int k = blockIdx.x * 64 + threadIdx.x;
     if (I.frozen || k < 1 || k > I.nz - 1) return;
     const int W = I.W, m = I.nr - 1;
-    double* x = F.rhs;
+    double* __restrict__ x = F.rhs;
+    const double* __restrict__ L1 = F.s3_L1;
+    const double* __restrict__ L2 = F.s3_L2;
+    const double* __restrict__ L3 = F.s3_L3;
+    const double* __restrict__ Dinv = F.s3_Dinv;
+    // forward: y_i = x_i - L1_i y_{i-1} - L2_i y_{i-2} - L3_i y_{i-3}
     double y1 = 0.0, y2 = 0.0, y3 = 0.0;  // y at rows i-1, i-2, i-3
-    for (int i = 1; i <= m; ++i) {
-        const long long n = (long long)i * W + k;
-        const double y = ((x[n] - F.s3_L1[n] * y1) - F.s3_L2[n] * y2) - F.s3_L3[n] * y3;
-        x[n] = y;
-        y3 = y2;
-        y2 = y1;
-        y1 = y;
+    for (int ib = 1; ib <= m; ib += kB3) {
+        double xb[kB3], l1[kB3], l2[kB3], l3[kB3];
+#pragma unroll
+        for (int u = 0; u < kB3; ++u) {
+            const long long n = (long long)min(ib + u, m) * W + k;
+            xb[u] = x[n]; l1[u] = L1[n]; l2[u] = L2[n]; l3[u] = L3[n];
+        }
+#pragma unroll
+        for (int u = 0; u < kB3; ++u) {
+            if (ib + u > m) break;
+            const double y = ((xb[u] - l1[u] * y1) - l2[u] * y2) - l3[u] * y3;
+            x[(long long)(ib + u) * W + k] = y;
+            y3 = y2;
+            y2 = y1;
+            y1 = y;
+        }
     }
+    // backward: v_i = y_i Dinv_i - L1_{i+1} v_{i+1} - L2_{i+2} v_{i+2} - L3_{i+3} v_{i+3}
     double x1 = 0.0, x2 = 0.0, x3 = 0.0;  // x at rows i+1, i+2, i+3
-    for (int i = m; i >= 1; --i) {
-        const long long n = (long long)i * W + k;
-        const double l1 = i + 1 <= m ? F.s3_L1[n + W] : 0.0;
-        const double l2 = i + 2 <= m ? F.s3_L2[n + 2 * W] : 0.0;
-        const double l3 = i + 3 <= m ? F.s3_L3[n + 3 * W] : 0.0;
-        const double v = ((x[n] * F.s3_Dinv[n] - l1 * x1) - l2 * x2) - l3 * x3;
-        x[n] = v;
-        x3 = x2;
-        x2 = x1;
-        x1 = v;
+    for (int ib = m; ib >= 1; ib -= kB3) {
+        double yb[kB3], di[kB3], l1[kB3], l2[kB3], l3[kB3];
+#pragma unroll
+        for (int u = 0; u < kB3; ++u) {
+            const int i = max(ib - u, 1);
+            const long long n = (long long)i * W + k;
+            yb[u] = x[n];
+            di[u] = Dinv[n];
+            l1[u] = i + 1 <= m ? L1[n + W] : 0.0;
+            l2[u] = i + 2 <= m ? L2[n + 2 * W] : 0.0;
+            l3[u] = i + 3 <= m ? L3[n + 3 * W] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < kB3; ++u) {
+            if (ib - u < 1) break;
+            const double v = ((yb[u] * di[u] - l1[u] * x1) - l2[u] * x2) - l3[u] * x3;
+            x[(long long)(ib - u) * W + k] = v;
+            x3 = x2;
+            x2 = x1;
+            x1 = v;
+        }
     }
 }
 
@@ -582,7 +612,9 @@ __global__ void k3_post(const DevInst* __restrict__ It, const FieldDev* __restri
     for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < ext;
          t += (long long)gridDim.x * blockDim.x) {
         const int gi = (int)(t / WX), gj = (int)(t - (long long)gi * WX);
-        F.cx[t] = coef(gi - 1, gj - 1);
+        const double ct = coef(gi - 1, gj - 1);
+        F.cx[t] = ct;
+        if (F.cxf) F.cxf[t] = (float)ct;
         if (gi > I.nr || gj > I.nz) continue;
         // node (gi, gj)
         const double nb[3] = {1.0 / 6.0, 4.0 / 6.0, 1.0 / 6.0};

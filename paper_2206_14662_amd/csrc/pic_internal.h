@@ -319,6 +319,7 @@ struct FieldDev {
     // per-mode LDL^T factors of the 7-band r systems ([i][k], row length W)
     long long* Qx;
     double* cx;
+    float* cxf;            // FP32 copy of cx for the batched form (else NULL)
     const double *s3_L1, *s3_L2, *s3_L3, *s3_Dinv;
 };
 
