@@ -241,3 +241,23 @@ def test_fp32_cubic_tracks_the_oracle_over_a_run():
     assert gd["peak_density"] == pytest.approx(od["peak_density"], rel=0.02)
     assert gd["n_live"] == pytest.approx(od["n_live"], rel=0.02)
     g.close()
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("mode", [F64, F32])
+def test_cubic_charge_bookkeeping_with_source_and_ionisation(mode):
+    """Every path that deposits (the window, device atomics, ionisation
+    children, seed-source electrons): the cubic grid and the bilinear grid
+    each hold exactly W per live electron after every step."""
+    cfg = cubic(n_init=30000, p_mbar=30.0, E_cap_eV=3000.0, src_rate=40.0, src_T_eV=2.0)
+    g = B.Sim([cfg], mode=mode)
+    W = None
+    for _ in range(6):
+        g.step(3)
+        d = g.diag()
+        W = W or round(cfg["weight"] * 2.0 ** d["S"])
+        Qx, _ = g.spline3()
+        assert Qx.sum() == d["n_live"] * W
+        assert g.charge().sum() == d["n_live"] * W
+    assert d["n_ioniz"] > 0 and d["n_source"] > 0
+    g.close()
