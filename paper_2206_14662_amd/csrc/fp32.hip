@@ -83,7 +83,7 @@ struct PSet {
 
 
 // control block: [1] particles to push this step (sorted + tails), [2] sorted
-// particles over all instances, [3] collision candidates queued this step,
+// particles over all instances, [3] collision events queued this step,
 // [4] queue overflow flag, [5 .. 5+n_inst] prefix of the instances' tail counts
 
 struct KArgs {
@@ -100,7 +100,7 @@ struct KArgs {
     const long long* tile_start;   // first slot of each tile in the input store
     const long long* tile_dst;     // first slot of each tile in the output store (SCATTER)
     const long long* new_base;     // per instance: slots of the sorted output
-    unsigned long long* queue;     // collision candidates: (instance << 40) | slot
+    unsigned long long* queue;     // real collision events: (instance << 40) | slot
     long long qcap;
     int n_inst, n_tiles, TR, TZ, halo, C, win_max;
     int win3_max;                  // ghosted cubic window nodes (even; 0 without cubic shapes)
@@ -269,7 +269,7 @@ __device__ __forceinline__ int event_kind_f(const EvConst& c, const DevInst& I, 
     return 0;
 }
 
-// The real event of a queued candidate.  Returns 0 null, 1 elastic, 2
+// The event of a queued candidate.  Returns 0 null, 1 elastic, 2
 // ionisation; sets the parent's new velocity and, for an ionisation, the new
 // electron's velocity and key.
 __device__ __forceinline__ int collide_f(const DevInst& I, unsigned long long key, unsigned int step, uint4 b0,
@@ -382,7 +382,7 @@ __device__ __forceinline__ unsigned int wave_aggregate(bool act, int key, F&& ad
     return rank;
 }
 
-// LDS queue of null-collision candidates per workgroup and chunk
+// LDS queue of the real collision events per workgroup and chunk
 constexpr int kLQ = 512;
 
 // chunk-level event counters kept in LDS and their device counter slots
@@ -864,7 +864,7 @@ __device__ __forceinline__ void particles_body(const KArgs& A) {
                 bool inr[U];
                 float r[U], z[U], vr[U], vt[U], vz[U], w[U];
                 unsigned long long key[U];
-    #pragma unroll
+#pragma unroll
                 for (int u = 0; u < U; ++u) {
                     const int q = base + u * kPWG + tid;
                     inr[u] = q >= 0 && q < count;
@@ -877,7 +877,7 @@ __device__ __forceinline__ void particles_body(const KArgs& A) {
                     w[u] = wu != 0.0f ? wu : A.p.w[pp[u]];
                     key[u] = A.p.key[pp[u]];
                 }
-    #pragma unroll
+#pragma unroll
                 for (int u = 0; u < U; ++u)
                     push_particle<COUNT, SCATTER, INS, CUB>(A, X, pp[u], inr[u], r[u], z[u], vr[u], vt[u], vz[u], w[u], key[u],
                                                   c_push);
@@ -888,7 +888,7 @@ __device__ __forceinline__ void particles_body(const KArgs& A) {
                 const unsigned long long v = s_ctr[tid];
                 if (v) atomicAdd((unsigned long long*)&cnt[kCounterOf[tid]], v);
             }
-            // the chunk's queued candidates: one device reservation
+            // the chunk's queued events: one device reservation
             const unsigned int q_all = s_qn;
             const unsigned int q_lds = min(q_all, (unsigned int)kLQ);
             if (tid == SC_N) {
@@ -1358,7 +1358,7 @@ struct F32State {
     long long* ctl = nullptr;
     unsigned int* cbuf[2] = {nullptr, nullptr};  // per-tile totals counted for the next sort
     unsigned int* tile_fill = nullptr;
-    unsigned long long* queue = nullptr;  // collision candidates of one step
+    unsigned long long* queue = nullptr;  // real collision events of one step
     long long qcap = 0;
     FieldDev* dF = nullptr;  // field table (owned by the context)
     hipStream_t gstream = nullptr;
@@ -1525,12 +1525,13 @@ static pic_status build_store(pic_ctx* ctx, F32State* S, const std::vector<long 
     }
     PSet ns[2] = {alloc_set(ctx, off), alloc_set(ctx, off)};
     unsigned long long* nkey = (unsigned long long*)pic_dev_alloc(ctx, sizeof(unsigned long long) * off);
-    // collision candidates per step are binomial(N, P_null): size the queue far
-    // above the mean (an overflow is reported, never ignored)
+    // collision candidates per step are binomial(N, P_null) and the real
+    // events a part of them: size the queue far above the candidates' mean
+    // (an overflow is reported, never ignored)
     double pmax = 0.0;
     for (int k = 0; k < n; ++k) pmax = std::max(pmax, pic_inst_dev(ctx, k).P_null);
     const long long qcap = std::min<long long>(off, std::max<long long>(1 << 16, (long long)(64.0 * pmax * (double)off)));
-    // collision kernel grid: about four expected candidates per thread
+    // collision kernel grid: at most four expected candidates per thread
     S->coll_grid = (int)std::min<double>(4096.0, std::max(64.0, std::ceil(pmax * (double)off / (4.0 * kWG))));
     unsigned long long* nq = (unsigned long long*)pic_dev_alloc(ctx, sizeof(unsigned long long) * qcap);
     if (!set_ok(ns[0]) || !set_ok(ns[1]) || !nkey || !nq) {
@@ -2293,7 +2294,7 @@ pic_status f32_check(pic_ctx* ctx) {
     F32State* S = pic_get_f32(ctx);
     long long over = 0;
     CK32(hipMemcpy(&over, S->ctl + CTL_QOVER, sizeof(long long), hipMemcpyDeviceToHost));
-    if (over) return f32_fail(ctx, PIC_ECAPACITY, "collision candidate queue overflowed");
+    if (over) return f32_fail(ctx, PIC_ECAPACITY, "collision event queue overflowed");
     return PIC_OK;
 }
 

@@ -136,7 +136,7 @@ enum Counter {
 };
 
 // Control words of the batched FP32 step (device array, FP32 form only):
-// particles pushed this step, of which tile-sorted, collision candidates
+// particles pushed this step, of which tile-sorted, real collision events
 // queued, queue overflow flag, then per-instance exclusive prefix of the
 // tail counts (electrons created since the last sort).
 enum { CTL_TOTAL = 1, CTL_SORTED = 2, CTL_QCOUNT = 3, CTL_QOVER = 4, CTL_TAIL = 5 };
