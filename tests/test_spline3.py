@@ -261,3 +261,24 @@ def test_cubic_charge_bookkeeping_with_source_and_ionisation(mode):
         assert g.charge().sum() == d["n_live"] * W
     assert d["n_ioniz"] > 0 and d["n_source"] > 0
     g.close()
+
+
+@pytest.mark.gpu
+def test_fp32_cubic_autotune_and_growth_keep_the_bits():
+    """The autotuner's trial shapes (the cubic windows included in the LDS
+    budget) and storage regrowth change no result of a cubic run."""
+    cfg = cubic(n_init=40000, p_mbar=3.0, E_cap_eV=3000.0)
+    g = B.Sim([cfg], mode=F32, capacity_factor=1.3)
+    t = g.autotune(trial_steps=4)
+    assert t["trials"] >= 10 and t["ms_per_step"] > 0
+    g.step(150)
+    got = (by_key(g.get_particles()), g.spline3()[0], g.diag())
+    g.close()
+    ref = B.Sim([cfg], mode=F32, capacity_factor=8.0)
+    ref.step(got[2]["step"])
+    want = (by_key(ref.get_particles()), ref.spline3()[0], ref.diag())
+    ref.close()
+    for k in ("key", "r", "z", "vr", "vt", "vz"):
+        assert np.array_equal(want[0][k], got[0][k]), k
+    assert np.array_equal(want[1], got[1])
+    assert want[2]["n_ioniz"] == got[2]["n_ioniz"] > 0
