@@ -887,11 +887,28 @@ static pic_status init_instance_storage(pic_ctx* ctx, Inst& in) {
     in.Bz = dalloc<double>(ctx, N);
     in.V = dalloc<double>(ctx, N);
     in.avg_acc = dalloc<double>(ctx, N);
-    in.th_cp = dalloc<double>(ctx, N);
-    in.th_im = dalloc<double>(ctx, N);
-    in.th_lo = dalloc<double>(ctx, N);
-    in.th_G = dalloc<double>(ctx, N);
-    in.th_H = dalloc<double>(ctx, N);
+    // The r-direction factors depend only on the mesh and the end condition:
+    // instances that agree on these share one copy (read-only after set-up),
+    // so a batched solve streams them once from the cache for all of them.
+    const Inst* twin = nullptr;
+    for (const Inst& o : ctx->in) {
+        if (&o == &in) break;
+        if (o.th_cp && o.c.nr == in.c.nr && o.c.nz == in.c.nz && o.c.a == in.c.a && o.c.b == in.c.b &&
+            o.c.L == in.c.L && o.c.end_mode == in.c.end_mode) {
+            twin = &o;
+            break;
+        }
+    }
+    if (twin) {
+        in.th_cp = twin->th_cp; in.th_im = twin->th_im; in.th_lo = twin->th_lo;
+        in.th_G = twin->th_G; in.th_H = twin->th_H;
+    } else {
+        in.th_cp = dalloc<double>(ctx, N);
+        in.th_im = dalloc<double>(ctx, N);
+        in.th_lo = dalloc<double>(ctx, N);
+        in.th_G = dalloc<double>(ctx, N);
+        in.th_H = dalloc<double>(ctx, N);
+    }
     if (!in.Q || !in.rhs || !in.phi || !in.phi_vac || !in.phiB || !in.Br || !in.Bz || !in.V ||
         !in.avg_acc || !in.th_cp || !in.th_im || !in.th_lo || !in.th_G || !in.th_H)
         return fail(ctx, PIC_ENOMEM, "device allocation of node arrays failed");
@@ -923,14 +940,16 @@ static pic_status init_instance_storage(pic_ctx* ctx, Inst& in) {
     CK(hipStreamSynchronize(s));
     host_volume(in.c, in.V_host);
     CK(hipMemcpyAsync(in.V, in.V_host.data(), sizeof(double) * N, hipMemcpyHostToDevice, s));
-    std::vector<double> gg, hh;
-    host_thomas(in.c, thomas_segments(ctx->max_nr), a, b, cc, gg, hh);
-    CK(hipMemcpyAsync(in.th_cp, a.data(), sizeof(double) * N, hipMemcpyHostToDevice, s));
-    CK(hipMemcpyAsync(in.th_im, b.data(), sizeof(double) * N, hipMemcpyHostToDevice, s));
-    CK(hipMemcpyAsync(in.th_lo, cc.data(), sizeof(double) * N, hipMemcpyHostToDevice, s));
-    CK(hipMemcpyAsync(in.th_G, gg.data(), sizeof(double) * N, hipMemcpyHostToDevice, s));
-    CK(hipMemcpyAsync(in.th_H, hh.data(), sizeof(double) * N, hipMemcpyHostToDevice, s));
-    CK(hipStreamSynchronize(s));
+    if (!twin) {
+        std::vector<double> gg, hh;
+        host_thomas(in.c, thomas_segments(ctx->max_nr), a, b, cc, gg, hh);
+        CK(hipMemcpyAsync(in.th_cp, a.data(), sizeof(double) * N, hipMemcpyHostToDevice, s));
+        CK(hipMemcpyAsync(in.th_im, b.data(), sizeof(double) * N, hipMemcpyHostToDevice, s));
+        CK(hipMemcpyAsync(in.th_lo, cc.data(), sizeof(double) * N, hipMemcpyHostToDevice, s));
+        CK(hipMemcpyAsync(in.th_G, gg.data(), sizeof(double) * N, hipMemcpyHostToDevice, s));
+        CK(hipMemcpyAsync(in.th_H, hh.data(), sizeof(double) * N, hipMemcpyHostToDevice, s));
+        CK(hipStreamSynchronize(s));
+    }
     if (in.I.spline3) {
         const long long X = (long long)(in.c.nr + 3) * (in.c.nz + 3);
         in.Qx = dalloc<long long>(ctx, X);
