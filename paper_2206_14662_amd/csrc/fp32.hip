@@ -102,6 +102,8 @@ struct KArgs {
     const long long* new_base;     // per instance: slots of the sorted output
     unsigned long long* queue;     // real collision events: (instance << 40) | slot
     long long qcap;
+    unsigned int* crec;            // per (workgroup, chunk): survivors per neighbouring tile, from COUNT
+    int crec_max;                  // chunks per workgroup with a record
     int n_inst, n_tiles, TR, TZ, halo, C, win_max;
     int win3_max;                  // ghosted cubic window nodes (even; 0 without cubic shapes)
 };
@@ -737,6 +739,11 @@ __device__ __forceinline__ void particles_body(const KArgs& A) {
     // than left to the last ones.
     const long long total = A.ctl[CTL_TOTAL], nsorted = A.ctl[CTL_SORTED];
     const long long G = gridDim.x, wg = blockIdx.x;
+    // The sorted part is cut into the same chunks in every step between two
+    // sorts, so the counting step records each chunk's survivors per
+    // neighbouring tile and the sorting step reserves its destinations from
+    // that record instead of reading the positions a second time.
+    int kc = 0;
     for (int part = 0; part < 2; ++part) {
         const long long n_part = part ? total - nsorted : nsorted;
         const long long per = n_part / G, rmd = n_part % G;
@@ -786,6 +793,9 @@ __device__ __forceinline__ void particles_body(const KArgs& A) {
             const PSet out = SCATTER ? A.out : A.p;
             const int W = I.W;
             const bool win = tr0 >= 0;
+            const bool rec = win && kc < A.crec_max;
+            const long long rbase = (wg * A.crec_max + kc) * 9;
+            if (win) ++kc;
             const int ti_c = win ? tr0 / A.TR : 0, tj_c = win ? tz0 / A.TZ : 0;
             int i0 = 0, i1 = -1, j0 = 0, j1 = -1, ww = 1;
             if (win) {
@@ -811,10 +821,12 @@ __device__ __forceinline__ void particles_body(const KArgs& A) {
                 }
             }
             if (SCATTER && win) {
-                // pass 1: destinations of this chunk's particles per neighbouring tile
+                // pass 1: destinations of this chunk's particles per neighbouring
+                // tile, unless the counting step recorded them
+                const bool from_rec = !COUNT && rec;
                 const LocalInst L1 = local_inst(I);
                 const int lead = (int)(start & 63);
-                for (int base = -lead; base < count; base += kPWG) {
+                for (int base = from_rec ? count : -lead; base < count; base += kPWG) {
                     const int q = base + tid;
                     const bool in = q >= 0 && q < count;
                     const long long p = start + (in ? q : 0);
@@ -832,9 +844,9 @@ __device__ __forceinline__ void particles_body(const KArgs& A) {
                         return 0u;
                     });
                 }
-                __syncthreads();
+                if (!from_rec) __syncthreads();
                 if (tid < 9) {
-                    unsigned int n = s_bcnt[tid];
+                    unsigned int n = from_rec ? A.crec[rbase + tid] : s_bcnt[tid];
                     if (n) {
                         int t = I.tile_off + (ti_c + tid / 3 - 1) * I.ntz + (tj_c + tid % 3 - 1);
                         s_bbase[tid] = atomicAdd(&A.tile_fill[t], n);
@@ -898,6 +910,7 @@ __device__ __forceinline__ void particles_body(const KArgs& A) {
             if (COUNT && win && tid < 9) {
                 const unsigned int v = s_ccnt[tid];
                 if (v) atomicAdd(&A.cnt_out[I.tile_off + (ti_c + tid / 3 - 1) * I.ntz + (tj_c + tid % 3 - 1)], v);
+                if (!SCATTER && rec) A.crec[rbase + tid] = v;
             }
             __syncthreads();
             for (unsigned int t = tid; t < q_lds; t += kPWG) {
@@ -1339,6 +1352,10 @@ unsigned int grid_for(long long n, long long cap = 16384) {
 // host side
 // ---------------------------------------------------------------------------
 
+// Chunks per workgroup whose neighbouring-tile counts the counting step
+// records for the sorting step (later chunks count again).
+constexpr int kRecMax = 64;
+
 struct F32State {
     int TR = 8, TZ = 32, halo = 8, K = 16, C = 1 << 22, win_max = 0, win3_max = 0;
     bool ins = false;  // some instance has the elliptic insert
@@ -1358,6 +1375,7 @@ struct F32State {
     long long* ctl = nullptr;
     unsigned int* cbuf[2] = {nullptr, nullptr};  // per-tile totals counted for the next sort
     unsigned int* tile_fill = nullptr;
+    unsigned int* crec = nullptr;         // chunk records of the counting step (kRecMax per workgroup)
     unsigned long long* queue = nullptr;  // real collision events of one step
     long long qcap = 0;
     FieldDev* dF = nullptr;  // field table (owned by the context)
@@ -1401,6 +1419,8 @@ static KArgs kargs(pic_ctx* ctx, F32State* S, int set) {
     A.ctl = S->ctl;
     A.cnt_out = nullptr;
     A.tile_fill = S->tile_fill;
+    A.crec = S->crec;
+    A.crec_max = kRecMax;
     A.tile_start = S->tstart[set];
     A.tile_dst = S->tstart[1 - set];
     A.new_base = S->inst_live;
@@ -1459,7 +1479,7 @@ static pic_status build_tiles(pic_ctx* ctx, F32State* S) {
     S->win_max = win;
     S->win3_max = win3;
     void* old[] = {S->tile_count, S->tstart[0], S->tstart[1], S->tile_lpre, S->vtile,
-                   S->tile_info, S->cbuf[0],   S->cbuf[1],   S->tile_fill};
+                   S->tile_info, S->cbuf[0],   S->cbuf[1],   S->tile_fill, S->crec};
     for (void* q : old) pic_dev_free(ctx, q);
     int toff = 0;
     std::vector<int4> tinfo;
@@ -1499,6 +1519,8 @@ static pic_status build_tiles(pic_ctx* ctx, F32State* S) {
         omin = std::min(omin, occ);
     }
     S->wg_per_cu = omin > 0 ? omin : 1;
+    S->crec = (unsigned int*)pic_dev_alloc(ctx, sizeof(unsigned int) * 9 * kRecMax * (size_t)S->cu * S->wg_per_cu);
+    if (!S->crec) return f32_fail(ctx, PIC_ENOMEM, "FP32 chunk records");
     return PIC_OK;
 }
 
