@@ -1108,9 +1108,16 @@ __global__ void k_zero_q(const DevInst* It, const FieldDev* Ft) {
     const DevInst& I = It[blockIdx.y];
     long long* Q = Ft[blockIdx.y].Q;
     long long* Qw = Ft[blockIdx.y].Qw;
-    for (int n = blockIdx.x * blockDim.x + threadIdx.x; n < I.nodes; n += gridDim.x * blockDim.x) {
-        Q[n] = 0;
-        if (Qw) Qw[n] = 0;
+    // pairs of nodes as 16-byte stores (the arrays are 256-byte aligned), then an odd last node
+    const int pairs = I.nodes / 2;
+    const longlong2 z2 = make_longlong2(0, 0);
+    for (int n = blockIdx.x * blockDim.x + threadIdx.x; n < pairs; n += gridDim.x * blockDim.x) {
+        reinterpret_cast<longlong2*>(Q)[n] = z2;
+        if (Qw) reinterpret_cast<longlong2*>(Qw)[n] = z2;
+    }
+    if ((I.nodes & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
+        Q[I.nodes - 1] = 0;
+        if (Qw) Qw[I.nodes - 1] = 0;
     }
     if (I.spline3) {  // the ghosted cubic grid
         long long* Qx = Ft[blockIdx.y].Qx;
@@ -1674,7 +1681,7 @@ static pic_status launch_step(pic_ctx* ctx, F32State* S, hipStream_t s, bool tim
     KArgs A = kargs(ctx, S, S->cur);
     long long max_nodes = 0;
     for (int k = 0; k < n; ++k) max_nodes = std::max<long long>(max_nodes, pic_inst_dev(ctx, k).nodes);
-    hipLaunchKernelGGL(k_zero_q, dim3(grid_for(max_nodes, 1024), n), dim3(kWG), 0, s, A.It, A.Ft);
+    hipLaunchKernelGGL(k_zero_q, dim3(grid_for(max_nodes / 8, 128), n), dim3(kWG), 0, s, A.It, A.Ft);
     CK32(hipGetLastError());
     const unsigned int tgrid = (unsigned int)((S->n_tiles + 255) / 256);
     if (mode & 2) {

@@ -53,6 +53,12 @@ __device__ __forceinline__ void dft8(double2* v) {
     v[3] = cadd(e3, o3); v[7] = csub(e3, o3);
 }
 
+// LDS slot of FFT point i: one spare slot after every 8 points, so that the
+// first pass's writes (8 consecutive points per thread, threads 128 bytes
+// apart) spread over the banks instead of falling on the same four.
+__device__ __forceinline__ int lp(int i) { return i + (i >> 3); }
+inline size_t fft_lds_bytes(int max_nz) { return sizeof(double2) * (size_t)(2 * max_nz + (2 * max_nz) / 8); }
+
 // One Stockham pass of radix R over N points in LDS (in place: every
 // thread reads its 8 / R butterflies' inputs, barrier, writes).  Butterfly
 // j of span Ns reads y[j + r N/R], twiddles input r by exp(-2 pi i r k /
@@ -68,7 +74,7 @@ __device__ __forceinline__ void fft_pass(double2* y, int N, int Ns, const double
         const int j = threadIdx.x + q * blockDim.x;
         if (j < nb) {
 #pragma unroll
-            for (int r = 0; r < R; ++r) v[q * R + r] = y[j + r * nb];
+            for (int r = 0; r < R; ++r) v[q * R + r] = y[lp(j + r * nb)];
         }
     }
     __syncthreads();
@@ -86,7 +92,7 @@ __device__ __forceinline__ void fft_pass(double2* y, int N, int Ns, const double
             else dft2(w);
             const int d = (j - k) * R + k;
 #pragma unroll
-            for (int m = 0; m < R; ++m) y[d + m * Ns] = w[m];
+            for (int m = 0; m < R; ++m) y[lp(d + m * Ns)] = w[m];
         }
     }
     __syncthreads();
@@ -142,7 +148,7 @@ __global__ void __launch_bounds__(kFftMaxBlock) kf_dst(const DevInst* __restrict
                 vb = hasB ? F.rhs[(long long)iB * W + jj] : 0.0;
             }
         }
-        y[j] = make_double2(sg * va, sg * vb);
+        y[lp(j)] = make_double2(sg * va, sg * vb);
         if (open && j == 0) ends[0] = make_double2(va, vb);
         if (open && j == nz) ends[1] = make_double2(va, vb);
     }
@@ -152,8 +158,9 @@ __global__ void __launch_bounds__(kFftMaxBlock) kf_dst(const DevInst* __restrict
         const double2 e0 = ends[0], e1 = ends[1];
         for (int k = threadIdx.x; k <= nz; k += blockDim.x) {
             const double sgn = (k & 1) ? -1.0 : 1.0;
-            double SA = 0.5 * (y[k].x + (e0.x + sgn * e1.x));
-            double SB = 0.5 * (y[k].y + (e0.y + sgn * e1.y));
+            const double2 yk = y[lp(k)];
+            double SA = 0.5 * (yk.x + (e0.x + sgn * e1.x));
+            double SB = 0.5 * (yk.y + (e0.y + sgn * e1.y));
             const long long nA = (long long)iA * W + k, nB = (long long)iB * W + k;
             if (mode == 2) {
                 F.phi[nA] = F.phi_vac[nA] + SA;
@@ -169,7 +176,8 @@ __global__ void __launch_bounds__(kFftMaxBlock) kf_dst(const DevInst* __restrict
     // y = -2i X_A + 2 X_B for odd real inputs A (real part) and B (imag part)
     const double sc = 2.0 / (double)nz;
     for (int k = threadIdx.x + 1; k <= nz - 1; k += blockDim.x) {
-        double XA = -0.5 * y[k].y, XB = 0.5 * y[k].x;
+        const double2 yk = y[lp(k)];
+        double XA = -0.5 * yk.y, XB = 0.5 * yk.x;
         long long nA = (long long)iA * W + k, nB = (long long)iB * W + k;
         if (mode == 2) {
             F.phi[nA] = F.phi_vac[nA] + sc * XA;
@@ -636,7 +644,7 @@ hipError_t launch_solve3_tab(const DevInst* It, const FieldDev* Ft, const FieldD
     hipLaunchKernelGGL(k3_fold, dim3((unsigned)((max_nodes + 255) / 256), n_inst), dim3(256), 0, s, It, F3, bscale);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    size_t lds = sizeof(double2) * 2 * (size_t)max_nz;
+    size_t lds = fft_lds_bytes(max_nz);
     dim3 gdst((unsigned)(max_nr / 2), (unsigned)n_inst);
     const dim3 fb((unsigned)fft_block(max_nz));
     hipLaunchKernelGGL(kf_dst, gdst, fb, lds, s, It, F3, 0, tw, tw_n, 1, bscale);
@@ -661,7 +669,7 @@ hipError_t launch_solve_tab(const DevInst* It, const FieldDev* Ft, int inst_base
                             int max_nr, int max_nz, const double2* tw, int tw_n, int mode,
                             const double* bscale, bool edges, hipStream_t s) {
     if (n_inst <= 0) return hipSuccess;
-    size_t lds = sizeof(double2) * 2 * (size_t)max_nz;
+    size_t lds = fft_lds_bytes(max_nz);
     dim3 gdst((unsigned)(max_nr / 2), (unsigned)n_inst);
     const dim3 fb((unsigned)fft_block(max_nz));
     hipLaunchKernelGGL(kf_dst, gdst, fb, lds, s, It, Ft, inst_base, tw, tw_n, mode, bscale);
@@ -708,7 +716,7 @@ hipError_t launch_sample_tab(const DevInst* It, const FieldDev* Ft, int n_inst, 
 }
 
 hipError_t set_field_kernel_attrs(int max_nz) {
-    size_t lds = sizeof(double2) * 2 * (size_t)max_nz;
+    size_t lds = fft_lds_bytes(max_nz);
     if (lds > 65536)
         return hipFuncSetAttribute((const void*)kf_dst, hipFuncAttributeMaxDynamicSharedMemorySize,
                                    (int)lds);
