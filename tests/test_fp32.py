@@ -44,7 +44,11 @@ def test_invariant_to_tiles_sort_interval_chunk_and_graph():
     assert ref[0][2]["n_ioniz"] > 10 and ref[0][2]["n_elastic"] > 100
     for kw in (dict(tile_r=8, tile_z=8, sort_interval=1, use_graph=0),
                dict(tile_r=4, tile_z=32, sort_interval=3, halo=1, chunk=300),
-               dict(tile_r=32, tile_z=8, sort_interval=16, halo=8, chunk=100000, use_graph=1)):
+               dict(tile_r=32, tile_z=8, sort_interval=16, halo=8, chunk=100000, use_graph=1),
+               # one-particle chunks, a sort every second step: more chunks per
+               # workgroup than the counting step records, so the sorting step
+               # counts the later ones itself
+               dict(tile_r=8, tile_z=16, sort_interval=2, halo=2, chunk=1, use_graph=0)):
         same(ref[0], run32([cfg], 40, **kw)[0])
     same(ref[0], run32([cfg], 40, tile_r=16, tile_z=16, sort_interval=8, use_graph=1)[0])
 
