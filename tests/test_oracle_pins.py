@@ -450,6 +450,61 @@ def test_null_collision_rate_constant_sigma():
     assert dg["n_ioniz"] == 0
 
 
+def test_lotz_cross_section_hand_values():
+    """The Lotz single-shell ionisation cross section a q ln(E/I)/(E I) at a few
+    energies, each value worked out by hand for the workloads' parameters
+    (a = 4.5e-18 m^2 eV^2, q = 2, I = 15.4 eV, so a q = 9e-18):
+      E = 20 eV:    9e-18 * ln(1.298701)  / 308   = 9e-18 * 0.2613648 / 308
+      E = 100 eV:   9e-18 * ln(6.493506)  / 1540  = 9e-18 * 1.8708025 / 1540
+      E = 1000 eV:  9e-18 * ln(64.93506)  / 15400 = 9e-18 * 4.1733877 / 15400
+    zero at and below the threshold, largest at E = e I = 41.8615 eV where it
+    equals a q / (e I^2) = 9e-18 / 644.6677 = 1.396068e-20 m^2."""
+    c = pi.coax64()
+    for E0, sig in ((20.0, 7.637282e-21), (100.0, 1.093326e-20), (1000.0, 2.438993e-21),
+                    (41.86154, 1.396068e-20)):
+        assert oracle.sigma_iz(c, E0) == pytest.approx(sig, rel=2e-6)
+    assert oracle.sigma_iz(c, 15.4) == 0.0 and oracle.sigma_iz(c, 10.0) == 0.0
+    top = oracle.sigma_iz(c, 41.86154)
+    assert all(oracle.sigma_iz(c, E0) < top for E0 in (38.0, 41.0, 42.7, 46.0))
+
+
+def test_null_collision_decision_both_processes():
+    """Elastic and ionising collisions both switched on (Sec. II.A, null-collision
+    MCC): a mono-energetic isotropic 100 eV beam, no fields, one step at
+    nu' dt ~ 0.02.  Each electron is a candidate with probability P_null and then
+    undergoes an elastic event with probability nu_el / nu' and an ionisation with
+    probability nu_iz / nu', nu = n_n sigma(E0) v0, sigma_iz(100 eV) the hand value
+    of the Lotz formula.  The three counts must each lie within 5 sigma of their
+    binomial means; swapping or truncating either branch of the decision (e.g.
+    ionising for R < nu_iz instead of nu_el <= R < nu_el + nu_iz) fails."""
+    E0 = 100.0
+    c = pi.coax64(p_mbar=1.2, E_cap_eV=100.5, M_gas_amu=1e12, diag_interval=1)
+    d = oracle.derive(c)
+    v0 = math.sqrt(2.0 * E0 * E / ME)
+    n = 400000
+    rng = np.random.default_rng(21)
+    u = rng.normal(size=(3, n))
+    u /= np.linalg.norm(u, axis=0)
+    st = dict(r=np.full(n, 5e-3), z=np.full(n, 30e-3), vr=v0 * u[0], vt=v0 * u[1], vz=v0 * u[2],
+              w=np.full(n, c["weight"]), key=np.arange(n, dtype=np.uint64))
+    s = frozen_sim(c, pi.uniform_fields(c), st)
+    s.step(1)
+    dg = s.diag()
+    sig_iz = 1.093326e-20                       # hand value at 100 eV (test above)
+    nu_el = d["n_n"] * c["sigma_el"] * v0
+    nu_iz = d["n_n"] * sig_iz * v0
+    assert 0.01 < d["nu_prime"] * c["dt"] < 0.03 and nu_iz < nu_el < d["nu_prime"]
+
+    def within(count, p):
+        return abs(count - n * p) < 5.0 * math.sqrt(n * p * (1.0 - p))
+
+    assert within(dg["n_null_cand"], d["P_null"])
+    assert within(dg["n_elastic"], d["P_null"] * nu_el / d["nu_prime"])
+    assert within(dg["n_ioniz"], d["P_null"] * nu_iz / d["nu_prime"])
+    assert dg["n_ioniz"] > 500 and dg["n_elastic"] > 5000
+    assert dg["n_live"] == n + dg["n_ioniz"]
+
+
 def _step_pair(c, st):
     """Same particles stepped with and without collisions."""
     f = pi.uniform_fields(c)
