@@ -32,6 +32,9 @@ HBM_PEAK_GBS = 8000.0
 # of these workloads carries its instance's macro-weight, so the weight array
 # is not read (a per-particle weight would add 4 B)
 BYTES_FP32 = 48
+# the same with a per-particle weight array read (4 B more): the accounting of
+# a kernel that streams the whole 24-B state plus the key
+BYTES_FP32_WEIGHTED = 52
 # plain FP64 push kernel: read r, z, vr, vt, vz (5 x 8 B) + w on absorption only, write 5 x 8 B
 BYTES_FP64_PUSH = 80
 
@@ -124,7 +127,42 @@ def cpu_baseline(cfg0, target_s=15.0):
     return {"value": ps / dt, "unit": "particle-steps/s", "cores": oracle.num_threads(), "kind": "oracle",
             "sample": f"instance 0 of the workload ({cfg0['nr']}x{cfg0['nz']} mesh, {int(cfg0['n_init'])} electrons, "
                       f"p={cfg0['p_mbar']:g} mbar), {k} steps after one warm step, incl. FP64 Poisson, "
-                      f"{dt:.1f} s timed"}
+                      f"{dt:.1f} s timed",
+            "build": "gcc -O3 -ffp-contract=off -fopenmp (plain C11, FP64)",
+            **host_cpu()}
+
+
+def host_cpu():
+    """The host's CPU model, its physical cores and hardware threads (from
+    /proc/cpuinfo) and the CPUs this process may run on."""
+    model, phys, logical = None, set(), 0
+    pid, core = None, None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                k, _, v = line.partition(":")
+                k, v = k.strip(), v.strip()
+                if k == "processor":
+                    logical += 1
+                elif k == "model name" and model is None:
+                    model = v
+                elif k == "physical id":
+                    pid = v
+                elif k == "core id":
+                    core = v
+                elif not k and pid is not None and core is not None:
+                    phys.add((pid, core))
+                    pid, core = None, None
+        if pid is not None and core is not None:
+            phys.add((pid, core))
+    except OSError:
+        pass
+    try:
+        allowed = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        allowed = None
+    return {"cpu_model": model, "host_physical_cores": len(phys) or None, "host_hw_threads": logical or None,
+            "cpus_allowed": allowed}
 
 
 def accuracy(B, torch, workload, steps, p_mbar=None, ref="gpu64"):
@@ -329,6 +367,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "k_particles", "bytes_per_particle_step": BYTES_FP32,
+                     "frac_52B": achieved * BYTES_FP32_WEIGHTED / BYTES_FP32 / HBM_PEAK_GBS,
                      "avg_launch_ms": kern_avg_ms, "launches": ev["launches"],
                      "far_deposit_fraction": ev["far_frac"],
                      "timed_with": "HIP events around each launch, plain launches, same workload and run"},

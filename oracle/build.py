@@ -13,7 +13,7 @@ LIB = os.path.join(HERE, "liborc.so")
 
 
 def build(verbose=False):
-    cmd = ["gcc", "-std=c11", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
+    cmd = ["gcc", "-std=c11", "-O3", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
            "-fPIC", "-shared", "-D_GNU_SOURCE", "-Wall", "-Wno-unknown-pragmas",
            "-o", LIB + ".tmp"] + [os.path.join(HERE, s) for s in SOURCES] + ["-lm"]
     if verbose:
