@@ -24,8 +24,9 @@
  *     released by pic_destroy(); it comes from the caller's allocator when
  *     one is given in pic_run_cfg, else from hipMalloc.
  *   - pic_step() is asynchronous on the context's stream.  Device-side error
- *     flags (spawn overflow, fixed-point overflow) are sticky and reported by
- *     the next call that synchronises (pic_diag, pic_get_*, pic_sync).
+ *     flags (spawn overflow, fixed-point overflow, a non-finite particle) are
+ *     sticky and reported by the next call that synchronises (pic_diag,
+ *     pic_get_*, pic_sync); pic_diag still fills its output then.
  *   - One context must not be used from two host threads at once.
  */
 #ifndef PIC_H
@@ -46,7 +47,10 @@ typedef enum {
     PIC_EDEVICE = -3,    /* HIP runtime error (message in pic_last_error)        */
     PIC_ECAPACITY = -4,  /* particle storage full: new electrons were dropped    */
     PIC_EOVERFLOW = -5,  /* a weight does not fit the fixed-point charge scale   */
-    PIC_ESTATE = -6      /* call not valid in the current state                  */
+    PIC_ESTATE = -6,     /* call not valid in the current state                  */
+    PIC_ENONFINITE = -7  /* a particle's new position was not finite (NaN or inf,
+                            e.g. from a non-finite field value): it was removed
+                            and counted in n_nonfinite, not as absorbed charge   */
 } pic_status;
 
 typedef enum {
@@ -157,6 +161,9 @@ typedef struct {
     long long particle_steps;  /* live macro-electrons pushed, summed over steps */
     long long n_far_deposit;   /* FP32 form: deposits that missed the LDS window */
     long long n_source;        /* electrons created by the seed source           */
+    long long n_nonfinite;     /* particles removed because their new position was
+                                  not finite; > 0 makes every synchronising call
+                                  return PIC_ENONFINITE (sticky)                  */
 } pic_diag_t;
 
 /* Host-derived constants of an instance (FP64); see pic_derive. */
@@ -178,8 +185,9 @@ typedef struct {
  * (Sec. III.A initial homogeneous Maxwellian cloud), deposit them and solve
  * for the first field.  run->n_instances entries of inst are read.
  * Errors: PIC_EINVAL (bad configuration; nz must be a power of two),
- * PIC_ENOMEM, PIC_EDEVICE, PIC_EOVERFLOW (weight too large for S).  On
- * error *out is NULL and nothing is leaked.
+ * PIC_ENOMEM, PIC_EDEVICE, PIC_EOVERFLOW (weight 2^S above 2^31 for an
+ * explicit fx_shift; checked before any device call).  On error *out is
+ * NULL and nothing is leaked.
  */
 pic_status pic_init(const pic_run_cfg* run, const pic_instance_cfg* inst, pic_ctx** out);
 
@@ -218,6 +226,8 @@ pic_status pic_sync(pic_ctx* ctx);
  * the live count.  Keys identify particles across steps: loaded electrons
  * have keys 0..n_init-1, electrons created by ionisation have the top bit
  * set.  If cap < *n only cap entries are written and PIC_EINVAL is returned.
+ * After a sticky device error (PIC_ECAPACITY, PIC_ENONFINITE) the arrays
+ * are still filled and that status is returned.
  */
 pic_status pic_get_particles(pic_ctx* ctx, int inst, double* r, double* z, double* vr,
                              double* vt, double* vz, double* w, unsigned long long* key,
@@ -226,8 +236,10 @@ pic_status pic_get_particles(pic_ctx* ctx, int inst, double* r, double* z, doubl
 /*
  * pic_set_particles -- replace instance `inst`'s particles with n host FP64
  * particles (velocities are v^{n-1/2}), redeposit and, unless the field is
- * frozen, solve for the field.  Every particle must lie in a<r<b, 0<z<L.
- * Errors: PIC_EINVAL, PIC_ECAPACITY (n above the slots), PIC_EOVERFLOW.
+ * frozen, solve for the field.  Every particle must lie in a<r<b, 0<z<L
+ * with finite velocity components and a weight > 0.
+ * Errors: PIC_EINVAL, PIC_ECAPACITY (n above the slots), PIC_EOVERFLOW
+ * (a weight with w 2^S > 2^31).
  */
 pic_status pic_set_particles(pic_ctx* ctx, int inst, long long n, const double* r,
                              const double* z, const double* vr, const double* vt,
@@ -238,7 +250,10 @@ pic_status pic_set_particles(pic_ctx* ctx, int inst, long long n, const double* 
  * pic_set_fields -- overwrite instance `inst`'s nodal fields with host FP64
  * node arrays (NULL leaves a component unchanged).  frozen = 1 keeps E fixed
  * (the Poisson stage is skipped; charge is still deposited), frozen = 0
- * returns to the self-consistent field at the next solve.
+ * returns to the self-consistent field at the next solve.  Values are not
+ * checked: a particle that gathers a non-finite value gets a non-finite
+ * position, is removed and makes later synchronising calls return
+ * PIC_ENONFINITE.
  */
 pic_status pic_set_fields(pic_ctx* ctx, int inst, const double* Er, const double* Ez,
                           const double* Br, const double* Bz, int frozen);

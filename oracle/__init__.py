@@ -52,6 +52,7 @@ class OrcDiag(C.Structure):
         ("I_wall", C.c_double * 4), ("peak_density", C.c_double),
         ("peak_I_outer", C.c_double), ("peak_I_inner", C.c_double),
         ("n_source", C.c_int64),
+        ("n_nonfinite", C.c_int64),
     ]
 
 
@@ -88,6 +89,10 @@ def lib():
         L.orc_efield.argtypes = [C.POINTER(OrcCfg), _D, _D, _D]
         L.orc_node_volume.argtypes = [C.POINTER(OrcCfg), _D]
         L.orc_deposit_one.argtypes = [C.POINTER(OrcCfg), C.c_double, C.c_double, C.c_double, _I64]
+        L.orc_xs_bound.argtypes = [C.c_double]
+        L.orc_xs_bound.restype = C.c_double
+        L.orc_null_candidates.argtypes = [C.POINTER(OrcCfg), C.c_uint32, C.c_int64, _U64, C.POINTER(C.c_uint8)]
+        L.orc_deposit_f32.argtypes = [C.POINTER(OrcCfg), C.c_int64, _D, _D, _D, _I64]
         L.orc_create.argtypes = [C.POINTER(OrcCfg), C.c_int64]
         L.orc_create.restype = C.c_void_p
         L.orc_destroy.argtypes = [C.c_void_p]
@@ -269,6 +274,27 @@ def deposit_one(d, r, z, w, fx_shift=None):
     return Q.reshape(_shape(d))
 
 
+def deposit_f32(d, r, z, w, fx_shift=None):
+    """The deposit of particles (r, z, w) taken in single precision from their
+    FP32 values: the node charges the batched FP32 form must produce."""
+    c = make_cfg(d, fx_shift)
+    r, z, w = (np.ascontiguousarray(a, dtype=np.float64) for a in (r, z, w))
+    Q = np.zeros(_nodes(d), dtype=np.int64)
+    lib().orc_deposit_f32(C.byref(c), len(r), _dp(r), _dp(z), _dp(w), Q.ctypes.data_as(_I64))
+    return Q.reshape(_shape(d))
+
+
+def null_candidates(d, step, keys):
+    """Boolean mask: which electrons (by key) are null-collision candidates
+    at `step` (the analytic model's P_null)."""
+    c = make_cfg(d)
+    keys = np.ascontiguousarray(keys, dtype=np.uint64)
+    out = np.zeros(len(keys), dtype=np.uint8)
+    lib().orc_null_candidates(C.byref(c), int(step) & 0xFFFFFFFF, len(keys), keys.ctypes.data_as(_U64),
+                              out.ctypes.data_as(C.POINTER(C.c_uint8)))
+    return out.astype(bool)
+
+
 def well_depth(d, phi, r_mid):
     """Well depth (V) and the position of the potential maximum along the
     field lines through r_mid at the midplane."""
@@ -327,6 +353,10 @@ def xs_at(E, s, x):
     E = np.ascontiguousarray(E, dtype=np.float64)
     s = np.ascontiguousarray(s, dtype=np.float64)
     return lib().orc_xs_at(len(E), _dp(E), _dp(s), float(x))
+
+
+def xs_bound(sigv_max):
+    return lib().orc_xs_bound(float(sigv_max))
 
 
 def xs_sigv_max(d, E, el, iz):

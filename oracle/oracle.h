@@ -92,6 +92,7 @@ typedef struct {
     double peak_density;       /* time max of the spatial max (m^-3)            */
     double peak_I_outer, peak_I_inner;
     int64_t n_source;          /* electrons created by the seed source          */
+    int64_t n_nonfinite;       /* removed with a non-finite new position        */
 } orc_diag;
 
 typedef struct orc_sim orc_sim;
@@ -107,6 +108,7 @@ void   orc_scatter(double ur, double ut, double uz, double cosx, double phi, dou
 double orc_sigma_iz(const orc_cfg* c, double E_eV);
 double orc_xs_at(int n, const double* E, const double* s, double x);
 double orc_xs_sigv_max(const orc_cfg* c, int n, const double* E, const double* el, const double* iz);
+double orc_xs_bound(double sigv_max);   /* widened by 2^-20, rounded up to 12 bits */
 
 /* Node arrays are r-major: node (i,j) at i*(nz+1)+j, i in [0,nr], j in [0,nz]. */
 void orc_bfield(const orc_cfg* c, double* Br, double* Bz);
@@ -116,6 +118,10 @@ void orc_poisson_charge(const orc_cfg* c, const int64_t* Q, double* phi_sc);
 void orc_efield(const orc_cfg* c, const double* phi, double* Er, double* Ez);
 void orc_node_volume(const orc_cfg* c, double* V);
 void orc_deposit_one(const orc_cfg* c, double r, double z, double w, int64_t* Q);
+/* The same deposit of n particles into a zeroed node array Q, evaluated in
+ * single precision from the FP32 values of r, z and w (orc_fp32.c). */
+void orc_deposit_f32(const orc_cfg* c, int64_t n, const double* r, const double* z, const double* w,
+                     int64_t* Q);
 /* Potential-well depth along the configured magnetic field lines (Sec. II.B):
  * line l passes r_mid[l] at z = L/2 and keeps r^2 Bz(z) constant; phi is
  * sampled (bilinearly) at every node column inside a < r < b; depth[l] =
@@ -161,6 +167,9 @@ void     orc_s3_solve(const orc_s3* S, const orc_cfg* c, const int64_t* Qx, doub
 void     orc_s3_field(const orc_cfg* c, const double* cx, double r, double z, double* Er, double* Ez);
 double   orc_s3_phi_at(const orc_cfg* c, const double* cx, double r, double z);
 int      orc_s3_poisson_fn(const orc_cfg* c, double (*f)(double, double, void*), void* user, double* cx);
+
+/* null-collision candidates among n electrons at a step (analytic model) */
+void orc_null_candidates(const orc_cfg* c, uint32_t step, int64_t n, const uint64_t* key, uint8_t* out);
 
 /* ---- simulation object ---- */
 orc_sim* orc_create(const orc_cfg* c, int64_t capacity);

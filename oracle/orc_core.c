@@ -195,6 +195,15 @@ double orc_xs_sigv_max(const orc_cfg* c, int n, const double* E, const double* e
     return best;
 }
 
+/* The null-collision bound of a table in use: the maximum of sigma v widened
+ * by 2^-20, then rounded up to 12 significant bits, so the bound does not
+ * depend on how the maximum's own rounding came out. */
+double orc_xs_bound(double sigv_max) {
+    int e;
+    const double m = frexp(sigv_max * (1.0 + 0x1p-20), &e);
+    return ldexp(ceil(ldexp(m, 12)), e - 12);
+}
+
 /* Single-shell Lotz ionisation cross section (m^2) at energy E (eV). */
 double orc_sigma_iz(const orc_cfg* c, double E_eV) {
     if (!(E_eV > c->iz_I_eV)) return 0.0;

@@ -124,7 +124,8 @@ void orc_deposit_one(const orc_cfg* c, double r, double z, double w, int64_t* Q)
 }
 
 /* ---- push: Boris in the local (r,theta,z) frame, then the remap ---- */
-/* returns -1 if the particle survives, else the wall index 0..3 */
+/* returns -1 if the particle survives, the wall index 0..3 if an electrode
+ * or an end absorbs it, 4 if its new position is not finite */
 static inline int push_one(const orc_sim* s, int64_t p, double* rr, double* zz,
                            double* vrr, double* vtt, double* vzz) {
     const orc_cfg* c = &s->c;
@@ -163,8 +164,13 @@ static inline int push_one(const orc_sim* s, int64_t p, double* rr, double* zz,
     double x = r + vr * c->dt;
     double y = vt * c->dt;
     double zn = z + vz * c->dt;
-    double rn = sqrt(x * x + y * y);
+    double rr2 = x * x + y * y;
+    double rn = sqrt(rr2);
     int wall = -1;
+    /* a new position that is not finite (from a non-finite field value or
+     * velocity) removes the particle; it is counted apart, not as charge
+     * absorbed by an electrode */
+    if (!(isfinite(rr2) && isfinite(zn))) return 4;
     if (rn <= c->a) wall = 0;
     else if (rn >= c->b) wall = 1;
     else if (s->ins && orc_ins_g(c, rn, zn) <= 0.0) wall = 1;   /* the insert is part of the outer electrode */
@@ -257,6 +263,22 @@ static inline int mcc_one(const orc_sim* s, int64_t p, orc_part* child) {
     child->w = s->w[p];
     child->key = ((((uint64_t)b3[2]) << 32) | (uint64_t)b3[3]) | (1ull << 63);
     return 2;
+}
+
+/* Which of n electrons (by key) are null-collision candidates at step
+ * `step` of an instance with the analytic cross sections: the first uniform
+ * of Philox block 0 below P_null (the test mcc_one starts with). */
+void orc_null_candidates(const orc_cfg* c, uint32_t step, int64_t n, const uint64_t* key, uint8_t* out) {
+    orc_derived d;
+    orc_derive(c, &d);
+    const uint32_t k[2] = {(uint32_t)c->seed, (uint32_t)(c->seed >> 32)};
+#pragma omp parallel for schedule(static)
+    for (int64_t p = 0; p < n; ++p) {
+        const uint32_t ctr[4] = {(uint32_t)key[p], (uint32_t)(key[p] >> 32), step, 0u};
+        uint32_t o[4];
+        orc_philox4x32_10(ctr, k, o);
+        out[p] = orc_u52(o[0], o[1]) < d.P_null ? 1 : 0;
+    }
 }
 
 /* ---- deposit of all particles into s->Q (per-thread grids, exact sums) ---- */
@@ -494,8 +516,8 @@ int orc_set_cross_sections(orc_sim* s, int n, const double* E, const double* el,
     memcpy(s->xs_E, E, sizeof(double) * n);
     memcpy(s->xs_el, el, sizeof(double) * n);
     memcpy(s->xs_iz, iz, sizeof(double) * n);
-    /* the bound, widened by 2^-20 against rounding */
-    s->d.nu_prime = (s->d.n_n * orc_xs_sigv_max(&s->c, n, E, el, iz)) * (1.0 + 0x1p-20);
+    /* the bound, widened and rounded up (orc_xs_bound) */
+    s->d.nu_prime = s->d.n_n * orc_xs_bound(orc_xs_sigv_max(&s->c, n, E, el, iz));
     s->d.P_null = -expm1(-(s->d.nu_prime * s->c.dt));
     return 0;
 }
@@ -595,6 +617,10 @@ int orc_step(orc_sim* s, int n_steps) {
         for (int64_t p = 0; p < n; ++p) wall[p] = push_one(s, p, s->r, s->z, s->vr, s->vt, s->vz);
         int64_t m = 0;
         for (int64_t p = 0; p < n; ++p) {
+            if (wall[p] == 4) {
+                s->dg.n_nonfinite += 1;
+                continue;
+            }
             if (wall[p] >= 0) {
                 s->dg.n_absorbed[wall[p]] += 1;
                 s->dg.absorbed_W[wall[p]] += (int64_t)rint(s->w[p] * s->d.two_S);

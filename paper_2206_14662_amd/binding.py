@@ -14,9 +14,10 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libpicmcc.so")
 
 PIC_OK, PIC_EINVAL, PIC_ENOMEM, PIC_EDEVICE, PIC_ECAPACITY, PIC_EOVERFLOW, PIC_ESTATE = 0, -1, -2, -3, -4, -5, -6
+PIC_ENONFINITE = -7
 PIC_MODE_FP64_PLAIN, PIC_MODE_FP32_BATCHED = 0, 1
 _STATUS = {0: "PIC_OK", -1: "PIC_EINVAL", -2: "PIC_ENOMEM", -3: "PIC_EDEVICE",
-           -4: "PIC_ECAPACITY", -5: "PIC_EOVERFLOW", -6: "PIC_ESTATE"}
+           -4: "PIC_ECAPACITY", -5: "PIC_EOVERFLOW", -6: "PIC_ESTATE", -7: "PIC_ENONFINITE"}
 
 
 class PicError(RuntimeError):
@@ -76,6 +77,7 @@ class pic_diag_t(C.Structure):
         ("particle_steps", C.c_longlong),
         ("n_far_deposit", C.c_longlong),
         ("n_source", C.c_longlong),
+        ("n_nonfinite", C.c_longlong),
     ]
 
 
@@ -282,7 +284,7 @@ def pic_diag(ctx, inst, nodes=None, want_density=False):
     st = lib().pic_diag(ctx, int(inst), C.byref(out),
                         dens.ctypes.data_as(_D) if dens is not None else None,
                         avg.ctypes.data_as(_D) if avg is not None else None)
-    if st not in (PIC_OK, PIC_ECAPACITY, PIC_EOVERFLOW):
+    if st not in (PIC_OK, PIC_ECAPACITY, PIC_EOVERFLOW, PIC_ENONFINITE):
         _check(st, ctx)
     d = {}
     for name, _ in pic_diag_t._fields_:
@@ -298,8 +300,10 @@ def pic_get_particles(ctx, inst, cap):
     a = [np.zeros(cap) for _ in range(6)]
     key = np.zeros(cap, dtype=np.uint64)
     n = C.c_longlong()
-    _check(lib().pic_get_particles(ctx, int(inst), *[x.ctypes.data_as(_D) for x in a],
-                                   key.ctypes.data_as(_ULL), int(cap), C.byref(n)), ctx)
+    st = lib().pic_get_particles(ctx, int(inst), *[x.ctypes.data_as(_D) for x in a],
+                                 key.ctypes.data_as(_ULL), int(cap), C.byref(n))
+    if st not in (PIC_OK, PIC_ECAPACITY, PIC_ENONFINITE):
+        _check(st, ctx)
     m = n.value
     out = dict(zip(("r", "z", "vr", "vt", "vz", "w"), [x[:m] for x in a]))
     out["key"] = key[:m]

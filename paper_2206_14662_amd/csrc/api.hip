@@ -490,9 +490,7 @@ static void fill_devinst(Inst& in) {
     I.has_ins = (c.ins_er > 0.0 && c.ins_ez > 0.0) ? 1 : 0;
     I.spline3 = c.spline_order == 3 ? 1 : 0;
     if (I.has_ins) {
-        const double band = c.ins_band > 0.0 ? c.ins_band : 3.0;
-        I.ins_r0 = c.ins_r0; I.ins_z0 = c.ins_z0; I.ins_er = c.ins_er; I.ins_ez = c.ins_ez;
-        I.ins_gam = 2.0 * band * std::max(d.dr / c.ins_er, d.dz / c.ins_ez);
+        ins_fill(c, d.dr, d.dz, I);
         I.ins_r0_f = (float)c.ins_r0; I.ins_z0_f = (float)c.ins_z0;
         I.ins_inv_er_f = (float)(1.0 / c.ins_er); I.ins_inv_ez_f = (float)(1.0 / c.ins_ez);
         I.ins_gam_f = (float)I.ins_gam;
@@ -1026,6 +1024,10 @@ extern "C" pic_status pic_init(const pic_run_cfg* run, const pic_instance_cfg* i
     for (int k = 0; k < run->n_instances; ++k) {
         std::string m = validate(inst[k]);
         if (!m.empty()) return fail(nullptr, PIC_EINVAL, "instance " + std::to_string(k) + ": " + m);
+        const double w = inst[k].weight > 0.0 ? inst[k].weight : 1.0;
+        const int S = inst[k].fx_shift != 0 ? inst[k].fx_shift : pic_auto_shift(w);
+        if (ldexp(w, S) > 2147483648.0)
+            return fail(nullptr, PIC_EOVERFLOW, "instance " + std::to_string(k) + ": weight * 2^S exceeds 2^31");
     }
     pic_ctx* ctx = new pic_ctx();
     ctx->run = *run;
@@ -1210,6 +1212,10 @@ static pic_status check_counts(pic_ctx* ctx, std::vector<long long>& cnt) {
             return fail(ctx, PIC_ECAPACITY, "instance " + std::to_string(k) + ": new electrons dropped (storage full)");
         if (cnt[k * C_NCOUNT + C_OVERFLOW] > 0)
             return fail(ctx, PIC_EOVERFLOW, "instance " + std::to_string(k) + ": fixed-point overflow");
+        if (cnt[k * C_NCOUNT + C_NONFIN] > 0)
+            return fail(ctx, PIC_ENONFINITE, "instance " + std::to_string(k) + ": " +
+                                                 std::to_string(cnt[k * C_NCOUNT + C_NONFIN]) +
+                                                 " particles with a non-finite position removed");
     }
     if (ctx->mode == PIC_MODE_FP32_BATCHED) return f32_check(ctx);
     return PIC_OK;
@@ -1374,6 +1380,8 @@ extern "C" pic_status pic_set_particles(pic_ctx* ctx, int k, long long n, const 
     for (long long q = 0; q < n; ++q) {
         if (!(r[q] > in.c.a && r[q] < in.c.b && z[q] > 0.0 && z[q] < in.c.L))
             return fail(ctx, PIC_EINVAL, "particle " + std::to_string(q) + " outside a<r<b, 0<z<L");
+        if (!(std::isfinite(vr[q]) && std::isfinite(vt[q]) && std::isfinite(vz[q])))
+            return fail(ctx, PIC_EINVAL, "particle " + std::to_string(q) + ": non-finite velocity");
         if (!(w[q] > 0.0)) return fail(ctx, PIC_EINVAL, "weights must be > 0");
         if (w[q] * in.d.two_S > 2147483648.0) return fail(ctx, PIC_EOVERFLOW, "weight * 2^S exceeds 2^31");
     }
@@ -1416,9 +1424,12 @@ extern "C" pic_status pic_get_particles(pic_ctx* ctx, int k, double* r, double* 
     if (st != PIC_OK) return st;
     std::vector<long long> cnt;
     st = check_counts(ctx, cnt);
-    if (st != PIC_OK && st != PIC_ECAPACITY) return st;
+    if (st != PIC_OK && st != PIC_ECAPACITY && st != PIC_ENONFINITE) return st;
     Inst& in = ctx->in[k];
-    if (ctx->mode != PIC_MODE_FP64_PLAIN) return f32_get_particles(ctx, k, r, z, vr, vt, vz, w, key, cap, n_out);
+    if (ctx->mode != PIC_MODE_FP64_PLAIN) {
+        const pic_status g = f32_get_particles(ctx, k, r, z, vr, vt, vz, w, key, cap, n_out);
+        return g != PIC_OK ? g : st;
+    }
     long long slots = cnt[(size_t)k * C_NCOUNT + C_SLOTS];
     P64 p = in.p64[in.cur];
     std::vector<double> hr(slots), hz(slots), hvr(slots), hvt(slots), hvz(slots), hw(slots);
@@ -1549,38 +1560,48 @@ extern "C" pic_status pic_get_band_charge(pic_ctx* ctx, int k, long long* Qw) {
     return PIC_OK;
 }
 
-// max over 0 <= E <= E_cap of (sigma_el + sigma_iz)(E) v(E) for a table:
-// every piece between table points, the threshold and E_cap is linear in E,
-// so (alpha + beta E) sqrt(E) peaks at an end or at E = -alpha / (3 beta).
+// Null-collision bound of a cross-section table (Sec. II.A null-collision
+// method): the largest sigma_total(E) v(E) over 0 <= E <= E_cap.  Between
+// consecutive knots (table energies, the ionisation threshold, 0 and E_cap)
+// the total is linear in E, s(E) = s0 + m (E - e0), so s(E) sqrt(E) can
+// only peak at the knots or where m E + s(E) / 2 = 0.  The threshold is a
+// knot on both sides: ionisation is off just below it and on from it.
 static double table_sigv_max(const pic_instance_cfg& c, int n, const double* E, const double* el,
                              const double* iz) {
-    const double two_e_over_me = (2.0 * kE) / kMe;
-    auto total = [&](double x, bool above) {
-        double t = xs_interp(n, E, el, x);
-        if (x > c.iz_I_eV || (above && x == c.iz_I_eV)) t += xs_interp(n, E, iz, x);
-        return t;
+    const double v2_per_eV = (2.0 * kE) / kMe;
+    const double top = c.E_cap_eV, thr = c.iz_I_eV;
+    std::vector<double> knot{0.0, top};
+    for (int t = 0; t < n; ++t)
+        if (E[t] > 0.0 && E[t] < top) knot.push_back(E[t]);
+    if (thr > 0.0 && thr < top) knot.push_back(thr);
+    std::sort(knot.begin(), knot.end());
+    knot.erase(std::unique(knot.begin(), knot.end()), knot.end());
+    // the total cross section at x, approached from above (up) or below
+    auto sigma = [&](double x, bool up) {
+        const bool ion = up ? x >= thr : x > thr;
+        return xs_interp(n, E, el, x) + (ion ? xs_interp(n, E, iz, x) : 0.0);
     };
-    std::vector<double> cut;
-    cut.push_back(0.0);
-    for (int k = 0; k < n; ++k)
-        if (E[k] > 0.0 && E[k] < c.E_cap_eV) cut.push_back(E[k]);
-    if (c.iz_I_eV > 0.0 && c.iz_I_eV < c.E_cap_eV) cut.push_back(c.iz_I_eV);
-    cut.push_back(c.E_cap_eV);
-    std::sort(cut.begin(), cut.end());
-    double best = 0.0;
-    for (size_t i = 0; i + 1 < cut.size(); ++i) {
-        const double p = cut[i], q = cut[i + 1];
-        if (!(q > p)) continue;
-        const double sp = total(p, true), sq = total(q, false);
-        best = std::max(best, sp * sqrt(p * two_e_over_me));
-        best = std::max(best, sq * sqrt(q * two_e_over_me));
-        const double beta = (sq - sp) / (q - p), alpha = sp - beta * p;
-        if (beta < 0.0 && alpha > 0.0) {
-            const double x = -alpha / (3.0 * beta);
-            if (x > p && x < q) best = std::max(best, (alpha + beta * x) * sqrt(x * two_e_over_me));
+    auto sv = [&](double s, double x) { return s * sqrt(x * v2_per_eV); };
+    double peak = 0.0;
+    for (size_t t = 1; t < knot.size(); ++t) {
+        const double e0 = knot[t - 1], e1 = knot[t];
+        const double s0 = sigma(e0, true), s1 = sigma(e1, false);
+        peak = std::max({peak, sv(s0, e0), sv(s1, e1)});
+        const double m = (s1 - s0) / (e1 - e0);
+        if (m < 0.0) {
+            const double x = (m * e0 - s0) / (3.0 * m);
+            if (x > e0 && x < e1) peak = std::max(peak, sv(s0 + m * (x - e0), x));
         }
     }
-    return best;
+    return peak;
+}
+
+// The bound in use: the maximum widened by 2^-20 and rounded up to 12
+// significant bits, so it does not depend on the maximum's own rounding.
+static double table_bound(double sigv_max) {
+    int ex;
+    const double frac = frexp(sigv_max * (1.0 + 0x1p-20), &ex);
+    return ldexp(ceil(frac * 4096.0), ex - 12);
 }
 
 extern "C" pic_status pic_set_cross_sections(pic_ctx* ctx, int k, int n, const double* E_eV,
@@ -1623,8 +1644,7 @@ extern "C" pic_status pic_set_cross_sections(pic_ctx* ctx, int k, int n, const d
         CK(hipStreamSynchronize(ctx->stream));
         if (!ok) return fail(ctx, PIC_ENOMEM, "device allocation of the cross-section table failed");
         I.xs_n = n;
-        // the bound, widened by 2^-20 against rounding
-        d.nu_prime = (d.n_n * table_sigv_max(in.c, n, E_eV, sigma_el, sigma_iz)) * (1.0 + 0x1p-20);
+        d.nu_prime = d.n_n * table_bound(table_sigv_max(in.c, n, E_eV, sigma_el, sigma_iz));
         d.P_null = -expm1(-(d.nu_prime * in.c.dt));
     }
     in.d.nu_prime = d.nu_prime;
@@ -1715,7 +1735,7 @@ extern "C" pic_status pic_diag(pic_ctx* ctx, int k, pic_diag_t* out, double* den
     if (!out) return fail(ctx, PIC_EINVAL, "out is NULL");
     std::vector<long long> all;
     pic_status cs = check_counts(ctx, all);
-    if (cs != PIC_OK && cs != PIC_ECAPACITY && cs != PIC_EOVERFLOW) return cs;
+    if (cs != PIC_OK && cs != PIC_ECAPACITY && cs != PIC_EOVERFLOW && cs != PIC_ENONFINITE) return cs;
     Inst& in = ctx->in[k];
     const long long* c = all.data() + (size_t)k * C_NCOUNT;
     memset(out, 0, sizeof(*out));
@@ -1738,6 +1758,7 @@ extern "C" pic_status pic_diag(pic_ctx* ctx, int k, pic_diag_t* out, double* den
     out->particle_steps = c[C_PSTEPS];
     out->n_far_deposit = c[C_FARDEP];
     out->n_source = c[C_SOURCE];
+    out->n_nonfinite = c[C_NONFIN];
     out->S = in.S;
     if (ctx->mode == PIC_MODE_FP64_PLAIN) out->n_live = c[C_SLOTS] - c[C_DEAD];
     else out->n_live = f32_live_count(ctx, k, c);

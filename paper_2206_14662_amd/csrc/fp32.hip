@@ -389,11 +389,12 @@ constexpr int kLQ = 512;
 
 // chunk-level event counters kept in LDS and their device counter slots
 enum {
-    SC_ABS_N = 0, SC_ABS_W = 4, SC_DEAD = 8, SC_CAND = 9, SC_CAP = 10, SC_FAR = 11, SC_EL = 12, SC_IZ = 13, SC_N = 14
+    SC_ABS_N = 0, SC_ABS_W = 4, SC_DEAD = 8, SC_CAND = 9, SC_CAP = 10, SC_FAR = 11, SC_EL = 12, SC_IZ = 13,
+    SC_NONFIN = 14, SC_N = 15
 };
 __constant__ int kCounterOf[SC_N] = {C_ABS_N,     C_ABS_N + 1, C_ABS_N + 2, C_ABS_N + 3, C_ABS_W,   C_ABS_W + 1,
                                      C_ABS_W + 2, C_ABS_W + 3, C_DEAD,      C_CAND,      C_CAPOVER, C_FARDEP,
-                                     C_ELASTIC,   C_IONIZ};
+                                     C_ELASTIC,   C_IONIZ,     C_NONFIN};
 
 
 // Cubic B-spline weights of the nodes i-1 .. i+2 at offset f in [0, 1) from
@@ -565,7 +566,11 @@ __device__ __forceinline__ void push_particle(const KArgs& A, const ChunkCtx& X,
     const float inv = __builtin_amdgcn_rsqf(rr2);
     const float rn = rr2 * inv;
     int wall = -1;
-    if (rn <= L.a) wall = 0;
+    // a non-finite new position (a non-finite field or velocity) removes the
+    // particle without counting it as absorbed charge; x = y = 0 (rn NaN from
+    // 0 * inf) is the inner wall
+    if (!(rr2 < __builtin_inff() && fabsf(zn) < __builtin_inff())) wall = 4;
+    else if (!(rn > L.a)) wall = 0;
     else if (rn >= L.b) wall = 1;
     else if (INS && L.has_ins && fmaf((rn - L.ins_r0) * L.ins_inv_er, (rn - L.ins_r0) * L.ins_inv_er,
                                ((zn - L.ins_z0) * L.ins_inv_ez) * ((zn - L.ins_z0) * L.ins_inv_ez)) - 1.0f <= 0.0f)
@@ -584,9 +589,13 @@ __device__ __forceinline__ void push_particle(const KArgs& A, const ChunkCtx& X,
     if (live) {
         ++c_push;
         if (wall >= 0) {
-            const unsigned long long Wq = (unsigned long long)(unsigned int)rintf(w * L.two_S);
-            atomicAdd(&X.s_ctr[SC_ABS_N + wall], 1ull);
-            atomicAdd(&X.s_ctr[SC_ABS_W + wall], Wq);
+            if (wall == 4) {
+                atomicAdd(&X.s_ctr[SC_NONFIN], 1ull);
+            } else {
+                const unsigned long long Wq = (unsigned long long)(unsigned int)rintf(w * L.two_S);
+                atomicAdd(&X.s_ctr[SC_ABS_N + wall], 1ull);
+                atomicAdd(&X.s_ctr[SC_ABS_W + wall], Wq);
+            }
             atomicAdd(&X.s_ctr[SC_DEAD], 1ull);
             out.r[dst] = -1.0f;
         }
@@ -1170,32 +1179,60 @@ __global__ void __launch_bounds__(kWG) k_sort_count(KArgs A, unsigned long long*
     }
 }
 
-// Per instance: exclusive scan of the tile totals -> each tile's first slot
-// in the destination store (absolute) and its offset among the instance's
-// sorted particles; the instance's sorted total.
-__global__ void __launch_bounds__(1024) k_sort_plan1(const DevInst* It, const unsigned int* tile_count,
-                                                     long long* tile_start, long long* tile_lpre,
-                                                     long long* inst_live) {
-    __shared__ long long s_cnt[1024];
-    const DevInst& I = It[blockIdx.x];
-    const int nt = I.ntr * I.ntz, base = I.tile_off;
-    const int seg = (nt + 1023) / 1024;
-    const int t0 = threadIdx.x * seg, t1 = min(t0 + seg, nt);
-    long long sc = 0;
-    for (int t = t0; t < t1; ++t) sc += tile_count[base + t];
-    s_cnt[threadIdx.x] = sc;
+// Inclusive prefix sum of v over the 64 lanes of the wave (Hillis-Steele:
+// six cross-lane shifts).
+__device__ __forceinline__ long long wave_inclusive_scan(long long v) {
+    const int lane = __lane_id();
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const long long t = __shfl_up(v, off);
+        if (lane >= off) v += t;
+    }
+    return v;
+}
+
+// Exclusive prefix sum of v over the kScanWG threads of the block (every
+// thread calls it): each wave scans its lanes, the first wave scans the wave
+// totals, each thread adds its wave's offset.  *total gets the block's sum.
+// s_wave is kScanWG / 64 + 1 entries of LDS; the call ends with a barrier,
+// so it can be called again.
+constexpr int kScanWG = 1024;
+__device__ __forceinline__ long long block_exclusive_scan(long long v, long long* s_wave, long long* total) {
+    constexpr int NW = kScanWG / 64;
+    const int lane = __lane_id(), wave = (int)(threadIdx.x >> 6);
+    const long long inc = wave_inclusive_scan(v);
+    if (lane == 63) s_wave[wave] = inc;
     __syncthreads();
-    if (threadIdx.x == 0) {
-        long long a = 0;
-        for (int k = 0; k < 1024; ++k) {
-            long long x = s_cnt[k];
-            s_cnt[k] = a;
-            a += x;
-        }
-        inst_live[blockIdx.x] = a;
+    if (wave == 0) {
+        const long long t = lane < NW ? s_wave[lane] : 0;
+        const long long ti = wave_inclusive_scan(t);
+        if (lane < NW) s_wave[lane] = ti - t;
+        if (lane == NW - 1) s_wave[NW] = ti;
     }
     __syncthreads();
-    long long a = s_cnt[threadIdx.x];
+    const long long ex = s_wave[wave] + (inc - v);
+    *total = s_wave[NW];
+    __syncthreads();
+    return ex;
+}
+
+// Per instance: exclusive scan of the tile totals -> each tile's first slot
+// in the destination store (absolute) and its offset among the instance's
+// sorted particles; the instance's sorted total.  Each thread sums a
+// contiguous run of tiles, the block scans the run totals.
+__global__ void __launch_bounds__(kScanWG) k_sort_plan1(const DevInst* It, const unsigned int* tile_count,
+                                                        long long* tile_start, long long* tile_lpre,
+                                                        long long* inst_live) {
+    __shared__ long long s_wave[kScanWG / 64 + 1];
+    const DevInst& I = It[blockIdx.x];
+    const int nt = I.ntr * I.ntz, base = I.tile_off;
+    const int seg = (nt + kScanWG - 1) / kScanWG;
+    const int t0 = min((int)threadIdx.x * seg, nt), t1 = min(t0 + seg, nt);
+    long long sc = 0;
+    for (int t = t0; t < t1; ++t) sc += tile_count[base + t];
+    long long total;
+    long long a = block_exclusive_scan(sc, s_wave, &total);
+    if (threadIdx.x == 0) inst_live[blockIdx.x] = total;
     for (int t = t0; t < t1; ++t) {
         tile_start[base + t] = I.p_off + a;
         tile_lpre[base + t] = a;
@@ -1204,16 +1241,24 @@ __global__ void __launch_bounds__(1024) k_sort_plan1(const DevInst* It, const un
 }
 
 // Instances' offsets in the step's particle order; total sorted particles.
-__global__ void k_sort_plan2(const long long* inst_live, long long* inst_voff, long long* ctl, long long* vtile,
-                             int n_inst, int n_tiles) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    long long a = 0;
-    for (int k = 0; k < n_inst; ++k) {
-        inst_voff[k] = a;
-        a += inst_live[k];
+// One block scans the instance totals kScanWG at a time with a carry.
+__global__ void __launch_bounds__(kScanWG) k_sort_plan2(const long long* inst_live, long long* inst_voff,
+                                                        long long* ctl, long long* vtile, int n_inst,
+                                                        int n_tiles) {
+    __shared__ long long s_wave[kScanWG / 64 + 1];
+    long long carry = 0;
+    for (int k0 = 0; k0 < n_inst; k0 += kScanWG) {
+        const int k = k0 + (int)threadIdx.x;
+        const long long v = k < n_inst ? inst_live[k] : 0;
+        long long total;
+        const long long ex = block_exclusive_scan(v, s_wave, &total);
+        if (k < n_inst) inst_voff[k] = carry + ex;
+        carry += total;
     }
-    ctl[CTL_SORTED] = a;
-    vtile[n_tiles] = a;
+    if (threadIdx.x == 0) {
+        ctl[CTL_SORTED] = carry;
+        vtile[n_tiles] = carry;
+    }
 }
 
 // Global prefix of sorted particles over all tiles.
@@ -1687,7 +1732,7 @@ static pic_status launch_step(pic_ctx* ctx, F32State* S, hipStream_t s, bool tim
     if (mode & 2) {
         hipLaunchKernelGGL(k_zero_u32, dim3(tgrid), dim3(256), 0, s, S->tile_fill, S->n_tiles);
         CK32(hipGetLastError());
-        hipLaunchKernelGGL(k_sort_plan1, dim3(n), dim3(1024), 0, s, A.It, S->cbuf[S->cur], S->tstart[1 - S->cur],
+        hipLaunchKernelGGL(k_sort_plan1, dim3(n), dim3(kScanWG), 0, s, A.It, S->cbuf[S->cur], S->tstart[1 - S->cur],
                            S->tile_lpre, S->inst_live);
         CK32(hipGetLastError());
         hipLaunchKernelGGL(k_scatter_pre, dim3((n + 63) / 64), dim3(64), 0, s, A.cnt, n);
@@ -1722,7 +1767,7 @@ static pic_status launch_step(pic_ctx* ctx, F32State* S, hipStream_t s, bool tim
         CK32(hipGetLastError());
     }
     if (mode & 2) {
-        hipLaunchKernelGGL(k_sort_plan2, dim3(1), dim3(64), 0, s, S->inst_live, S->inst_voff, S->ctl, S->vtile, n,
+        hipLaunchKernelGGL(k_sort_plan2, dim3(1), dim3(kScanWG), 0, s, S->inst_live, S->inst_voff, S->ctl, S->vtile, n,
                            S->n_tiles);
         CK32(hipGetLastError());
         hipLaunchKernelGGL(k_sort_plan3, dim3(tgrid), dim3(256), 0, s, S->tile_info, S->n_tiles, S->tile_lpre,
@@ -1742,10 +1787,10 @@ static pic_status launch_sort(pic_ctx* ctx, F32State* S, hipStream_t s) {
     unsigned int gx = grid_for(max_slots(ctx), 2048);
     hipLaunchKernelGGL(k_sort_count, dim3(gx, n), dim3(kWG), 0, s, A, S->sortkey, S->tile_count);
     CK32(hipGetLastError());
-    hipLaunchKernelGGL(k_sort_plan1, dim3(n), dim3(1024), 0, s, A.It, S->tile_count, S->tstart[1 - S->cur],
+    hipLaunchKernelGGL(k_sort_plan1, dim3(n), dim3(kScanWG), 0, s, A.It, S->tile_count, S->tstart[1 - S->cur],
                        S->tile_lpre, S->inst_live);
     CK32(hipGetLastError());
-    hipLaunchKernelGGL(k_sort_plan2, dim3(1), dim3(64), 0, s, S->inst_live, S->inst_voff, S->ctl, S->vtile, n,
+    hipLaunchKernelGGL(k_sort_plan2, dim3(1), dim3(kScanWG), 0, s, S->inst_live, S->inst_voff, S->ctl, S->vtile, n,
                        S->n_tiles);
     CK32(hipGetLastError());
     hipLaunchKernelGGL(k_sort_plan3, dim3((S->n_tiles + 255) / 256), dim3(256), 0, s, S->tile_info, S->n_tiles,
@@ -1949,6 +1994,9 @@ static pic_status capacity_check(pic_ctx* ctx, F32State* S, hipStream_t work) {
                 return f32_fail(ctx, PIC_ECAPACITY, "instance " + std::to_string(k) + ": new electrons dropped");
             if (c[C_OVERFLOW] > 0)
                 return f32_fail(ctx, PIC_EOVERFLOW, "instance " + std::to_string(k) + ": fixed-point overflow");
+            if (c[C_NONFIN] > 0)
+                return f32_fail(ctx, PIC_ENONFINITE,
+                                "instance " + std::to_string(k) + ": particles with a non-finite position removed");
             const long long cap = pic_inst_dev(ctx, k).p_cap;
             const long long used = c[C_SLOTS];
             // the lag spans up to two check periods: growth at the rate seen

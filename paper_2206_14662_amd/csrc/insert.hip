@@ -24,8 +24,8 @@
 //     y = A_rect^-1 b,  s = H y_M,  x = y - A_rect^-1 E s,
 // with H = (I + D G)^-1 D, G = (A_rect^-1)_MM set up once from m unit solves.
 #include <algorithm>
+#include <array>
 #include <cmath>
-#include <map>
 #include <string>
 #include <vector>
 
@@ -36,236 +36,295 @@ namespace pic {
 // ---------------------------------------------------------------------------
 // host set-up
 // ---------------------------------------------------------------------------
+
+void ins_fill(const pic_instance_cfg& c, double dr, double dz, DevInst& I) {
+    const double band = c.ins_band > 0.0 ? c.ins_band : 3.0;
+    I.ins_r0 = c.ins_r0;
+    I.ins_z0 = c.ins_z0;
+    I.ins_er = c.ins_er;
+    I.ins_ez = c.ins_ez;
+    I.ins_gam = 2.0 * band * std::max(dr / c.ins_er, dz / c.ins_ez);
+}
+
 namespace {
 
-constexpr int kQDepth = 6;
-constexpr int kExtRadius = 4;
-const double kGX[3] = {-0.77459666924148337704, 0.0, 0.77459666924148337704};
-const double kGW[3] = {5.0 / 9.0, 8.0 / 9.0, 5.0 / 9.0};
+// Cut boxes are split into four down to this many levels; an outer hat looks
+// for its block of inner hats within this many nodes in each direction.
+constexpr int kCutLevels = 6;
+constexpr int kBlockReach = 4;
 
-struct Geo {
-    const pic_instance_cfg* c;
-    DevInst I;  // only the insert fields are used
-    int nr, nz, W, j0, j1;
-    double dr, dz, gam;
-};
+// Three-point Gauss-Legendre rule on [-1, 1].
+constexpr double kGaussX[3] = {-0.77459666924148337704, 0.0, 0.77459666924148337704};
+constexpr double kGaussW[3] = {0.55555555555555555556, 0.88888888888888888889, 0.55555555555555555556};
 
-// exact range of g over a box (sum of convex parabolas: minimum at the
-// clamped centre, maximum at the farthest corner)
-void box_range(const Geo& G, double rl, double rh, double zl, double zh, double& gmin, double& gmax) {
-    const double r0 = G.I.ins_r0, z0 = G.I.ins_z0;
-    const double rc = std::min(std::max(r0, rl), rh), zc = std::min(std::max(z0, zl), zh);
-    const double rf = std::fabs(rl - r0) > std::fabs(rh - r0) ? rl : rh;
-    const double zf = std::fabs(zl - z0) > std::fabs(zh - z0) ? zl : zh;
-    gmin = ins_g(G.I, rc, zc);
-    gmax = ins_g(G.I, rf, zf);
-}
+// How a cell or a box sits against the insert: g > 0 everywhere (free), g
+// changes sign inside (cut), g <= 0 everywhere (metal).
+enum Where { kFree, kCut, kMetal };
 
-void cell_range(const Geo& G, int ci, int cj, double& gmin, double& gmax) {
-    const double rl = G.c->a + (double)ci * G.dr, zl = (double)cj * G.dz;
-    box_range(G, rl, rl + G.dr, zl, zl + G.dz, gmin, gmax);
-}
+// Node roles (pic_insert_layout's counts): 0 not an unknown of the solve,
+// 1 inner hat, 2 outer hat, 3 exterior (all its cells in the metal).
+enum Role { kFixed = 0, kInner = 1, kOuter = 2, kExterior = 3 };
 
-// weight function gradient (the value is ins_w)
-void w_grad(const Geo& G, double r, double z, double g, double& wr, double& wz) {
-    wr = wz = 0.0;
-    if (g <= 0.0 || g >= G.gam) return;
-    const double s = 1.0 - g / G.gam;
-    const double dw = 3.0 * s * s / G.gam;
-    wr = dw * (2.0 * (r - G.I.ins_r0) / (G.I.ins_er * G.I.ins_er));
-    wz = dw * (2.0 * (z - G.I.ins_z0) / (G.I.ins_ez * G.I.ins_ez));
-}
-
-// r-major corners of a cell: (0,0), (1,0), (0,1), (1,1)
-const int kCR[4] = {0, 1, 0, 1}, kCZ[4] = {0, 0, 1, 1};
-
-void q1_element(const Geo& G, int ci, double E[4][4]) {
-    const double rl = G.c->a + (double)ci * G.dr, rh = rl + G.dr, rm = 0.5 * (rl + rh);
-    const double kr2[2][2] = {{rm / G.dr, -rm / G.dr}, {-rm / G.dr, rm / G.dr}};
-    const double mr2[2][2] = {{G.dr * (3.0 * rl + rh) / 12.0, G.dr * (rl + rh) / 12.0},
-                              {G.dr * (rl + rh) / 12.0, G.dr * (rl + 3.0 * rh) / 12.0}};
-    const double kz2[2][2] = {{1.0 / G.dz, -1.0 / G.dz}, {-1.0 / G.dz, 1.0 / G.dz}};
-    const double mz2[2][2] = {{2.0 * G.dz / 6.0, G.dz / 6.0}, {G.dz / 6.0, 2.0 * G.dz / 6.0}};
-    for (int p = 0; p < 4; ++p)
-        for (int q = 0; q < 4; ++q)
-            E[p][q] = kr2[kCR[p]][kCR[q]] * mz2[kCZ[p]][kCZ[q]] + mr2[kCR[p]][kCR[q]] * kz2[kCZ[p]][kCZ[q]];
-}
-
-struct WeightedAcc {
-    double rl, zl;
-    double E[4][4];
-};
-
-void add_point(const Geo& G, WeightedAcc& A, double r, double z, double g, double wq) {
-    const double w = ins_w(G.I, g);
-    double wr, wz;
-    w_grad(G, r, z, g, wr, wz);
-    const double fr = (r - A.rl) / G.dr, fz = (z - A.zl) / G.dz;
-    const double N[4] = {(1.0 - fr) * (1.0 - fz), fr * (1.0 - fz), (1.0 - fr) * fz, fr * fz};
-    const double Nr[4] = {-(1.0 - fz) / G.dr, (1.0 - fz) / G.dr, -fz / G.dr, fz / G.dr};
-    const double Nz[4] = {-(1.0 - fr) / G.dz, -fr / G.dz, (1.0 - fr) / G.dz, fr / G.dz};
-    double gr[4], gz[4];
-    for (int p = 0; p < 4; ++p) {
-        gr[p] = wr * N[p] + w * Nr[p];
-        gz[p] = wz * N[p] + w * Nz[p];
+class InsertMesh {
+public:
+    InsertMesh(const pic_instance_cfg& c) : c_(c) {
+        dr_ = (c.b - c.a) / (double)c.nr;
+        dz_ = c.L / (double)c.nz;
+        ins_fill(c, dr_, dz_, I_);
+        W_ = c.nz + 1;
+        jlo_ = c.end_mode == 2 ? 0 : 1;
+        jhi_ = c.end_mode == 2 ? c.nz : c.nz - 1;
     }
-    const double f = r * wq;
-    for (int p = 0; p < 4; ++p)
-        for (int q = 0; q < 4; ++q) A.E[p][q] += f * (gr[p] * gr[q] + gz[p] * gz[q]);
-}
+    int W() const { return W_; }
+    int nodes() const { return (c_.nr + 1) * W_; }
+    double dr() const { return dr_; }
+    double dz() const { return dz_; }
+    double gam() const { return I_.ins_gam; }
+    double r_of(int i) const { return c_.a + (double)i * dr_; }
+    double z_of(int j) const { return (double)j * dz_; }
+    bool unknown(int i, int j) const { return i >= 1 && i <= c_.nr - 1 && j >= jlo_ && j <= jhi_; }
+    double g(double r, double z) const { return ins_g(I_, r, z); }
+    double w(double g) const { return ins_w(I_, g); }
 
-void weighted_box(const Geo& G, WeightedAcc& A, double rl, double rh, double zl, double zh, int depth) {
-    double gmin, gmax;
-    box_range(G, rl, rh, zl, zh, gmin, gmax);
-    if (gmax <= 0.0) return;
-    if (gmin <= 0.0 && depth < kQDepth) {
-        const double rm = 0.5 * (rl + rh), zm = 0.5 * (zl + zh);
-        weighted_box(G, A, rl, rm, zl, zm, depth + 1);
-        weighted_box(G, A, rm, rh, zl, zm, depth + 1);
-        weighted_box(G, A, rl, rm, zm, zh, depth + 1);
-        weighted_box(G, A, rm, rh, zm, zh, depth + 1);
-        return;
+    // Lowest and highest g over the box [rl, rh] x [zl, zh]: g is a sum of one
+    // square in r and one in z, each monotone away from the centre.
+    void g_range(double rl, double rh, double zl, double zh, double& lo, double& hi) const {
+        double ulo, uhi, vlo, vhi;
+        sq_range((rl - I_.ins_r0) / I_.ins_er, (rh - I_.ins_r0) / I_.ins_er, ulo, uhi);
+        sq_range((zl - I_.ins_z0) / I_.ins_ez, (zh - I_.ins_z0) / I_.ins_ez, vlo, vhi);
+        lo = (ulo + vlo) - 1.0;
+        hi = (uhi + vhi) - 1.0;
     }
-    const double hr = rh - rl, hz = zh - zl;
-    for (int a = 0; a < 3; ++a)
-        for (int b = 0; b < 3; ++b) {
-            const double r = rl + 0.5 * hr * (1.0 + kGX[a]);
-            const double z = zl + 0.5 * hz * (1.0 + kGX[b]);
-            const double g = ins_g(G.I, r, z);
-            if (g <= 0.0) continue;
-            add_point(G, A, r, z, g, (0.25 * hr * hz) * kGW[a] * kGW[b]);
+    Where where(double rl, double rh, double zl, double zh) const {
+        double lo, hi;
+        g_range(rl, rh, zl, zh, lo, hi);
+        return lo > 0.0 ? kFree : (hi > 0.0 ? kCut : kMetal);
+    }
+    void cell_g(int ci, int cj, double& lo, double& hi) const {
+        g_range(r_of(ci), r_of(ci + 1), z_of(cj), z_of(cj + 1), lo, hi);
+    }
+
+    // Gradient of the weight function at (r, z) where g = g(r, z).
+    void w_grad(double r, double z, double g, double& gr, double& gz) const {
+        if (!(g > 0.0 && g < I_.ins_gam)) {
+            gr = gz = 0.0;
+            return;
         }
+        const double t = 1.0 - g / I_.ins_gam;
+        const double dwdg = 3.0 * t * t / I_.ins_gam;
+        gr = dwdg * (2.0 * (r - I_.ins_r0) / (I_.ins_er * I_.ins_er));
+        gz = dwdg * (2.0 * (z - I_.ins_z0) / (I_.ins_ez * I_.ins_ez));
+    }
+
+private:
+    // range of x^2 for x in [a, b]
+    static void sq_range(double a, double b, double& lo, double& hi) {
+        const double qa = a * a, qb = b * b;
+        hi = std::max(qa, qb);
+        lo = (a <= 0.0 && b >= 0.0) ? 0.0 : std::min(qa, qb);
+    }
+    const pic_instance_cfg& c_;
+    DevInst I_;
+    double dr_, dz_;
+    int W_, jlo_, jhi_;
+};
+
+// Cell corners in r-major order: (i, j), (i+1, j), (i, j+1), (i+1, j+1).
+inline int corner(const InsertMesh& M, int ci, int cj, int p) { return (ci + (p & 1)) * M.W() + cj + (p >> 1); }
+
+// The Q1 stiffness of one cell in the r-weighted form (the rectangle's
+// element matrix): K_r (x) M_z + M_r (x) K_z with the 1-D matrices of the
+// cell [r_i, r_i+1] x [z_j, z_j+1].
+void rect_element(const InsertMesh& M, int ci, double E[4][4]) {
+    const double h = M.dr(), k = M.dz();
+    const double r0 = M.r_of(ci), r1 = r0 + h;
+    const double Kr[2][2] = {{0.5 * (r0 + r1) / h, -0.5 * (r0 + r1) / h}, {-0.5 * (r0 + r1) / h, 0.5 * (r0 + r1) / h}};
+    const double off = h * (r0 + r1) / 12.0;
+    const double Mr[2][2] = {{h * (3.0 * r0 + r1) / 12.0, off}, {off, h * (r0 + 3.0 * r1) / 12.0}};
+    const double Kz[2][2] = {{1.0 / k, -1.0 / k}, {-1.0 / k, 1.0 / k}};
+    const double Mz[2][2] = {{k / 3.0, k / 6.0}, {k / 6.0, k / 3.0}};
+    for (int p = 0; p < 4; ++p) {
+        const int pr = p & 1, pz = p >> 1;
+        for (int q = 0; q < 4; ++q) {
+            const int qr = q & 1, qz = q >> 1;
+            E[p][q] = Kr[pr][qr] * Mz[pz][qz] + Mr[pr][qr] * Kz[pz][qz];
+        }
+    }
 }
 
-void weighted_element(const Geo& G, int ci, int cj, double E[4][4]) {
-    WeightedAcc A;
-    A.rl = G.c->a + (double)ci * G.dr;
-    A.zl = (double)cj * G.dz;
+// The weighted element: integral over the cell of r grad(w N_p) . grad(w N_q)
+// for the cell's four hats N.  The cell is cut into 2x2 boxes; a box that
+// the insert cuts is split into four, level by level, down to kCutLevels;
+// other boxes (and cut ones at the last level, without their points in the
+// metal) take the 3x3 Gauss rule; boxes wholly in the metal add nothing.
+void weighted_element(const InsertMesh& M, int ci, int cj, double E[4][4]) {
+    struct Box {
+        double rl, rh, zl, zh;
+        int level;
+    };
     for (int p = 0; p < 4; ++p)
-        for (int q = 0; q < 4; ++q) A.E[p][q] = 0.0;
-    const double hr = 0.5 * G.dr, hz = 0.5 * G.dz;
-    for (int sr = 0; sr < 2; ++sr)
-        for (int sz = 0; sz < 2; ++sz)
-            weighted_box(G, A, A.rl + hr * sr, A.rl + hr * (sr + 1), A.zl + hz * sz, A.zl + hz * (sz + 1), 0);
-    for (int p = 0; p < 4; ++p)
-        for (int q = 0; q < 4; ++q) E[p][q] = A.E[p][q];
+        for (int q = 0; q < 4; ++q) E[p][q] = 0.0;
+    const double r0 = M.r_of(ci), z0 = M.z_of(cj), h = M.dr(), k = M.dz();
+    std::vector<Box> todo;
+    for (int b = 0; b < 4; ++b) {
+        const double rl = r0 + 0.5 * h * (b & 1), zl = z0 + 0.5 * k * (b >> 1);
+        todo.push_back({rl, rl + 0.5 * h, zl, zl + 0.5 * k, 0});
+    }
+    while (!todo.empty()) {
+        const Box bx = todo.back();
+        todo.pop_back();
+        const Where at = M.where(bx.rl, bx.rh, bx.zl, bx.zh);
+        if (at == kMetal) continue;
+        if (at == kCut && bx.level < kCutLevels) {
+            const double rm = 0.5 * (bx.rl + bx.rh), zm = 0.5 * (bx.zl + bx.zh);
+            todo.push_back({bx.rl, rm, bx.zl, zm, bx.level + 1});
+            todo.push_back({rm, bx.rh, bx.zl, zm, bx.level + 1});
+            todo.push_back({bx.rl, rm, zm, bx.zh, bx.level + 1});
+            todo.push_back({rm, bx.rh, zm, bx.zh, bx.level + 1});
+            continue;
+        }
+        const double hr = bx.rh - bx.rl, hz = bx.zh - bx.zl;
+        for (int a = 0; a < 3; ++a) {
+            const double r = bx.rl + 0.5 * hr * (1.0 + kGaussX[a]);
+            for (int b = 0; b < 3; ++b) {
+                const double z = bx.zl + 0.5 * hz * (1.0 + kGaussX[b]);
+                const double g = M.g(r, z);
+                if (!(g > 0.0)) continue;
+                const double wv = M.w(g);
+                double wr, wz;
+                M.w_grad(r, z, g, wr, wz);
+                // hats of the cell and their derivatives at the point
+                const double s = (r - r0) / h, t = (z - z0) / k;
+                const double hs[2] = {1.0 - s, s}, ht[2] = {1.0 - t, t};
+                const double ds[2] = {-1.0 / h, 1.0 / h}, dt[2] = {-1.0 / k, 1.0 / k};
+                double gr[4], gz[4];
+                for (int p = 0; p < 4; ++p) {
+                    const double N = hs[p & 1] * ht[p >> 1];
+                    gr[p] = wr * N + wv * (ds[p & 1] * ht[p >> 1]);
+                    gz[p] = wz * N + wv * (hs[p & 1] * dt[p >> 1]);
+                }
+                const double f = r * ((0.25 * hr * hz) * (kGaussW[a] * kGaussW[b]));
+                for (int p = 0; p < 4; ++p)
+                    for (int q = 0; q < 4; ++q) E[p][q] += f * (gr[p] * gr[q] + gz[p] * gz[q]);
+            }
+        }
+    }
 }
 
 }  // namespace
 
+// Web-spline set-up of an instance's insert (readings of Sec. II.A for the
+// gun geometry of Sec. III): node roles, the outer hats' extension blocks,
+// the node set M and the correction D = A - A_rect on it, the load map and
+// the basis at the nodes of M.
 std::string ins_build(const pic_instance_cfg& c, InsHost& h) {
-    Geo G;
-    G.c = &c;
-    G.nr = c.nr;
-    G.nz = c.nz;
-    G.W = c.nz + 1;
-    G.j0 = c.end_mode == 2 ? 0 : 1;
-    G.j1 = c.end_mode == 2 ? c.nz : c.nz - 1;
-    G.dr = (c.b - c.a) / (double)c.nr;
-    G.dz = c.L / (double)c.nz;
-    const double band = c.ins_band > 0.0 ? c.ins_band : 3.0;
-    G.gam = 2.0 * band * std::max(G.dr / c.ins_er, G.dz / c.ins_ez);
-    G.I = DevInst();
-    G.I.ins_r0 = c.ins_r0;
-    G.I.ins_z0 = c.ins_z0;
-    G.I.ins_er = c.ins_er;
-    G.I.ins_ez = c.ins_ez;
-    G.I.ins_gam = G.gam;
-    const int W = G.W, NN = (c.nr + 1) * W;
-    auto unknown = [&](int i, int j) { return i >= 1 && i <= c.nr - 1 && j >= G.j0 && j <= G.j1; };
+    const InsertMesh M(c);
+    const int W = M.W(), NN = M.nodes(), nr = c.nr, nz = c.nz;
 
-    // node classes
-    std::vector<int> cls(NN, 0);
-    for (int i = 1; i <= c.nr - 1; ++i)
-        for (int j = G.j0; j <= G.j1; ++j) {
-            bool any_in = false, any_cut = false;
-            for (int ci = i - 1; ci <= i; ++ci)
-                for (int cj = j - 1; cj <= j; ++cj) {
-                    if (ci < 0 || ci >= c.nr || cj < 0 || cj >= c.nz) continue;
-                    double gmin, gmax;
-                    cell_range(G, ci, cj, gmin, gmax);
-                    if (gmin > 0.0) any_in = true;
-                    else if (gmax > 0.0) any_cut = true;
-                }
-            cls[i * W + j] = any_in ? 1 : (any_cut ? 2 : 3);
+    // where each cell sits against the insert
+    std::vector<Where> cell((size_t)nr * nz);
+    std::vector<double> cell_lo((size_t)nr * nz), cell_hi((size_t)nr * nz);
+    for (int ci = 0; ci < nr; ++ci)
+        for (int cj = 0; cj < nz; ++cj) {
+            const size_t x = (size_t)ci * nz + cj;
+            M.cell_g(ci, cj, cell_lo[x], cell_hi[x]);
+            cell[x] = cell_lo[x] > 0.0 ? kFree : (cell_hi[x] > 0.0 ? kCut : kMetal);
         }
-    for (int n = 0; n < NN; ++n) h.counts[cls[n]] += 1;
 
-    // extension blocks of the outer hats
-    std::vector<int> blk(NN, -1);
-    std::vector<double> e4((size_t)NN * 4, 0.0);
-    for (int k1 = 1; k1 <= c.nr - 1; ++k1)
-        for (int k2 = G.j0; k2 <= G.j1; ++k2) {
-            const int n = k1 * W + k2;
-            if (cls[n] != 2) continue;
-            double best = -1.0;
-            int b1 = 0, b2 = 0;
-            for (int l1 = k1 - kExtRadius; l1 <= k1 + kExtRadius - 1; ++l1)
-                for (int l2 = k2 - kExtRadius; l2 <= k2 + kExtRadius - 1; ++l2) {
-                    if (!unknown(l1, l2) || !unknown(l1 + 1, l2 + 1)) continue;
-                    if (cls[l1 * W + l2] != 1 || cls[(l1 + 1) * W + l2] != 1 || cls[l1 * W + l2 + 1] != 1 ||
-                        cls[(l1 + 1) * W + l2 + 1] != 1)
-                        continue;
-                    const double du = ((double)l1 + 0.5 - (double)k1) * G.dr;
-                    const double dv = ((double)l2 + 0.5 - (double)k2) * G.dz;
-                    const double d2 = du * du + dv * dv;
-                    if (best < 0.0 || d2 < best) {
-                        best = d2;
-                        b1 = l1;
-                        b2 = l2;
+    // node roles from the cells of each unknown's support: inner if one of
+    // them is free, outer if none is free but one is cut, else exterior
+    std::vector<int> role(NN, kFixed);
+    for (int i = 0; i <= nr; ++i)
+        for (int j = 0; j <= nz; ++j) {
+            if (!M.unknown(i, j)) continue;
+            bool free_cell = false, cut_cell = false;
+            for (int di = -1; di <= 0; ++di)
+                for (int dj = -1; dj <= 0; ++dj) {
+                    const int ci = i + di, cj = j + dj;
+                    if (ci < 0 || ci >= nr || cj < 0 || cj >= nz) continue;
+                    const Where at = cell[(size_t)ci * nz + cj];
+                    free_cell |= at == kFree;
+                    cut_cell |= at == kCut;
+                }
+            role[i * W + j] = free_cell ? kInner : (cut_cell ? kOuter : kExterior);
+        }
+    for (int n = 0; n < NN; ++n) h.counts[role[n]] += 1;
+
+    // blocks: lower-left corners of 2x2 squares of inner unknowns
+    auto inner = [&](int i, int j) { return M.unknown(i, j) && role[i * W + j] == kInner; };
+    auto block_ok = [&](int i, int j) { return inner(i, j) && inner(i + 1, j) && inner(i, j + 1) && inner(i + 1, j + 1); };
+
+    // each outer hat joins the block whose centre is nearest (the distance
+    // in units of half a cell: (2 di + 1) dr, (2 dj + 1) dz), ties to the
+    // lower index in r, then in z, with the bilinear Lagrange weights of its
+    // index offsets from the block's lower-left node
+    std::vector<int> base(NN, -1);
+    std::vector<std::array<double, 4>> ext(NN);
+    for (int i = 1; i < nr; ++i)
+        for (int j = 0; j <= nz; ++j) {
+            const int n = i * W + j;
+            if (role[n] != kOuter) continue;
+            bool found = false;
+            double best_d = 0.0;
+            int bi = 0, bj = 0;
+            for (int li = i - kBlockReach; li < i + kBlockReach; ++li)
+                for (int lj = j - kBlockReach; lj < j + kBlockReach; ++lj) {
+                    if (!block_ok(li, lj)) continue;
+                    const double er = (double)(2 * (li - i) + 1) * M.dr();
+                    const double ez = (double)(2 * (lj - j) + 1) * M.dz();
+                    const double d = er * er + ez * ez;
+                    if (!found || d < best_d || (d == best_d && (li < bi || (li == bi && lj < bj)))) {
+                        found = true;
+                        best_d = d;
+                        bi = li;
+                        bj = lj;
                     }
                 }
-            if (best < 0.0) return "no 2x2 block of inner nodes near an outer node: refine the mesh";
-            const double x = (double)(k1 - b1), y = (double)(k2 - b2);
-            blk[n] = b1 * W + b2;
-            e4[(size_t)n * 4 + 0] = (1.0 - x) * (1.0 - y);
-            e4[(size_t)n * 4 + 1] = x * (1.0 - y);
-            e4[(size_t)n * 4 + 2] = (1.0 - x) * y;
-            e4[(size_t)n * 4 + 3] = x * y;
+            if (!found) return "no 2x2 block of inner nodes near an outer node: refine the mesh";
+            const double x = (double)(i - bi), y = (double)(j - bj);
+            base[n] = bi * W + bj;
+            ext[n] = {(1.0 - x) * (1.0 - y), x * (1.0 - y), (1.0 - x) * y, x * y};
         }
-    // the nodes a hat feeds, with factors (nodes, not M indices)
-    auto feeds = [&](int n, int* u, double* f) -> int {
-        if (n < 0 || n >= NN || cls[n] == 0) return 0;
-        if (cls[n] == 1) {
-            u[0] = n;
-            f[0] = 1.0;
+
+    // the inner unknowns a node's hat contributes to, with their factors
+    struct Feed {
+        int n;
+        double f;
+    };
+    auto feed = [&](int n, Feed* out) -> int {
+        if (role[n] == kInner) {
+            out[0] = {n, 1.0};
             return 1;
         }
-        if (cls[n] != 2) return 0;
-        const int b = blk[n];
-        const int nd[4] = {b, b + W, b + 1, b + W + 1};
-        for (int q = 0; q < 4; ++q) {
-            u[q] = nd[q];
-            f[q] = e4[(size_t)n * 4 + q];
-        }
+        if (role[n] != kOuter) return 0;
+        const int b = base[n];
+        const int to[4] = {b, b + W, b + 1, b + W + 1};
+        for (int q = 0; q < 4; ++q) out[q] = {to[q], ext[n][q]};
         return 4;
     };
 
-    // M: unknown corners of the cells that meet the band, and the blocks
-    // (a cell inside the metal adds nothing unless it has an inner corner)
-    std::vector<char> inM(NN, 0);
-    auto meets = [&](int ci, int cj) {
-        double gmin, gmax;
-        cell_range(G, ci, cj, gmin, gmax);
-        if (gmin >= G.gam) return false;
-        if (gmax > 0.0) return true;
+    // cells whose matrix differs from the rectangle's: they meet the weight
+    // band and are not wholly in the metal, or are in the metal with an
+    // inner corner
+    auto band_cell = [&](int ci, int cj) {
+        const size_t x = (size_t)ci * nz + cj;
+        if (!(cell_lo[x] < M.gam())) return false;
+        if (cell[x] != kMetal) return true;
         for (int p = 0; p < 4; ++p)
-            if (cls[(ci + kCR[p]) * W + cj + kCZ[p]] == 1) return true;
+            if (role[corner(M, ci, cj, p)] == kInner) return true;
         return false;
     };
-    for (int ci = 0; ci < c.nr; ++ci)
-        for (int cj = 0; cj < c.nz; ++cj) {
-            if (!meets(ci, cj)) continue;
-            for (int p = 0; p < 4; ++p) {
-                const int i = ci + kCR[p], j = cj + kCZ[p];
-                if (unknown(i, j)) inM[i * W + j] = 1;
-            }
-        }
+    std::vector<char> inM(NN, 0);
+    for (int ci = 0; ci < nr; ++ci)
+        for (int cj = 0; cj < nz; ++cj)
+            if (band_cell(ci, cj))
+                for (int p = 0; p < 4; ++p) {
+                    const int n = corner(M, ci, cj, p);
+                    if (role[n] != kFixed) inM[n] = 1;
+                }
     for (int n = 0; n < NN; ++n)
-        if (cls[n] == 2) {
-            const int b = blk[n];
-            inM[b] = inM[b + W] = inM[b + 1] = inM[b + W + 1] = 1;
-        }
+        if (role[n] == kOuter)
+            for (int q = 0; q < 4; ++q) inM[base[n] + (q & 1) * W + (q >> 1)] = 1;
     h.map.assign(NN, -1);
     h.Mnode.clear();
     for (int n = 0; n < NN; ++n)
@@ -275,98 +334,99 @@ std::string ins_build(const pic_instance_cfg& c, InsHost& h) {
         }
     h.m = (int)h.Mnode.size();
 
-    // D = A - A_rect on M x M, from the cells that meet the band
-    std::map<long long, double> D;
-    auto addD = [&](int nu, int nv, double v) {
-        const int a = h.map[nu], b = h.map[nv];
-        D[(long long)a * h.m + b] += v;
+    // D on M x M as (row, column, value) triplets, summed per entry below:
+    // the weighted element through the extension, minus the rectangle's
+    // entries that the web-spline space replaces (pairs with an inner node;
+    // outer and exterior nodes keep the rectangle's rows among themselves)
+    struct Trip {
+        long long rc;
+        double v;
     };
-    for (int ci = 0; ci < c.nr; ++ci)
-        for (int cj = 0; cj < c.nz; ++cj) {
-            if (!meets(ci, cj)) continue;
-            double gmin, gmax;
-            cell_range(G, ci, cj, gmin, gmax);
-            double Ex[4][4];
-            q1_element(G, ci, Ex);
+    std::vector<Trip> trips;
+    for (int ci = 0; ci < nr; ++ci)
+        for (int cj = 0; cj < nz; ++cj) {
+            if (!band_cell(ci, cj)) continue;
             int nd[4];
-            for (int p = 0; p < 4; ++p) nd[p] = (ci + kCR[p]) * W + cj + kCZ[p];
-            if (gmax > 0.0) {
-                double Eq[4][4];
-                weighted_element(G, ci, cj, Eq);
+            for (int p = 0; p < 4; ++p) nd[p] = corner(M, ci, cj, p);
+            if (cell[(size_t)ci * nz + cj] != kMetal) {
+                double Ew[4][4];
+                weighted_element(M, ci, cj, Ew);
+                Feed fp[4], fq[4];
                 for (int p = 0; p < 4; ++p) {
-                    int up[4];
-                    double fp[4];
-                    const int mp = feeds(nd[p], up, fp);
+                    const int mp = feed(nd[p], fp);
                     for (int q = 0; q < 4; ++q) {
-                        int uq[4];
-                        double fq[4];
-                        const int mq = feeds(nd[q], uq, fq);
+                        const int mq = feed(nd[q], fq);
                         for (int s = 0; s < mp; ++s)
-                            for (int t = 0; t < mq; ++t) addD(up[s], uq[t], fp[s] * fq[t] * Eq[p][q]);
+                            for (int t = 0; t < mq; ++t)
+                                trips.push_back({(long long)h.map[fp[s].n] * h.m + h.map[fq[t].n],
+                                                 fp[s].f * fq[t].f * Ew[p][q]});
                     }
                 }
             }
-            // the rectangle's entries, kept between outer/exterior pairs
+            double Er[4][4];
+            rect_element(M, ci, Er);
             for (int p = 0; p < 4; ++p)
                 for (int q = 0; q < 4; ++q) {
-                    const int np = nd[p], nq = nd[q];
-                    if (cls[np] == 0 || cls[nq] == 0) continue;
-                    if (cls[np] >= 2 && cls[nq] >= 2) continue;
-                    addD(np, nq, -Ex[p][q]);
+                    const int rp = role[nd[p]], rq = role[nd[q]];
+                    if (rp == kFixed || rq == kFixed) continue;
+                    if (rp != kInner && rq != kInner) continue;
+                    trips.push_back({(long long)h.map[nd[p]] * h.m + h.map[nd[q]], -Er[p][q]});
                 }
         }
+    std::stable_sort(trips.begin(), trips.end(), [](const Trip& x, const Trip& y) { return x.rc < y.rc; });
     h.Dr.clear();
     h.Dc.clear();
     h.Dv.clear();
-    for (const auto& kv : D) {
-        h.Dr.push_back((int)(kv.first / h.m));
-        h.Dc.push_back((int)(kv.first % h.m));
-        h.Dv.push_back(kv.second);
+    for (size_t t = 0; t < trips.size();) {
+        const long long rc = trips[t].rc;
+        double v = 0.0;
+        for (; t < trips.size() && trips[t].rc == rc; ++t) v += trips[t].v;
+        h.Dr.push_back((int)(rc / h.m));
+        h.Dc.push_back((int)(rc % h.m));
+        h.Dv.push_back(v);
     }
 
-    // load of each M node: inner nodes gather their own charge and that of
-    // the outer hats whose block holds them; the others take none
-    std::vector<std::vector<std::pair<int, double>>> load(h.m);
+    // load of each node of M: the charges of the hats that feed it (an inner
+    // node its own, plus the outer hats whose block holds it); outer and
+    // metal nodes of M take none
+    std::vector<std::vector<Feed>> load(h.m);
     for (int n = 0; n < NN; ++n) {
-        if (cls[n] != 1 && cls[n] != 2) continue;
-        int u[4];
-        double f[4];
-        const int k = feeds(n, u, f);
-        for (int q = 0; q < k; ++q) {
-            const int a = h.map[u[q]];
-            if (a >= 0) load[a].push_back({n, f[q]});
-        }
+        Feed f[4];
+        const int k = feed(n, f);
+        for (int q = 0; q < k; ++q)
+            if (h.map[f[q].n] >= 0) load[h.map[f[q].n]].push_back({n, f[q].f});
     }
     h.rp.assign(h.m + 1, 0);
     h.rk.clear();
     h.rf.clear();
     for (int a = 0; a < h.m; ++a) {
-        for (const auto& e : load[a]) {
-            h.rk.push_back(e.first);
-            h.rf.push_back(e.second);
+        for (const Feed& e : load[a]) {
+            h.rk.push_back(e.n);
+            h.rf.push_back(e.f);
         }
         h.rp[a + 1] = (int)h.rk.size();
     }
 
-    // the basis at the nodes of M
+    // the basis at the nodes of M: an inner node is its own coefficient times
+    // w, an outer node inside the domain w times its block's extension, a
+    // node in the metal 0
     h.typ.assign(h.m, 0);
     h.wn.assign(h.m, 0.0);
     h.ek.assign((size_t)h.m * 4, 0);
     h.ef.assign((size_t)h.m * 4, 0.0);
     for (int a = 0; a < h.m; ++a) {
-        const int n = h.Mnode[a], i = n / W, j = n % W;
-        const double r = c.a + (double)i * G.dr, z = (double)j * G.dz;
-        const double g = ins_g(G.I, r, z);
-        h.wn[a] = ins_w(G.I, g);
-        if (cls[n] == 1) {
+        const int n = h.Mnode[a];
+        const double g = M.g(M.r_of(n / W), M.z_of(n % W));
+        h.wn[a] = M.w(g);
+        if (role[n] == kInner) {
             h.typ[a] = 1;
-        } else if (cls[n] == 2 && g > 0.0) {
+        } else if (role[n] == kOuter && g > 0.0) {
             h.typ[a] = 2;
-            const int b = blk[n];
-            const int nd[4] = {b, b + W, b + 1, b + W + 1};
+            Feed f[4];
+            feed(n, f);
             for (int q = 0; q < 4; ++q) {
-                h.ek[(size_t)a * 4 + q] = nd[q];
-                h.ef[(size_t)a * 4 + q] = e4[(size_t)n * 4 + q];
+                h.ek[(size_t)a * 4 + q] = f[q].n;
+                h.ef[(size_t)a * 4 + q] = f[q].f;
             }
         }
     }

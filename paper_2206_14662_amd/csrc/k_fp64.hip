@@ -147,17 +147,25 @@ __global__ void __launch_bounds__(kBlock) k_push64(DevInst I, P64 p, const doubl
         double x = r + vr * dt;
         double y = vt * dt;
         double zn = z + vz * dt;
-        double rn = sqrt(x * x + y * y);
+        double rr2 = x * x + y * y;
+        double rn = sqrt(rr2);
         int wall = -1;
-        if (rn <= I.a) wall = 0;
+        // a non-finite new position (a non-finite field or velocity) removes
+        // the particle without counting it as absorbed charge
+        if (!(rr2 < HUGE_VAL && fabs(zn) < HUGE_VAL)) wall = 4;
+        else if (rn <= I.a) wall = 0;
         else if (rn >= I.b) wall = 1;
         else if (I.has_ins && ins_g(I, rn, zn) <= 0.0) wall = 1;  // the insert is outer-electrode metal
         else if (zn <= 0.0) wall = 2;
         else if (zn >= I.L) wall = 3;
         if (wall >= 0) {
-            long long Wq = (long long)rint(p.w[q] * I.two_S);
-            atomicAdd((unsigned long long*)&cnt[C_ABS_N + wall], 1ull);
-            atomicAdd((unsigned long long*)&cnt[C_ABS_W + wall], (unsigned long long)Wq);
+            if (wall == 4) {
+                atomicAdd((unsigned long long*)&cnt[C_NONFIN], 1ull);
+            } else {
+                long long Wq = (long long)rint(p.w[q] * I.two_S);
+                atomicAdd((unsigned long long*)&cnt[C_ABS_N + wall], 1ull);
+                atomicAdd((unsigned long long*)&cnt[C_ABS_W + wall], (unsigned long long)Wq);
+            }
             atomicAdd((unsigned long long*)&cnt[C_DEAD], 1ull);
             p.r[q] = -1.0;
             continue;

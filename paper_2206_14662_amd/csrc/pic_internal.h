@@ -132,6 +132,7 @@ enum Counter {
     C_PSTEPS,                // particle-steps pushed so far
     C_FARDEP,                // deposits outside the LDS window (FP32 form)
     C_SOURCE,                // electrons created by the seed source
+    C_NONFIN,                // particles removed with a non-finite position (sticky error)
     C_NCOUNT = 40
 };
 
@@ -392,6 +393,9 @@ hipError_t set_field_kernel_attrs(int max_nz);
 // Elliptic insert (insert.hip).  ins_build classifies the nodes, attaches
 // the outer hats, and assembles D on the host; an empty string means success.
 std::string ins_build(const pic_instance_cfg& c, InsHost& h);
+// The insert fields of DevInst (centre, semi-axes, weight band gam) of an
+// instance with mesh spacings dr, dz.
+void ins_fill(const pic_instance_cfg& c, double dr, double dz, DevInst& I);
 // Cubic shapes (k_field.hip): load folded from Qx, sine transform, the
 // 7-band solves, inverse transform into the coefficient buffer (the table's
 // phi), then the ghosted coefficients and phi = phi_vac + nodal value.

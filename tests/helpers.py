@@ -36,3 +36,52 @@ def rel_vec_err(a, b):
 
 COUNTERS = ("n_live", "n_elastic", "n_ioniz", "n_null_cand", "n_cap_overflow", "n_absorbed",
             "absorbed_W", "total_Q", "n_samples")
+
+
+def f32_values(st):
+    """A state whose floating-point arrays hold FP32 values (so the FP32 form
+    and the FP64 oracle start from identical numbers)."""
+    return {k: (v.astype(np.float32).astype(np.float64) if v.dtype.kind == "f" else v) for k, v in st.items()}
+
+
+# Element-wise bars of one FP32 step against the FP64 oracle from the same
+# FP32-valued state and field (relative error of the velocity vector; measured
+# worst cases 2.5e-7 and 5.5e-6 over 40k particles): the push alone, and a
+# particle the oracle scattered, whose FP32 scattering (uniforms of 23 instead
+# of 52 bits, float sincos/tan/atan/log) is ill-conditioned near back-scatter.
+TOL_PUSH32 = 2e-6
+TOL_COLL32 = 1e-4
+TOL_POS32 = 2e-6
+
+
+def fp32_step_parity(after, ref, ref_nocoll, max_flips):
+    """Compare particles `after` (FP32 form, one step) with the oracle's `ref`
+    from the same state, and with `ref_nocoll` (the oracle without the
+    collision stage, which tells which particles the oracle scattered).
+    Every particle present on both sides is matched by key; a decision flip
+    is a particle present on one side only (an absorption or an ionisation
+    decided differently at FP32 rounding) or one beyond its bar.  Asserts the
+    bars on all others and at most max_flips flips; returns the counts."""
+    a, o, z = by_key(after), by_key(ref), by_key(ref_nocoll)
+    keys = np.intersect1d(a["key"], o["key"])
+    only = len(a["key"]) + len(o["key"]) - 2 * len(keys)
+    ai, oi = np.searchsorted(a["key"], keys), np.searchsorted(o["key"], keys)
+    aq = {k: v[ai] for k, v in a.items()}
+    oq = {k: v[oi] for k, v in o.items()}
+    zi = np.searchsorted(z["key"], keys)
+    zi = np.minimum(zi, len(z["key"]) - 1)
+    inz = z["key"][zi] == keys
+    scattered = ~inz | (z["vr"][zi] != oq["vr"]) | (z["vt"][zi] != oq["vt"]) | (z["vz"][zi] != oq["vz"])
+    err = rel_vec_err(aq, oq)
+    pos = np.maximum(np.abs(aq["r"] / oq["r"] - 1.0), np.abs(aq["z"] / oq["z"] - 1.0))
+    bar = np.where(scattered, TOL_COLL32, TOL_PUSH32)
+    bad = (err > bar) | (pos > TOL_POS32) | (aq["w"] != oq["w"])
+    flips = only + int(bad.sum())
+    ok = ~bad
+    res = dict(matched=len(keys), scattered=int(scattered.sum()), flips=flips,
+               max_err_push=float(err[ok & ~scattered].max(initial=0.0)),
+               max_err_scattered=float(err[ok & scattered].max(initial=0.0)),
+               max_pos=float(pos[ok].max(initial=0.0)))
+    print("fp32 step parity:", res, flush=True)
+    assert flips <= max_flips, res
+    return res

@@ -82,6 +82,21 @@ def test_init_rejects_bad_configs_without_touching_a_gpu():
     assert e.value.status == B.PIC_EINVAL
 
 
+def test_init_reports_fixed_point_overflow_without_touching_a_gpu():
+    """A weight that does not fit the 2^31 fixed-point budget at an explicit
+    shift S is refused with PIC_EOVERFLOW before any device call; the
+    automatic shift always fits."""
+    w = pi.coax64()["weight"]
+    S = B.pic_auto_shift(w)
+    assert w * 2.0**S <= 2.0**31 < w * 2.0 ** (S + 1)
+    with pytest.raises(B.PicError) as e:
+        B.pic_init([dict(pi.coax64(), fx_shift=S + 1)], use_torch=False)
+    assert e.value.status == B.PIC_EOVERFLOW
+    with pytest.raises(B.PicError) as e:
+        B.pic_init([pi.coax64(), dict(pi.coax64(), weight=4.0 * w, fx_shift=S)], use_torch=False)
+    assert e.value.status == B.PIC_EOVERFLOW and "instance 1" in B.pic_last_error()
+
+
 def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(B, "_lib", None)
     monkeypatch.setattr(B, "LIB_PATH", str(tmp_path / "missing.so"))

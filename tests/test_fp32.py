@@ -7,7 +7,7 @@ import pytest
 
 import oracle
 import pic_inputs as pi
-from helpers import by_key, gpu_and_oracle, rel_vec_err
+from helpers import by_key, f32_values, fp32_step_parity, gpu_and_oracle
 from paper_2206_14662_amd import binding as B
 
 pytestmark = pytest.mark.gpu
@@ -92,37 +92,37 @@ def test_total_charge_and_bookkeeping():
     assert np.sum(p["key"] >= np.uint64(1 << 63)) <= d["n_ioniz"]
 
 
-def test_one_step_against_oracle_fp32_accuracy():
-    cfg = pi.coax64(p_mbar=30.0, E_cap_eV=3000.0)
-    st = pi.cloud_state(cfg, 20000, seed=21)
-    # states exactly representable in FP32, so both sides start equal
-    st = {k: (v.astype(np.float32).astype(np.float64) if v.dtype == np.float64 else v) for k, v in st.items()}
-    f = pi.random_fields(cfg, 22)
-    f = {k: v.astype(np.float32).astype(np.float64) for k, v in f.items()}
+@pytest.mark.parametrize("p_mbar,seed", [(30.0, 21), (3.0, 23)])
+def test_one_step_against_oracle_fp32_accuracy(p_mbar, seed):
+    """One step from an FP32-valued state and field at a collisional pressure:
+    every particle against the oracle's within the element-wise FP32 bars,
+    decision flips counted (at most 4 of 20000), and the deposited grid equal
+    bit for bit to the oracle's deposit of the FP32 form's new positions taken
+    in single precision (the precision in which the FP32 form decides the
+    integer node charges)."""
+    cfg = pi.coax64(p_mbar=p_mbar, E_cap_eV=3000.0)
+    st = f32_values(pi.cloud_state(cfg, 20000, seed=seed))
+    f = f32_values(pi.random_fields(cfg, 22))
     g, o = gpu_and_oracle(cfg, st, f, mode=F32)
+    assert np.array_equal(g.charge(), oracle.deposit_f32(cfg, st["r"], st["z"], st["w"], fx_shift=o.S))
+    o0 = oracle.Sim(dict(cfg, collisions=0), fx_shift=o.S)
+    o0.set_fields(**f, frozen=1)
+    o0.set_particles(st)
     g.step(1)
     o.step(1)
+    o0.step(1)
     gd, od = g.diag(), o.diag()
     # the null-collision test is an exact integer compare on the same Philox words
     assert gd["n_null_cand"] == od["n_null_cand"]
-    assert abs(gd["n_elastic"] - od["n_elastic"]) <= 2 and abs(gd["n_ioniz"] - od["n_ioniz"]) <= 2
-    assert gd["n_absorbed"] == od["n_absorbed"]
-    gp, op = by_key(g.get_particles()), by_key(o.get_particles())
-    keep = np.intersect1d(gp["key"], op["key"])
-    gi = np.searchsorted(gp["key"], keep)
-    oi = np.searchsorted(op["key"], keep)
-    gq = {k: v[gi] for k, v in gp.items()}
-    oq = {k: v[oi] for k, v in op.items()}
-    assert len(keep) >= len(op["key"]) - 4
-    np.testing.assert_allclose(gq["r"], oq["r"], rtol=2e-6)
-    np.testing.assert_allclose(gq["z"], oq["z"], rtol=2e-6)
-    err = rel_vec_err(gq, oq)
-    assert np.quantile(err, 0.999) < 1e-4
-    # deposited charge: exact total, density close
+    assert gd["n_elastic"] > 100 and gd["n_ioniz"] > 10
+    res = fp32_step_parity(g.get_particles(), o.get_particles(), o0.get_particles(), max_flips=4)
+    # the oracle's scattered particles: elastic, ionised primaries and new electrons
+    assert res["scattered"] + res["flips"] >= od["n_elastic"] + 2 * od["n_ioniz"]
+    assert abs(gd["n_elastic"] - od["n_elastic"]) + abs(gd["n_ioniz"] - od["n_ioniz"]) <= res["flips"]
+    gp = g.get_particles()
     W = round(cfg["weight"] * 2.0 ** o.S)
     assert g.charge().sum() == gd["n_live"] * W
-    qo = o.charge().astype(np.float64)
-    assert np.linalg.norm(g.charge() - qo) <= 1e-4 * np.linalg.norm(qo)
+    assert np.array_equal(g.charge(), oracle.deposit_f32(cfg, gp["r"], gp["z"], gp["w"], fx_shift=o.S))
 
 
 def test_fp32_tracks_fp64_over_a_run():

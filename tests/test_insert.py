@@ -72,6 +72,38 @@ def _flat_error(nr, band):
     return np.abs(phi - ex).max() / abs(c["V_inner"])
 
 
+def _flat_error_gpu(nr, band):
+    """The same vacuum potential computed by the library (its own web-spline
+    set-up and the corrected fast solve, through pic_init and pic_get_phi)
+    against the same closed form: no oracle involved."""
+    a, b, L, er = 1e-3, 10e-3, 60e-3, 2.37e-3
+    c = pi.coax64(nr=nr, nz=8, end_mode=2, V_end=0.0, n_init=0, ins_r0=b, ins_z0=L / 2, ins_er=er, ins_ez=200 * L,
+                  ins_band=band)
+    g = B.Sim([c])
+    phi = g.phi()
+    g.close()
+    r = a + (b - a) * np.arange(nr + 1) / nr
+    z = L * np.arange(9) / 8
+    rw = b - er * np.sqrt(1.0 - ((z - L / 2) / c["ins_ez"]) ** 2)
+    ex = c["V_inner"] + (c["V_outer"] - c["V_inner"]) * np.log(r[:, None] / a) / np.log(rw[None, :] / a)
+    ex = np.where(r[:, None] < rw[None, :], ex, c["V_outer"])
+    return np.abs(phi - ex).max() / abs(c["V_inner"])
+
+
+@pytest.mark.gpu
+def test_gpu_flat_insert_converges_to_the_coaxial_log_profile():
+    """The library path alone: with a fixed-width band the GPU vacuum
+    potential's error against the coaxial log profile between a and the
+    insert's wall r_w(z) falls as h^2 (at least 3x per halving of the mesh),
+    to below 5e-5 of the bias at 128 cells."""
+    fixed = [_flat_error_gpu(nr, 3.0 * nr / 16) for nr in (16, 32, 64, 128)]
+    print("gpu flat-insert errors:", fixed, flush=True)
+    for e0, e1 in zip(fixed, fixed[1:]):
+        assert e0 / e1 > 3.0, fixed
+    assert fixed[-1] < 5e-5
+    assert _flat_error_gpu(128, 0.0) < 1e-4
+
+
 def test_flat_insert_converges_to_the_coaxial_log_profile():
     """The wall sits between mesh lines (at 0.74 of the gap).  With a weight
     band of fixed width (3 cells of the coarsest mesh) the error falls as h^2,

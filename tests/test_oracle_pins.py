@@ -515,6 +515,18 @@ def _step_pair(c, st):
     return a.get_particles(), b.get_particles(), b.diag()
 
 
+def test_null_candidate_mask_counts_the_candidates_of_a_step():
+    """The candidate mask used to pick test samples marks exactly the electrons
+    whose null-collision test succeeds in a step."""
+    c = pi.coax64(p_mbar=30.0, E_cap_eV=3000.0)
+    st = pi.cloud_state(c, 20000, seed=16)
+    s = frozen_sim(c, pi.uniform_fields(c), st)
+    s.set_step(11)
+    s.step(1)
+    m = oracle.null_candidates(c, 11, st["key"])
+    assert s.diag()["n_null_cand"] == m.sum() > 100
+
+
 def test_elastic_energy_loss_matches_angle():
     c = pi.coax64(p_mbar=300.0, lotz_a=0.0, M_gas_amu=4.0, E_cap_eV=2000.0)
     d = oracle.derive(c)
@@ -592,6 +604,99 @@ def test_charge_bookkeeping_with_collisions():
     assert dg["n_live"] + sum(dg["n_absorbed"]) == 20000 + dg["n_ioniz"]
     assert dg["total_Q"] + sum(dg["absorbed_W"]) == q0 + dg["n_ioniz"] * W
     assert np.all((p["r"] > c["a"]) & (p["r"] < c["b"]) & (p["z"] > 0) & (p["z"] < c["L"]))
+
+
+def _dyadic_cfg():
+    """A trap whose a, dr, dz are powers of two, so that on positions of a
+    2^-20 m grid every FP32 operation of the deposit is exact."""
+    return pi.coax64(a=2.0**-10, b=2.0**-10 + 64 * 2.0**-12, L=128 * 2.0**-12, nr=64, nz=128,
+                     r_lo=2.0**-9, r_hi=2.0**-8, z_lo=2.0**-6, z_hi=2.0**-5, weight=2.0**17)
+
+
+def test_fp32_deposit_exact_where_single_precision_is_exact():
+    """Dyadic mesh, positions on a 2^-20 grid (cell offsets multiples of 2^-8)
+    and a power-of-two weight: the single-precision deposit rounds nothing, so
+    it must equal the FP64 deposit (itself pinned by brute force) node by node.
+    A swapped offset or a dropped node fails here."""
+    c = _dyadic_cfg()
+    S = oracle.auto_shift(c["weight"])
+    assert c["weight"] * 2.0**S == 2.0**31
+    rng = np.random.default_rng(14)
+    n = 3000
+    r = c["a"] + rng.integers(1, 64 * 256, n) * 2.0**-20
+    z = rng.integers(1, 128 * 256, n) * 2.0**-20
+    w = np.full(n, c["weight"])
+    q32 = oracle.deposit_f32(c, r, z, w, fx_shift=S)
+    q64 = np.zeros_like(q32)
+    for x, y in zip(r, z):
+        q64 += oracle.deposit_one(c, x, y, c["weight"], fx_shift=S)
+    assert np.array_equal(q32, q64)
+    assert q32.sum() == n * 2**31
+
+
+def test_fp32_deposit_within_single_precision_rounding():
+    """Arbitrary FP32 positions: every particle adds exactly W = rint(w 2^S) of
+    its FP32 weight, and each node differs from the FP64 deposit by no more
+    than the particles' single-precision rounding allows.  With s = (r - a)/dr
+    the FP32 cell offset is off by at most (3 s + a/dr + 1) 2^-24 (a, 1/dr
+    rounded, a difference and a product), the z offset by (2 t + 1) 2^-24; a
+    node weight then by their sum plus two product roundings, the node charge
+    by W times that plus 1/2 for each of the two rint; the remainder node takes
+    the other three's errors as well."""
+    c = pi.coax64()
+    S = oracle.auto_shift(c["weight"])
+    st = pi.particle_state(c, 4000, seed=15, margin_cells=0.01)
+    r, z = (st[k].astype(np.float32).astype(np.float64) for k in ("r", "z"))
+    w = np.full(len(r), float(np.float32(c["weight"])))
+    q32 = oracle.deposit_f32(c, r, z, w, fx_shift=S)
+    W = round(w[0] * 2.0**S)
+    assert q32.sum() == len(r) * W
+    d = oracle.derive(c, fx_shift=S)
+    nodes = q32.shape
+    bound = np.zeros(nodes)
+    q64 = np.zeros(nodes, dtype=np.int64)
+    eps = 2.0**-24
+    for x, y in zip(r, z):
+        qi = oracle.deposit_one(c, x, y, w[0], fx_shift=S)
+        q64 += qi
+        s, t = (x - c["a"]) * d["inv_dr"], y * d["inv_dz"]
+        e_w = ((3 * s + c["a"] * d["inv_dr"] + 1) + (2 * t + 1) + 2) * eps
+        e_q = W * e_w + 1.0
+        i = min(int(s), c["nr"] - 1)
+        j = min(int(t), c["nz"] - 1)
+        # the cell may differ by one on either side: bound the 4x4 block around it
+        blk = np.full((4, 4), 4 * e_q)
+        i0, j0 = max(i - 1, 0), max(j - 1, 0)
+        bound[i0:i0 + 4, j0:j0 + 4] += blk[:min(4, nodes[0] - i0), :min(4, nodes[1] - j0)]
+    diff = np.abs(q32 - q64)
+    assert np.all(diff <= bound)
+    assert diff.max() > 0                  # the single-precision path really differs
+
+
+def test_non_finite_particles_are_removed_and_counted():
+    """A particle whose new position is not finite (here a NaN or infinite
+    velocity component) is removed and counted apart: it is not absorbed
+    charge, deposits nothing, and the other particles step exactly as in a run
+    without it."""
+    c = pi.coax64(collisions=0)
+    st = pi.cloud_state(c, 2000, seed=12)
+    bad = {k: v.copy() for k, v in st.items()}
+    bad["vr"][5] = np.nan
+    bad["vz"][17] = np.inf
+    bad["vt"][40] = -np.inf
+    f = pi.random_fields(c, 13)
+    a, b = frozen_sim(c, f, st), frozen_sim(c, f, bad)
+    a.step(3)
+    b.step(3)
+    da, db = a.diag(), b.diag()
+    assert db["n_nonfinite"] == 3 and da["n_nonfinite"] == 0
+    assert db["n_absorbed"] == da["n_absorbed"] and db["absorbed_W"] == da["absorbed_W"]
+    W = round(c["weight"] * 2.0**a.S)
+    assert db["n_live"] == da["n_live"] - 3 and db["total_Q"] == db["n_live"] * W
+    pa, pb = a.get_particles(), b.get_particles()
+    keep = ~np.isin(pa["key"], st["key"][[5, 17, 40]])
+    for k in ("key", "r", "z", "vr", "vt", "vz"):
+        assert np.array_equal(pa[k][keep], pb[k]), k
 
 
 def test_absorbing_walls_and_current():

@@ -43,6 +43,21 @@ def test_null_bound_is_the_maximum_of_sigma_v():
     assert got == pytest.approx(1e-19 * np.sqrt(2 * QE * c["E_cap_eV"] / ME), rel=1e-14)
 
 
+def test_bound_in_use_is_widened_and_rounded_up_to_12_bits():
+    """The bound a table installs is the maximum of sigma v times (1 + 2^-20),
+    rounded up to 12 significant bits: never below the widened maximum, less
+    than 2^-11 above it, and a multiple of 2^(e - 12) for its binade."""
+    rng = np.random.default_rng(9)
+    for x in np.concatenate([rng.uniform(1e-14, 1e-12, 200), [2.0**-40, 3.0 * 2.0**-41, 1.2345e-13]]):
+        b = oracle.xs_bound(x)
+        w = x * (1 + 2.0**-20)
+        assert w <= b < w * (1 + 2.0**-11)
+        m, e = np.frexp(b)
+        assert m * 4096 == np.floor(m * 4096)
+    # already on the grid after widening: unchanged
+    assert oracle.xs_bound(0.75 / (1 + 2.0**-20)) in (0.75, 0.75 + 2.0**-13)
+
+
 def test_oracle_collision_rate_follows_the_table():
     """A mono-energetic beam: the elastic events per step are binomial with
     p = P_null n_n sigma(E) v / nu' for the table's sigma(E)."""
