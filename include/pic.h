@@ -409,6 +409,22 @@ pic_status pic_moments(pic_ctx* ctx, int inst, double* out);
 pic_status pic_well_depth(pic_ctx* ctx, int inst, int n_lines, const double* r_mid, double* depth,
                           double* z_max);
 
+/*
+ * pic_moments_noalloc -- for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): the moments of pic_moments, written to the caller's DEVICE
+ * array out (11 channel-major node arrays of (nr+1)(nz+1) doubles, same
+ * layout and values up to the order of the floating-point sums), queued on
+ * the context's stream without synchronising and without any allocation.
+ * The partial sums live in a fixed device scratch array of 32 MiB per GPU
+ * (held until the process ends), so the instance's mesh may have at most
+ * 381300 nodes (PIC_EINVAL beyond).  All contexts on one GPU share that
+ * array: calls whose work overlaps on one GPU (different streams at once)
+ * race and must be ordered by the caller.  Errors: PIC_EINVAL, PIC_ESTATE,
+ * PIC_EDEVICE.
+ */
+pic_status pic_moments_noalloc(pic_ctx* ctx, int inst, double* out);
+
 /* pic_capacity -- the slots of instance `inst` and the number of storage
  * regrowths so far (per context). */
 pic_status pic_capacity(pic_ctx* ctx, int inst, long long* slots, long long* grow_events);

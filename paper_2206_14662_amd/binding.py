@@ -92,7 +92,7 @@ EXPORTS = ("pic_init", "pic_step", "pic_diag", "pic_destroy", "pic_last_error", 
            "pic_get_particles", "pic_set_particles", "pic_set_fields", "pic_get_fields",
            "pic_get_charge", "pic_get_phi", "pic_set_step", "pic_derive", "pic_auto_shift",
            "pic_timing", "pic_tuning", "pic_retune", "pic_autotune", "pic_reserve", "pic_capacity",
-           "pic_moments", "pic_well_depth", "pic_get_band_charge", "pic_insert_layout",
+           "pic_moments", "pic_moments_noalloc", "pic_well_depth", "pic_get_band_charge", "pic_insert_layout",
            "pic_set_cross_sections", "pic_get_spline3", "pic_set_anisotropy")
 
 _lib = None
@@ -142,6 +142,7 @@ def lib():
     L.pic_reserve.argtypes = [vp, C.c_int, C.c_longlong]
     L.pic_capacity.argtypes = [vp, C.c_int, _LL, _LL]
     L.pic_moments.argtypes = [vp, C.c_int, _D]
+    L.pic_moments_noalloc.argtypes = [vp, C.c_int, vp]
     L.pic_well_depth.argtypes = [vp, C.c_int, C.c_int, _D, _D, _D]
     L.pic_get_band_charge.argtypes = [vp, C.c_int, _LL]
     L.pic_insert_layout.argtypes = [C.POINTER(pic_instance_cfg), _I, _I, _LL]
@@ -428,6 +429,12 @@ def pic_moments(ctx, inst, nodes):
     out = np.zeros(11 * nodes)
     _check(lib().pic_moments(ctx, int(inst), out.ctypes.data_as(_D)), ctx)
     return out
+
+
+def pic_moments_noalloc(ctx, inst, out_ptr):
+    """The moments into a caller-owned device array (address out_ptr, 11 x
+    nodes doubles), queued on the context's stream; nothing is allocated."""
+    _check(lib().pic_moments_noalloc(ctx, int(inst), C.c_void_p(int(out_ptr))), ctx)
 
 
 def pic_well_depth(ctx, inst, r_mid):

@@ -23,6 +23,7 @@ SOURCES = {
     "k_field.hip": [],
     "fp32.hip": [],
     "insert.hip": ["-ffp-contract=off"],
+    "noalloc.hip": [],
 }
 
 COMMON = [

@@ -134,6 +134,7 @@ void pic_dev_free(pic_ctx* ctx, void* p) {
 }
 
 hipStream_t pic_stream(pic_ctx* ctx) { return ctx->stream; }
+int pic_device(pic_ctx* ctx) { return ctx->run.device; }
 
 template <class T>
 static T* dalloc(pic_ctx* ctx, long long count) {
@@ -662,6 +663,8 @@ DevInst& pic_inst_dev(pic_ctx* ctx, int k) { return ctx->in[k].I; }
 const pic_instance_cfg& pic_inst_cfg(pic_ctx* ctx, int k) { return ctx->in[k].c; }
 long long* pic_counters(pic_ctx* ctx) { return ctx->dcnt; }
 long long* pic_inst_Q(pic_ctx* ctx, int k) { return ctx->in[k].Q; }
+long long pic_inst_nodes(pic_ctx* ctx, int k) { return ctx->in[k].nodes; }
+const double* pic_inst_volume(pic_ctx* ctx, int k) { return ctx->in[k].V; }
 long long* pic_inst_Qw(pic_ctx* ctx, int k) { return ctx->in[k].Qw; }
 long long* pic_inst_Qx(pic_ctx* ctx, int k) { return ctx->in[k].Qx; }
 float4* pic_inst_EB(pic_ctx* ctx, int k) { return ctx->in[k].EB; }
@@ -1033,8 +1036,9 @@ extern "C" pic_status pic_init(const pic_run_cfg* run, const pic_instance_cfg* i
     ctx->run = *run;
     ctx->mode = run->mode;
     hipError_t e = hipSetDevice(run->device);
+    if (e == hipSuccess) e = noalloc_setup(run->device);
     if (e != hipSuccess) {
-        std::string m = std::string("hipSetDevice: ") + hipGetErrorString(e);
+        std::string m = std::string("device set-up: ") + hipGetErrorString(e);
         delete ctx;
         return fail(nullptr, PIC_EDEVICE, m);
     }
@@ -1364,6 +1368,9 @@ static pic_status check_inst(pic_ctx* ctx, int k) {
     if (k < 0 || k >= (int)ctx->in.size()) return fail(ctx, PIC_EINVAL, "instance index out of range");
     return PIC_OK;
 }
+
+pic_status pic_check_instance(pic_ctx* ctx, int k) { return check_inst(ctx, k); }
+pic_status pic_fail(pic_ctx* ctx, pic_status st, const std::string& msg) { return fail(ctx, st, msg); }
 
 extern "C" pic_status pic_set_particles(pic_ctx* ctx, int k, long long n, const double* r,
                                         const double* z, const double* vr, const double* vt,
@@ -1851,6 +1858,14 @@ extern "C" pic_status pic_capacity(pic_ctx* ctx, int k, long long* slots, long l
     return PIC_OK;
 }
 
+pic_status pic_moments_accumulate(pic_ctx* ctx, int k, double* acc) {
+    Inst& in = ctx->in[k];
+    if (ctx->mode != PIC_MODE_FP64_PLAIN) return f32_moments(ctx, k, acc);
+    const hipError_t e = launch_moments64(in.I, in.p64[in.cur], in.cnt, acc, ctx->stream);
+    if (e != hipSuccess) return fail(ctx, PIC_EDEVICE, std::string("moments: ") + hipGetErrorString(e));
+    return PIC_OK;
+}
+
 extern "C" pic_status pic_moments(pic_ctx* ctx, int k, double* out) {
     pic_status st = check_inst(ctx, k);
     if (st != PIC_OK) return st;
@@ -1862,10 +1877,7 @@ extern "C" pic_status pic_moments(pic_ctx* ctx, int k, double* out) {
     double* acc = dalloc<double>(ctx, kMoments * N);
     if (!acc) return fail(ctx, PIC_ENOMEM, "moment accumulators");
     hipError_t e = hipMemsetAsync(acc, 0, sizeof(double) * kMoments * N, s);
-    if (e == hipSuccess) {
-        if (ctx->mode == PIC_MODE_FP64_PLAIN) e = launch_moments64(in.I, in.p64[in.cur], in.cnt, acc, s);
-        else st = f32_moments(ctx, k, acc);
-    }
+    if (e == hipSuccess) st = pic_moments_accumulate(ctx, k, acc);
     if (e == hipSuccess && st == PIC_OK) e = hipMemcpyAsync(out, acc, sizeof(double) * kMoments * N, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess && st == PIC_OK) e = hipStreamSynchronize(s);
     pic_dev_free(ctx, acc);

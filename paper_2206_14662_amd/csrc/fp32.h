@@ -13,6 +13,16 @@ struct F32State;
 void* pic_dev_alloc(pic_ctx* ctx, size_t bytes);
 void pic_dev_free(pic_ctx* ctx, void* p);
 hipStream_t pic_stream(pic_ctx* ctx);
+// instance k exists (PIC_OK) or the error recorded on ctx
+pic_status pic_check_instance(pic_ctx* ctx, int k);
+// record an error message on ctx and return st
+pic_status pic_fail(pic_ctx* ctx, pic_status st, const std::string& msg);
+int pic_device(pic_ctx* ctx);
+long long pic_inst_nodes(pic_ctx* ctx, int k);
+const double* pic_inst_volume(pic_ctx* ctx, int k);   // device node volumes
+// launch the moment kernels of instance k into acc (kMoments channel-major
+// node arrays, zeroed by the caller) on the context's stream; no allocation
+pic_status pic_moments_accumulate(pic_ctx* ctx, int k, double* acc);
 int pic_n_inst(pic_ctx* ctx);
 pic::DevInst& pic_inst_dev(pic_ctx* ctx, int k);
 const pic_instance_cfg& pic_inst_cfg(pic_ctx* ctx, int k);

@@ -393,6 +393,9 @@ hipError_t set_field_kernel_attrs(int max_nz);
 // Elliptic insert (insert.hip).  ins_build classifies the nodes, attaches
 // the outer hats, and assembles D on the host; an empty string means success.
 std::string ins_build(const pic_instance_cfg& c, InsHost& h);
+// The allocation-free entry points' scratch on the current device
+// (noalloc.hip): look up its address once per device.
+hipError_t noalloc_setup(int device);
 // The insert fields of DevInst (centre, semi-axes, weight band gam) of an
 // instance with mesh spacings dr, dz.
 void ins_fill(const pic_instance_cfg& c, double dr, double dz, DevInst& I);
