@@ -115,7 +115,7 @@ def test_one_step_against_oracle_fp32_accuracy(p_mbar, seed):
     # the null-collision test is an exact integer compare on the same Philox words
     assert gd["n_null_cand"] == od["n_null_cand"]
     assert gd["n_elastic"] > 100 and gd["n_ioniz"] > 10
-    res = fp32_step_parity(g.get_particles(), o.get_particles(), o0.get_particles(), max_flips=4)
+    res = fp32_step_parity(g.get_particles(), o.get_particles(), o0.get_particles(), max_flips=4, before=st)
     # the oracle's scattered particles: elastic, ionised primaries and new electrons
     assert res["scattered"] + res["flips"] >= od["n_elastic"] + 2 * od["n_ioniz"]
     assert abs(gd["n_elastic"] - od["n_elastic"]) + abs(gd["n_ioniz"] - od["n_ioniz"]) <= res["flips"]
