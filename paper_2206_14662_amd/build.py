@@ -14,6 +14,9 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 OUT = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libpicmcc.so")
+# streaming-bandwidth probes (a measurement tool beside the library)
+PROBE_SRC = "stream_probe.hip"
+PROBE_LIB = os.path.join(PKG, "libstreamprobe.so")
 ARCH = os.environ.get("PIC_OFFLOAD_ARCH", "gfx950")
 
 # source -> extra flags
@@ -59,6 +62,10 @@ def build(verbose=False, jobs=None):
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
     os.replace(LIB + ".tmp", LIB)
+    probe = _compile(PROBE_SRC, [], verbose)
+    cmd = ["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", PROBE_LIB + ".tmp", probe]
+    subprocess.run(cmd, check=True)
+    os.replace(PROBE_LIB + ".tmp", PROBE_LIB)
     return LIB
 
 
