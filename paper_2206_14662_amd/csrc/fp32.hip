@@ -173,8 +173,25 @@ struct LocalInst {
     int nr, nz, W, ntz, tile_off, collisions, has_ins;
     unsigned int seed_lo, seed_hi;
     unsigned long long null_k;
-    EvConst ev;
 };
+
+// The instance table seen through the constant address space: a field read
+// with a wave-uniform index becomes a scalar load, so rare paths can fetch
+// instance constants when they need them instead of holding them in
+// registers across the particle loop.
+// The empty asm keeps the index (and so the load) where it is written: the
+// compiler would otherwise hoist the invariant load out of the loop and hold
+// its value in a register for the whole chunk.
+typedef __attribute__((address_space(4))) const DevInst cDevInst;
+__device__ __forceinline__ cDevInst* const_inst(const DevInst* It, int k) {
+    asm volatile("" : "+s"(k));
+    return (cDevInst*)(const __attribute__((address_space(1))) DevInst*)It + k;
+}
+typedef __attribute__((address_space(4))) const FieldDev cFieldDev;
+__device__ __forceinline__ cFieldDev* const_field(const FieldDev* Ft, int k) {
+    asm volatile("" : "+s"(k));
+    return (cFieldDev*)(const __attribute__((address_space(1))) FieldDev*)Ft + k;
+}
 
 __device__ __forceinline__ float uniform_f(float x) {
     return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x)));
@@ -200,9 +217,6 @@ __device__ __forceinline__ LocalInst local_inst(const DevInst& I) {
     const unsigned long long k = I.null_k;
     L.null_k = ((unsigned long long)(unsigned int)__builtin_amdgcn_readfirstlane((int)(k >> 32)) << 32) |
                (unsigned long long)(unsigned int)__builtin_amdgcn_readfirstlane((int)(unsigned int)k);
-    L.ev.half_me_over_e = uniform_f(I.half_me_over_e_f); L.ev.nsig_el = uniform_f(I.nsig_el_f);
-    L.ev.iz_I = uniform_f(I.iz_I_f); L.ev.lotz_aq = uniform_f(I.lotz_aq_f); L.ev.n_n = uniform_f(I.n_n_f);
-    L.ev.nu_prime = uniform_f(I.nu_prime_f); L.ev.xs_n = __builtin_amdgcn_readfirstlane(I.xs_n);
     return L;
 }
 
@@ -293,7 +307,8 @@ __device__ __forceinline__ void scatter_f(float ur, float ut, float uz, float co
 // energy it used.  The particle kernel calls it to queue only real events;
 // the collision kernel calls it again on the same stored velocity, so both
 // take the same decision.  I supplies the cross-section tables only.
-__device__ __forceinline__ int event_kind_f(const EvConst& c, const DevInst& I, unsigned int bits, float vr,
+template <class INST>
+__device__ __forceinline__ int event_kind_f(const EvConst& c, const INST& I, unsigned int bits, float vr,
                                             float vt, float vz, float& v, float& E) {
     const float u_proc = u23(bits);
     const float v2 = (vr * vr + vt * vt) + vz * vz;
@@ -553,7 +568,7 @@ __device__ __forceinline__ void push_particle(const KArgs& A, const ChunkCtx& X,
         const int li = (i - X.i0) * X.ww + (j - X.j0);
         f00 = X.sEB[li]; f01 = X.sEB[li + 1]; f10 = X.sEB[li + X.ww]; f11 = X.sEB[li + X.ww + 1];
     } else {
-        gbl_v4f* G = as_gbl(X.EB);
+        gbl_v4f* G = as_gbl(const_field(A.Ft, X.inst)->EB);
         const long long n00 = (long long)i * L.W + j;
         f00 = G[n00]; f01 = G[n00 + 1]; f10 = G[n00 + L.W]; f11 = G[n00 + L.W + 1];
     }
@@ -608,18 +623,22 @@ __device__ __forceinline__ void push_particle(const KArgs& A, const ChunkCtx& X,
     const float rr2 = fmaf(x, x, y * y);
     const float inv = __builtin_amdgcn_rsqf(rr2);
     const float rn = rr2 * inv;
+    // The wall that absorbs the particle, by priority: a non-finite new
+    // position (a non-finite field or velocity; removed, not counted as
+    // absorbed charge) before the inner electrode (x = y = 0 gives rn NaN
+    // from 0 * inf: inner), the outer one, the insert (outer-electrode
+    // metal), then the ends.  Written as selects, lowest priority first.
     int wall = -1;
-    // a non-finite new position (a non-finite field or velocity) removes the
-    // particle without counting it as absorbed charge; x = y = 0 (rn NaN from
-    // 0 * inf) is the inner wall
-    if (!(rr2 < __builtin_inff() && fabsf(zn) < __builtin_inff())) wall = 4;
-    else if (!(rn > L.a)) wall = 0;
-    else if (rn >= L.b) wall = 1;
-    else if (INS && L.has_ins && fmaf((rn - L.ins_r0) * L.ins_inv_er, (rn - L.ins_r0) * L.ins_inv_er,
-                               ((zn - L.ins_z0) * L.ins_inv_ez) * ((zn - L.ins_z0) * L.ins_inv_ez)) - 1.0f <= 0.0f)
-        wall = 1;  // the insert is outer-electrode metal
-    else if (zn <= 0.0f) wall = 2;
-    else if (zn >= L.L) wall = 3;
+    wall = zn >= L.L ? 3 : wall;
+    wall = zn <= 0.0f ? 2 : wall;
+    if (INS && L.has_ins)
+        wall = fmaf((rn - L.ins_r0) * L.ins_inv_er, (rn - L.ins_r0) * L.ins_inv_er,
+                    ((zn - L.ins_z0) * L.ins_inv_ez) * ((zn - L.ins_z0) * L.ins_inv_ez)) - 1.0f <= 0.0f
+                   ? 1
+                   : wall;
+    wall = rn >= L.b ? 1 : wall;
+    wall = !(rn > L.a) ? 0 : wall;
+    wall = !(rr2 < __builtin_inff() && fabsf(zn) < __builtin_inff()) ? 4 : wall;
     const float cs = x * inv, sn = y * inv;
     const float vrn = fmaf(cs, vr, sn * vt);
     const float vtn = fmaf(cs, vt, -(sn * vr));
@@ -653,7 +672,11 @@ __device__ __forceinline__ void push_particle(const KArgs& A, const ChunkCtx& X,
             // straight to the device
             atomicAdd(&X.s_ctr[SC_CAND], 1ull);
             float sp, en;
-            const int kind = event_kind_f(L.ev, A.It[X.inst], b0.z, vrn, vtn, vz, sp, en);
+            cDevInst* Ic = const_inst(A.It, X.inst);
+            EvConst ev;
+            ev.half_me_over_e = Ic->half_me_over_e_f; ev.nsig_el = Ic->nsig_el_f; ev.iz_I = Ic->iz_I_f;
+            ev.lotz_aq = Ic->lotz_aq_f; ev.n_n = Ic->n_n_f; ev.nu_prime = Ic->nu_prime_f; ev.xs_n = Ic->xs_n;
+            const int kind = event_kind_f(ev, *Ic, b0.z, vrn, vtn, vz, sp, en);
             if (kind != 0) {
                 atomicAdd(&X.s_ctr[kind == 1 ? SC_EL : SC_IZ], 1ull);
                 const unsigned int qr = atomicAdd(X.s_qn, 1u);
@@ -689,7 +712,7 @@ __device__ __forceinline__ void push_particle(const KArgs& A, const ChunkCtx& X,
             lds_add(&X.sQ[l + X.ww + 1], (unsigned long long)q11);
         } else {
             atomicAdd(&X.s_ctr[SC_FAR], 1ull);
-            gbl_u64* Qg = as_gbl(X.Q);
+            gbl_u64* Qg = as_gbl(const_field(A.Ft, X.inst)->Q);
             const long long n00 = (long long)ni * L.W + nj;
             gbl_add(&Qg[n00], (unsigned long long)q00);
             gbl_add(&Qg[n00 + L.W], (unsigned long long)q10);
