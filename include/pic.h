@@ -119,9 +119,11 @@ typedef struct {
      * walls' Dirichlet conditions built in by odd reflection, and the
      * space-charge field -grad phi_sc evaluated at each particle from the
      * spline coefficients (the vacuum field stays the order-1 nodal field).
-     * Order 3 runs in both forms (the batched FP32 form gathers from an FP32
-     * copy of the coefficients); it needs end_mode 0 or 1, no insert, and the
-     * same order for every instance of the context. */
+     * With open ends (end_mode 2) the coefficients are reflected evenly at
+     * z = 0 and z = L instead, so the space-charge potential has zero
+     * z-derivative there.  Order 3 runs in both forms (the batched FP32 form
+     * gathers from an FP32 copy of the coefficients); it needs no insert and
+     * the same order for every instance of the context. */
     int spline_order;
 } pic_instance_cfg;
 

@@ -22,6 +22,11 @@
  * The external (vacuum) field stays the order-1 nodal field of orc_field.c;
  * the space-charge field at a particle is -grad phi_sc from the cubic
  * derivatives.
+ * Open ends (end_mode 2, Sec. II.A: d phi / dz = 0 at z = 0 and z = L): the
+ * coefficients are reflected evenly in z instead (c at j = -1 is c at j = 1,
+ * c at j = nz+1 is c at j = nz-1, and c at j = 0 and j = nz are unknowns),
+ * so every basis function has zero z-derivative on the ends; the unknowns in
+ * z are then 0 <= j <= nz.  The r direction keeps the odd reflection.
  */
 #include "oracle.h"
 
@@ -31,6 +36,7 @@
 
 struct orc_s3 {
     int nr, nz, N, bw;
+    int open;          /* even reflection in z (open ends) */
     double a, dr, dz;
     double* Lb;  /* banded Cholesky factor */
 };
@@ -83,6 +89,13 @@ void orc_s3_deposit(const orc_cfg* c, double r, double z, int64_t Wq, int64_t* Q
         }
 }
 
+/* raw index in [-1, n+1] -> unknown index in [0, n] with its sign under the
+ * even reflection of open ends (every index maps to an unknown) */
+static int fold_even(int i, int n, int* u) {
+    *u = i < 0 ? -i : (i > n ? 2 * n - i : i);
+    return 1;
+}
+
 /* raw index in [-1, n+1] -> unknown index in [1, n-1] with its sign; 0 if the
  * coefficient is fixed at 0 (on the wall) */
 static int fold(int i, int n, int* u) {
@@ -101,10 +114,17 @@ static int fold(int i, int n, int* u) {
     return 0;
 }
 
+/* z fold of the configuration: odd (Dirichlet ends) or even (open ends) */
+static int fold_z(int open, int j, int nz, int* u) { return open ? fold_even(j, nz, u) : fold(j, nz, u); }
+
+/* first unknown index in z and the number of unknowns in z */
+static int zfirst(const orc_s3* S) { return S->open ? 0 : 1; }
+static int nz_unk(const orc_s3* S) { return S->open ? S->nz + 1 : S->nz - 1; }
+
 static int unk(const orc_s3* S, int i, int j) {
-    const int nri = S->nr - 1, nzi = S->nz - 1;
-    if (nri <= nzi) return (j - 1) * nri + (i - 1);
-    return (i - 1) * nzi + (j - 1);
+    const int nri = S->nr - 1, nzi = nz_unk(S), jj = j - zfirst(S);
+    if (nri <= nzi) return jj * nri + (i - 1);
+    return (i - 1) * nzi + jj;
 }
 
 static const double G4X[4] = {-0.86113631159405257522, -0.33998104358485626480, 0.33998104358485626480,
@@ -119,16 +139,17 @@ void orc_s3_destroy(orc_s3* S) {
 }
 
 orc_s3* orc_s3_create(const orc_cfg* c) {
-    if (c->end_mode == 2 || c->nr < 4 || c->nz < 4) return NULL;
+    if (c->nr < 4 || c->nz < 4) return NULL;
     orc_s3* S = (orc_s3*)calloc(1, sizeof(orc_s3));
     S->nr = c->nr;
     S->nz = c->nz;
+    S->open = c->end_mode == 2;
     S->a = c->a;
     S->dr = (c->b - c->a) / (double)c->nr;
     S->dz = c->L / (double)c->nz;
-    S->N = (c->nr - 1) * (c->nz - 1);
+    S->N = (c->nr - 1) * nz_unk(S);
     /* couplings reach 3 nodes in each direction (the fold keeps them there) */
-    const int nri = c->nr - 1, nzi = c->nz - 1;
+    const int nri = c->nr - 1, nzi = nz_unk(S);
     S->bw = nri <= nzi ? 3 * nri + 3 : 3 * nzi + 3;
     const int B1 = S->bw + 1;
     double* A = (double*)calloc((size_t)S->N * B1, sizeof(double));
@@ -158,8 +179,8 @@ orc_s3* orc_s3_create(const orc_cfg* c) {
             int up[16], sp[16];
             for (int a = 0; a < 4; ++a)
                 for (int b = 0; b < 4; ++b) {
-                    int ui, uj;
-                    const int si = fold(ci - 1 + a, c->nr, &ui), sj = fold(cj - 1 + b, c->nz, &uj);
+                    int ui = 0, uj = 0;
+                    const int si = fold(ci - 1 + a, c->nr, &ui), sj = fold_z(S->open, cj - 1 + b, c->nz, &uj);
                     sp[a * 4 + b] = si * sj;
                     up[a * 4 + b] = (si && sj) ? unk(S, ui, uj) : -1;
                 }
@@ -204,8 +225,8 @@ void orc_s3_solve(const orc_s3* S, const orc_cfg* c, const int64_t* Qx, double* 
     double* x = (double*)calloc(S->N, sizeof(double));
     for (int i = -1; i <= c->nr + 1; ++i)
         for (int j = -1; j <= c->nz + 1; ++j) {
-            int ui, uj;
-            const int si = fold(i, c->nr, &ui), sj = fold(j, c->nz, &uj);
+            int ui = 0, uj = 0;
+            const int si = fold(i, c->nr, &ui), sj = fold_z(S->open, j, c->nz, &uj);
             if (!si || !sj) continue;
             x[unk(S, ui, uj)] += (double)(si * sj) * (double)Qx[(size_t)(i + 1) * WX + (size_t)(j + 1)];
         }
@@ -224,8 +245,8 @@ void orc_s3_solve(const orc_s3* S, const orc_cfg* c, const int64_t* Qx, double* 
     }
     for (int i = -1; i <= c->nr + 1; ++i)
         for (int j = -1; j <= c->nz + 1; ++j) {
-            int ui, uj;
-            const int si = fold(i, c->nr, &ui), sj = fold(j, c->nz, &uj);
+            int ui = 0, uj = 0;
+            const int si = fold(i, c->nr, &ui), sj = fold_z(S->open, j, c->nz, &uj);
             cx[(size_t)(i + 1) * WX + (size_t)(j + 1)] = (si && sj) ? (double)(si * sj) * x[unk(S, ui, uj)] : 0.0;
         }
     const double nb[3] = {1.0 / 6.0, 4.0 / 6.0, 1.0 / 6.0};
@@ -302,8 +323,8 @@ int orc_s3_poisson_fn(const orc_cfg* c, double (*f)(double, double, void*), void
     double* x = (double*)calloc(S->N, sizeof(double));
     for (int i = -1; i <= c->nr + 1; ++i)
         for (int j = -1; j <= c->nz + 1; ++j) {
-            int ui, uj;
-            const int si = fold(i, c->nr, &ui), sj = fold(j, c->nz, &uj);
+            int ui = 0, uj = 0;
+            const int si = fold(i, c->nr, &ui), sj = fold_z(S->open, j, c->nz, &uj);
             if (!si || !sj) continue;
             x[unk(S, ui, uj)] += (double)(si * sj) * load[(size_t)(i + 1) * WX + (size_t)(j + 1)];
         }
@@ -321,8 +342,8 @@ int orc_s3_poisson_fn(const orc_cfg* c, double (*f)(double, double, void*), void
     }
     for (int i = -1; i <= c->nr + 1; ++i)
         for (int j = -1; j <= c->nz + 1; ++j) {
-            int ui, uj;
-            const int si = fold(i, c->nr, &ui), sj = fold(j, c->nz, &uj);
+            int ui = 0, uj = 0;
+            const int si = fold(i, c->nr, &ui), sj = fold_z(S->open, j, c->nz, &uj);
             cx[(size_t)(i + 1) * WX + (size_t)(j + 1)] = (si && sj) ? (double)(si * sj) * x[unk(S, ui, uj)] : 0.0;
         }
     free(x);

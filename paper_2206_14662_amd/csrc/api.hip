@@ -214,7 +214,6 @@ static std::string validate(const pic_instance_cfg& c) {
     if (c.end_mode < 0 || c.end_mode > 2) return "end_mode must be 0, 1 or 2";
     if (c.diag_interval < 0) return "diag_interval must be >= 0";
     if (c.spline_order != 0 && c.spline_order != 1 && c.spline_order != 3) return "spline_order must be 1 or 3";
-    if (c.spline_order == 3 && c.end_mode == 2) return "cubic shapes need end_mode 0 or 1";
     if (c.spline_order == 3 && (c.ins_er != 0.0 || c.ins_ez != 0.0)) return "cubic shapes do not take the insert";
     if (c.ins_er != 0.0 || c.ins_ez != 0.0) {
         if (!(c.ins_er > 0.0 && c.ins_ez > 0.0 && std::isfinite(c.ins_r0) && std::isfinite(c.ins_z0)))
@@ -369,12 +368,15 @@ static void host_thomas(const pic_instance_cfg& c, int nseg, std::vector<double>
         }
 }
 
-// Cubic shapes: per sine mode k the 7-band r system (mu_k Kr + kappa_k Mr),
+// Cubic shapes: per z mode k the 7-band r system (mu_k Kr + kappa_k Mr),
 // Kr = int r psi_i' psi_i'' dr, Mr = int r psi_i psi_i' dr over the
 // odd-reflected cubic B-splines of the unknowns 1 .. nr-1 (4-point Gauss per
-// cell, exact), mu_k and kappa_k the sine-transform eigenvalues of the
-// reflected cubic mass and stiffness in z (autocorrelations of the cubic
-// B-spline and of its derivative); factored as L D L^T, stored [i][k].
+// cell, exact), mu_k and kappa_k the eigenvalues of the reflected cubic mass
+// and stiffness in z (autocorrelations of the cubic B-spline and of its
+// derivative) for the sine modes 1 .. nz-1 (odd reflection, electrode ends)
+// or the cosine modes 0 .. nz (even reflection, open ends: the Galerkin end
+// rows are half the periodic operator's, which the cosine transform of the
+// loads accounts for); factored as L D L^T, stored [i][k].
 static void host_spline3(const pic_instance_cfg& c, std::vector<double>& L1, std::vector<double>& L2,
                          std::vector<double>& L3, std::vector<double>& Dinv) {
     const int nr = c.nr, nz = c.nz, W = nz + 1, m = nr - 1;
@@ -412,7 +414,8 @@ static void host_spline3(const pic_instance_cfg& c, std::vector<double>& L1, std
     const double mm[4] = {151.0 / 315.0, 397.0 / 1680.0, 1.0 / 42.0, 1.0 / 5040.0};
     const double kk[4] = {2.0 / 3.0, -1.0 / 8.0, -1.0 / 5.0, -1.0 / 120.0};
     std::vector<double> A((size_t)(m + 1) * 4), Lr((size_t)(m + 1) * 4, 0.0), D(m + 1, 0.0);
-    for (int k = 1; k <= nz - 1; ++k) {
+    const bool open = c.end_mode == 2;
+    for (int k = open ? 0 : 1; k <= (open ? nz : nz - 1); ++k) {
         const double th = kPi * (double)k / (double)nz;
         double mu = mm[0], ka = kk[0];
         for (int l = 1; l <= 3; ++l) {

@@ -504,6 +504,8 @@ __global__ void ks_commit(const DevInst* __restrict__ It, long long* cnt_base, l
 // ---- cubic B-spline space charge ------------------------------------------
 // Unknown coefficients at 1 <= i <= nr-1, 1 <= j <= nz-1; the ghost nodes
 // -1 and nr+1 (nz+1) hold minus the reflected coefficient, the wall nodes 0.
+// Open ends reflect evenly in z instead: j = 0 .. nz are unknowns and the
+// ghosts j = -1, nz+1 hold the coefficients at 1, nz-1.
 
 // raw index in [-1, n+1] -> unknown index and sign (0: fixed at 0)
 __device__ __forceinline__ int fold3(int i, int n, int& u) {
@@ -515,6 +517,13 @@ __device__ __forceinline__ int fold3(int i, int n, int& u) {
     return (i == -1 || i == n + 1) ? -1 : 0;
 }
 
+// the z fold: odd (electrode ends) or even (open ends)
+__device__ __forceinline__ int fold3z(int j, int n, bool open, int& u) {
+    if (!open) return fold3(j, n, u);
+    u = j < 0 ? -j : (j > n ? 2 * n - j : j);
+    return 1;
+}
+
 // load of the unknowns: the ghosted deposit folded with the reflection signs
 __global__ void k3_fold(const DevInst* __restrict__ It, const FieldDev* __restrict__ F3,
                         const double* __restrict__ bscale) {
@@ -523,16 +532,19 @@ __global__ void k3_fold(const DevInst* __restrict__ It, const FieldDev* __restri
     if (I.frozen) return;
     const int W = I.W, WX = I.nz + 3;
     const double bs = bscale[blockIdx.y];
+    const bool open = I.open_ends != 0;
+    const double sz = open ? 1.0 : -1.0;  // sign of the z ghosts
+    const int jlo = open ? 0 : 1, jhi = open ? I.nz : I.nz - 1;
     for (int n = blockIdx.x * blockDim.x + threadIdx.x; n < I.nodes; n += gridDim.x * blockDim.x) {
         const int i = n / W, j = n - i * W;
-        if (i < 1 || i > I.nr - 1 || j < 1 || j > I.nz - 1) continue;
+        if (i < 1 || i > I.nr - 1 || j < jlo || j > jhi) continue;
         const int ri[2] = {i, i == 1 ? -1 : (i == I.nr - 1 ? I.nr + 1 : -100)};
         const int rj[2] = {j, j == 1 ? -1 : (j == I.nz - 1 ? I.nz + 1 : -100)};
         double v = 0.0;
         for (int a = 0; a < 2; ++a)
             for (int b = 0; b < 2; ++b) {
                 if (ri[a] == -100 || rj[b] == -100) continue;
-                const double sg = (a == 0 ? 1.0 : -1.0) * (b == 0 ? 1.0 : -1.0);
+                const double sg = (a == 0 ? 1.0 : -1.0) * (b == 0 ? 1.0 : sz);
                 v += sg * (double)F.Qx[(long long)(ri[a] + 1) * WX + (rj[b] + 1)];
             }
         F.rhs[n] = v * bs;
@@ -549,7 +561,8 @@ __global__ void __launch_bounds__(64) k3_band(const DevInst* __restrict__ It, co
     const DevInst& I = It[blockIdx.y];
     const FieldDev& F = F3[blockIdx.y];
     const int k = blockIdx.x * 64 + threadIdx.x;
-    if (I.frozen || k < 1 || k > I.nz - 1) return;
+    const bool open = I.open_ends != 0;
+    if (I.frozen || k < (open ? 0 : 1) || k > (open ? I.nz : I.nz - 1)) return;
     const int W = I.W, m = I.nr - 1;
     double* __restrict__ x = F.rhs;
     const double* __restrict__ L1 = F.s3_L1;
@@ -612,9 +625,10 @@ __global__ void k3_post(const DevInst* __restrict__ It, const FieldDev* __restri
     const double* c = F3[blockIdx.y].phi;
     const int W = I.W, WX = I.nz + 3;
     const long long ext = (long long)(I.nr + 3) * WX;
+    const bool open = I.open_ends != 0;
     auto coef = [&](int ri, int rj) {
         int ui, uj;
-        const int si = fold3(ri, I.nr, ui), sj = fold3(rj, I.nz, uj);
+        const int si = fold3(ri, I.nr, ui), sj = fold3z(rj, I.nz, open, uj);
         return (si && sj) ? (double)(si * sj) * c[(long long)ui * W + uj] : 0.0;
     };
     for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < ext;
@@ -649,7 +663,8 @@ hipError_t launch_solve3_tab(const DevInst* It, const FieldDev* Ft, const FieldD
     const dim3 fb((unsigned)fft_block(max_nz));
     hipLaunchKernelGGL(kf_dst, gdst, fb, lds, s, It, F3, 0, tw, tw_n, 1, bscale);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(k3_band, dim3((unsigned)((max_nz + 63) / 64), n_inst), dim3(64), 0, s, It, F3);
+    // modes 0 .. nz (open ends) or 1 .. nz-1: nz + 1 lanes
+    hipLaunchKernelGGL(k3_band, dim3((unsigned)((max_nz + 1 + 63) / 64), n_inst), dim3(64), 0, s, It, F3);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(kf_dst, gdst, fb, lds, s, It, F3, 0, tw, tw_n, 2, bscale);
     if ((e = hipGetLastError()) != hipSuccess) return e;

@@ -92,6 +92,56 @@ def test_manufactured_solution_fourth_order():
     assert errs[-1] < 2e-7
 
 
+def _manufactured_open(c):
+    a, b, L = c["a"], c["b"], c["L"]
+    kr, kz = np.pi / (b - a), np.pi / L
+    phi = lambda r, z: np.sin(kr * (r - a)) * np.cos(kz * z)
+    f = lambda r, z: (kr ** 2 + kz ** 2) * phi(r, z) - kr * np.cos(kr * (r - a)) * np.cos(kz * z) / r
+    return phi, f
+
+
+def test_manufactured_solution_fourth_order_open_ends():
+    """Open ends (zero z-derivative at z = 0, L, Sec. II.A): phi* = sin(pi
+    (r-a)/(b-a)) cos(pi z/L) is odd about the electrodes and even about the
+    ends, so the cubic space with odd reflection in r and even reflection in z
+    holds it to fourth order (its gradient to third).  Dropping the even
+    reflection (Dirichlet ends) cannot represent cos(pi z/L) at the ends and
+    fails this."""
+    rng = np.random.default_rng(4)
+    errs, ferrs = [], []
+    for nr, nz in ((8, 16), (16, 32), (32, 64)):
+        c = cubic(nr=nr, nz=nz, end_mode=2, V_end=0.0)
+        phi, f = _manufactured_open(c)
+        cx = oracle.s3_poisson_fn(c, f)
+        pts = [(rng.uniform(c["a"], c["b"]), rng.uniform(0, c["L"])) for _ in range(200)]
+        pts += [(rng.uniform(c["a"], c["b"]), z) for z in (0.0, c["L"] * (1 - 1e-12))]
+        errs.append(max(abs(oracle.s3_phi_at(c, cx, r, z) - phi(r, z)) for r, z in pts))
+        e = 0.0
+        for r, z in pts[:60]:
+            er, ez = oracle.s3_field(c, cx, r, z)
+            h = 1e-7
+            e = max(e, abs(er + (phi(r + h, z) - phi(r - h, z)) / (2 * h)),
+                    abs(ez + (phi(r, z + h) - phi(r, z - h)) / (2 * h)))
+        ferrs.append(e)
+        # the z-derivative vanishes on the ends
+        for r in np.linspace(c["a"], c["b"], 7)[1:-1]:
+            assert abs(oracle.s3_field(c, cx, r, 0.0)[1]) < 1e-12 * abs(ferrs[-1] + 1.0) * 1e6
+    assert errs[0] / errs[1] > 12 and errs[1] / errs[2] > 12, errs
+    assert ferrs[0] / ferrs[1] > 6 and ferrs[1] / ferrs[2] > 6, ferrs
+    assert errs[-1] < 2e-7
+
+
+def test_open_ends_column_charge_gives_a_z_independent_potential():
+    """A source that does not depend on z, with open ends: the solution is
+    the radial one at every z (the z-constant function is in the evenly
+    reflected space), so every column of coefficients is the same."""
+    c = cubic(nr=16, nz=32, end_mode=2, V_end=0.0)
+    cx = oracle.s3_poisson_fn(c, lambda r, z: np.sin(7.0e2 * (r - c["a"])) + 1.0).reshape(c["nr"] + 3, -1)
+    inner = cx[1:-1, :]                       # ghosted rows 0 .. nr, every z column (ghosts included)
+    spread = np.abs(inner - inner[:, [1]]).max()
+    assert spread <= 1e-12 * np.abs(inner).max() and np.abs(inner).max() > 0.0
+
+
 def test_green_reciprocity_of_deposit_and_gather():
     """The potential of charge 1 read with the cubic basis at x2 equals that
     of charge 2 at x1 (symmetric system, the same basis for load and read)."""
@@ -125,8 +175,11 @@ def test_cubic_and_bilinear_agree_on_a_smooth_cloud():
 
 
 @pytest.mark.gpu
-def test_gpu_cubic_solve_matches_the_oracle():
-    c = cubic(nr=64, nz=128)
+@pytest.mark.parametrize("end_mode", [0, 2])
+def test_gpu_cubic_solve_matches_the_oracle(end_mode):
+    """The transform-based cubic solve (sine modes for electrode ends, cosine
+    modes for open ends) against the oracle's assembled Galerkin system."""
+    c = cubic(nr=64, nz=128, end_mode=end_mode)
     st = pi.particle_state(c, 40000, seed=12)
     g, o = gpu_and_oracle(c, st, frozen=0)
     Qx, cx = g.spline3()
@@ -141,9 +194,10 @@ def test_gpu_cubic_solve_matches_the_oracle():
 
 
 @pytest.mark.gpu
-@pytest.mark.parametrize("collisions", [0, 1])
-def test_gpu_cubic_steps_match_the_oracle(collisions):
-    c = cubic(nr=64, nz=128, p_mbar=30.0 if collisions else 1e-6, E_cap_eV=3000.0, collisions=collisions)
+@pytest.mark.parametrize("collisions,end_mode", [(0, 0), (1, 0), (1, 2)])
+def test_gpu_cubic_steps_match_the_oracle(collisions, end_mode):
+    c = cubic(nr=64, nz=128, p_mbar=30.0 if collisions else 1e-6, E_cap_eV=3000.0, collisions=collisions,
+              end_mode=end_mode)
     st = pi.cloud_state(c, 30000, seed=13)
     g, o = gpu_and_oracle(c, st, frozen=0)
     g.step(15)
@@ -161,8 +215,7 @@ def test_gpu_cubic_steps_match_the_oracle(collisions):
 
 @pytest.mark.gpu
 def test_cubic_configurations_refused():
-    for cfgs, mode in (([cubic(), pi.coax64(n_init=0)], F64), ([cubic(), pi.coax64(n_init=0)], F32),
-                       ([cubic(end_mode=2)], F64), ([cubic(end_mode=2)], F32)):
+    for cfgs, mode in (([cubic(), pi.coax64(n_init=0)], F64), ([cubic(), pi.coax64(n_init=0)], F32)):
         with pytest.raises(B.PicError) as e:
             B.Sim(cfgs, mode=mode)
         assert e.value.status == B.PIC_EINVAL
@@ -197,8 +250,9 @@ def test_fp32_cubic_is_invariant_to_tiles_and_launches():
 
 
 @pytest.mark.gpu
-def test_fp32_cubic_one_step_against_the_oracle():
-    c = cubic(nr=64, nz=128, p_mbar=30.0, E_cap_eV=3000.0)
+@pytest.mark.parametrize("end_mode", [0, 2])
+def test_fp32_cubic_one_step_against_the_oracle(end_mode):
+    c = cubic(nr=64, nz=128, p_mbar=30.0, E_cap_eV=3000.0, end_mode=end_mode)
     st = _fp32_exact(pi.cloud_state(c, 20000, seed=41))
     g, o = gpu_and_oracle(c, st, frozen=0, mode=F32)
     Qg, cg = g.spline3()
@@ -224,10 +278,11 @@ def test_fp32_cubic_one_step_against_the_oracle():
 
 
 @pytest.mark.gpu
-def test_fp32_cubic_tracks_the_oracle_over_a_run():
+@pytest.mark.parametrize("end_mode", [0, 2])
+def test_fp32_cubic_tracks_the_oracle_over_a_run(end_mode):
     """The small trap at the raised pressure, 300 self-consistent steps with
     cubic shapes: FP32 density and counts within 2% of the FP64 oracle."""
-    cfg = cubic(n_init=50000, p_mbar=1e-1, diag_interval=10)
+    cfg = cubic(n_init=50000, p_mbar=1e-1, diag_interval=10, end_mode=end_mode)
     g = B.Sim([cfg], mode=F32)
     o = oracle.Sim(cfg, fx_shift=g.diag()["S"])
     o.load()
