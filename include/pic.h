@@ -125,6 +125,14 @@ typedef struct {
      * gathers from an FP32 copy of the coefficients); it needs no insert and
      * the same order for every instance of the context. */
     int spline_order;
+    /* Energy-dependent anisotropy of elastic and ionisation scattering
+     * (Sec. II.A, Okhrimovskyy's differential cross section): okh_E0_eV > 0
+     * takes the screened-Coulomb parameter xi(E) = 4 e / (1 + 4 e) with
+     * e = E / okh_E0_eV (E the electron's energy; okh_E0_eV = 27.211386 eV,
+     * the atomic unit of energy, in Okhrimovskyy et al.) instead of the
+     * constant okh_xi; a table from pic_set_anisotropy takes precedence over
+     * both.  0: the constant okh_xi. */
+    double okh_E0_eV;
 } pic_instance_cfg;
 
 typedef struct {

@@ -31,7 +31,7 @@ class OrcCfg(C.Structure):
         ("fx_shift", C.c_int), ("diag_interval", C.c_int), ("collisions", C.c_int),
         ("src_rate", C.c_double), ("src_T_eV", C.c_double),
         ("ins_r0", C.c_double), ("ins_z0", C.c_double), ("ins_er", C.c_double), ("ins_ez", C.c_double),
-        ("ins_band", C.c_double), ("spline_order", C.c_int),
+        ("ins_band", C.c_double), ("spline_order", C.c_int), ("okh_E0_eV", C.c_double),
     ]
 
 
@@ -92,6 +92,8 @@ def lib():
         L.orc_xs_bound.argtypes = [C.c_double]
         L.orc_xs_bound.restype = C.c_double
         L.orc_null_candidates.argtypes = [C.POINTER(OrcCfg), C.c_uint32, C.c_int64, _U64, C.POINTER(C.c_uint8)]
+        L.orc_xi_sc.argtypes = [C.c_double, C.c_double]
+        L.orc_xi_sc.restype = C.c_double
         L.orc_deposit_f32.argtypes = [C.POINTER(OrcCfg), C.c_int64, _D, _D, _D, _I64]
         L.orc_create.argtypes = [C.POINTER(OrcCfg), C.c_int64]
         L.orc_create.restype = C.c_void_p
@@ -353,6 +355,10 @@ def xs_at(E, s, x):
     E = np.ascontiguousarray(E, dtype=np.float64)
     s = np.ascontiguousarray(s, dtype=np.float64)
     return lib().orc_xs_at(len(E), _dp(E), _dp(s), float(x))
+
+
+def xi_sc(E0, E):
+    return lib().orc_xi_sc(float(E0), float(E))
 
 
 def xs_bound(sigv_max):

@@ -63,6 +63,7 @@ typedef struct {
     double ins_r0, ins_z0, ins_er, ins_ez;
     double ins_band;           /* weight-function band in cells (0: 3)          */
     int spline_order;          /* space-charge shapes and FEM: 1 (0) bilinear/Q1, 3 cubic */
+    double okh_E0_eV;          /* > 0: xi(E) = 4e/(1+4e), e = E/okh_E0_eV (screened Coulomb) */
 } orc_cfg;
 
 /* Host-derived constants (all FP64). */
@@ -109,6 +110,7 @@ double orc_sigma_iz(const orc_cfg* c, double E_eV);
 double orc_xs_at(int n, const double* E, const double* s, double x);
 double orc_xs_sigv_max(const orc_cfg* c, int n, const double* E, const double* el, const double* iz);
 double orc_xs_bound(double sigv_max);   /* widened by 2^-20, rounded up to 12 bits */
+double orc_xi_sc(double E0_eV, double E_eV);   /* screened-Coulomb anisotropy 4e/(1+4e), e = E/E0 */
 
 /* Node arrays are r-major: node (i,j) at i*(nz+1)+j, i in [0,nr], j in [0,nz]. */
 void orc_bfield(const orc_cfg* c, double* Br, double* Bz);

@@ -195,9 +195,18 @@ static inline void philox_blk(const orc_sim* s, uint64_t key, uint32_t step, uin
 }
 
 /* Anisotropy of the scattering of an electron of energy E (eV): the table
- * xi(E), linear in E and held at its ends, else the constant okh_xi. */
+ * xi(E), linear in E and held at its ends; else, with okh_E0_eV > 0, the
+ * screened-Coulomb parameter of Okhrimovskyy et al. (2002),
+ * xi = 4 e / (1 + 4 e) with e = E / E0 (E0 their atomic energy unit); else
+ * the constant okh_xi. */
+double orc_xi_sc(double E0, double E) {
+    const double e4 = 4.0 * (E * (1.0 / E0));
+    return e4 / (1.0 + e4);
+}
+
 static inline double xi_at(const orc_sim* s, double E) {
-    return s->xi_n > 0 ? orc_xs_at(s->xi_n, s->xi_E, s->xi_v, E) : s->c.okh_xi;
+    if (s->xi_n > 0) return orc_xs_at(s->xi_n, s->xi_E, s->xi_v, E);
+    return s->c.okh_E0_eV > 0.0 ? orc_xi_sc(s->c.okh_E0_eV, E) : s->c.okh_xi;
 }
 
 /* event: 0 none, 1 elastic, 2 ionisation (child filled), 3 candidate rejected.

@@ -52,7 +52,7 @@ class pic_instance_cfg(C.Structure):
         ("fx_shift", C.c_int), ("diag_interval", C.c_int), ("collisions", C.c_int),
         ("src_rate", C.c_double), ("src_T_eV", C.c_double),
         ("ins_r0", C.c_double), ("ins_z0", C.c_double), ("ins_er", C.c_double), ("ins_ez", C.c_double),
-        ("ins_band", C.c_double), ("spline_order", C.c_int),
+        ("ins_band", C.c_double), ("spline_order", C.c_int), ("okh_E0_eV", C.c_double),
     ]
 
 

@@ -201,6 +201,7 @@ static std::string validate(const pic_instance_cfg& c) {
     if (!(c.sigma_el >= 0.0) || !(c.lotz_a >= 0.0) || !(c.lotz_q >= 0.0)) return "cross sections must be >= 0";
     if (!(c.iz_I_eV > 0.0) || !(c.opal_Ebar_eV > 0.0)) return "iz_I_eV and opal_Ebar_eV must be > 0";
     if (!(c.okh_xi > -1.0 && c.okh_xi < 1.0)) return "okh_xi must be in (-1, 1)";
+    if (!(c.okh_E0_eV >= 0.0 && c.okh_E0_eV < 1e30)) return "okh_E0_eV must be >= 0 and finite";
     if (!(c.E_cap_eV > 0.0)) return "E_cap_eV must be > 0";
     if (c.n_init < 0) return "n_init must be >= 0";
     if (c.n_init > 0) {
@@ -483,6 +484,8 @@ static void fill_devinst(Inst& in) {
     I.nu_prime_f = (float)d.nu_prime; I.nsig_el_f = (float)d.nsig_el; I.n_n_f = (float)d.n_n;
     I.lotz_aq_f = (float)d.lotz_aq; I.iz_I_f = (float)c.iz_I_eV; I.opal_Ebar_f = (float)c.opal_Ebar_eV;
     I.okh_xi_f = (float)c.okh_xi; I.half_me_over_e_f = (float)d.half_me_over_e;
+    I.okh_inv_E0 = c.okh_E0_eV > 0.0 ? 1.0 / c.okh_E0_eV : 0.0;
+    I.okh_inv_E0_f = (float)I.okh_inv_E0;
     I.two_e_over_me_f = (float)d.two_e_over_me; I.mass_ratio2_f = (float)d.mass_ratio2;
     I.v_cap2_f = (float)(d.v_cap * d.v_cap);
     I.diag_D = c.diag_interval > 0 ? c.diag_interval : 1;

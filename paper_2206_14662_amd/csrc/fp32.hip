@@ -274,7 +274,13 @@ __device__ __forceinline__ void flush_counter(long long* slot, unsigned long lon
 // Anisotropy of the scattering law for an electron of energy E (eV), FP32:
 // the table xi(E) when the instance has one, else the constant okh_xi.
 __device__ __forceinline__ float xi_at_f(const DevInst& I, float E) {
-    return I.xi_n > 0 ? xs_interp(I.xi_n, I.xi_Ef, I.xi_vf, E) : I.okh_xi_f;
+    if (I.xi_n > 0) return xs_interp(I.xi_n, I.xi_Ef, I.xi_vf, E);
+    if (I.okh_inv_E0_f > 0.0f) {
+        // screened-Coulomb xi(E) = 4 e / (1 + 4 e), e = E / E0
+        const float e4 = 4.0f * (E * I.okh_inv_E0_f);
+        return e4 / (1.0f + e4);
+    }
+    return I.okh_xi_f;
 }
 
 __device__ __forceinline__ float okh_cos_f(float xi, float u) {

@@ -183,7 +183,13 @@ __global__ void __launch_bounds__(kBlock) k_push64(DevInst I, P64 p, const doubl
 // Anisotropy of the scattering law for an electron of energy E (eV): the
 // table xi(E) when the instance has one, else the constant okh_xi.
 __device__ __forceinline__ double xi_at(const DevInst& I, double E) {
-    return I.xi_n > 0 ? xs_interp(I.xi_n, I.xi_E, I.xi_v, E) : I.okh_xi;
+    if (I.xi_n > 0) return xs_interp(I.xi_n, I.xi_E, I.xi_v, E);
+    if (I.okh_inv_E0 > 0.0) {
+        // screened-Coulomb xi(E) = 4 e / (1 + 4 e), e = E / E0
+        const double e4 = 4.0 * (E * I.okh_inv_E0);
+        return e4 / (1.0 + e4);
+    }
+    return I.okh_xi;
 }
 
 __device__ __forceinline__ double okh_cos(double xi, double u) {

@@ -33,6 +33,7 @@ struct DevInst {
     double h, dt;
     // collisions
     double P_null, nu_prime, nsig_el, n_n, lotz_aq, iz_I, opal_Ebar, okh_xi;
+    double okh_inv_E0;          // 1 / okh_E0_eV, 0: no screened-Coulomb xi(E)
     double half_me_over_e, two_e_over_me, mass_ratio2, v_cap2;
     unsigned long long null_k;      // u52 < P_null  <=>  (x >> 12) < null_k
     unsigned int seed_lo, seed_hi;
@@ -44,7 +45,7 @@ struct DevInst {
     long long p_off, p_cap;
     // single-precision copies for the FP32 form
     float a_f, b_f, L_f, inv_dr_f, inv_dz_f, h_f, dt_f;
-    float nu_prime_f, nsig_el_f, n_n_f, lotz_aq_f, iz_I_f, opal_Ebar_f, okh_xi_f;
+    float nu_prime_f, nsig_el_f, n_n_f, lotz_aq_f, iz_I_f, opal_Ebar_f, okh_xi_f, okh_inv_E0_f;
     float half_me_over_e_f, two_e_over_me_f, mass_ratio2_f, v_cap2_f;
     // sort tiles (FP32 form)
     int ntr, ntz;                   // tiles in r and z

@@ -38,7 +38,7 @@ _BASE = dict(
     T_init_eV=1.0, weight=1.0e5, load_mode=1,
     seed=0, dt=1.0e-12, fx_shift=0, diag_interval=10, collisions=1,
     src_rate=0.0, src_T_eV=0.0,
-    ins_r0=0.0, ins_z0=0.0, ins_er=0.0, ins_ez=0.0, ins_band=0.0, spline_order=1,
+    ins_r0=0.0, ins_z0=0.0, ins_er=0.0, ins_ez=0.0, ins_band=0.0, spline_order=1, okh_E0_eV=0.0,
 )
 
 # Total seed charge of the small case (50k x 1e5 electrons) is kept for the

@@ -78,6 +78,48 @@ def test_oracle_elastic_loss_follows_the_table():
     assert abs(got - mt_ratio(0.0)) > 20 * sd
 
 
+E_HARTREE = 27.211386245988   # eV, the atomic unit of energy
+
+
+def test_screened_coulomb_xi_hand_values():
+    """xi(E) = 4 e / (1 + 4 e), e = E / E0: 0 at rest, 1/2 at E0/4, 3/4 at
+    3E0/4, 4/5 at E0, rising to 1 at high energy."""
+    E0 = E_HARTREE
+    for E, want in ((0.0, 0.0), (0.25 * E0, 0.5), (0.75 * E0, 0.75), (E0, 0.8), (10.0 * E0, 40.0 / 41.0)):
+        assert oracle.xi_sc(E0, E) == pytest.approx(want, rel=1e-15, abs=1e-300)
+    assert oracle.xi_sc(E0, 1e6) > 0.9999
+
+
+def test_oracle_elastic_loss_follows_the_screened_coulomb_xi():
+    """Mono-energetic elastic events with okh_E0_eV set: the mean energy loss
+    gives 1 - <cos chi> at xi(E0) of the closed form, not at okh_xi."""
+    E0, n = 150.0, 120000
+    c = pi.coax64(p_mbar=30.0, n_init=0, E_cap_eV=3000.0, okh_xi=0.0, okh_E0_eV=E_HARTREE, lotz_a=0.0)
+    v = math.sqrt(2 * QE * E0 / ME)
+    rng = np.random.default_rng(35)
+    u = rng.normal(size=(3, n))
+    u /= np.linalg.norm(u, axis=0)
+    st = dict(r=np.full(n, 5e-3), z=np.full(n, 30e-3), vr=v * u[0], vt=v * u[1], vz=v * u[2],
+              w=np.full(n, c["weight"]), key=np.arange(n, dtype=np.uint64))
+    o = oracle.Sim(c, capacity=n + 1000)
+    o.set_fields(**pi.uniform_fields(c, Bz=0.0), frozen=1)
+    o.set_particles(st)
+    o.step(1)
+    p = by_key(o.get_particles())
+    d = o.diag()
+    o.close()
+    En = 0.5 * ME * (p["vr"] ** 2 + p["vt"] ** 2 + p["vz"] ** 2) / QE
+    rel = 1.0 - En / E0
+    hit = np.abs(rel) > 1e-14    # forward-peaked: some events lose < 1e-9
+    assert hit.sum() == d["n_elastic"] > 5000
+    m_ratio = 2.0 * ME / (c["M_gas_amu"] * AMU)
+    got = rel[hit].mean() / m_ratio
+    sd = rel[hit].std() / m_ratio / math.sqrt(hit.sum())
+    xi = 4 * (E0 / E_HARTREE) / (1 + 4 * (E0 / E_HARTREE))
+    assert abs(got - mt_ratio(xi)) <= 5 * sd, (got, mt_ratio(xi), sd)
+    assert abs(got - mt_ratio(0.0)) > 20 * sd
+
+
 def test_refused_anisotropy_tables():
     o = oracle.Sim(pi.coax64(n_init=0))
     for E, xi in (([1.0], [0.1]), ([1.0, 1.0], [0.1, 0.2]), ([1.0, 2.0], [0.1, 1.0]), ([1.0, 2.0], [-1.0, 0.0])):
@@ -99,6 +141,29 @@ def test_gpu_with_anisotropy_matches_the_oracle(mode):
     E, xi = xi_table()
     g.set_anisotropy(0, E, xi)
     o.set_anisotropy(E, xi)
+    g.step(2)
+    o.step(2)
+    gd, od = g.diag(), o.diag()
+    assert gd["n_null_cand"] == od["n_null_cand"] > 100
+    if mode == F64:
+        assert gd["n_elastic"] == od["n_elastic"] > 100 and gd["n_ioniz"] == od["n_ioniz"] > 10
+        gp, op = by_key(g.get_particles()), by_key(o.get_particles())
+        assert np.array_equal(gp["key"], op["key"])
+        assert rel_vec_err(gp, op).max() <= 1e-12
+        assert np.array_equal(g.charge(), o.charge())
+    else:
+        assert abs(gd["n_elastic"] - od["n_elastic"]) <= 2 and abs(gd["n_ioniz"] - od["n_ioniz"]) <= 2
+    g.close()
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("mode", [F64, F32])
+def test_gpu_screened_coulomb_xi_matches_the_oracle(mode):
+    cfg = pi.coax64(p_mbar=30.0, E_cap_eV=3000.0, okh_E0_eV=E_HARTREE)
+    st = pi.cloud_state(cfg, 20000, seed=36)
+    st = {k: (v.astype(np.float32).astype(np.float64) if v.dtype == np.float64 else v) for k, v in st.items()}
+    f = {k: v.astype(np.float32).astype(np.float64) for k, v in pi.random_fields(cfg, 37).items()}
+    g, o = gpu_and_oracle(cfg, st, f, mode=mode)
     g.step(2)
     o.step(2)
     gd, od = g.diag(), o.diag()
