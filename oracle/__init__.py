@@ -123,6 +123,14 @@ def lib():
         L.orc_get_coef3.argtypes = [C.c_void_p, _D]
         L.orc_s3_weights.argtypes = [C.c_double, _D, _D]
         L.orc_s3_poisson_fn.argtypes = [C.POINTER(OrcCfg), _FN, C.c_void_p, _D]
+        L.orc_is3_poisson_fn.argtypes = [C.POINTER(OrcCfg), _FN, C.c_void_p, _D]
+        L.orc_is3_poisson_fn.restype = C.c_int
+        L.orc_is3_phi_at.argtypes = [C.POINTER(OrcCfg), _D, C.c_double, C.c_double]
+        L.orc_is3_phi_at.restype = C.c_double
+        L.orc_is3_field.argtypes = [C.POINTER(OrcCfg), _D, C.c_double, C.c_double, _D, _D]
+        L.orc_is3_info.argtypes = [C.POINTER(OrcCfg), C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)]
+        L.orc_is3_info.restype = C.c_int
+        L.orc_get_charge3w.argtypes = [C.c_void_p, _I64]
         L.orc_s3_poisson_fn.restype = C.c_int
         L.orc_s3_phi_at.argtypes = [C.POINTER(OrcCfg), _D, C.c_double, C.c_double]
         L.orc_s3_phi_at.restype = C.c_double
@@ -411,6 +419,37 @@ def s3_field(d, cx, r, z):
     return float(a[0]), float(b[0])
 
 
+def is3_poisson_fn(d, f):
+    """Cubic web-splines with the insert: ghosted expanded coefficients of the
+    solution of -lap(phi) = f, phi = 0 on the electrodes and the insert (zero
+    z-derivative at open ends)."""
+    cb = _FN(lambda r, z, u: float(f(r, z)))
+    cx = np.zeros(_ext(d))
+    if lib().orc_is3_poisson_fn(C.byref(make_cfg(d)), cb, None, _dp(cx)) != 0:
+        raise ValueError("cubic insert configuration refused")
+    return cx
+
+
+def is3_phi_at(d, cx, r, z):
+    cx = np.ascontiguousarray(cx, dtype=np.float64).reshape(-1)
+    return lib().orc_is3_phi_at(C.byref(make_cfg(d)), _dp(cx), float(r), float(z))
+
+
+def is3_field(d, cx, r, z):
+    cx = np.ascontiguousarray(cx, dtype=np.float64).reshape(-1)
+    a = np.zeros(1); b = np.zeros(1)
+    lib().orc_is3_field(C.byref(make_cfg(d)), _dp(cx), float(r), float(z), _dp(a), _dp(b))
+    return float(a[0]), float(b[0])
+
+
+def is3_info(d):
+    n, bw = C.c_int(), C.c_int()
+    cnt = (C.c_int * 4)()
+    if lib().orc_is3_info(C.byref(make_cfg(d)), C.byref(n), C.byref(bw), cnt) != 0:
+        raise ValueError("cubic insert configuration refused")
+    return dict(n_inner=n.value, bandwidth=bw.value, counts=list(cnt))
+
+
 def num_threads():
     return lib().orc_num_threads()
 
@@ -520,6 +559,11 @@ class Sim:
         c = np.zeros(_ext(self.d))
         lib().orc_get_coef3(self.h, _dp(c))
         return c.reshape(self.d["nr"] + 3, self.d["nz"] + 3)
+
+    def charge3w(self):
+        Q = np.zeros(_ext(self.d), dtype=np.int64)
+        lib().orc_get_charge3w(self.h, Q.ctypes.data_as(_I64))
+        return Q.reshape(self.d["nr"] + 3, self.d["nz"] + 3)
 
     def band_charge(self):
         Q = np.zeros(self.nodes, dtype=np.int64)

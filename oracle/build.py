@@ -8,7 +8,7 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SOURCES = ["orc_core.c", "orc_field.c", "orc_sim.c", "orc_insert.c", "orc_spline3.c", "orc_fp32.c"]
+SOURCES = ["orc_core.c", "orc_field.c", "orc_sim.c", "orc_insert.c", "orc_spline3.c", "orc_fp32.c", "orc_insert3.c"]
 LIB = os.path.join(HERE, "liborc.so")
 
 

@@ -173,6 +173,19 @@ int      orc_s3_poisson_fn(const orc_cfg* c, double (*f)(double, double, void*),
 /* null-collision candidates among n electrons at a step (analytic model) */
 void orc_null_candidates(const orc_cfg* c, uint32_t step, int64_t n, const uint64_t* key, uint8_t* out);
 
+/* ---- elliptic insert with cubic shapes (web-splines of degree 3), orc_insert3.c ---- */
+typedef struct orc_is3 orc_is3;
+orc_is3* orc_is3_create(const orc_cfg* c);
+void     orc_is3_destroy(orc_is3* S);
+/* load Qx + Qxw (ghosted, fixed point) -> ghosted expanded coefficients cx and
+ * the nodal space-charge potential (NULL skips it) */
+void     orc_is3_solve(const orc_is3* S, const orc_cfg* c, const int64_t* Qx, const int64_t* Qxw, double* cx,
+                       double* phi_sc);
+void     orc_is3_field(const orc_cfg* c, const double* cx, double r, double z, double* Er, double* Ez);
+double   orc_is3_phi_at(const orc_cfg* c, const double* cx, double r, double z);
+int      orc_is3_poisson_fn(const orc_cfg* c, double (*f)(double, double, void*), void* user, double* cx);
+int      orc_is3_info(const orc_cfg* c, int* n_inner, int* bandwidth, int counts[4]);
+
 /* ---- simulation object ---- */
 orc_sim* orc_create(const orc_cfg* c, int64_t capacity);
 void     orc_destroy(orc_sim* s);
@@ -207,6 +220,7 @@ void     orc_get_charge_w(const orc_sim* s, int64_t* Qw);   /* insert: band char
  * ((nr+3)(nz+3) arrays, ghost layer included; zeros for order 1) */
 void     orc_get_charge3(const orc_sim* s, int64_t* Qx);
 void     orc_get_coef3(const orc_sim* s, double* cx);
+void     orc_get_charge3w(const orc_sim* s, int64_t* Qxw);  /* cubic + insert: band charges (else 0) */
 void     orc_get_phi(const orc_sim* s, double* phi);
 void     orc_get_diag(const orc_sim* s, orc_diag* d);
 void     orc_get_time_avg_density(const orc_sim* s, double* n_avg);

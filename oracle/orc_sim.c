@@ -37,6 +37,8 @@ struct orc_sim {
     int64_t* Qx;               /* cubic shapes: ghosted cubic deposit (else NULL) */
     double* cx;                /* cubic shapes: ghosted space-charge coefficients */
     orc_s3* s3;                /* cubic shapes: factorised Galerkin system      */
+    orc_is3* is3;              /* cubic shapes with the insert: web-spline system */
+    int64_t* Qxw;              /* cubic shapes with the insert: band deposit    */
     int xs_n;                  /* tabulated cross sections (0: constant / Lotz) */
     double *xs_E, *xs_el, *xs_iz;
     int xi_n;                  /* tabulated anisotropy xi(E) (0: the constant okh_xi) */
@@ -134,11 +136,12 @@ static inline int push_one(const orc_sim* s, int64_t p, double* rr, double* zz,
     double r = rr[p], z = zz[p], vr = vrr[p], vt = vtt[p], vz = vzz[p];
     orc_shape sh = shape_at(c, d, r, z);
     double Er = gather(&sh, s->Er, W), Ez = gather(&sh, s->Ez, W);
-    if (s->s3) {
+    if (s->s3 || s->is3) {
         /* cubic shapes: the nodal arrays hold the vacuum field; the space
          * charge's comes from the spline coefficients at the particle */
         double er, ez;
-        orc_s3_field(c, s->cx, r, z, &er, &ez);
+        if (s->is3) orc_is3_field(c, s->cx, r, z, &er, &ez);
+        else orc_s3_field(c, s->cx, r, z, &er, &ez);
         Er += er;
         Ez += ez;
     }
@@ -301,11 +304,13 @@ static void deposit_all(orc_sim* s) {
     memset(s->Q, 0, sizeof(int64_t) * N);
     if (s->Qw) memset(s->Qw, 0, sizeof(int64_t) * N);
     if (s->Qx) memset(s->Qx, 0, sizeof(int64_t) * NX);
+    if (s->Qxw) memset(s->Qxw, 0, sizeof(int64_t) * NX);
 #pragma omp parallel
     {
         int64_t* loc = (int64_t*)calloc(N, sizeof(int64_t));
         int64_t* locw = s->Qw ? (int64_t*)calloc(N, sizeof(int64_t)) : NULL;
         int64_t* locx = s->Qx ? (int64_t*)calloc(NX, sizeof(int64_t)) : NULL;
+        int64_t* locxw = s->Qxw ? (int64_t*)calloc(NX, sizeof(int64_t)) : NULL;
 #pragma omp for schedule(static)
         for (int64_t p = 0; p < s->n; ++p) {
             orc_shape sh = shape_at(&s->c, &s->d, s->r[p], s->z[p]);
@@ -316,6 +321,10 @@ static void deposit_all(orc_sim* s) {
                 deposit_shape(&sh, (int64_t)rint((double)Wq * (wp - 1.0)), locw, W);
             }
             if (locx) orc_s3_deposit(&s->c, s->r[p], s->z[p], Wq, locx);
+            if (locxw && orc_ins_g(&s->c, s->r[p], s->z[p]) < gam) {
+                double wp = orc_ins_wp(&s->c, s->r[p], s->z[p]);
+                orc_s3_deposit(&s->c, s->r[p], s->z[p], (int64_t)rint((double)Wq * (wp - 1.0)), locxw);
+            }
         }
 #pragma omp critical
         {
@@ -324,15 +333,24 @@ static void deposit_all(orc_sim* s) {
                 for (int k = 0; k < N; ++k) s->Qw[k] += locw[k];
             if (locx)
                 for (int k = 0; k < NX; ++k) s->Qx[k] += locx[k];
+            if (locxw)
+                for (int k = 0; k < NX; ++k) s->Qxw[k] += locxw[k];
         }
         free(loc);
         free(locw);
         free(locx);
+        free(locxw);
     }
 }
 
 static void solve_fields(orc_sim* s) {
     if (s->frozen) return;
+    if (s->is3) {
+        /* cubic shapes with the insert: the nodal E stays the vacuum field */
+        orc_is3_solve(s->is3, &s->c, s->Qx, s->Qxw, s->cx, s->phi);
+        for (int k = 0; k < s->nodes; ++k) s->phi[k] += s->phi_vac[k];
+        return;
+    }
     if (s->s3) {
         /* cubic shapes: the nodal E stays the vacuum field */
         orc_s3_solve(s->s3, &s->c, s->Qx, s->cx, s->phi);
@@ -364,11 +382,12 @@ orc_sim* orc_create(const orc_cfg* c, int64_t capacity) {
     s->avg_acc = (double*)calloc(s->nodes, sizeof(double));
     if (s->c.spline_order == 3) {
         if (orc_has_insert(&s->c)) {
-            orc_destroy(s);
-            return NULL;
+            s->is3 = orc_is3_create(&s->c);
+            s->Qxw = (int64_t*)calloc((size_t)orc_s3_ext(&s->c), sizeof(int64_t));
+        } else {
+            s->s3 = orc_s3_create(&s->c);
         }
-        s->s3 = orc_s3_create(&s->c);
-        if (!s->s3) {
+        if (!s->s3 && !s->is3) {
             orc_destroy(s);
             return NULL;
         }
@@ -384,7 +403,7 @@ orc_sim* orc_create(const orc_cfg* c, int64_t capacity) {
             orc_destroy(s);
             return NULL;
         }
-        s->Qw = (int64_t*)calloc(s->nodes, sizeof(int64_t));
+        if (!s->is3) s->Qw = (int64_t*)calloc(s->nodes, sizeof(int64_t));
     }
     orc_bfield(&s->c, s->Br, s->Bz);
     orc_vacuum(&s->c, s->phi_vac);
@@ -402,6 +421,8 @@ void orc_destroy(orc_sim* s) {
     free(s->Qw);
     free(s->Qx); free(s->cx);
     orc_s3_destroy(s->s3);
+    orc_is3_destroy(s->is3);
+    free(s->Qxw);
     free(s->xs_E); free(s->xs_el); free(s->xs_iz);
     free(s->xi_E); free(s->xi_v);
     orc_ins_destroy(s->ins);
@@ -485,7 +506,7 @@ void orc_set_fields(orc_sim* s, const double* Er, const double* Ez,
     if (Br) memcpy(s->Br, Br, b);
     if (Bz) memcpy(s->Bz, Bz, b);
     s->frozen = frozen;
-    if (s->s3) {
+    if (s->s3 || s->is3) {
         /* cubic shapes: a frozen field is the given nodal one alone; back to
          * the self-consistent field, the nodal arrays hold the vacuum field */
         memset(s->cx, 0, sizeof(double) * (size_t)orc_s3_ext(&s->c));
@@ -745,6 +766,10 @@ void orc_get_charge3(const orc_sim* s, int64_t* Qx) {
 void orc_get_coef3(const orc_sim* s, double* cx) {
     if (s->cx) memcpy(cx, s->cx, sizeof(double) * (size_t)orc_s3_ext(&s->c));
     else memset(cx, 0, sizeof(double) * (size_t)orc_s3_ext(&s->c));
+}
+void orc_get_charge3w(const orc_sim* s, int64_t* Qxw) {
+    if (s->Qxw) memcpy(Qxw, s->Qxw, sizeof(int64_t) * (size_t)orc_s3_ext(&s->c));
+    else memset(Qxw, 0, sizeof(int64_t) * (size_t)orc_s3_ext(&s->c));
 }
 void orc_get_charge_w(const orc_sim* s, int64_t* Qw) {
     if (s->Qw) memcpy(Qw, s->Qw, sizeof(int64_t) * s->nodes);
