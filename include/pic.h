@@ -103,9 +103,10 @@ typedef struct {
     /* Elliptic insert on the outer electrode (Sec. III: the gun geometry, a
      * filled ellipse on the outer cylinder): metal at V_outer where
      * ((r-ins_r0)/ins_er)^2 + ((z-ins_z0)/ins_ez)^2 <= 1.  The space-charge
-     * potential uses weighted extended B-splines of degree 1 (Sec. II.A):
-     * hat functions times a weight function that vanishes on the ellipse and
-     * is 1 beyond a band of about ins_band cells.  Particles entering it are
+     * potential uses weighted extended B-splines (Sec. II.A) of the degree of
+     * the particle shapes (1 or 3, spline_order): B-splines times a weight
+     * function that vanishes on the ellipse and is 1 beyond a band of about
+     * ins_band cells; the vacuum potential uses those of degree 1.  Particles entering it are
      * absorbed as at r = b; seed-source electrons drawn inside it are not
      * created.  The band must keep 3 cells from r = a and from end plates,
      * and the load box must lie outside the ellipse (PIC_EINVAL otherwise).
@@ -121,9 +122,11 @@ typedef struct {
      * spline coefficients (the vacuum field stays the order-1 nodal field).
      * With open ends (end_mode 2) the coefficients are reflected evenly at
      * z = 0 and z = L instead, so the space-charge potential has zero
-     * z-derivative there.  Order 3 runs in both forms (the batched FP32 form
-     * gathers from an FP32 copy of the coefficients); it needs no insert and
-     * the same order for every instance of the context. */
+     * z-derivative there.  With the elliptic insert the space-charge basis
+     * is the cubic web-spline one, the field at a particle -grad(w u) =
+     * w (-grad u) - u grad w.  Order 3 runs in both forms (the batched FP32
+     * form gathers from an FP32 copy of the coefficients) and needs the same
+     * order for every instance of the context. */
     int spline_order;
     /* Energy-dependent anisotropy of elastic and ionisation scattering
      * (Sec. II.A, Okhrimovskyy's differential cross section): okh_E0_eV > 0
@@ -303,10 +306,12 @@ pic_status pic_set_cross_sections(pic_ctx* ctx, int inst, int n, const double* E
 pic_status pic_set_anisotropy(pic_ctx* ctx, int inst, int n, const double* E_eV, const double* xi);
 
 /* pic_get_band_charge -- with the elliptic insert (Sec. II.A web-splines):
- * copy the fixed-point node charges of q (w(x_p) - 1) that the particles
- * inside the weight function's band deposit next to Q (node array, units
- * 2^-S electrons; all zero without an insert).  The load of the Poisson
- * system is Q + Qw carried through the web-spline extension. */
+ * copy the fixed-point charges of q (w(x_p) - 1) that the particles inside
+ * the weight function's band deposit next to the plain charges (units 2^-S
+ * electrons; all zero without an insert): a node array ((nr+1) x (nz+1))
+ * with bilinear shapes, the ghosted cubic layout of pic_get_spline3
+ * ((nr+3) x (nz+3)) with cubic shapes.  The load of the Poisson system is
+ * the plain grid plus this one carried through the web-spline extension. */
 pic_status pic_get_band_charge(pic_ctx* ctx, int inst, long long* Qw);
 
 /* pic_get_spline3 -- with cubic shapes: copy the ghosted cubic deposit Qx
@@ -319,8 +324,10 @@ pic_status pic_get_spline3(pic_ctx* ctx, int inst, long long* Qx, double* cx);
 /* pic_insert_layout -- host-only check of an instance's elliptic insert
  * (no device work): node counts by class (counts[0] not an unknown, [1]
  * inner, [2] outer, [3] inside the metal), the m nodes whose rows differ
- * from the plain grid's, and the entries of that difference.  PIC_EINVAL
- * when the instance is invalid or has no insert. */
+ * from the plain grid's, and the entries of that difference; for the
+ * space-charge system of the instance's shapes (the cubic B-spline unknowns
+ * with spline_order 3).  PIC_EINVAL when the instance is invalid or has no
+ * insert. */
 pic_status pic_insert_layout(const pic_instance_cfg* inst, int counts[4], int* m, long long* entries);
 
 /* pic_get_phi -- copy the last solved potential (V) of instance `inst`. */

@@ -506,6 +506,12 @@ class Sim:
         return pic_get_spline3(self.ctx, k, d["nr"], d["nz"])
 
     def band_charge(self, k=0):
+        """Band charges of the insert: a node array with bilinear shapes, the
+        ghosted (nr+3, nz+3) grid of pic_get_spline3 with cubic shapes."""
+        d = self.instances[k]
+        if d.get("spline_order", 1) == 3:
+            shape = (d["nr"] + 3, d["nz"] + 3)
+            return pic_get_band_charge(self.ctx, k, shape[0] * shape[1]).reshape(shape)
         return pic_get_band_charge(self.ctx, k, self.nodes(k)).reshape(self.shapes[k])
 
     def phi(self, k=0):

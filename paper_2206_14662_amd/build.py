@@ -26,6 +26,7 @@ SOURCES = {
     "k_field.hip": [],
     "fp32.hip": [],
     "insert.hip": ["-ffp-contract=off"],
+    "insert3.hip": ["-ffp-contract=off"],
     "noalloc.hip": [],
 }
 

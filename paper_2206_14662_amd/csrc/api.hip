@@ -39,6 +39,12 @@ struct Inst {
     InsDev idev;              // device pointers of the corrected solve
     int h_owner = -1;         // an earlier instance with the same corrected system: its H is used
     long long* Qw = nullptr;
+    // cubic shapes with the insert: the web-spline system of degree 3 (the
+    // bilinear one above still gives the vacuum potential)
+    Ins3Host ih3;
+    InsDev idev3;             // its corrected solve (M, H and the buffers of insert.hip's kernels)
+    Ins3Dev xdev3;            // its load map and rebuilt coefficients
+    int h3_owner = -1;
     // cubic shapes
     long long* Qx = nullptr;
     double *cx = nullptr, *cbuf = nullptr, *zeros = nullptr;
@@ -74,6 +80,15 @@ struct pic_ctx {
     bool s3 = false;
     long long max_ext = 0;
     FieldDev* dF3 = nullptr;                    // coefficient solve: rhs, phi -> cbuf, phi_vac -> zeros
+    // cubic shapes with the insert: the corrected solve's tables (insert
+    // instances in ins_list order) and the two fast solves' field tables
+    int max_m3 = 0, max_nx3 = 0;
+    InsDev* dIns3 = nullptr;
+    Ins3Dev* dX3 = nullptr;
+    int n_grp3 = 0;
+    std::vector<int> h_goff3, h_gmem3;
+    int *dGoff3 = nullptr, *dGmem3 = nullptr;
+    FieldDev *dF3a = nullptr, *dF3b = nullptr;  // first solve (phi -> ybuf of the insert instances), second
     long long* dcnt = nullptr;
     long long* prep_ctl = nullptr;  // FP32 step plan the end-of-step kernel refreshes
     long long* dtmp = nullptr;
@@ -215,7 +230,6 @@ static std::string validate(const pic_instance_cfg& c) {
     if (c.end_mode < 0 || c.end_mode > 2) return "end_mode must be 0, 1 or 2";
     if (c.diag_interval < 0) return "diag_interval must be >= 0";
     if (c.spline_order != 0 && c.spline_order != 1 && c.spline_order != 3) return "spline_order must be 1 or 3";
-    if (c.spline_order == 3 && (c.ins_er != 0.0 || c.ins_ez != 0.0)) return "cubic shapes do not take the insert";
     if (c.ins_er != 0.0 || c.ins_ez != 0.0) {
         if (!(c.ins_er > 0.0 && c.ins_ez > 0.0 && std::isfinite(c.ins_r0) && std::isfinite(c.ins_z0)))
             return "insert: need ins_er > 0, ins_ez > 0 and a finite centre";
@@ -512,10 +526,33 @@ static pic_status upload_insert_inst(pic_ctx* ctx) {
     return PIC_OK;
 }
 
+// Groups of insert instances sharing one H: group g holds the entries
+// gmem[goff[g] .. goff[g+1]) of D.
+static void h_groups(const std::vector<InsDev>& D, std::vector<int>& goff, std::vector<int>& gmem, int& n_grp) {
+    std::vector<const double*> hs;
+    std::vector<std::vector<int>> mem;
+    for (size_t t = 0; t < D.size(); ++t) {
+        size_t g = std::find(hs.begin(), hs.end(), D[t].H) - hs.begin();
+        if (g == hs.size()) {
+            hs.push_back(D[t].H);
+            mem.emplace_back();
+        }
+        mem[g].push_back((int)t);
+    }
+    goff.assign(1, 0);
+    gmem.clear();
+    for (auto& v : mem) {
+        gmem.insert(gmem.end(), v.begin(), v.end());
+        goff.push_back((int)gmem.size());
+    }
+    n_grp = (int)mem.size();
+}
+
 static pic_status upload_tables(pic_ctx* ctx) {
     std::vector<DevInst> I;
-    std::vector<FieldDev> F, Fv, F1, F1v, F2, F2v, F3;
-    std::vector<InsDev> D;
+    std::vector<FieldDev> F, Fv, F1, F1v, F2, F2v, F3, F3a, F3b;
+    std::vector<InsDev> D, D3;
+    std::vector<Ins3Dev> X3;
     std::vector<double> bs;
     for (auto& in : ctx->in) {
         in.I.frozen = in.frozen ? 1 : 0;
@@ -559,6 +596,19 @@ static pic_status upload_tables(pic_ctx* ctx) {
             f3.phi_vac = in.zeros;
             f3.s3_L1 = in.s3_L1; f3.s3_L2 = in.s3_L2; f3.s3_L3 = in.s3_L3; f3.s3_Dinv = in.s3_Dinv;
             F3.push_back(f3);
+            // with the insert: the first solve into ybuf, the second (the
+            // correction's load on top of ybuf) into the coefficient buffer
+            FieldDev f3a = f3;
+            if (in.has_ins) {
+                f3a.phi = in.idev3.ybuf;
+                FieldDev f3b = f3;
+                f3b.rhs = in.idev3.rhs2;
+                f3b.phi_vac = in.idev3.ybuf;
+                F3b.push_back(f3b);
+                D3.push_back(in.idev3);
+                X3.push_back(in.xdev3);
+            }
+            F3a.push_back(f3a);
         }
     }
     hipStream_t s = ctx->stream;
@@ -574,27 +624,22 @@ static pic_status upload_tables(pic_ctx* ctx) {
         CK(hipMemcpyAsync(ctx->dF2v, F2v.data(), sizeof(FieldDev) * F2v.size(), hipMemcpyHostToDevice, s));
         CK(hipMemcpyAsync(ctx->dIns, D.data(), sizeof(InsDev) * D.size(), hipMemcpyHostToDevice, s));
         // groups of insert instances by their H (shared between equal corrected systems)
-        std::vector<const double*> hs;
-        std::vector<std::vector<int>> mem;
-        for (size_t t = 0; t < D.size(); ++t) {
-            size_t g = std::find(hs.begin(), hs.end(), D[t].H) - hs.begin();
-            if (g == hs.size()) {
-                hs.push_back(D[t].H);
-                mem.emplace_back();
-            }
-            mem[g].push_back((int)t);
-        }
-        ctx->h_goff.assign(1, 0);
-        ctx->h_gmem.clear();
-        for (auto& v : mem) {
-            ctx->h_gmem.insert(ctx->h_gmem.end(), v.begin(), v.end());
-            ctx->h_goff.push_back((int)ctx->h_gmem.size());
-        }
-        ctx->n_grp = (int)mem.size();
+        h_groups(D, ctx->h_goff, ctx->h_gmem, ctx->n_grp);
         CK(hipMemcpyAsync(ctx->dGoff, ctx->h_goff.data(), sizeof(int) * ctx->h_goff.size(), hipMemcpyHostToDevice,
                           s));
         CK(hipMemcpyAsync(ctx->dGmem, ctx->h_gmem.data(), sizeof(int) * ctx->h_gmem.size(), hipMemcpyHostToDevice,
                           s));
+        if (ctx->s3) {
+            CK(hipMemcpyAsync(ctx->dF3a, F3a.data(), sizeof(FieldDev) * F3a.size(), hipMemcpyHostToDevice, s));
+            CK(hipMemcpyAsync(ctx->dF3b, F3b.data(), sizeof(FieldDev) * F3b.size(), hipMemcpyHostToDevice, s));
+            CK(hipMemcpyAsync(ctx->dIns3, D3.data(), sizeof(InsDev) * D3.size(), hipMemcpyHostToDevice, s));
+            CK(hipMemcpyAsync(ctx->dX3, X3.data(), sizeof(Ins3Dev) * X3.size(), hipMemcpyHostToDevice, s));
+            h_groups(D3, ctx->h_goff3, ctx->h_gmem3, ctx->n_grp3);
+            CK(hipMemcpyAsync(ctx->dGoff3, ctx->h_goff3.data(), sizeof(int) * ctx->h_goff3.size(),
+                              hipMemcpyHostToDevice, s));
+            CK(hipMemcpyAsync(ctx->dGmem3, ctx->h_gmem3.data(), sizeof(int) * ctx->h_gmem3.size(),
+                              hipMemcpyHostToDevice, s));
+        }
         pic_status st = upload_insert_inst(ctx);
         if (st != PIC_OK) return st;
     }
@@ -627,15 +672,35 @@ static pic_status solve_tables(pic_ctx* ctx, bool vac, bool from_q, bool edges, 
     return PIC_OK;
 }
 
-// Field of every non-frozen instance from its current Q.
-pic_status pic_solve_all(pic_ctx* ctx) {
-    int n = (int)ctx->in.size();
-    hipStream_t s = ctx->stream;
-    if (ctx->s3) {  // the nodal E arrays keep the vacuum field
+// Cubic space-charge solve of every non-frozen instance from Qx (and the
+// band charges Qw of the insert instances): the plain fast solve, or for a
+// context with inserts the load of M over the folded load, the first fast
+// solve (insert instances into ybuf), the correction through H, the second
+// fast solve of the insert instances on top of ybuf, the ghosted
+// coefficients and nodal potential, rebuilt where the insert changes them.
+static pic_status solve3_tables(pic_ctx* ctx, hipStream_t s) {
+    const int n = (int)ctx->in.size(), ni = (int)ctx->ins_list.size();
+    if (ni == 0) {
         CK(launch_solve3_tab(ctx->dI, ctx->dF, ctx->dF3, n, ctx->max_nr, ctx->max_nz, ctx->max_ext, ctx->tw,
                              ctx->tw_n, ctx->dbscale, s));
         return PIC_OK;
     }
+    CK(launch_s3_fold(ctx->dI, ctx->dF3, n, ctx->max_nodes, ctx->dbscale, s));
+    CK(launch_ins3_rhs(ctx->dI, ctx->dX3, ni, ctx->max_m3, ctx->dF3, ctx->dbscale, s));
+    CK(launch_s3_rect(ctx->dI, ctx->dF3a, n, ctx->max_nr, ctx->max_nz, ctx->tw, ctx->tw_n, ctx->dbscale, s));
+    CK(launch_ins_correct(ctx->dI, ctx->dIns3, ni, ctx->dGoff3, ctx->dGmem3, ctx->n_grp3, ctx->max_m3,
+                          ctx->max_nodes, ctx->dF3, s));
+    CK(launch_s3_rect(ctx->dIins, ctx->dF3b, ni, ctx->max_nr, ctx->max_nz, ctx->tw, ctx->tw_n, ctx->dbscale, s));
+    CK(launch_s3_post(ctx->dI, ctx->dF, ctx->dF3, n, ctx->max_ext, s));
+    CK(launch_ins3_post(ctx->dI, ctx->dX3, ni, ctx->max_nx3, ctx->max_nodes, ctx->dF, ctx->dF3, s));
+    return PIC_OK;
+}
+
+// Field of every non-frozen instance from its current Q.
+pic_status pic_solve_all(pic_ctx* ctx) {
+    int n = (int)ctx->in.size();
+    hipStream_t s = ctx->stream;
+    if (ctx->s3) return solve3_tables(ctx, s);  // the nodal E arrays keep the vacuum field
     pic_status st = solve_tables(ctx, false, true, true, s);
     if (st != PIC_OK) return st;
     CK(launch_efield_tab(ctx->dI, ctx->dF, 0, n, ctx->max_nodes, true, s));
@@ -647,8 +712,8 @@ pic_status pic_field_stage(pic_ctx* ctx, hipStream_t s) {
     // per step: the electrode rows of phi and the static B half of EB keep
     // the values the initial solve (or pic_set_fields) gave them
     if (ctx->s3) {
-        CK(launch_solve3_tab(ctx->dI, ctx->dF, ctx->dF3, n, ctx->max_nr, ctx->max_nz, ctx->max_ext, ctx->tw,
-                             ctx->tw_n, ctx->dbscale, s));
+        pic_status st = solve3_tables(ctx, s);
+        if (st != PIC_OK) return st;
         CK(launch_sample_tab(ctx->dI, ctx->dF, n, ctx->dcnt, ctx->prep_ctl, s));
         return PIC_OK;
     }
@@ -748,6 +813,12 @@ static bool same_insert_system(const Inst& x, const Inst& y) {
            x.ih.Dv == y.ih.Dv;
 }
 
+// Entries of the band-charge grid Qw: one per node with bilinear shapes, the
+// ghosted (nr+3) x (nz+3) grid with cubic shapes.
+static long long band_cells(const Inst& in) {
+    return in.I.spline3 ? (long long)(in.c.nr + 3) * (in.c.nz + 3) : in.nodes;
+}
+
 // Device arrays of an instance's insert.  H is filled by setup_insert, or is
 // that of an earlier instance with the same corrected system.
 static pic_status init_insert_storage(pic_ctx* ctx, Inst& in) {
@@ -782,23 +853,23 @@ static pic_status init_insert_storage(pic_ctx* ctx, Inst& in) {
     D.yM = dalloc<double>(ctx, m);
     D.sM = dalloc<double>(ctx, m);
     D.val = dalloc<double>(ctx, m);
-    in.Qw = dalloc<long long>(ctx, N);
+    const long long nQw = band_cells(in);
+    in.Qw = dalloc<long long>(ctx, nQw);
     if (!ok || !H || !D.ybuf || !D.rhs2 || !D.yM || !D.sM || !D.val || !in.Qw)
         return fail(ctx, PIC_ENOMEM, "device allocation of the insert arrays failed");
     if (in.h_owner < 0) CK(hipMemsetAsync(H, 0, sizeof(double) * m * m, s));
     CK(hipMemsetAsync(D.ybuf, 0, sizeof(double) * N, s));
     CK(hipMemsetAsync(D.rhs2, 0, sizeof(double) * N, s));
-    CK(hipMemsetAsync(in.Qw, 0, sizeof(long long) * N, s));
+    CK(hipMemsetAsync(in.Qw, 0, sizeof(long long) * nQw, s));
     CK(hipStreamSynchronize(s));
     return PIC_OK;
 }
 
 // H = (I + D G)^-1 D with G = (A_rect^-1)_MM from m unit solves of the
-// rectangle system (batched as copies of the instance), Gauss-Jordan on the
-// device.
-static pic_status setup_insert(pic_ctx* ctx, Inst& in) {
-    const int m = in.ih.m;
-    if (m == 0 || in.h_owner >= 0) return PIC_OK;
+// rectangle system (batched as copies of the instance; the cubic one when
+// cubic), Gauss-Jordan on the device.
+static pic_status build_H(pic_ctx* ctx, Inst& in, int m, const int* Mnode, const std::vector<int>& Dr,
+                          const std::vector<int>& Dc, const std::vector<double>& Dv, double* Hout, bool cubic) {
     hipStream_t s = ctx->stream;
     const long long N = in.nodes;
     const int B = std::min(64, m);
@@ -834,6 +905,7 @@ static pic_status setup_insert(pic_ctx* ctx, Inst& in) {
         f.phi = phiT + (long long)t * N;
         f.phi_vac = zeros;
         f.th_cp = in.th_cp; f.th_im = in.th_im; f.th_lo = in.th_lo; f.th_G = in.th_G; f.th_H = in.th_H;
+        f.s3_L1 = in.s3_L1; f.s3_L2 = in.s3_L2; f.s3_L3 = in.s3_L3; f.s3_Dinv = in.s3_Dinv;
         Fv[t] = f;
     }
     hipError_t e = hipMemsetAsync(zeros, 0, sizeof(double) * N, s);
@@ -842,11 +914,12 @@ static pic_status setup_insert(pic_ctx* ctx, Inst& in) {
     if (e == hipSuccess) e = hipMemcpyAsync(Ftab, Fv.data(), sizeof(FieldDev) * B, hipMemcpyHostToDevice, s);
     for (int b0 = 0; b0 < m && e == hipSuccess; b0 += B) {
         const int cnt = std::min(B, m - b0);
-        e = launch_ins_units(rhsT, N, N, in.idev.Mnode, b0, cnt, s);
+        e = launch_ins_units(rhsT, N, N, Mnode, b0, cnt, s);
         if (e == hipSuccess)
-            e = launch_solve_tab(It, Ftab, 0, cnt, ctx->max_nr, ctx->max_nz, ctx->tw, ctx->tw_n, 1, ctx->dbscale,
-                                 false, s);
-        if (e == hipSuccess) e = launch_ins_collect(phiT, N, in.idev.Mnode, m, b0, cnt, Gd, s);
+            e = cubic ? launch_s3_rect(It, Ftab, cnt, ctx->max_nr, ctx->max_nz, ctx->tw, ctx->tw_n, ctx->dbscale, s)
+                      : launch_solve_tab(It, Ftab, 0, cnt, ctx->max_nr, ctx->max_nz, ctx->tw, ctx->tw_n, 1,
+                                         ctx->dbscale, false, s);
+        if (e == hipSuccess) e = launch_ins_collect(phiT, N, Mnode, m, b0, cnt, Gd, s);
     }
     std::vector<double> G((size_t)m * m);
     if (e == hipSuccess) e = hipMemcpyAsync(G.data(), Gd, sizeof(double) * G.size(), hipMemcpyDeviceToHost, s);
@@ -858,10 +931,9 @@ static pic_status setup_insert(pic_ctx* ctx, Inst& in) {
     // [C | D] with C = I + D G
     std::vector<double> CD((size_t)m * 2 * m, 0.0);
     for (int a = 0; a < m; ++a) CD[(size_t)a * 2 * m + a] = 1.0;
-    const InsHost& h = in.ih;
-    for (size_t t = 0; t < h.Dv.size(); ++t) {
-        const int a = h.Dr[t], c = h.Dc[t];
-        const double v = h.Dv[t];
+    for (size_t t = 0; t < Dv.size(); ++t) {
+        const int a = Dr[t], c = Dc[t];
+        const double v = Dv[t];
         double* row = &CD[(size_t)a * 2 * m];
         const double* gr = &G[(size_t)c * m];
         for (int j = 0; j < m; ++j) row[j] += v * gr[j];
@@ -872,14 +944,79 @@ static pic_status setup_insert(pic_ctx* ctx, Inst& in) {
     std::vector<double> pv(m);
     if (e == hipSuccess) e = hipMemcpyAsync(pv.data(), pval, sizeof(double) * m, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess)
-        e = hipMemcpy2DAsync((void*)in.idev.H, sizeof(double) * m, CDd + m, sizeof(double) * 2 * m,
-                             sizeof(double) * m, m, hipMemcpyDeviceToDevice, s);
+        e = hipMemcpy2DAsync((void*)Hout, sizeof(double) * m, CDd + m, sizeof(double) * 2 * m, sizeof(double) * m, m,
+                             hipMemcpyDeviceToDevice, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     release();
     if (e != hipSuccess) return fail(ctx, PIC_EDEVICE, std::string("insert set-up: ") + hipGetErrorString(e));
     for (int a = 0; a < m; ++a)
         if (!(std::fabs(pv[a]) > 0.0) || !std::isfinite(pv[a]))
             return fail(ctx, PIC_EINVAL, "insert: the corrected system is singular");
+    return PIC_OK;
+}
+
+static pic_status setup_insert(pic_ctx* ctx, Inst& in) {
+    if (in.ih.m > 0 && in.h_owner < 0) {
+        pic_status st = build_H(ctx, in, in.ih.m, in.idev.Mnode, in.ih.Dr, in.ih.Dc, in.ih.Dv,
+                                const_cast<double*>(in.idev.H), false);
+        if (st != PIC_OK) return st;
+    }
+    if (in.I.spline3 && in.ih3.m > 0 && in.h3_owner < 0)
+        return build_H(ctx, in, in.ih3.m, in.idev3.Mnode, in.ih3.Dr, in.ih3.Dc, in.ih3.Dv,
+                       const_cast<double*>(in.idev3.H), true);
+    return PIC_OK;
+}
+
+// Whether two cubic insert instances have the same corrected system.
+static bool same_insert3_system(const Inst& x, const Inst& y) {
+    const pic_instance_cfg &a = x.c, &b = y.c;
+    return a.nr == b.nr && a.nz == b.nz && a.a == b.a && a.b == b.b && a.L == b.L && a.end_mode == b.end_mode &&
+           x.ih3.m == y.ih3.m && x.ih3.Mnode == y.ih3.Mnode && x.ih3.Dr == y.ih3.Dr && x.ih3.Dc == y.ih3.Dc &&
+           x.ih3.Dv == y.ih3.Dv;
+}
+
+// Device arrays of an instance's cubic web-spline system.
+static pic_status init_insert3_storage(pic_ctx* ctx, Inst& in) {
+    const Ins3Host& h = in.ih3;
+    InsDev& D = in.idev3;
+    Ins3Dev& X = in.xdev3;
+    hipStream_t s = ctx->stream;
+    bool ok = true;
+    const long long N = in.nodes, m = std::max(1, h.m);
+    D.m = h.m;
+    D.nodes = N;
+    D.Mnode = upload_vec(ctx, h.Mnode, s, ok);
+    D.map = upload_vec(ctx, h.map, s, ok);
+    X.m = h.m;
+    X.nx = h.nx;
+    X.Mnode = D.Mnode;
+    X.typ = upload_vec(ctx, h.typ, s, ok);
+    X.rp = upload_vec(ctx, h.rp, s, ok);
+    X.rk = upload_vec(ctx, h.rk, s, ok);
+    X.rf = upload_vec(ctx, h.rf, s, ok);
+    X.xk = upload_vec(ctx, h.xk, s, ok);
+    X.xn = upload_vec(ctx, h.xn, s, ok);
+    X.xf = upload_vec(ctx, h.xf, s, ok);
+    in.h3_owner = -1;
+    for (size_t k = 0; k < ctx->in.size() && &ctx->in[k] != &in; ++k) {
+        const Inst& o = ctx->in[k];
+        if (o.has_ins && o.h3_owner < 0 && o.idev3.H && same_insert3_system(o, in)) {
+            in.h3_owner = (int)k;
+            break;
+        }
+    }
+    double* H = in.h3_owner >= 0 ? const_cast<double*>(ctx->in[in.h3_owner].idev3.H) : dalloc<double>(ctx, m * m);
+    D.H = H;
+    D.ybuf = dalloc<double>(ctx, N);
+    D.rhs2 = dalloc<double>(ctx, N);
+    D.yM = dalloc<double>(ctx, m);
+    D.sM = dalloc<double>(ctx, m);
+    if (!ok || !H || !D.ybuf || !D.rhs2 || !D.yM || !D.sM)
+        return fail(ctx, PIC_ENOMEM, "device allocation of the cubic insert arrays failed");
+    if (in.h3_owner < 0) CK(hipMemsetAsync(H, 0, sizeof(double) * m * m, s));
+    CK(hipMemsetAsync(D.ybuf, 0, sizeof(double) * N, s));
+    CK(hipMemsetAsync(D.rhs2, 0, sizeof(double) * N, s));
+    CK(hipStreamSynchronize(s));
     return PIC_OK;
 }
 
@@ -991,6 +1128,12 @@ static pic_status init_instance_storage(pic_ctx* ctx, Inst& in) {
         if (!m.empty()) return fail(ctx, PIC_EINVAL, "insert: " + m);
         pic_status st = init_insert_storage(ctx, in);
         if (st != PIC_OK) return st;
+        if (in.I.spline3) {
+            m = ins3_build(in.c, in.ih3);
+            if (!m.empty()) return fail(ctx, PIC_EINVAL, "insert: " + m);
+            st = init_insert3_storage(ctx, in);
+            if (st != PIC_OK) return st;
+        }
     }
     host_vacuum_rhs(in.c, in.has_ins ? in.c.V_outer : 0.0, a, b);
     if (in.has_ins)
@@ -1075,6 +1218,8 @@ extern "C" pic_status pic_init(const pic_run_cfg* run, const pic_instance_cfg* i
         fill_devinst(in);
         in.has_ins = in.I.has_ins != 0;
         in.idev.inst = k;
+        in.idev3.inst = k;
+        in.xdev3.inst = k;
         if (in.has_ins) ctx->ins_list.push_back(k);
         ctx->max_nr = std::max(ctx->max_nr, in.c.nr);
         ctx->max_nz = std::max(ctx->max_nz, in.c.nz);
@@ -1116,6 +1261,16 @@ extern "C" pic_status pic_init(const pic_run_cfg* run, const pic_instance_cfg* i
             ctx->dF3 = dalloc<FieldDev>(ctx, n);
             if (!ctx->dF3) st = fail(ctx, PIC_ENOMEM, "device allocation of the cubic table failed");
         }
+        if (st == PIC_OK && ctx->s3 && ni > 0) {
+            ctx->dIns3 = dalloc<InsDev>(ctx, ni);
+            ctx->dX3 = dalloc<Ins3Dev>(ctx, ni);
+            ctx->dF3a = dalloc<FieldDev>(ctx, n);
+            ctx->dF3b = dalloc<FieldDev>(ctx, ni);
+            ctx->dGoff3 = dalloc<int>(ctx, ni + 1);
+            ctx->dGmem3 = dalloc<int>(ctx, ni);
+            if (!ctx->dIns3 || !ctx->dX3 || !ctx->dF3a || !ctx->dF3b || !ctx->dGoff3 || !ctx->dGmem3)
+                st = fail(ctx, PIC_ENOMEM, "device allocation of the cubic insert tables failed");
+        }
     }
     if (st == PIC_OK) {
         std::vector<double2> tw(ctx->tw_n);  // the full circle
@@ -1129,7 +1284,11 @@ extern "C" pic_status pic_init(const pic_run_cfg* run, const pic_instance_cfg* i
         if (e != hipSuccess && st == PIC_OK) st = fail(ctx, PIC_EDEVICE, "LDS attribute failed");
     }
     for (int k = 0; k < n && st == PIC_OK; ++k) st = init_instance_storage(ctx, ctx->in[k]);
-    for (int k : ctx->ins_list) ctx->max_m = std::max(ctx->max_m, ctx->in[k].ih.m);
+    for (int k : ctx->ins_list) {
+        ctx->max_m = std::max(ctx->max_m, ctx->in[k].ih.m);
+        ctx->max_m3 = std::max(ctx->max_m3, ctx->in[k].ih3.m);
+        ctx->max_nx3 = std::max(ctx->max_nx3, ctx->in[k].ih3.nx);
+    }
     if (st == PIC_OK && ctx->mode == PIC_MODE_FP32_BATCHED) st = f32_init(ctx);
     if (st == PIC_OK) {
         std::vector<long long> cnt((size_t)n * C_NCOUNT, 0);
@@ -1196,7 +1355,7 @@ static pic_status deposit_and_solve(pic_ctx* ctx, int k_only) {
         if (k_only >= 0 && k != k_only) continue;
         Inst& in = ctx->in[k];
         CK(launch_zero_i64(in.Q, in.nodes, s));
-        if (in.Qw) CK(launch_zero_i64(in.Qw, in.nodes, s));
+        if (in.Qw) CK(launch_zero_i64(in.Qw, band_cells(in), s));
         if (in.Qx) CK(launch_zero_i64(in.Qx, (long long)(in.c.nr + 3) * (in.c.nz + 3), s));
         if (ctx->mode == PIC_MODE_FP64_PLAIN) {
             CK(launch_deposit64(in.I, in.p64[in.cur], in.Q, in.Qw, in.Qx, in.cnt, in.cap, s));
@@ -1325,7 +1484,7 @@ static pic_status step64(pic_ctx* ctx, int n_steps) {
                 Inst& in = ctx->in[k];
                 P64 p = in.p64[in.cur];
                 CK(launch_zero_i64(in.Q, in.nodes, s));
-                if (in.Qw) CK(launch_zero_i64(in.Qw, in.nodes, s));
+                if (in.Qw) CK(launch_zero_i64(in.Qw, band_cells(in), s));
                 if (in.Qx) CK(launch_zero_i64(in.Qx, (long long)(in.c.nr + 3) * (in.c.nz + 3), s));
                 hipEvent_t e0 = nullptr, e1 = nullptr;
                 if (ctx->timing) {
@@ -1565,11 +1724,12 @@ extern "C" pic_status pic_get_band_charge(pic_ctx* ctx, int k, long long* Qw) {
     if (st != PIC_OK) return st;
     if (!Qw) return fail(ctx, PIC_EINVAL, "Qw is NULL");
     CK(hipStreamSynchronize(ctx->stream));
-    if (!ctx->in[k].Qw) {
-        memset(Qw, 0, sizeof(long long) * ctx->in[k].nodes);
+    const Inst& in = ctx->in[k];
+    if (!in.Qw) {
+        memset(Qw, 0, sizeof(long long) * band_cells(in));
         return PIC_OK;
     }
-    CK(hipMemcpy(Qw, ctx->in[k].Qw, sizeof(long long) * ctx->in[k].nodes, hipMemcpyDeviceToHost));
+    CK(hipMemcpy(Qw, in.Qw, sizeof(long long) * band_cells(in), hipMemcpyDeviceToHost));
     return PIC_OK;
 }
 
@@ -1714,6 +1874,16 @@ extern "C" pic_status pic_insert_layout(const pic_instance_cfg* inst, int counts
     std::string msg = validate(*inst);
     if (!msg.empty()) return fail(nullptr, PIC_EINVAL, msg);
     if (!(inst->ins_er > 0.0 && inst->ins_ez > 0.0)) return fail(nullptr, PIC_EINVAL, "no insert");
+    if (inst->spline_order == 3) {
+        Ins3Host h3;
+        msg = ins3_build(*inst, h3);
+        if (!msg.empty()) return fail(nullptr, PIC_EINVAL, "insert: " + msg);
+        if (counts)
+            for (int t = 0; t < 4; ++t) counts[t] = h3.counts[t];
+        if (m) *m = h3.m;
+        if (entries) *entries = (long long)h3.Dv.size();
+        return PIC_OK;
+    }
     InsHost h;
     msg = ins_build(*inst, h);
     if (!msg.empty()) return fail(nullptr, PIC_EINVAL, "insert: " + msg);

@@ -395,11 +395,15 @@ __device__ __forceinline__ void node_charges(float w, float two_S, float fr, flo
 
 // Elliptic insert in FP32: g <= 0 in the metal; in the weight function's
 // band (0 < g < gam) a particle adds its charge times (w(x_p) - 1) to Qw,
-// rint(W (w - 1)) split over the four nodes by the same exact-sum rule.
+// rint(W (w - 1)) split over the four nodes by the same exact-sum rule (over
+// the sixteen nodes of the ghosted grid with cubic shapes).
 __device__ __forceinline__ float ins_g_f(const DevInst& I, float r, float z) {
     const float u = (r - I.ins_r0_f) * I.ins_inv_er_f, v = (z - I.ins_z0_f) * I.ins_inv_ez_f;
     return fmaf(u, u, v * v) - 1.0f;
 }
+
+__device__ __forceinline__ void bspline3_f(float f, float w[4], float dw[4]);
+__device__ __forceinline__ void band_cubic_gbl(long long* Qx, int WX, int i, int j, float Wt, float fr, float fz);
 
 __device__ __forceinline__ void deposit_qw(const DevInst& I, long long* Qw, float w, float r, float z) {
     const float g = ins_g_f(I, r, z);
@@ -411,6 +415,10 @@ __device__ __forceinline__ void deposit_qw(const DevInst& I, long long* Qw, floa
     int i, j;
     float fr, fz;
     cell_of(I, r, z, i, j, fr, fz);
+    if (I.spline3) {
+        band_cubic_gbl(Qw, I.nz + 3, i, j, Wt, fr, fz);
+        return;
+    }
     const float gr = 1.0f - fr, gz = 1.0f - fz;
     const long long a = (long long)rintf(Wt * (gr * gz));
     const long long b = (long long)rintf(Wt * (fr * gz));
@@ -507,6 +515,26 @@ __device__ __forceinline__ void deposit_cubic_gbl(long long* Qx, int WX, int i, 
     });
 }
 
+// The band charge Wt = rint(W (w - 1)) (negative) of a particle whose cell
+// is (i, j) with offsets (fr, fz) into the ghosted grid: rint(Wt w_a w_b) for
+// fifteen nodes, the remainder for the last.
+__device__ __forceinline__ void band_cubic_gbl(long long* Qx, int WX, int i, int j, float Wt, float fr, float fz) {
+    float wr[4], dwr[4], wz[4], dwz[4];
+    bspline3_f(fr, wr, dwr);
+    bspline3_f(fz, wz, dwz);
+    gbl_u64* Q = as_gbl(Qx);
+    const long long total = (long long)Wt;
+    long long sum = 0;
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const long long q = (a == 3 && b == 3) ? total - sum : (long long)rintf(Wt * (wr[a] * wz[b]));
+            sum += q;
+            gbl_add(&Q[(long long)(i + a) * WX + (j + b)], (unsigned long long)q);
+        }
+}
+
 // Everything the particle loop needs about the current chunk.
 struct ChunkCtx {
     LocalInst L;
@@ -588,7 +616,7 @@ __device__ __forceinline__ void push_particle(const KArgs& A, const ChunkCtx& X,
         float wr[4], dwr[4], wz[4], dwz[4];
         bspline3_f(fr, wr, dwr);
         bspline3_f(fz, wz, dwz);
-        float gr3 = 0.0f, gz3 = 0.0f;
+        float gr3 = 0.0f, gz3 = 0.0f, u3 = 0.0f;
 #pragma unroll
         for (int a = 0; a < 4; ++a) {
             float c[4];
@@ -606,9 +634,29 @@ __device__ __forceinline__ void push_particle(const KArgs& A, const ChunkCtx& X,
             const float dz = fmaf(c[3], dwz[3], fmaf(c[2], dwz[2], fmaf(c[1], dwz[1], c[0] * dwz[0])));
             gr3 = fmaf(dwr[a], sz, gr3);
             gz3 = fmaf(wr[a], dz, gz3);
+            if (INS) u3 = fmaf(wr[a], sz, u3);
         }
-        er = fmaf(-gr3, L.inv_dr, er);
-        ez = fmaf(-gz3, L.inv_dz, ez);
+        if (INS && L.has_ins) {
+            // web-splines: phi_sc = w u, so E = w (-grad u) - u grad w, with
+            // w = 1 - (1 - g/gam)^3 and its gradient inside the band
+            float e3r = -gr3 * L.inv_dr, e3z = -gz3 * L.inv_dz;
+            const float gu = (r - L.ins_r0) * L.ins_inv_er, gv = (z - L.ins_z0) * L.ins_inv_ez;
+            const float g = fmaf(gu, gu, gv * gv) - 1.0f;
+            if (g < L.ins_gam) {
+                const float s = 1.0f - g / L.ins_gam;
+                const bool in = g > 0.0f;
+                const float wv = in ? 1.0f - s * s * s : 0.0f;
+                const float d = in ? 3.0f * s * s / L.ins_gam : 0.0f;
+                const float gwr = d * (2.0f * gu * L.ins_inv_er), gwz = d * (2.0f * gv * L.ins_inv_ez);
+                e3r = fmaf(wv, e3r, -u3 * gwr);
+                e3z = fmaf(wv, e3z, -u3 * gwz);
+            }
+            er += e3r;
+            ez += e3z;
+        } else {
+            er = fmaf(-gr3, L.inv_dr, er);
+            ez = fmaf(-gz3, L.inv_dz, ez);
+        }
     }
     const float br = fmaf(w11, f11.z, fmaf(w01, f01.z, fmaf(w10, f10.z, w00 * f00.z)));
     const float bz = fmaf(w11, f11.w, fmaf(w01, f01.w, fmaf(w10, f10.w, w00 * f00.w)));
@@ -1188,7 +1236,7 @@ __global__ void k_prep(long long* ctl, const long long* cnt, int n_inst) {
 __global__ void k_zero_q(const DevInst* It, const FieldDev* Ft) {
     const DevInst& I = It[blockIdx.y];
     long long* Q = Ft[blockIdx.y].Q;
-    long long* Qw = Ft[blockIdx.y].Qw;
+    long long* Qw = I.spline3 ? nullptr : Ft[blockIdx.y].Qw;  // node array with bilinear shapes
     // pairs of nodes as 16-byte stores (the arrays are 256-byte aligned), then an odd last node
     const int pairs = I.nodes / 2;
     const longlong2 z2 = make_longlong2(0, 0);
@@ -1200,10 +1248,14 @@ __global__ void k_zero_q(const DevInst* It, const FieldDev* Ft) {
         Q[I.nodes - 1] = 0;
         if (Qw) Qw[I.nodes - 1] = 0;
     }
-    if (I.spline3) {  // the ghosted cubic grid
+    if (I.spline3) {  // the ghosted cubic grids
         long long* Qx = Ft[blockIdx.y].Qx;
+        long long* Qxw = Ft[blockIdx.y].Qw;
         const int ext = (I.nr + 3) * (I.nz + 3);
-        for (int n = blockIdx.x * blockDim.x + threadIdx.x; n < ext; n += gridDim.x * blockDim.x) Qx[n] = 0;
+        for (int n = blockIdx.x * blockDim.x + threadIdx.x; n < ext; n += gridDim.x * blockDim.x) {
+            Qx[n] = 0;
+            if (Qxw) Qxw[n] = 0;
+        }
     }
 }
 
@@ -1442,8 +1494,7 @@ __global__ void k_deposit32(DevInst I, PSet P, long long* Q, long long* Qw, long
 }
 
 typedef void (*ParticleKernel)(KArgs);
-// Variant v = step kind (bits 0-1) | insert (4) | cubic shapes (8); the
-// cubic shapes are not combined with the insert.
+// Variant v = step kind (bits 0-1) | insert (4) | cubic shapes (8).
 ParticleKernel particle_kernel(int v) {
     switch (v) {
         case 0: return k_particles<0>;
@@ -1457,7 +1508,11 @@ ParticleKernel particle_kernel(int v) {
         case 8: return k_particles3<0>;
         case 9: return k_particles3<1>;
         case 10: return k_particles3<2>;
-        default: return k_particles3<3>;
+        case 11: return k_particles3<3>;
+        case 12: return k_particles3<4>;
+        case 13: return k_particles3<5>;
+        case 14: return k_particles3<6>;
+        default: return k_particles3<7>;
     }
 }
 
@@ -1636,8 +1691,8 @@ static pic_status build_tiles(pic_ctx* ctx, F32State* S) {
     const size_t lds = particle_lds(S->win_max, S->win3_max);
     // every workgroup of the statically balanced grid must be resident at once
     int omin = 1 << 30;
-    for (int v = S->cub ? 8 : 0; v < (S->cub ? 12 : 8); ++v) {
-        const void* f = (const void*)particle_kernel(v);
+    for (int q = 0; q < 4; ++q) {  // the context's variants
+        const void* f = (const void*)particle_kernel(q | (S->ins ? 4 : 0) | (S->cub ? 8 : 0));
         CK32(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
         int occ = 0;
         (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, f, kPWG, lds);

@@ -650,26 +650,44 @@ __global__ void k3_post(const DevInst* __restrict__ It, const FieldDev* __restri
 
 }  // namespace
 
-hipError_t launch_solve3_tab(const DevInst* It, const FieldDev* Ft, const FieldDev* F3, int n_inst, int max_nr,
-                             int max_nz, long long max_ext, const double2* tw, int tw_n, const double* bscale,
-                             hipStream_t s) {
+hipError_t launch_s3_fold(const DevInst* It, const FieldDev* F3, int n_inst, long long max_nodes,
+                          const double* bscale, hipStream_t s) {
     if (n_inst <= 0) return hipSuccess;
-    const long long max_nodes = (long long)(max_nr + 1) * (max_nz + 1);
     hipLaunchKernelGGL(k3_fold, dim3((unsigned)((max_nodes + 255) / 256), n_inst), dim3(256), 0, s, It, F3, bscale);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    return hipGetLastError();
+}
+
+hipError_t launch_s3_rect(const DevInst* It, const FieldDev* F3, int n_inst, int max_nr, int max_nz,
+                          const double2* tw, int tw_n, const double* bscale, hipStream_t s) {
+    if (n_inst <= 0) return hipSuccess;
     size_t lds = fft_lds_bytes(max_nz);
     dim3 gdst((unsigned)(max_nr / 2), (unsigned)n_inst);
     const dim3 fb((unsigned)fft_block(max_nz));
     hipLaunchKernelGGL(kf_dst, gdst, fb, lds, s, It, F3, 0, tw, tw_n, 1, bscale);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
     // modes 0 .. nz (open ends) or 1 .. nz-1: nz + 1 lanes
     hipLaunchKernelGGL(k3_band, dim3((unsigned)((max_nz + 1 + 63) / 64), n_inst), dim3(64), 0, s, It, F3);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(kf_dst, gdst, fb, lds, s, It, F3, 0, tw, tw_n, 2, bscale);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+    return hipGetLastError();
+}
+
+hipError_t launch_s3_post(const DevInst* It, const FieldDev* Ft, const FieldDev* F3, int n_inst, long long max_ext,
+                          hipStream_t s) {
+    if (n_inst <= 0) return hipSuccess;
     hipLaunchKernelGGL(k3_post, dim3((unsigned)((max_ext + 255) / 256), n_inst), dim3(256), 0, s, It, Ft, F3);
     return hipGetLastError();
+}
+
+hipError_t launch_solve3_tab(const DevInst* It, const FieldDev* Ft, const FieldDev* F3, int n_inst, int max_nr,
+                             int max_nz, long long max_ext, const double2* tw, int tw_n, const double* bscale,
+                             hipStream_t s) {
+    const long long max_nodes = (long long)(max_nr + 1) * (max_nz + 1);
+    hipError_t e = launch_s3_fold(It, F3, n_inst, max_nodes, bscale, s);
+    if (e == hipSuccess) e = launch_s3_rect(It, F3, n_inst, max_nr, max_nz, tw, tw_n, bscale, s);
+    if (e == hipSuccess) e = launch_s3_post(It, Ft, F3, n_inst, max_ext, s);
+    return e;
 }
 
 hipError_t launch_zero_i64(long long* p, long long n, hipStream_t s) {

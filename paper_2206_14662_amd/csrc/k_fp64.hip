@@ -50,7 +50,9 @@ __device__ __forceinline__ void base3(double s, int n, int& i0, double& f) {
 }
 
 // Space-charge field -grad phi_sc at (r, z) from the ghosted cubic
-// coefficients (nodes i0-1 .. i0+2 at ghosted rows i0 .. i0+3).
+// coefficients (nodes i0-1 .. i0+2 at ghosted rows i0 .. i0+3).  With the
+// insert phi_sc = w u (web-splines, u the cubic expansion), so inside the
+// weight band E = w (-grad u) - u grad w.
 __device__ __forceinline__ void field3(const DevInst& I, const double* cx, double r, double z, double& er,
                                        double& ez) {
     int i0, j0;
@@ -60,15 +62,30 @@ __device__ __forceinline__ void field3(const DevInst& I, const double* cx, doubl
     bspline3(fr, wr, dwr);
     bspline3(fz, wz, dwz);
     const int WX = I.nz + 3;
-    double gr = 0.0, gz = 0.0;
+    double gr = 0.0, gz = 0.0, u = 0.0;
     for (int a = 0; a < 4; ++a)
         for (int b = 0; b < 4; ++b) {
             const double v = cx[(long long)(i0 + a) * WX + (j0 + b)];
             gr += v * (dwr[a] * wz[b]);
             gz += v * (wr[a] * dwz[b]);
+            u += v * (wr[a] * wz[b]);
         }
     er = -(gr / I.dr);
     ez = -(gz / I.dz);
+    if (I.has_ins) {
+        const double g = ins_g(I, r, z);
+        if (g < I.ins_gam) {
+            const double w = ins_w(I, g);
+            double gwr = 0.0, gwz = 0.0;
+            if (g > 0.0) {
+                const double s = 1.0 - g / I.ins_gam, d = 3.0 * s * s / I.ins_gam;
+                gwr = d * (2.0 * (r - I.ins_r0) / (I.ins_er * I.ins_er));
+                gwz = d * (2.0 * (z - I.ins_z0) / (I.ins_ez * I.ins_ez));
+            }
+            er = w * er - u * gwr;
+            ez = w * ez - u * gwz;
+        }
+    }
 }
 
 __device__ __forceinline__ double gather64(const Shape& sh, const double* F, int W) {
@@ -343,7 +360,8 @@ __global__ void __launch_bounds__(kBlock) k_moments64(DevInst I, P64 p, const lo
 // Fixed-point deposit: node charges rint(W w_k) for three nodes, the fourth
 // takes the remainder so every particle adds exactly W.  With the insert, a
 // particle in the weight function's band also deposits rint(W (w(x_p) - 1))
-// into Qw by the same rule.
+// into Qw by the same rule (by the 16-node rule into the ghosted Qw with
+// cubic shapes).
 __device__ __forceinline__ void deposit4(long long* Q, const Shape& sh, int W, long long Wq) {
     const double Wd = (double)Wq;
     const long long q00 = (long long)rint(Wd * sh.w00);
@@ -392,8 +410,13 @@ __global__ void __launch_bounds__(kBlock) k_deposit64(DevInst I, P64 p, long lon
         if (wq > 2147483648.0) atomicMax((unsigned long long*)&cnt[C_OVERFLOW], 1ull);
         deposit4(Q, sh, I.W, Wq);
         if (Qw) {
+            // the band charge, on the particle's own shape grid
             const double g = ins_g(I, r, p.z[q]);
-            if (g < I.ins_gam) deposit4(Qw, sh, I.W, (long long)rint((double)Wq * (ins_w(I, g) - 1.0)));
+            if (g < I.ins_gam) {
+                const long long Wb = (long long)rint((double)Wq * (ins_w(I, g) - 1.0));
+                if (Qx) deposit16(I, Qw, r, p.z[q], Wb);
+                else deposit4(Qw, sh, I.W, Wb);
+            }
         }
         if (Qx) deposit16(I, Qx, r, p.z[q], Wq);
     }

@@ -316,7 +316,8 @@ struct FieldDev {
     float4* EB;            // FP32 form output (or null)
     const double* V;       // node volumes
     double* avg_acc;       // time-average accumulator
-    long long* Qw;         // insert: node charges of q (w(x_p) - 1) of the particles in the weight band
+    long long* Qw;         // insert: charges of q (w(x_p) - 1) of the particles in the weight band, a node
+                           // array with bilinear shapes, ghosted like Qx with cubic shapes
     // cubic shapes: ghosted deposit and coefficients ((nr+3) x (nz+3)), the
     // per-mode LDL^T factors of the 7-band r systems ([i][k], row length W)
     long long* Qx;
@@ -367,6 +368,32 @@ struct InsDev {
     double* val;           // [m]
 };
 
+// Cubic shapes with the insert (insert3.hip): the load of the unknowns of M
+// and the ghosted coefficients rebuilt after the corrected solve.
+struct Ins3Dev {
+    int inst;              // instance in the main tables
+    int m;                 // unknowns in M
+    int nx;                // ghosted coefficients rebuilt after a solve
+    const int* Mnode;      // [m] node of each unknown of M
+    const int* typ;        // [m] 1: inner (takes its load), 0: load 0
+    const int* rp;         // [m+1] load of M entry a: sum_t rf[t] (Qx + Qw)[rk[t]] (ghosted)
+    const int* rk;
+    const double* rf;
+    const int* xk;         // [nx] ghosted index of a rebuilt coefficient
+    const int* xn;         // [16 nx] nodes of the block's coefficients (-1: none)
+    const double* xf;      // [16 nx] their factors (reflection sign times extension weight)
+};
+
+// Host set-up of one instance's cubic web-spline system (insert3.hip).
+struct Ins3Host {
+    int m = 0, nx = 0;
+    std::vector<int> Mnode, map, typ, rp, rk, xk, xn;
+    std::vector<double> rf, xf;
+    std::vector<int> Dr, Dc;          // correction matrix D (entries by M index)
+    std::vector<double> Dv;
+    int counts[4] = {0, 0, 0, 0};     // nodes: not an unknown, inner, outer, exterior
+};
+
 // Host set-up of one instance's insert (independent of the device).
 struct InsHost {
     int m = 0;
@@ -406,6 +433,24 @@ void ins_fill(const pic_instance_cfg& c, double dr, double dz, DevInst& I);
 hipError_t launch_solve3_tab(const DevInst* It, const FieldDev* Ft, const FieldDev* F3, int n_inst, int max_nr,
                              int max_nz, long long max_ext, const double2* tw, int tw_n, const double* bscale,
                              hipStream_t s);
+// ... and its three parts: the folded load into the table's rhs; the
+// rectangle solve of rhs (phi = phi_vac + A_rect^-1 rhs); the ghosted
+// coefficients and the nodal potential.
+hipError_t launch_s3_fold(const DevInst* It, const FieldDev* F3, int n_inst, long long max_nodes,
+                          const double* bscale, hipStream_t s);
+hipError_t launch_s3_rect(const DevInst* It, const FieldDev* F3, int n_inst, int max_nr, int max_nz,
+                          const double2* tw, int tw_n, const double* bscale, hipStream_t s);
+hipError_t launch_s3_post(const DevInst* It, const FieldDev* Ft, const FieldDev* F3, int n_inst, long long max_ext,
+                          hipStream_t s);
+// Cubic web-splines with the insert (insert3.hip): host set-up (an empty
+// string means success), the load of M over the plain folded load, and after
+// the corrected solve the rebuilt ghosted coefficients and the nodal
+// potential phi_vac + w (coefficient sum).
+std::string ins3_build(const pic_instance_cfg& c, Ins3Host& h);
+hipError_t launch_ins3_rhs(const DevInst* It, const Ins3Dev* X, int n_ins, int max_m, const FieldDev* Ft,
+                           const double* bscale, hipStream_t s);
+hipError_t launch_ins3_post(const DevInst* It, const Ins3Dev* X, int n_ins, int max_nx, long long max_nodes,
+                            const FieldDev* Ft, const FieldDev* F3, hipStream_t s);
 // per step (or for the vacuum): the load of every insert instance's nodes
 // from Q and Qw (scaled by bscale) into rhs
 hipError_t launch_ins_rhs(const DevInst* It, const InsDev* D, int n_ins, long long max_nodes, const FieldDev* Ft,
