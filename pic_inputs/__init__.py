@@ -151,12 +151,13 @@ def synthetic_xs(cfg, n=200, E_max=1.0e5):
     """A synthetic cross-section table in LXCat layout (the paper's Ne data
     are not available): n log-spaced energies 1e-2 .. E_max eV, an elastic
     momentum-transfer cross section falling from ~2e-19 m^2 at low energy to
-    ~2e-21 m^2 at 10 keV, and the Lotz ionisation formula of the
-    configuration sampled at the same energies (zero below threshold)."""
+    ~2e-21 m^2 at 10 keV, and an ionisation cross section that is zero up to
+    the configuration's threshold, peaks at 1e-20 m^2 at 100 eV above it and
+    falls as 1/E beyond (a plain rational curve, not a physics model)."""
     E = np.geomspace(1.0e-2, E_max, n)
     el = 2.0e-19 / (1.0 + E / 50.0) ** 0.75 + 2.0e-22
-    I = cfg["iz_I_eV"]
-    iz = np.where(E > I, cfg["lotz_a"] * cfg["lotz_q"] * np.log(np.maximum(E, I) / I) / (E * I), 0.0)
+    t = np.maximum(E - cfg["iz_I_eV"], 0.0) / 100.0
+    iz = 4.0e-20 * t / (1.0 + t) ** 2
     return E, el, iz
 
 
