@@ -31,7 +31,7 @@ def kernel_source_hash():
 
 
 def short_name(name):
-    m = re.search(r"(k[a-z0-9]*_[A-Za-z0-9_]+(?:<[0-9, ]+>)?)\(", name)
+    m = re.search(r"([A-Za-z_][A-Za-z0-9_]*(?:<[0-9, ]+>)?)\(", name)
     if m:
         return m.group(1)
     return name.split("(")[0][:48]
