@@ -44,7 +44,7 @@ def trap(p_mbar, nr=128, nz=256, n0=1.0e15, weight=2.0e4, src_per_step=2.0, E_re
     return c, tau_d
 
 
-def force_balance(g, k, cfg, samples=64, gap=16):
+def force_balance(g, k, cfg, samples=64, gap=16, omit=()):
     """Sec. IV force terms of the electron fluid from the moments, averaged
     over `samples` snapshots `gap` steps apart (several cyclotron periods),
     in the cloud (n > 0.2 n_max).  With T = m_e sum w v v / V the full second
@@ -53,7 +53,9 @@ def force_balance(g, k, cfg, samples=64, gap=16):
         theta: -(dT_rt/dr + 2 T_rt/r + dT_tz/dz) + q (G_z B_r - G_r B_z) - m D_t = 0
     with G = n u and D = (sum w nu_m / V) u the collisional drag.  Returns the
     median over cloud nodes of |sum| / (sum of |terms|) for both equations,
-    and the median of the azimuthal drag-to-Lorentz ratio m D_t / (q G_r B_z)."""
+    and the median of the azimuthal drag-to-Lorentz ratio m D_t / (q G_r B_z).
+    `omit` leaves named terms out of both sums ("stress", "curvature",
+    "electric", "magnetic", "drag"), to show what each one carries."""
     import numpy as np
     acc = None
     for _ in range(samples):
@@ -71,8 +73,12 @@ def force_balance(g, k, cfg, samples=64, gap=16):
     safe = np.where(n > 0, n, 1.0)
     Dr, Dt = nu * Gr / safe, nu * Gt / safe
     grad = lambda a, ax: np.gradient(a, d[ax], axis=ax)
-    radial = [-grad(Trr, 0), -(Trr - Ttt) / r, -grad(Trz, 1), q * n * f["Er"], q * Gt * f["Bz"], -ME * Dr]
-    azim = [-grad(Trt, 0), -2.0 * Trt / r, -grad(Ttz, 1), q * Gz * f["Br"], -q * Gr * f["Bz"], -ME * Dt]
+    radial = [("stress", -grad(Trr, 0)), ("curvature", -(Trr - Ttt) / r), ("stress", -grad(Trz, 1)),
+              ("electric", q * n * f["Er"]), ("magnetic", q * Gt * f["Bz"]), ("drag", -ME * Dr)]
+    azim = [("stress", -grad(Trt, 0)), ("curvature", -2.0 * Trt / r), ("stress", -grad(Ttz, 1)),
+            ("magnetic", q * Gz * f["Br"]), ("magnetic", -q * Gr * f["Bz"]), ("drag", -ME * Dt)]
+    radial = [v for name, v in radial if name not in omit]
+    azim = [v for name, v in azim if name not in omit]
     cloud = n > 0.2 * n.max()
     cloud[0, :] = cloud[-1, :] = cloud[:, 0] = cloud[:, -1] = False
 
