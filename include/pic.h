@@ -69,7 +69,8 @@ typedef struct {
 /* One simulation instance (one coaxial trap). */
 typedef struct {
     double a, b, L;            /* inner radius, outer radius, length (m); 0<a<b  */
-    int nr, nz;                /* cells in r and z; nz a power of two >= 4       */
+    int nr, nz;                /* cells in r and z; nz a multiple of 4 in [4, 4096]
+                                  with no prime factor above 5 (2 nz-point FFTs) */
     double V_inner, V_outer;   /* electrode potentials at r=a, r=b (V)           */
     double V_end;              /* end electrodes at z=0,L (V), see end_mode      */
     int end_mode;              /* 0: phi_end(r) = phi_coax(r) + V_end; 1: V_end;
@@ -197,7 +198,8 @@ typedef struct {
  * Maxwellian electrons per instance from the instance's Philox stream
  * (Sec. III.A initial homogeneous Maxwellian cloud), deposit them and solve
  * for the first field.  run->n_instances entries of inst are read.
- * Errors: PIC_EINVAL (bad configuration; nz must be a power of two),
+ * Errors: PIC_EINVAL (bad configuration; nz must be a multiple of 4 with no
+ * prime factor above 5),
  * PIC_ENOMEM, PIC_EDEVICE, PIC_EOVERFLOW (weight 2^S above 2^31 for an
  * explicit fx_shift; checked before any device call).  On error *out is
  * NULL and nothing is leaked.

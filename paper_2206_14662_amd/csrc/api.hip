@@ -7,6 +7,7 @@
 #include <cmath>
 
 #include <algorithm>
+#include <numeric>
 #include <string>
 #include <vector>
 
@@ -204,12 +205,21 @@ static unsigned long long null_threshold(double P) {
     return k;
 }
 
-static bool is_pow2(int x) { return x > 0 && (x & (x - 1)) == 0; }
+// nz for the z transforms: 2 nz points, a multiple of 8 with no prime factor
+// beyond 5
+static bool fft_size_ok(int nz) {
+    if (nz < 4 || nz % 4 != 0) return false;
+    int m = nz;
+    for (int p : {2, 3, 5})
+        while (m % p == 0) m /= p;
+    return m == 1;
+}
 
 static std::string validate(const pic_instance_cfg& c) {
     if (!(c.a > 0.0 && c.b > c.a && c.L > 0.0)) return "need 0 < a < b and L > 0";
     if (c.nr < 4 || c.nr > 16384) return "nr must be in [4, 16384]";
-    if (!is_pow2(c.nz) || c.nz < 4 || c.nz > 4096) return "nz must be a power of two in [4, 4096]";
+    if (!fft_size_ok(c.nz) || c.nz > 4096)
+        return "nz must be a multiple of 4 in [4, 4096] with no prime factor above 5";
     if (!(c.dt > 0.0)) return "dt must be > 0";
     if (!(c.T_gas_K > 0.0) || !(c.p_mbar >= 0.0)) return "need T_gas_K > 0 and p_mbar >= 0";
     if (!(c.M_gas_amu > 0.0)) return "M_gas_amu must be > 0";
@@ -1239,7 +1249,12 @@ extern "C" pic_status pic_init(const pic_run_cfg* run, const pic_instance_cfg* i
         ctx->dbscale = dalloc<double>(ctx, n);
         ctx->dcnt = dalloc<long long>(ctx, (long long)n * C_NCOUNT);
         ctx->dtmp = dalloc<long long>(ctx, 64);
-        ctx->tw_n = 2 * ctx->max_nz;
+        // one twiddle table for every instance: the full circle at a
+        // resolution that every transform length 2 nz divides
+        long long tw = 1;
+        for (const Inst& x : ctx->in) tw = std::lcm(tw, 2ll * x.c.nz);
+        if (tw > (1ll << 22)) st = fail(ctx, PIC_EINVAL, "the instances' nz values have too large a common multiple");
+        ctx->tw_n = (int)std::min(tw, 1ll << 22);
         ctx->tw = dalloc<double2>(ctx, ctx->tw_n);
         if (!ctx->dI || !ctx->dF || !ctx->dFvac || !ctx->dbscale || !ctx->dcnt || !ctx->dtmp || !ctx->tw)
             st = fail(ctx, PIC_ENOMEM, "device allocation of tables failed");

@@ -53,6 +53,34 @@ __device__ __forceinline__ void dft8(double2* v) {
     v[3] = cadd(e3, o3); v[7] = csub(e3, o3);
 }
 
+// Forward DFTs of 3 and 5 points (kernel exp(-2 pi i r m / R)): with
+// c_l = cos(2 pi l / R), s_l = sin(2 pi l / R), pairs of inputs r and R - r
+// enter as their sum (times c) and difference (times -i s).
+__device__ __forceinline__ void dft3(double2* v) {
+    const double s1 = 0.86602540378443864676;  // sin(2 pi / 3)
+    const double2 t = cadd(v[1], v[2]), d = csub(v[1], v[2]);
+    const double2 b = make_double2(v[0].x - 0.5 * t.x, v[0].y - 0.5 * t.y);
+    const double2 e = make_double2(s1 * d.y, -s1 * d.x);  // -i s1 d
+    v[0] = cadd(v[0], t);
+    v[1] = cadd(b, e);
+    v[2] = csub(b, e);
+}
+__device__ __forceinline__ void dft5(double2* v) {
+    const double c1 = 0.30901699437494742410, c2 = -0.80901699437494742410;  // cos(2 pi / 5), cos(4 pi / 5)
+    const double s1 = 0.95105651629515357212, s2 = 0.58778525229247312917;   // sin(2 pi / 5), sin(4 pi / 5)
+    const double2 t1 = cadd(v[1], v[4]), t2 = cadd(v[2], v[3]);
+    const double2 t3 = csub(v[1], v[4]), t4 = csub(v[2], v[3]);
+    const double2 b1 = make_double2(v[0].x + c1 * t1.x + c2 * t2.x, v[0].y + c1 * t1.y + c2 * t2.y);
+    const double2 b2 = make_double2(v[0].x + c2 * t1.x + c1 * t2.x, v[0].y + c2 * t1.y + c1 * t2.y);
+    const double2 d1 = make_double2(s1 * t3.x + s2 * t4.x, s1 * t3.y + s2 * t4.y);
+    const double2 d2 = make_double2(s2 * t3.x - s1 * t4.x, s2 * t3.y - s1 * t4.y);
+    v[0] = cadd(v[0], cadd(t1, t2));
+    v[1] = make_double2(b1.x + d1.y, b1.y - d1.x);  // b1 - i d1
+    v[4] = make_double2(b1.x - d1.y, b1.y + d1.x);  // b1 + i d1
+    v[2] = make_double2(b2.x + d2.y, b2.y - d2.x);
+    v[3] = make_double2(b2.x - d2.y, b2.y + d2.x);
+}
+
 // LDS slot of FFT point i: one spare slot after every 8 points, so that the
 // first pass's writes (8 consecutive points per thread, threads 128 bytes
 // apart) spread over the banks instead of falling on the same four.
@@ -60,15 +88,16 @@ __device__ __forceinline__ int lp(int i) { return i + (i >> 3); }
 inline size_t fft_lds_bytes(int max_nz) { return sizeof(double2) * (size_t)(2 * max_nz + (2 * max_nz) / 8); }
 
 // One Stockham pass of radix R over N points in LDS (in place: every
-// thread reads its 8 / R butterflies' inputs, barrier, writes).  Butterfly
-// j of span Ns reads y[j + r N/R], twiddles input r by exp(-2 pi i r k /
-// (Ns R)) with k = j mod Ns, and writes output m to y[(j/Ns) Ns R + k + m Ns].
+// thread reads its butterflies' inputs -- at most ceil(8 / R) of them, the
+// block holding at least N / 8 threads -- barrier, writes).  Butterfly j of
+// span Ns reads y[j + r N/R], twiddles input r by exp(-2 pi i r k / (Ns R))
+// with k = j mod Ns, and writes output m to y[(j/Ns) Ns R + k + m Ns].
 // tw[t] = exp(-2 pi i t / tw_n) over the full circle, tw_n a multiple of N.
 template <int R>
 __device__ __forceinline__ void fft_pass(double2* y, int N, int Ns, const double2* __restrict__ tw, int tw_n) {
-    constexpr int PER = 8 / R;
+    constexpr int PER = (8 + R - 1) / R;
     const int nb = N / R;
-    double2 v[8];
+    double2 v[PER * R];
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
         const int j = threadIdx.x + q * blockDim.x;
@@ -83,12 +112,14 @@ __device__ __forceinline__ void fft_pass(double2* y, int N, int Ns, const double
     for (int q = 0; q < PER; ++q) {
         const int j = threadIdx.x + q * blockDim.x;
         if (j < nb) {
-            const int k = j & (Ns - 1);
+            const int k = j - (j / Ns) * Ns;
             double2* w = v + q * R;
 #pragma unroll
             for (int r = 1; r < R; ++r) w[r] = cmul(w[r], tw[r * k * tscale]);
             if (R == 8) dft8(w);
+            else if (R == 5) dft5(w);
             else if (R == 4) dft4(w[0], w[1], w[2], w[3]);
+            else if (R == 3) dft3(w);
             else dft2(w);
             const int d = (j - k) * R + k;
 #pragma unroll
@@ -98,16 +129,30 @@ __device__ __forceinline__ void fft_pass(double2* y, int N, int Ns, const double
     __syncthreads();
 }
 
-// Forward FFT of N = 2^n points (N >= 2) in natural order in LDS, radix 8
-// passes then one of radix 4 or 2.
+// Forward FFT of N = 2^a 3^b 5^c points (N a multiple of 8) in natural
+// order in LDS: radix-8 passes while 8 divides what is left, then radix 4
+// or 2, then the radix-3 and radix-5 passes.
 __device__ void fft_lds(double2* y, int N, const double2* __restrict__ tw, int tw_n) {
     int Ns = 1;
-    while (N / Ns >= 8) {
+    while ((N / Ns) % 8 == 0) {
         fft_pass<8>(y, N, Ns, tw, tw_n);
         Ns *= 8;
     }
-    if (N / Ns == 4) fft_pass<4>(y, N, Ns, tw, tw_n);
-    else if (N / Ns == 2) fft_pass<2>(y, N, Ns, tw, tw_n);
+    if ((N / Ns) % 4 == 0) {
+        fft_pass<4>(y, N, Ns, tw, tw_n);
+        Ns *= 4;
+    } else if ((N / Ns) % 2 == 0) {
+        fft_pass<2>(y, N, Ns, tw, tw_n);
+        Ns *= 2;
+    }
+    while ((N / Ns) % 3 == 0) {
+        fft_pass<3>(y, N, Ns, tw, tw_n);
+        Ns *= 3;
+    }
+    while ((N / Ns) % 5 == 0) {
+        fft_pass<5>(y, N, Ns, tw, tw_n);
+        Ns *= 5;
+    }
 }
 
 // z transform of interior rows, two per block.  Dirichlet ends: sine

@@ -66,7 +66,7 @@ def test_derive_bit_equal_to_oracle(cfg):
 
 def test_init_rejects_bad_configs_without_touching_a_gpu():
     bad = [
-        dict(pi.coax64(), nz=100),          # not a power of two
+        dict(pi.coax64(), nz=28),           # a prime factor above 5
         dict(pi.coax64(), a=0.02),          # a > b
         dict(pi.coax64(), dt=0.0),
         dict(pi.coax64(), okh_xi=1.0),
