@@ -56,6 +56,7 @@ def autotune(B, torch, cfgs, cache):
     t0 = time.perf_counter()
     t = sim.autotune(trial_steps=48, cache_path=cache)
     t["tune_s"] = time.perf_counter() - t0
+    t["lanes"] = B.pic_tuning(sim.ctx)["lanes"]
     sim.close()
     torch.cuda.synchronize()
     return t
@@ -68,7 +69,7 @@ def measure(B, torch, cfgs, mode, steps, warmup, graph_region, tuning=None):
     kernel launch (plain launches) for the kernel's average duration."""
     kw = {}
     if tuning:
-        kw = {k: tuning[k] for k in ("tile_r", "tile_z", "halo", "sort_interval")}
+        kw = {k: tuning[k] for k in ("tile_r", "tile_z", "halo", "sort_interval", "lanes") if k in tuning}
     sim = B.Sim(cfgs, mode=mode, **kw)
     ctx = sim.ctx
     n = len(cfgs)
@@ -243,7 +244,7 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 2 GiB device copy three times (reference for HBM byte counters)")
     ap.add_argument("--no-tune", action="store_true", help="default tiles instead of the autotuner's choice")
-    ap.add_argument("--tiles", default=None, help="TR,TZ,HALO,K instead of the autotuner")
+    ap.add_argument("--tiles", default=None, help="TR,TZ,HALO,K[,LANES] instead of the autotuner")
     ap.add_argument("--tune-cache", default=os.path.join(os.environ.get("TMPDIR", "/tmp"), "picmcc_tune.jsonl"))
     ap.add_argument("--accuracy", default=None, choices=("coax64hot", "coax256", "coax512"),
                     help="instead of timing, report FP32-vs-FP64 errors on this workload")
@@ -316,7 +317,8 @@ def main():
     tuned = None
     if args.tiles:
         v = [int(x) for x in args.tiles.split(",")]
-        tuned = dict(zip(("tile_r", "tile_z", "halo", "sort_interval"), v), trials=0, ms_per_step=0.0, tune_s=0.0)
+        tuned = dict(zip(("tile_r", "tile_z", "halo", "sort_interval", "lanes"), v), trials=0, ms_per_step=0.0,
+                     tune_s=0.0)
     elif not args.no_tune:
         tuned = autotune(B, torch, cfgs, args.tune_cache)
         print(f"# autotune: {tuned}", file=sys.stderr, flush=True)

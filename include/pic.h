@@ -152,6 +152,12 @@ typedef struct {
     pic_allocator alloc;       /* alloc == NULL: hipMalloc/hipFree               */
     double capacity_factor;    /* particle slots = factor * n_init; 0 = 2.0      */
     long long capacity_min;    /* lower bound on slots per instance; 0 = 4096    */
+    /* FP32 form: particles per lane and pass of the bilinear particle kernel.
+     * 0 or 1: one, at 64 registers, two workgroups per CU; 2: two, whose
+     * loads are in flight together, at up to 128 registers, one workgroup per
+     * CU.  Results are bit-identical either way; pic_autotune times both and
+     * keeps the faster.  Cubic shapes always take one. */
+    int lanes;
 } pic_run_cfg;
 
 /* Per-instance diagnostics (Sec. III.A: peak density and boundary currents). */
@@ -360,9 +366,11 @@ int pic_auto_shift(double w_max);
  */
 pic_status pic_timing(pic_ctx* ctx, int enable, long long* launches, double* total_ms);
 
-/* pic_tuning -- the tile shape, halo, sort interval and chunk in use. */
+/* pic_tuning -- the tile shape, halo, sort interval, chunk and particles per
+ * lane and pass (1 or 2, see pic_run_cfg.lanes) in use; any pointer may be
+ * NULL; zeros in the FP64 form. */
 pic_status pic_tuning(pic_ctx* ctx, int* tile_r, int* tile_z, int* halo, int* sort_interval,
-                      int* chunk);
+                      int* chunk, int* lanes);
 
 /*
  * pic_retune -- FP32 form only: switch to tile_r x tile_z cell tiles, a
@@ -377,7 +385,8 @@ pic_status pic_retune(pic_ctx* ctx, int tile_r, int tile_z, int halo, int sort_i
 
 /*
  * pic_autotune -- FP32 form only: time the context's own workload under
- * candidate tile shapes, halos and sort intervals (about 20 trials of
+ * candidate tile shapes, halos and sort intervals, for one and for two
+ * particles per lane and pass (pic_run_cfg.lanes; about 20 trials each of
  * max(trial_steps, 2 sort intervals) steps each, after two intervals of
  * warm-up) and keep the fastest.  The trial steps advance the simulation
  * like any other steps.  cache_path (or NULL) names a text file of one JSON

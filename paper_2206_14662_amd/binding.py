@@ -61,7 +61,7 @@ class pic_run_cfg(C.Structure):
         ("mode", C.c_int), ("n_instances", C.c_int), ("tile_r", C.c_int), ("tile_z", C.c_int),
         ("halo", C.c_int), ("sort_interval", C.c_int), ("chunk", C.c_int), ("use_graph", C.c_int),
         ("device", C.c_int), ("stream", C.c_void_p), ("alloc", pic_allocator),
-        ("capacity_factor", C.c_double), ("capacity_min", C.c_longlong),
+        ("capacity_factor", C.c_double), ("capacity_min", C.c_longlong), ("lanes", C.c_int),
     ]
 
 
@@ -136,7 +136,7 @@ def lib():
     L.pic_auto_shift.argtypes = [C.c_double]
     L.pic_auto_shift.restype = C.c_int
     L.pic_timing.argtypes = [vp, C.c_int, _LL, _D]
-    L.pic_tuning.argtypes = [vp, _I, _I, _I, _I, _I]
+    L.pic_tuning.argtypes = [vp, _I, _I, _I, _I, _I, _I]
     L.pic_retune.argtypes = [vp, C.c_int, C.c_int, C.c_int, C.c_int]
     L.pic_autotune.argtypes = [vp, C.c_int, C.c_char_p, _I, _I, _I, _I, _D, _I]
     L.pic_reserve.argtypes = [vp, C.c_int, C.c_longlong]
@@ -232,7 +232,7 @@ class _TorchAllocator:
 
 def pic_init(instances, mode=PIC_MODE_FP64_PLAIN, device=0, stream=None, use_torch=True,
              tile_r=0, tile_z=0, halo=0, sort_interval=0, chunk=0, use_graph=1,
-             capacity_factor=0.0, capacity_min=0):
+             capacity_factor=0.0, capacity_min=0, lanes=0):
     """Create a context for a list of instance dicts.  Returns (ctx, keep)
     where keep holds the callbacks that must outlive the context."""
     n = len(instances)
@@ -243,6 +243,7 @@ def pic_init(instances, mode=PIC_MODE_FP64_PLAIN, device=0, stream=None, use_tor
     run.sort_interval, run.chunk, run.use_graph = sort_interval, chunk, use_graph
     run.device = device
     run.capacity_factor, run.capacity_min = float(capacity_factor), int(capacity_min)
+    run.lanes = int(lanes)
     keep = []
     if use_torch:
         import torch
@@ -392,9 +393,9 @@ def pic_timing(ctx, enable):
 
 
 def pic_tuning(ctx):
-    v = [C.c_int() for _ in range(5)]
+    v = [C.c_int() for _ in range(6)]
     _check(lib().pic_tuning(ctx, *[C.byref(x) for x in v]), ctx)
-    return dict(zip(("tile_r", "tile_z", "halo", "sort_interval", "chunk"), [x.value for x in v]))
+    return dict(zip(("tile_r", "tile_z", "halo", "sort_interval", "chunk", "lanes"), [x.value for x in v]))
 
 
 def pic_retune(ctx, tile_r=0, tile_z=0, halo=-1, sort_interval=0):

@@ -1183,6 +1183,7 @@ extern "C" pic_status pic_init(const pic_run_cfg* run, const pic_instance_cfg* i
         return fail(nullptr, PIC_EINVAL, "unknown mode");
     if (run->capacity_factor < 0.0 || (run->capacity_factor > 0.0 && run->capacity_factor < 1.0))
         return fail(nullptr, PIC_EINVAL, "capacity_factor must be 0 or >= 1");
+    if (run->lanes < 0 || run->lanes > 2) return fail(nullptr, PIC_EINVAL, "lanes must be 0, 1 or 2");
     for (int k = 0; k < run->n_instances; ++k) {
         std::string m = validate(inst[k]);
         if (!m.empty()) return fail(nullptr, PIC_EINVAL, "instance " + std::to_string(k) + ": " + m);
@@ -1997,7 +1998,7 @@ extern "C" pic_status pic_timing(pic_ctx* ctx, int enable, long long* launches, 
 }
 
 extern "C" pic_status pic_tuning(pic_ctx* ctx, int* tile_r, int* tile_z, int* halo,
-                                 int* sort_interval, int* chunk) {
+                                 int* sort_interval, int* chunk, int* lanes) {
     if (!ctx) return PIC_EINVAL;
     if (ctx->mode != PIC_MODE_FP32_BATCHED) {
         if (tile_r) *tile_r = 0;
@@ -2005,9 +2006,10 @@ extern "C" pic_status pic_tuning(pic_ctx* ctx, int* tile_r, int* tile_z, int* ha
         if (halo) *halo = 0;
         if (sort_interval) *sort_interval = 0;
         if (chunk) *chunk = 0;
+        if (lanes) *lanes = 0;
         return PIC_OK;
     }
-    return f32_tuning(ctx, tile_r, tile_z, halo, sort_interval, chunk);
+    return f32_tuning(ctx, tile_r, tile_z, halo, sort_interval, chunk, lanes);
 }
 
 extern "C" pic_status pic_retune(pic_ctx* ctx, int tile_r, int tile_z, int halo, int sort_interval) {

@@ -840,7 +840,7 @@ __device__ __forceinline__ int wave_search(const long long* a, int n, long long 
 // elliptic insert (absorption on it and the band charges compiled in).
 // MODE bit 3: cubic shapes (the space-charge field from the cubic
 // coefficients, the cubic deposit into the ghosted grid beside Q).
-template <int MODE>
+template <int MODE, int U>
 __device__ __forceinline__ void particles_body(const KArgs& A) {
     constexpr bool COUNT = (MODE & 1) != 0;
     constexpr bool SCATTER = (MODE & 2) != 0;
@@ -994,10 +994,9 @@ __device__ __forceinline__ void particles_body(const KArgs& A) {
             X.win = win; X.step = step;
             X.sC = sC; X.sQx = sQx; X.cxf = F.cxf; X.Qx = F.Qx; X.WX = I.nz + 3;
             // U particles per lane per pass (their loads are all in flight before
-            // any is processed); U = 1 measured fastest on gfx950 (occupancy wins)
-            // Passes start on a 64-slot boundary so that every wave's loads and
-            // stores cover whole aligned lines; lanes before the chunk idle.
-            constexpr int U = 1;
+            // any is processed, and their arithmetic interleaves).  Passes start
+            // on a 64-slot boundary so that every wave's loads and stores cover
+            // whole aligned lines; lanes before the chunk idle.
             const int lead = (int)(start & 63);
             const float wu = X.L.w_uni;
             for (int base = -lead; base < count; base += U * kPWG) {
@@ -1073,17 +1072,26 @@ __device__ __forceinline__ void particles_body(const KArgs& A) {
     }
 }
 
-// The bilinear forms keep 64 registers so two workgroups share a CU.
+// Two launch shapes of the bilinear forms, both timed by the autotuner: one
+// particle per lane and pass at 64 registers, so two workgroups share a CU
+// (8 waves per SIMD); or two particles per lane and pass at up to 128
+// registers, one workgroup per CU (4 waves per SIMD), whose two particles'
+// loads are in flight together and whose arithmetic interleaves.
 template <int MODE>
 __global__ void __launch_bounds__(kPWG) __attribute__((amdgpu_waves_per_eu(8, 8))) k_particles(KArgs A) {
-    particles_body<MODE>(A);
+    particles_body<MODE, 1>(A);
+}
+
+template <int MODE>
+__global__ void __launch_bounds__(kPWG) __attribute__((amdgpu_waves_per_eu(4, 4))) k_particles2(KArgs A) {
+    particles_body<MODE, 2>(A);
 }
 
 // Cubic shapes: the 16-node gather and deposit keep their values in up to
 // 128 registers (one workgroup per CU) instead of spilling.
 template <int MODE>
 __global__ void __launch_bounds__(kPWG) k_particles3(KArgs A) {
-    particles_body<MODE | 8>(A);
+    particles_body<MODE | 8, 1>(A);
 }
 
 // Resolve the collision events queued by the particle kernel (which took
@@ -1494,8 +1502,21 @@ __global__ void k_deposit32(DevInst I, PSet P, long long* Q, long long* Qw, long
 }
 
 typedef void (*ParticleKernel)(KArgs);
-// Variant v = step kind (bits 0-1) | insert (4) | cubic shapes (8).
-ParticleKernel particle_kernel(int v) {
+// Variant v = step kind (bits 0-1) | insert (4) | cubic shapes (8); lanes =
+// particles per lane and pass of the bilinear forms (1 or 2).
+ParticleKernel particle_kernel(int v, int lanes) {
+    if (lanes == 2 && v < 8) {
+        switch (v) {
+            case 0: return k_particles2<0>;
+            case 1: return k_particles2<1>;
+            case 2: return k_particles2<2>;
+            case 3: return k_particles2<3>;
+            case 4: return k_particles2<4>;
+            case 5: return k_particles2<5>;
+            case 6: return k_particles2<6>;
+            default: return k_particles2<7>;
+        }
+    }
     switch (v) {
         case 0: return k_particles<0>;
         case 1: return k_particles<1>;
@@ -1541,6 +1562,7 @@ struct F32State {
     bool cub = false;  // the instances use cubic shapes
     int coll_grid = 64;   // workgroups of k_collide
     int cu = 256, wg_per_cu = 4;
+    int lanes = 1;        // particles per lane and pass of the bilinear particle kernel (1 or 2)
     PSet set[2];
     int cur = 0;
     long long total_cap = 0;
@@ -1692,7 +1714,7 @@ static pic_status build_tiles(pic_ctx* ctx, F32State* S) {
     // every workgroup of the statically balanced grid must be resident at once
     int omin = 1 << 30;
     for (int q = 0; q < 4; ++q) {  // the context's variants
-        const void* f = (const void*)particle_kernel(q | (S->ins ? 4 : 0) | (S->cub ? 8 : 0));
+        const void* f = (const void*)particle_kernel(q | (S->ins ? 4 : 0) | (S->cub ? 8 : 0), S->lanes);
         CK32(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
         int occ = 0;
         (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, f, kPWG, lds);
@@ -1784,6 +1806,7 @@ pic_status f32_init(pic_ctx* ctx) {
     if (run.chunk > 0) S->C = run.chunk;
     for (int k = 0; k < pic_n_inst(ctx); ++k) S->ins = S->ins || pic_inst_dev(ctx, k).has_ins != 0;
     S->cub = pic_inst_dev(ctx, 0).spline3 != 0;  // every instance of a context has the same shapes
+    S->lanes = (run.lanes == 2 && !S->cub) ? 2 : 1;
     pic_status st = build_tiles(ctx, S);
     if (st != PIC_OK) return st;
     const int n = pic_n_inst(ctx);
@@ -1878,7 +1901,8 @@ static pic_status launch_step(pic_ctx* ctx, F32State* S, hipStream_t s, bool tim
     }
     const size_t lds = particle_lds(S->win_max, S->win3_max);
     const dim3 grid(S->cu * S->wg_per_cu);
-    hipLaunchKernelGGL(particle_kernel((mode & 3) | (S->ins ? 4 : 0) | (S->cub ? 8 : 0)), grid, dim3(kPWG), lds, s,
+    hipLaunchKernelGGL(particle_kernel((mode & 3) | (S->ins ? 4 : 0) | (S->cub ? 8 : 0), S->lanes), grid, dim3(kPWG),
+                       lds, s,
                        A);
     CK32(hipGetLastError());
     if (timed) CK32(hipEventRecord(e1, s));
@@ -2073,6 +2097,24 @@ pic_status f32_retune(pic_ctx* ctx, int tile_r, int tile_z, int halo, int sort_i
     return resort_all(ctx, S);
 }
 
+// Switch the bilinear particle kernel's launch shape (1 or 2 particles per
+// lane and pass): a new resident grid and its chunk records, a full sort.
+static pic_status f32_set_lanes(pic_ctx* ctx, int lanes) {
+    F32State* S = pic_get_f32(ctx);
+    if (S->cub || lanes == S->lanes) return PIC_OK;
+    pic_status st = quiesce(ctx, S);
+    if (st != PIC_OK) return st;
+    const int old = S->lanes;
+    S->lanes = lanes;
+    st = build_tiles(ctx, S);
+    if (st == PIC_EINVAL) {
+        S->lanes = old;
+        return st;
+    }
+    if (st != PIC_OK) return st;
+    return resort_all(ctx, S);
+}
+
 pic_status f32_reserve(pic_ctx* ctx, int k, long long slots) {
     F32State* S = pic_get_f32(ctx);
     const int n = pic_n_inst(ctx);
@@ -2223,8 +2265,9 @@ pic_status f32_step(pic_ctx* ctx, int n_steps) {
 
 // ---- autotuner ---------------------------------------------------------------
 // Times the real workload under candidate tile shapes, halos and sort
-// intervals (coordinate search: tile shape, then halo, then interval) and
-// keeps the fastest.  Every result of the method is independent of these
+// intervals (coordinate search: tile shape, then halo, then interval), for
+// each launch shape of the particle kernel (one or two particles per lane
+// and pass), and keeps the fastest.  Every result of the method is independent of these
 // choices (bit-identical), so the trial steps are ordinary steps of the run.
 // A cache file holds one JSON object per line keyed by a workload signature.
 
@@ -2248,7 +2291,7 @@ static std::string tune_signature(pic_ctx* ctx) {
     return sig;
 }
 
-static bool tune_lookup(const char* path, const std::string& sig, int v[4]) {
+static bool tune_lookup(const char* path, const std::string& sig, int v[4], int* lanes) {
     FILE* f = path ? fopen(path, "r") : nullptr;
     if (!f) return false;
     char line[4096];
@@ -2264,7 +2307,11 @@ static bool tune_lookup(const char* path, const std::string& sig, int v[4]) {
             if (at == std::string::npos) { ok = false; break; }
             v[i] = atoi(l.c_str() + at + strlen(names[i]));
         }
-        if (ok) found = true;
+        if (ok) {
+            found = true;
+            const size_t at = l.find("\"lanes\": ");
+            *lanes = at == std::string::npos ? 1 : atoi(l.c_str() + at + 10);
+        }
     }
     fclose(f);
     return found;
@@ -2274,9 +2321,11 @@ pic_status f32_autotune(pic_ctx* ctx, int trial_steps, const char* cache, int ou
                         int* trials_out) {
     F32State* S = pic_get_f32(ctx);
     const std::string sig = tune_signature(ctx);
-    int v[4];
-    if (tune_lookup(cache, sig, v)) {
-        pic_status st = f32_retune(ctx, v[0], v[1], v[2], v[3]);
+    int v[4], lanes = 1;
+    if (tune_lookup(cache, sig, v, &lanes)) {
+        pic_status st = f32_set_lanes(ctx, lanes == 2 ? 2 : 1);
+        if (st != PIC_OK) return st;
+        st = f32_retune(ctx, v[0], v[1], v[2], v[3]);
         if (st != PIC_OK) return st;
         for (int i = 0; i < 4; ++i) out[i] = v[i];
         if (ms_out) *ms_out = 0.0;
@@ -2300,11 +2349,17 @@ pic_status f32_autotune(pic_ctx* ctx, int trial_steps, const char* cache, int ou
         for (int k = 0; k < n; ++k) t += cnt[(size_t)k * C_NCOUNT + C_PSTEPS];
         return t;
     };
-    auto trial = [&](int TR, int TZ, int h, int K, double& ms) -> pic_status {
+    // one candidate: particles per lane and pass, tile shape, halo, sort interval
+    typedef std::array<int, 5> Cand;
+    auto trial = [&](const Cand& c, double& ms) -> pic_status {
         ms = 1e30;
-        pic_status st = f32_retune(ctx, TR, TZ, h, K);
+        pic_status st = f32_set_lanes(ctx, c[0]);
         if (st == PIC_EINVAL) return PIC_OK;  // does not fit: skipped
         if (st != PIC_OK) return st;
+        st = f32_retune(ctx, c[1], c[2], c[3], c[4]);
+        if (st == PIC_EINVAL) return PIC_OK;
+        if (st != PIC_OK) return st;
+        const int K = c[4];
         st = f32_step(ctx, 2 * K);  // every step kind captured and warm
         if (st != PIC_OK) return st;
         const int T = ((std::max(trial_steps, 2 * K) + K - 1) / K) * K;
@@ -2323,36 +2378,38 @@ pic_status f32_autotune(pic_ctx* ctx, int trial_steps, const char* cache, int ou
         ++trials;
         return PIC_OK;
     };
-    int best[4] = {S->TR, S->TZ, S->halo, S->K};
+    Cand best = {S->lanes, S->TR, S->TZ, S->halo, S->K};
     double best_ms = 1e30;
     pic_status st = PIC_OK;
     const bool verbose = getenv("PICMCC_TUNE_LOG") != nullptr;  // trial log on stderr
-    std::vector<std::array<int, 4>> tried;
+    std::vector<Cand> tried;
     std::vector<double> tried_ms;
-    auto consider = [&](int TR, int TZ, int h, int K) {
-        const std::array<int, 4> c = {TR, TZ, h, K};
+    auto consider = [&](const Cand& c) {
         if (st != PIC_OK || std::find(tried.begin(), tried.end(), c) != tried.end()) return;
         double ms;
-        st = trial(TR, TZ, h, K, ms);
+        st = trial(c, ms);
         tried.push_back(c);
         tried_ms.push_back(ms);
         if (verbose)
-            fprintf(stderr, "autotune: tile %dx%d halo %d sort %d: %.4g ps per particle-step%s\n", TR, TZ, h, K,
-                    ms * 1e9, ms >= 1e29 ? " (does not fit)" : "");
+            fprintf(stderr, "autotune: %d per lane, tile %dx%d halo %d sort %d: %.4g ps per particle-step%s\n", c[0],
+                    c[1], c[2], c[3], c[4], ms * 1e9, ms >= 1e29 ? " (does not fit)" : "");
         if (st == PIC_OK && ms < best_ms) {
             best_ms = ms;
-            best[0] = TR; best[1] = TZ; best[2] = h; best[3] = K;
+            best = c;
         }
     };
     const int shapes[][2] = {{8, 32}, {8, 8}, {8, 16}, {16, 8}, {16, 16}, {32, 8}, {16, 32},
                              {32, 16}, {32, 32}, {8, 64}, {16, 64}, {4, 64}, {4, 32}};
     const int halos[] = {2, 4, 8, 12};
     const int Ks[] = {4, 8, 16, 32};
-    for (int round = 0; round < 2; ++round) {  // coordinate search, twice
-        for (auto& sh : shapes) consider(sh[0], sh[1], best[2], best[3]);
-        for (int h : halos) consider(best[0], best[1], h, best[3]);
-        for (int K : Ks) consider(best[0], best[1], best[2], K);
-    }
+    // coordinate search, twice, for each launch shape of the particle kernel
+    // (cubic shapes have one), each starting from the best found so far
+    for (int lanes = 1; lanes <= (S->cub ? 1 : 2); ++lanes)
+        for (int round = 0; round < 2; ++round) {
+            for (auto& sh : shapes) consider({lanes, sh[0], sh[1], best[3], best[4]});
+            for (int h : halos) consider({lanes, best[1], best[2], h, best[4]});
+            for (int K : Ks) consider({lanes, best[1], best[2], best[3], K});
+        }
     // The run evolves while the trials go on, which biases trials far apart
     // in time: the four best are timed again, interleaved, twice each, and
     // the lowest mean of those repeats wins.
@@ -2364,28 +2421,30 @@ pic_status f32_autotune(pic_ctx* ctx, int trial_steps, const char* cache, int ou
         std::vector<double> sum(top, 0.0);
         for (int rep = 0; rep < 2 && st == PIC_OK; ++rep)
             for (int c = 0; c < top && st == PIC_OK; ++c) {
-                const auto& v = tried[order[c]];
+                const Cand& v = tried[order[c]];
                 double ms;
-                st = trial(v[0], v[1], v[2], v[3], ms);
+                st = trial(v, ms);
                 sum[c] += ms;
                 if (verbose)
-                    fprintf(stderr, "autotune: repeat tile %dx%d halo %d sort %d: %.4g ps per particle-step\n", v[0],
-                            v[1], v[2], v[3], ms * 1e9);
+                    fprintf(stderr, "autotune: repeat %d per lane, tile %dx%d halo %d sort %d: %.4g ps per particle-step\n",
+                            v[0], v[1], v[2], v[3], v[4], ms * 1e9);
             }
         if (st == PIC_OK) {
             int bc = 0;
             for (int c = 1; c < top; ++c)
                 if (sum[c] < sum[bc]) bc = c;
-            for (int i = 0; i < 4; ++i) best[i] = tried[order[bc]][i];
+            best = tried[order[bc]];
             best_ms = sum[bc] / 2.0;
         }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (st != PIC_OK) return st;
-    st = f32_retune(ctx, best[0], best[1], best[2], best[3]);
+    st = f32_set_lanes(ctx, best[0]);
     if (st != PIC_OK) return st;
-    for (int i = 0; i < 4; ++i) out[i] = best[i];
+    st = f32_retune(ctx, best[1], best[2], best[3], best[4]);
+    if (st != PIC_OK) return st;
+    for (int i = 0; i < 4; ++i) out[i] = best[i + 1];
     long long live = 0;
     (void)psteps();
     for (int k = 0; k < n; ++k) live += cnt[(size_t)k * C_NCOUNT + C_SLOTS] - cnt[(size_t)k * C_NCOUNT + C_DEAD];
@@ -2396,8 +2455,8 @@ pic_status f32_autotune(pic_ctx* ctx, int trial_steps, const char* cache, int ou
         FILE* f = fopen(cache, "a");
         if (f) {
             fprintf(f, "{\"sig\": \"%s\", \"tile_r\": %d, \"tile_z\": %d, \"halo\": %d, \"sort_interval\": %d, "
-                       "\"ms_per_step\": %.6f, \"trials\": %d}\n",
-                    sig.c_str(), best[0], best[1], best[2], best[3], best_ms, trials);
+                       "\"lanes\": %d, \"ms_per_step\": %.6f, \"trials\": %d}\n",
+                    sig.c_str(), best[1], best[2], best[3], best[4], best[0], best_ms, trials);
             fclose(f);
         }
     }
@@ -2514,8 +2573,10 @@ pic_status f32_check(pic_ctx* ctx) {
     return PIC_OK;
 }
 
-pic_status f32_tuning(pic_ctx* ctx, int* tile_r, int* tile_z, int* halo, int* sort_interval, int* chunk) {
+pic_status f32_tuning(pic_ctx* ctx, int* tile_r, int* tile_z, int* halo, int* sort_interval, int* chunk,
+                      int* lanes) {
     F32State* S = pic_get_f32(ctx);
+    if (lanes) *lanes = S->lanes;
     if (tile_r) *tile_r = S->TR;
     if (tile_z) *tile_z = S->TZ;
     if (halo) *halo = S->halo;

@@ -45,6 +45,9 @@ def test_invariant_to_tiles_sort_interval_chunk_and_graph():
     for kw in (dict(tile_r=8, tile_z=8, sort_interval=1, use_graph=0),
                dict(tile_r=4, tile_z=32, sort_interval=3, halo=1, chunk=300),
                dict(tile_r=32, tile_z=8, sort_interval=16, halo=8, chunk=100000, use_graph=1),
+               # two particles per lane and pass, one workgroup per CU
+               dict(tile_r=8, tile_z=32, sort_interval=5, halo=4, lanes=2, use_graph=1),
+               dict(tile_r=16, tile_z=8, sort_interval=2, chunk=777, lanes=2, use_graph=0),
                # one-particle chunks, a sort every second step: more chunks per
                # workgroup than the counting step records, so the sorting step
                # counts the later ones itself

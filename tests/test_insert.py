@@ -320,7 +320,8 @@ def test_fp32_with_insert_is_invariant_and_tracks_the_oracle():
     c = pi.gun(E_cap_eV=33020.0)
     ref = None
     for kw in (dict(tile_r=8, tile_z=32, sort_interval=8, use_graph=1),
-               dict(tile_r=4, tile_z=16, sort_interval=3, halo=1, use_graph=0)):
+               dict(tile_r=4, tile_z=16, sort_interval=3, halo=1, use_graph=0),
+               dict(tile_r=8, tile_z=16, sort_interval=6, halo=4, lanes=2, use_graph=1)):
         g = B.Sim([c], mode=F32, **kw)
         g.step(40)
         out = (by_key(g.get_particles()), g.charge(), g.band_charge(), g.diag())

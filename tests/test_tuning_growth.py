@@ -83,6 +83,8 @@ def test_autotune_picks_a_valid_choice_and_caches_it(tmp_path):
     assert t2["trials"] == 0
     for k in ("tile_r", "tile_z", "halo", "sort_interval"):
         assert t2[k] == t[k]
+    # the launch shape the trials chose is cached and restored with the tiles
+    assert lines[0]["lanes"] in (1, 2) and B.pic_tuning(h.ctx)["lanes"] == lines[0]["lanes"] == cur["lanes"]
     h.close()
 
 
