@@ -2309,8 +2309,9 @@ static bool tune_lookup(const char* path, const std::string& sig, int v[4], int*
         }
         if (ok) {
             found = true;
-            const size_t at = l.find("\"lanes\": ");
-            *lanes = at == std::string::npos ? 1 : atoi(l.c_str() + at + 10);
+            const char* lk = "\"lanes\": ";
+            const size_t at = l.find(lk);
+            *lanes = at == std::string::npos ? 1 : atoi(l.c_str() + at + strlen(lk));
         }
     }
     fclose(f);

@@ -86,6 +86,15 @@ def test_autotune_picks_a_valid_choice_and_caches_it(tmp_path):
     # the launch shape the trials chose is cached and restored with the tiles
     assert lines[0]["lanes"] in (1, 2) and B.pic_tuning(h.ctx)["lanes"] == lines[0]["lanes"] == cur["lanes"]
     h.close()
+    # the last cached line of a signature wins: two particles per lane are restored as such
+    with open(cache, "a") as f:
+        f.write(json.dumps(dict(lines[0], tile_r=8, tile_z=16, lanes=2)) + "\n")
+    h = B.Sim(cfgs, mode=F32)
+    t3 = h.autotune(trial_steps=4, cache_path=cache)
+    tun = B.pic_tuning(h.ctx)
+    assert t3["trials"] == 0 and tun["lanes"] == 2 and (tun["tile_r"], tun["tile_z"]) == (8, 16)
+    h.step(5)
+    h.close()
 
 
 @pytest.mark.parametrize("mode", [F32, F64])
