@@ -377,7 +377,8 @@ pic_status pic_tuning(pic_ctx* ctx, int* tile_r, int* tile_z, int* halo, int* so
  * halo-cell LDS window and a sort every sort_interval steps (a value <= 0,
  * or < 0 for halo, keeps the current one), then re-sort every particle.
  * Synchronises.  No result of the method depends on these choices.
- * Errors: PIC_EINVAL (out of range, window above 64 KiB of LDS, or the FP64
+ * Errors: PIC_EINVAL (out of range, a window above the LDS of the launch shape --
+ * 64 KiB with one particle per lane, 144 KiB with two -- or the FP64
  * form; the context is unchanged), PIC_ENOMEM/PIC_EDEVICE (the context must
  * then be destroyed).
  */

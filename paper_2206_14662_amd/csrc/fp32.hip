@@ -1669,7 +1669,11 @@ static pic_status build_tiles(pic_ctx* ctx, F32State* S) {
                                          "1 <= chunk <= 2^30");
     const int win = (S->TR + 2 * S->halo + 1) * (S->TZ + 2 * S->halo + 1);
     const int win3 = S->cub ? ((S->TR + 2 * S->halo + 3) * (S->TZ + 2 * S->halo + 3) + 1) / 2 * 2 : 0;
-    if (particle_lds(win, win3) > 64 * 1024) return f32_fail(ctx, PIC_EINVAL, "tile window exceeds 64 KiB of LDS");
+    // two workgroups per CU share its 160 KiB of LDS with one particle per
+    // lane; with two, one workgroup has it to itself
+    const size_t lds_cap = S->lanes == 2 ? 144 * 1024 : 64 * 1024;
+    if (particle_lds(win, win3) > lds_cap)
+        return f32_fail(ctx, PIC_EINVAL, "tile window exceeds the LDS of the launch shape (64 or 144 KiB)");
     const int n = pic_n_inst(ctx);
     long long tsum = 0;
     for (int k = 0; k < n; ++k) {
@@ -2079,40 +2083,30 @@ pic_status f32_rates_changed(pic_ctx* ctx) {
 }
 
 
-pic_status f32_retune(pic_ctx* ctx, int tile_r, int tile_z, int halo, int sort_interval) {
+// New tiles, halo, sort interval and launch shape (lanes 1 or 2; 0 keeps
+// it): the tile tables rebuilt and every particle re-sorted.  PIC_EINVAL
+// leaves the context as it was.
+static pic_status reconfigure(pic_ctx* ctx, int lanes, int tile_r, int tile_z, int halo, int sort_interval) {
     F32State* S = pic_get_f32(ctx);
     pic_status st = quiesce(ctx, S);
     if (st != PIC_OK) return st;
-    const int old[4] = {S->TR, S->TZ, S->halo, S->K};
+    const int old[5] = {S->TR, S->TZ, S->halo, S->K, S->lanes};
     if (tile_r > 0) S->TR = tile_r;
     if (tile_z > 0) S->TZ = tile_z;
     if (halo >= 0) S->halo = halo;
     if (sort_interval > 0) S->K = sort_interval;
+    if (lanes > 0 && !S->cub) S->lanes = lanes;
     st = build_tiles(ctx, S);
     if (st == PIC_EINVAL) {  // rejected before anything changed
-        S->TR = old[0]; S->TZ = old[1]; S->halo = old[2]; S->K = old[3];
+        S->TR = old[0]; S->TZ = old[1]; S->halo = old[2]; S->K = old[3]; S->lanes = old[4];
         return st;
     }
     if (st != PIC_OK) return st;
     return resort_all(ctx, S);
 }
 
-// Switch the bilinear particle kernel's launch shape (1 or 2 particles per
-// lane and pass): a new resident grid and its chunk records, a full sort.
-static pic_status f32_set_lanes(pic_ctx* ctx, int lanes) {
-    F32State* S = pic_get_f32(ctx);
-    if (S->cub || lanes == S->lanes) return PIC_OK;
-    pic_status st = quiesce(ctx, S);
-    if (st != PIC_OK) return st;
-    const int old = S->lanes;
-    S->lanes = lanes;
-    st = build_tiles(ctx, S);
-    if (st == PIC_EINVAL) {
-        S->lanes = old;
-        return st;
-    }
-    if (st != PIC_OK) return st;
-    return resort_all(ctx, S);
+pic_status f32_retune(pic_ctx* ctx, int tile_r, int tile_z, int halo, int sort_interval) {
+    return reconfigure(ctx, 0, tile_r, tile_z, halo, sort_interval);
 }
 
 pic_status f32_reserve(pic_ctx* ctx, int k, long long slots) {
@@ -2324,9 +2318,7 @@ pic_status f32_autotune(pic_ctx* ctx, int trial_steps, const char* cache, int ou
     const std::string sig = tune_signature(ctx);
     int v[4], lanes = 1;
     if (tune_lookup(cache, sig, v, &lanes)) {
-        pic_status st = f32_set_lanes(ctx, lanes == 2 ? 2 : 1);
-        if (st != PIC_OK) return st;
-        st = f32_retune(ctx, v[0], v[1], v[2], v[3]);
+        pic_status st = reconfigure(ctx, lanes == 2 ? 2 : 1, v[0], v[1], v[2], v[3]);
         if (st != PIC_OK) return st;
         for (int i = 0; i < 4; ++i) out[i] = v[i];
         if (ms_out) *ms_out = 0.0;
@@ -2354,11 +2346,8 @@ pic_status f32_autotune(pic_ctx* ctx, int trial_steps, const char* cache, int ou
     typedef std::array<int, 5> Cand;
     auto trial = [&](const Cand& c, double& ms) -> pic_status {
         ms = 1e30;
-        pic_status st = f32_set_lanes(ctx, c[0]);
+        pic_status st = reconfigure(ctx, c[0], c[1], c[2], c[3], c[4]);
         if (st == PIC_EINVAL) return PIC_OK;  // does not fit: skipped
-        if (st != PIC_OK) return st;
-        st = f32_retune(ctx, c[1], c[2], c[3], c[4]);
-        if (st == PIC_EINVAL) return PIC_OK;
         if (st != PIC_OK) return st;
         const int K = c[4];
         st = f32_step(ctx, 2 * K);  // every step kind captured and warm
@@ -2399,8 +2388,10 @@ pic_status f32_autotune(pic_ctx* ctx, int trial_steps, const char* cache, int ou
             best = c;
         }
     };
+    // (the last three fit the LDS with two particles per lane only)
     const int shapes[][2] = {{8, 32}, {8, 8}, {8, 16}, {16, 8}, {16, 16}, {32, 8}, {16, 32},
-                             {32, 16}, {32, 32}, {8, 64}, {16, 64}, {4, 64}, {4, 32}};
+                             {32, 16}, {32, 32}, {8, 64}, {16, 64}, {4, 64}, {4, 32},
+                             {32, 64}, {16, 128}, {64, 32}};
     const int halos[] = {2, 4, 8, 12};
     const int Ks[] = {4, 8, 16, 32};
     // coordinate search, twice, for each launch shape of the particle kernel
@@ -2441,9 +2432,7 @@ pic_status f32_autotune(pic_ctx* ctx, int trial_steps, const char* cache, int ou
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (st != PIC_OK) return st;
-    st = f32_set_lanes(ctx, best[0]);
-    if (st != PIC_OK) return st;
-    st = f32_retune(ctx, best[1], best[2], best[3], best[4]);
+    st = reconfigure(ctx, best[0], best[1], best[2], best[3], best[4]);
     if (st != PIC_OK) return st;
     for (int i = 0; i < 4; ++i) out[i] = best[i + 1];
     long long live = 0;
