@@ -33,8 +33,8 @@ def _replay(cfg, S, fields, step, sample, collisions):
     return o.get_particles()
 
 
-def full_size_steps(cfgs, check, steps=6, n_sample=4096, max_flips=2, need_events=False):
-    g = B.Sim(cfgs, mode=F32, **TILES)
+def full_size_steps(cfgs, check, steps=6, n_sample=4096, max_flips=2, need_events=False, tiles=TILES):
+    g = B.Sim(cfgs, mode=F32, **tiles)
     rng = np.random.default_rng(7)
     n0 = [c["n_init"] for c in cfgs]
     flips_total = 0
@@ -81,6 +81,12 @@ def full_size_steps(cfgs, check, steps=6, n_sample=4096, max_flips=2, need_event
 
 def test_batch8_full_size_sort_cycle():
     full_size_steps(pi.batch8(), check=(0, 5, 7))
+
+
+def test_batch8_full_size_sort_cycle_two_particles_per_lane():
+    """The launch shape the benchmark's autotuner picks for this workload: two
+    particles per lane and pass, one workgroup per CU, a wider window."""
+    full_size_steps(pi.batch8(), check=(0, 3, 6), tiles=dict(tile_r=16, tile_z=128, halo=8, sort_interval=4, lanes=2))
 
 
 def test_batch8_full_size_raised_pressure_sort_cycle():
