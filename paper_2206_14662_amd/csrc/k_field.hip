@@ -16,6 +16,10 @@ namespace {
 // least 64): every thread holds 8 points per pass.
 constexpr int kFftMaxBlock = 1024;
 inline int fft_block(int max_nz) { return 2 * max_nz / 8 > 64 ? 2 * max_nz / 8 : 64; }
+// Nodes per thread and row in the load and store phases of the z transform:
+// the block holds at least nz / 4 threads, so for nz >= 4 one round covers
+// the nz + 1 nodes of a row.
+constexpr int kRowPer = 5;
 
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
     return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
@@ -180,56 +184,98 @@ __global__ void __launch_bounds__(kFftMaxBlock) kf_dst(const DevInst* __restrict
     // an instance with the elliptic insert has its load in rhs already
     const bool from_q = mode == 0 && !I.has_ins;
     const double bs = from_q ? bscale[inst] : 1.0;
-    for (int j = threadIdx.x; j < N; j += blockDim.x) {
-        int jj = j <= nz ? j : N - j;
-        double sg = (open || j <= nz) ? 1.0 : -1.0;
-        double va = 0.0, vb = 0.0;
-        if (open || (jj >= 1 && jj <= nz - 1)) {
-            if (from_q) {
-                va = (double)F.Q[(long long)iA * W + jj] * bs;
-                vb = hasB ? (double)F.Q[(long long)iB * W + jj] * bs : 0.0;
-            } else {
-                va = F.rhs[(long long)iA * W + jj];
-                vb = hasB ? F.rhs[(long long)iB * W + jj] : 0.0;
-            }
+    // Each node of the two rows is read once, a thread's loads all issued
+    // before the first is used, and stored to its slot jj and (interior
+    // nodes) to the mirror slot N - jj of the odd (even) extension.
+    const unsigned long long* src =
+        from_q ? reinterpret_cast<const unsigned long long*>(F.Q) : reinterpret_cast<const unsigned long long*>(F.rhs);
+    for (int j0 = 0; j0 <= nz; j0 += kRowPer * blockDim.x) {
+        unsigned long long ba[kRowPer], bb[kRowPer];
+#pragma unroll
+        for (int q = 0; q < kRowPer; ++q) {
+            const int jj = j0 + threadIdx.x + q * blockDim.x;
+            const bool ld = jj <= nz && (open || (jj >= 1 && jj <= nz - 1));
+            ba[q] = ld ? src[(long long)iA * W + jj] : 0ull;
+            bb[q] = ld && hasB ? src[(long long)iB * W + jj] : 0ull;
         }
-        y[lp(j)] = make_double2(sg * va, sg * vb);
-        if (open && j == 0) ends[0] = make_double2(va, vb);
-        if (open && j == nz) ends[1] = make_double2(va, vb);
+#pragma unroll
+        for (int q = 0; q < kRowPer; ++q) {
+            const int jj = j0 + threadIdx.x + q * blockDim.x;
+            if (jj > nz) continue;
+            const bool ld = open || (jj >= 1 && jj <= nz - 1);
+            double va = 0.0, vb = 0.0;
+            if (ld) {
+                va = from_q ? (double)(long long)ba[q] * bs : __longlong_as_double((long long)ba[q]);
+                if (hasB) vb = from_q ? (double)(long long)bb[q] * bs : __longlong_as_double((long long)bb[q]);
+            }
+            y[lp(jj)] = make_double2(va, vb);
+            if (jj >= 1 && jj <= nz - 1) {
+                const double sg = open ? 1.0 : -1.0;
+                y[lp(N - jj)] = make_double2(sg * va, sg * vb);
+            }
+            if (open && jj == 0) ends[0] = make_double2(va, vb);
+            if (open && jj == nz) ends[1] = make_double2(va, vb);
+        }
     }
     __syncthreads();
     fft_lds(y, N, tw, tw_n);
     if (open) {
         const double2 e0 = ends[0], e1 = ends[1];
-        for (int k = threadIdx.x; k <= nz; k += blockDim.x) {
-            const double sgn = (k & 1) ? -1.0 : 1.0;
-            const double2 yk = y[lp(k)];
-            double SA = 0.5 * (yk.x + (e0.x + sgn * e1.x));
-            double SB = 0.5 * (yk.y + (e0.y + sgn * e1.y));
-            const long long nA = (long long)iA * W + k, nB = (long long)iB * W + k;
-            if (mode == 2) {
-                F.phi[nA] = F.phi_vac[nA] + SA;
-                if (hasB) F.phi[nB] = F.phi_vac[nB] + SB;
-            } else {
-                const double ck = (k == 0 || k == nz) ? (double)nz : 0.5 * (double)nz;
-                F.rhs[nA] = SA / ck;
-                if (hasB) F.rhs[nB] = SB / ck;
+        for (int k0 = 0; k0 <= nz; k0 += kRowPer * blockDim.x) {
+            double pa[kRowPer], pb[kRowPer];
+#pragma unroll
+            for (int q = 0; q < kRowPer; ++q) {
+                const int k = k0 + threadIdx.x + q * blockDim.x;
+                const bool ld = mode == 2 && k <= nz;
+                pa[q] = ld ? F.phi_vac[(long long)iA * W + k] : 0.0;
+                pb[q] = ld && hasB ? F.phi_vac[(long long)iB * W + k] : 0.0;
+            }
+#pragma unroll
+            for (int q = 0; q < kRowPer; ++q) {
+                const int k = k0 + threadIdx.x + q * blockDim.x;
+                if (k > nz) continue;
+                const double sgn = (k & 1) ? -1.0 : 1.0;
+                const double2 yk = y[lp(k)];
+                double SA = 0.5 * (yk.x + (e0.x + sgn * e1.x));
+                double SB = 0.5 * (yk.y + (e0.y + sgn * e1.y));
+                const long long nA = (long long)iA * W + k, nB = (long long)iB * W + k;
+                if (mode == 2) {
+                    F.phi[nA] = pa[q] + SA;
+                    if (hasB) F.phi[nB] = pb[q] + SB;
+                } else {
+                    const double ck = (k == 0 || k == nz) ? (double)nz : 0.5 * (double)nz;
+                    F.rhs[nA] = SA / ck;
+                    if (hasB) F.rhs[nB] = SB / ck;
+                }
             }
         }
         return;
     }
     // y = -2i X_A + 2 X_B for odd real inputs A (real part) and B (imag part)
     const double sc = 2.0 / (double)nz;
-    for (int k = threadIdx.x + 1; k <= nz - 1; k += blockDim.x) {
-        const double2 yk = y[lp(k)];
-        double XA = -0.5 * yk.y, XB = 0.5 * yk.x;
-        long long nA = (long long)iA * W + k, nB = (long long)iB * W + k;
-        if (mode == 2) {
-            F.phi[nA] = F.phi_vac[nA] + sc * XA;
-            if (hasB) F.phi[nB] = F.phi_vac[nB] + sc * XB;
-        } else {
-            F.rhs[nA] = XA;
-            if (hasB) F.rhs[nB] = XB;
+    for (int k0 = 1; k0 <= nz - 1; k0 += kRowPer * blockDim.x) {
+        double pa[kRowPer], pb[kRowPer];
+#pragma unroll
+        for (int q = 0; q < kRowPer; ++q) {
+            const int k = k0 + threadIdx.x + q * blockDim.x;
+            const bool ld = mode == 2 && k <= nz - 1;
+            pa[q] = ld ? F.phi_vac[(long long)iA * W + k] : 0.0;
+            pb[q] = ld && hasB ? F.phi_vac[(long long)iB * W + k] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < kRowPer; ++q) {
+            const int k = k0 + threadIdx.x + q * blockDim.x;
+            if (k > nz - 1) continue;
+            const double2 yk = y[lp(k)];
+            double XA = -0.5 * yk.y, XB = 0.5 * yk.x;
+            long long nA = (long long)iA * W + k, nB = (long long)iB * W + k;
+            if (mode == 2) {
+                F.phi[nA] = pa[q] + sc * XA;
+                if (hasB) F.phi[nB] = pb[q] + sc * XB;
+            } else {
+                F.rhs[nA] = XA;
+                if (hasB) F.rhs[nB] = XB;
+            }
         }
     }
 }
