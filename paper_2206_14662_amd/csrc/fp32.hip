@@ -1234,11 +1234,11 @@ __global__ void __launch_bounds__(kWG) k_moments32(DevInst I, PSet P, const long
     }
 }
 
-// Tail plan of the coming step (see prep_tails) when no field stage ran
+// Tail plan of the coming step (see prep_tails_block) when no field stage ran
 // since the counters changed (after a full sort).
 __global__ void k_prep(long long* ctl, const long long* cnt, int n_inst) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    prep_tails(ctl, cnt, n_inst);
+    if (blockIdx.x != 0) return;
+    prep_tails_block(ctl, cnt, n_inst);
 }
 
 __global__ void k_zero_q(const DevInst* It, const FieldDev* Ft) {

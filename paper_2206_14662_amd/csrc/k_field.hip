@@ -589,7 +589,7 @@ __global__ void ks_commit(const DevInst* __restrict__ It, long long* cnt_base, l
         c[C_STEP] += 1;
     }
     __syncthreads();
-    if (ctl && threadIdx.x == 0) prep_tails(ctl, cnt_base, n_inst);
+    if (ctl) prep_tails_block(ctl, cnt_base, n_inst);
 }
 
 // ---- cubic B-spline space charge ------------------------------------------
@@ -805,7 +805,9 @@ hipError_t launch_solve_tab(const DevInst* It, const FieldDev* Ft, int inst_base
         const int rows = (max_nr - 1 + nseg - 1) / nseg;
         const dim3 blk(64, kThomasSegReg);
         const dim3 g2((unsigned)((max_nz + 1 + 31) / 32), (unsigned)n_inst);
-        if (rows <= 8)
+        if (rows <= 4)  // meshes up to 129 cells in r: half the loads of R = 8
+            hipLaunchKernelGGL((kf_thomas_reg<4, 2>), g2, blk, 0, s, It, Ft, inst_base);
+        else if (rows <= 8)
             hipLaunchKernelGGL((kf_thomas_reg<8, 2>), g2, blk, 0, s, It, Ft, inst_base);
         else
             hipLaunchKernelGGL((kf_thomas_reg<16, 2>), g2, blk, 0, s, It, Ft, inst_base);

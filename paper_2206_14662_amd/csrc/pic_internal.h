@@ -144,17 +144,42 @@ enum Counter {
 enum { CTL_TOTAL = 1, CTL_SORTED = 2, CTL_QCOUNT = 3, CTL_QOVER = 4, CTL_TAIL = 5 };
 
 // Plan of the coming step from the committed counters: tail prefix, total,
-// an empty collision queue.  One thread.
-__device__ inline void prep_tails(long long* ctl, const long long* cnt, int n_inst) {
+// an empty collision queue.  Every thread of one block (at most 256
+// threads) calls it; the prefix is an LDS scan over up to blockDim
+// instances at a time.
+__device__ inline void prep_tails_block(long long* ctl, const long long* cnt, int n_inst) {
+    __shared__ long long s_v[256];
+    __shared__ long long s_carry;
     long long* tb = ctl + CTL_TAIL;
-    tb[0] = 0;
-    ctl[CTL_QCOUNT] = 0;
-    for (int k = 0; k < n_inst; ++k) {
-        const long long* c = cnt + (long long)k * C_NCOUNT;
-        const long long tail = c[C_SLOTS] - c[C_LIVE_SORTED];
-        tb[k + 1] = tb[k] + (tail > 0 ? tail : 0);
+    const int t = threadIdx.x, nt = blockDim.x;
+    if (t == 0) {
+        tb[0] = 0;
+        ctl[CTL_QCOUNT] = 0;
+        s_carry = 0;
     }
-    ctl[CTL_TOTAL] = ctl[CTL_SORTED] + tb[n_inst];
+    for (int k0 = 0; k0 < n_inst; k0 += nt) {
+        const int k = k0 + t;
+        long long v = 0;
+        if (k < n_inst) {
+            const long long* c = cnt + (long long)k * C_NCOUNT;
+            const long long tail = c[C_SLOTS] - c[C_LIVE_SORTED];
+            v = tail > 0 ? tail : 0;
+        }
+        s_v[t] = v;
+        __syncthreads();
+        for (int off = 1; off < nt; off <<= 1) {  // inclusive scan
+            const long long add = t >= off ? s_v[t - off] : 0;
+            __syncthreads();
+            s_v[t] += add;
+            __syncthreads();
+        }
+        const long long carry = s_carry;
+        if (k < n_inst) tb[k + 1] = carry + s_v[t];
+        __syncthreads();
+        if (t == nt - 1) s_carry = carry + s_v[t];
+        __syncthreads();
+    }
+    if (t == 0) ctl[CTL_TOTAL] = ctl[CTL_SORTED] + s_carry;
 }
 
 // ---------------------------------------------------------------------------
