@@ -64,6 +64,18 @@ def test_batched_equals_solo():
         same(batch[k], run32([c], 30)[0])
 
 
+def test_batch_wider_than_one_scan_block_equals_solo():
+    """260 instances: the end-of-step tail plan scans the instances 256 at a
+    time, so the instances past the first block take their tail offsets from
+    the carry.  Ionisation adds tails every step and the sorts merge them;
+    instances on both sides of the block edge match their solo runs."""
+    cfgs = [hot(seed=100 + k, nr=16, nz=32, n_init=1500) for k in range(260)]
+    batch = run32(cfgs, 12, sort_interval=4, tile_r=8, tile_z=16)
+    assert sum(d["n_ioniz"] for _, _, d in batch) > 10
+    for k in (0, 255, 256, 259):
+        same(batch[k], run32([cfgs[k]], 12, sort_interval=4, tile_r=8, tile_z=16)[0])
+
+
 def test_resume_is_bit_identical():
     cfg = hot()
     g = B.Sim([cfg], mode=F32)
