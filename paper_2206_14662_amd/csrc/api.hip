@@ -775,7 +775,9 @@ hipEvent_t pic_timing_begin(pic_ctx* ctx, hipEvent_t* stop) {
     if (ctx->ev_used + 2 > ctx->ev.size()) {
         for (int k = 0; k < 64; ++k) {
             hipEvent_t e;
-            if (hipEventCreate(&e) != hipSuccess) return nullptr;
+            // timing only (read after a stream synchronisation): no system-scope
+            // fence, whose cache writeback and invalidation would be timed too
+            if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return nullptr;
             ctx->ev.push_back(e);
         }
     }
