@@ -56,7 +56,8 @@ def autotune(B, torch, cfgs, cache):
     t0 = time.perf_counter()
     t = sim.autotune(trial_steps=48, cache_path=cache)
     t["tune_s"] = time.perf_counter() - t0
-    t["lanes"] = B.pic_tuning(sim.ctx)["lanes"]
+    tun = B.pic_tuning(sim.ctx)
+    t["lanes"], t["use_graph"] = tun["lanes"], tun["use_graph"]
     sim.close()
     torch.cuda.synchronize()
     return t
@@ -69,7 +70,8 @@ def measure(B, torch, cfgs, mode, steps, warmup, graph_region, tuning=None):
     kernel launch (plain launches) for the kernel's average duration."""
     kw = {}
     if tuning:
-        kw = {k: tuning[k] for k in ("tile_r", "tile_z", "halo", "sort_interval", "lanes") if k in tuning}
+        kw = {k: tuning[k] for k in ("tile_r", "tile_z", "halo", "sort_interval", "lanes", "use_graph")
+              if k in tuning}
     sim = B.Sim(cfgs, mode=mode, **kw)
     ctx = sim.ctx
     n = len(cfgs)

@@ -146,7 +146,10 @@ typedef struct {
     int halo;                  /* LDS deposit-window halo in cells; 0 = default  */
     int sort_interval;         /* steps between tile sorts; 0 = default          */
     int chunk;                 /* max particles per work item; 0 = default       */
-    int use_graph;             /* 1: replay the step as a captured HIP graph     */
+    int use_graph;             /* 0: plain launches; 1: each sort cycle (and    */
+                               /* step kind) replayed as a captured HIP graph;  */
+                               /* 2: graphs until pic_autotune, which times     */
+                               /* both modes on its choice and keeps the faster */
     int device;                /* HIP device ordinal                             */
     void* stream;              /* hipStream_t to run on; NULL = a library stream */
     pic_allocator alloc;       /* alloc == NULL: hipMalloc/hipFree               */
@@ -366,11 +369,12 @@ int pic_auto_shift(double w_max);
  */
 pic_status pic_timing(pic_ctx* ctx, int enable, long long* launches, double* total_ms);
 
-/* pic_tuning -- the tile shape, halo, sort interval, chunk and particles per
- * lane and pass (1 or 2, see pic_run_cfg.lanes) in use; any pointer may be
- * NULL; zeros in the FP64 form. */
+/* pic_tuning -- the tile shape, halo, sort interval, chunk, particles per
+ * lane and pass (1 or 2, see pic_run_cfg.lanes) and launch mode (1: captured
+ * graphs, 0: plain launches) in use; any pointer may be NULL; zeros in the
+ * FP64 form. */
 pic_status pic_tuning(pic_ctx* ctx, int* tile_r, int* tile_z, int* halo, int* sort_interval,
-                      int* chunk, int* lanes);
+                      int* chunk, int* lanes, int* use_graph);
 
 /*
  * pic_retune -- FP32 form only: switch to tile_r x tile_z cell tiles, a
@@ -389,8 +393,10 @@ pic_status pic_retune(pic_ctx* ctx, int tile_r, int tile_z, int halo, int sort_i
  * candidate tile shapes, halos and sort intervals, for one and for two
  * particles per lane and pass (pic_run_cfg.lanes; about 20 trials each of
  * max(trial_steps, 2 sort intervals) steps each, after two intervals of
- * warm-up) and keep the fastest.  The trial steps advance the simulation
- * like any other steps.  cache_path (or NULL) names a text file of one JSON
+ * warm-up) and keep the fastest; with pic_run_cfg.use_graph = 2 it then
+ * times captured graphs against plain launches on that choice (twice each)
+ * and keeps the faster mode.  The trial steps advance the simulation like
+ * any other steps.  cache_path (or NULL) names a text file of one JSON
  * object per line keyed by a signature of the device and the workload
  * (meshes, live counts to a power of two): a hit applies the stored choice
  * without trials (*trials = 0), a miss appends the new result.  Outputs may

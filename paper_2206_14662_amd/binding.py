@@ -136,7 +136,7 @@ def lib():
     L.pic_auto_shift.argtypes = [C.c_double]
     L.pic_auto_shift.restype = C.c_int
     L.pic_timing.argtypes = [vp, C.c_int, _LL, _D]
-    L.pic_tuning.argtypes = [vp, _I, _I, _I, _I, _I, _I]
+    L.pic_tuning.argtypes = [vp, _I, _I, _I, _I, _I, _I, _I]
     L.pic_retune.argtypes = [vp, C.c_int, C.c_int, C.c_int, C.c_int]
     L.pic_autotune.argtypes = [vp, C.c_int, C.c_char_p, _I, _I, _I, _I, _D, _I]
     L.pic_reserve.argtypes = [vp, C.c_int, C.c_longlong]
@@ -231,7 +231,7 @@ class _TorchAllocator:
 # ---- the C calls, marshalled -----------------------------------------------
 
 def pic_init(instances, mode=PIC_MODE_FP64_PLAIN, device=0, stream=None, use_torch=True,
-             tile_r=0, tile_z=0, halo=0, sort_interval=0, chunk=0, use_graph=1,
+             tile_r=0, tile_z=0, halo=0, sort_interval=0, chunk=0, use_graph=2,
              capacity_factor=0.0, capacity_min=0, lanes=0):
     """Create a context for a list of instance dicts.  Returns (ctx, keep)
     where keep holds the callbacks that must outlive the context."""
@@ -393,9 +393,10 @@ def pic_timing(ctx, enable):
 
 
 def pic_tuning(ctx):
-    v = [C.c_int() for _ in range(6)]
+    v = [C.c_int() for _ in range(7)]
     _check(lib().pic_tuning(ctx, *[C.byref(x) for x in v]), ctx)
-    return dict(zip(("tile_r", "tile_z", "halo", "sort_interval", "chunk", "lanes"), [x.value for x in v]))
+    return dict(zip(("tile_r", "tile_z", "halo", "sort_interval", "chunk", "lanes", "use_graph"),
+                    [x.value for x in v]))
 
 
 def pic_retune(ctx, tile_r=0, tile_z=0, halo=-1, sort_interval=0):

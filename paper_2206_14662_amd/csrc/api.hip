@@ -1186,6 +1186,7 @@ extern "C" pic_status pic_init(const pic_run_cfg* run, const pic_instance_cfg* i
     if (run->capacity_factor < 0.0 || (run->capacity_factor > 0.0 && run->capacity_factor < 1.0))
         return fail(nullptr, PIC_EINVAL, "capacity_factor must be 0 or >= 1");
     if (run->lanes < 0 || run->lanes > 2) return fail(nullptr, PIC_EINVAL, "lanes must be 0, 1 or 2");
+    if (run->use_graph < 0 || run->use_graph > 2) return fail(nullptr, PIC_EINVAL, "use_graph must be 0, 1 or 2");
     for (int k = 0; k < run->n_instances; ++k) {
         std::string m = validate(inst[k]);
         if (!m.empty()) return fail(nullptr, PIC_EINVAL, "instance " + std::to_string(k) + ": " + m);
@@ -2000,7 +2001,7 @@ extern "C" pic_status pic_timing(pic_ctx* ctx, int enable, long long* launches, 
 }
 
 extern "C" pic_status pic_tuning(pic_ctx* ctx, int* tile_r, int* tile_z, int* halo,
-                                 int* sort_interval, int* chunk, int* lanes) {
+                                 int* sort_interval, int* chunk, int* lanes, int* use_graph) {
     if (!ctx) return PIC_EINVAL;
     if (ctx->mode != PIC_MODE_FP32_BATCHED) {
         if (tile_r) *tile_r = 0;
@@ -2009,9 +2010,10 @@ extern "C" pic_status pic_tuning(pic_ctx* ctx, int* tile_r, int* tile_z, int* ha
         if (sort_interval) *sort_interval = 0;
         if (chunk) *chunk = 0;
         if (lanes) *lanes = 0;
+        if (use_graph) *use_graph = 0;
         return PIC_OK;
     }
-    return f32_tuning(ctx, tile_r, tile_z, halo, sort_interval, chunk, lanes);
+    return f32_tuning(ctx, tile_r, tile_z, halo, sort_interval, chunk, lanes, use_graph);
 }
 
 extern "C" pic_status pic_retune(pic_ctx* ctx, int tile_r, int tile_z, int halo, int sort_interval) {

@@ -65,7 +65,7 @@ pic_status f32_get_particles(pic_ctx* ctx, int k, double* r, double* z, double* 
 pic_status f32_check(pic_ctx* ctx);
 long long f32_live_count(pic_ctx* ctx, int k, const long long* cnt);
 pic_status f32_tuning(pic_ctx* ctx, int* tile_r, int* tile_z, int* halo, int* sort_interval, int* chunk,
-                      int* lanes);
+                      int* lanes, int* use_graph);
 pic_status f32_retune(pic_ctx* ctx, int tile_r, int tile_z, int halo, int sort_interval);
 pic_status f32_reserve(pic_ctx* ctx, int k, long long slots);
 pic_status f32_autotune(pic_ctx* ctx, int trial_steps, const char* cache, int out[4], double* ms_out,

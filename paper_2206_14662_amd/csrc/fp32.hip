@@ -1592,6 +1592,7 @@ struct F32State {
     hipGraphExec_t g_step[4][2] = {{nullptr, nullptr}, {nullptr, nullptr}, {nullptr, nullptr}, {nullptr, nullptr}};
     hipGraphExec_t g_cycle[2] = {nullptr, nullptr};  // K steps from a sort to the next, per store
     bool graphs = false;
+    bool graph_auto = false;  // the autotuner chooses between graphs and plain launches
     int phase = 0;        // steps since the last sort
     bool counted = false; // the last step counted tile totals for a scatter
 };
@@ -1832,6 +1833,7 @@ pic_status f32_init(pic_ctx* ctx) {
     CK32(hipEventCreateWithFlags(&S->ev_out, hipEventDisableTiming));
     CK32(hipEventCreateWithFlags(&S->ev_snap, hipEventDisableTiming));
     S->graphs = run.use_graph != 0;
+    S->graph_auto = run.use_graph == 2;
     S->dF = pic_field_table(ctx);
     return PIC_OK;
 }
@@ -2285,7 +2287,7 @@ static std::string tune_signature(pic_ctx* ctx) {
     return sig;
 }
 
-static bool tune_lookup(const char* path, const std::string& sig, int v[4], int* lanes) {
+static bool tune_lookup(const char* path, const std::string& sig, int v[4], int* lanes, int* graphs) {
     FILE* f = path ? fopen(path, "r") : nullptr;
     if (!f) return false;
     char line[4096];
@@ -2306,6 +2308,9 @@ static bool tune_lookup(const char* path, const std::string& sig, int v[4], int*
             const char* lk = "\"lanes\": ";
             const size_t at = l.find(lk);
             *lanes = at == std::string::npos ? 1 : atoi(l.c_str() + at + strlen(lk));
+            const char* gk = "\"graphs\": ";
+            const size_t ag = l.find(gk);
+            *graphs = ag == std::string::npos ? -1 : atoi(l.c_str() + ag + strlen(gk));
         }
     }
     fclose(f);
@@ -2316,17 +2321,26 @@ pic_status f32_autotune(pic_ctx* ctx, int trial_steps, const char* cache, int ou
                         int* trials_out) {
     F32State* S = pic_get_f32(ctx);
     const std::string sig = tune_signature(ctx);
-    int v[4], lanes = 1;
-    if (tune_lookup(cache, sig, v, &lanes)) {
+    int v[4], lanes = 1, graphs = -1;
+    if (tune_lookup(cache, sig, v, &lanes, &graphs)) {
         pic_status st = reconfigure(ctx, lanes == 2 ? 2 : 1, v[0], v[1], v[2], v[3]);
         if (st != PIC_OK) return st;
+        if (S->graph_auto && graphs >= 0) S->graphs = graphs != 0;
         for (int i = 0; i < 4; ++i) out[i] = v[i];
         if (ms_out) *ms_out = 0.0;
         if (trials_out) *trials_out = 0;
         return PIC_OK;
     }
     hipStream_t s = pic_stream(ctx);
-    hipEvent_t e0, e1;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    struct EventPair {  // destroyed on every way out
+        hipEvent_t* a;
+        hipEvent_t* b;
+        ~EventPair() {
+            if (*a) (void)hipEventDestroy(*a);
+            if (*b) (void)hipEventDestroy(*b);
+        }
+    } guard{&e0, &e1};
     CK32(hipEventCreate(&e0));
     CK32(hipEventCreate(&e1));
     int trials = 0;
@@ -2429,11 +2443,36 @@ pic_status f32_autotune(pic_ctx* ctx, int trial_steps, const char* cache, int ou
             best_ms = sum[bc] / 2.0;
         }
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
     if (st != PIC_OK) return st;
     st = reconfigure(ctx, best[0], best[1], best[2], best[3], best[4]);
     if (st != PIC_OK) return st;
+    if (S->graph_auto) {
+        // the launch mode on the chosen tiles: captured graphs against plain
+        // launches, interleaved, twice each, per particle-step; the lower sum wins
+        const int K = best[4];
+        const int T = ((std::max(trial_steps, 2 * K) + K - 1) / K) * K;
+        double sum[2] = {0.0, 0.0};
+        for (int rep = 0; rep < 2; ++rep)
+            for (int g = 1; g >= 0; --g) {
+                S->graphs = g != 0;
+                st = f32_step(ctx, 2 * K);
+                if (st != PIC_OK) return st;
+                const long long ps0 = psteps();
+                CK32(hipEventRecord(e0, s));
+                st = f32_step(ctx, T);
+                if (st != PIC_OK) return st;
+                CK32(hipEventRecord(e1, s));
+                CK32(hipEventSynchronize(e1));
+                float t = 0.0f;
+                CK32(hipEventElapsedTime(&t, e0, e1));
+                sum[g] += (double)t / (double)std::max(1ll, psteps() - ps0);
+                ++trials;
+            }
+        S->graphs = sum[1] <= sum[0];
+        if (verbose)
+            fprintf(stderr, "autotune: graphs %.4g, plain launches %.4g ps per particle-step\n", sum[1] * 0.5e9,
+                    sum[0] * 0.5e9);
+    }
     for (int i = 0; i < 4; ++i) out[i] = best[i + 1];
     long long live = 0;
     (void)psteps();
@@ -2445,8 +2484,8 @@ pic_status f32_autotune(pic_ctx* ctx, int trial_steps, const char* cache, int ou
         FILE* f = fopen(cache, "a");
         if (f) {
             fprintf(f, "{\"sig\": \"%s\", \"tile_r\": %d, \"tile_z\": %d, \"halo\": %d, \"sort_interval\": %d, "
-                       "\"lanes\": %d, \"ms_per_step\": %.6f, \"trials\": %d}\n",
-                    sig.c_str(), best[1], best[2], best[3], best[4], best[0], best_ms, trials);
+                       "\"lanes\": %d, \"graphs\": %d, \"ms_per_step\": %.6f, \"trials\": %d}\n",
+                    sig.c_str(), best[1], best[2], best[3], best[4], best[0], S->graphs ? 1 : 0, best_ms, trials);
             fclose(f);
         }
     }
@@ -2564,9 +2603,10 @@ pic_status f32_check(pic_ctx* ctx) {
 }
 
 pic_status f32_tuning(pic_ctx* ctx, int* tile_r, int* tile_z, int* halo, int* sort_interval, int* chunk,
-                      int* lanes) {
+                      int* lanes, int* use_graph) {
     F32State* S = pic_get_f32(ctx);
     if (lanes) *lanes = S->lanes;
+    if (use_graph) *use_graph = S->graphs ? 1 : 0;
     if (tile_r) *tile_r = S->TR;
     if (tile_z) *tile_z = S->TZ;
     if (halo) *halo = S->halo;

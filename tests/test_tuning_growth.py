@@ -85,6 +85,13 @@ def test_autotune_picks_a_valid_choice_and_caches_it(tmp_path):
         assert t2[k] == t[k]
     # the launch shape the trials chose is cached and restored with the tiles
     assert lines[0]["lanes"] in (1, 2) and B.pic_tuning(h.ctx)["lanes"] == lines[0]["lanes"] == cur["lanes"]
+    # and so is the launch mode (graphs or plain launches), timed on that choice
+    assert lines[0]["graphs"] in (0, 1) and B.pic_tuning(h.ctx)["use_graph"] == lines[0]["graphs"] == cur["use_graph"]
+    h.close()
+    # an explicit launch mode is kept: the cached choice does not override it
+    h = B.Sim(cfgs, mode=F32, use_graph=1 - lines[0]["graphs"])
+    h.autotune(trial_steps=4, cache_path=cache)
+    assert B.pic_tuning(h.ctx)["use_graph"] == 1 - lines[0]["graphs"]
     h.close()
     # the last cached line of a signature wins: two particles per lane are restored as such
     with open(cache, "a") as f:
