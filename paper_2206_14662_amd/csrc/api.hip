@@ -729,8 +729,8 @@ pic_status pic_field_stage(pic_ctx* ctx, hipStream_t s) {
     }
     pic_status st = solve_tables(ctx, false, true, false, s);
     if (st != PIC_OK) return st;
-    CK(launch_efield_tab(ctx->dI, ctx->dF, 0, n, ctx->max_nodes, false, s));
-    CK(launch_sample_tab(ctx->dI, ctx->dF, n, ctx->dcnt, ctx->prep_ctl, s));
+    CK(launch_efield_tab(ctx->dI, ctx->dF, 0, n, ctx->max_nodes, false, s, ctx->dcnt));
+    CK(launch_commit(ctx->dI, ctx->dcnt, ctx->prep_ctl, n, s));
     return PIC_OK;
 }
 

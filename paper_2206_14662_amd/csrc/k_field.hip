@@ -501,16 +501,10 @@ __global__ void kf_phi_edges(const DevInst* __restrict__ It, const FieldDev* __r
     }
 }
 
-// E = -grad phi at the nodes (central inside, second-order one-sided on the
+// E = -grad phi at node n (central inside, second-order one-sided on the
 // edges); writes FP64 arrays and/or the packed FP32 {Er, Ez, Br, Bz} (the
 // static B half only with with_B).
-__global__ void kf_efield(const DevInst* __restrict__ It, const FieldDev* __restrict__ Ft,
-                          int inst_base, int with_B) {
-    const int inst = inst_base + blockIdx.y;
-    const DevInst& I = It[inst];
-    const FieldDev& F = Ft[inst];
-    const int n = blockIdx.x * blockDim.x + threadIdx.x;
-    if (I.frozen || n >= I.nodes) return;
+__device__ __forceinline__ void efield_node(const DevInst& I, const FieldDev& F, int n, bool with_B) {
     const int W = I.W, i = n / W, j = n - i * W;
     const double hr = 0.5 / I.dr, hz = 0.5 / I.dz;
     const double* P = F.phi;
@@ -531,37 +525,31 @@ __global__ void kf_efield(const DevInst* __restrict__ It, const FieldDev* __rest
     }
 }
 
-__global__ void kz_zero(long long* p, long long n) {
-    for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < n;
-         q += (long long)gridDim.x * blockDim.x)
-        p[q] = 0;
+// Diagnostics sample (every D steps): the density at node n into the
+// running spatial max mx and its charge into the time-average accumulator.
+__device__ __forceinline__ void sample_node(const DevInst& I, const FieldDev& F, int n, double& mx) {
+    double q = (double)F.Q[n];
+    double dens = (q * I.inv_two_S) / F.V[n];
+    mx = dens > mx ? dens : mx;
+    F.avg_acc[n] += q;
 }
 
-// Every D steps: spatial-max density into the running time max, the
-// time-average accumulator, and windowed wall currents.
-__global__ void ks_sample(const DevInst* __restrict__ It, const FieldDev* __restrict__ Ft, long long* cnt_base) {
-    const int inst = blockIdx.y;
-    const DevInst& I = It[inst];
-    const FieldDev& F = Ft[inst];
-    long long* cnt = cnt_base + (long long)inst * C_NCOUNT;
-    const int D = I.diag_D;
-    if ((cnt[C_STEP] + 1) % D != 0) return;
+// The rest of a sample in a 256-thread block (every thread calls it): the
+// block's max density into the time max (one device atomic, and only when
+// it exceeds the max seen so far); in the instance's first block the
+// windowed wall currents and their peaks.
+__device__ void sample_block(const DevInst& I, long long* cnt, double mx, bool first_block) {
     __shared__ double red[256];
-    double mx = 0.0;
-    for (int n = blockIdx.x * blockDim.x + threadIdx.x; n < I.nodes; n += gridDim.x * blockDim.x) {
-        double q = (double)F.Q[n];
-        double dens = (q * I.inv_two_S) / F.V[n];
-        mx = dens > mx ? dens : mx;
-        F.avg_acc[n] += q;
-    }
     red[threadIdx.x] = mx;
     __syncthreads();
     for (int s = blockDim.x / 2; s > 0; s >>= 1) {
         if (threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
         __syncthreads();
     }
-    if (threadIdx.x == 0 && red[0] > 0.0) atomic_max_pos_double(&cnt[C_PEAK], red[0]);
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (threadIdx.x == 0 && red[0] > 0.0 && red[0] > __longlong_as_double(cnt[C_PEAK]))
+        atomic_max_pos_double(&cnt[C_PEAK], red[0]);
+    if (first_block && threadIdx.x == 0) {
+        const int D = I.diag_D;
         cnt[C_NSAMP] += 1;
         double span = (double)D * I.dt;
         for (int w = 0; w < 4; ++w) {
@@ -575,6 +563,44 @@ __global__ void ks_sample(const DevInst* __restrict__ It, const FieldDev* __rest
         if (io > __longlong_as_double(cnt[C_PEAKI_OUT])) cnt[C_PEAKI_OUT] = __double_as_longlong(io);
         if (ii > __longlong_as_double(cnt[C_PEAKI_IN])) cnt[C_PEAKI_IN] = __double_as_longlong(ii);
     }
+}
+
+// Nodal E of every instance (blockIdx.y), one node per thread; with
+// cnt_base, also the diagnostics sample of the step on the same nodes (the
+// per-step form of ks_sample, saving its launch).
+__global__ void __launch_bounds__(256) kf_efield(const DevInst* __restrict__ It, const FieldDev* __restrict__ Ft,
+                                                 int inst_base, int with_B, long long* cnt_base) {
+    const int inst = inst_base + blockIdx.y;
+    const DevInst& I = It[inst];
+    const FieldDev& F = Ft[inst];
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (!I.frozen && n < I.nodes) efield_node(I, F, n, with_B != 0);
+    if (!cnt_base) return;
+    long long* cnt = cnt_base + (long long)inst * C_NCOUNT;
+    if ((cnt[C_STEP] + 1) % I.diag_D != 0) return;  // the same for the whole block
+    double mx = 0.0;
+    if (n < I.nodes) sample_node(I, F, n, mx);
+    sample_block(I, cnt, mx, blockIdx.x == 0);
+}
+
+__global__ void kz_zero(long long* p, long long n) {
+    for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < n;
+         q += (long long)gridDim.x * blockDim.x)
+        p[q] = 0;
+}
+
+// Every D steps: spatial-max density into the running time max, the
+// time-average accumulator, and windowed wall currents.
+__global__ void ks_sample(const DevInst* __restrict__ It, const FieldDev* __restrict__ Ft, long long* cnt_base) {
+    const int inst = blockIdx.y;
+    const DevInst& I = It[inst];
+    const FieldDev& F = Ft[inst];
+    long long* cnt = cnt_base + (long long)inst * C_NCOUNT;
+    if ((cnt[C_STEP] + 1) % I.diag_D != 0) return;
+    double mx = 0.0;
+    for (int n = blockIdx.x * blockDim.x + threadIdx.x; n < I.nodes; n += gridDim.x * blockDim.x)
+        sample_node(I, F, n, mx);
+    sample_block(I, cnt, mx, blockIdx.x == 0);
 }
 
 // End of step, one block: fold each instance's new electrons into its slot
@@ -824,10 +850,15 @@ hipError_t launch_solve_tab(const DevInst* It, const FieldDev* Ft, int inst_base
 }
 
 hipError_t launch_efield_tab(const DevInst* It, const FieldDev* Ft, int inst_base, int n_inst,
-                             long long max_nodes, bool with_B, hipStream_t s) {
+                             long long max_nodes, bool with_B, hipStream_t s, long long* cnt) {
     if (n_inst <= 0) return hipSuccess;
     dim3 g((unsigned)((max_nodes + 255) / 256), (unsigned)n_inst);
-    hipLaunchKernelGGL(kf_efield, g, dim3(256), 0, s, It, Ft, inst_base, with_B ? 1 : 0);
+    hipLaunchKernelGGL(kf_efield, g, dim3(256), 0, s, It, Ft, inst_base, with_B ? 1 : 0, cnt);
+    return hipGetLastError();
+}
+
+hipError_t launch_commit(const DevInst* It, long long* cnt, long long* ctl, int n_inst, hipStream_t s) {
+    hipLaunchKernelGGL(ks_commit, dim3(1), dim3(256), 0, s, It, cnt, ctl, n_inst);
     return hipGetLastError();
 }
 

@@ -434,14 +434,18 @@ hipError_t launch_zero_i64(long long* p, long long n, hipStream_t s);
 hipError_t launch_solve_tab(const DevInst* It, const FieldDev* Ft, int inst_base, int n_inst,
                             int max_nr, int max_nz, const double2* tw, int tw_n, int mode,
                             const double* bscale, bool edges, hipStream_t s);
+// cnt: the instances' counters (from instance 0) when the step's diagnostics
+// sample rides on the same launch, else NULL
 hipError_t launch_efield_tab(const DevInst* It, const FieldDev* Ft, int inst_base, int n_inst,
-                             long long max_nodes, bool with_B, hipStream_t s);
+                             long long max_nodes, bool with_B, hipStream_t s, long long* cnt = nullptr);
 // Diagnostics sample (every D steps), then the end of the step: counters
 // committed (slots += spawned, step += 1) and, when ctl is given, the next
 // FP32 step planned.
 hipError_t launch_sample_tab(const DevInst* It, const FieldDev* Ft, int n_inst, long long* cnt, long long* ctl,
                              hipStream_t s);
 hipError_t set_field_kernel_attrs(int max_nz);
+// the end of the step alone (after a sample taken by launch_efield_tab)
+hipError_t launch_commit(const DevInst* It, long long* cnt, long long* ctl, int n_inst, hipStream_t s);
 
 // Elliptic insert (insert.hip).  ins_build classifies the nodes, attaches
 // the outer hats, and assembles D on the host; an empty string means success.
