@@ -97,6 +97,9 @@ inline size_t fft_lds_bytes(int max_nz) { return sizeof(double2) * (size_t)(2 * 
 // span Ns reads y[j + r N/R], twiddles input r by exp(-2 pi i r k / (Ns R))
 // with k = j mod Ns, and writes output m to y[(j/Ns) Ns R + k + m Ns].
 // tw[t] = exp(-2 pi i t / tw_n) over the full circle, tw_n a multiple of N.
+// Only the first twiddle of a butterfly is read from the table; the others
+// are its powers, so a pass waits on one table read instead of R - 1 (the
+// powers round within a few ulp).
 template <int R>
 __device__ __forceinline__ void fft_pass(double2* y, int N, int Ns, const double2* __restrict__ tw, int tw_n) {
     constexpr int PER = (8 + R - 1) / R;
@@ -118,8 +121,13 @@ __device__ __forceinline__ void fft_pass(double2* y, int N, int Ns, const double
         if (j < nb) {
             const int k = j - (j / Ns) * Ns;
             double2* w = v + q * R;
+            const double2 w1 = tw[k * tscale];
+            double2 wp = w1;
 #pragma unroll
-            for (int r = 1; r < R; ++r) w[r] = cmul(w[r], tw[r * k * tscale]);
+            for (int r = 1; r < R; ++r) {
+                w[r] = cmul(w[r], wp);
+                wp = cmul(wp, w1);
+            }
             if (R == 8) dft8(w);
             else if (R == 5) dft5(w);
             else if (R == 4) dft4(w[0], w[1], w[2], w[3]);
