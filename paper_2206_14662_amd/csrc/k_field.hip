@@ -516,13 +516,17 @@ __device__ __forceinline__ void efield_node(const DevInst& I, const FieldDev& F,
     const int W = I.W, i = n / W, j = n - i * W;
     const double hr = 0.5 / I.dr, hz = 0.5 / I.dz;
     const double* P = F.phi;
-    double gr, gz;
-    if (i == 0) gr = (-3.0 * P[j] + 4.0 * P[W + j] - P[2 * W + j]) * hr;
-    else if (i == I.nr) gr = (3.0 * P[n] - 4.0 * P[n - W] + P[n - 2 * W]) * hr;
-    else gr = (P[n + W] - P[n - W]) * hr;
-    if (j == 0) gz = (-3.0 * P[n] + 4.0 * P[n + 1] - P[n + 2]) * hz;
-    else if (j == I.nz) gz = (3.0 * P[n] - 4.0 * P[n - 1] + P[n - 2]) * hz;
-    else gz = (P[n + 1] - P[n - 1]) * hz;
+    // every stencil value is read unconditionally (unused ones at n), then
+    // the edge or interior difference is selected
+    const bool r0 = i == 0, r1 = i == I.nr, z0 = j == 0, z1 = j == I.nz;
+    const double a0 = P[r0 ? j : (r1 ? n : n + W)];
+    const double a1 = P[r0 ? W + j : n - W];
+    const double a2 = P[r0 ? 2 * W + j : (r1 ? n - 2 * W : n)];
+    const double b0 = P[(z0 || z1) ? n : n + 1];
+    const double b1 = P[z0 ? n + 1 : n - 1];
+    const double b2 = P[z0 ? n + 2 : (z1 ? n - 2 : n)];
+    const double gr = r0 ? (-3.0 * a0 + 4.0 * a1 - a2) * hr : (r1 ? (3.0 * a0 - 4.0 * a1 + a2) * hr : (a0 - a1) * hr);
+    const double gz = z0 ? (-3.0 * b0 + 4.0 * b1 - b2) * hz : (z1 ? (3.0 * b0 - 4.0 * b1 + b2) * hz : (b0 - b1) * hz);
     if (F.Er) {
         F.Er[n] = -gr;
         F.Ez[n] = -gz;
