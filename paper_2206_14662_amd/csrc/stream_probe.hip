@@ -124,6 +124,41 @@ __global__ void __launch_bounds__(1024) sp_aosoa8_pers(unsigned int* p, long lon
     }
 }
 
+// Seven-word blocks in the particle kernel's two launch shapes: U elements
+// per lane and pass, 1024-thread workgroups over statically balanced ranges
+// of whole blocks (U = 1: two workgroups per CU; U = 2: one, every element's
+// loads issued before any element's stores).
+template <int U>
+__global__ void __launch_bounds__(1024) sp_aosoa_pers(unsigned int* p, long long n) {
+    const long long G = gridDim.x, w = blockIdx.x;
+    const long long blocks = (n + 63) / 64;
+    const long long b0 = w * blocks / G, b1 = (w + 1) * blocks / G;
+    const long long end = min(b1 * 64, n);
+    for (long long base = b0 * 64; base < end; base += 1024 * U) {
+        float a[U], b[U], c[U], d[U], e[U];
+        unsigned long long k[U];
+        unsigned int* q[U];
+        bool in[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const long long i = base + u * 1024 + threadIdx.x;
+            in[u] = i < end;
+            q[u] = p + ((in[u] ? i : base) >> 6) * 448 + ((in[u] ? i : base) & 63);
+            a[u] = __uint_as_float(q[u][0]); b[u] = __uint_as_float(q[u][64]); c[u] = __uint_as_float(q[u][128]);
+            d[u] = __uint_as_float(q[u][192]); e[u] = __uint_as_float(q[u][256]);
+            k[u] = ((unsigned long long)q[u][384] << 32) | q[u][320];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            touch(a[u], b[u], c[u], d[u], e[u], k[u]);
+            if (in[u]) {
+                q[u][0] = __float_as_uint(a[u]); q[u][64] = __float_as_uint(b[u]); q[u][128] = __float_as_uint(c[u]);
+                q[u][192] = __float_as_uint(d[u]); q[u][256] = __float_as_uint(e[u]);
+            }
+        }
+    }
+}
+
 __global__ void sp_fill(unsigned int* p, long long n, unsigned int v) {
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
         p[i] = v + (unsigned int)(i & 0xff);
@@ -184,6 +219,14 @@ extern "C" double sp_run(int pattern, long long n, int reps, double* gbytes) {
                 break;
             case 7:
                 hipLaunchKernelGGL(sp_aosoa8_pers, dim3((unsigned int)cus * 2), dim3(1024), 0, 0, buf, n);
+                bytes = 48.0 * (double)n;
+                break;
+            case 8:
+                hipLaunchKernelGGL(sp_aosoa_pers<1>, dim3((unsigned int)cus * 2), dim3(1024), 0, 0, buf, n);
+                bytes = 48.0 * (double)n;
+                break;
+            case 9:
+                hipLaunchKernelGGL(sp_aosoa_pers<2>, dim3((unsigned int)cus), dim3(1024), 0, 0, buf, n);
                 bytes = 48.0 * (double)n;
                 break;
             default:

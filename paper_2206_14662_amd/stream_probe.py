@@ -10,7 +10,8 @@ import json
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-PATTERNS = ("copy", "read6", "write5", "soa", "soa_pers", "aosoa", "aosoa8", "aosoa8_pers")
+PATTERNS = ("copy", "read6", "write5", "soa", "soa_pers", "aosoa", "aosoa8", "aosoa8_pers", "aosoa_pers",
+            "aosoa_pers2")
 
 
 def run(n=128_000_000, reps=10):
