@@ -81,6 +81,7 @@ __device__ __forceinline__ void gbl_add(gbl_u64* p, unsigned long long v) {
 // keep an array of their own.
 constexpr long long kBlkSlots = 64;
 constexpr long long kBlkWords = 448;   // 4-byte words per block
+constexpr long long kDynUnit = 32768;  // particles per unit of a plain step's shared last part
 constexpr long long kBlkBytes = 4 * kBlkWords;
 struct PSet {
     unsigned int* b = nullptr;
@@ -104,7 +105,8 @@ struct PSet {
 };
 
 
-// control block: [1] particles to push this step (sorted + tails), [2] sorted
+// control block: [0] units of the shared last part handed out this step
+// (plain steps), [1] particles to push this step (sorted + tails), [2] sorted
 // particles over all instances, [3] collision events queued this step,
 // [4] queue overflow flag, [5 .. 5+n_inst] prefix of the instances' tail counts
 
@@ -873,201 +875,223 @@ __device__ __forceinline__ void particles_body(const KArgs& A) {
     // neighbouring tile and the sorting step reserves its destinations from
     // that record instead of reading the positions a second time.
     int kc = 0;
-    for (int part = 0; part < 2; ++part) {
-        const long long n_part = part ? total - nsorted : nsorted;
-        const long long per = n_part / G, rmd = n_part % G;
-        long long v = (part ? nsorted : 0ll) + wg * per + min(wg, rmd);
-        const long long vend = v + per + (wg < rmd ? 1 : 0);
-        while (v < vend) {
-            if (tid < 64) {
-                if (v < nsorted) {
-                    const int t = wave_search(A.vtile, A.n_tiles, v);
-                    if (tid == 0) {
-                        const long long tv = A.vtile[t], tv1 = A.vtile[t + 1];
-                        const int4 ti = A.tile_info[t];
-                        s_start = A.tile_start[t] + (v - tv);
-                        s_count = (int)min(min(vend, tv1) - v, (long long)A.C);
-                        s_inst = ti.x;
-                        s_tr0 = ti.y * A.TR;
-                        s_tz0 = ti.z * A.TZ;
-                    }
-                } else {
-                    const long long u = v - nsorted;
-                    const long long* tb = A.ctl + CTL_TAIL;
-                    const int k = wave_search(tb, A.n_inst, u);
-                    if (tid == 0) {
-                        const long long* cj = A.cnt + (long long)k * C_NCOUNT;
-                        s_start = A.It[k].p_off + cj[C_LIVE_SORTED] + (u - tb[k]);
-                        s_count = (int)min(min(vend - v, tb[k + 1] - u), (long long)A.C);
-                        s_inst = k;
-                        s_tr0 = -1;
-                        s_tz0 = -1;
-                    }
-                }
+    // Plain steps hand out the last twelfth of the sorted particles in units
+    // of kDynUnit from a device counter (ctl[CTL_WORK], cleared at every step
+    // end) once a workgroup's own ranges are done, so the workgroups that run
+    // faster take more of it and all finish together; the counting and
+    // sorting steps keep the static cut their records depend on.
+    constexpr bool DYN = !COUNT && !SCATTER;
+    const long long n_dyn = DYN ? nsorted / 12 : 0;
+    __shared__ long long s_unit;
+    for (int part = 0; part < (DYN ? 3 : 2); ++part) {
+        for (;;) {
+            long long v, vend;
+            if (part < 2) {
+                const long long n_part = part ? total - nsorted : nsorted - n_dyn;
+                const long long per = n_part / G, rmd = n_part % G;
+                v = (part ? nsorted : 0ll) + wg * per + min(wg, rmd);
+                vend = v + per + (wg < rmd ? 1 : 0);
+            } else {
+                if (tid == 0) s_unit = (long long)atomicAdd((unsigned long long*)&A.ctl[CTL_WORK], 1ull);
+                __syncthreads();
+                const long long a = nsorted - n_dyn + s_unit * kDynUnit;
+                __syncthreads();
+                if (a >= nsorted) break;
+                v = a;
+                vend = min(a + kDynUnit, nsorted);
             }
-            if (SCATTER && tid < 9) s_bcnt[tid] = 0u;
-            if (COUNT && tid < 9) s_ccnt[tid] = 0u;
-            if (tid < SC_N) s_ctr[tid] = 0ull;
-            if (tid == SC_N) s_qn = 0u;
-            __syncthreads();
-            const int count = __builtin_amdgcn_readfirstlane(s_count);
-            v += count;
-            const long long start = s_start;
-            const int inst = __builtin_amdgcn_readfirstlane(s_inst);
-            const int tr0 = __builtin_amdgcn_readfirstlane(s_tr0), tz0 = __builtin_amdgcn_readfirstlane(s_tz0);
-            const DevInst& I = A.It[inst];
-            const FieldDev& F = A.Ft[inst];
-            long long* cnt = A.cnt + (long long)inst * C_NCOUNT;
-            const unsigned int step = (unsigned int)cnt[C_STEP];
-            const PSet out = SCATTER ? A.out : A.p;
-            const int W = I.W;
-            const bool win = tr0 >= 0;
-            const bool rec = win && kc < A.crec_max;
-            const long long rbase = (wg * A.crec_max + kc) * 9;
-            if (win) ++kc;
-            const int ti_c = win ? tr0 / A.TR : 0, tj_c = win ? tz0 / A.TZ : 0;
-            int i0 = 0, i1 = -1, j0 = 0, j1 = -1, ww = 1;
-            if (win) {
-                i0 = max(tr0 - A.halo, 0);
-                i1 = min(tr0 + A.TR + A.halo, I.nr);
-                j0 = max(tz0 - A.halo, 0);
-                j1 = min(tz0 + A.TZ + A.halo, I.nz);
-                ww = j1 - j0 + 1;
-                const int nwin = (i1 - i0 + 1) * ww;
-                for (int t = tid; t < nwin; t += kPWG) {
-                    int a = t / ww, b = t - a * ww;
-                    sEB[t] = as_gbl(F.EB)[(long long)(i0 + a) * W + (j0 + b)];
-                    sQ[t] = 0ull;
-                }
-                if (CUB) {
-                    // ghosted nodes i0 .. i1 + 2, j0 .. j1 + 2 (physical i - 1)
-                    const int w3 = ww + 2, nwin3 = (i1 - i0 + 3) * w3, WX = I.nz + 3;
-                    for (int t = tid; t < nwin3; t += kPWG) {
-                        int a = t / w3, b = t - a * w3;
-                        sC[t] = ((gbl_f32*)F.cxf)[(long long)(i0 + a) * WX + (j0 + b)];
-                        sQx[t] = 0ull;
+            while (v < vend) {
+                if (tid < 64) {
+                    if (v < nsorted) {
+                        const int t = wave_search(A.vtile, A.n_tiles, v);
+                        if (tid == 0) {
+                            const long long tv = A.vtile[t], tv1 = A.vtile[t + 1];
+                            const int4 ti = A.tile_info[t];
+                            s_start = A.tile_start[t] + (v - tv);
+                            s_count = (int)min(min(vend, tv1) - v, (long long)A.C);
+                            s_inst = ti.x;
+                            s_tr0 = ti.y * A.TR;
+                            s_tz0 = ti.z * A.TZ;
+                        }
+                    } else {
+                        const long long u = v - nsorted;
+                        const long long* tb = A.ctl + CTL_TAIL;
+                        const int k = wave_search(tb, A.n_inst, u);
+                        if (tid == 0) {
+                            const long long* cj = A.cnt + (long long)k * C_NCOUNT;
+                            s_start = A.It[k].p_off + cj[C_LIVE_SORTED] + (u - tb[k]);
+                            s_count = (int)min(min(vend - v, tb[k + 1] - u), (long long)A.C);
+                            s_inst = k;
+                            s_tr0 = -1;
+                            s_tz0 = -1;
+                        }
                     }
                 }
-            }
-            if (SCATTER && win) {
-                // pass 1: destinations of this chunk's particles per neighbouring
-                // tile, unless the counting step recorded them
-                const bool from_rec = !COUNT && rec;
-                const LocalInst L1 = local_inst(I);
-                const int lead = (int)(start & 63);
-                for (int base = from_rec ? count : -lead; base < count; base += kPWG) {
-                    const int q = base + tid;
-                    const bool in = q >= 0 && q < count;
-                    const long long p = start + (in ? q : 0);
-                    const float r = A.p.r(p), z = A.p.z(p);
-                    int bkt = -1;
-                    if (in && r >= 0.0f) {
-                        int i, j;
-                        float fr, fz;
-                        cell_of(L1, r, z, i, j, fr, fz);
-                        int dr = i / A.TR - ti_c, dz = j / A.TZ - tj_c;
-                        if (dr >= -1 && dr <= 1 && dz >= -1 && dz <= 1) bkt = (dr + 1) * 3 + (dz + 1);
-                    }
-                    wave_aggregate<false>(bkt >= 0, bkt, [&](int k, unsigned int n) {
-                        atomicAdd(&s_bcnt[k], n);
-                        return 0u;
-                    });
-                }
-                if (!from_rec) __syncthreads();
-                if (tid < 9) {
-                    unsigned int n = from_rec ? A.crec[rbase + tid] : s_bcnt[tid];
-                    if (n) {
-                        int t = I.tile_off + (ti_c + tid / 3 - 1) * I.ntz + (tj_c + tid % 3 - 1);
-                        s_bbase[tid] = atomicAdd(&A.tile_fill[t], n);
-                    }
-                    s_bcnt[tid] = 0u;
-                }
-            }
-            __syncthreads();
-            unsigned int c_push = 0;
-            ChunkCtx X;
-            X.L = local_inst(I);
-            X.sEB = sEB; X.sQ = sQ; X.s_ctr = s_ctr; X.s_bcnt = s_bcnt; X.s_bbase = s_bbase; X.s_ccnt = s_ccnt;
-            X.s_qn = &s_qn; X.s_q = s_q;
-            X.out = out; X.EB = F.EB; X.Q = F.Q; X.Qw = F.Qw;
-            X.inst = inst; X.ti_c = ti_c; X.tj_c = tj_c; X.i0 = i0; X.i1 = i1; X.j0 = j0; X.j1 = j1; X.ww = ww;
-            X.win = win; X.step = step;
-            X.sC = sC; X.sQx = sQx; X.cxf = F.cxf; X.Qx = F.Qx; X.WX = I.nz + 3;
-            // U particles per lane per pass (their loads are all in flight before
-            // any is processed, and their arithmetic interleaves).  Passes start
-            // on a 64-slot boundary so that every wave's loads and stores cover
-            // whole aligned lines; lanes before the chunk idle.
-            const int lead = (int)(start & 63);
-            const float wu = X.L.w_uni;
-            for (int base = -lead; base < count; base += U * kPWG) {
-                long long pp[U];
-                bool inr[U];
-                float r[U], z[U], vr[U], vt[U], vz[U], w[U];
-                unsigned long long key[U];
-#pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    const int q = base + u * kPWG + tid;
-                    inr[u] = q >= 0 && q < count;
-                    pp[u] = start + (inr[u] ? q : 0);
-                    r[u] = A.p.r(pp[u]);
-                    z[u] = A.p.z(pp[u]);
-                    vr[u] = A.p.vr(pp[u]);
-                    vt[u] = A.p.vt(pp[u]);
-                    vz[u] = A.p.vz(pp[u]);
-                    w[u] = wu != 0.0f ? wu : A.p.w(pp[u]);
-                    key[u] = A.p.key(pp[u]);
-                }
-#pragma unroll
-                for (int u = 0; u < U; ++u)
-                    push_particle<COUNT, SCATTER, INS, CUB>(A, X, pp[u], inr[u], r[u], z[u], vr[u], vt[u], vz[u], w[u], key[u],
-                                                  c_push);
-            }
-            flush_counter(&cnt[C_PSTEPS], (unsigned long long)c_push);
-            __syncthreads();
-            if (tid < SC_N) {
-                const unsigned long long v = s_ctr[tid];
-                if (v) atomicAdd((unsigned long long*)&cnt[kCounterOf[tid]], v);
-            }
-            // the chunk's queued events: one device reservation
-            const unsigned int q_all = s_qn;
-            const unsigned int q_lds = min(q_all, (unsigned int)kLQ);
-            if (tid == SC_N) {
-                s_qbase = q_lds ? (long long)atomicAdd((unsigned long long*)&A.ctl[CTL_QCOUNT], (unsigned long long)q_lds)
-                                : 0ll;
-            }
-            if (COUNT && win && tid < 9) {
-                const unsigned int v = s_ccnt[tid];
-                if (v) atomicAdd(&A.cnt_out[I.tile_off + (ti_c + tid / 3 - 1) * I.ntz + (tj_c + tid % 3 - 1)], v);
-                if (!SCATTER && rec) A.crec[rbase + tid] = v;
-            }
-            __syncthreads();
-            for (unsigned int t = tid; t < q_lds; t += kPWG) {
-                const long long qi = s_qbase + t;
-                if (qi < A.qcap) A.queue[qi] = s_q[t];
-                else A.ctl[CTL_QOVER] = 1;
-            }
-            if (win) {
-                const int nwin = (i1 - i0 + 1) * ww;
-                gbl_u64* Qg = as_gbl(F.Q);
-                for (int t = tid; t < nwin; t += kPWG) {
-                    const unsigned long long v = sQ[t];
-                    if (v != 0ull) {
+                if (SCATTER && tid < 9) s_bcnt[tid] = 0u;
+                if (COUNT && tid < 9) s_ccnt[tid] = 0u;
+                if (tid < SC_N) s_ctr[tid] = 0ull;
+                if (tid == SC_N) s_qn = 0u;
+                __syncthreads();
+                const int count = __builtin_amdgcn_readfirstlane(s_count);
+                v += count;
+                const long long start = s_start;
+                const int inst = __builtin_amdgcn_readfirstlane(s_inst);
+                const int tr0 = __builtin_amdgcn_readfirstlane(s_tr0), tz0 = __builtin_amdgcn_readfirstlane(s_tz0);
+                const DevInst& I = A.It[inst];
+                const FieldDev& F = A.Ft[inst];
+                long long* cnt = A.cnt + (long long)inst * C_NCOUNT;
+                const unsigned int step = (unsigned int)cnt[C_STEP];
+                const PSet out = SCATTER ? A.out : A.p;
+                const int W = I.W;
+                const bool win = tr0 >= 0;
+                const bool rec = win && kc < A.crec_max;
+                const long long rbase = (wg * A.crec_max + kc) * 9;
+                if (win) ++kc;
+                const int ti_c = win ? tr0 / A.TR : 0, tj_c = win ? tz0 / A.TZ : 0;
+                int i0 = 0, i1 = -1, j0 = 0, j1 = -1, ww = 1;
+                if (win) {
+                    i0 = max(tr0 - A.halo, 0);
+                    i1 = min(tr0 + A.TR + A.halo, I.nr);
+                    j0 = max(tz0 - A.halo, 0);
+                    j1 = min(tz0 + A.TZ + A.halo, I.nz);
+                    ww = j1 - j0 + 1;
+                    const int nwin = (i1 - i0 + 1) * ww;
+                    for (int t = tid; t < nwin; t += kPWG) {
                         int a = t / ww, b = t - a * ww;
-                        gbl_add(&Qg[(long long)(i0 + a) * W + (j0 + b)], v);
+                        sEB[t] = as_gbl(F.EB)[(long long)(i0 + a) * W + (j0 + b)];
+                        sQ[t] = 0ull;
+                    }
+                    if (CUB) {
+                        // ghosted nodes i0 .. i1 + 2, j0 .. j1 + 2 (physical i - 1)
+                        const int w3 = ww + 2, nwin3 = (i1 - i0 + 3) * w3, WX = I.nz + 3;
+                        for (int t = tid; t < nwin3; t += kPWG) {
+                            int a = t / w3, b = t - a * w3;
+                            sC[t] = ((gbl_f32*)F.cxf)[(long long)(i0 + a) * WX + (j0 + b)];
+                            sQx[t] = 0ull;
+                        }
                     }
                 }
-                if (CUB) {
-                    const int w3 = ww + 2, nwin3 = (i1 - i0 + 3) * w3, WX = I.nz + 3;
-                    gbl_u64* Qx = as_gbl(F.Qx);
-                    for (int t = tid; t < nwin3; t += kPWG) {
-                        const unsigned long long v = sQx[t];
+                if (SCATTER && win) {
+                    // pass 1: destinations of this chunk's particles per neighbouring
+                    // tile, unless the counting step recorded them
+                    const bool from_rec = !COUNT && rec;
+                    const LocalInst L1 = local_inst(I);
+                    const int lead = (int)(start & 63);
+                    for (int base = from_rec ? count : -lead; base < count; base += kPWG) {
+                        const int q = base + tid;
+                        const bool in = q >= 0 && q < count;
+                        const long long p = start + (in ? q : 0);
+                        const float r = A.p.r(p), z = A.p.z(p);
+                        int bkt = -1;
+                        if (in && r >= 0.0f) {
+                            int i, j;
+                            float fr, fz;
+                            cell_of(L1, r, z, i, j, fr, fz);
+                            int dr = i / A.TR - ti_c, dz = j / A.TZ - tj_c;
+                            if (dr >= -1 && dr <= 1 && dz >= -1 && dz <= 1) bkt = (dr + 1) * 3 + (dz + 1);
+                        }
+                        wave_aggregate<false>(bkt >= 0, bkt, [&](int k, unsigned int n) {
+                            atomicAdd(&s_bcnt[k], n);
+                            return 0u;
+                        });
+                    }
+                    if (!from_rec) __syncthreads();
+                    if (tid < 9) {
+                        unsigned int n = from_rec ? A.crec[rbase + tid] : s_bcnt[tid];
+                        if (n) {
+                            int t = I.tile_off + (ti_c + tid / 3 - 1) * I.ntz + (tj_c + tid % 3 - 1);
+                            s_bbase[tid] = atomicAdd(&A.tile_fill[t], n);
+                        }
+                        s_bcnt[tid] = 0u;
+                    }
+                }
+                __syncthreads();
+                unsigned int c_push = 0;
+                ChunkCtx X;
+                X.L = local_inst(I);
+                X.sEB = sEB; X.sQ = sQ; X.s_ctr = s_ctr; X.s_bcnt = s_bcnt; X.s_bbase = s_bbase; X.s_ccnt = s_ccnt;
+                X.s_qn = &s_qn; X.s_q = s_q;
+                X.out = out; X.EB = F.EB; X.Q = F.Q; X.Qw = F.Qw;
+                X.inst = inst; X.ti_c = ti_c; X.tj_c = tj_c; X.i0 = i0; X.i1 = i1; X.j0 = j0; X.j1 = j1; X.ww = ww;
+                X.win = win; X.step = step;
+                X.sC = sC; X.sQx = sQx; X.cxf = F.cxf; X.Qx = F.Qx; X.WX = I.nz + 3;
+                // U particles per lane per pass (their loads are all in flight before
+                // any is processed, and their arithmetic interleaves).  Passes start
+                // on a 64-slot boundary so that every wave's loads and stores cover
+                // whole aligned lines; lanes before the chunk idle.
+                const int lead = (int)(start & 63);
+                const float wu = X.L.w_uni;
+                for (int base = -lead; base < count; base += U * kPWG) {
+                    long long pp[U];
+                    bool inr[U];
+                    float r[U], z[U], vr[U], vt[U], vz[U], w[U];
+                    unsigned long long key[U];
+#pragma unroll
+                    for (int u = 0; u < U; ++u) {
+                        const int q = base + u * kPWG + tid;
+                        inr[u] = q >= 0 && q < count;
+                        pp[u] = start + (inr[u] ? q : 0);
+                        r[u] = A.p.r(pp[u]);
+                        z[u] = A.p.z(pp[u]);
+                        vr[u] = A.p.vr(pp[u]);
+                        vt[u] = A.p.vt(pp[u]);
+                        vz[u] = A.p.vz(pp[u]);
+                        w[u] = wu != 0.0f ? wu : A.p.w(pp[u]);
+                        key[u] = A.p.key(pp[u]);
+                    }
+#pragma unroll
+                    for (int u = 0; u < U; ++u)
+                        push_particle<COUNT, SCATTER, INS, CUB>(A, X, pp[u], inr[u], r[u], z[u], vr[u], vt[u], vz[u], w[u], key[u],
+                                                      c_push);
+                }
+                flush_counter(&cnt[C_PSTEPS], (unsigned long long)c_push);
+                __syncthreads();
+                if (tid < SC_N) {
+                    const unsigned long long v = s_ctr[tid];
+                    if (v) atomicAdd((unsigned long long*)&cnt[kCounterOf[tid]], v);
+                }
+                // the chunk's queued events: one device reservation
+                const unsigned int q_all = s_qn;
+                const unsigned int q_lds = min(q_all, (unsigned int)kLQ);
+                if (tid == SC_N) {
+                    s_qbase = q_lds ? (long long)atomicAdd((unsigned long long*)&A.ctl[CTL_QCOUNT], (unsigned long long)q_lds)
+                                    : 0ll;
+                }
+                if (COUNT && win && tid < 9) {
+                    const unsigned int v = s_ccnt[tid];
+                    if (v) atomicAdd(&A.cnt_out[I.tile_off + (ti_c + tid / 3 - 1) * I.ntz + (tj_c + tid % 3 - 1)], v);
+                    if (!SCATTER && rec) A.crec[rbase + tid] = v;
+                }
+                __syncthreads();
+                for (unsigned int t = tid; t < q_lds; t += kPWG) {
+                    const long long qi = s_qbase + t;
+                    if (qi < A.qcap) A.queue[qi] = s_q[t];
+                    else A.ctl[CTL_QOVER] = 1;
+                }
+                if (win) {
+                    const int nwin = (i1 - i0 + 1) * ww;
+                    gbl_u64* Qg = as_gbl(F.Q);
+                    for (int t = tid; t < nwin; t += kPWG) {
+                        const unsigned long long v = sQ[t];
                         if (v != 0ull) {
-                            int a = t / w3, b = t - a * w3;
-                            gbl_add(&Qx[(long long)(i0 + a) * WX + (j0 + b)], v);
+                            int a = t / ww, b = t - a * ww;
+                            gbl_add(&Qg[(long long)(i0 + a) * W + (j0 + b)], v);
+                        }
+                    }
+                    if (CUB) {
+                        const int w3 = ww + 2, nwin3 = (i1 - i0 + 3) * w3, WX = I.nz + 3;
+                        gbl_u64* Qx = as_gbl(F.Qx);
+                        for (int t = tid; t < nwin3; t += kPWG) {
+                            const unsigned long long v = sQx[t];
+                            if (v != 0ull) {
+                                int a = t / w3, b = t - a * w3;
+                                gbl_add(&Qx[(long long)(i0 + a) * WX + (j0 + b)], v);
+                            }
                         }
                     }
                 }
             }
+            if (part < 2) break;
         }
     }
 }

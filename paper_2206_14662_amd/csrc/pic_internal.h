@@ -138,13 +138,14 @@ enum Counter {
 };
 
 // Control words of the batched FP32 step (device array, FP32 form only):
-// particles pushed this step, of which tile-sorted, real collision events
-// queued, queue overflow flag, then per-instance exclusive prefix of the
-// tail counts (electrons created since the last sort).
-enum { CTL_TOTAL = 1, CTL_SORTED = 2, CTL_QCOUNT = 3, CTL_QOVER = 4, CTL_TAIL = 5 };
+// work units handed out in a plain step, particles pushed this step, of
+// which tile-sorted, real collision events queued, queue overflow flag, then
+// per-instance exclusive prefix of the tail counts (electrons created since
+// the last sort).
+enum { CTL_WORK = 0, CTL_TOTAL = 1, CTL_SORTED = 2, CTL_QCOUNT = 3, CTL_QOVER = 4, CTL_TAIL = 5 };
 
 // Plan of the coming step from the committed counters: tail prefix, total,
-// an empty collision queue.  Every thread of one block (at most 256
+// an empty collision queue, no work units handed out.  Every thread of one block (at most 256
 // threads) calls it; the prefix is an LDS scan over up to blockDim
 // instances at a time.
 __device__ inline void prep_tails_block(long long* ctl, const long long* cnt, int n_inst) {
@@ -155,6 +156,7 @@ __device__ inline void prep_tails_block(long long* ctl, const long long* cnt, in
     if (t == 0) {
         tb[0] = 0;
         ctl[CTL_QCOUNT] = 0;
+        ctl[CTL_WORK] = 0;
         s_carry = 0;
     }
     for (int k0 = 0; k0 < n_inst; k0 += nt) {
