@@ -880,8 +880,10 @@ __device__ __forceinline__ void particles_body(const KArgs& A) {
     // end) once a workgroup's own ranges are done, so the workgroups that run
     // faster take more of it and all finish together; the counting and
     // sorting steps keep the static cut their records depend on.
+    // (Only when a workgroup's share holds at least two units: on small
+    // workloads a unit would outweigh the static shares.)
     constexpr bool DYN = !COUNT && !SCATTER;
-    const long long n_dyn = DYN ? nsorted / 12 : 0;
+    const long long n_dyn = DYN && nsorted >= 2 * kDynUnit * G ? nsorted / 12 : 0;
     __shared__ long long s_unit;
     for (int part = 0; part < (DYN ? 3 : 2); ++part) {
         for (;;) {
