@@ -1113,6 +1113,14 @@ __global__ void __launch_bounds__(kPWG) __attribute__((amdgpu_waves_per_eu(4, 4)
     particles_body<MODE, 2>(A);
 }
 
+// The elliptic insert's variants with one particle per lane: their band
+// test and band deposit spill 11-25 registers at 64, so they take up to 128
+// registers and one workgroup per CU (gun8: 1.83 -> 1.68 ms per launch).
+template <int MODE>
+__global__ void __launch_bounds__(kPWG) k_particles_ins(KArgs A) {
+    particles_body<MODE, 1>(A);
+}
+
 // Cubic shapes: the 16-node gather and deposit keep their values in up to
 // 128 registers (one workgroup per CU) instead of spilling.
 template <int MODE>
@@ -1548,10 +1556,10 @@ ParticleKernel particle_kernel(int v, int lanes) {
         case 1: return k_particles<1>;
         case 2: return k_particles<2>;
         case 3: return k_particles<3>;
-        case 4: return k_particles<4>;
-        case 5: return k_particles<5>;
-        case 6: return k_particles<6>;
-        case 7: return k_particles<7>;
+        case 4: return k_particles_ins<4>;
+        case 5: return k_particles_ins<5>;
+        case 6: return k_particles_ins<6>;
+        case 7: return k_particles_ins<7>;
         case 8: return k_particles3<0>;
         case 9: return k_particles3<1>;
         case 10: return k_particles3<2>;
