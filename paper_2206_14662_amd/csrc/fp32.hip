@@ -1113,9 +1113,10 @@ __global__ void __launch_bounds__(kPWG) __attribute__((amdgpu_waves_per_eu(4, 4)
     particles_body<MODE, 2>(A);
 }
 
-// The elliptic insert's variants with one particle per lane: their band
-// test and band deposit spill 11-25 registers at 64, so they take up to 128
-// registers and one workgroup per CU (gun8: 1.83 -> 1.68 ms per launch).
+// The elliptic insert's plain step with one particle per lane: its band
+// test and band deposit spill 11 registers at 64, so it takes up to 128
+// registers and one workgroup per CU; its counting and sorting steps keep
+// two workgroups per CU (their spills cost less than half the workgroups).
 template <int MODE>
 __global__ void __launch_bounds__(kPWG) k_particles_ins(KArgs A) {
     particles_body<MODE, 1>(A);
@@ -1557,9 +1558,9 @@ ParticleKernel particle_kernel(int v, int lanes) {
         case 2: return k_particles<2>;
         case 3: return k_particles<3>;
         case 4: return k_particles_ins<4>;
-        case 5: return k_particles_ins<5>;
-        case 6: return k_particles_ins<6>;
-        case 7: return k_particles_ins<7>;
+        case 5: return k_particles<5>;
+        case 6: return k_particles<6>;
+        case 7: return k_particles<7>;
         case 8: return k_particles3<0>;
         case 9: return k_particles3<1>;
         case 10: return k_particles3<2>;
@@ -1595,7 +1596,8 @@ struct F32State {
     bool ins = false;  // some instance has the elliptic insert
     bool cub = false;  // the instances use cubic shapes
     int coll_grid = 64;   // workgroups of k_collide
-    int cu = 256, wg_per_cu = 4;
+    int cu = 256, wg_per_cu = 4;  // resident workgroups per CU of the counting and sorting steps
+    int wg_per_cu_plain = 4;      // and of the plain step
     int lanes = 1;        // particles per lane and pass of the bilinear particle kernel (1 or 2)
     PSet set[2];
     int cur = 0;
@@ -1750,16 +1752,21 @@ static pic_status build_tiles(pic_ctx* ctx, F32State* S) {
     CK32(hipMemcpyAsync(S->tile_info, tinfo.data(), sizeof(int4) * toff, hipMemcpyHostToDevice, s));
     CK32(hipStreamSynchronize(s));
     const size_t lds = particle_lds(S->win_max, S->win3_max);
-    // every workgroup of the statically balanced grid must be resident at once
-    int omin = 1 << 30;
+    // every workgroup of the statically balanced grid must be resident at
+    // once; the counting and sorting steps share one grid (the sorting step
+    // reads the counting step's records per workgroup), the plain step may
+    // hold another number per CU
+    int omin = 1 << 30, oplain = 1;
     for (int q = 0; q < 4; ++q) {  // the context's variants
         const void* f = (const void*)particle_kernel(q | (S->ins ? 4 : 0) | (S->cub ? 8 : 0), S->lanes);
         CK32(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
         int occ = 0;
         (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, f, kPWG, lds);
-        omin = std::min(omin, occ);
+        if (q == 0) oplain = occ;
+        else omin = std::min(omin, occ);
     }
     S->wg_per_cu = omin > 0 ? omin : 1;
+    S->wg_per_cu_plain = oplain > 0 ? oplain : 1;
     S->crec = (unsigned int*)pic_dev_alloc(ctx, sizeof(unsigned int) * 9 * kRecMax * (size_t)S->cu * S->wg_per_cu);
     if (!S->crec) return f32_fail(ctx, PIC_ENOMEM, "FP32 chunk records");
     return PIC_OK;
@@ -1940,7 +1947,7 @@ static pic_status launch_step(pic_ctx* ctx, F32State* S, hipStream_t s, bool tim
         CK32(hipEventRecord(e0, s));
     }
     const size_t lds = particle_lds(S->win_max, S->win3_max);
-    const dim3 grid(S->cu * S->wg_per_cu);
+    const dim3 grid(S->cu * ((mode & 3) ? S->wg_per_cu : S->wg_per_cu_plain));
     hipLaunchKernelGGL(particle_kernel((mode & 3) | (S->ins ? 4 : 0) | (S->cub ? 8 : 0), S->lanes), grid, dim3(kPWG),
                        lds, s,
                        A);
