@@ -103,3 +103,29 @@ def test_scan32_full_size_sort_cycle():
     cfgs = pi.scan32()
     sizes = [c["n_init"] for c in cfgs]
     full_size_steps(cfgs, check=(0, int(np.argmin(sizes)), int(np.argmax(sizes)), 31))
+
+
+def test_shared_last_part_leaves_the_results_unchanged():
+    """20M electrons in one 256x1024 trap at 1e-1 mbar (ionisation fills the
+    tails every step): with two particles per lane (256 workgroups) a plain
+    step hands out its last twelfth of the sorted particles from a device
+    counter, with one per lane (512 workgroups, under two 32768-particle units
+    each) every range is static.  Twelve steps of both, with different tiles,
+    sort intervals and launch modes, end in the same electrons, charge grid
+    and counters."""
+    from helpers import by_key
+    cfg = pi.coax256(n_init=20_000_000, p_mbar=1.0e-1)
+    out = []
+    for run in (dict(tile_r=16, tile_z=128, halo=8, sort_interval=8, lanes=2, use_graph=0),
+                dict(tile_r=8, tile_z=32, halo=4, sort_interval=3, lanes=1, use_graph=1)):
+        g = B.Sim([cfg], mode=F32, **run)
+        g.step(12)
+        out.append((by_key(g.get_particles()), g.charge(), g.diag()))
+        g.close()
+    (pa, qa, da), (pb, qb, db) = out
+    assert da["n_ioniz"] > 1000
+    for k in ("key", "r", "z", "vr", "vt", "vz", "w"):
+        assert np.array_equal(pa[k], pb[k]), k
+    assert np.array_equal(qa, qb)
+    for k in ("n_live", "n_elastic", "n_ioniz", "n_null_cand", "n_absorbed", "absorbed_W", "total_Q"):
+        assert da[k] == db[k], k
