@@ -129,3 +129,31 @@ def test_shared_last_part_leaves_the_results_unchanged():
     assert np.array_equal(qa, qb)
     for k in ("n_live", "n_elastic", "n_ioniz", "n_null_cand", "n_absorbed", "absorbed_W", "total_Q"):
         assert da[k] == db[k], k
+
+
+def test_insert_batch_at_scale_is_invariant_to_launch_shape():
+    """Eight instances of the paper's gun geometry (elliptic insert, open
+    ends, 1e-1 mbar) with 2.5M electrons each, 20M in all, so plain steps
+    share their last part in both launch shapes: the insert's one-per-lane
+    plain step (one wide workgroup per CU) and counting and sorting steps (two
+    per CU) against two particles per lane, with different tiles and sort
+    intervals.  Twelve steps end in the same electrons, grids and counters."""
+    from helpers import by_key
+    cfgs = [pi.gun(n_init=2_500_000, weight=3.6e6 * 50000 / 2_500_000, seed=(9 << 32) | k) for k in range(8)]
+    out = []
+    for run in (dict(tile_r=8, tile_z=32, halo=8, sort_interval=4, lanes=1, use_graph=0),
+                dict(tile_r=16, tile_z=64, halo=4, sort_interval=6, lanes=2, use_graph=1)):
+        g = B.Sim(cfgs, mode=F32, **run)
+        g.step(12)
+        out.append(([by_key(g.get_particles(k)) for k in (0, 7)], [g.charge(k) for k in range(8)],
+                    [g.band_charge(k) for k in range(8)], [g.diag(k) for k in range(8)]))
+        g.close()
+    (pa, qa, wa, da), (pb, qb, wb, db) = out
+    assert sum(d["n_ioniz"] for d in da) > 1000
+    for x, y in zip(pa, pb):
+        for k in ("key", "r", "z", "vr", "vt", "vz", "w"):
+            assert np.array_equal(x[k], y[k]), k
+    for k in range(8):
+        assert np.array_equal(qa[k], qb[k]) and np.array_equal(wa[k], wb[k]), k
+        for f in ("n_live", "n_elastic", "n_ioniz", "n_null_cand", "n_absorbed", "absorbed_W", "total_Q"):
+            assert da[k][f] == db[k][f], (k, f)
