@@ -714,6 +714,75 @@ def test_absorbing_walls_and_current():
     assert dg["peak_I_outer"] == dg["I_wall"][1]
 
 
+def _ballistic(c, groups, v):
+    """Electrons moving radially at speed v (E = B = 0) placed so that group
+    (wall, step s, count) crosses its wall during step s: half a step's
+    flight short of it at s - 1/2 steps before."""
+    r, vr = [], []
+    h = v * c["dt"]
+    for wall, s, n in groups:
+        r += [c["b"] - (s - 0.5) * h if wall == 1 else c["a"] + (s - 0.5) * h] * n
+        vr += [v if wall == 1 else -v] * n
+    n = len(r)
+    return dict(r=np.array(r), z=np.linspace(5e-3, 55e-3, n), vr=np.array(vr), vt=np.zeros(n), vz=np.zeros(n),
+                w=np.full(n, c["weight"]), key=np.arange(n, dtype=np.uint64))
+
+
+def test_windowed_wall_currents_and_their_peaks():
+    """The sampled current of a wall is the charge it absorbed over the last
+    window of D steps divided by D dt, and the peaks are the largest such
+    window values so far (Sec. III.A's time traces).  Ballistic electrons
+    cross the outer wall 5 in window 1, 20 in window 3 and 8 in window 4, the
+    inner one 12 in window 2 and 3 in window 4."""
+    D = 10
+    c = pi.coax64(nr=16, nz=32, collisions=0, diag_interval=D)
+    groups = [(1, 3, 5), (0, 12, 4), (0, 17, 8)] + [(1, s, 2) for s in range(21, 31)] + [(1, 35, 8), (0, 38, 3)]
+    s = frozen_sim(c, pi.uniform_fields(c), _ballistic(c, groups, 1.0e7))
+    unit = c["weight"] * E / (D * c["dt"])  # one electron per window, in A
+    # (inner, outer) of the window just sampled, and the peaks so far
+    want = [((0, 5), (0, 5)), ((12, 0), (12, 5)), ((0, 20), (12, 20)), ((3, 8), (12, 20))]
+    for (cur_in, cur_out), (pk_in, pk_out) in want:
+        s.step(D)
+        dg = s.diag()
+        assert dg["I_wall"][0] == pytest.approx(cur_in * unit, rel=1e-12, abs=0.0)
+        assert dg["I_wall"][1] == pytest.approx(cur_out * unit, rel=1e-12, abs=0.0)
+        assert dg["I_wall"][2] == 0.0 and dg["I_wall"][3] == 0.0
+        assert dg["peak_I_inner"] == pytest.approx(pk_in * unit, rel=1e-12)
+        assert dg["peak_I_outer"] == pytest.approx(pk_out * unit, rel=1e-12)
+    assert dg["n_absorbed"] == [15, 33, 0, 0] and dg["n_live"] == 0
+
+
+def test_sampled_density_time_average_and_peak():
+    """Density samples every D steps: charge over the node's volume.  A cloud
+    of n electrons at one point, drifting along z by one cell per window, sits
+    at a cell centre at every sample, so each sample puts n w / 4 on the
+    cell's four nodes; an interior node's volume is 2 pi r_i dr dz (the hat
+    function's r-weighted integral).  The time average over four samples and
+    the peak follow in closed form."""
+    D = 10
+    c = pi.coax64(nr=16, nz=32, collisions=0, diag_interval=D)
+    a, b, L, nr, nz = c["a"], c["b"], c["L"], c["nr"], c["nz"]
+    dr, dz = (b - a) / nr, L / nz
+    n, i, j0 = 1000, 5, 9
+    st = dict(r=np.full(n, a + (i + 0.5) * dr), z=np.full(n, (j0 + 0.5) * dz), vr=np.zeros(n), vt=np.zeros(n),
+              vz=np.full(n, dz / (D * c["dt"])), w=np.full(n, c["weight"]), key=np.arange(n, dtype=np.uint64))
+    s = frozen_sim(c, pi.uniform_fields(c), st)
+    s.step(4 * D)
+    dg = s.diag()
+    assert dg["n_samples"] == 4 and dg["n_live"] == n
+    vol = lambda ii: 2.0 * math.pi * (a + ii * dr) * dr * dz
+    q = n * c["weight"] / 4.0  # electrons per node and sample
+    want = np.zeros((nr + 1, nz + 1))
+    for k in range(1, 5):  # the cloud sits in cell (i, j0 + k) at sample k
+        for ii in (i, i + 1):
+            for jj in (j0 + k, j0 + k + 1):
+                want[ii, jj] += q / vol(ii) / 4.0
+    got = s.time_avg_density()
+    assert np.allclose(got, want, rtol=1e-12, atol=0.0)
+    assert np.count_nonzero(got) == 10
+    assert dg["peak_density"] == pytest.approx(q / vol(i), rel=1e-12)
+
+
 # --------------------------------------------------------------------------
 # Volumetric seed source (Sec. II.A): uniform in space, Maxwellian in velocity
 # --------------------------------------------------------------------------
