@@ -229,6 +229,21 @@ def random_fields(cfg, seed, e_scale=2.0e6, b_scale=0.3):
                 Bz=b_scale + smooth(0.2 * b_scale))
 
 
+def ballistic_state(cfg, groups, v):
+    """Electrons moving radially at speed v, for runs with zero fields: group
+    (wall, s, n) holds n electrons that start half of a step's flight v dt
+    short of s steps from wall 0 (inner, moving inward) or 1 (outer, moving
+    outward), spread along z over the middle of the trap."""
+    r, vr = [], []
+    h = v * cfg["dt"]
+    for wall, s, n in groups:
+        r += [cfg["b"] - (s - 0.5) * h if wall == 1 else cfg["a"] + (s - 0.5) * h] * n
+        vr += [v if wall == 1 else -v] * n
+    n = len(r)
+    return dict(r=np.array(r), z=np.linspace(0.1 * cfg["L"], 0.9 * cfg["L"], n), vr=np.array(vr),
+                vt=np.zeros(n), vz=np.zeros(n), w=np.full(n, cfg["weight"]), key=np.arange(n, dtype=np.uint64))
+
+
 def uniform_fields(cfg, Er=0.0, Ez=0.0, Br=0.0, Bz=0.0):
     shape = (cfg["nr"] + 1, cfg["nz"] + 1)
     return dict(Er=np.full(shape, float(Er)), Ez=np.full(shape, float(Ez)),

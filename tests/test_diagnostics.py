@@ -143,3 +143,67 @@ def test_set_particles_refuses_non_finite_velocity_and_oversized_weight(mode):
     g.set_particles(st)
     assert g.diag()["n_live"] == 100
     g.close()
+
+
+@pytest.mark.parametrize("mode", [B.PIC_MODE_FP64_PLAIN, F32])
+def test_windowed_currents_of_ballistic_electrons_in_closed_form(mode):
+    """Electrons crossing the walls in chosen windows with zero fields (the
+    oracle pin's case, here on the GPU in both forms): each sampled current is
+    the window's absorbed charge over D dt, the peaks the largest windows so
+    far, and the counts per wall exact."""
+    D = 10
+    c = pi.coax64(nr=16, nz=32, collisions=0, diag_interval=D)
+    groups = [(1, 3, 5), (0, 12, 4), (0, 17, 8)] + [(1, s, 2) for s in range(21, 31)] + [(1, 35, 8), (0, 38, 3)]
+    g, _ = gpu_and_oracle(c, pi.ballistic_state(c, groups, 1.0e7), pi.uniform_fields(c), mode=mode)
+    unit = c["weight"] * 1.602176634e-19 / (D * c["dt"])
+    want = [((0, 5), (0, 5)), ((12, 0), (12, 5)), ((0, 20), (12, 20)), ((3, 8), (12, 20))]
+    for (cur_in, cur_out), (pk_in, pk_out) in want:
+        g.step(D)
+        d = g.diag()
+        assert d["I_wall"][0] == pytest.approx(cur_in * unit, rel=1e-12, abs=0.0)
+        assert d["I_wall"][1] == pytest.approx(cur_out * unit, rel=1e-12, abs=0.0)
+        assert d["I_wall"][2] == 0.0 and d["I_wall"][3] == 0.0
+        assert d["peak_I_inner"] == pytest.approx(pk_in * unit, rel=1e-12)
+        assert d["peak_I_outer"] == pytest.approx(pk_out * unit, rel=1e-12)
+    assert d["n_absorbed"] == [15, 33, 0, 0] and d["n_live"] == 0
+    g.close()
+
+
+@pytest.mark.parametrize("mode", [B.PIC_MODE_FP64_PLAIN, F32])
+def test_sampled_density_of_a_drifting_point_cloud_in_closed_form(mode):
+    """A point cloud drifting one cell along z per window sits at a cell
+    centre at every sample: the time-averaged density and the peak density
+    follow from n w / 4 per node over the interior node volume
+    2 pi r_i dr dz.  FP64: to rounding.  FP32: forty FP32 updates of z (each
+    rounding by at most half an ulp, 2^-30 m at z < 2^-5 m) move the cloud
+    off the cell centre by up to 3.7e-8 m = 2e-5 dz, so a node's weight 1/2
+    is off by up to 4e-5 of itself: each node within 1e-4, the sum per sample
+    exact (the remainder rule)."""
+    import math
+    D = 10
+    c = pi.coax64(nr=16, nz=32, collisions=0, diag_interval=D)
+    a, b, L, nr, nz = c["a"], c["b"], c["L"], c["nr"], c["nz"]
+    dr, dz = (b - a) / nr, L / nz
+    n, i, j0 = 1000, 5, 9
+    st = dict(r=np.full(n, a + (i + 0.5) * dr), z=np.full(n, (j0 + 0.5) * dz), vr=np.zeros(n), vt=np.zeros(n),
+              vz=np.full(n, dz / (D * c["dt"])), w=np.full(n, c["weight"]), key=np.arange(n, dtype=np.uint64))
+    g, _ = gpu_and_oracle(c, st, pi.uniform_fields(c), mode=mode)
+    g.step(4 * D)
+    d = g.diag(want_density=True)
+    assert d["n_samples"] == 4 and d["n_live"] == n
+    vol = lambda ii: 2.0 * math.pi * (a + ii * dr) * dr * dz
+    q = n * c["weight"] / 4.0
+    want = np.zeros((nr + 1, nz + 1))
+    for k in range(1, 5):
+        for ii in (i, i + 1):
+            for jj in (j0 + k, j0 + k + 1):
+                want[ii, jj] += q / vol(ii) / 4.0
+    got = d["time_avg_density"].reshape(want.shape)
+    rel = 1e-12 if mode == B.PIC_MODE_FP64_PLAIN else 1e-4
+    assert np.count_nonzero(got) == 10
+    np.testing.assert_allclose(got, want, rtol=rel, atol=0.0)
+    assert d["peak_density"] == pytest.approx(q / vol(i), rel=rel)
+    # the electrons' charge per sample: sum of density times volume
+    vols = np.array([[vol(ii) for _ in range(nz + 1)] for ii in range(nr + 1)])
+    assert (got * vols).sum() == pytest.approx(n * c["weight"], rel=1e-12)
+    g.close()

@@ -714,20 +714,6 @@ def test_absorbing_walls_and_current():
     assert dg["peak_I_outer"] == dg["I_wall"][1]
 
 
-def _ballistic(c, groups, v):
-    """Electrons moving radially at speed v (E = B = 0) placed so that group
-    (wall, step s, count) crosses its wall during step s: half a step's
-    flight short of it at s - 1/2 steps before."""
-    r, vr = [], []
-    h = v * c["dt"]
-    for wall, s, n in groups:
-        r += [c["b"] - (s - 0.5) * h if wall == 1 else c["a"] + (s - 0.5) * h] * n
-        vr += [v if wall == 1 else -v] * n
-    n = len(r)
-    return dict(r=np.array(r), z=np.linspace(5e-3, 55e-3, n), vr=np.array(vr), vt=np.zeros(n), vz=np.zeros(n),
-                w=np.full(n, c["weight"]), key=np.arange(n, dtype=np.uint64))
-
-
 def test_windowed_wall_currents_and_their_peaks():
     """The sampled current of a wall is the charge it absorbed over the last
     window of D steps divided by D dt, and the peaks are the largest such
@@ -737,7 +723,7 @@ def test_windowed_wall_currents_and_their_peaks():
     D = 10
     c = pi.coax64(nr=16, nz=32, collisions=0, diag_interval=D)
     groups = [(1, 3, 5), (0, 12, 4), (0, 17, 8)] + [(1, s, 2) for s in range(21, 31)] + [(1, 35, 8), (0, 38, 3)]
-    s = frozen_sim(c, pi.uniform_fields(c), _ballistic(c, groups, 1.0e7))
+    s = frozen_sim(c, pi.uniform_fields(c), pi.ballistic_state(c, groups, 1.0e7))
     unit = c["weight"] * E / (D * c["dt"])  # one electron per window, in A
     # (inner, outer) of the window just sampled, and the peaks so far
     want = [((0, 5), (0, 5)), ((12, 0), (12, 5)), ((0, 20), (12, 20)), ((3, 8), (12, 20))]
