@@ -257,8 +257,8 @@ def main():
                     help="cubic against bilinear shapes in both forms on the workload's instance 0")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU layout is a "
-              "design note, not part of this build", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the library has no multi-GPU "
+              "path (instances would shard across GPUs with no communication)", file=sys.stderr)
         sys.exit(2)
 
     import torch
