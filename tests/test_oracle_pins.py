@@ -173,6 +173,45 @@ def test_speed_conserved_under_pure_B():
     np.testing.assert_allclose(v1, v0[alive], rtol=1e-12)
 
 
+def test_mirror_field_reflects_at_the_adiabatic_turning_point():
+    """The mirror field B_z = B0 (1 + k zeta^2), zeta = (z - L/2)/(L/2), with
+    B_r = -(r/2) dB_z/dz (divergence-free): a 100 eV electron at the centre
+    with sin^2 of its pitch angle 0.85 keeps its magnetic moment (Larmor
+    radius 1e-3 of the field's scale), so it turns where B = B0 / 0.85,
+    zeta = sqrt((1/0.85 - 1)/k), and its guiding centre stays on its field
+    line, r^2 B_z constant.  A dropped or sign-flipped B_r removes the mirror
+    force (the electron reaches the end plate); B_r off by a factor moves the
+    guiding centre off the line; a wrong zeta moves the turning point."""
+    k = 0.3
+    c = quiet(mirror_k=k)
+    Br, Bz = oracle.bfield(c)
+    L, r0 = c["L"], 5.5e-3
+    v = math.sqrt(2.0 * 100.0 * E / ME)
+    s2 = 0.85
+    # all the perpendicular speed radial: the gyration centre sits beside the
+    # electron in theta, at radius sqrt(r0^2 + rL^2)
+    st = one_particle(c, r0, L / 2, v * math.sqrt(s2), 0.0, v * math.sqrt(1.0 - s2))
+    rL = ME * v * math.sqrt(s2) / (E * c["B0"])
+    s = frozen_sim(c, dict(Er=np.zeros_like(Br), Ez=np.zeros_like(Br), Br=Br, Bz=Bz), st)
+    zs, rs = [], []
+    for _ in range(6000):
+        s.step(5)
+        p = s.get_particles()
+        assert len(p["r"]) == 1, "the electron left the trap"
+        zs.append(p["z"][0]); rs.append(p["r"][0])
+    zs, rs = np.array(zs), np.array(rs)
+    zeta_turn = math.sqrt((1.0 / s2 - 1.0) / k)
+    top = int(np.argmax(zs))
+    assert 0 < top < len(zs) - 100 and zs[-1] < zs[top] - 5e-3  # turned and came back
+    assert (zs[top] - L / 2) / (L / 2) == pytest.approx(zeta_turn, rel=0.01)
+    # guiding centre near the turning point: r averaged over the samples within
+    # 0.5 mm of it (many gyrations, the electron is slow there)
+    near = np.abs(zs - zs[top]) < 0.5e-3
+    assert near.sum() > 100
+    r_gc = math.hypot(r0, rL) * math.sqrt(1.0 / (1.0 + k * zeta_turn ** 2))
+    assert rs[near].mean() == pytest.approx(r_gc, rel=0.005)
+
+
 def test_free_streaming_straight_line_and_angular_momentum():
     c = quiet()
     r0, z0, vr, vt, vz = 4e-3, 25e-3, -3e5, 8e5, 2e5
