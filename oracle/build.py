@@ -23,6 +23,22 @@ def build(verbose=False):
     return LIB
 
 
+def build_selftest(out, sanitize=True, verbose=False):
+    """The stand-alone oracle driver (selftest.c) as an executable at `out`;
+    with `sanitize`, under gcc's address and undefined-behaviour checks (any
+    report aborts the run)."""
+    flags = ["-O1", "-g", "-fno-omit-frame-pointer"]
+    if sanitize:
+        flags += ["-fsanitize=address,undefined", "-fno-sanitize-recover=all"]
+    cmd = ["gcc", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-D_GNU_SOURCE", "-Wall",
+           "-Wno-unknown-pragmas"] + flags + ["-o", out, os.path.join(HERE, "selftest.c")] + \
+          [os.path.join(HERE, s) for s in SOURCES] + ["-lm"]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    return out
+
+
 if __name__ == "__main__":
     build(verbose=True)
     sys.exit(0)
