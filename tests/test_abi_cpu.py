@@ -102,3 +102,14 @@ def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(B, "LIB_PATH", str(tmp_path / "missing.so"))
     with pytest.raises(RuntimeError):
         B.lib()
+
+
+def test_bench_refuses_more_than_one_gpu_before_touching_one():
+    """bench.py measures one GPU: asked for more it exits with status 2 and
+    says why, before importing torch or loading the library."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120, cwd=root)
+    assert r.returncode == 2 and "one GPU only" in r.stderr and r.stdout == ""
